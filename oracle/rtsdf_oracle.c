@@ -1,0 +1,882 @@
+/*
+ * rtsdf_oracle.c -- plain CPU oracle of the RTSDF SDF-generation path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or helper
+ * with the GPU library: it is written separately from the paper (Tan, Chua,
+ * Koh, Bhojan, "RTSDF: Generating Signed Distance Fields in Real Time for
+ * Soft Shadow Rendering", PG 2020 short paper) and from the published
+ * algorithms it cites.
+ *
+ * Everything is straightforward loops in double precision, except where the
+ * result itself is defined as a float32 value (the coarse SDF and the ray
+ * origins/directions, which both sides must produce bit-identically); those
+ * are computed with float operations, each rounded separately (this file is
+ * compiled with -ffp-contract=off), and then widened to double.
+ *
+ * Sections of the paper referred to below:
+ *   Sec. 2      two-level design: coarse SDF by jump flooding, fine SDF by
+ *               ray tracing near surfaces, soft shadows from the fine SDF.
+ *   Sec. 2.1    voxelization by orthographic projection along x, y and z with
+ *               depth culling disabled; 3D jump flooding with occupied voxels
+ *               as seeds; coarse distance minus a bias beta.
+ *   Sec. 2.2    selection of fine texels with coarse distance within d; rays
+ *               towards random points on a sphere; per-frame minimum hit
+ *               distance r_t; Eq. (1) temporal update with decay alpha;
+ *               sign from accumulated front/back hit counts.
+ *   Sec. 2.3    sphere-traced soft shadows through the fine SDF.
+ * Readings where the paper is silent are stated at each function.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <float.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Voxelization (Sec. 2.1).                                                  */
+/*                                                                           */
+/* The paper rasterizes the scene three times with an orthographic camera    */
+/* looking along x, y and z, depth writes off, so every triangle produces    */
+/* fragments, and marks the voxel under each fragment.  Reading used here    */
+/* (the raster rule itself is not given): vertex coordinates are snapped to  */
+/* 1/256 of a voxel; for each triangle and each axis, a voxel column is      */
+/* covered when its centre lies inside or on the boundary of the projected   */
+/* triangle; the covered voxel is the one containing the triangle's depth    */
+/* at the column centre (floor of the exact rational depth), a depth exactly */
+/* on the far face of the domain goes to the last layer, depths outside the  */
+/* domain are dropped, and edge-on projections (zero area) are skipped.      */
+/* ------------------------------------------------------------------------ */
+
+static int64_t floor_div_i64(int64_t num, int64_t den) /* den > 0 */
+{
+    int64_t q = num / den;
+    if ((num % den) != 0 && num < 0) q -= 1;
+    return q;
+}
+
+/* twice the signed area of (u, v, p) in the projection plane */
+static int64_t edge_fn(const int64_t u[2], const int64_t v[2], const int64_t p[2])
+{
+    return (v[0] - u[0]) * (p[1] - u[1]) - (v[1] - u[1]) * (p[0] - u[0]);
+}
+
+int oracle_voxelize(const float *v, int nv, const int *f, int nt,
+                    const float lo[3], float h, int n, int *seeds)
+{
+    if (n <= 0 || h <= 0.0f) return ORC_EINVAL;
+    const double side = (double)n * (double)h;
+    int64_t *X = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)(nv > 0 ? nv : 1));
+    if (!X) return ORC_EINVAL;
+    for (int i = 0; i < nv; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            double rel = (double)v[3 * i + a] - (double)lo[a];
+            if (!(rel >= -side && rel <= 2.0 * side)) { free(X); return ORC_EINVAL; }
+            X[3 * i + a] = (int64_t)rint(rel / (double)h * 256.0);
+        }
+    }
+    for (int t = 0; t < nt; ++t)
+        for (int k = 0; k < 3; ++k)
+            if (f[3 * t + k] < 0 || f[3 * t + k] >= nv) { free(X); return ORC_EINVAL; }
+
+    const size_t nvox = (size_t)n * n * n;
+    for (size_t i = 0; i < nvox; ++i) seeds[i] = -1;
+
+    for (int t = 0; t < nt; ++t) {
+        for (int a = 0; a < 3; ++a) {
+            const int e1 = (a + 1) % 3, e2 = (a + 2) % 3;
+            int64_t P[3][2], Z[3];
+            for (int k = 0; k < 3; ++k) {
+                const int64_t *x = &X[3 * f[3 * t + k]];
+                P[k][0] = x[e1];
+                P[k][1] = x[e2];
+                Z[k] = x[a];
+            }
+            int64_t area2 = edge_fn(P[0], P[1], P[2]);
+            if (area2 == 0) continue;
+            if (area2 < 0) { /* make the projected triangle counter-clockwise */
+                int64_t tp[2] = {P[1][0], P[1][1]}, tz = Z[1];
+                P[1][0] = P[2][0]; P[1][1] = P[2][1]; Z[1] = Z[2];
+                P[2][0] = tp[0]; P[2][1] = tp[1]; Z[2] = tz;
+                area2 = -area2;
+            }
+            /* every column centre of the grid; the oracle does not bother
+               restricting to the bounding box */
+            for (int j = 0; j < n; ++j) {
+                for (int i = 0; i < n; ++i) {
+                    const int64_t c[2] = {256 * (int64_t)i + 128, 256 * (int64_t)j + 128};
+                    const int64_t w0 = edge_fn(P[1], P[2], c);
+                    const int64_t w1 = edge_fn(P[2], P[0], c);
+                    const int64_t w2 = edge_fn(P[0], P[1], c);
+                    if (w0 < 0 || w1 < 0 || w2 < 0) continue;
+                    const int64_t num = w0 * Z[0] + w1 * Z[1] + w2 * Z[2];
+                    const int64_t den = area2 * 256;
+                    int64_t L;
+                    if (num == (int64_t)n * den) L = n - 1;
+                    else {
+                        L = floor_div_i64(num, den);
+                        if (L < 0 || L >= n) continue;
+                    }
+                    int q[3];
+                    q[a] = (int)L;
+                    q[e1] = i;
+                    q[e2] = j;
+                    const size_t idx = (size_t)q[0] + (size_t)n * ((size_t)q[1] + (size_t)n * q[2]);
+                    seeds[idx] = (int)idx;
+                }
+            }
+        }
+    }
+    free(X);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Jump flooding in 3D (Sec. 2.1; Rong & Tan's jump flooding extended to     */
+/* three dimensions).  Each voxel keeps the nearest seed found so far; pass  */
+/* k looks at the seeds of the 26 voxels at offsets k*(i, j, l),             */
+/* i, j, l in {-1, 0, 1}, plus its own, for k = n/2, n/4, ..., 1.  Each pass */
+/* reads only the previous pass's field.  Ties in squared distance go to    */
+/* the seed with the lowest linear index.                                    */
+/* ------------------------------------------------------------------------ */
+
+static int64_t seed_d2(int n, int p, int s)
+{
+    const int px = p % n, py = (p / n) % n, pz = p / (n * n);
+    const int sx = s % n, sy = (s / n) % n, sz = s / (n * n);
+    const int64_t dx = px - sx, dy = py - sy, dz = pz - sz;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+void oracle_jfa_pass(int n, int k, const int *in, int *out)
+{
+    const int total = n * n * n;
+#pragma omp parallel for schedule(static)
+    for (int p = 0; p < total; ++p) {
+        const int px = p % n, py = (p / n) % n, pz = p / (n * n);
+        int best = -1;
+        int64_t best_d2 = 0;
+        for (int oz = -1; oz <= 1; ++oz)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const int qx = px + k * ox, qy = py + k * oy, qz = pz + k * oz;
+                    if (qx < 0 || qy < 0 || qz < 0 || qx >= n || qy >= n || qz >= n) continue;
+                    const int s = in[qx + n * (qy + n * qz)];
+                    if (s < 0) continue;
+                    const int64_t d2 = seed_d2(n, p, s);
+                    if (best < 0 || d2 < best_d2 || (d2 == best_d2 && s < best)) {
+                        best = s;
+                        best_d2 = d2;
+                    }
+                }
+        out[p] = best;
+    }
+}
+
+int oracle_jfa(int n, const int *seeds_in, int *seeds_out)
+{
+    if (n <= 0 || (n & (n - 1)) != 0) return ORC_EINVAL;
+    const size_t total = (size_t)n * n * n;
+    int *a = (int *)malloc(sizeof(int) * total), *b = (int *)malloc(sizeof(int) * total);
+    if (!a || !b) { free(a); free(b); return ORC_EINVAL; }
+    memcpy(a, seeds_in, sizeof(int) * total);
+    for (int k = n / 2; k >= 1; k /= 2) {
+        oracle_jfa_pass(n, k, a, b);
+        int *t = a; a = b; b = t;
+    }
+    memcpy(seeds_out, a, sizeof(int) * total);
+    free(a);
+    free(b);
+    return ORC_OK;
+}
+
+/* Coarse SDF (Sec. 2.1): distance to the nearest seed voxel minus the bias
+ * beta.  Stored as float: c = h * sqrt(D^2) - beta with float operations
+ * each rounded once (sqrt correctly rounded).  No seed at all: D^2 is
+ * INT32_MAX and c = +inf. */
+void oracle_coarse(int n, const int *seeds, float h, float beta, int *dist2, float *c)
+{
+    const int total = n * n * n;
+    for (int p = 0; p < total; ++p) {
+        if (seeds[p] < 0) {
+            dist2[p] = INT32_MAX;
+            c[p] = INFINITY;
+            continue;
+        }
+        const int64_t d2 = seed_d2(n, p, seeds[p]);
+        dist2[p] = (int)d2;
+        volatile float r = sqrtf((float)d2);
+        volatile float m = h * r;
+        c[p] = m - beta;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Selection (Sec. 2.2; Eq. (1) case split).  A fine texel is traced when    */
+/* the coarse SDF at its coarse voxel is within d:  c <= d  with             */
+/* c = h_c sqrt(D^2) - beta, i.e. D^2 <= K, K = floor(((d + beta)/h_c)^2)    */
+/* evaluated exactly in integers.  The fine texel j reads the coarse voxel   */
+/* containing its centre (j / r per axis with r = n_f / n_c).  The queue     */
+/* lists the selected texels' linear indices in ascending Morton order of    */
+/* their fine coordinates (bit b of x, y, z goes to bit 3b, 3b+1, 3b+2).     */
+/* ------------------------------------------------------------------------ */
+
+int oracle_select_threshold(float hc, float beta, float d)
+{
+    const double q = ((double)d + (double)beta) / (double)hc;
+    if (q < 0) return -1;
+    const double k = floor(q * q);
+    return k > (double)INT32_MAX ? INT32_MAX : (int)k;
+}
+
+static uint64_t morton3(uint32_t x, uint32_t y, uint32_t z)
+{
+    uint64_t m = 0;
+    for (int b = 0; b < 21; ++b) {
+        m |= (uint64_t)((x >> b) & 1u) << (3 * b);
+        m |= (uint64_t)((y >> b) & 1u) << (3 * b + 1);
+        m |= (uint64_t)((z >> b) & 1u) << (3 * b + 2);
+    }
+    return m;
+}
+
+typedef struct { uint64_t key; int idx; } keyed_t;
+
+static int cmp_keyed(const void *a, const void *b)
+{
+    const keyed_t *x = (const keyed_t *)a, *y = (const keyed_t *)b;
+    return (x->key > y->key) - (x->key < y->key);
+}
+
+int oracle_select(int nc, const int *dist2, int nf, int K,
+                  unsigned char *mask, int *queue, int cap, int *count)
+{
+    if (nc <= 0 || nf <= 0 || nf % nc != 0) return ORC_EINVAL;
+    const int r = nf / nc;
+    const size_t total = (size_t)nf * nf * nf;
+    size_t cnt = 0;
+    for (size_t j = 0; j < total; ++j) {
+        const int x = (int)(j % nf), y = (int)((j / nf) % nf), z = (int)(j / ((size_t)nf * nf));
+        const int cidx = x / r + nc * (y / r + nc * (z / r));
+        mask[j] = (unsigned char)(dist2[cidx] <= K);
+        cnt += mask[j];
+    }
+    *count = (int)cnt;
+    keyed_t *list = (keyed_t *)malloc(sizeof(keyed_t) * (cnt ? cnt : 1));
+    if (!list) return ORC_EINVAL;
+    size_t w = 0;
+    for (size_t j = 0; j < total; ++j) {
+        if (!mask[j]) continue;
+        const int x = (int)(j % nf), y = (int)((j / nf) % nf), z = (int)(j / ((size_t)nf * nf));
+        list[w].key = morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
+        list[w].idx = (int)j;
+        ++w;
+    }
+    qsort(list, cnt, sizeof(keyed_t), cmp_keyed);
+    const size_t lim = cnt < (size_t)cap ? cnt : (size_t)cap;
+    for (size_t i = 0; i < lim; ++i) queue[i] = list[i].idx;
+    free(list);
+    return cnt > (size_t)cap ? -4 : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random sphere directions (Sec. 2.2: rays towards random points on the     */
+/* surface of a sphere).  Random bits: Philox4x64 with 10 rounds (Salmon,   */
+/* Moraes, Dror, Shaw, SC'11), key (seed, 0), counter (texel, frame*2^32 +   */
+/* ray, scene, attempt).  Each 32-bit half h gives the float                 */
+/* x = (2*(h >> 9) + 1 - 2^23) * 2^-23 in (-1, 1); consecutive halves form   */
+/* pairs (x1, x2); the first pair with s = x1^2 + x2^2 < 1 is mapped to the  */
+/* sphere by Marsaglia's 1972 method:                                        */
+/*   w = (2 x1 sqrt(1 - s), 2 x2 sqrt(1 - s), 1 - 2 s).                      */
+/* After 8 attempts (32 pairs) without success, w = (0, 0, 1).               */
+/* ------------------------------------------------------------------------ */
+
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    const unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void oracle_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += W0; k1 += W1; }
+        uint64_t hi0, lo0, hi1, lo1;
+        mulhilo64(M0, x0, &hi0, &lo0);
+        mulhilo64(M1, x2, &hi1, &lo1);
+        const uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static float uniform_pm1(uint32_t h)
+{
+    const int32_t m = (int32_t)((h >> 9) << 1) + 1 - 8388608;
+    return (float)m * 0x1p-23f;
+}
+
+/* returns the attempt that succeeded (0..7) or 8 for the fallback */
+int oracle_direction(uint64_t seed, uint64_t texel, uint32_t frame, uint32_t ray,
+                     uint32_t scene, float out[3])
+{
+    const uint64_t key[2] = {seed, 0};
+    for (uint32_t attempt = 0; attempt < 8; ++attempt) {
+        const uint64_t ctr[4] = {texel, ((uint64_t)frame << 32) | ray, scene, attempt};
+        uint64_t w[4];
+        oracle_philox4x64_10(ctr, key, w);
+        uint32_t h[8];
+        for (int i = 0; i < 4; ++i) {
+            h[2 * i] = (uint32_t)w[i];
+            h[2 * i + 1] = (uint32_t)(w[i] >> 32);
+        }
+        for (int p = 0; p < 4; ++p) {
+            volatile float x1 = uniform_pm1(h[2 * p]);
+            volatile float x2 = uniform_pm1(h[2 * p + 1]);
+            volatile float a = x1 * x1;
+            volatile float b = x2 * x2;
+            volatile float s = a + b;
+            if (s < 1.0f) {
+                volatile float om = 1.0f - s;
+                volatile float q = sqrtf(om);
+                volatile float t1 = 2.0f * x1;
+                volatile float t2 = 2.0f * x2;
+                volatile float ts = 2.0f * s;
+                out[0] = t1 * q;
+                out[1] = t2 * q;
+                out[2] = 1.0f - ts;
+                return (int)attempt;
+            }
+        }
+    }
+    out[0] = 0.0f;
+    out[1] = 0.0f;
+    out[2] = 1.0f;
+    return 8;
+}
+
+/* Texel centre in world units, each coordinate lo + (i + 1/2) h in float. */
+static void texel_origin(int nf, const float lo[3], float h, int j, float o[3])
+{
+    const int idx[3] = {j % nf, (j / nf) % nf, j / (nf * nf)};
+    for (int a = 0; a < 3; ++a) {
+        volatile float c = (float)idx[a] + 0.5f;
+        volatile float m = c * h;
+        o[a] = lo[a] + m;
+    }
+}
+
+void oracle_texel_origin(int nf, const float lo[3], float h, int j, float o[3])
+{
+    texel_origin(nf, lo, h, j, o);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Closest hit (Sec. 2.2: the distance each ray travels to its closest hit). */
+/* Ray/triangle test of Moller and Trumbore (1997) in double precision:      */
+/* hit iff the determinant is non-zero, u, v >= 0, u + v <= 1 and t > 0.     */
+/* The closest hit is the smallest (t, triangle index).  A hit is on the     */
+/* front face when the ray runs against the geometric normal                 */
+/* (v1 - v0) x (v2 - v0).                                                    */
+/*                                                                           */
+/* A ray is flagged ambiguous when a float32 evaluation could legitimately   */
+/* pick a different closest triangle: some triangle whose plane is crossed   */
+/* no farther than the closest hit (plus a margin) is crossed within 1e-6 of */
+/* one of its edges, or the closest hit grazes its triangle (|cos| < 1e-2).  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double lo[3], hi[3];
+    int left, right;  /* children (internal) */
+    int start, count; /* triangle range in the permutation (leaf: count > 0) */
+} onode_t;
+
+typedef struct oracle_scene {
+    int nv, nt;
+    double *v;   /* [nv][3] */
+    int *f;      /* [nt][3] */
+    int *perm;   /* triangle order of the hierarchy */
+    onode_t *nodes;
+    int nnodes;
+    int use_bvh;
+} oracle_scene;
+
+static void tri_bounds(const oracle_scene *s, int t, double lo[3], double hi[3])
+{
+    for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+    for (int k = 0; k < 3; ++k) {
+        const double *p = &s->v[3 * s->f[3 * t + k]];
+        for (int a = 0; a < 3; ++a) {
+            if (p[a] < lo[a]) lo[a] = p[a];
+            if (p[a] > hi[a]) hi[a] = p[a];
+        }
+    }
+}
+
+static double *g_centroid_axis; /* qsort context (build is single-threaded) */
+
+static int cmp_centroid(const void *a, const void *b)
+{
+    const double x = g_centroid_axis[*(const int *)a], y = g_centroid_axis[*(const int *)b];
+    if (x < y) return -1;
+    if (x > y) return 1;
+    return (*(const int *)a > *(const int *)b) - (*(const int *)a < *(const int *)b);
+}
+
+/* Median-split bounding volume hierarchy.  Only an acceleration: the        */
+/* closest hit it returns is the same as testing every triangle, because     */
+/* boxes are padded by 1e-5 (plus a relative margin), far more than any      */
+/* rounding in the box test, and a box is skipped only when it starts beyond */
+/* the closest hit found so far (plus the ambiguity margin).                 */
+static int build_rec(oracle_scene *s, double *cent, int start, int count, int *cap)
+{
+    if (s->nnodes >= *cap) {
+        *cap *= 2;
+        s->nodes = (onode_t *)realloc(s->nodes, sizeof(onode_t) * (size_t)(*cap));
+    }
+    const int id = s->nnodes++;
+    onode_t nd;
+    for (int a = 0; a < 3; ++a) { nd.lo[a] = INFINITY; nd.hi[a] = -INFINITY; }
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = start; i < start + count; ++i) {
+        double tl[3], th[3];
+        tri_bounds(s, s->perm[i], tl, th);
+        for (int a = 0; a < 3; ++a) {
+            if (tl[a] < nd.lo[a]) nd.lo[a] = tl[a];
+            if (th[a] > nd.hi[a]) nd.hi[a] = th[a];
+            const double c = cent[3 * s->perm[i] + a];
+            if (c < clo[a]) clo[a] = c;
+            if (c > chi[a]) chi[a] = c;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        const double pad = 1e-5 + 1e-7 * (fabs(nd.lo[a]) + fabs(nd.hi[a]));
+        nd.lo[a] -= pad;
+        nd.hi[a] += pad;
+    }
+    nd.left = nd.right = -1;
+    nd.start = start;
+    nd.count = count;
+    if (count <= 4) {
+        s->nodes[id] = nd;
+        return id;
+    }
+    int axis = 0;
+    for (int a = 1; a < 3; ++a)
+        if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+    double *key = (double *)malloc(sizeof(double) * (size_t)s->nt);
+    for (int t = 0; t < s->nt; ++t) key[t] = cent[3 * t + axis];
+    g_centroid_axis = key;
+    qsort(&s->perm[start], (size_t)count, sizeof(int), cmp_centroid);
+    free(key);
+    const int half = count / 2;
+    nd.count = 0;
+    s->nodes[id] = nd;
+    const int l = build_rec(s, cent, start, half, cap);
+    const int r = build_rec(s, cent, start + half, count - half, cap);
+    s->nodes[id].left = l;
+    s->nodes[id].right = r;
+    return id;
+}
+
+static oracle_scene *scene_create_common(oracle_scene *s, const int *f, int nt, int use_bvh);
+
+oracle_scene *oracle_scene_create(const float *v, int nv, const int *f, int nt, int use_bvh)
+{
+    oracle_scene *s = (oracle_scene *)calloc(1, sizeof(oracle_scene));
+    s->nv = nv;
+    s->v = (double *)malloc(sizeof(double) * 3 * (size_t)(nv > 0 ? nv : 1));
+    for (int i = 0; i < 3 * nv; ++i) s->v[i] = (double)v[i];
+    return scene_create_common(s, f, nt, use_bvh);
+}
+
+/* Same with double-precision vertices (finite-difference checks). */
+oracle_scene *oracle_scene_create_f64(const double *v, int nv, const int *f, int nt, int use_bvh)
+{
+    oracle_scene *s = (oracle_scene *)calloc(1, sizeof(oracle_scene));
+    s->nv = nv;
+    s->v = (double *)malloc(sizeof(double) * 3 * (size_t)(nv > 0 ? nv : 1));
+    memcpy(s->v, v, sizeof(double) * 3 * (size_t)nv);
+    return scene_create_common(s, f, nt, use_bvh);
+}
+
+static oracle_scene *scene_create_common(oracle_scene *s, const int *f, int nt, int use_bvh)
+{
+    s->nt = nt;
+    s->f = (int *)malloc(sizeof(int) * 3 * (size_t)(nt > 0 ? nt : 1));
+    s->perm = (int *)malloc(sizeof(int) * (size_t)(nt > 0 ? nt : 1));
+    memcpy(s->f, f, sizeof(int) * 3 * (size_t)nt);
+    for (int t = 0; t < nt; ++t) s->perm[t] = t;
+    s->use_bvh = use_bvh && nt > 0;
+    if (s->use_bvh) {
+        double *cent = (double *)malloc(sizeof(double) * 3 * (size_t)nt);
+        for (int t = 0; t < nt; ++t)
+            for (int a = 0; a < 3; ++a)
+                cent[3 * t + a] = (s->v[3 * s->f[3 * t] + a] + s->v[3 * s->f[3 * t + 1] + a] + s->v[3 * s->f[3 * t + 2] + a]) / 3.0;
+        int cap = 2 * nt + 1;
+        s->nodes = (onode_t *)malloc(sizeof(onode_t) * (size_t)cap);
+        build_rec(s, cent, 0, nt, &cap);
+        free(cent);
+    }
+    return s;
+}
+
+void oracle_scene_destroy(oracle_scene *s)
+{
+    if (!s) return;
+    free(s->v);
+    free(s->f);
+    free(s->perm);
+    free(s->nodes);
+    free(s);
+}
+
+static void cross3(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* Moller-Trumbore.  Returns 1 on a hit; always reports the plane parameter
+ * and barycentrics when the determinant is non-zero (for the ambiguity
+ * test).  *valid tells whether the plane is crossed at all. */
+static int mt_intersect(const double o[3], const double d[3], const double *v0, const double *v1,
+                        const double *v2, double *t, double *u, double *w, int *valid)
+{
+    double e1[3], e2[3], p[3], s[3], q[3];
+    for (int a = 0; a < 3; ++a) { e1[a] = v1[a] - v0[a]; e2[a] = v2[a] - v0[a]; s[a] = o[a] - v0[a]; }
+    cross3(d, e2, p);
+    const double det = dot3(e1, p);
+    *valid = 0;
+    if (det == 0.0) return 0;
+    const double inv = 1.0 / det;
+    *u = dot3(s, p) * inv;
+    cross3(s, e1, q);
+    *w = dot3(d, q) * inv;
+    *t = dot3(e2, q) * inv;
+    *valid = 1;
+    if (*u < 0.0 || *w < 0.0 || *u + *w > 1.0) return 0;
+    return *t > 0.0;
+}
+
+typedef struct {
+    double t;
+    int tri;
+    int front;
+    int ambiguous;
+    double b[3]; /* barycentrics of the closest hit for vertices 0, 1, 2 */
+} ohit_t;
+
+/* distance-based edge proximity of a plane crossing at barycentrics (u, w) */
+static int near_edge(const double *v0, const double *v1, const double *v2, double u, double w)
+{
+    double e[3][3];
+    for (int a = 0; a < 3; ++a) {
+        e[0][a] = v1[a] - v0[a];
+        e[1][a] = v2[a] - v1[a];
+        e[2][a] = v0[a] - v2[a];
+    }
+    double n[3];
+    cross3(e[0], e[2], n);
+    const double area2 = sqrt(dot3(n, n));
+    /* barycentric b_k is (distance to the opposite edge) / (height onto it) */
+    const double bary[3] = {1.0 - u - w, u, w};
+    const int opp[3] = {1, 2, 0}; /* edge opposite vertex k */
+    for (int k = 0; k < 3; ++k) {
+        const double len = sqrt(dot3(e[opp[k]], e[opp[k]]));
+        const double height = len > 0 ? area2 / len : 0.0;
+        if (fabs(bary[k]) * height <= 1e-6) return 1;
+    }
+    return 0;
+}
+
+static void test_tri(const oracle_scene *s, int t, const double o[3], const double d[3], ohit_t *best)
+{
+    const double *v0 = &s->v[3 * s->f[3 * t]], *v1 = &s->v[3 * s->f[3 * t + 1]], *v2 = &s->v[3 * s->f[3 * t + 2]];
+    double tt, u, w;
+    int valid;
+    const int hit = mt_intersect(o, d, v0, v1, v2, &tt, &u, &w, &valid);
+    if (hit && (tt < best->t || (tt == best->t && t < best->tri))) {
+        best->t = tt;
+        best->tri = t;
+        best->b[0] = 1.0 - u - w;
+        best->b[1] = u;
+        best->b[2] = w;
+    }
+}
+
+/* second sweep over candidates for the ambiguity flag */
+static void amb_tri(const oracle_scene *s, int t, const double o[3], const double d[3], double tlim, int *amb)
+{
+    const double *v0 = &s->v[3 * s->f[3 * t]], *v1 = &s->v[3 * s->f[3 * t + 1]], *v2 = &s->v[3 * s->f[3 * t + 2]];
+    double tt, u, w;
+    int valid;
+    mt_intersect(o, d, v0, v1, v2, &tt, &u, &w, &valid);
+    if (!valid || !(tt > -1e-6) || tt > tlim) return;
+    const double tol = -1e-3; /* only crossings close to the triangle matter */
+    if (u < tol || w < tol || u + w > 1.0 - tol) return;
+    if (near_edge(v0, v1, v2, u, w)) *amb = 1;
+}
+
+static int box_hit(const onode_t *nd, const double o[3], const double d[3], double tmax)
+{
+    double t0 = 0.0, t1 = tmax;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) {
+            if (o[a] < nd->lo[a] || o[a] > nd->hi[a]) return 0;
+            continue;
+        }
+        double ta = (nd->lo[a] - o[a]) / d[a], tb = (nd->hi[a] - o[a]) / d[a];
+        if (ta > tb) { double x = ta; ta = tb; tb = x; }
+        if (ta > t0) t0 = ta;
+        if (tb < t1) t1 = tb;
+        if (t0 > t1) return 0;
+    }
+    return 1;
+}
+
+static void visit(const oracle_scene *s, const double o[3], const double d[3], ohit_t *best,
+                  double margin, int amb_pass, double tlim, int *amb)
+{
+    if (!s->use_bvh) {
+        for (int t = 0; t < s->nt; ++t) {
+            if (amb_pass) amb_tri(s, t, o, d, tlim, amb);
+            else test_tri(s, t, o, d, best);
+        }
+        return;
+    }
+    int stack[256];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        const onode_t *nd = &s->nodes[stack[--sp]];
+        const double lim = amb_pass ? tlim : (best->t * (1.0 + margin) + margin);
+        if (!box_hit(nd, o, d, lim)) continue;
+        if (nd->count > 0) {
+            for (int i = nd->start; i < nd->start + nd->count; ++i) {
+                if (amb_pass) amb_tri(s, s->perm[i], o, d, tlim, amb);
+                else test_tri(s, s->perm[i], o, d, best);
+            }
+        } else {
+            stack[sp++] = nd->left;
+            stack[sp++] = nd->right;
+        }
+    }
+}
+
+static void closest_hit(const oracle_scene *s, const double o[3], const double d[3], ohit_t *best)
+{
+    best->t = INFINITY;
+    best->tri = -1;
+    best->front = 0;
+    best->ambiguous = 0;
+    visit(s, o, d, best, 1e-9, 0, 0.0, NULL);
+    const double tlim = (isinf(best->t) ? 1e30 : best->t * (1.0 + 1e-6) + 1e-6);
+    int amb = 0;
+    visit(s, o, d, best, 0.0, 1, tlim, &amb);
+    if (best->tri >= 0) {
+        const int t = best->tri;
+        const double *v0 = &s->v[3 * s->f[3 * t]], *v1 = &s->v[3 * s->f[3 * t + 1]], *v2 = &s->v[3 * s->f[3 * t + 2]];
+        double e1[3], e2[3], n[3];
+        for (int a = 0; a < 3; ++a) { e1[a] = v1[a] - v0[a]; e2[a] = v2[a] - v0[a]; }
+        cross3(e1, e2, n);
+        const double dn = dot3(d, n);
+        best->front = dn < 0.0;
+        const double cosv = fabs(dn) / (sqrt(dot3(n, n)) * sqrt(dot3(d, d)));
+        if (cosv < 1e-2) amb = 1;
+    }
+    best->ambiguous = amb;
+}
+
+/* Closest hits of a batch of rays (double precision): for tests. */
+void oracle_closest_hits(const oracle_scene *s, int nr, const double *orig, const double *dir,
+                         double *t, int *tri, int *front, int *amb)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int i = 0; i < nr; ++i) {
+        ohit_t h;
+        closest_hit(s, &orig[3 * i], &dir[3 * i], &h);
+        t[i] = h.t;
+        tri[i] = h.tri;
+        front[i] = h.front;
+        amb[i] = h.ambiguous;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One frame of fine-SDF tracing and temporal accumulation (Sec. 2.2,        */
+/* Eq. (1)).  Reading used for the points the equation leaves open:          */
+/*  * the state keeps an unsigned distance u; the sign is applied to the    */
+/*    output only:  u_t = min(alpha u_{t-1} + (1 - alpha) max(c_t, 0), r_t)  */
+/*    with u = +inf before the first traced frame (alpha = 1 makes this the  */
+/*    running minimum of all hit distances);                                 */
+/*  * r_t is the smallest closest-hit distance t |w| among the texel's rays */
+/*    this frame (+inf if none hits); ties go to the lowest ray index;       */
+/*  * front and back counts add the closest hit of every ray;               */
+/*  * f_t = u_t if finite, else c_t; negated when back > front;             */
+/*  * the argmin record (frame, ray, triangle) belongs to u_t when it came   */
+/*    from a ray; it is kept on ties (earliest wins) and cleared when the    */
+/*    decayed term wins with alpha < 1;                                      */
+/*  * texels not selected this frame output c_t and their state resets.    */
+/* ``texels`` optionally restricts the work to a subset (the state arrays    */
+/* are still full-size); pass NULL / ntex < 0 for every texel.              */
+/* ------------------------------------------------------------------------ */
+
+/* Eq. (1) for a selected texel, on the unsigned state:
+ *   u_t = min(alpha * u_{t-1} + (1 - alpha) * max(c_t, 0), r_t).
+ * *src tells where u_t came from: 1 = this frame's rays (r_t strictly
+ * smaller), 0 = the previous state unchanged (alpha = 1), 2 = the decayed
+ * mixture (alpha < 1; the value no longer belongs to one ray). */
+double oracle_eq1(double alpha, double u_prev, float c, double rt, int *src)
+{
+    const double cm = c > 0.0f ? (double)c : 0.0;
+    const double decayed = alpha == 1.0 ? u_prev : alpha * u_prev + (1.0 - alpha) * cm;
+    if (rt < decayed) { *src = 1; return rt; }
+    *src = (alpha == 1.0) ? 0 : 2;
+    return decayed;
+}
+
+/* Output value of a selected texel: the accumulated distance if any ray has
+ * hit so far, else the coarse value; negative when more closest hits were
+ * back faces than front faces (Sec. 2.2). */
+double oracle_fine_value(double u, float c, int nfront, int nback)
+{
+    double val = isinf(u) ? (double)c : u;
+    return nback > nfront ? -val : val;
+}
+
+int oracle_trace_frame(const oracle_scene *s,
+                       int nc, const float *coarse_sdf,
+                       int nf, const float lo[3], float hf,
+                       const unsigned char *mask, const int *texels, int ntex,
+                       int rays, uint32_t frame, uint64_t seed, uint32_t scene, double alpha,
+                       double *u, int *nfront, int *nback,
+                       int *arg_frame, int *arg_ray, int *arg_tri, unsigned char *arg_amb,
+                       double *fine, double *rmin_out)
+{
+    if (nc <= 0 || nf <= 0 || nf % nc != 0 || rays <= 0) return ORC_EINVAL;
+    const int r = nf / nc;
+    const long total = (long)nf * nf * nf;
+    const long count = texels ? ntex : total;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long i = 0; i < count; ++i) {
+        const int j = texels ? texels[i] : (int)i;
+        const int x = j % nf, y = (j / nf) % nf, z = j / (nf * nf);
+        const float c = coarse_sdf[x / r + nc * (y / r + nc * (z / r))];
+        if (!mask[j]) {
+            u[j] = INFINITY;
+            nfront[j] = nback[j] = 0;
+            arg_frame[j] = arg_ray[j] = arg_tri[j] = -1;
+            arg_amb[j] = 0;
+            fine[j] = (double)c;
+            if (rmin_out) rmin_out[j] = INFINITY;
+            continue;
+        }
+        float of[3];
+        texel_origin(nf, lo, hf, j, of);
+        const double o[3] = {of[0], of[1], of[2]};
+        double rt = INFINITY;
+        int best_ray = -1, best_tri = -1, best_amb = 0;
+        for (int k = 0; k < rays; ++k) {
+            float wf[3];
+            oracle_direction(seed, (uint64_t)j, frame, (uint32_t)k, scene, wf);
+            const double w[3] = {wf[0], wf[1], wf[2]};
+            ohit_t h;
+            closest_hit(s, o, w, &h);
+            if (h.tri < 0) continue;
+            if (h.front) nfront[j] += 1;
+            else nback[j] += 1;
+            const double dist = h.t * sqrt(dot3(w, w));
+            if (dist < rt) {
+                rt = dist;
+                best_ray = k;
+                best_tri = h.tri;
+                best_amb = h.ambiguous;
+            }
+        }
+        if (rmin_out) rmin_out[j] = rt;
+        int src;
+        u[j] = oracle_eq1(alpha, u[j], c, rt, &src);
+        if (src == 1) {
+            arg_frame[j] = (int)frame;
+            arg_ray[j] = best_ray;
+            arg_tri[j] = best_tri;
+            arg_amb[j] = (unsigned char)best_amb;
+        } else if (src == 2) {
+            arg_frame[j] = arg_ray[j] = arg_tri[j] = -1;
+            arg_amb[j] = 0;
+        }
+        fine[j] = oracle_fine_value(u[j], c, nfront[j], nback[j]);
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gradient of the fine SDF with respect to vertex positions (not in the     */
+/* paper; the derivative of its ray-traced distance).  A texel whose value   */
+/* came from a ray with direction w hitting triangle (v0, v1, v2) at         */
+/* barycentrics b has f = sign * t |w| with t the ray parameter; moving      */
+/* vertex i by delta moves the hit point's plane by b_i (n . delta) along    */
+/* the normal n, so dt/dv_i = b_i n / (n . w).  The sign, the selection, the */
+/* flooding and the identity of the argmin ray are piecewise constant and    */
+/* contribute nothing.                                                       */
+/* grad_v[3*vertex + a] += grad_f[j] * sign_j * |w| * b_i * n_a / (n . w).   */
+/* ------------------------------------------------------------------------ */
+int oracle_fine_grad(const oracle_scene *s, int nf, const float lo[3], float hf,
+                     uint64_t seed, uint32_t scene, const double *fine,
+                     const int *arg_frame, const int *arg_ray, const int *arg_tri,
+                     const double *grad_f, double *grad_v)
+{
+    const long total = (long)nf * nf * nf;
+    for (long j = 0; j < total; ++j) {
+        const int t = arg_tri[j];
+        if (t < 0 || grad_f[j] == 0.0) continue;
+        float of[3], wf[3];
+        texel_origin(nf, lo, hf, (int)j, of);
+        oracle_direction(seed, (uint64_t)j, (uint32_t)arg_frame[j], (uint32_t)arg_ray[j], scene, wf);
+        const double o[3] = {of[0], of[1], of[2]}, w[3] = {wf[0], wf[1], wf[2]};
+        const int iv[3] = {s->f[3 * t], s->f[3 * t + 1], s->f[3 * t + 2]};
+        const double *v0 = &s->v[3 * iv[0]], *v1 = &s->v[3 * iv[1]], *v2 = &s->v[3 * iv[2]];
+        double tt, u, w2;
+        int valid;
+        mt_intersect(o, w, v0, v1, v2, &tt, &u, &w2, &valid);
+        if (!valid) continue;
+        double e1[3], e2[3], n[3];
+        for (int a = 0; a < 3; ++a) { e1[a] = v1[a] - v0[a]; e2[a] = v2[a] - v0[a]; }
+        cross3(e1, e2, n);
+        const double nw = dot3(n, w);
+        const double sgn = fine[j] < 0 ? -1.0 : 1.0;
+        const double scale = grad_f[j] * sgn * sqrt(dot3(w, w)) / nw;
+        const double b[3] = {1.0 - u - w2, u, w2};
+        for (int k = 0; k < 3; ++k)
+            for (int a = 0; a < 3; ++a) grad_v[3 * iv[k] + a] += scale * b[k] * n[a];
+    }
+    return ORC_OK;
+}
