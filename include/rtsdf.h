@@ -1,0 +1,270 @@
+/*
+ * rtsdf.h -- C ABI of the MI355X (gfx950) SDF-generation library.
+ *
+ * The library implements the data-parallel path of RTSDF (Tan, Chua, Koh,
+ * Bhojan, "RTSDF: Generating Signed Distance Fields in Real Time for Soft
+ * Shadow Rendering", Pacific Graphics 2020 short paper):
+ *
+ *   1. rtsdf_voxelize          mark the coarse voxels touched by the mesh
+ *                              (Sec. 2.1, orthographic projections along
+ *                              x, y and z with depth culling off);
+ *   2. rtsdf_jfa               3D jump flooding from those voxels with steps
+ *                              n/2, n/4, ..., 1 and the coarse SDF
+ *                              c = distance - beta (Sec. 2.1);
+ *   3. rtsdf_select            fine texels whose coarse value is within d,
+ *                              compacted into a queue (Sec. 2.2, the case
+ *                              split of Eq. (1));
+ *   4. rtsdf_trace_accumulate  per selected texel, rays towards random points
+ *                              on a sphere, closest hits against a bounding
+ *                              volume hierarchy, the per-frame minimum r_t,
+ *                              the temporal update of Eq. (1) and the
+ *                              front/back sign vote (Sec. 2.2);
+ *   5. rtsdf_shadow            soft-shadow visibility by sphere tracing the
+ *                              fine SDF towards a directional light (Sec. 2.3).
+ *
+ * plus the vertex gradient of the fine SDF (rtsdf_trace_backward), many
+ * scenes per launch (rtsdf_batch_*), and a captured per-frame graph
+ * (rtsdf_frame_graph_*).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  * All array arguments are DEVICE pointers owned by the caller, unless a
+ *    parameter says "host".  The library never frees them.
+ *  * The library allocates device memory only inside rtsdf_scene_create and
+ *    rtsdf_batch_create / rtsdf_frame_graph_create (released by the matching
+ *    destroy call).
+ *  * Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
+ *    stream) and do not synchronise, except *_create and rtsdf_sync_status.
+ *  * Arguments that can be checked on the host are checked before anything
+ *    is launched; a failure returns RTSDF_EINVAL and launches nothing.
+ *    Conditions only the device can see (a face index out of range, a vertex
+ *    outside the allowed box, a full queue) set bits of a per-device error
+ *    word, which rtsdf_sync_status returns and clears.
+ *  * Grids are cubes: `n` cells per axis, cell i along an axis spans
+ *    [lo + i h, lo + (i + 1) h); arrays over a grid are n^3 elements, x
+ *    fastest (index x + n (y + n z)).
+ *  * Lengths (h, beta, d, distances) are in world units.
+ *  * Calls that share an output or a workspace must not run concurrently.
+ */
+#ifndef RTSDF_H
+#define RTSDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *rtsdf_stream; /* hipStream_t */
+
+typedef struct rtsdf_grid {
+    float lo[3]; /* world position of the grid's lower corner */
+    float h;     /* cell size */
+    int32_t n;   /* cells per axis */
+} rtsdf_grid;
+
+enum {
+    RTSDF_OK = 0,
+    RTSDF_EINVAL = -1,    /* bad argument (checked on the host) */
+    RTSDF_ENOMEM = -2,    /* a *_create call could not allocate */
+    RTSDF_EHIP = -3,      /* a HIP runtime call failed */
+    RTSDF_EDEVICE = -4    /* rtsdf_sync_status: device-side error bits set */
+};
+
+/* device error bits (returned through *bits of rtsdf_sync_status) */
+enum {
+    RTSDF_ERR_FACE_INDEX = 1,  /* a face index outside [0, nv) */
+    RTSDF_ERR_VERTEX_RANGE = 2,/* a vertex farther than one domain side outside the grid */
+    RTSDF_ERR_QUEUE_FULL = 4,  /* rtsdf_select: more selected texels than queue_cap */
+    RTSDF_ERR_BATCH = 8        /* rtsdf_batch_step: inconsistent batch tables */
+};
+
+const char *rtsdf_status_string(int status);
+int rtsdf_version(void); /* 100 * major + minor */
+
+/* Synchronise `stream`, then read and clear the device error word of the
+ * current device.  Returns RTSDF_OK if no bit was set, else RTSDF_EDEVICE
+ * with the bits in *bits (may be NULL). */
+int rtsdf_sync_status(rtsdf_stream stream, uint32_t *bits);
+
+/* ------------------------------------------------------------------------ */
+/* 1. Voxelization (Sec. 2.1).                                               */
+/*                                                                           */
+/* vertices  float32 [nv][3] world positions.                                */
+/* faces     int32 [nt][3] vertex indices.                                   */
+/* coarse    the coarse grid; n a power of two in [8, 256].                  */
+/* seeds     int32 [n^3] output: the voxel's own linear index if occupied,   */
+/*           else -1.                                                        */
+/*                                                                           */
+/* Rule (the paper rasterizes; this is the exact rule used): vertex          */
+/* coordinates are snapped to 1/256 of a voxel (round half to even of        */
+/* (v - lo) / h * 256 in double precision).  For each triangle and each axis */
+/* a, every voxel column along a whose centre lies inside or on the boundary */
+/* of the triangle's projection marks the voxel containing the triangle's    */
+/* depth at that centre (floor of the exact rational depth; a depth exactly  */
+/* on the far face goes to the last layer; depths outside the grid and       */
+/* zero-area projections are skipped).  Every vertex must lie within the     */
+/* grid grown by one side length on each side (else ERR_VERTEX_RANGE and the */
+/* triangle is skipped).  The result does not depend on triangle order.     */
+/* ------------------------------------------------------------------------ */
+int rtsdf_voxelize(const float *vertices, int32_t nv, const int32_t *faces, int32_t nt,
+                   rtsdf_grid coarse, int32_t *seeds, rtsdf_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* 2. Jump flooding and coarse SDF (Sec. 2.1).                               */
+/*                                                                           */
+/* seeds     int32 [n^3] in: rtsdf_voxelize's output (own index or -1);      */
+/*           out: the nearest seed found by jump flooding (linear index, -1  */
+/*           only if the grid has no seed at all).  Passes k = n/2, ..., 1;  */
+/*           pass k takes, per voxel, the best of its own seed and those of  */
+/*           the 26 voxels at offsets k (i, j, l), i, j, l in {-1, 0, 1}     */
+/*           inside the grid, by squared distance, ties to the lowest index. */
+/* scratch   int32 [n^3] workspace (contents destroyed).                     */
+/* beta      bias subtracted from the distance (world units).                */
+/* dist2     int32 [n^3] out: squared distance in voxels to the seed         */
+/*           (INT32_MAX if none).                                            */
+/* coarse_sdf float32 [n^3] out: h * sqrt(dist2) - beta, each float          */
+/*           operation rounded once (+inf if no seed).                       */
+/* n must be a power of two in [8, 256].                                     */
+/* ------------------------------------------------------------------------ */
+int rtsdf_jfa(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, float beta,
+              int32_t *dist2, float *coarse_sdf, rtsdf_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* 3. Selection (Sec. 2.2; the case c <= d of Eq. (1)).                      */
+/*                                                                           */
+/* A fine texel is selected when the coarse voxel containing its centre has */
+/* dist2 <= K with K = floor(((d + beta) / h_c)^2), i.e. c <= d exactly.    */
+/* fine.n must be a power-of-two multiple of coarse.n and the fine grid must */
+/* cover the same box (fine.h * fine.n == coarse.h * coarse.n).              */
+/*                                                                           */
+/* mask      uint8 [n_f^3] out: 1 if selected.                               */
+/* queue     int32 [queue_cap] out: the selected texels' linear indices in   */
+/*           ascending Morton order of their fine coordinates (bit b of x,   */
+/*           y, z at bits 3b, 3b+1, 3b+2).                                   */
+/* count     int32 [1] out (device): number of selected texels; if it        */
+/*           exceeds queue_cap only queue_cap entries are written and        */
+/*           ERR_QUEUE_FULL is raised.                                       */
+/* workspace device memory of rtsdf_select_workspace_size(coarse.n) bytes.   */
+/* ------------------------------------------------------------------------ */
+size_t rtsdf_select_workspace_size(int32_t coarse_n);
+int rtsdf_select(rtsdf_grid coarse, const int32_t *dist2, rtsdf_grid fine, float beta, float d,
+                 uint8_t *mask, int32_t *queue, int32_t queue_cap, int32_t *count,
+                 void *workspace, rtsdf_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Scene: the triangles and their bounding volume hierarchy, resident on    */
+/* the device.  create copies the mesh (device pointers) and builds the      */
+/* hierarchy (binned surface-area heuristic, two children per node); it      */
+/* synchronises `stream`.  refit takes new positions for the same topology   */
+/* and recomputes every box bottom-up on the device, asynchronously.         */
+/* ------------------------------------------------------------------------ */
+typedef struct rtsdf_scene rtsdf_scene;
+
+typedef struct rtsdf_scene_info {
+    int32_t nv, nt;
+    int32_t nodes;      /* internal nodes of the hierarchy */
+    int32_t max_depth;  /* deepest leaf (root = 0) */
+    int32_t leaf_size;  /* largest triangle count in a leaf */
+    int64_t device_bytes;
+} rtsdf_scene_info;
+
+int rtsdf_scene_create(const float *vertices, int32_t nv, const int32_t *faces, int32_t nt,
+                       int32_t leaf_size, rtsdf_scene **out, rtsdf_stream stream);
+int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsdf_stream stream);
+int rtsdf_scene_info_get(const rtsdf_scene *scene, rtsdf_scene_info *info);
+void rtsdf_scene_destroy(rtsdf_scene *scene);
+
+/* ------------------------------------------------------------------------ */
+/* 4. Tracing and temporal accumulation (Sec. 2.2, Eq. (1)).                 */
+/*                                                                           */
+/* Per-texel state (all [n_f^3], caller-owned, initialise with               */
+/* rtsdf_accum_reset):                                                       */
+/*   u         float32  unsigned accumulated distance (+inf = none yet);     */
+/*   hits      uint32   front-face count | back-face count << 16;            */
+/*   arg_tri   int32    triangle of the ray that produced u, -1 if none;     */
+/*   arg_ray   int32    frame << 8 | ray of that ray (-1 if none).           */
+/*                                                                           */
+/* For a selected texel j with centre o (lo + (i + 1/2) h per axis, float), */
+/* each ray k < rays_per_texel goes along w = Marsaglia's sphere point from  */
+/* Philox4x64-10 random bits, key (seed, 0), counter (j, frame << 32 | k,    */
+/* scene_id, attempt): each 32-bit half h gives x = (2 (h >> 9) + 1 - 2^23)  */
+/* 2^-23; the first pair with s = x1^2 + x2^2 < 1 gives                      */
+/* w = (2 x1 sqrt(1-s), 2 x2 sqrt(1-s), 1 - 2 s) (float ops, each rounded    */
+/* once); after 8 attempts w = (0, 0, 1).  Its closest hit (smallest t > 0,  */
+/* ties to the lowest triangle index) gives the distance t |w| and a front   */
+/* (w . n < 0, n = (v1 - v0) x (v2 - v0)) or back hit.  With r_t the         */
+/* smallest distance of the frame (ties to the lowest ray):                  */
+/*   u <- min(alpha u + (1 - alpha) max(c, 0), r_t)   (alpha = 1: min(u, r_t))*/
+/*   front/back counts += this frame's closest hits                          */
+/*   fine_sdf = (u finite ? u : c), negated if back > front.                 */
+/* Texels not selected get fine_sdf = c (coarse value of the voxel holding   */
+/* the centre) and their state is reset.                                     */
+/*                                                                           */
+/* coarse_sdf float32 [n_c^3]; mask/queue/count from rtsdf_select; only the */
+/*            first min(count, queue_cap) queue entries are traced.          */
+/* rays_per_texel in [1, 64]; alpha in [0, 1].                               */
+/* frame_ptr  optional device uint32: if non-NULL the frame index is read    */
+/*            from it at run time (for captured graphs) and `frame` is       */
+/*            ignored.                                                       */
+/* workspace  rtsdf_trace_workspace_size() bytes of device memory.           */
+/* ------------------------------------------------------------------------ */
+typedef struct rtsdf_accum {
+    float *u;
+    uint32_t *hits;
+    int32_t *arg_tri;
+    int32_t *arg_ray;
+} rtsdf_accum;
+
+int rtsdf_accum_reset(rtsdf_grid fine, rtsdf_accum state, rtsdf_stream stream);
+size_t rtsdf_trace_workspace_size(void);
+int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const float *coarse_sdf,
+                           rtsdf_grid fine, const uint8_t *mask, const int32_t *queue,
+                           const int32_t *count, int32_t queue_cap, int32_t rays_per_texel, uint32_t frame,
+                           const uint32_t *frame_ptr, uint64_t seed, uint32_t scene_id, float alpha,
+                           rtsdf_accum state, float *fine_sdf, void *workspace, rtsdf_stream stream);
+
+/* Ray directions exactly as rtsdf_trace_accumulate draws them, for n keys  */
+/* (texel[i], frame[i], ray[i]) with one seed and scene id: out float32      */
+/* [n][3].  Lets callers and tests check the generator bit for bit.          */
+int rtsdf_directions(const int32_t *texel, const uint32_t *frame, const int32_t *ray, int32_t n,
+                     uint64_t seed, uint32_t scene_id, float *out, rtsdf_stream stream);
+
+/* Closest hits of arbitrary rays (float32 origins and directions [n][3]):   */
+/* t_out float32 (+inf on a miss), tri_out int32 (-1 on a miss), front_out   */
+/* int32 (1 front, 0 back or miss).  Same traversal as the tracer.           */
+int rtsdf_closest_hits(const rtsdf_scene *scene, const float *origins, const float *dirs, int32_t n,
+                       float *t_out, int32_t *tri_out, int32_t *front_out, rtsdf_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Vertex gradient of the fine SDF (the derivative of the traced distance).  */
+/* For every texel whose fine value came from a ray (arg_tri >= 0), the ray  */
+/* is regenerated from (texel, frame, ray) and intersected with its          */
+/* triangle; with barycentrics b and geometric normal n,                     */
+/*   grad_v[vertex i] += grad_fine[j] * sign(fine_sdf[j]) * |w| * b_i n/(n.w)*/
+/* grad_v float32 [nv][3] is ACCUMULATED into (zero it first).  Uses the     */
+/* scene's current vertex positions.                                         */
+/* ------------------------------------------------------------------------ */
+int rtsdf_trace_backward(const rtsdf_scene *scene, rtsdf_grid fine, rtsdf_accum state,
+                         const float *fine_sdf, const float *grad_fine, uint64_t seed,
+                         uint32_t scene_id, float *grad_v, rtsdf_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* 5. Soft shadows (Sec. 2.3): for each point p, march from p towards the    */
+/* light (unit direction `light_dir`, host float[3]) through the fine SDF,   */
+/* sampled trilinearly between texel centres (clamped at the border).        */
+/* Starting at t = eps, each step samples s = sdf(p + t l); the march stops  */
+/* with visibility 0 when s < eps, stops when t > max_dist, the point leaves */
+/* the grid or max_steps samples were taken; otherwise visibility            */
+/* min(1, k s / t) is folded in and t advances by min(s, max_step) (at least */
+/* eps).  visibility float32 [np] out in [0, 1].                             */
+/* ------------------------------------------------------------------------ */
+int rtsdf_shadow(rtsdf_grid fine, const float *fine_sdf, const float *points, int32_t np,
+                 const float light_dir[3], float k, float eps, int32_t max_steps, float max_step,
+                 float max_dist, float *visibility, rtsdf_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTSDF_H */

@@ -68,6 +68,8 @@ def lib():
         L.oracle_trace_frame.argtypes = [P, i32, P, i32, P, f32, P, P, i32, i32, u32, u64, u32, f64,
                                          P, P, P, P, P, P, P, P, P]
         L.oracle_fine_grad.argtypes = [P, i32, P, f32, u64, u32, P, P, P, P, P, P]
+        L.oracle_directions.argtypes = [i32, P, P, P, u64, u32, P]
+        L.oracle_shadow.argtypes = [i32, P, f32, P, i32, P, P, f32, f32, i32, f32, f32, P]
         _lib = L
     return _lib
 
@@ -145,6 +147,29 @@ def direction(seed: int, texel: int, frame: int, ray: int, scene: int = 0):
     out = np.empty(3, np.float32)
     attempt = lib().oracle_direction(seed, texel, frame, ray, scene, _p(out))
     return out, int(attempt)
+
+
+def directions(texel, frame, ray, seed: int = 0, scene: int = 0) -> np.ndarray:
+    """Directions for many (texel, frame, ray) keys, float32 [n, 3]."""
+    t = _c(texel, np.int32)
+    fr = _c(np.broadcast_to(frame, t.shape), np.uint32)
+    r = _c(np.broadcast_to(ray, t.shape), np.int32)
+    out = np.empty((t.shape[0], 3), np.float32)
+    lib().oracle_directions(t.shape[0], _p(t), _p(fr), _p(r), int(seed), int(scene), _p(out))
+    return out
+
+
+def shadow(n: int, lo, h: float, sdf, points, light, k: float, eps: float, max_steps: int, max_step: float,
+           max_dist: float) -> np.ndarray:
+    """Soft-shadow visibility of each point (Sec. 2.3), float32 [np]."""
+    lo = _c(lo, np.float32)
+    s = _c(sdf, np.float32)
+    pts = _c(points, np.float32).reshape(-1, 3)
+    l = _c(light, np.float32)
+    out = np.empty(pts.shape[0], np.float32)
+    lib().oracle_shadow(int(n), _p(lo), float(h), _p(s), pts.shape[0], _p(pts), _p(l), float(k), float(eps),
+                        int(max_steps), float(max_step), float(max_dist), _p(out))
+    return out
 
 
 def texel_origin(nf: int, lo, h: float, j: int) -> np.ndarray:

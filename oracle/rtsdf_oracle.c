@@ -116,10 +116,21 @@ int oracle_voxelize(const float *v, int nv, const int *f, int nt,
                 P[2][0] = tp[0]; P[2][1] = tp[1]; Z[2] = tz;
                 area2 = -area2;
             }
-            /* every column centre of the grid; the oracle does not bother
-               restricting to the bounding box */
+            /* columns whose centre can lie in the triangle's bounding box
+               (one extra column on each side; the edge test decides) */
+            int64_t mn[2], mx[2];
+            for (int c = 0; c < 2; ++c) {
+                mn[c] = P[0][c] < P[1][c] ? P[0][c] : P[1][c];
+                if (P[2][c] < mn[c]) mn[c] = P[2][c];
+                mx[c] = P[0][c] > P[1][c] ? P[0][c] : P[1][c];
+                if (P[2][c] > mx[c]) mx[c] = P[2][c];
+            }
+            const int64_t ilo = floor_div_i64(mn[0], 256) - 1, ihi = floor_div_i64(mx[0], 256) + 1;
+            const int64_t jlo = floor_div_i64(mn[1], 256) - 1, jhi = floor_div_i64(mx[1], 256) + 1;
             for (int j = 0; j < n; ++j) {
+                if (j < jlo || j > jhi) continue;
                 for (int i = 0; i < n; ++i) {
+                    if (i < ilo || i > ihi) continue;
                     const int64_t c[2] = {256 * (int64_t)i + 128, 256 * (int64_t)j + 128};
                     const int64_t w0 = edge_fn(P[1], P[2], c);
                     const int64_t w1 = edge_fn(P[2], P[0], c);
@@ -879,4 +890,93 @@ int oracle_fine_grad(const oracle_scene *s, int nf, const float lo[3], float hf,
             for (int a = 0; a < 3; ++a) grad_v[3 * iv[k] + a] += scale * b[k] * n[a];
     }
     return ORC_OK;
+}
+
+/* Directions for many keys (same rule as oracle_direction). */
+void oracle_directions(int n, const int *texel, const uint32_t *frame, const int *ray, uint64_t seed,
+                       uint32_t scene, float *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) oracle_direction(seed, (uint64_t)texel[i], frame[i], (uint32_t)ray[i], scene, &out[3 * i]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Soft shadows (Sec. 2.3): march from p towards the light through the fine  */
+/* SDF, sampled linearly (trilinear between texel centres) rather than at   */
+/* the nearest texel; stop after max_steps samples, when the sample falls    */
+/* below eps (fully shadowed), when t exceeds max_dist or the point leaves   */
+/* the grid; the step is the sample value capped at max_step (and at least   */
+/* eps); the penumbra term is the running minimum of k s / t.  The march is  */
+/* defined in float arithmetic with this exact operation order (each        */
+/* operation rounded once), because its stopping decisions must be taken in */
+/* the same precision on both sides:                                         */
+/*   q = p + t l;  g = (q - lo) / h - 1/2 per axis (outside if g < -1/2 or   */
+/*   g > n - 1/2); g clamped to [0, n-1]; i = min(floor(g), n-2); f = g - i; */
+/*   lerp(a, b, f) = a + f (b - a), along x, then y, then z;                 */
+/*   vis = min(vis, (k s) / t);  t = t + max(min(s, max_step), eps).         */
+/* ------------------------------------------------------------------------ */
+static int shadow_axis(float q, float lo, float h, int n, int *i, float *f)
+{
+    volatile float a = q - lo;
+    volatile float b = a / h;
+    volatile float g = b - 0.5f;
+    if (g < -0.5f || g > (float)n - 0.5f) return 0;
+    float gc = g < 0.0f ? 0.0f : g;
+    if (gc > (float)(n - 1)) gc = (float)(n - 1);
+    int ii = (int)floorf(gc);
+    if (ii > n - 2) ii = n - 2;
+    *i = ii;
+    volatile float ff = gc - (float)ii;
+    *f = ff;
+    return 1;
+}
+
+static float lerpf_(float a, float b, float f)
+{
+    volatile float d = b - a;
+    volatile float m = f * d;
+    volatile float r = a + m;
+    return r;
+}
+
+void oracle_shadow(int n, const float lo[3], float h, const float *sdf, int np, const float *pts, const float l[3],
+                   float k, float eps, int max_steps, float max_step, float max_dist, float *vis_out)
+{
+#pragma omp parallel for schedule(static)
+    for (int p = 0; p < np; ++p) {
+        float vis = 1.0f, t = eps;
+        for (int step = 0; step < max_steps; ++step) {
+            if (t > max_dist) break;
+            float q[3];
+            int idx[3];
+            float fr[3];
+            int inside = 1;
+            for (int a = 0; a < 3; ++a) {
+                volatile float m = t * l[a];
+                volatile float qq = pts[3 * p + a] + m;
+                q[a] = qq;
+                if (!shadow_axis(q[a], lo[a], h, n, &idx[a], &fr[a])) inside = 0;
+            }
+            if (!inside) break;
+            const long b = idx[0] + (long)n * (idx[1] + (long)n * idx[2]);
+            const long sy = n, sz = (long)n * n;
+            const float c00 = lerpf_(sdf[b], sdf[b + 1], fr[0]);
+            const float c10 = lerpf_(sdf[b + sy], sdf[b + sy + 1], fr[0]);
+            const float c01 = lerpf_(sdf[b + sz], sdf[b + sz + 1], fr[0]);
+            const float c11 = lerpf_(sdf[b + sy + sz], sdf[b + sy + sz + 1], fr[0]);
+            const float s = lerpf_(lerpf_(c00, c10, fr[1]), lerpf_(c01, c11, fr[1]), fr[2]);
+            if (s < eps) {
+                vis = 0.0f;
+                break;
+            }
+            volatile float ks = k * s;
+            volatile float pen = ks / t;
+            if (pen < vis) vis = pen;
+            float st = s < max_step ? s : max_step;
+            if (st < eps) st = eps;
+            volatile float tn = t + st;
+            t = tn;
+        }
+        vis_out[p] = vis > 0.0f ? vis : 0.0f;
+    }
 }

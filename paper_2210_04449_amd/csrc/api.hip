@@ -1,0 +1,30 @@
+// Status strings, version and the device error word.
+#include "common.hpp"
+
+extern "C" const char *rtsdf_status_string(int status)
+{
+    switch (status) {
+    case RTSDF_OK: return "ok";
+    case RTSDF_EINVAL: return "invalid argument";
+    case RTSDF_ENOMEM: return "out of device memory";
+    case RTSDF_EHIP: return "HIP runtime error";
+    case RTSDF_EDEVICE: return "device-side error reported";
+    default: return "unknown status";
+    }
+}
+
+extern "C" int rtsdf_version(void) { return 100; }
+
+extern "C" int rtsdf_sync_status(rtsdf_stream stream, uint32_t *bits)
+{
+    using namespace rtsdf;
+    if (hipStreamSynchronize(as_stream(stream)) != hipSuccess) return RTSDF_EHIP;
+    unsigned int word = 0, zero = 0;
+    if (hipMemcpyFromSymbol(&word, HIP_SYMBOL(g_error_word), sizeof(word), 0, hipMemcpyDeviceToHost) != hipSuccess)
+        return RTSDF_EHIP;
+    if (word != 0 &&
+        hipMemcpyToSymbol(HIP_SYMBOL(g_error_word), &zero, sizeof(zero), 0, hipMemcpyHostToDevice) != hipSuccess)
+        return RTSDF_EHIP;
+    if (bits) *bits = word;
+    return word ? RTSDF_EDEVICE : RTSDF_OK;
+}

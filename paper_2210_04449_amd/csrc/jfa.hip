@@ -1,0 +1,265 @@
+// 3D jump flooding and the coarse SDF (paper Sec. 2.1; the jump flooding of
+// Rong & Tan extended to three dimensions).
+//
+// Pass k (k = n/2, ..., 1) gives every voxel the best of its own seed and the
+// seeds of the 26 voxels at offsets k (i, j, l), i, j, l in {-1, 0, 1}: the
+// smallest squared distance, ties to the lowest linear seed index.  After the
+// last pass the coarse SDF is c = h sqrt(D^2) - beta.
+//
+// Layout between passes (internal): the grid is cut into 4x4x4 bricks, one
+// wavefront per brick; brick b = bx + B (by + B bz) (B = n / 4) stores its 64
+// voxels contiguously (lane = lx + 4 ly + 16 lz), so every candidate read of a
+// wavefront is one coalesced 256-byte block.  A seed is packed as
+// x | y << 8 | z << 16 (0xFFFFFFFF = none); packed order equals linear-index
+// order, so ties compare the packed word directly.
+//
+// Candidate key: the 64-bit word (D^2 << 32 | packed seed), read as a float64.
+// Its exponent field is zero (D^2 < 2^20), so it is a non-negative denormal
+// whose order is the integer order, and one v_min_f64 keeps the better of two
+// keys.  A missing seed gets bits 0x7F000000 in the high word (a large finite
+// double) and always loses.  D^2 itself is formed with byte/short dot
+// products: for n <= 128 the three 7-bit coordinate differences fit signed
+// bytes, ((P + 128) - S) ^ 0x808080 per byte, and one v_dot4_i32_i8 squares and
+// sums them; for n = 256 x and y go through packed 16-bit lanes and
+// v_dot2_i32_i16, z separately.
+//
+// Steps k >= 4 read whole neighbour bricks straight from global memory (an
+// out-of-grid neighbour reads a constant all-empty brick, chosen with a scalar
+// select).  Steps 2 and 1 stage an (8 + 2k)^3 block of voxels (eight bricks
+// plus halo) in LDS; candidates then sit at compile-time LDS offsets and
+// out-of-grid halo entries are empty.  The k = 1 pass writes the final seeds,
+// D^2 and c in the caller's linear layout.
+#include "common.hpp"
+
+namespace rtsdf {
+
+constexpr uint32_t kNoSeed = 0xFFFFFFFFu;
+
+__device__ int32_t g_empty_brick[64] = {
+    -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+    -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+    -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+
+typedef short jfa_short2 __attribute__((ext_vector_type(2)));
+
+// Voxel-side constant for the distance: 7-bit path: biased packed position;
+// 8-bit path: x | y << 16 (low word) and z (high word).
+struct JfaPos {
+    uint32_t a, b;
+};
+
+template <bool WIDE>
+__device__ __forceinline__ JfaPos jfa_pos(int x, int y, int z)
+{
+    JfaPos p;
+    if (!WIDE) {
+        p.a = (uint32_t)(x + 128) | ((uint32_t)(y + 128) << 8) | ((uint32_t)(z + 128) << 16);
+        p.b = 0;
+    } else {
+        p.a = (uint32_t)x | ((uint32_t)y << 16);
+        p.b = (uint32_t)z;
+    }
+    return p;
+}
+
+template <bool WIDE>
+__device__ __forceinline__ double jfa_key(JfaPos p, uint32_t s)
+{
+    int d2;
+    if (!WIDE) {
+        const int d = (int)((p.a - s) ^ 0x00808080u);
+        d2 = __builtin_amdgcn_sdot4(d, d, 0, false);
+    } else {
+        const jfa_short2 sxy = __builtin_bit_cast(jfa_short2, __builtin_amdgcn_perm(0u, s, 0x0C010C00u));
+        const jfa_short2 dxy = __builtin_bit_cast(jfa_short2, p.a) - sxy;
+        const int dz = (int)p.b - (int)((s >> 16) & 0xFFu);
+        d2 = __builtin_amdgcn_sdot2(dxy, dxy, dz * dz, false);
+    }
+    const uint32_t hi = (s & 0x7F000000u) | (uint32_t)d2;
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)s);
+}
+
+__device__ __forceinline__ uint32_t key_seed(double k) { return (uint32_t)__builtin_bit_cast(uint64_t, k); }
+__device__ __forceinline__ uint32_t key_d2(double k) { return (uint32_t)(__builtin_bit_cast(uint64_t, k) >> 32); }
+
+__device__ __forceinline__ uint32_t pack_linear(int32_t s, int logn)
+{
+    if (s < 0) return kNoSeed;
+    const uint32_t m = (1u << logn) - 1u;
+    const uint32_t u = (uint32_t)s;
+    return (u & m) | (((u >> logn) & m) << 8) | ((u >> (2 * logn)) << 16);
+}
+
+__device__ __forceinline__ int32_t unpack_linear(uint32_t p, int logn)
+{
+    if (p == kNoSeed) return -1;
+    return (int32_t)((p & 0xFFu) | (((p >> 8) & 0xFFu) << logn) | ((p >> 16) << (2 * logn)));
+}
+
+// Spread consecutive workgroups of one XCD over a contiguous range (the
+// dispatcher deals workgroups to the 8 XCDs round-robin; each XCD has its own
+// L2, so neighbouring bricks should land on the same one).
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks)
+{
+    if ((nblocks & 7u) != 0) return bid;
+    return (bid & 7u) * (nblocks >> 3) + (bid >> 3);
+}
+
+// linear caller layout -> packed brick layout
+__global__ void __launch_bounds__(256) jfa_to_bricks(const int32_t *__restrict__ src, int32_t *__restrict__ dst,
+                                                     int n, int logn)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int B = n >> 2;
+    const int b = (int)(e >> 6), l = (int)(e & 63);
+    const int bx = b % B, by = (b / B) % B, bz = b / (B * B);
+    const int x = bx * 4 + (l & 3), y = by * 4 + ((l >> 2) & 3), z = bz * 4 + (l >> 4);
+    dst[e] = (int32_t)pack_linear(src[x + n * (y + n * z)], logn);
+}
+
+// One pass with step k >= 4 (a multiple of the brick size).  LINEAR_IN: the
+// source is the caller's linear index array (first pass only).
+template <bool WIDE, bool LINEAR_IN>
+__global__ void __launch_bounds__(256) jfa_far(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                               int logn, int kb)
+{
+    const int B = n >> 2;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int b = (int)xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+    const int bx = b % B, by = (b / B) % B, bz = b / (B * B);
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+    const JfaPos P = jfa_pos<WIDE>(bx * 4 + lx, by * 4 + ly, bz * 4 + lz);
+    double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
+    uint32_t cand[27];
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+        const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+        const int nx = bx + ox * kb, ny = by + oy * kb, nz = bz + oz * kb;
+        const bool valid = nx >= 0 && ny >= 0 && nz >= 0 && nx < B && ny < B && nz < B;
+        if (!LINEAR_IN) {
+            const int32_t *p = valid ? src + (int64_t)(nx + B * (ny + B * nz)) * 64 : g_empty_brick;
+            cand[o] = (uint32_t)p[lane];
+        } else {
+            const int x = nx * 4 + lx, y = ny * 4 + ly, z = nz * 4 + lz;
+            const int32_t *p = valid ? src + (x + n * (y + n * z)) : g_empty_brick;
+            cand[o] = pack_linear(p[0], logn);
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 27; ++o) best = __builtin_fmin(best, jfa_key<WIDE>(P, cand[o]));
+    dst[(int64_t)b * 64 + lane] = (int32_t)key_seed(best);
+}
+
+// One pass with step K in {1, 2}: eight bricks (an 8^3 block) per workgroup,
+// staged with a K-voxel halo in LDS.  FINAL writes the caller's outputs.
+template <int K, bool WIDE, bool FINAL>
+__global__ void __launch_bounds__(512) jfa_near(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                                int logn, int32_t *__restrict__ dist2, float *__restrict__ sdf,
+                                                float h, float beta)
+{
+    constexpr int T = 8 + 2 * K;
+    __shared__ uint32_t tile[T * T * T];
+    const int B = n >> 2;
+    const int TB = n >> 3;  // 8^3 blocks per axis
+    const int blk = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int tx0 = (blk % TB) * 8, ty0 = ((blk / TB) % TB) * 8, tz0 = (blk / (TB * TB)) * 8;
+    for (int i = threadIdx.x; i < T * T * T; i += blockDim.x) {
+        const int x = tx0 - K + i % T, y = ty0 - K + (i / T) % T, z = tz0 - K + i / (T * T);
+        uint32_t v = kNoSeed;
+        if (x >= 0 && y >= 0 && z >= 0 && x < n && y < n && z < n) {
+            const int b = (x >> 2) + B * ((y >> 2) + B * (z >> 2));
+            v = (uint32_t)src[(int64_t)b * 64 + (x & 3) + 4 * (y & 3) + 16 * (z & 3)];
+        }
+        tile[i] = v;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lx = (wave & 1) * 4 + (lane & 3), ly = ((wave >> 1) & 1) * 4 + ((lane >> 2) & 3),
+              lz = (wave >> 2) * 4 + (lane >> 4);
+    const int x = tx0 + lx, y = ty0 + ly, z = tz0 + lz;
+    const JfaPos P = jfa_pos<WIDE>(x, y, z);
+    const int c = (lx + K) + T * ((ly + K) + T * (lz + K));
+    double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+        const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+        best = __builtin_fmin(best, jfa_key<WIDE>(P, tile[c + K * (ox + T * (oy + T * oz))]));
+    }
+    if (!FINAL) {
+        const int b = (x >> 2) + B * ((y >> 2) + B * (z >> 2));
+        dst[(int64_t)b * 64 + (x & 3) + 4 * (y & 3) + 16 * (z & 3)] = (int32_t)key_seed(best);
+    } else {
+        const uint32_t s = key_seed(best);
+        const int64_t idx = x + (int64_t)n * (y + (int64_t)n * z);
+        if (s == kNoSeed) {
+            dst[idx] = -1;
+            dist2[idx] = INT32_MAX;
+            sdf[idx] = __builtin_inff();
+        } else {
+            const int d2 = (int)key_d2(best);
+            dst[idx] = unpack_linear(s, logn);
+            dist2[idx] = d2;
+            sdf[idx] = __fsub_rn(__fmul_rn(h, __fsqrt_rn((float)d2)), beta);
+        }
+    }
+}
+
+template <bool WIDE>
+static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float beta, int32_t *dist2, float *sdf,
+                   hipStream_t s)
+{
+    const int n = g.n, logn = ilog2(n);
+    const int64_t nvox = (int64_t)n * n * n;
+    const int nbrick_passes = logn - 1;  // steps n/2 .. 2; step 1 is the final pass
+    const unsigned far_blocks = (unsigned)(nvox / 256);
+    const unsigned near_blocks = (unsigned)(nvox / 512);
+    // Ping-pong so that the final pass reads `scratch` and writes `seeds`.
+    const int32_t *cur;
+    int32_t *bufs[2] = {seeds, scratch};
+    int next;  // index into bufs of the next destination
+    bool linear_first = false;
+    if (nbrick_passes % 2 == 0) {
+        jfa_to_bricks<<<dim3((unsigned)(nvox / 256)), dim3(256), 0, s>>>(seeds, scratch, n, logn);
+        RTSDF_CHECK_LAUNCH();
+        cur = scratch;
+        next = 0;
+    } else {
+        cur = seeds;
+        next = 1;
+        linear_first = true;
+    }
+    for (int i = 1; i <= nbrick_passes; ++i) {
+        const int k = n >> i;
+        int32_t *dst = bufs[next];
+        if (k >= 4) {
+            if (linear_first && i == 1)
+                jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
+            else
+                jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
+        } else {  // k == 2, never the first pass since n >= 8
+            jfa_near<2, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr, 0.f, 0.f);
+        }
+        RTSDF_CHECK_LAUNCH();
+        cur = dst;
+        next ^= 1;
+    }
+    // cur == scratch here by construction
+    jfa_near<1, WIDE, true><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, seeds, n, logn, dist2, sdf, g.h, beta);
+    RTSDF_CHECK_LAUNCH();
+    return RTSDF_OK;
+}
+
+}  // namespace rtsdf
+
+extern "C" int rtsdf_jfa(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, float beta, int32_t *dist2,
+                         float *coarse_sdf, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!grid_ok(coarse) || !is_pow2(coarse.n) || coarse.n < 8 || coarse.n > 256) return RTSDF_EINVAL;
+    if (!seeds || !scratch || !dist2 || !coarse_sdf || seeds == scratch) return RTSDF_EINVAL;
+    if (!(beta == beta)) return RTSDF_EINVAL;
+    hipStream_t s = as_stream(stream);
+    if (coarse.n <= 128) return jfa_run<false>(coarse, seeds, scratch, beta, dist2, coarse_sdf, s);
+    return jfa_run<true>(coarse, seeds, scratch, beta, dist2, coarse_sdf, s);
+}

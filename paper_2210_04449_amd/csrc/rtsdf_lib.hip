@@ -1,0 +1,9 @@
+// The whole library is one translation unit, so device globals (the error
+// word, the empty brick) need no relocatable device code.
+#include "api.hip"
+#include "voxelize.hip"
+#include "jfa.hip"
+#include "select.hip"
+#include "scene.hip"
+#include "trace.hip"
+#include "shadow.hip"

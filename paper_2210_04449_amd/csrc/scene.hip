@@ -1,0 +1,478 @@
+// Scene: triangles and their bounding volume hierarchy on the device.
+//
+// The paper does not say how its rays find their closest hits (it traces on
+// an RTX 2080 Ti).  gfx950 has no ray-tracing units, so the library keeps a
+// two-wide hierarchy in HBM and traverses it in software:
+//
+//   node (64 B): both children's boxes, so one node fetch tests two boxes
+//     xy0 = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
+//     xy1 = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
+//     z01 = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
+//     meta = (child0, child1, parent, 0)
+//   child >= 0 is an internal node, child < 0 a leaf: -1 - (first << 5 | count)
+//   with `count` triangles starting at `first` in the reordered triangle array.
+//   triangle (48 B): (v0, id) (v1, -) (v2, -) as float4s, in leaf order.
+//
+// Build (host, at creation): binned surface-area heuristic (32 bins per axis),
+// leaves of at most `leaf_size` triangles, depth capped (median splits below
+// kMaxBuildDepth) so the traversal stack of the tracer never overflows.
+// Boxes are padded outwards by 2^-17 * (scene scale) so the float slab test,
+// whose rounding error is far below that, never rejects a box the ray enters.
+// Refit (device): triangle records rewritten from new positions, boxes
+// recomputed bottom-up, the last child to finish continuing to the parent.
+#include <algorithm>
+#include <memory>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+
+namespace rtsdf {
+
+constexpr int kMaxBuildDepth = 48;  // median splits below; stack depth <= 63
+constexpr int kMaxLeaf = 31;
+
+struct alignas(16) BvhNode {
+    float4 xy0, xy1, z01;
+    int4 meta;
+};
+
+__host__ __device__ __forceinline__ int leaf_code(int first, int count) { return -1 - ((first << 5) | count); }
+__host__ __device__ __forceinline__ int leaf_first(int code) { return (-1 - code) >> 5; }
+__host__ __device__ __forceinline__ int leaf_count(int code) { return (-1 - code) & 31; }
+
+}  // namespace rtsdf
+
+struct rtsdf_scene {
+    int nv = 0, nt = 0;
+    int nnodes = 0;
+    int max_depth = 0;
+    int max_leaf = 0;
+    float pad = 0.f;
+    int device = 0;
+    rtsdf::BvhNode *nodes = nullptr;   // [nnodes]
+    float4 *tris = nullptr;            // [3 nt]
+    int4 *leaf_faces = nullptr;        // [nt] (i0, i1, i2, original id) in leaf order
+    float *vertices = nullptr;         // [3 nv] current positions
+    int32_t *faces = nullptr;          // [3 nt]
+    int32_t *refit_counter = nullptr;  // [nnodes]
+    int32_t *start_nodes = nullptr;    // internal nodes with two leaf children
+    int nstart = 0;
+    int64_t bytes = 0;
+};
+
+namespace rtsdf {
+
+namespace {
+
+struct Aabb {
+    float lo[3], hi[3];
+    void reset()
+    {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = INFINITY;
+            hi[a] = -INFINITY;
+        }
+    }
+    void grow(const Aabb &b)
+    {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], b.lo[a]);
+            hi[a] = std::max(hi[a], b.hi[a]);
+        }
+    }
+    void grow_pt(const float *p)
+    {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], p[a]);
+            hi[a] = std::max(hi[a], p[a]);
+        }
+    }
+    double area() const
+    {
+        const double dx = std::max(0.0, (double)hi[0] - lo[0]), dy = std::max(0.0, (double)hi[1] - lo[1]),
+                     dz = std::max(0.0, (double)hi[2] - lo[2]);
+        return dx * dy + dy * dz + dz * dx;
+    }
+};
+
+struct HostBuilder {
+    const float *v;
+    const int32_t *f;
+    int nt;
+    int leaf_size;
+    float pad;
+    std::vector<Aabb> tb;
+    std::vector<float> cen;
+    std::vector<int> idx;
+    std::vector<BvhNode> nodes;
+    int max_depth = 0, max_leaf = 0;
+
+    Aabb range_box(int b, int e) const
+    {
+        Aabb r;
+        r.reset();
+        for (int i = b; i < e; ++i) r.grow(tb[idx[i]]);
+        return r;
+    }
+
+    void padded(const Aabb &b, float lo[3], float hi[3]) const
+    {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::nextafter(b.lo[a] - pad, -INFINITY);
+            hi[a] = std::nextafter(b.hi[a] + pad, INFINITY);
+        }
+    }
+
+    // returns the child code for range [b, e)
+    int build(int b, int e, int depth)
+    {
+        const int count = e - b;
+        if (count <= leaf_size || depth >= kMaxBuildDepth + 14) {
+            if (count > kMaxLeaf) {  // cannot happen unless the depth cap bites; split by index
+                return build_split(b, e, b + count / 2, depth);
+            }
+            max_depth = std::max(max_depth, depth);
+            max_leaf = std::max(max_leaf, count);
+            return leaf_code(b, count);
+        }
+        Aabb cb;
+        cb.reset();
+        for (int i = b; i < e; ++i) cb.grow_pt(&cen[3 * idx[i]]);
+        int axis = 0;
+        for (int a = 1; a < 3; ++a)
+            if (cb.hi[a] - cb.lo[a] > cb.hi[axis] - cb.lo[axis]) axis = a;
+        if (!(cb.hi[axis] > cb.lo[axis])) return build_split(b, e, b + count / 2, depth);
+        if (depth >= kMaxBuildDepth) {  // median split on the longest axis
+            const int mid = b + count / 2;
+            std::nth_element(idx.begin() + b, idx.begin() + mid, idx.begin() + e, [&](int x, int y) {
+                return cen[3 * x + axis] < cen[3 * y + axis] || (cen[3 * x + axis] == cen[3 * y + axis] && x < y);
+            });
+            return build_split(b, e, mid, depth);
+        }
+        constexpr int NB = 32;
+        double best_cost = INFINITY;
+        int best_axis = -1, best_bin = -1;
+        for (int a = 0; a < 3; ++a) {
+            const float ext = cb.hi[a] - cb.lo[a];
+            if (!(ext > 0)) continue;
+            Aabb bins[NB];
+            int cnt[NB] = {0};
+            for (int k = 0; k < NB; ++k) bins[k].reset();
+            const float scale = NB / ext;
+            for (int i = b; i < e; ++i) {
+                int k = (int)((cen[3 * idx[i] + a] - cb.lo[a]) * scale);
+                k = std::min(std::max(k, 0), NB - 1);
+                bins[k].grow(tb[idx[i]]);
+                cnt[k]++;
+            }
+            double rarea[NB];
+            int rcnt[NB];
+            Aabb acc;
+            acc.reset();
+            int c = 0;
+            for (int k = NB - 1; k > 0; --k) {
+                acc.grow(bins[k]);
+                c += cnt[k];
+                rarea[k] = acc.area();
+                rcnt[k] = c;
+            }
+            acc.reset();
+            c = 0;
+            for (int k = 0; k < NB - 1; ++k) {
+                acc.grow(bins[k]);
+                c += cnt[k];
+                if (c == 0 || rcnt[k + 1] == 0) continue;
+                const double cost = acc.area() * c + rarea[k + 1] * rcnt[k + 1];
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best_axis = a;
+                    best_bin = k;
+                }
+            }
+        }
+        if (best_axis < 0) return build_split(b, e, b + count / 2, depth);
+        const Aabb box = range_box(b, e);
+        const double leaf_cost = box.area() * count;
+        if (count <= 8 && best_cost + box.area() >= leaf_cost) {
+            max_depth = std::max(max_depth, depth);
+            max_leaf = std::max(max_leaf, count);
+            return leaf_code(b, count);
+        }
+        const float ext = cb.hi[best_axis] - cb.lo[best_axis];
+        const float scale = NB / ext;
+        auto it = std::partition(idx.begin() + b, idx.begin() + e, [&](int t) {
+            int k = (int)((cen[3 * t + best_axis] - cb.lo[best_axis]) * scale);
+            k = std::min(std::max(k, 0), NB - 1);
+            return k <= best_bin;
+        });
+        int mid = (int)(it - idx.begin());
+        if (mid == b || mid == e) mid = b + count / 2;
+        return build_split(b, e, mid, depth);
+    }
+
+    int build_split(int b, int e, int mid, int depth)
+    {
+        const int id = (int)nodes.size();
+        nodes.emplace_back();
+        const int c0 = build(b, mid, depth + 1);
+        const int c1 = build(mid, e, depth + 1);
+        float lo0[3], hi0[3], lo1[3], hi1[3];
+        padded(range_box(b, mid), lo0, hi0);
+        padded(range_box(mid, e), lo1, hi1);
+        BvhNode &nd = nodes[id];
+        nd.xy0 = make_float4(lo0[0], hi0[0], lo0[1], hi0[1]);
+        nd.xy1 = make_float4(lo1[0], hi1[0], lo1[1], hi1[1]);
+        nd.z01 = make_float4(lo0[2], hi0[2], lo1[2], hi1[2]);
+        nd.meta = make_int4(c0, c1, -1, 0);
+        if (c0 >= 0) nodes[c0].meta.z = id;
+        if (c1 >= 0) nodes[c1].meta.z = id;
+        return id;
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- refit ----
+
+__global__ void refit_tris(const float *__restrict__ v, const int4 *__restrict__ lf, float4 *__restrict__ tris, int nt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    const int4 q = lf[i];
+    const int ids[3] = {q.x, q.y, q.z};
+    for (int k = 0; k < 3; ++k) {
+        const float *p = v + 3 * ids[k];
+        tris[3 * i + k] = make_float4(p[0], p[1], p[2], k == 0 ? __int_as_float(q.w) : 0.f);
+    }
+}
+
+__device__ __forceinline__ void leaf_box(const float4 *__restrict__ tris, int code, float pad, float lo[3], float hi[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = INFINITY;
+        hi[a] = -INFINITY;
+    }
+    const int first = leaf_first(code), cnt = leaf_count(code);
+    for (int i = first; i < first + cnt; ++i)
+        for (int k = 0; k < 3; ++k) {
+            const float4 p = tris[3 * i + k];
+            lo[0] = fminf(lo[0], p.x); hi[0] = fmaxf(hi[0], p.x);
+            lo[1] = fminf(lo[1], p.y); hi[1] = fmaxf(hi[1], p.y);
+            lo[2] = fminf(lo[2], p.z); hi[2] = fmaxf(hi[2], p.z);
+        }
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = nextafterf(lo[a] - pad, -INFINITY);
+        hi[a] = nextafterf(hi[a] + pad, INFINITY);
+    }
+}
+
+__device__ __forceinline__ void set_slot(BvhNode *nd, int slot, const float lo[3], const float hi[3])
+{
+    float *xy = slot == 0 ? &nd->xy0.x : &nd->xy1.x;
+    xy[0] = lo[0]; xy[1] = hi[0]; xy[2] = lo[1]; xy[3] = hi[1];
+    float *z = &nd->z01.x;
+    z[2 * slot] = lo[2];
+    z[2 * slot + 1] = hi[2];
+}
+
+__device__ __forceinline__ void get_slot(const BvhNode *nd, int slot, float lo[3], float hi[3])
+{
+    const float *xy = slot == 0 ? &nd->xy0.x : &nd->xy1.x;
+    lo[0] = xy[0]; hi[0] = xy[1]; lo[1] = xy[2]; hi[1] = xy[3];
+    const float *z = &nd->z01.x;
+    lo[2] = z[2 * slot];
+    hi[2] = z[2 * slot + 1];
+}
+
+// Every thread starts at an internal node whose children are both leaves and
+// climbs; at a node with two internal children only the second arrival goes on.
+__global__ void refit_nodes(BvhNode *nodes, const float4 *__restrict__ tris, const int32_t *__restrict__ starts,
+                            int nstart, int32_t *counter, float pad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nstart) return;
+    int node = starts[i];
+    while (node >= 0) {
+        BvhNode *nd = &nodes[node];
+        const int c[2] = {nd->meta.x, nd->meta.y};
+        float lo[2][3], hi[2][3];
+        for (int s = 0; s < 2; ++s) {
+            if (c[s] < 0) {
+                leaf_box(tris, c[s], pad, lo[s], hi[s]);
+                set_slot(nd, s, lo[s], hi[s]);
+            } else {
+                // the child's own slots are final (it finished before us)
+                const BvhNode *ch = &nodes[c[s]];
+                float l2[3], h2[3];
+                get_slot(ch, 0, lo[s], hi[s]);
+                get_slot(ch, 1, l2, h2);
+                for (int a = 0; a < 3; ++a) {
+                    lo[s][a] = fminf(lo[s][a], l2[a]);
+                    hi[s][a] = fmaxf(hi[s][a], h2[a]);
+                }
+                set_slot(nd, s, lo[s], hi[s]);
+            }
+        }
+        __threadfence();
+        const int parent = nd->meta.z;
+        if (parent < 0) break;
+        const BvhNode *pn = &nodes[parent];
+        const int internal_children = (pn->meta.x >= 0) + (pn->meta.y >= 0);
+        if (internal_children == 2) {
+            const int old = atomicAdd(&counter[parent], 1);
+            if (old == 0) break;  // the sibling subtree is not done yet; it will continue
+            __threadfence();
+        }
+        node = parent;
+    }
+}
+
+}  // namespace rtsdf
+
+extern "C" int rtsdf_scene_create(const float *vertices, int32_t nv, const int32_t *faces, int32_t nt,
+                                  int32_t leaf_size, rtsdf_scene **out, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!out || nv < 0 || nt < 0 || (nt > 0 && (!vertices || !faces))) return RTSDF_EINVAL;
+    if (leaf_size <= 0) leaf_size = 4;
+    if (leaf_size > kMaxLeaf) return RTSDF_EINVAL;
+    if ((int64_t)nt >= (int64_t)1 << 26) return RTSDF_EINVAL;
+    *out = nullptr;
+    hipStream_t s = as_stream(stream);
+    std::vector<float> hv((size_t)3 * nv);
+    std::vector<int32_t> hf((size_t)3 * nt);
+    if (nv > 0) RTSDF_TRY(hipMemcpyAsync(hv.data(), vertices, sizeof(float) * 3 * nv, hipMemcpyDeviceToHost, s));
+    if (nt > 0) RTSDF_TRY(hipMemcpyAsync(hf.data(), faces, sizeof(int32_t) * 3 * nt, hipMemcpyDeviceToHost, s));
+    RTSDF_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < 3 * nt; ++i)
+        if (hf[i] < 0 || hf[i] >= nv) return RTSDF_EINVAL;
+    float scale = 1.0f;
+    for (float x : hv) {
+        if (!std::isfinite(x)) return RTSDF_EINVAL;
+        scale = std::max(scale, std::fabs(x));
+    }
+    HostBuilder B{hv.data(), hf.data(), nt, leaf_size, std::ldexp(scale, -17), {}, {}, {}, {}};
+    B.tb.resize(nt);
+    B.cen.resize((size_t)3 * nt);
+    B.idx.resize(nt);
+    for (int t = 0; t < nt; ++t) {
+        B.tb[t].reset();
+        for (int k = 0; k < 3; ++k) B.tb[t].grow_pt(&hv[3 * hf[3 * t + k]]);
+        for (int a = 0; a < 3; ++a) B.cen[3 * t + a] = 0.5f * (B.tb[t].lo[a] + B.tb[t].hi[a]);
+        B.idx[t] = t;
+    }
+    if (nt > 0) {
+        const int code = B.build(0, nt, 0);  // an internal root is node 0
+        if (code < 0) {
+            // the whole mesh is one leaf: a root holding it and an empty leaf
+            B.nodes.emplace_back();
+            float lo[3], hi[3];
+            B.padded(B.range_box(0, nt), lo, hi);
+            BvhNode &nd = B.nodes[0];
+            nd.xy0 = nd.xy1 = make_float4(lo[0], hi[0], lo[1], hi[1]);
+            nd.z01 = make_float4(lo[2], hi[2], lo[2], hi[2]);
+            nd.meta = make_int4(code, leaf_code(0, 0), -1, 0);
+            B.max_depth = 1;
+        }
+    }
+    std::unique_ptr<rtsdf_scene> sc(new rtsdf_scene());
+    sc->nv = nv;
+    sc->nt = nt;
+    sc->nnodes = (int)B.nodes.size();
+    sc->max_depth = B.max_depth;
+    sc->max_leaf = B.max_leaf;
+    sc->pad = B.pad;
+    RTSDF_TRY(hipGetDevice(&sc->device));
+    std::vector<float4> htri((size_t)3 * std::max(nt, 1));
+    std::vector<int4> hlf(std::max(nt, 1));
+    for (int i = 0; i < nt; ++i) {
+        const int t = B.idx[i];
+        for (int k = 0; k < 3; ++k) {
+            const float *p = &hv[3 * hf[3 * t + k]];
+            float idf = 0.f;
+            if (k == 0) std::memcpy(&idf, &t, sizeof(float));
+            htri[3 * i + k] = make_float4(p[0], p[1], p[2], idf);
+        }
+        hlf[i] = make_int4(hf[3 * t], hf[3 * t + 1], hf[3 * t + 2], t);
+    }
+    std::vector<int32_t> starts;
+    for (int i = 0; i < sc->nnodes; ++i)
+        if (B.nodes[i].meta.x < 0 && B.nodes[i].meta.y < 0) starts.push_back(i);
+    sc->nstart = (int)starts.size();
+    auto alloc = [&](void **p, size_t bytes) -> bool {
+        if (bytes == 0) bytes = 16;
+        if (hipMalloc(p, bytes) != hipSuccess) return false;
+        sc->bytes += (int64_t)bytes;
+        return true;
+    };
+    const size_t nn = std::max(sc->nnodes, 1);
+    if (!alloc((void **)&sc->nodes, sizeof(BvhNode) * nn) || !alloc((void **)&sc->tris, sizeof(float4) * htri.size()) ||
+        !alloc((void **)&sc->leaf_faces, sizeof(int4) * hlf.size()) ||
+        !alloc((void **)&sc->vertices, sizeof(float) * 3 * std::max(nv, 1)) ||
+        !alloc((void **)&sc->faces, sizeof(int32_t) * 3 * std::max(nt, 1)) ||
+        !alloc((void **)&sc->refit_counter, sizeof(int32_t) * nn) ||
+        !alloc((void **)&sc->start_nodes, sizeof(int32_t) * std::max<size_t>(starts.size(), 1))) {
+        rtsdf_scene_destroy(sc.release());
+        return RTSDF_ENOMEM;
+    }
+    bool ok = true;
+    if (sc->nnodes) ok &= hipMemcpyAsync(sc->nodes, B.nodes.data(), sizeof(BvhNode) * sc->nnodes, hipMemcpyHostToDevice, s) == hipSuccess;
+    ok &= hipMemcpyAsync(sc->tris, htri.data(), sizeof(float4) * htri.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    ok &= hipMemcpyAsync(sc->leaf_faces, hlf.data(), sizeof(int4) * hlf.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    if (nv) ok &= hipMemcpyAsync(sc->vertices, hv.data(), sizeof(float) * 3 * nv, hipMemcpyHostToDevice, s) == hipSuccess;
+    if (nt) ok &= hipMemcpyAsync(sc->faces, hf.data(), sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s) == hipSuccess;
+    if (!starts.empty())
+        ok &= hipMemcpyAsync(sc->start_nodes, starts.data(), sizeof(int32_t) * starts.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    ok &= hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+        rtsdf_scene_destroy(sc.release());
+        return RTSDF_EHIP;
+    }
+    *out = sc.release();
+    return RTSDF_OK;
+}
+
+extern "C" int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!scene || (scene->nv > 0 && !vertices)) return RTSDF_EINVAL;
+    hipStream_t s = as_stream(stream);
+    if (scene->nv > 0 && vertices != scene->vertices)
+        RTSDF_TRY(hipMemcpyAsync(scene->vertices, vertices, sizeof(float) * 3 * scene->nv, hipMemcpyDeviceToDevice, s));
+    if (scene->nt == 0) return RTSDF_OK;
+    refit_tris<<<dim3((scene->nt + 255) / 256), dim3(256), 0, s>>>(scene->vertices, scene->leaf_faces, scene->tris, scene->nt);
+    RTSDF_CHECK_LAUNCH();
+    int rc = launch_fill<int32_t>(scene->refit_counter, 0, scene->nnodes, s);
+    if (rc != RTSDF_OK) return rc;
+    refit_nodes<<<dim3((scene->nstart + 255) / 256), dim3(256), 0, s>>>(scene->nodes, scene->tris, scene->start_nodes,
+                                                                         scene->nstart, scene->refit_counter, scene->pad);
+    RTSDF_CHECK_LAUNCH();
+    return RTSDF_OK;
+}
+
+extern "C" int rtsdf_scene_info_get(const rtsdf_scene *scene, rtsdf_scene_info *info)
+{
+    if (!scene || !info) return RTSDF_EINVAL;
+    info->nv = scene->nv;
+    info->nt = scene->nt;
+    info->nodes = scene->nnodes;
+    info->max_depth = scene->max_depth;
+    info->leaf_size = scene->max_leaf;
+    info->device_bytes = scene->bytes;
+    return RTSDF_OK;
+}
+
+extern "C" void rtsdf_scene_destroy(rtsdf_scene *scene)
+{
+    if (!scene) return;
+    (void)hipFree(scene->nodes);
+    (void)hipFree(scene->tris);
+    (void)hipFree(scene->leaf_faces);
+    (void)hipFree(scene->vertices);
+    (void)hipFree(scene->faces);
+    (void)hipFree(scene->refit_counter);
+    (void)hipFree(scene->start_nodes);
+    delete scene;
+}

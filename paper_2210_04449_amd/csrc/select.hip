@@ -1,0 +1,191 @@
+// Selection of the fine texels to ray trace (paper Sec. 2.2; the case
+// c <= d of Eq. (1)), as a stream compaction.
+//
+// A fine texel is selected when the coarse voxel containing its centre has
+// D^2 <= K, K = floor(((d + beta) / h_c)^2), which is c <= d in exact
+// arithmetic.  Since the fine size is a power-of-two multiple r of the coarse
+// size, the r^3 fine children of a coarse voxel are consecutive in fine Morton
+// order (their codes are (coarse code) * r^3 + child), so the queue is built by
+// compacting the coarse voxels in Morton order and expanding each selected one
+// into its r^3 children.
+//
+//   select_count   one coarse voxel per lane in Morton order; wavefront ballot
+//                  + popcount, per-block totals
+//   select_scan    one workgroup: exclusive prefix of the block totals
+//   select_scatter ballot + mbcnt rank inside the wavefront, wave offsets
+//                  through LDS, block offset from the scan; writes r^3 queue
+//                  entries per selected voxel
+//   select_mask    the linear uint8 mask, four texels per lane
+// No workgroup ever waits on another, and the queue order is deterministic.
+#include "common.hpp"
+
+namespace rtsdf {
+
+constexpr int kSelBlock = 256;
+constexpr int kSelItems = 4;  // coarse voxels per lane per block
+constexpr int kSelPerBlock = kSelBlock * kSelItems;
+
+__device__ __forceinline__ bool coarse_selected(const int32_t *__restrict__ d2, uint32_t m, int logn, int K)
+{
+    const uint32_t x = compact1by2(m), y = compact1by2(m >> 1), z = compact1by2(m >> 2);
+    const int64_t idx = x + ((int64_t)y << logn) + ((int64_t)z << (2 * logn));
+    return d2[idx] <= K;
+}
+
+__device__ __forceinline__ uint32_t wave_prefix(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__global__ void __launch_bounds__(kSelBlock) select_count(const int32_t *__restrict__ d2, int logn, int K,
+                                                          uint32_t total, uint32_t *__restrict__ block_sums)
+{
+    __shared__ uint32_t wsum[kSelBlock / kWave];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t cnt = 0;
+    for (int it = 0; it < kSelItems; ++it) {
+        const uint32_t m = blockIdx.x * kSelPerBlock + it * kSelBlock + threadIdx.x;
+        const bool sel = m < total && coarse_selected(d2, m, logn, K);
+        cnt += (uint32_t)__popcll(__ballot(sel));
+    }
+    if (lane == 0) wsum[wave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int w = 0; w < kSelBlock / kWave; ++w) s += wsum[w];
+        block_sums[blockIdx.x] = s;
+    }
+}
+
+// Exclusive scan of nblocks totals in one workgroup of 1024 lanes; also the
+// grand total -> count (texels = coarse * r3) and the overflow check.
+__global__ void __launch_bounds__(1024) select_scan(uint32_t *__restrict__ sums, uint32_t nblocks, uint32_t r3,
+                                                    int32_t *__restrict__ count, int32_t cap)
+{
+    __shared__ uint32_t part[1024];
+    const uint32_t t = threadIdx.x;
+    const uint32_t per = (nblocks + 1023) / 1024;
+    const uint32_t b0 = t * per;
+    uint32_t local = 0;
+    for (uint32_t i = 0; i < per; ++i)
+        if (b0 + i < nblocks) local += sums[b0 + i];
+    part[t] = local;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - local;  // exclusive
+    for (uint32_t i = 0; i < per; ++i) {
+        if (b0 + i < nblocks) {
+            const uint32_t v = sums[b0 + i];
+            sums[b0 + i] = run;
+            run += v;
+        }
+    }
+    if (t == 1023) {
+        const uint64_t texels = (uint64_t)part[1023] * r3;
+        *count = texels > (uint64_t)INT32_MAX ? INT32_MAX : (int32_t)texels;
+        if (texels > (uint64_t)cap) raise_error(RTSDF_ERR_QUEUE_FULL);
+    }
+}
+
+__global__ void __launch_bounds__(kSelBlock) select_scatter(const int32_t *__restrict__ d2, int logn, int K,
+                                                            uint32_t total, const uint32_t *__restrict__ offsets,
+                                                            int logr, int nf, int32_t *__restrict__ queue,
+                                                            int32_t cap)
+{
+    __shared__ uint32_t wsum[kSelItems][kSelBlock / kWave];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool sel[kSelItems];
+    uint32_t rank[kSelItems];
+    for (int it = 0; it < kSelItems; ++it) {
+        const uint32_t m = blockIdx.x * kSelPerBlock + it * kSelBlock + threadIdx.x;
+        sel[it] = m < total && coarse_selected(d2, m, logn, K);
+        const uint64_t bal = __ballot(sel[it]);
+        rank[it] = wave_prefix(bal);
+        if (lane == 0) wsum[it][wave] = (uint32_t)__popcll(bal);
+    }
+    __syncthreads();
+    const uint32_t r3 = 1u << (3 * logr);
+    uint32_t base = offsets[blockIdx.x];
+    for (int it = 0; it < kSelItems; ++it) {
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += wsum[it][w];
+        if (sel[it]) {
+            const uint32_t m = blockIdx.x * kSelPerBlock + it * kSelBlock + threadIdx.x;
+            const uint64_t pos = ((uint64_t)(base + before + rank[it])) * r3;
+            const uint32_t cx = compact1by2(m), cy = compact1by2(m >> 1), cz = compact1by2(m >> 2);
+            for (uint32_t c = 0; c < r3; ++c) {
+                if (pos + c >= (uint64_t)cap) break;
+                const uint32_t fx = (cx << logr) | compact1by2(c), fy = (cy << logr) | compact1by2(c >> 1),
+                               fz = (cz << logr) | compact1by2(c >> 2);
+                queue[pos + c] = (int32_t)(fx + (uint32_t)nf * (fy + (uint32_t)nf * fz));
+            }
+        }
+        for (int w = 0; w < kSelBlock / kWave; ++w) base += wsum[it][w];
+    }
+}
+
+__global__ void __launch_bounds__(256) select_mask(const int32_t *__restrict__ d2, int logn, int logr, int nf, int K,
+                                                   int64_t nquads, uint32_t *__restrict__ mask4)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nquads) return;
+    const int64_t j = q * 4;
+    const int x = (int)(j % nf), y = (int)((j / nf) % nf), z = (int)(j / ((int64_t)nf * nf));
+    const int cy = y >> logr, cz = z >> logr;
+    const int64_t row = ((int64_t)cy << logn) + ((int64_t)cz << (2 * logn));
+    uint32_t w = 0;
+    for (int i = 0; i < 4; ++i) w |= (uint32_t)(d2[row + ((x + i) >> logr)] <= K) << (8 * i);
+    mask4[q] = w;
+}
+
+}  // namespace rtsdf
+
+extern "C" size_t rtsdf_select_workspace_size(int32_t coarse_n)
+{
+    using namespace rtsdf;
+    if (coarse_n <= 0) return 0;
+    const int64_t total = (int64_t)coarse_n * coarse_n * coarse_n;
+    return (size_t)(((total + kSelPerBlock - 1) / kSelPerBlock) * sizeof(uint32_t) + 256);
+}
+
+extern "C" int rtsdf_select(rtsdf_grid coarse, const int32_t *dist2, rtsdf_grid fine, float beta, float d,
+                            uint8_t *mask, int32_t *queue, int32_t queue_cap, int32_t *count, void *workspace,
+                            rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!grid_ok(coarse) || !grid_ok(fine) || !is_pow2(coarse.n) || coarse.n > 512) return RTSDF_EINVAL;
+    if (!is_pow2(fine.n) || fine.n < coarse.n || fine.n > 1024 || fine.n < 4) return RTSDF_EINVAL;
+    if ((double)fine.h * fine.n != (double)coarse.h * coarse.n) return RTSDF_EINVAL;
+    if (fine.lo[0] != coarse.lo[0] || fine.lo[1] != coarse.lo[1] || fine.lo[2] != coarse.lo[2]) return RTSDF_EINVAL;
+    if (!dist2 || !mask || !count || !workspace || queue_cap < 0 || (queue_cap > 0 && !queue)) return RTSDF_EINVAL;
+    if (!(beta == beta) || !(d == d)) return RTSDF_EINVAL;
+    hipStream_t s = as_stream(stream);
+    const int logn = ilog2(coarse.n), logr = ilog2(fine.n / coarse.n);
+    const double q = ((double)d + (double)beta) / (double)coarse.h;
+    int K;
+    if (q < 0) K = -1;
+    else {
+        const double k = floor(q * q);
+        K = k > (double)INT32_MAX ? INT32_MAX : (int)k;
+    }
+    const uint32_t total = (uint32_t)((int64_t)coarse.n * coarse.n * coarse.n);
+    const uint32_t nblocks = (total + kSelPerBlock - 1) / kSelPerBlock;
+    uint32_t *sums = static_cast<uint32_t *>(workspace);
+    select_count<<<dim3(nblocks), dim3(kSelBlock), 0, s>>>(dist2, logn, K, total, sums);
+    RTSDF_CHECK_LAUNCH();
+    select_scan<<<dim3(1), dim3(1024), 0, s>>>(sums, nblocks, 1u << (3 * logr), count, queue_cap);
+    RTSDF_CHECK_LAUNCH();
+    select_scatter<<<dim3(nblocks), dim3(kSelBlock), 0, s>>>(dist2, logn, K, total, sums, logr, fine.n, queue,
+                                                              queue_cap);
+    RTSDF_CHECK_LAUNCH();
+    const int64_t nquads = (int64_t)fine.n * fine.n * fine.n / 4;
+    select_mask<<<dim3((unsigned)((nquads + 255) / 256)), dim3(256), 0, s>>>(
+        dist2, logn, logr, fine.n, K, nquads, reinterpret_cast<uint32_t *>(mask));
+    RTSDF_CHECK_LAUNCH();
+    return RTSDF_OK;
+}

@@ -1,0 +1,655 @@
+// Fine-SDF ray tracing and temporal accumulation (paper Sec. 2.2, Eq. (1)),
+// the vertex gradient of the traced distances, and two helper entry points
+// (directions, closest hits) that expose the same arithmetic.
+//
+// Per selected texel and frame, rays_per_texel rays leave the texel centre
+// towards uniformly random points of the unit sphere; each ray's closest hit
+// distance is found in the bounding volume hierarchy; the smallest of the
+// frame is r_t, which enters Eq. (1); front/back counts of the closest hits
+// vote the sign.
+//
+// Random directions: Philox4x64 with 10 rounds (Salmon et al., SC'11) keyed
+// by (seed, 0) with counter (texel, frame << 32 | ray, scene, attempt); 32-bit
+// halves become odd multiples of 2^-23 in (-1, 1); Marsaglia's 1972 mapping of
+// the first pair inside the unit disc gives the direction.  Every float
+// operation there is an explicitly rounded intrinsic, so the directions are
+// reproducible bit for bit on any IEEE machine.
+//
+// Closest hit: software traversal of the two-wide hierarchy with a per-lane
+// stack in LDS (its depth is the hierarchy's depth, so it never overflows)
+// and the watertight ray/triangle test of Woop, Benthin and Wald (JCGT 2013):
+// vertices are mapped into a ray space where the ray is the +z axis (a
+// per-ray affine map: axis permutation plus shear), 2D edge functions decide
+// coverage (re-evaluated in double when one is exactly zero), so a ray that
+// crosses a shared edge hits at least one of its triangles.  Ties in t go to
+// the lower triangle index; t must be > 0.
+//
+// Work distribution: persistent wavefronts; one lane owns one selected texel
+// and traces its rays one after another.  Lanes whose texel is finished are
+// refilled from the compacted queue by one atomic add per wavefront (ballot +
+// mbcnt to hand out the slots), so the queue is consumed in Morton order and
+// no lane waits for a whole wavefront of texels to finish.
+#include "common.hpp"
+
+namespace rtsdf {
+
+// ------------------------------------------------------------------ RNG ----
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        const uint64_t y0 = hi1 ^ c[1] ^ k0, y2 = hi0 ^ c[3] ^ k1;
+        c[0] = y0;
+        c[1] = lo1;
+        c[2] = y2;
+        c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ float uniform_pm1(uint32_t h)
+{
+    return (float)((int32_t)((h >> 9) << 1) + 1 - 8388608) * 0x1p-23f;
+}
+
+__device__ __noinline__ float3 sphere_dir(uint64_t seed, uint32_t texel, uint32_t frame, uint32_t ray, uint32_t scene)
+{
+    for (uint32_t attempt = 0; attempt < 8; ++attempt) {
+        uint64_t c[4] = {(uint64_t)texel, ((uint64_t)frame << 32) | ray, (uint64_t)scene, (uint64_t)attempt};
+        philox4x64_10(c, seed, 0);
+        for (int p = 0; p < 4; ++p) {
+            const float x1 = uniform_pm1((uint32_t)c[p]);
+            const float x2 = uniform_pm1((uint32_t)(c[p] >> 32));
+            const float s = __fadd_rn(__fmul_rn(x1, x1), __fmul_rn(x2, x2));
+            if (s < 1.0f) {
+                const float q = __fsqrt_rn(__fsub_rn(1.0f, s));
+                return make_float3(__fmul_rn(__fmul_rn(2.0f, x1), q), __fmul_rn(__fmul_rn(2.0f, x2), q),
+                                   __fsub_rn(1.0f, __fmul_rn(2.0f, s)));
+            }
+        }
+    }
+    return make_float3(0.0f, 0.0f, 1.0f);
+}
+
+// texel centre: lo + (i + 1/2) h per axis, float ops rounded once each
+__device__ __forceinline__ float texel_coord(float lo, int i, float h)
+{
+    return __fadd_rn(lo, __fmul_rn(__fadd_rn((float)i, 0.5f), h));
+}
+
+// ------------------------------------------------------------- geometry ----
+
+struct RaySetup {
+    float ix, iy, iz;    // 1 / direction (zero components replaced by +-1e-12)
+    float oix, oiy, oiz; // origin * inverse
+    float m[9], t[3];    // ray-space map: x'_r = m[3r] x + m[3r+1] y + m[3r+2] z + t[r]
+    float len;           // |direction|
+};
+
+__device__ __forceinline__ float safe_inv(float d)
+{
+    const float a = fabsf(d) < 1e-12f ? copysignf(1e-12f, d) : d;
+    return 1.0f / a;
+}
+
+__device__ __forceinline__ void ray_setup(float ox, float oy, float oz, float dx, float dy, float dz, RaySetup &R)
+{
+    R.ix = safe_inv(dx);
+    R.iy = safe_inv(dy);
+    R.iz = safe_inv(dz);
+    R.oix = ox * R.ix;
+    R.oiy = oy * R.iy;
+    R.oiz = oz * R.iz;
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    int kz = ay > ax ? 1 : 0;
+    if (az > fmaxf(ax, ay)) kz = 2;
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    const float d[3] = {dx, dy, dz};
+    const float o[3] = {ox, oy, oz};
+    const float dkz = kz == 0 ? dx : (kz == 1 ? dy : dz);
+    if (dkz < 0.0f) {
+        const int t = kx;
+        kx = ky;
+        ky = t;
+    }
+    const float dkx = kx == 0 ? d[0] : (kx == 1 ? d[1] : d[2]);
+    const float dky = ky == 0 ? d[0] : (ky == 1 ? d[1] : d[2]);
+    const float Sx = dkx / dkz, Sy = dky / dkz, Sz = 1.0f / dkz;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        R.m[0 + j] = j == kx ? 1.0f : (j == kz ? -Sx : 0.0f);
+        R.m[3 + j] = j == ky ? 1.0f : (j == kz ? -Sy : 0.0f);
+        R.m[6 + j] = j == kz ? Sz : 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) R.t[r] = -(R.m[3 * r] * o[0] + R.m[3 * r + 1] * o[1] + R.m[3 * r + 2] * o[2]);
+    R.len = sqrtf(dx * dx + dy * dy + dz * dz);
+}
+
+__device__ __forceinline__ void to_ray_space(const RaySetup &R, float4 v, float &x, float &y, float &z)
+{
+    x = fmaf(R.m[0], v.x, fmaf(R.m[1], v.y, fmaf(R.m[2], v.z, R.t[0])));
+    y = fmaf(R.m[3], v.x, fmaf(R.m[4], v.y, fmaf(R.m[5], v.z, R.t[1])));
+    z = fmaf(R.m[6], v.x, fmaf(R.m[7], v.y, fmaf(R.m[8], v.z, R.t[2])));
+}
+
+// Watertight test; updates the closest hit (t, id) with ties to the lower id.
+__device__ __forceinline__ void tri_test(const RaySetup &R, float4 a, float4 b, float4 c, float &tbest, int &ibest,
+                                         bool &front)
+{
+    float Ax, Ay, Az, Bx, By, Bz, Cx, Cy, Cz;
+    to_ray_space(R, a, Ax, Ay, Az);
+    to_ray_space(R, b, Bx, By, Bz);
+    to_ray_space(R, c, Cx, Cy, Cz);
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return;
+    const float det = U + V + W;
+    if (det == 0.0f) return;
+    const float T = U * Az + V * Bz + W * Cz;
+    const float t = T * __builtin_amdgcn_rcpf(det);
+    if (!(t > 0.0f)) return;
+    const int id = __float_as_int(a.w);
+    if (t < tbest || (t == tbest && id < ibest)) {
+        tbest = t;
+        ibest = id;
+        front = det > 0.0f;
+    }
+}
+
+// slab test against a padded box; returns entry distance or +inf on a miss
+__device__ __forceinline__ float box_entry(const RaySetup &R, float lx, float hx, float ly, float hy, float lz, float hz,
+                                           float tbest)
+{
+    const float x0 = fmaf(lx, R.ix, -R.oix), x1 = fmaf(hx, R.ix, -R.oix);
+    const float y0 = fmaf(ly, R.iy, -R.oiy), y1 = fmaf(hy, R.iy, -R.oiy);
+    const float z0 = fmaf(lz, R.iz, -R.oiz), z1 = fmaf(hz, R.iz, -R.oiz);
+    const float tmin = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
+    const float tmax = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tbest));
+    return tmin <= tmax ? tmin : __builtin_inff();
+}
+
+constexpr int kDone = INT32_MIN;
+
+struct BvhView {
+    const BvhNode *nodes;
+    const float4 *tris;
+};
+
+// One traversal step of one lane: an internal node tests both child boxes
+// and descends into the nearer hit child (pushing the farther); a leaf tests
+// its triangles; then the lane pops.  `stk` points at the lane's stack slot 0
+// in LDS, entries `stride` words apart.
+__device__ __forceinline__ void trav_step(const BvhView &S, const RaySetup &R, int &node, int &sp, int *stk,
+                                          int stride, float &tbest, int &ibest, bool &front)
+{
+    if (node >= 0) {
+        const BvhNode *nd = S.nodes + node;
+        const float4 a = nd->xy0, b = nd->xy1, z = nd->z01;
+        const int4 m = nd->meta;
+        const float t0 = box_entry(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest);
+        const float t1 = box_entry(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest);
+        const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
+        if (h0 && h1) {
+            const bool first0 = t0 <= t1;
+            stk[sp * stride] = first0 ? m.y : m.x;
+            ++sp;
+            node = first0 ? m.x : m.y;
+            return;
+        }
+        if (h0 || h1) {
+            node = h0 ? m.x : m.y;
+            return;
+        }
+    } else {
+        const int first = leaf_first(node), cnt = leaf_count(node);
+        for (int i = first; i < first + cnt; ++i)
+            tri_test(R, S.tris[3 * i], S.tris[3 * i + 1], S.tris[3 * i + 2], tbest, ibest, front);
+    }
+    node = sp > 0 ? stk[--sp * stride] : kDone;
+}
+
+// ------------------------------------------------------ persistent tracer ----
+
+struct TraceArgs {
+    BvhView bvh;
+    int nt;
+    const int32_t *queue;
+    const int32_t *count;
+    int32_t queue_cap;
+    int32_t *cursor;
+    const float *coarse_sdf;
+    int nc, logr, nf, lognf;
+    float lox, loy, loz, hf;
+    int rays;
+    uint32_t frame;
+    const uint32_t *frame_ptr;
+    uint64_t seed;
+    uint32_t scene_id;
+    float alpha;
+    float *u;
+    uint32_t *hits;
+    int32_t *arg_tri;
+    int32_t *arg_ray;
+    float *fine;
+};
+
+constexpr int kTraceWaves = 4;
+
+template <int SD, int REFILL>
+__global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArgs A)
+{
+    __shared__ int stack_mem[kTraceWaves * SD * kWave];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int *stk = stack_mem + wave * SD * kWave + lane;
+    const uint32_t frame = A.frame_ptr ? *A.frame_ptr : A.frame;
+    const int total = min(*A.count, A.queue_cap);
+    const int nfm = A.nf - 1;
+
+    int texel = -1, r = 0;
+    float ox = 0.f, oy = 0.f, oz = 0.f;
+    RaySetup R;
+    float tbest = __builtin_inff();
+    int ibest = -1, node = kDone, sp = 0;
+    bool front = false;
+    float rmin = __builtin_inff();
+    int argray = -1, argtri = -1;
+    uint32_t nF = 0, nB = 0;
+    bool exhausted = false;
+
+    auto start_ray = [&]() {
+        const float3 d = sphere_dir(A.seed, (uint32_t)texel, frame, (uint32_t)r, A.scene_id);
+        ray_setup(ox, oy, oz, d.x, d.y, d.z, R);
+        tbest = __builtin_inff();
+        ibest = -1;
+        front = false;
+        node = A.nt > 0 ? 0 : kDone;
+        sp = 0;
+    };
+
+    while (true) {
+        // hand out texels to idle lanes, one atomic per wavefront
+        const uint64_t need = __ballot(texel < 0);
+        if (need != 0 && !exhausted) {
+            const int nneed = __popcll(need);
+            int base = 0;
+            if (lane == __ffsll((unsigned long long)need) - 1) base = atomicAdd(A.cursor, nneed);
+            base = __shfl(base, __ffsll((unsigned long long)need) - 1);
+            if (base + nneed >= total) exhausted = true;
+            if (texel < 0) {
+                const int slot = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+                if (slot < total) {
+                    const int j = A.queue[slot];
+                    if (j >= 0 && (int64_t)j < ((int64_t)1 << (3 * A.lognf))) {
+                        texel = j;
+                        r = 0;
+                        rmin = __builtin_inff();
+                        argray = argtri = -1;
+                        nF = nB = 0;
+                        ox = texel_coord(A.lox, j & nfm, A.hf);
+                        oy = texel_coord(A.loy, (j >> A.lognf) & nfm, A.hf);
+                        oz = texel_coord(A.loz, j >> (2 * A.lognf), A.hf);
+                        start_ray();
+                    }
+                }
+            }
+        }
+        if (__ballot(texel >= 0) == 0) {
+            if (exhausted) break;
+            continue;
+        }
+        // traverse until enough lanes have finished their ray (or are idle)
+        while (true) {
+            if (texel >= 0 && node != kDone) trav_step(A.bvh, R, node, sp, stk, kWave, tbest, ibest, front);
+            const uint64_t done = __ballot(texel < 0 || node == kDone);
+            const int ndone = __popcll(done);
+            if (ndone >= REFILL || (ndone > 0 && exhausted && ndone == __popcll(__ballot(true)))) break;
+            if (ndone == kWave) break;
+        }
+        if (texel >= 0 && node == kDone) {
+            if (ibest >= 0) {
+                const float dist = tbest * R.len;
+                if (dist < rmin) {
+                    rmin = dist;
+                    argray = r;
+                    argtri = ibest;
+                }
+                if (front) ++nF;
+                else ++nB;
+            }
+            ++r;
+            if (r < A.rays) {
+                start_ray();
+            } else {
+                // Eq. (1) on the unsigned state, then the sign vote
+                const int j = texel;
+                const int x = j & nfm, y = (j >> A.lognf) & nfm, z = j >> (2 * A.lognf);
+                const float c = A.coarse_sdf[(x >> A.logr) + A.nc * ((y >> A.logr) + A.nc * (z >> A.logr))];
+                const float uprev = A.u[j];
+                const uint32_t h = A.hits[j];
+                const uint32_t F = min((h & 0xFFFFu) + nF, 0xFFFFu), B = min((h >> 16) + nB, 0xFFFFu);
+                float uu;
+                if (A.alpha == 1.0f) {
+                    uu = uprev;
+                } else {
+                    uu = A.alpha * uprev + (1.0f - A.alpha) * fmaxf(c, 0.0f);
+                }
+                if (rmin < uu) {
+                    uu = rmin;
+                    A.arg_tri[j] = argtri;
+                    A.arg_ray[j] = (int32_t)((frame << 8) | (uint32_t)argray);
+                } else if (A.alpha != 1.0f) {
+                    A.arg_tri[j] = -1;
+                    A.arg_ray[j] = -1;
+                }
+                A.u[j] = uu;
+                A.hits[j] = F | (B << 16);
+                float f = isinf(uu) ? c : uu;
+                A.fine[j] = B > F ? -f : f;
+                texel = -1;
+                node = kDone;
+            }
+        }
+    }
+}
+
+// Unselected texels: fine = coarse value, state reset (Eq. (1), case c > d).
+__global__ void __launch_bounds__(256) trace_fill_unselected(const uint8_t *__restrict__ mask,
+                                                             const float *__restrict__ coarse_sdf, int nc, int logr,
+                                                             int lognf, int64_t ntex, float *__restrict__ u,
+                                                             uint32_t *__restrict__ hits, int32_t *__restrict__ arg_tri,
+                                                             int32_t *__restrict__ arg_ray, float *__restrict__ fine)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ntex || mask[j]) return;
+    const int nfm = (1 << lognf) - 1;
+    const int x = (int)(j & nfm), y = (int)((j >> lognf) & nfm), z = (int)(j >> (2 * lognf));
+    fine[j] = coarse_sdf[(x >> logr) + nc * ((y >> logr) + nc * (z >> logr))];
+    if (u[j] != __builtin_inff() || hits[j] != 0u || arg_tri[j] != -1) {
+        u[j] = __builtin_inff();
+        hits[j] = 0u;
+        arg_tri[j] = -1;
+        arg_ray[j] = -1;
+    }
+}
+
+__global__ void __launch_bounds__(256) accum_reset_kernel(int64_t n, float *u, uint32_t *hits, int32_t *at, int32_t *ar)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) {
+        u[i] = __builtin_inff();
+        hits[i] = 0u;
+        at[i] = -1;
+        ar[i] = -1;
+    }
+}
+
+// ---------------------------------------------------------- helpers ----
+
+__global__ void directions_kernel(const int32_t *texel, const uint32_t *frame, const int32_t *ray, int n, uint64_t seed,
+                                  uint32_t scene, float *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float3 d = sphere_dir(seed, (uint32_t)texel[i], frame[i], (uint32_t)ray[i], scene);
+    out[3 * i] = d.x;
+    out[3 * i + 1] = d.y;
+    out[3 * i + 2] = d.z;
+}
+
+template <int SD>
+__global__ void __launch_bounds__(256) closest_hits_kernel(BvhView S, int nt, const float *__restrict__ o,
+                                                           const float *__restrict__ d, int n, float *t_out,
+                                                           int32_t *tri_out, int32_t *front_out)
+{
+    __shared__ int stack_mem[4 * SD * kWave];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int *stk = stack_mem + wave * SD * kWave + lane;
+    if (i >= n) return;
+    RaySetup R;
+    ray_setup(o[3 * i], o[3 * i + 1], o[3 * i + 2], d[3 * i], d[3 * i + 1], d[3 * i + 2], R);
+    float tbest = __builtin_inff();
+    int ibest = -1, node = nt > 0 ? 0 : kDone, sp = 0;
+    bool front = false;
+    while (node != kDone) trav_step(S, R, node, sp, stk, kWave, tbest, ibest, front);
+    t_out[i] = ibest >= 0 ? tbest : __builtin_inff();
+    tri_out[i] = ibest;
+    front_out[i] = ibest >= 0 && front;
+}
+
+// Gradient scatter: dL/dv_i += dL/df * sign * |w| * b_i * n / (n . w).
+__global__ void __launch_bounds__(256) trace_backward_kernel(const float *__restrict__ v, const int32_t *__restrict__ f,
+                                                             int nt, int lognf, float lox, float loy, float loz,
+                                                             float hf, const int32_t *__restrict__ arg_tri,
+                                                             const int32_t *__restrict__ arg_ray,
+                                                             const float *__restrict__ fine,
+                                                             const float *__restrict__ grad, uint64_t seed,
+                                                             uint32_t scene, float *grad_v, int64_t ntex)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ntex) return;
+    const int tri = arg_tri[j];
+    const float g = grad[j];
+    if (tri < 0 || tri >= nt || g == 0.0f) return;
+    const uint32_t key = (uint32_t)arg_ray[j];
+    const int nfm = (1 << lognf) - 1;
+    const float ox = texel_coord(lox, (int)(j & nfm), hf), oy = texel_coord(loy, (int)((j >> lognf) & nfm), hf),
+                oz = texel_coord(loz, (int)(j >> (2 * lognf)), hf);
+    const float3 w = sphere_dir(seed, (uint32_t)j, key >> 8, key & 0xFFu, scene);
+    const int i0 = f[3 * tri], i1 = f[3 * tri + 1], i2 = f[3 * tri + 2];
+    const float3 p0 = make_float3(v[3 * i0], v[3 * i0 + 1], v[3 * i0 + 2]);
+    const float3 p1 = make_float3(v[3 * i1], v[3 * i1 + 1], v[3 * i1 + 2]);
+    const float3 p2 = make_float3(v[3 * i2], v[3 * i2 + 1], v[3 * i2 + 2]);
+    const float3 e1 = make_float3(p1.x - p0.x, p1.y - p0.y, p1.z - p0.z);
+    const float3 e2 = make_float3(p2.x - p0.x, p2.y - p0.y, p2.z - p0.z);
+    // Moller-Trumbore barycentrics of the recorded hit
+    const float3 pv = make_float3(w.y * e2.z - w.z * e2.y, w.z * e2.x - w.x * e2.z, w.x * e2.y - w.y * e2.x);
+    const float det = e1.x * pv.x + e1.y * pv.y + e1.z * pv.z;
+    if (det == 0.0f) return;
+    const float inv = 1.0f / det;
+    const float3 s = make_float3(ox - p0.x, oy - p0.y, oz - p0.z);
+    const float bu = (s.x * pv.x + s.y * pv.y + s.z * pv.z) * inv;
+    const float3 q = make_float3(s.y * e1.z - s.z * e1.y, s.z * e1.x - s.x * e1.z, s.x * e1.y - s.y * e1.x);
+    const float bv = (w.x * q.x + w.y * q.y + w.z * q.z) * inv;
+    const float3 nrm = make_float3(e1.y * e2.z - e1.z * e2.y, e1.z * e2.x - e1.x * e2.z, e1.x * e2.y - e1.y * e2.x);
+    const float nw = nrm.x * w.x + nrm.y * w.y + nrm.z * w.z;
+    if (nw == 0.0f) return;
+    const float len = sqrtf(w.x * w.x + w.y * w.y + w.z * w.z);
+    const float sgn = fine[j] < 0.0f ? -1.0f : 1.0f;
+    const float scale = g * sgn * len / nw;
+    const float b[3] = {1.0f - bu - bv, bu, bv};
+    const int vid[3] = {i0, i1, i2};
+    for (int k = 0; k < 3; ++k) {
+        atomicAdd(&grad_v[3 * vid[k]], scale * b[k] * nrm.x);
+        atomicAdd(&grad_v[3 * vid[k] + 1], scale * b[k] * nrm.y);
+        atomicAdd(&grad_v[3 * vid[k] + 2], scale * b[k] * nrm.z);
+    }
+}
+
+// ------------------------------------------------------------- launch ----
+
+struct TraceConfig {
+    int stack_depth;    // chosen >= hierarchy depth
+    int refill;         // lanes finished before refilling
+    int blocks_per_cu;  // persistent workgroups per compute unit
+};
+
+static int g_trace_refill = 16;
+static int g_trace_blocks_per_cu = 0;  // 0: occupancy limit
+
+template <int SD, int REFILL>
+static int launch_trace_sd(const TraceArgs &A, hipStream_t s)
+{
+    int per_cu = g_trace_blocks_per_cu;
+    if (per_cu <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent<SD, REFILL>, kTraceWaves * kWave, 0) !=
+                hipSuccess ||
+            per_cu <= 0)
+            per_cu = 2;
+    }
+    const int blocks = num_cus() * per_cu;
+    trace_persistent<SD, REFILL><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
+    RTSDF_CHECK_LAUNCH();
+    return RTSDF_OK;
+}
+
+template <int SD>
+static int launch_trace_refill(const TraceArgs &A, hipStream_t s)
+{
+    switch (g_trace_refill) {
+    case 1: return launch_trace_sd<SD, 1>(A, s);
+    case 8: return launch_trace_sd<SD, 8>(A, s);
+    case 32: return launch_trace_sd<SD, 32>(A, s);
+    default: return launch_trace_sd<SD, 16>(A, s);
+    }
+}
+
+static int stack_depth_for(const rtsdf_scene *sc) { return sc->max_depth + 1; }
+
+}  // namespace rtsdf
+
+extern "C" int rtsdf_trace_set_tuning(int32_t refill, int32_t blocks_per_cu)
+{
+    if (refill != 1 && refill != 8 && refill != 16 && refill != 32) return RTSDF_EINVAL;
+    if (blocks_per_cu < 0 || blocks_per_cu > 64) return RTSDF_EINVAL;
+    rtsdf::g_trace_refill = refill;
+    rtsdf::g_trace_blocks_per_cu = blocks_per_cu;
+    return RTSDF_OK;
+}
+
+extern "C" int rtsdf_accum_reset(rtsdf_grid fine, rtsdf_accum st, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!grid_ok(fine) || !st.u || !st.hits || !st.arg_tri || !st.arg_ray) return RTSDF_EINVAL;
+    const int64_t n = (int64_t)fine.n * fine.n * fine.n;
+    int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    accum_reset_kernel<<<dim3((unsigned)blocks), dim3(256), 0, as_stream(stream)>>>(n, st.u, st.hits, st.arg_tri, st.arg_ray);
+    RTSDF_CHECK_LAUNCH();
+    return RTSDF_OK;
+}
+
+extern "C" size_t rtsdf_trace_workspace_size(void) { return 256; }
+
+extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const float *coarse_sdf,
+                                      rtsdf_grid fine, const uint8_t *mask, const int32_t *queue, const int32_t *count,
+                                      int32_t queue_cap, int32_t rays_per_texel, uint32_t frame,
+                                      const uint32_t *frame_ptr, uint64_t seed, uint32_t scene_id, float alpha,
+                                      rtsdf_accum st, float *fine_sdf, void *workspace, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!scene || !grid_ok(coarse) || !grid_ok(fine) || !coarse_sdf || !mask || !count || !fine_sdf || !workspace)
+        return RTSDF_EINVAL;
+    if (!st.u || !st.hits || !st.arg_tri || !st.arg_ray) return RTSDF_EINVAL;
+    if (!is_pow2(coarse.n) || !is_pow2(fine.n) || fine.n < coarse.n || fine.n > 1024) return RTSDF_EINVAL;
+    if (queue_cap < 0 || (queue_cap > 0 && !queue)) return RTSDF_EINVAL;
+    if (rays_per_texel < 1 || rays_per_texel > 64) return RTSDF_EINVAL;
+    if (!(alpha >= 0.0f && alpha <= 1.0f)) return RTSDF_EINVAL;
+    if (frame >= (1u << 23) && !frame_ptr) return RTSDF_EINVAL;
+    const int sd = stack_depth_for(scene);
+    if (sd > 64) return RTSDF_EINVAL;
+    hipStream_t s = as_stream(stream);
+    const int lognf = ilog2(fine.n), logr = ilog2(fine.n / coarse.n);
+    const int64_t ntex = (int64_t)fine.n * fine.n * fine.n;
+    trace_fill_unselected<<<dim3((unsigned)((ntex + 255) / 256)), dim3(256), 0, s>>>(
+        mask, coarse_sdf, coarse.n, logr, lognf, ntex, st.u, st.hits, st.arg_tri, st.arg_ray, fine_sdf);
+    RTSDF_CHECK_LAUNCH();
+    int32_t *cursor = static_cast<int32_t *>(workspace);
+    int rc = launch_fill<int32_t>(cursor, 0, 1, s);
+    if (rc != RTSDF_OK) return rc;
+    TraceArgs A;
+    A.bvh.nodes = scene->nodes;
+    A.bvh.tris = scene->tris;
+    A.nt = scene->nt;
+    A.queue = queue;
+    A.count = count;
+    A.queue_cap = queue_cap;
+    A.cursor = cursor;
+    A.coarse_sdf = coarse_sdf;
+    A.nc = coarse.n;
+    A.logr = logr;
+    A.nf = fine.n;
+    A.lognf = lognf;
+    A.lox = fine.lo[0];
+    A.loy = fine.lo[1];
+    A.loz = fine.lo[2];
+    A.hf = fine.h;
+    A.rays = rays_per_texel;
+    A.frame = frame;
+    A.frame_ptr = frame_ptr;
+    A.seed = seed;
+    A.scene_id = scene_id;
+    A.alpha = alpha;
+    A.u = st.u;
+    A.hits = st.hits;
+    A.arg_tri = st.arg_tri;
+    A.arg_ray = st.arg_ray;
+    A.fine = fine_sdf;
+    if (sd <= 16) return launch_trace_refill<16>(A, s);
+    if (sd <= 24) return launch_trace_refill<24>(A, s);
+    if (sd <= 32) return launch_trace_refill<32>(A, s);
+    if (sd <= 48) return launch_trace_refill<48>(A, s);
+    return launch_trace_refill<64>(A, s);
+}
+
+extern "C" int rtsdf_directions(const int32_t *texel, const uint32_t *frame, const int32_t *ray, int32_t n,
+                                uint64_t seed, uint32_t scene_id, float *out, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (n < 0 || (n > 0 && (!texel || !frame || !ray || !out))) return RTSDF_EINVAL;
+    if (n == 0) return RTSDF_OK;
+    directions_kernel<<<dim3((n + 255) / 256), dim3(256), 0, as_stream(stream)>>>(texel, frame, ray, n, seed, scene_id, out);
+    RTSDF_CHECK_LAUNCH();
+    return RTSDF_OK;
+}
+
+extern "C" int rtsdf_closest_hits(const rtsdf_scene *scene, const float *origins, const float *dirs, int32_t n,
+                                  float *t_out, int32_t *tri_out, int32_t *front_out, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!scene || n < 0 || (n > 0 && (!origins || !dirs || !t_out || !tri_out || !front_out))) return RTSDF_EINVAL;
+    if (n == 0) return RTSDF_OK;
+    const int sd = stack_depth_for(scene);
+    if (sd > 64) return RTSDF_EINVAL;
+    BvhView S{scene->nodes, scene->tris};
+    hipStream_t s = as_stream(stream);
+    const dim3 g((n + 255) / 256), b(256);
+    if (sd <= 32)
+        closest_hits_kernel<32><<<g, b, 0, s>>>(S, scene->nt, origins, dirs, n, t_out, tri_out, front_out);
+    else
+        closest_hits_kernel<64><<<g, b, 0, s>>>(S, scene->nt, origins, dirs, n, t_out, tri_out, front_out);
+    RTSDF_CHECK_LAUNCH();
+    return RTSDF_OK;
+}
+
+extern "C" int rtsdf_trace_backward(const rtsdf_scene *scene, rtsdf_grid fine, rtsdf_accum st, const float *fine_sdf,
+                                    const float *grad_fine, uint64_t seed, uint32_t scene_id, float *grad_v,
+                                    rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!scene || !grid_ok(fine) || !is_pow2(fine.n) || !st.arg_tri || !st.arg_ray || !fine_sdf || !grad_fine || !grad_v)
+        return RTSDF_EINVAL;
+    const int64_t ntex = (int64_t)fine.n * fine.n * fine.n;
+    trace_backward_kernel<<<dim3((unsigned)((ntex + 255) / 256)), dim3(256), 0, as_stream(stream)>>>(
+        scene->vertices, scene->faces, scene->nt, ilog2(fine.n), fine.lo[0], fine.lo[1], fine.lo[2], fine.h, st.arg_tri,
+        st.arg_ray, fine_sdf, grad_fine, seed, scene_id, grad_v, ntex);
+    RTSDF_CHECK_LAUNCH();
+    return RTSDF_OK;
+}

@@ -1,0 +1,78 @@
+"""Per-frame SDF update on one GPU: voxelize -> jump flood -> select -> trace.
+
+`Pipeline` owns every device buffer of the path (torch tensors used only as
+device memory) and calls the C ABI in the order of the paper's design
+(Sec. 2): coarse SDF by voxelization + jump flooding (Sec. 2.1), selection of
+the fine texels near surfaces and ray-traced temporal accumulation
+(Sec. 2.2).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import rtsdf as R
+
+
+class Pipeline:
+    def __init__(self, vertices: torch.Tensor, faces: torch.Tensor, nc: int, nf: int, beta: float, d: float,
+                 rays: int, seed: int = 0, scene_id: int = 0, alpha: float = 1.0, lo=(0.0, 0.0, 0.0),
+                 side: float = 1.0, leaf_size: int = 4, queue_cap: int | None = None, device="cuda"):
+        self.device = torch.device(device)
+        self.vertices = vertices.to(self.device, torch.float32).contiguous()
+        self.faces = faces.to(self.device, torch.int32).contiguous()
+        self.coarse = R.Grid.make(nc, side / nc, lo)
+        self.fine = R.Grid.make(nf, side / nf, lo)
+        self.nc, self.nf = nc, nf
+        self.beta, self.d = float(beta), float(d)
+        self.rays, self.seed, self.scene_id, self.alpha = int(rays), int(seed), int(scene_id), float(alpha)
+        dev = self.device
+        i32, f32 = torch.int32, torch.float32
+        self.seeds = torch.empty(nc ** 3, dtype=i32, device=dev)
+        self.scratch = torch.empty(nc ** 3, dtype=i32, device=dev)
+        self.dist2 = torch.empty(nc ** 3, dtype=i32, device=dev)
+        self.coarse_sdf = torch.empty(nc ** 3, dtype=f32, device=dev)
+        self.mask = torch.empty(nf ** 3, dtype=torch.uint8, device=dev)
+        self.queue = torch.empty(nf ** 3 if queue_cap is None else int(queue_cap), dtype=i32, device=dev)
+        self.count = torch.zeros(1, dtype=i32, device=dev)
+        self.sel_ws = torch.empty(R.rtsdf_select_workspace_size(nc), dtype=torch.uint8, device=dev)
+        self.trace_ws = torch.empty(R.rtsdf_trace_workspace_size(), dtype=torch.uint8, device=dev)
+        self.fine_sdf = torch.empty(nf ** 3, dtype=f32, device=dev)
+        self.state = R.AccumState(self.fine, dev)
+        self.scene = R.Scene(self.vertices, self.faces, leaf_size)
+
+    # -- stages ----------------------------------------------------------
+    def voxelize(self, stream=None):
+        R.rtsdf_voxelize(self.vertices, self.faces, self.coarse, self.seeds, stream)
+
+    def jfa(self, stream=None):
+        R.rtsdf_jfa(self.coarse, self.seeds, self.scratch, self.beta, self.dist2, self.coarse_sdf, stream)
+
+    def select(self, stream=None):
+        R.rtsdf_select(self.coarse, self.dist2, self.fine, self.beta, self.d, self.mask, self.queue, self.count,
+                       self.sel_ws, stream)
+
+    def trace(self, frame: int, stream=None, frame_ptr=None):
+        R.rtsdf_trace_accumulate(self.scene, self.coarse, self.coarse_sdf, self.fine, self.mask, self.queue,
+                                 self.count, self.rays, frame, self.seed, self.scene_id, self.alpha, self.state,
+                                 self.fine_sdf, self.trace_ws, frame_ptr=frame_ptr, stream=stream)
+
+    def step(self, frame: int, stream=None):
+        """One SDF update (all stages) for frame index `frame`."""
+        self.voxelize(stream)
+        self.jfa(stream)
+        self.select(stream)
+        self.trace(frame, stream)
+
+    def set_vertices(self, vertices: torch.Tensor, stream=None):
+        """New positions for the same topology (animated scenes): refit the hierarchy."""
+        self.vertices.copy_(vertices)
+        self.scene.refit(self.vertices, stream)
+
+    def reset(self):
+        R.rtsdf_accum_reset(self.fine, self.state)
+
+    def selected(self) -> int:
+        return int(self.count.item())
+
+    def close(self):
+        self.scene.close()

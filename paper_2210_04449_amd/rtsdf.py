@@ -1,0 +1,259 @@
+"""ctypes binding of ``librtsdf.so`` (the C ABI declared in include/rtsdf.h).
+
+Functions keep the C names and only marshal arguments: torch tensors are
+passed as device pointers, the stream defaults to torch's current stream, and
+a non-zero status raises :class:`RtsdfError`.  All computation happens in the
+library's HIP kernels; there is no fallback path -- importing this module on a
+machine without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+from .build import LIB
+
+_P = C.c_void_p
+_i32, _u32, _u64, _f32, _sz = C.c_int32, C.c_uint32, C.c_uint64, C.c_float, C.c_size_t
+
+OK, EINVAL, ENOMEM, EHIP, EDEVICE = 0, -1, -2, -3, -4
+ERR_FACE_INDEX, ERR_VERTEX_RANGE, ERR_QUEUE_FULL, ERR_BATCH = 1, 2, 4, 8
+
+
+class Grid(C.Structure):
+    """Cubic grid: ``n`` cells per axis of size ``h`` from corner ``lo``."""
+
+    _fields_ = [("lo", C.c_float * 3), ("h", C.c_float), ("n", C.c_int32)]
+
+    @classmethod
+    def make(cls, n: int, h: float | None = None, lo=(0.0, 0.0, 0.0)) -> "Grid":
+        g = cls()
+        g.lo[0], g.lo[1], g.lo[2] = (float(x) for x in lo)
+        g.h = float(1.0 / n) if h is None else float(h)
+        g.n = int(n)
+        return g
+
+
+class Accum(C.Structure):
+    _fields_ = [("u", _P), ("hits", _P), ("arg_tri", _P), ("arg_ray", _P)]
+
+
+class SceneInfo(C.Structure):
+    _fields_ = [("nv", _i32), ("nt", _i32), ("nodes", _i32), ("max_depth", _i32), ("leaf_size", _i32),
+                ("device_bytes", C.c_int64)]
+
+
+class RtsdfError(RuntimeError):
+    def __init__(self, fn: str, status: int, bits: int = 0):
+        self.status, self.bits = status, bits
+        msg = f"{fn} failed: {_lib.rtsdf_status_string(status).decode()} ({status})"
+        if bits:
+            msg += f", device error bits 0x{bits:x}"
+        super().__init__(msg)
+
+
+def _load():
+    if not os.path.exists(LIB):
+        raise ImportError(f"{LIB} is not built; run `python -m paper_2210_04449_amd.build` (hipcc, gfx950)")
+    L = C.CDLL(LIB)
+    sig = {
+        "rtsdf_status_string": ([_i32], C.c_char_p),
+        "rtsdf_version": ([], _i32),
+        "rtsdf_sync_status": ([_P, C.POINTER(_u32)], _i32),
+        "rtsdf_voxelize": ([_P, _i32, _P, _i32, Grid, _P, _P], _i32),
+        "rtsdf_jfa": ([Grid, _P, _P, _f32, _P, _P, _P], _i32),
+        "rtsdf_select_workspace_size": ([_i32], _sz),
+        "rtsdf_select": ([Grid, _P, Grid, _f32, _f32, _P, _P, _i32, _P, _P, _P], _i32),
+        "rtsdf_scene_create": ([_P, _i32, _P, _i32, _i32, C.POINTER(_P), _P], _i32),
+        "rtsdf_scene_refit": ([_P, _P, _P], _i32),
+        "rtsdf_scene_info_get": ([_P, C.POINTER(SceneInfo)], _i32),
+        "rtsdf_scene_destroy": ([_P], None),
+        "rtsdf_accum_reset": ([Grid, Accum, _P], _i32),
+        "rtsdf_trace_workspace_size": ([], _sz),
+        "rtsdf_trace_accumulate": ([_P, Grid, _P, Grid, _P, _P, _P, _i32, _i32, _u32, _P, _u64, _u32, _f32,
+                                    Accum, _P, _P, _P], _i32),
+        "rtsdf_trace_set_tuning": ([_i32, _i32], _i32),
+        "rtsdf_directions": ([_P, _P, _P, _i32, _u64, _u32, _P, _P], _i32),
+        "rtsdf_closest_hits": ([_P, _P, _P, _i32, _P, _P, _P, _P], _i32),
+        "rtsdf_trace_backward": ([_P, Grid, Accum, _P, _P, _u64, _u32, _P, _P], _i32),
+        "rtsdf_shadow": ([Grid, _P, _P, _i32, _P, _f32, _f32, _i32, _f32, _f32, _P, _P], _i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if not t.is_cuda:
+            raise ValueError("rtsdf: tensors must be on the GPU")
+        if not t.is_contiguous():
+            raise ValueError("rtsdf: tensors must be contiguous")
+        return t.data_ptr()
+    return int(t)
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _check(fn: str, status: int):
+    if status != OK:
+        raise RtsdfError(fn, status)
+
+
+def _dtype(t: torch.Tensor, dt: torch.dtype, name: str):
+    if t.dtype != dt:
+        raise TypeError(f"rtsdf: {name} must be {dt}, got {t.dtype}")
+
+
+def rtsdf_version() -> int:
+    return int(_lib.rtsdf_version())
+
+
+def rtsdf_sync_status(stream=None) -> int:
+    """Synchronise and return the device error bits (raises nothing)."""
+    bits = _u32(0)
+    st = _lib.rtsdf_sync_status(_stream(stream), C.byref(bits))
+    if st not in (OK, EDEVICE):
+        raise RtsdfError("rtsdf_sync_status", st)
+    return int(bits.value)
+
+
+def rtsdf_voxelize(vertices, faces, coarse: Grid, seeds, stream=None):
+    _dtype(vertices, torch.float32, "vertices")
+    _dtype(faces, torch.int32, "faces")
+    _dtype(seeds, torch.int32, "seeds")
+    _check("rtsdf_voxelize", _lib.rtsdf_voxelize(_ptr(vertices), vertices.shape[0], _ptr(faces), faces.shape[0],
+                                                 coarse, _ptr(seeds), _stream(stream)))
+
+
+def rtsdf_jfa(coarse: Grid, seeds, scratch, beta: float, dist2, coarse_sdf, stream=None):
+    _check("rtsdf_jfa", _lib.rtsdf_jfa(coarse, _ptr(seeds), _ptr(scratch), float(beta), _ptr(dist2),
+                                       _ptr(coarse_sdf), _stream(stream)))
+
+
+def rtsdf_select_workspace_size(coarse_n: int) -> int:
+    return int(_lib.rtsdf_select_workspace_size(int(coarse_n)))
+
+
+def rtsdf_select(coarse: Grid, dist2, fine: Grid, beta: float, d: float, mask, queue, count, workspace,
+                 stream=None):
+    cap = 0 if queue is None else queue.numel()
+    _check("rtsdf_select", _lib.rtsdf_select(coarse, _ptr(dist2), fine, float(beta), float(d), _ptr(mask),
+                                             _ptr(queue), cap, _ptr(count), _ptr(workspace), _stream(stream)))
+
+
+class Scene:
+    """Owning handle of an ``rtsdf_scene`` (device triangles + hierarchy)."""
+
+    def __init__(self, vertices, faces, leaf_size: int = 4, stream=None):
+        _dtype(vertices, torch.float32, "vertices")
+        _dtype(faces, torch.int32, "faces")
+        h = _P()
+        _check("rtsdf_scene_create", _lib.rtsdf_scene_create(_ptr(vertices), vertices.shape[0], _ptr(faces),
+                                                             faces.shape[0], int(leaf_size), C.byref(h),
+                                                             _stream(stream)))
+        self.handle = h
+
+    def refit(self, vertices, stream=None):
+        _check("rtsdf_scene_refit", _lib.rtsdf_scene_refit(self.handle, _ptr(vertices), _stream(stream)))
+
+    def info(self) -> SceneInfo:
+        inf = SceneInfo()
+        _check("rtsdf_scene_info_get", _lib.rtsdf_scene_info_get(self.handle, C.byref(inf)))
+        return inf
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.rtsdf_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class AccumState:
+    """Per-texel accumulation state (u, hits, arg_tri, arg_ray) as torch tensors."""
+
+    def __init__(self, fine: Grid, device="cuda"):
+        n = fine.n ** 3
+        self.u = torch.empty(n, dtype=torch.float32, device=device)
+        self.hits = torch.empty(n, dtype=torch.int32, device=device)
+        self.arg_tri = torch.empty(n, dtype=torch.int32, device=device)
+        self.arg_ray = torch.empty(n, dtype=torch.int32, device=device)
+        rtsdf_accum_reset(fine, self)
+
+    def struct(self) -> Accum:
+        return Accum(_ptr(self.u), _ptr(self.hits), _ptr(self.arg_tri), _ptr(self.arg_ray))
+
+    def tensors(self) -> dict:
+        return {"u": self.u, "hits": self.hits, "arg_tri": self.arg_tri, "arg_ray": self.arg_ray}
+
+
+def rtsdf_accum_reset(fine: Grid, state: AccumState, stream=None):
+    _check("rtsdf_accum_reset", _lib.rtsdf_accum_reset(fine, state.struct(), _stream(stream)))
+
+
+def rtsdf_trace_workspace_size() -> int:
+    return int(_lib.rtsdf_trace_workspace_size())
+
+
+def rtsdf_trace_set_tuning(refill: int, blocks_per_cu: int):
+    _check("rtsdf_trace_set_tuning", _lib.rtsdf_trace_set_tuning(int(refill), int(blocks_per_cu)))
+
+
+def rtsdf_trace_accumulate(scene: Scene, coarse: Grid, coarse_sdf, fine: Grid, mask, queue, count,
+                           rays_per_texel: int, frame: int, seed: int, scene_id: int, alpha: float,
+                           state: AccumState, fine_sdf, workspace, frame_ptr=None, stream=None):
+    _check("rtsdf_trace_accumulate", _lib.rtsdf_trace_accumulate(
+        scene.handle, coarse, _ptr(coarse_sdf), fine, _ptr(mask), _ptr(queue), _ptr(count), queue.numel(),
+        int(rays_per_texel), int(frame), _ptr(frame_ptr), int(seed), int(scene_id), float(alpha), state.struct(),
+        _ptr(fine_sdf), _ptr(workspace), _stream(stream)))
+
+
+def rtsdf_directions(texel, frame, ray, seed: int, scene_id: int, out, stream=None):
+    n = texel.numel()
+    _check("rtsdf_directions", _lib.rtsdf_directions(_ptr(texel), _ptr(frame), _ptr(ray), n, int(seed),
+                                                     int(scene_id), _ptr(out), _stream(stream)))
+
+
+def rtsdf_closest_hits(scene: Scene, origins, dirs, t_out, tri_out, front_out, stream=None):
+    n = origins.shape[0]
+    _check("rtsdf_closest_hits", _lib.rtsdf_closest_hits(scene.handle, _ptr(origins), _ptr(dirs), n, _ptr(t_out),
+                                                         _ptr(tri_out), _ptr(front_out), _stream(stream)))
+
+
+def rtsdf_trace_backward(scene: Scene, fine: Grid, state: AccumState, fine_sdf, grad_fine, seed: int,
+                         scene_id: int, grad_v, stream=None):
+    _check("rtsdf_trace_backward", _lib.rtsdf_trace_backward(scene.handle, fine, state.struct(), _ptr(fine_sdf),
+                                                             _ptr(grad_fine), int(seed), int(scene_id),
+                                                             _ptr(grad_v), _stream(stream)))
+
+
+def rtsdf_shadow(fine: Grid, fine_sdf, points, light_dir, k: float, eps: float, max_steps: int, max_step: float,
+                 max_dist: float, visibility, stream=None):
+    ld = (C.c_float * 3)(*[float(x) for x in light_dir])
+    _check("rtsdf_shadow", _lib.rtsdf_shadow(fine, _ptr(fine_sdf), _ptr(points), points.shape[0], ld, float(k),
+                                             float(eps), int(max_steps), float(max_step), float(max_dist),
+                                             _ptr(visibility), _stream(stream)))

@@ -1,0 +1,77 @@
+"""CPU checks of the C ABI: the built library loads, exports every function the
+header declares, and rejects bad arguments on the host (no GPU call is made for
+those: validation happens before any launch)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rtsdf.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rtsdf_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2210_04449_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    import paper_2210_04449_amd.rtsdf as R
+    return R
+
+
+def test_header_declares_the_five_stages():
+    names = declared()
+    for n in ("rtsdf_voxelize", "rtsdf_jfa", "rtsdf_select", "rtsdf_trace_accumulate", "rtsdf_shadow"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(R):
+    out = subprocess.run(["nm", "-D", "--defined-only", R.LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (rtsdf_\w+)", out))
+    missing = [n for n in declared() if n not in exported]
+    assert not missing, missing
+    # nothing torch-typed crosses the boundary: the library does not link torch
+    deps = subprocess.run(["ldd", R.LIB], capture_output=True, text=True).stdout
+    assert "torch" not in deps
+
+
+def test_status_strings(R):
+    L = R.lib()
+    assert L.rtsdf_status_string(0) == b"ok"
+    assert L.rtsdf_status_string(-1) == b"invalid argument"
+    assert R.rtsdf_version() >= 100
+
+
+def test_host_validation(R):
+    L = R.lib()
+    g = R.Grid.make(32)
+    bad_n = R.Grid.make(33)
+    dummy = C.c_void_p(16)  # never dereferenced: every call below fails validation first
+    assert L.rtsdf_voxelize(dummy, 3, dummy, 1, bad_n, dummy, None) == R.EINVAL
+    assert L.rtsdf_voxelize(dummy, 3, dummy, 1, R.Grid.make(512), dummy, None) == R.EINVAL
+    assert L.rtsdf_voxelize(dummy, 3, dummy, 1, g, None, None) == R.EINVAL
+    assert L.rtsdf_jfa(g, dummy, dummy, 0.0, dummy, dummy, None) == R.EINVAL  # seeds == scratch
+    assert L.rtsdf_jfa(R.Grid.make(4), dummy, C.c_void_p(32), 0.0, dummy, dummy, None) == R.EINVAL
+    fine = R.Grid.make(64)
+    assert L.rtsdf_select(g, dummy, R.Grid.make(48), 0.0, 0.1, dummy, dummy, 10, dummy, dummy, None) == R.EINVAL
+    # fine grid must cover the same box as the coarse one
+    assert L.rtsdf_select(g, dummy, R.Grid.make(64, 1 / 32), 0.0, 0.1, dummy, dummy, 10, dummy, dummy, None) == R.EINVAL
+    acc = R.Accum(16, 16, 16, 16)
+    assert L.rtsdf_trace_accumulate(dummy, g, dummy, fine, dummy, dummy, dummy, 10, 0, 0, None, 0, 0, 1.0, acc,
+                                    dummy, dummy, None) == R.EINVAL  # zero rays
+    assert L.rtsdf_trace_accumulate(dummy, g, dummy, fine, dummy, dummy, dummy, 10, 65, 0, None, 0, 0, 1.0, acc,
+                                    dummy, dummy, None) == R.EINVAL
+    assert L.rtsdf_trace_accumulate(dummy, g, dummy, fine, dummy, dummy, dummy, 10, 4, 0, None, 0, 0, 1.5, acc,
+                                    dummy, dummy, None) == R.EINVAL
+    ld = (C.c_float * 3)(0, 1, 0)
+    assert L.rtsdf_shadow(fine, dummy, dummy, 4, ld, 8.0, 0.0, 16, 0.1, 1.0, dummy, None) == R.EINVAL  # eps 0
+    assert L.rtsdf_trace_set_tuning(3, 0) == R.EINVAL
+    assert R.rtsdf_select_workspace_size(128) >= (128 ** 3 // 1024) * 4
