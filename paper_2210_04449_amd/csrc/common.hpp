@@ -18,6 +18,35 @@ __device__ unsigned int g_error_word;
 
 __device__ __forceinline__ void raise_error(unsigned int bit) { atomicOr(&g_error_word, bit); }
 
+// Float operations that are rounded exactly once (round to nearest even) and
+// never fused with a neighbour into an FMA: the texel centres, ray directions,
+// coarse SDF values and shadow marches must be reproducible bit for bit.
+// (HIP's __fadd_rn/__fmul_rn are plain operators that the compiler may
+// contract, and its __fsqrt_rn is the approximate native square root; the
+// builtin square root and division below are correctly rounded under hipcc's
+// default fp32 settings.)
+__device__ __forceinline__ float rn_add(float a, float b)
+{
+#pragma clang fp contract(off)
+    return a + b;
+}
+__device__ __forceinline__ float rn_sub(float a, float b)
+{
+#pragma clang fp contract(off)
+    return a - b;
+}
+__device__ __forceinline__ float rn_mul(float a, float b)
+{
+#pragma clang fp contract(off)
+    return a * b;
+}
+__device__ __forceinline__ float rn_div(float a, float b)
+{
+#pragma clang fp contract(off)
+    return a / b;
+}
+__device__ __forceinline__ float rn_sqrt(float a) { return __builtin_sqrtf(a); }
+
 inline hipStream_t as_stream(rtsdf_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
 inline bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }

@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(512) jfa_near(const int32_t *__restrict__ src,
             const int d2 = (int)key_d2(best);
             dst[idx] = unpack_linear(s, logn);
             dist2[idx] = d2;
-            sdf[idx] = __fsub_rn(__fmul_rn(h, __fsqrt_rn((float)d2)), beta);
+            sdf[idx] = rn_sub(rn_mul(h, rn_sqrt((float)d2)), beta);
         }
     }
 }

@@ -14,17 +14,17 @@
 
 namespace rtsdf {
 
-__device__ __forceinline__ float lerp_rn(float a, float b, float f) { return __fadd_rn(a, __fmul_rn(f, __fsub_rn(b, a))); }
+__device__ __forceinline__ float lerp_rn(float a, float b, float f) { return rn_add(a, rn_mul(f, rn_sub(b, a))); }
 
 // coordinate of q along one axis in texel-centre units, clamped to [0, n-1];
 // false if q is outside the grid box
 __device__ __forceinline__ bool grid_coord(float q, float lo, float h, int n, int &i, float &f)
 {
-    const float g = __fsub_rn(__fdiv_rn(__fsub_rn(q, lo), h), 0.5f);
+    const float g = rn_sub(rn_div(rn_sub(q, lo), h), 0.5f);
     if (g < -0.5f || g > (float)n - 0.5f) return false;
     const float gc = fminf(fmaxf(g, 0.0f), (float)(n - 1));
     i = min((int)floorf(gc), n - 2);
-    f = __fsub_rn(gc, (float)i);
+    f = rn_sub(gc, (float)i);
     return true;
 }
 
@@ -40,9 +40,9 @@ __global__ void __launch_bounds__(256) shadow_kernel(rtsdf_grid g, const float *
     float vis = 1.0f, t = eps;
     for (int step = 0; step < max_steps; ++step) {
         if (t > max_dist) break;
-        const float qx = __fadd_rn(px, __fmul_rn(t, lx));
-        const float qy = __fadd_rn(py, __fmul_rn(t, ly));
-        const float qz = __fadd_rn(pz, __fmul_rn(t, lz));
+        const float qx = rn_add(px, rn_mul(t, lx));
+        const float qy = rn_add(py, rn_mul(t, ly));
+        const float qz = rn_add(pz, rn_mul(t, lz));
         int ix, iy, iz;
         float fx, fy, fz;
         if (!grid_coord(qx, g.lo[0], g.h, n, ix, fx) || !grid_coord(qy, g.lo[1], g.h, n, iy, fy) ||
@@ -59,8 +59,8 @@ __global__ void __launch_bounds__(256) shadow_kernel(rtsdf_grid g, const float *
             vis = 0.0f;
             break;
         }
-        vis = fminf(vis, __fdiv_rn(__fmul_rn(k, s), t));
-        t = __fadd_rn(t, fmaxf(fminf(s, max_step), eps));
+        vis = fminf(vis, rn_div(rn_mul(k, s), t));
+        t = rn_add(t, fmaxf(fminf(s, max_step), eps));
     }
     vis_out[p] = fmaxf(vis, 0.0f);
 }

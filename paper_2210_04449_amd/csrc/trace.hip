@@ -68,11 +68,11 @@ __device__ __noinline__ float3 sphere_dir(uint64_t seed, uint32_t texel, uint32_
         for (int p = 0; p < 4; ++p) {
             const float x1 = uniform_pm1((uint32_t)c[p]);
             const float x2 = uniform_pm1((uint32_t)(c[p] >> 32));
-            const float s = __fadd_rn(__fmul_rn(x1, x1), __fmul_rn(x2, x2));
+            const float s = rn_add(rn_mul(x1, x1), rn_mul(x2, x2));
             if (s < 1.0f) {
-                const float q = __fsqrt_rn(__fsub_rn(1.0f, s));
-                return make_float3(__fmul_rn(__fmul_rn(2.0f, x1), q), __fmul_rn(__fmul_rn(2.0f, x2), q),
-                                   __fsub_rn(1.0f, __fmul_rn(2.0f, s)));
+                const float q = rn_sqrt(rn_sub(1.0f, s));
+                return make_float3(rn_mul(rn_mul(2.0f, x1), q), rn_mul(rn_mul(2.0f, x2), q),
+                                   rn_sub(1.0f, rn_mul(2.0f, s)));
             }
         }
     }
@@ -82,7 +82,7 @@ __device__ __noinline__ float3 sphere_dir(uint64_t seed, uint32_t texel, uint32_
 // texel centre: lo + (i + 1/2) h per axis, float ops rounded once each
 __device__ __forceinline__ float texel_coord(float lo, int i, float h)
 {
-    return __fadd_rn(lo, __fmul_rn(__fadd_rn((float)i, 0.5f), h));
+    return rn_add(lo, rn_mul(rn_add((float)i, 0.5f), h));
 }
 
 // ------------------------------------------------------------- geometry ----
