@@ -224,6 +224,15 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
                            const uint32_t *frame_ptr, uint64_t seed, uint32_t scene_id, float alpha,
                            rtsdf_accum state, float *fine_sdf, void *workspace, rtsdf_stream stream);
 
+/* Tuning and instrumentation of the tracer (process-wide, host-side state):
+ * refill         a wavefront hands out new work once this many of its lanes
+ *                have finished their ray (1, 8, 16 or 32);
+ * blocks_per_cu  persistent workgroups per compute unit (0 = occupancy limit);
+ * stats          1: count node visits, triangle tests and rays into 64-bit
+ *                counters at byte offsets 8, 16 and 24 of the workspace
+ *                (slower; for measurement only).                            */
+int rtsdf_trace_config(int32_t refill, int32_t blocks_per_cu, int32_t stats);
+
 /* Ray directions exactly as rtsdf_trace_accumulate draws them, for n keys  */
 /* (texel[i], frame[i], ray[i]) with one seed and scene id: out float32      */
 /* [n][3].  Lets callers and tests check the generator bit for bit.          */

@@ -195,10 +195,13 @@ struct BvhView {
 // and descends into the nearer hit child (pushing the farther); a leaf tests
 // its triangles; then the lane pops.  `stk` points at the lane's stack slot 0
 // in LDS, entries `stride` words apart.
+template <bool STATS = false>
 __device__ __forceinline__ void trav_step(const BvhView &S, const RaySetup &R, int &node, int &sp, int *stk,
-                                          int stride, float &tbest, int &ibest, bool &front)
+                                          int stride, float &tbest, int &ibest, bool &front, uint32_t *nodes_visited = nullptr,
+                                          uint32_t *tris_tested = nullptr)
 {
     if (node >= 0) {
+        if (STATS) ++*nodes_visited;
         const BvhNode *nd = S.nodes + node;
         const float4 a = nd->xy0, b = nd->xy1, z = nd->z01;
         const int4 m = nd->meta;
@@ -218,6 +221,7 @@ __device__ __forceinline__ void trav_step(const BvhView &S, const RaySetup &R, i
         }
     } else {
         const int first = leaf_first(node), cnt = leaf_count(node);
+        if (STATS) *tris_tested += (uint32_t)cnt;
         for (int i = first; i < first + cnt; ++i)
             tri_test(R, S.tris[3 * i], S.tris[3 * i + 1], S.tris[3 * i + 2], tbest, ibest, front);
     }
@@ -251,9 +255,12 @@ struct TraceArgs {
 
 constexpr int kTraceWaves = 4;
 
-template <int SD, int REFILL>
+// Instrumented runs (STATS) also count node visits, triangle tests and rays
+// into 64-bit counters at workspace offsets 8, 16 and 24.
+template <int SD, int REFILL, bool STATS>
 __global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArgs A)
 {
+    uint32_t st_nodes = 0, st_tris = 0, st_rays = 0;
     __shared__ int stack_mem[kTraceWaves * SD * kWave];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int *stk = stack_mem + wave * SD * kWave + lane;
@@ -316,13 +323,15 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArg
         }
         // traverse until enough lanes have finished their ray (or are idle)
         while (true) {
-            if (texel >= 0 && node != kDone) trav_step(A.bvh, R, node, sp, stk, kWave, tbest, ibest, front);
+            if (texel >= 0 && node != kDone)
+                trav_step<STATS>(A.bvh, R, node, sp, stk, kWave, tbest, ibest, front, &st_nodes, &st_tris);
             const uint64_t done = __ballot(texel < 0 || node == kDone);
             const int ndone = __popcll(done);
             if (ndone >= REFILL || (ndone > 0 && exhausted && ndone == __popcll(__ballot(true)))) break;
             if (ndone == kWave) break;
         }
         if (texel >= 0 && node == kDone) {
+            if (STATS) ++st_rays;
             if (ibest >= 0) {
                 const float dist = tbest * R.len;
                 if (dist < rmin) {
@@ -366,6 +375,12 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArg
                 node = kDone;
             }
         }
+    }
+    if (STATS) {
+        unsigned long long *ctr = reinterpret_cast<unsigned long long *>(A.cursor + 2);
+        atomicAdd(&ctr[0], (unsigned long long)st_nodes);
+        atomicAdd(&ctr[1], (unsigned long long)st_tris);
+        atomicAdd(&ctr[2], (unsigned long long)st_rays);
     }
 }
 
@@ -494,21 +509,28 @@ struct TraceConfig {
 
 static int g_trace_refill = 16;
 static int g_trace_blocks_per_cu = 0;  // 0: occupancy limit
+static int g_trace_stats = 0;
 
-template <int SD, int REFILL>
-static int launch_trace_sd(const TraceArgs &A, hipStream_t s)
+template <int SD, int REFILL, bool STATS>
+static int launch_trace_sd3(const TraceArgs &A, hipStream_t s)
 {
     int per_cu = g_trace_blocks_per_cu;
     if (per_cu <= 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent<SD, REFILL>, kTraceWaves * kWave, 0) !=
-                hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent<SD, REFILL, STATS>,
+                                                         kTraceWaves * kWave, 0) != hipSuccess ||
             per_cu <= 0)
             per_cu = 2;
     }
     const int blocks = num_cus() * per_cu;
-    trace_persistent<SD, REFILL><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
+    trace_persistent<SD, REFILL, STATS><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
     RTSDF_CHECK_LAUNCH();
     return RTSDF_OK;
+}
+
+template <int SD, int REFILL>
+static int launch_trace_sd(const TraceArgs &A, hipStream_t s)
+{
+    return g_trace_stats ? launch_trace_sd3<SD, REFILL, true>(A, s) : launch_trace_sd3<SD, REFILL, false>(A, s);
 }
 
 template <int SD>
@@ -526,12 +548,13 @@ static int stack_depth_for(const rtsdf_scene *sc) { return sc->max_depth + 1; }
 
 }  // namespace rtsdf
 
-extern "C" int rtsdf_trace_set_tuning(int32_t refill, int32_t blocks_per_cu)
+extern "C" int rtsdf_trace_config(int32_t refill, int32_t blocks_per_cu, int32_t stats)
 {
     if (refill != 1 && refill != 8 && refill != 16 && refill != 32) return RTSDF_EINVAL;
-    if (blocks_per_cu < 0 || blocks_per_cu > 64) return RTSDF_EINVAL;
+    if (blocks_per_cu < 0 || blocks_per_cu > 64 || stats < 0 || stats > 1) return RTSDF_EINVAL;
     rtsdf::g_trace_refill = refill;
     rtsdf::g_trace_blocks_per_cu = blocks_per_cu;
+    rtsdf::g_trace_stats = stats;
     return RTSDF_OK;
 }
 
@@ -572,7 +595,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
         mask, coarse_sdf, coarse.n, logr, lognf, ntex, st.u, st.hits, st.arg_tri, st.arg_ray, fine_sdf);
     RTSDF_CHECK_LAUNCH();
     int32_t *cursor = static_cast<int32_t *>(workspace);
-    int rc = launch_fill<int32_t>(cursor, 0, 1, s);
+    int rc = launch_fill<int32_t>(cursor, 0, g_trace_stats ? 8 : 1, s);
     if (rc != RTSDF_OK) return rc;
     TraceArgs A;
     A.bvh.nodes = scene->nodes;
