@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--refill", type=int, default=16)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 256 MiB device-to-device (scale for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -107,6 +109,12 @@ def main():
     w = workload(args.config)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     R.rtsdf_trace_config(args.refill, args.blocks_per_cu, False)
     p = Pipeline(torch.from_numpy(w.mesh.vertices).to(dev), torch.from_numpy(w.mesh.faces).to(dev), w.nc, w.nf,
                  w.beta, w.d, w.rays, seed=0, scene_id=w.scene_seed, alpha=w.alpha)

@@ -59,6 +59,8 @@ struct rtsdf_scene {
     int32_t *refit_counter = nullptr;  // [nnodes]
     int32_t *start_nodes = nullptr;    // internal nodes with two leaf children
     int nstart = 0;
+    int32_t *spill = nullptr;          // tracer stack entries beyond the LDS part
+    int64_t spill_entries = 0;
     int64_t bytes = 0;
 };
 
@@ -331,8 +333,10 @@ __global__ void refit_nodes(BvhNode *nodes, const float4 *__restrict__ tris, con
 
 }  // namespace rtsdf
 
-extern "C" int rtsdf_scene_create(const float *vertices, int32_t nv, const int32_t *faces, int32_t nt,
-                                  int32_t leaf_size, rtsdf_scene **out, rtsdf_stream stream)
+extern "C" void rtsdf_scene_destroy(rtsdf_scene *scene);
+
+static int rtsdf_scene_create_impl(const float *vertices, int32_t nv, const int32_t *faces, int32_t nt,
+                                   int32_t leaf_size, rtsdf_scene **out, rtsdf_stream stream)
 {
     using namespace rtsdf;
     if (!out || nv < 0 || nt < 0 || (nt > 0 && (!vertices || !faces))) return RTSDF_EINVAL;
@@ -434,6 +438,25 @@ extern "C" int rtsdf_scene_create(const float *vertices, int32_t nv, const int32
     return RTSDF_OK;
 }
 
+namespace rtsdf {
+static int ensure_spill(rtsdf_scene *sc);
+}
+
+// The tracer's spill area depends on the hierarchy depth; it is allocated
+// here, at creation, so trace calls never allocate.
+extern "C" int rtsdf_scene_create(const float *vertices, int32_t nv, const int32_t *faces, int32_t nt,
+                                  int32_t leaf_size, rtsdf_scene **out, rtsdf_stream stream)
+{
+    int rc = rtsdf_scene_create_impl(vertices, nv, faces, nt, leaf_size, out, stream);
+    if (rc != RTSDF_OK) return rc;
+    rc = rtsdf::ensure_spill(*out);
+    if (rc != RTSDF_OK) {
+        rtsdf_scene_destroy(*out);
+        *out = nullptr;
+    }
+    return rc;
+}
+
 extern "C" int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsdf_stream stream)
 {
     using namespace rtsdf;
@@ -474,5 +497,6 @@ extern "C" void rtsdf_scene_destroy(rtsdf_scene *scene)
     (void)hipFree(scene->faces);
     (void)hipFree(scene->refit_counter);
     (void)hipFree(scene->start_nodes);
+    (void)hipFree(scene->spill);
     delete scene;
 }

@@ -29,6 +29,8 @@
 // refilled from the compacted queue by one atomic add per wavefront (ballot +
 // mbcnt to hand out the slots), so the queue is consumed in Morton order and
 // no lane waits for a whole wavefront of texels to finish.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace rtsdf {
@@ -251,19 +253,66 @@ struct TraceArgs {
     int32_t *arg_tri;
     int32_t *arg_ray;
     float *fine;
+    int32_t *spill;       // deep stack entries: [(depth - SL) * spill_stride + lane]
+    int64_t spill_stride; // lanes in the launch
 };
 
 constexpr int kTraceWaves = 4;
 
+// One internal node: test both children's boxes, descend into the nearer hit
+// child and push the farther one; pop when neither is hit.
+template <int SL, bool STATS>
+__device__ __forceinline__ void inner_step(const TraceArgs &A, const RaySetup &R, int &node, int &sp, int *stk,
+                                           int32_t *spill, float tbest, uint32_t &st_nodes)
+{
+    if (STATS) ++st_nodes;
+    const BvhNode *nd = A.bvh.nodes + node;
+    const float4 a = nd->xy0, b = nd->xy1, z = nd->z01;
+    const int4 m = nd->meta;
+    const float t0 = box_entry(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest);
+    const float t1 = box_entry(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest);
+    const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
+    if (h0 && h1) {
+        const bool first0 = t0 <= t1;
+        const int far = first0 ? m.y : m.x;
+        if (sp < SL) stk[sp * kWave] = far;
+        else spill[(int64_t)(sp - SL) * A.spill_stride] = far;
+        ++sp;
+        node = first0 ? m.x : m.y;
+    } else if (h0 || h1) {
+        node = h0 ? m.x : m.y;
+    } else if (sp == 0) {
+        node = kDone;
+    } else {
+        --sp;
+        node = sp < SL ? stk[sp * kWave] : spill[(int64_t)(sp - SL) * A.spill_stride];
+    }
+}
+
+template <int SL>
+__device__ __forceinline__ int stack_pop(const TraceArgs &A, int &sp, const int *stk, const int32_t *spill)
+{
+    if (sp == 0) return kDone;
+    --sp;
+    return sp < SL ? stk[sp * kWave] : spill[(int64_t)(sp - SL) * A.spill_stride];
+}
+
+// Persistent tracer.  Traversal is organised in two phases per iteration
+// (after Aila and Laine's "while-while" loop with postponed leaves): first
+// every lane walks internal nodes until it holds a leaf to test (a lane that
+// already holds one keeps walking, so it is not idle, and stops at its second
+// leaf); then all lanes test their leaf's triangles together.  Mixing node and
+// triangle work in one iteration would leave most lanes masked off in each.
 // Instrumented runs (STATS) also count node visits, triangle tests and rays
 // into 64-bit counters at workspace offsets 8, 16 and 24.
-template <int SD, int REFILL, bool STATS>
+template <int SL, int REFILL, bool STATS>
 __global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArgs A)
 {
     uint32_t st_nodes = 0, st_tris = 0, st_rays = 0;
-    __shared__ int stack_mem[kTraceWaves * SD * kWave];
+    __shared__ int stack_mem[kTraceWaves * SL * kWave];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int *stk = stack_mem + wave * SD * kWave + lane;
+    int *stk = stack_mem + wave * SL * kWave + lane;
+    int32_t *spill = A.spill + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t frame = A.frame_ptr ? *A.frame_ptr : A.frame;
     const int total = min(*A.count, A.queue_cap);
     const int nfm = A.nf - 1;
@@ -272,7 +321,7 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArg
     float ox = 0.f, oy = 0.f, oz = 0.f;
     RaySetup R;
     float tbest = __builtin_inff();
-    int ibest = -1, node = kDone, sp = 0;
+    int ibest = -1, node = kDone, leaf = kDone, sp = 0;
     bool front = false;
     float rmin = __builtin_inff();
     int argray = -1, argtri = -1;
@@ -286,6 +335,7 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArg
         ibest = -1;
         front = false;
         node = A.nt > 0 ? 0 : kDone;
+        leaf = kDone;
         sp = 0;
     };
 
@@ -293,10 +343,11 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArg
         // hand out texels to idle lanes, one atomic per wavefront
         const uint64_t need = __ballot(texel < 0);
         if (need != 0 && !exhausted) {
+            const int leader = __ffsll((unsigned long long)need) - 1;
             const int nneed = __popcll(need);
             int base = 0;
-            if (lane == __ffsll((unsigned long long)need) - 1) base = atomicAdd(A.cursor, nneed);
-            base = __shfl(base, __ffsll((unsigned long long)need) - 1);
+            if (lane == leader) base = atomicAdd(A.cursor, nneed);
+            base = __shfl(base, leader);
             if (base + nneed >= total) exhausted = true;
             if (texel < 0) {
                 const int slot = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
@@ -323,14 +374,33 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArg
         }
         // traverse until enough lanes have finished their ray (or are idle)
         while (true) {
-            if (texel >= 0 && node != kDone)
-                trav_step<STATS>(A.bvh, R, node, sp, stk, kWave, tbest, ibest, front, &st_nodes, &st_tris);
-            const uint64_t done = __ballot(texel < 0 || node == kDone);
-            const int ndone = __popcll(done);
-            if (ndone >= REFILL || (ndone > 0 && exhausted && ndone == __popcll(__ballot(true)))) break;
-            if (ndone == kWave) break;
+            const bool active = texel >= 0;
+            if (active && leaf == kDone && node < 0 && node != kDone) {
+                leaf = node;
+                node = stack_pop<SL>(A, sp, stk, spill);
+            }
+            // phase 1: internal nodes until every active lane holds a leaf or is done
+            while (__ballot(active && node >= 0 && leaf == kDone)) {
+                if (active && node >= 0) {
+                    inner_step<SL, STATS>(A, R, node, sp, stk, spill, tbest, st_nodes);
+                    if (node < 0 && node != kDone && leaf == kDone) {
+                        leaf = node;
+                        node = stack_pop<SL>(A, sp, stk, spill);
+                    }
+                }
+            }
+            // phase 2: triangles of the held leaves
+            if (active && leaf != kDone) {
+                const int first = leaf_first(leaf), cnt = leaf_count(leaf);
+                if (STATS) st_tris += (uint32_t)cnt;
+                for (int i = first; i < first + cnt; ++i)
+                    tri_test(R, A.bvh.tris[3 * i], A.bvh.tris[3 * i + 1], A.bvh.tris[3 * i + 2], tbest, ibest, front);
+                leaf = kDone;
+            }
+            const uint64_t done = __ballot(!active || (node == kDone && leaf == kDone));
+            if (__popcll(done) >= REFILL) break;
         }
-        if (texel >= 0 && node == kDone) {
+        if (texel >= 0 && node == kDone && leaf == kDone) {
             if (STATS) ++st_rays;
             if (ibest >= 0) {
                 const float dist = tbest * R.len;
@@ -501,50 +571,65 @@ __global__ void __launch_bounds__(256) trace_backward_kernel(const float *__rest
 
 // ------------------------------------------------------------- launch ----
 
-struct TraceConfig {
-    int stack_depth;    // chosen >= hierarchy depth
-    int refill;         // lanes finished before refilling
-    int blocks_per_cu;  // persistent workgroups per compute unit
-};
-
 static int g_trace_refill = 16;
 static int g_trace_blocks_per_cu = 0;  // 0: occupancy limit
 static int g_trace_stats = 0;
+constexpr int kShortStack = 16;        // LDS part of each lane's traversal stack
+constexpr int kMaxBlocksPerCu = 8;     // persistent workgroups per CU (spill area sized for this)
 
-template <int SD, int REFILL, bool STATS>
-static int launch_trace_sd3(const TraceArgs &A, hipStream_t s)
+template <int SL, int REFILL, bool STATS>
+static int launch_trace3(TraceArgs A, hipStream_t s)
 {
     int per_cu = g_trace_blocks_per_cu;
     if (per_cu <= 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent<SD, REFILL, STATS>,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent<SL, REFILL, STATS>,
                                                          kTraceWaves * kWave, 0) != hipSuccess ||
             per_cu <= 0)
             per_cu = 2;
     }
+    per_cu = std::min(per_cu, kMaxBlocksPerCu);
     const int blocks = num_cus() * per_cu;
-    trace_persistent<SD, REFILL, STATS><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
+    A.spill_stride = (int64_t)blocks * kTraceWaves * kWave;
+    trace_persistent<SL, REFILL, STATS><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
     RTSDF_CHECK_LAUNCH();
     return RTSDF_OK;
 }
 
-template <int SD, int REFILL>
-static int launch_trace_sd(const TraceArgs &A, hipStream_t s)
+template <int REFILL>
+static int launch_trace2(const TraceArgs &A, hipStream_t s)
 {
-    return g_trace_stats ? launch_trace_sd3<SD, REFILL, true>(A, s) : launch_trace_sd3<SD, REFILL, false>(A, s);
+    return g_trace_stats ? launch_trace3<kShortStack, REFILL, true>(A, s)
+                         : launch_trace3<kShortStack, REFILL, false>(A, s);
 }
 
-template <int SD>
-static int launch_trace_refill(const TraceArgs &A, hipStream_t s)
+static int launch_trace(const TraceArgs &A, hipStream_t s)
 {
     switch (g_trace_refill) {
-    case 1: return launch_trace_sd<SD, 1>(A, s);
-    case 8: return launch_trace_sd<SD, 8>(A, s);
-    case 32: return launch_trace_sd<SD, 32>(A, s);
-    default: return launch_trace_sd<SD, 16>(A, s);
+    case 1: return launch_trace2<1>(A, s);
+    case 8: return launch_trace2<8>(A, s);
+    case 32: return launch_trace2<32>(A, s);
+    default: return launch_trace2<16>(A, s);
     }
 }
 
 static int stack_depth_for(const rtsdf_scene *sc) { return sc->max_depth + 1; }
+
+// spill area for stack entries beyond the LDS part (allocated once per scene)
+static int ensure_spill(rtsdf_scene *sc)
+{
+    const int deep = stack_depth_for(sc) - kShortStack;
+    if (deep <= 0) return RTSDF_OK;
+    const int64_t lanes = (int64_t)num_cus() * kMaxBlocksPerCu * kTraceWaves * kWave;
+    const int64_t need = lanes * deep;
+    if (sc->spill && sc->spill_entries >= need) return RTSDF_OK;
+    if (sc->spill) (void)hipFree(sc->spill);
+    sc->spill = nullptr;
+    sc->spill_entries = 0;
+    if (hipMalloc((void **)&sc->spill, sizeof(int32_t) * need) != hipSuccess) return RTSDF_ENOMEM;
+    sc->spill_entries = need;
+    sc->bytes += (int64_t)sizeof(int32_t) * need;
+    return RTSDF_OK;
+}
 
 }  // namespace rtsdf
 
@@ -588,6 +673,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     if (frame >= (1u << 23) && !frame_ptr) return RTSDF_EINVAL;
     const int sd = stack_depth_for(scene);
     if (sd > 64) return RTSDF_EINVAL;
+    if (!scene->spill && sd > kShortStack) return RTSDF_EINVAL;  // created without its spill area
     hipStream_t s = as_stream(stream);
     const int lognf = ilog2(fine.n), logr = ilog2(fine.n / coarse.n);
     const int64_t ntex = (int64_t)fine.n * fine.n * fine.n;
@@ -625,11 +711,9 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     A.arg_tri = st.arg_tri;
     A.arg_ray = st.arg_ray;
     A.fine = fine_sdf;
-    if (sd <= 16) return launch_trace_refill<16>(A, s);
-    if (sd <= 24) return launch_trace_refill<24>(A, s);
-    if (sd <= 32) return launch_trace_refill<32>(A, s);
-    if (sd <= 48) return launch_trace_refill<48>(A, s);
-    return launch_trace_refill<64>(A, s);
+    A.spill = scene->spill;
+    A.spill_stride = 0;
+    return launch_trace(A, s);
 }
 
 extern "C" int rtsdf_directions(const int32_t *texel, const uint32_t *frame, const int32_t *ray, int32_t n,

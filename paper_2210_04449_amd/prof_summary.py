@@ -1,0 +1,70 @@
+"""Summaries of rocprofv3 CSV output (kernel statistics and PMC counters).
+
+    python -m paper_2210_04449_amd.prof_summary stats <dir>/<name>_kernel_stats.csv
+    python -m paper_2210_04449_amd.prof_summary pmc <counter_collection.csv> [...]
+
+The PMC summary reports counter values per dispatch for each kernel.  HBM
+bytes come from FETCH_SIZE and WRITE_SIZE (KiB per dispatch); each is scaled
+by what the same counter reads for the device-to-device copy of a known size
+that ``bench.py --calibrate-copy`` performs first (256 MiB read, 256 MiB
+written; the copy runs as ``__amd_rocclr_copyBuffer``).
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import sys
+
+COPY_BYTES = 256 << 20
+
+
+def stats(path: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = [f"{'kernel':<100} {'calls':>5} {'avg_us':>12} {'min_us':>11} {'max_us':>11}"]
+    for r in rows:
+        out.append(f"{r['Name'][:100]:<100} {r['Calls']:>5} {float(r['AverageNs']) / 1e3:>12.1f} "
+                   f"{float(r['MinNs']) / 1e3:>11.1f} {float(r['MaxNs']) / 1e3:>11.1f}")
+    return "\n".join(out)
+
+
+def pmc(paths: list[str]) -> str:
+    per = collections.defaultdict(lambda: collections.defaultdict(list))  # kernel -> counter -> per dispatch
+    for p in paths:
+        acc = collections.defaultdict(float)
+        names = {}
+        for r in csv.DictReader(open(p)):
+            key = (r["Dispatch_Id"], r["Counter_Name"])
+            acc[key] += float(r["Counter_Value"])
+            names[r["Dispatch_Id"]] = r["Kernel_Name"]
+        for (disp, ctr), v in acc.items():
+            per[names[disp]][ctr].append(v)
+    out = []
+    scale = {}
+    for k, cs in per.items():
+        if "copyBuffer" in k:
+            for c in ("FETCH_SIZE", "WRITE_SIZE"):
+                if c in cs:
+                    scale[c] = COPY_BYTES / (sum(cs[c]) * 1024.0)
+    out.append("copy calibration (256 MiB device-to-device): bytes per counted byte = "
+               + ", ".join(f"{c} x{v:.3f}" for c, v in sorted(scale.items())))
+    for k, cs in sorted(per.items(), key=lambda kv: kv[0]):
+        out.append(f"\n{k}")
+        for c, vals in sorted(cs.items()):
+            mean = sum(vals) / len(vals)
+            line = f"  {c:<28} per dispatch {mean:>20.1f}  ({len(vals)} dispatches)"
+            if c in scale:
+                line += f"  -> {mean * 1024.0 * scale[c] / 1e6:.2f} MB"
+            out.append(line)
+    return "\n".join(out)
+
+
+def main(argv):
+    if len(argv) < 3 or argv[1] not in ("stats", "pmc"):
+        print(__doc__)
+        return 2
+    print(stats(argv[2]) if argv[1] == "stats" else pmc(argv[2:]))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv))
