@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--refill", type=int, default=16)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--loop", type=int, default=1, choices=[0, 1])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (scale for HBM byte counters)")
     return ap.parse_args()
@@ -115,7 +116,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    R.rtsdf_trace_config(args.refill, args.blocks_per_cu, False)
+    R.rtsdf_trace_config(args.refill, args.blocks_per_cu, False, args.loop)
     p = Pipeline(torch.from_numpy(w.mesh.vertices).to(dev), torch.from_numpy(w.mesh.faces).to(dev), w.nc, w.nf,
                  w.beta, w.d, w.rays, seed=0, scene_id=w.scene_seed, alpha=w.alpha)
     stream = torch.cuda.current_stream()
@@ -149,11 +150,11 @@ def main():
     trace_s = stage["trace"] / 1e3
 
     # instrumented frame (untimed): node visits and triangle tests per ray
-    R.rtsdf_trace_config(args.refill, args.blocks_per_cu, True)
+    R.rtsdf_trace_config(args.refill, args.blocks_per_cu, True, args.loop)
     p.trace(args.warmup + K)
     torch.cuda.synchronize()
     ctr = p.trace_ws[8:32].view(torch.int64).cpu().tolist()
-    R.rtsdf_trace_config(args.refill, args.blocks_per_cu, False)
+    R.rtsdf_trace_config(args.refill, args.blocks_per_cu, False, args.loop)
     nodes_per_ray = ctr[0] / max(ctr[2], 1)
     tris_per_ray = ctr[1] / max(ctr[2], 1)
     ops = rays * (OPS_RAY + nodes_per_ray * OPS_NODE + tris_per_ray * OPS_TRI)

@@ -225,13 +225,17 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
                            rtsdf_accum state, float *fine_sdf, void *workspace, rtsdf_stream stream);
 
 /* Tuning and instrumentation of the tracer (process-wide, host-side state):
- * refill         a wavefront hands out new work once this many of its lanes
- *                have finished their ray (1, 8, 16 or 32);
+ * refill         a wavefront hands out new rays once this many of its lanes
+ *                are free (1, 8, 16 or 32);
  * blocks_per_cu  persistent workgroups per compute unit (0 = occupancy limit);
  * stats          1: count node visits, triangle tests and rays into 64-bit
  *                counters at byte offsets 8, 16 and 24 of the workspace
- *                (slower; for measurement only).                            */
-int rtsdf_trace_config(int32_t refill, int32_t blocks_per_cu, int32_t stats);
+ *                (slower; for measurement only);
+ * loop           traversal loop shape: 0 = two phases per iteration (all
+ *                lanes walk nodes until each holds a leaf, then test the
+ *                leaves), 1 = one unit of work per lane per iteration (a
+ *                triangle, a node, or opening a leaf).  Results are identical. */
+int rtsdf_trace_config(int32_t refill, int32_t blocks_per_cu, int32_t stats, int32_t loop);
 
 /* Ray directions exactly as rtsdf_trace_accumulate draws them, for n keys  */
 /* (texel[i], frame[i], ray[i]) with one seed and scene id: out float32      */

@@ -62,7 +62,7 @@ __device__ __forceinline__ float uniform_pm1(uint32_t h)
     return (float)((int32_t)((h >> 9) << 1) + 1 - 8388608) * 0x1p-23f;
 }
 
-__device__ __noinline__ float3 sphere_dir(uint64_t seed, uint32_t texel, uint32_t frame, uint32_t ray, uint32_t scene)
+__device__ __forceinline__ float3 sphere_dir(uint64_t seed, uint32_t texel, uint32_t frame, uint32_t ray, uint32_t scene)
 {
     for (uint32_t attempt = 0; attempt < 8; ++attempt) {
         uint64_t c[4] = {(uint64_t)texel, ((uint64_t)frame << 32) | ray, (uint64_t)scene, (uint64_t)attempt};
@@ -297,154 +297,259 @@ __device__ __forceinline__ int stack_pop(const TraceArgs &A, int &sp, const int 
     return sp < SL ? stk[sp * kWave] : spill[(int64_t)(sp - SL) * A.spill_stride];
 }
 
-// Persistent tracer.  Traversal is organised in two phases per iteration
-// (after Aila and Laine's "while-while" loop with postponed leaves): first
-// every lane walks internal nodes until it holds a leaf to test (a lane that
-// already holds one keeps walking, so it is not idle, and stops at its second
-// leaf); then all lanes test their leaf's triangles together.  Mixing node and
-// triangle work in one iteration would leave most lanes masked off in each.
+// Octahedral direction bin (8 x 8 cells of the octahedral map, numbered in
+// Morton order so consecutive bins are neighbours on the sphere).
+constexpr int kBins = 64;
+__device__ __forceinline__ int direction_bin(float3 d)
+{
+    const float s = fabsf(d.x) + fabsf(d.y) + fabsf(d.z);
+    float u = d.x / s, v = d.y / s;
+    if (d.z < 0.0f) {
+        const float uu = (1.0f - fabsf(v)) * (u >= 0.0f ? 1.0f : -1.0f);
+        const float vv = (1.0f - fabsf(u)) * (v >= 0.0f ? 1.0f : -1.0f);
+        u = uu;
+        v = vv;
+    }
+    const int bu = min(7, max(0, (int)((u + 1.0f) * 4.0f)));
+    const int bv = min(7, max(0, (int)((v + 1.0f) * 4.0f)));
+    return (int)((bu & 1) | ((bv & 1) << 1) | ((bu & 2) << 1) | ((bv & 2) << 2) |
+                                          ((bu & 4) << 2) | ((bv & 4) << 3));
+}
+
+constexpr int kTileRays = 1024;  // rays per wavefront tile
+constexpr int kTileTexels = 64;
+
+struct WaveTile {
+    int32_t tex[kTileTexels];
+    unsigned long long key[kTileTexels];  // min over rays of (distance bits << 32 | ray << 26 | triangle)
+    uint32_t cnt[kTileTexels];            // front | back << 16 for this frame
+    uint32_t bin[kBins];                  // bin counts, then bin cursors
+    uint16_t perm[kTileRays];             // ray ids (slot * R + ray) sorted by direction bin
+    uint8_t binof[kTileRays];             // direction bin of each ray
+};
+
+// Persistent tracer.  Each wavefront repeatedly takes a tile of up to 64
+// consecutive queue texels (Morton order: a compact block of the fine grid),
+// draws all their rays' directions, sorts the rays by direction bin in LDS, and
+// traces them in that order, so the lanes of a wavefront follow rays that
+// start close together and point the same way.  Results are folded per texel
+// with LDS atomics (a 64-bit min keeps the smallest distance, ties to the
+// lowest ray index, together with its triangle; an add counts front and back
+// hits), which makes them independent of the order rays complete in.  The
+// traversal itself runs in two phases per iteration (after Aila and Laine's
+// "while-while" loop with postponed leaves): every lane walks internal nodes
+// until it holds a leaf (a lane that already holds one keeps walking and
+// stops at its second), then all held leaves are tested together.
 // Instrumented runs (STATS) also count node visits, triangle tests and rays
 // into 64-bit counters at workspace offsets 8, 16 and 24.
-template <int SL, int REFILL, bool STATS>
+template <int SL, int REFILL, int LOOP, bool STATS>
 __global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArgs A)
 {
     uint32_t st_nodes = 0, st_tris = 0, st_rays = 0;
     __shared__ int stack_mem[kTraceWaves * SL * kWave];
+    __shared__ WaveTile tiles[kTraceWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int *stk = stack_mem + wave * SL * kWave + lane;
+    WaveTile &T = tiles[wave];
     int32_t *spill = A.spill + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t frame = A.frame_ptr ? *A.frame_ptr : A.frame;
     const int total = min(*A.count, A.queue_cap);
     const int nfm = A.nf - 1;
-
-    int texel = -1, r = 0;
-    float ox = 0.f, oy = 0.f, oz = 0.f;
-    RaySetup R;
-    float tbest = __builtin_inff();
-    int ibest = -1, node = kDone, leaf = kDone, sp = 0;
-    bool front = false;
-    float rmin = __builtin_inff();
-    int argray = -1, argtri = -1;
-    uint32_t nF = 0, nB = 0;
-    bool exhausted = false;
-
-    auto start_ray = [&]() {
-        const float3 d = sphere_dir(A.seed, (uint32_t)texel, frame, (uint32_t)r, A.scene_id);
-        ray_setup(ox, oy, oz, d.x, d.y, d.z, R);
-        tbest = __builtin_inff();
-        ibest = -1;
-        front = false;
-        node = A.nt > 0 ? 0 : kDone;
-        leaf = kDone;
-        sp = 0;
-    };
+    const int R = A.rays;
+    const int tile_texels = min(kTileTexels, kTileRays / R);
+    const uint64_t ntex_grid = (uint64_t)1 << (3 * A.lognf);
 
     while (true) {
-        // hand out texels to idle lanes, one atomic per wavefront
-        const uint64_t need = __ballot(texel < 0);
-        if (need != 0 && !exhausted) {
-            const int leader = __ffsll((unsigned long long)need) - 1;
-            const int nneed = __popcll(need);
-            int base = 0;
-            if (lane == leader) base = atomicAdd(A.cursor, nneed);
-            base = __shfl(base, leader);
-            if (base + nneed >= total) exhausted = true;
-            if (texel < 0) {
-                const int slot = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
-                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
-                if (slot < total) {
-                    const int j = A.queue[slot];
-                    if (j >= 0 && (int64_t)j < ((int64_t)1 << (3 * A.lognf))) {
-                        texel = j;
-                        r = 0;
-                        rmin = __builtin_inff();
-                        argray = argtri = -1;
-                        nF = nB = 0;
-                        ox = texel_coord(A.lox, j & nfm, A.hf);
-                        oy = texel_coord(A.loy, (j >> A.lognf) & nfm, A.hf);
-                        oz = texel_coord(A.loz, j >> (2 * A.lognf), A.hf);
-                        start_ray();
-                    }
-                }
+        // ---- take a tile of texels
+        int base = 0;
+        if (lane == 0) base = atomicAdd(A.cursor, tile_texels);
+        base = __shfl(base, 0);
+        if (base >= total) break;
+        const int nt = min(tile_texels, total - base);
+        const int nrays = nt * R;
+        if (lane < nt) {
+            int j = A.queue[base + lane];
+            if (j < 0 || (uint64_t)j >= ntex_grid) j = -1;
+            T.tex[lane] = j;
+            T.key[lane] = ~0ull;
+            T.cnt[lane] = 0u;
+        }
+        T.bin[lane] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // ---- bin the tile's rays by direction (16 rays per lane)
+#pragma unroll 1
+        for (int q = lane; q < nrays; q += kWave) {
+            const int slot = q / R, r = q - slot * R;
+            const int j = T.tex[slot];
+            int b = 0;
+            if (j >= 0) b = direction_bin(sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, A.scene_id));
+            T.binof[q] = (uint8_t)b;
+            atomicAdd(&T.bin[b], 1u);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        {  // exclusive scan of the 64 bin counts, one per lane
+            const uint32_t c = T.bin[lane];
+            uint32_t x = c;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const uint32_t y = __shfl_up(x, off);
+                if (lane >= off) x += y;
             }
+            T.bin[lane] = x - c;
         }
-        if (__ballot(texel >= 0) == 0) {
-            if (exhausted) break;
-            continue;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+        for (int q = lane; q < nrays; q += kWave) {
+            const uint32_t pos = atomicAdd(&T.bin[T.binof[q]], 1u);
+            T.perm[pos] = (uint16_t)q;
         }
-        // traverse until enough lanes have finished their ray (or are idle)
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+
+        // ---- trace the tile's rays in bin order
+        int pool = 0;
+        bool busy = false;
+        int q = 0, slot = 0, r = 0;
+        RaySetup Rs;
+        float tbest = __builtin_inff();
+        int ibest = -1, node = kDone, leaf = kDone, sp = 0;
+        int tri_cur = 0, tri_end = 0;
+        bool front = false;
         while (true) {
-            const bool active = texel >= 0;
-            if (active && leaf == kDone && node < 0 && node != kDone) {
-                leaf = node;
-                node = stack_pop<SL>(A, sp, stk, spill);
+            const uint64_t need = __ballot(!busy);
+            if (need != 0 && pool < nrays) {
+                const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+                const int take = min(__popcll(need), nrays - pool);
+                if (!busy && rank < take) {
+                    q = T.perm[pool + rank];
+                    slot = q / R;
+                    r = q - slot * R;
+                    const int j = T.tex[slot];
+                    if (j >= 0) {
+                        const float ox = texel_coord(A.lox, j & nfm, A.hf);
+                        const float oy = texel_coord(A.loy, (j >> A.lognf) & nfm, A.hf);
+                        const float oz = texel_coord(A.loz, j >> (2 * A.lognf), A.hf);
+                        const float3 d = sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, A.scene_id);
+                        ray_setup(ox, oy, oz, d.x, d.y, d.z, Rs);
+                        node = A.nt > 0 ? 0 : kDone;
+                    } else {
+                        node = kDone;
+                    }
+                    tbest = __builtin_inff();
+                    ibest = -1;
+                    front = false;
+                    leaf = kDone;
+                    tri_cur = tri_end = 0;
+                    sp = 0;
+                    busy = true;
+                }
+                pool += take;
             }
-            // phase 1: internal nodes until every active lane holds a leaf or is done
-            while (__ballot(active && node >= 0 && leaf == kDone)) {
-                if (active && node >= 0) {
-                    inner_step<SL, STATS>(A, R, node, sp, stk, spill, tbest, st_nodes);
-                    if (node < 0 && node != kDone && leaf == kDone) {
+            if (__ballot(busy) == 0) break;
+            const int refill_at = pool < nrays ? REFILL : kWave;
+            if (LOOP == 0) {
+                while (true) {
+                    if (busy && leaf == kDone && node < 0 && node != kDone) {
                         leaf = node;
                         node = stack_pop<SL>(A, sp, stk, spill);
                     }
+                    // phase 1: internal nodes until every busy lane holds a leaf or is done
+                    while (__ballot(busy && node >= 0 && leaf == kDone)) {
+                        if (busy && node >= 0) {
+                            inner_step<SL, STATS>(A, Rs, node, sp, stk, spill, tbest, st_nodes);
+                            if (node < 0 && node != kDone && leaf == kDone) {
+                                leaf = node;
+                                node = stack_pop<SL>(A, sp, stk, spill);
+                            }
+                        }
+                    }
+                    // phase 2: triangles of the held leaves
+                    if (busy && leaf != kDone) {
+                        const int first = leaf_first(leaf), cnt = leaf_count(leaf);
+                        if (STATS) st_tris += (uint32_t)cnt;
+                        for (int i = first; i < first + cnt; ++i)
+                            tri_test(Rs, A.bvh.tris[3 * i], A.bvh.tris[3 * i + 1], A.bvh.tris[3 * i + 2], tbest,
+                                     ibest, front);
+                        leaf = kDone;
+                    }
+                    const uint64_t done = __ballot(!busy || (node == kDone && leaf == kDone));
+                    if (__popcll(done) >= refill_at) break;
                 }
-            }
-            // phase 2: triangles of the held leaves
-            if (active && leaf != kDone) {
-                const int first = leaf_first(leaf), cnt = leaf_count(leaf);
-                if (STATS) st_tris += (uint32_t)cnt;
-                for (int i = first; i < first + cnt; ++i)
-                    tri_test(R, A.bvh.tris[3 * i], A.bvh.tris[3 * i + 1], A.bvh.tris[3 * i + 2], tbest, ibest, front);
-                leaf = kDone;
-            }
-            const uint64_t done = __ballot(!active || (node == kDone && leaf == kDone));
-            if (__popcll(done) >= REFILL) break;
-        }
-        if (texel >= 0 && node == kDone && leaf == kDone) {
-            if (STATS) ++st_rays;
-            if (ibest >= 0) {
-                const float dist = tbest * R.len;
-                if (dist < rmin) {
-                    rmin = dist;
-                    argray = r;
-                    argtri = ibest;
-                }
-                if (front) ++nF;
-                else ++nB;
-            }
-            ++r;
-            if (r < A.rays) {
-                start_ray();
             } else {
-                // Eq. (1) on the unsigned state, then the sign vote
-                const int j = texel;
-                const int x = j & nfm, y = (j >> A.lognf) & nfm, z = j >> (2 * A.lognf);
-                const float c = A.coarse_sdf[(x >> A.logr) + A.nc * ((y >> A.logr) + A.nc * (z >> A.logr))];
-                const float uprev = A.u[j];
-                const uint32_t h = A.hits[j];
-                const uint32_t F = min((h & 0xFFFFu) + nF, 0xFFFFu), B = min((h >> 16) + nB, 0xFFFFu);
-                float uu;
-                if (A.alpha == 1.0f) {
-                    uu = uprev;
-                } else {
-                    uu = A.alpha * uprev + (1.0f - A.alpha) * fmaxf(c, 0.0f);
+                // one unit of work per lane per iteration: a triangle of the
+                // current leaf, else one internal node, else open the next leaf
+                while (true) {
+                    if (busy) {
+                        if (tri_cur < tri_end) {
+                            if (STATS) ++st_tris;
+                            tri_test(Rs, A.bvh.tris[3 * tri_cur], A.bvh.tris[3 * tri_cur + 1],
+                                     A.bvh.tris[3 * tri_cur + 2], tbest, ibest, front);
+                            ++tri_cur;
+                        } else if (node >= 0) {
+                            inner_step<SL, STATS>(A, Rs, node, sp, stk, spill, tbest, st_nodes);
+                        } else if (node != kDone) {
+                            tri_cur = leaf_first(node);
+                            tri_end = tri_cur + leaf_count(node);
+                            node = stack_pop<SL>(A, sp, stk, spill);
+                        }
+                    }
+                    const uint64_t done = __ballot(!busy || (node == kDone && tri_cur >= tri_end));
+                    if (__popcll(done) >= refill_at) break;
                 }
-                if (rmin < uu) {
-                    uu = rmin;
-                    A.arg_tri[j] = argtri;
-                    A.arg_ray[j] = (int32_t)((frame << 8) | (uint32_t)argray);
-                } else if (A.alpha != 1.0f) {
-                    A.arg_tri[j] = -1;
-                    A.arg_ray[j] = -1;
+            }
+            if (busy && node == kDone && leaf == kDone && tri_cur >= tri_end) {
+                if (STATS) ++st_rays;
+                if (ibest >= 0) {
+                    const float dist = tbest * Rs.len;
+                    const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) |
+                                                   ((unsigned long long)r << 26) | (unsigned long long)ibest;
+                    atomicMin(&T.key[slot], key);
+                    atomicAdd(&T.cnt[slot], front ? 1u : 0x10000u);
                 }
-                A.u[j] = uu;
-                A.hits[j] = F | (B << 16);
-                float f = isinf(uu) ? c : uu;
-                A.fine[j] = B > F ? -f : f;
-                texel = -1;
-                node = kDone;
+                busy = false;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+
+        // ---- Eq. (1) on the unsigned state, then the sign vote
+        if (lane < nt && T.tex[lane] >= 0) {
+            const int j = T.tex[lane];
+            const unsigned long long key = T.key[lane];
+            const uint32_t fc = T.cnt[lane];
+            const float rmin = key == ~0ull ? __builtin_inff() : __uint_as_float((uint32_t)(key >> 32));
+            const int argray = (int)((key >> 26) & 63u), argtri = (int)(key & ((1u << 26) - 1u));
+            const int x = j & nfm, y = (j >> A.lognf) & nfm, z = j >> (2 * A.lognf);
+            const float c = A.coarse_sdf[(x >> A.logr) + A.nc * ((y >> A.logr) + A.nc * (z >> A.logr))];
+            const float uprev = A.u[j];
+            const uint32_t h = A.hits[j];
+            const uint32_t F = min((h & 0xFFFFu) + (fc & 0xFFFFu), 0xFFFFu);
+            const uint32_t B = min((h >> 16) + (fc >> 16), 0xFFFFu);
+            float uu;
+            if (A.alpha == 1.0f) {
+                uu = uprev;
+            } else {
+                uu = A.alpha * uprev + (1.0f - A.alpha) * fmaxf(c, 0.0f);
+            }
+            if (rmin < uu) {
+                uu = rmin;
+                A.arg_tri[j] = argtri;
+                A.arg_ray[j] = (int32_t)((frame << 8) | (uint32_t)argray);
+            } else if (A.alpha != 1.0f) {
+                A.arg_tri[j] = -1;
+                A.arg_ray[j] = -1;
+            }
+            A.u[j] = uu;
+            A.hits[j] = F | (B << 16);
+            const float f = isinf(uu) ? c : uu;
+            A.fine[j] = B > F ? -f : f;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
     if (STATS) {
         unsigned long long *ctr = reinterpret_cast<unsigned long long *>(A.cursor + 2);
@@ -577,12 +682,14 @@ static int g_trace_stats = 0;
 constexpr int kShortStack = 16;        // LDS part of each lane's traversal stack
 constexpr int kMaxBlocksPerCu = 8;     // persistent workgroups per CU (spill area sized for this)
 
-template <int SL, int REFILL, bool STATS>
-static int launch_trace3(TraceArgs A, hipStream_t s)
+static int g_trace_loop = 1;  // 0: while-while phases, 1: one unit of work per iteration
+
+template <int SL, int REFILL, int LOOP, bool STATS>
+static int launch_trace4(TraceArgs A, hipStream_t s)
 {
     int per_cu = g_trace_blocks_per_cu;
     if (per_cu <= 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent<SL, REFILL, STATS>,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent<SL, REFILL, LOOP, STATS>,
                                                          kTraceWaves * kWave, 0) != hipSuccess ||
             per_cu <= 0)
             per_cu = 2;
@@ -590,16 +697,22 @@ static int launch_trace3(TraceArgs A, hipStream_t s)
     per_cu = std::min(per_cu, kMaxBlocksPerCu);
     const int blocks = num_cus() * per_cu;
     A.spill_stride = (int64_t)blocks * kTraceWaves * kWave;
-    trace_persistent<SL, REFILL, STATS><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
+    trace_persistent<SL, REFILL, LOOP, STATS><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
     RTSDF_CHECK_LAUNCH();
     return RTSDF_OK;
+}
+
+template <int REFILL, int LOOP>
+static int launch_trace3(const TraceArgs &A, hipStream_t s)
+{
+    return g_trace_stats ? launch_trace4<kShortStack, REFILL, LOOP, true>(A, s)
+                         : launch_trace4<kShortStack, REFILL, LOOP, false>(A, s);
 }
 
 template <int REFILL>
 static int launch_trace2(const TraceArgs &A, hipStream_t s)
 {
-    return g_trace_stats ? launch_trace3<kShortStack, REFILL, true>(A, s)
-                         : launch_trace3<kShortStack, REFILL, false>(A, s);
+    return g_trace_loop ? launch_trace3<REFILL, 1>(A, s) : launch_trace3<REFILL, 0>(A, s);
 }
 
 static int launch_trace(const TraceArgs &A, hipStream_t s)
@@ -633,13 +746,14 @@ static int ensure_spill(rtsdf_scene *sc)
 
 }  // namespace rtsdf
 
-extern "C" int rtsdf_trace_config(int32_t refill, int32_t blocks_per_cu, int32_t stats)
+extern "C" int rtsdf_trace_config(int32_t refill, int32_t blocks_per_cu, int32_t stats, int32_t loop)
 {
     if (refill != 1 && refill != 8 && refill != 16 && refill != 32) return RTSDF_EINVAL;
-    if (blocks_per_cu < 0 || blocks_per_cu > 64 || stats < 0 || stats > 1) return RTSDF_EINVAL;
+    if (blocks_per_cu < 0 || blocks_per_cu > 64 || stats < 0 || stats > 1 || loop < 0 || loop > 1) return RTSDF_EINVAL;
     rtsdf::g_trace_refill = refill;
     rtsdf::g_trace_blocks_per_cu = blocks_per_cu;
     rtsdf::g_trace_stats = stats;
+    rtsdf::g_trace_loop = loop;
     return RTSDF_OK;
 }
 
@@ -674,6 +788,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     const int sd = stack_depth_for(scene);
     if (sd > 64) return RTSDF_EINVAL;
     if (!scene->spill && sd > kShortStack) return RTSDF_EINVAL;  // created without its spill area
+    if (scene->nt >= (1 << 26)) return RTSDF_EINVAL;  // triangle ids share a 64-bit key with the distance
     hipStream_t s = as_stream(stream);
     const int lognf = ilog2(fine.n), logr = ilog2(fine.n / coarse.n);
     const int64_t ntex = (int64_t)fine.n * fine.n * fine.n;

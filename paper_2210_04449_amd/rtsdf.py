@@ -74,7 +74,7 @@ def _load():
         "rtsdf_trace_workspace_size": ([], _sz),
         "rtsdf_trace_accumulate": ([_P, Grid, _P, Grid, _P, _P, _P, _i32, _i32, _u32, _P, _u64, _u32, _f32,
                                     Accum, _P, _P, _P], _i32),
-        "rtsdf_trace_config": ([_i32, _i32, _i32], _i32),
+        "rtsdf_trace_config": ([_i32, _i32, _i32, _i32], _i32),
         "rtsdf_directions": ([_P, _P, _P, _i32, _u64, _u32, _P, _P], _i32),
         "rtsdf_closest_hits": ([_P, _P, _P, _i32, _P, _P, _P, _P], _i32),
         "rtsdf_trace_backward": ([_P, Grid, Accum, _P, _P, _u64, _u32, _P, _P], _i32),
@@ -219,8 +219,9 @@ def rtsdf_trace_workspace_size() -> int:
     return int(_lib.rtsdf_trace_workspace_size())
 
 
-def rtsdf_trace_config(refill: int = 16, blocks_per_cu: int = 0, stats: bool = False):
-    _check("rtsdf_trace_config", _lib.rtsdf_trace_config(int(refill), int(blocks_per_cu), int(bool(stats))))
+def rtsdf_trace_config(refill: int = 16, blocks_per_cu: int = 0, stats: bool = False, loop: int = 1):
+    _check("rtsdf_trace_config", _lib.rtsdf_trace_config(int(refill), int(blocks_per_cu), int(bool(stats)),
+                                                         int(loop)))
 
 
 def rtsdf_trace_accumulate(scene: Scene, coarse: Grid, coarse_sdf, fine: Grid, mask, queue, count,

@@ -73,5 +73,6 @@ def test_host_validation(R):
                                     dummy, dummy, None) == R.EINVAL
     ld = (C.c_float * 3)(0, 1, 0)
     assert L.rtsdf_shadow(fine, dummy, dummy, 4, ld, 8.0, 0.0, 16, 0.1, 1.0, dummy, None) == R.EINVAL  # eps 0
-    assert L.rtsdf_trace_config(3, 0, 0) == R.EINVAL
+    assert L.rtsdf_trace_config(3, 0, 0, 1) == R.EINVAL
+    assert L.rtsdf_trace_config(16, 0, 0, 2) == R.EINVAL
     assert R.rtsdf_select_workspace_size(128) >= (128 ** 3 // 1024) * 4
