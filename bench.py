@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--refill", type=int, default=16)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--loop", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--bin", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--stack-lds", type=int, default=12, choices=[12, 16, 24])
+    ap.add_argument("--leaf-size", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (scale for HBM byte counters)")
     return ap.parse_args()
@@ -108,6 +111,8 @@ def main():
     from synth.scenes import workload
 
     w = workload(args.config)
+    tuning = dict(refill=args.refill, blocks_per_cu=args.blocks_per_cu, stats=0, loop=args.loop,
+                  bin_directions=args.bin, stack_lds=args.stack_lds)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.calibrate_copy:
@@ -116,9 +121,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    R.rtsdf_trace_config(args.refill, args.blocks_per_cu, False, args.loop)
+    R.rtsdf_trace_config(**tuning)
     p = Pipeline(torch.from_numpy(w.mesh.vertices).to(dev), torch.from_numpy(w.mesh.faces).to(dev), w.nc, w.nf,
-                 w.beta, w.d, w.rays, seed=0, scene_id=w.scene_seed, alpha=w.alpha)
+                 w.beta, w.d, w.rays, seed=0, scene_id=w.scene_seed, alpha=w.alpha, leaf_size=args.leaf_size)
+    info = p.scene.info()
     stream = torch.cuda.current_stream()
     for f in range(args.warmup):
         p.step(f)
@@ -150,11 +156,11 @@ def main():
     trace_s = stage["trace"] / 1e3
 
     # instrumented frame (untimed): node visits and triangle tests per ray
-    R.rtsdf_trace_config(args.refill, args.blocks_per_cu, True, args.loop)
+    R.rtsdf_trace_config(**{**tuning, "stats": 1})
     p.trace(args.warmup + K)
     torch.cuda.synchronize()
     ctr = p.trace_ws[8:32].view(torch.int64).cpu().tolist()
-    R.rtsdf_trace_config(args.refill, args.blocks_per_cu, False, args.loop)
+    R.rtsdf_trace_config(**tuning)
     nodes_per_ray = ctr[0] / max(ctr[2], 1)
     tris_per_ray = ctr[1] / max(ctr[2], 1)
     ops = rays * (OPS_RAY + nodes_per_ray * OPS_NODE + tris_per_ray * OPS_TRI)
@@ -194,7 +200,9 @@ def main():
         "jfa": {"gbps": round(jfa_gbs, 1), "frac_hbm": round(jfa_gbs / HBM_PEAK_GBS, 4),
                 "algorithmic_bytes": jfa_bytes},
         "trace_stats": {"nodes_per_ray": round(nodes_per_ray, 2), "tris_per_ray": round(tris_per_ray, 2),
-                        "rays_counted": ctr[2]},
+                        "rays_counted": ctr[2], "bvh_nodes": info.nodes, "bvh_max_depth": info.max_depth,
+                        "bvh_max_leaf": info.leaf_size, "leaf_size": args.leaf_size},
+        "trace_tuning": tuning,
         "roofline": {
             "kernel": "trace_persistent",
             "bound": "alu",

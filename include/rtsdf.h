@@ -224,18 +224,28 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
                            const uint32_t *frame_ptr, uint64_t seed, uint32_t scene_id, float alpha,
                            rtsdf_accum state, float *fine_sdf, void *workspace, rtsdf_stream stream);
 
-/* Tuning and instrumentation of the tracer (process-wide, host-side state):
- * refill         a wavefront hands out new rays once this many of its lanes
- *                are free (1, 8, 16 or 32);
- * blocks_per_cu  persistent workgroups per compute unit (0 = occupancy limit);
- * stats          1: count node visits, triangle tests and rays into 64-bit
- *                counters at byte offsets 8, 16 and 24 of the workspace
- *                (slower; for measurement only);
- * loop           traversal loop shape: 0 = two phases per iteration (all
- *                lanes walk nodes until each holds a leaf, then test the
- *                leaves), 1 = one unit of work per lane per iteration (a
- *                triangle, a node, or opening a leaf).  Results are identical. */
-int rtsdf_trace_config(int32_t refill, int32_t blocks_per_cu, int32_t stats, int32_t loop);
+/* Tuning and instrumentation of the tracer (process-wide host-side state,
+ * read at each rtsdf_trace_accumulate call; results never depend on it):
+ *   refill          a wavefront hands out new rays once this many of its
+ *                   lanes are free (8 or 16);
+ *   blocks_per_cu   persistent workgroups per compute unit (0 = as many as
+ *                   fit, at most 8);
+ *   stats           1: count node visits, triangle tests and rays into 64-bit
+ *                   counters at byte offsets 8, 16 and 24 of the workspace
+ *                   (slower; for measurement only);
+ *   loop            0: two phases per iteration (walk nodes until every lane
+ *                   holds a leaf, then test the leaves); 1: one unit of work
+ *                   per lane per iteration (a triangle or a node);
+ *   bin_directions  1: each wavefront's tile of rays is sorted by direction
+ *                   before tracing (coherence); 0: queue order;
+ *   stack_lds       traversal stack entries kept in LDS per lane (12, 16 or
+ *                   24); deeper entries go to a spill area of the scene.
+ * rtsdf_trace_config rejects values outside these sets with RTSDF_EINVAL. */
+typedef struct rtsdf_trace_tuning {
+    int32_t refill, blocks_per_cu, stats, loop, bin_directions, stack_lds;
+} rtsdf_trace_tuning;
+int rtsdf_trace_config(const rtsdf_trace_tuning *tuning);
+int rtsdf_trace_config_get(rtsdf_trace_tuning *tuning);
 
 /* Ray directions exactly as rtsdf_trace_accumulate draws them, for n keys  */
 /* (texel[i], frame[i], ray[i]) with one seed and scene id: out float32      */

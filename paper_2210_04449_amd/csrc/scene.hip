@@ -197,7 +197,7 @@ struct HostBuilder {
         if (best_axis < 0) return build_split(b, e, b + count / 2, depth);
         const Aabb box = range_box(b, e);
         const double leaf_cost = box.area() * count;
-        if (count <= 8 && best_cost + box.area() >= leaf_cost) {
+        if (count <= 2 * leaf_size && best_cost + box.area() >= leaf_cost) {
             max_depth = std::max(max_depth, depth);
             max_leaf = std::max(max_leaf, count);
             return leaf_code(b, count);

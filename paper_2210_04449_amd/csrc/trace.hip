@@ -255,18 +255,50 @@ struct TraceArgs {
     float *fine;
     int32_t *spill;       // deep stack entries: [(depth - SL) * spill_stride + lane]
     int64_t spill_stride; // lanes in the launch
+    int bin_directions;   // sort each tile's rays by direction bin
 };
 
 constexpr int kTraceWaves = 4;
 
+typedef __attribute__((address_space(3))) int lds_int;
+
+__device__ __forceinline__ const BvhNode *node_ptr(const BvhNode *base, int node)
+{
+    return reinterpret_cast<const BvhNode *>(reinterpret_cast<const char *>(base) + (uint32_t)node * 64u);
+}
+
+__device__ __forceinline__ const float4 *tri_ptr(const float4 *base, int tri)
+{
+    return reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + (uint32_t)tri * 48u);
+}
+
+template <int SL>
+__device__ __forceinline__ void stack_push(const TraceArgs &A, int &sp, lds_int *stk, int32_t *spill, int v)
+{
+    if (sp < SL) stk[sp * kWave] = v;
+    else spill[(sp - SL) * (int)A.spill_stride] = v;
+    ++sp;
+}
+
+template <int SL>
+__device__ __forceinline__ int stack_pop(const TraceArgs &A, int &sp, const lds_int *stk, const int32_t *spill)
+{
+    if (sp == 0) return kDone;
+    --sp;
+    int v;
+    if (sp < SL) v = stk[sp * kWave];
+    else v = spill[(sp - SL) * (int)A.spill_stride];
+    return v;
+}
+
 // One internal node: test both children's boxes, descend into the nearer hit
 // child and push the farther one; pop when neither is hit.
 template <int SL, bool STATS>
-__device__ __forceinline__ void inner_step(const TraceArgs &A, const RaySetup &R, int &node, int &sp, int *stk,
+__device__ __forceinline__ void inner_step(const TraceArgs &A, const RaySetup &R, int &node, int &sp, lds_int *stk,
                                            int32_t *spill, float tbest, uint32_t &st_nodes)
 {
     if (STATS) ++st_nodes;
-    const BvhNode *nd = A.bvh.nodes + node;
+    const BvhNode *nd = node_ptr(A.bvh.nodes, node);
     const float4 a = nd->xy0, b = nd->xy1, z = nd->z01;
     const int4 m = nd->meta;
     const float t0 = box_entry(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest);
@@ -274,27 +306,51 @@ __device__ __forceinline__ void inner_step(const TraceArgs &A, const RaySetup &R
     const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
     if (h0 && h1) {
         const bool first0 = t0 <= t1;
-        const int far = first0 ? m.y : m.x;
-        if (sp < SL) stk[sp * kWave] = far;
-        else spill[(int64_t)(sp - SL) * A.spill_stride] = far;
-        ++sp;
+        stack_push<SL>(A, sp, stk, spill, first0 ? m.y : m.x);
         node = first0 ? m.x : m.y;
     } else if (h0 || h1) {
         node = h0 ? m.x : m.y;
-    } else if (sp == 0) {
-        node = kDone;
     } else {
-        --sp;
-        node = sp < SL ? stk[sp * kWave] : spill[(int64_t)(sp - SL) * A.spill_stride];
+        node = stack_pop<SL>(A, sp, stk, spill);
     }
 }
 
-template <int SL>
-__device__ __forceinline__ int stack_pop(const TraceArgs &A, int &sp, const int *stk, const int32_t *spill)
+// Same, but a leaf child is opened at once (its triangle range becomes the
+// lane's current work) instead of costing an iteration of its own.
+template <int SL, bool STATS>
+__device__ __forceinline__ void node_step(const TraceArgs &A, const RaySetup &R, int &node, int &sp, lds_int *stk,
+                                          int32_t *spill, float tbest, int &tri_cur, int &tri_end, uint32_t &st_nodes)
 {
-    if (sp == 0) return kDone;
-    --sp;
-    return sp < SL ? stk[sp * kWave] : spill[(int64_t)(sp - SL) * A.spill_stride];
+    if (STATS) ++st_nodes;
+    const BvhNode *nd = node_ptr(A.bvh.nodes, node);
+    const float4 a = nd->xy0, b = nd->xy1, z = nd->z01;
+    const int4 m = nd->meta;
+    const float t0 = box_entry(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest);
+    const float t1 = box_entry(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest);
+    const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
+    if (h0 && h1) {
+        const bool first0 = t0 <= t1;
+        const int near = first0 ? m.x : m.y, far = first0 ? m.y : m.x;
+        if (near < 0) {
+            tri_cur = leaf_first(near);
+            tri_end = tri_cur + leaf_count(near);
+            node = far;
+        } else {
+            stack_push<SL>(A, sp, stk, spill, far);
+            node = near;
+        }
+    } else if (h0 || h1) {
+        const int c = h0 ? m.x : m.y;
+        if (c < 0) {
+            tri_cur = leaf_first(c);
+            tri_end = tri_cur + leaf_count(c);
+            node = stack_pop<SL>(A, sp, stk, spill);
+        } else {
+            node = c;
+        }
+    } else {
+        node = stack_pop<SL>(A, sp, stk, spill);
+    }
 }
 
 // Octahedral direction bin (8 x 8 cells of the octahedral map, numbered in
@@ -316,7 +372,7 @@ __device__ __forceinline__ int direction_bin(float3 d)
                                           ((bu & 4) << 2) | ((bv & 4) << 3));
 }
 
-constexpr int kTileRays = 1024;  // rays per wavefront tile
+constexpr int kTileRays = 768;  // rays per wavefront tile
 constexpr int kTileTexels = 64;
 
 struct WaveTile {
@@ -343,13 +399,13 @@ struct WaveTile {
 // Instrumented runs (STATS) also count node visits, triangle tests and rays
 // into 64-bit counters at workspace offsets 8, 16 and 24.
 template <int SL, int REFILL, int LOOP, bool STATS>
-__global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArgs A)
+__global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_waves_per_eu(6, 8))) trace_persistent(TraceArgs A)
 {
     uint32_t st_nodes = 0, st_tris = 0, st_rays = 0;
     __shared__ int stack_mem[kTraceWaves * SL * kWave];
     __shared__ WaveTile tiles[kTraceWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int *stk = stack_mem + wave * SL * kWave + lane;
+    lds_int *stk = (lds_int *)(stack_mem + wave * SL * kWave + lane);
     WaveTile &T = tiles[wave];
     int32_t *spill = A.spill + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t frame = A.frame_ptr ? *A.frame_ptr : A.frame;
@@ -383,7 +439,8 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArg
             const int slot = q / R, r = q - slot * R;
             const int j = T.tex[slot];
             int b = 0;
-            if (j >= 0) b = direction_bin(sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, A.scene_id));
+            if (j >= 0 && A.bin_directions)
+                b = direction_bin(sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, A.scene_id));
             T.binof[q] = (uint8_t)b;
             atomicAdd(&T.bin[b], 1u);
         }
@@ -486,11 +543,11 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) trace_persistent(TraceArg
                     if (busy) {
                         if (tri_cur < tri_end) {
                             if (STATS) ++st_tris;
-                            tri_test(Rs, A.bvh.tris[3 * tri_cur], A.bvh.tris[3 * tri_cur + 1],
-                                     A.bvh.tris[3 * tri_cur + 2], tbest, ibest, front);
+                            const float4 *tp = tri_ptr(A.bvh.tris, tri_cur);
+                            tri_test(Rs, tp[0], tp[1], tp[2], tbest, ibest, front);
                             ++tri_cur;
                         } else if (node >= 0) {
-                            inner_step<SL, STATS>(A, Rs, node, sp, stk, spill, tbest, st_nodes);
+                            node_step<SL, STATS>(A, Rs, node, sp, stk, spill, tbest, tri_cur, tri_end, st_nodes);
                         } else if (node != kDone) {
                             tri_cur = leaf_first(node);
                             tri_end = tri_cur + leaf_count(node);
@@ -676,18 +733,14 @@ __global__ void __launch_bounds__(256) trace_backward_kernel(const float *__rest
 
 // ------------------------------------------------------------- launch ----
 
-static int g_trace_refill = 16;
-static int g_trace_blocks_per_cu = 0;  // 0: occupancy limit
-static int g_trace_stats = 0;
-constexpr int kShortStack = 16;        // LDS part of each lane's traversal stack
-constexpr int kMaxBlocksPerCu = 8;     // persistent workgroups per CU (spill area sized for this)
-
-static int g_trace_loop = 1;  // 0: while-while phases, 1: one unit of work per iteration
+static rtsdf_trace_tuning g_tuning = {16, 0, 0, 1, 1, 12};
+constexpr int kMaxBlocksPerCu = 8;  // persistent workgroups per CU (spill area sized for this)
+constexpr int kMinShortStack = 12;  // smallest LDS stack part (spill area sized for this)
 
 template <int SL, int REFILL, int LOOP, bool STATS>
 static int launch_trace4(TraceArgs A, hipStream_t s)
 {
-    int per_cu = g_trace_blocks_per_cu;
+    int per_cu = g_tuning.blocks_per_cu;
     if (per_cu <= 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent<SL, REFILL, LOOP, STATS>,
                                                          kTraceWaves * kWave, 0) != hipSuccess ||
@@ -702,26 +755,30 @@ static int launch_trace4(TraceArgs A, hipStream_t s)
     return RTSDF_OK;
 }
 
-template <int REFILL, int LOOP>
+template <int SL, int REFILL, int LOOP>
 static int launch_trace3(const TraceArgs &A, hipStream_t s)
 {
-    return g_trace_stats ? launch_trace4<kShortStack, REFILL, LOOP, true>(A, s)
-                         : launch_trace4<kShortStack, REFILL, LOOP, false>(A, s);
+    return g_tuning.stats ? launch_trace4<SL, REFILL, LOOP, true>(A, s) : launch_trace4<SL, REFILL, LOOP, false>(A, s);
 }
 
-template <int REFILL>
+template <int SL, int REFILL>
 static int launch_trace2(const TraceArgs &A, hipStream_t s)
 {
-    return g_trace_loop ? launch_trace3<REFILL, 1>(A, s) : launch_trace3<REFILL, 0>(A, s);
+    return g_tuning.loop ? launch_trace3<SL, REFILL, 1>(A, s) : launch_trace3<SL, REFILL, 0>(A, s);
+}
+
+template <int SL>
+static int launch_trace1(const TraceArgs &A, hipStream_t s)
+{
+    return g_tuning.refill == 8 ? launch_trace2<SL, 8>(A, s) : launch_trace2<SL, 16>(A, s);
 }
 
 static int launch_trace(const TraceArgs &A, hipStream_t s)
 {
-    switch (g_trace_refill) {
-    case 1: return launch_trace2<1>(A, s);
-    case 8: return launch_trace2<8>(A, s);
-    case 32: return launch_trace2<32>(A, s);
-    default: return launch_trace2<16>(A, s);
+    switch (g_tuning.stack_lds) {
+    case 12: return launch_trace1<12>(A, s);
+    case 24: return launch_trace1<24>(A, s);
+    default: return launch_trace1<16>(A, s);
     }
 }
 
@@ -730,7 +787,7 @@ static int stack_depth_for(const rtsdf_scene *sc) { return sc->max_depth + 1; }
 // spill area for stack entries beyond the LDS part (allocated once per scene)
 static int ensure_spill(rtsdf_scene *sc)
 {
-    const int deep = stack_depth_for(sc) - kShortStack;
+    const int deep = stack_depth_for(sc) - kMinShortStack;
     if (deep <= 0) return RTSDF_OK;
     const int64_t lanes = (int64_t)num_cus() * kMaxBlocksPerCu * kTraceWaves * kWave;
     const int64_t need = lanes * deep;
@@ -746,14 +803,22 @@ static int ensure_spill(rtsdf_scene *sc)
 
 }  // namespace rtsdf
 
-extern "C" int rtsdf_trace_config(int32_t refill, int32_t blocks_per_cu, int32_t stats, int32_t loop)
+extern "C" int rtsdf_trace_config(const rtsdf_trace_tuning *t)
 {
-    if (refill != 1 && refill != 8 && refill != 16 && refill != 32) return RTSDF_EINVAL;
-    if (blocks_per_cu < 0 || blocks_per_cu > 64 || stats < 0 || stats > 1 || loop < 0 || loop > 1) return RTSDF_EINVAL;
-    rtsdf::g_trace_refill = refill;
-    rtsdf::g_trace_blocks_per_cu = blocks_per_cu;
-    rtsdf::g_trace_stats = stats;
-    rtsdf::g_trace_loop = loop;
+    if (!t) return RTSDF_EINVAL;
+    if (t->refill != 8 && t->refill != 16) return RTSDF_EINVAL;
+    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return RTSDF_EINVAL;
+    if (t->stats < 0 || t->stats > 1 || t->loop < 0 || t->loop > 1) return RTSDF_EINVAL;
+    if (t->bin_directions < 0 || t->bin_directions > 1) return RTSDF_EINVAL;
+    if (t->stack_lds != 12 && t->stack_lds != 16 && t->stack_lds != 24) return RTSDF_EINVAL;
+    rtsdf::g_tuning = *t;
+    return RTSDF_OK;
+}
+
+extern "C" int rtsdf_trace_config_get(rtsdf_trace_tuning *t)
+{
+    if (!t) return RTSDF_EINVAL;
+    *t = rtsdf::g_tuning;
     return RTSDF_OK;
 }
 
@@ -787,7 +852,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     if (frame >= (1u << 23) && !frame_ptr) return RTSDF_EINVAL;
     const int sd = stack_depth_for(scene);
     if (sd > 64) return RTSDF_EINVAL;
-    if (!scene->spill && sd > kShortStack) return RTSDF_EINVAL;  // created without its spill area
+    if (!scene->spill && sd > kMinShortStack) return RTSDF_EINVAL;  // created without its spill area
     if (scene->nt >= (1 << 26)) return RTSDF_EINVAL;  // triangle ids share a 64-bit key with the distance
     hipStream_t s = as_stream(stream);
     const int lognf = ilog2(fine.n), logr = ilog2(fine.n / coarse.n);
@@ -796,7 +861,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
         mask, coarse_sdf, coarse.n, logr, lognf, ntex, st.u, st.hits, st.arg_tri, st.arg_ray, fine_sdf);
     RTSDF_CHECK_LAUNCH();
     int32_t *cursor = static_cast<int32_t *>(workspace);
-    int rc = launch_fill<int32_t>(cursor, 0, g_trace_stats ? 8 : 1, s);
+    int rc = launch_fill<int32_t>(cursor, 0, g_tuning.stats ? 8 : 1, s);
     if (rc != RTSDF_OK) return rc;
     TraceArgs A;
     A.bvh.nodes = scene->nodes;
@@ -828,6 +893,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     A.fine = fine_sdf;
     A.spill = scene->spill;
     A.spill_stride = 0;
+    A.bin_directions = g_tuning.bin_directions;
     return launch_trace(A, s);
 }
 

@@ -16,7 +16,8 @@ from . import rtsdf as R
 class Pipeline:
     def __init__(self, vertices: torch.Tensor, faces: torch.Tensor, nc: int, nf: int, beta: float, d: float,
                  rays: int, seed: int = 0, scene_id: int = 0, alpha: float = 1.0, lo=(0.0, 0.0, 0.0),
-                 side: float = 1.0, leaf_size: int = 4, queue_cap: int | None = None, device="cuda"):
+                 side: float = 1.0, leaf_size: int = 2, queue_cap: int | None = None, device="cuda"):
+        self.leaf_size = int(leaf_size)
         self.device = torch.device(device)
         self.vertices = vertices.to(self.device, torch.float32).contiguous()
         self.faces = faces.to(self.device, torch.int32).contiguous()

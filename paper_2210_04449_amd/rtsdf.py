@@ -40,6 +40,14 @@ class Accum(C.Structure):
     _fields_ = [("u", _P), ("hits", _P), ("arg_tri", _P), ("arg_ray", _P)]
 
 
+class TraceTuning(C.Structure):
+    _fields_ = [("refill", _i32), ("blocks_per_cu", _i32), ("stats", _i32), ("loop", _i32),
+                ("bin_directions", _i32), ("stack_lds", _i32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class SceneInfo(C.Structure):
     _fields_ = [("nv", _i32), ("nt", _i32), ("nodes", _i32), ("max_depth", _i32), ("leaf_size", _i32),
                 ("device_bytes", C.c_int64)]
@@ -74,7 +82,8 @@ def _load():
         "rtsdf_trace_workspace_size": ([], _sz),
         "rtsdf_trace_accumulate": ([_P, Grid, _P, Grid, _P, _P, _P, _i32, _i32, _u32, _P, _u64, _u32, _f32,
                                     Accum, _P, _P, _P], _i32),
-        "rtsdf_trace_config": ([_i32, _i32, _i32, _i32], _i32),
+        "rtsdf_trace_config": ([C.POINTER(TraceTuning)], _i32),
+        "rtsdf_trace_config_get": ([C.POINTER(TraceTuning)], _i32),
         "rtsdf_directions": ([_P, _P, _P, _i32, _u64, _u32, _P, _P], _i32),
         "rtsdf_closest_hits": ([_P, _P, _P, _i32, _P, _P, _P, _P], _i32),
         "rtsdf_trace_backward": ([_P, Grid, Accum, _P, _P, _u64, _u32, _P, _P], _i32),
@@ -219,9 +228,18 @@ def rtsdf_trace_workspace_size() -> int:
     return int(_lib.rtsdf_trace_workspace_size())
 
 
-def rtsdf_trace_config(refill: int = 16, blocks_per_cu: int = 0, stats: bool = False, loop: int = 1):
-    _check("rtsdf_trace_config", _lib.rtsdf_trace_config(int(refill), int(blocks_per_cu), int(bool(stats)),
-                                                         int(loop)))
+def rtsdf_trace_config_get() -> TraceTuning:
+    t = TraceTuning()
+    _check("rtsdf_trace_config_get", _lib.rtsdf_trace_config_get(C.byref(t)))
+    return t
+
+
+def rtsdf_trace_config(**kw) -> TraceTuning:
+    """Update the tracer tuning (fields of rtsdf_trace_tuning); returns the previous one."""
+    old = rtsdf_trace_config_get()
+    t = TraceTuning(**{**old.as_dict(), **kw})
+    _check("rtsdf_trace_config", _lib.rtsdf_trace_config(C.byref(t)))
+    return old
 
 
 def rtsdf_trace_accumulate(scene: Scene, coarse: Grid, coarse_sdf, fine: Grid, mask, queue, count,

@@ -73,6 +73,12 @@ def test_host_validation(R):
                                     dummy, dummy, None) == R.EINVAL
     ld = (C.c_float * 3)(0, 1, 0)
     assert L.rtsdf_shadow(fine, dummy, dummy, 4, ld, 8.0, 0.0, 16, 0.1, 1.0, dummy, None) == R.EINVAL  # eps 0
-    assert L.rtsdf_trace_config(3, 0, 0, 1) == R.EINVAL
-    assert L.rtsdf_trace_config(16, 0, 0, 2) == R.EINVAL
+    for bad in (dict(refill=3), dict(loop=2), dict(stack_lds=20), dict(bin_directions=5), dict(blocks_per_cu=-1)):
+        t = R.TraceTuning(**{**R.rtsdf_trace_config_get().as_dict(), **bad})
+        assert L.rtsdf_trace_config(C.byref(t)) == R.EINVAL
+    assert L.rtsdf_trace_config(None) == R.EINVAL
+    default = R.rtsdf_trace_config_get().as_dict()
+    prev = R.rtsdf_trace_config(refill=8, stack_lds=24)
+    assert prev.as_dict() == default and R.rtsdf_trace_config_get().refill == 8
+    R.rtsdf_trace_config(**default)
     assert R.rtsdf_select_workspace_size(128) >= (128 ** 3 // 1024) * 4
