@@ -49,6 +49,7 @@
 #ifndef RTSDF_H
 #define RTSDF_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -86,6 +87,10 @@ int rtsdf_version(void); /* 100 * major + minor */
  * current device.  Returns RTSDF_OK if no bit was set, else RTSDF_EDEVICE
  * with the bits in *bits (may be NULL). */
 int rtsdf_sync_status(rtsdf_stream stream, uint32_t *bits);
+
+/* Device-to-device copy of `bytes` bytes on `stream` (lets bindings copy
+ * library-owned buffers, e.g. a batch's outputs, into their own memory). */
+int rtsdf_copy(void *dst, const void *src, size_t bytes, rtsdf_stream stream);
 
 /* ------------------------------------------------------------------------ */
 /* 1. Voxelization (Sec. 2.1).                                               */
@@ -271,6 +276,98 @@ int rtsdf_closest_hits(const rtsdf_scene *scene, const float *origins, const flo
 int rtsdf_trace_backward(const rtsdf_scene *scene, rtsdf_grid fine, rtsdf_accum state,
                          const float *fine_sdf, const float *grad_fine, uint64_t seed,
                          uint32_t scene_id, float *grad_v, rtsdf_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* One SDF update as a captured graph.  The descriptor names every buffer of */
+/* the per-frame sequence (the same ones the stage calls take); create        */
+/* records  [refit ->] voxelize -> jfa -> select -> trace_accumulate  on a   */
+/* private stream (it synchronises `stream` first) and instantiates it;      */
+/* each launch replays the whole update on `stream` for frame index          */
+/* *frame_counter (device uint32) and then increments that counter.  The     */
+/* descriptor's pointers must stay valid while the graph exists; buffers     */
+/* are cleared with kernels only (no memset nodes).                          */
+/* ------------------------------------------------------------------------ */
+typedef struct rtsdf_frame_desc {
+    const float *vertices;      /* [nv][3]; refit reads it every launch if refit != 0 */
+    int32_t nv;
+    const int32_t *faces;       /* [nt][3] */
+    int32_t nt;
+    rtsdf_scene *scene;
+    int32_t refit;              /* 1: refit the scene from `vertices` each frame */
+    rtsdf_grid coarse, fine;
+    float beta, d;
+    int32_t rays_per_texel;
+    uint64_t seed;
+    uint32_t scene_id;
+    float alpha;
+    int32_t *seeds, *scratch, *dist2; /* [n_c^3] each */
+    float *coarse_sdf;                /* [n_c^3] */
+    uint8_t *mask;                    /* [n_f^3] */
+    int32_t *queue;                   /* [queue_cap] */
+    int32_t queue_cap;
+    int32_t *count;                   /* [1] */
+    void *select_workspace;           /* rtsdf_select_workspace_size(coarse.n) bytes */
+    rtsdf_accum state;
+    float *fine_sdf;                  /* [n_f^3] */
+    void *trace_workspace;            /* rtsdf_trace_workspace_size() bytes */
+    uint32_t *frame_counter;          /* [1], device */
+} rtsdf_frame_desc;
+
+typedef struct rtsdf_frame_graph rtsdf_frame_graph;
+int rtsdf_frame_graph_create(const rtsdf_frame_desc *desc, rtsdf_frame_graph **out, rtsdf_stream stream);
+int rtsdf_frame_graph_launch(rtsdf_frame_graph *graph, rtsdf_stream stream);
+void rtsdf_frame_graph_destroy(rtsdf_frame_graph *graph);
+
+/* ------------------------------------------------------------------------ */
+/* Many independent scenes per launch.  create copies each mesh (device     */
+/* pointers, as for rtsdf_scene_create), builds its hierarchy, allocates     */
+/* every buffer of every scene and resets the accumulation state; it         */
+/* synchronises `stream`.  step runs one SDF update of all scenes -- one     */
+/* launch per stage for the whole batch -- for frame index `frame` (or       */
+/* *frame_ptr if non-NULL).  Each scene's results are bit-identical to its   */
+/* single-scene run.  outputs gives device pointers into the batch's pools   */
+/* (valid until destroy).  Grids: coarse_n a power of two in [8, 128],       */
+/* fine_n a power-of-two multiple of it (at most 1024), both spanning the    */
+/* cube [lo, lo + side].                                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct rtsdf_batch rtsdf_batch;
+
+typedef struct rtsdf_batch_scene {
+    const float *vertices;  /* [nv][3], device */
+    int32_t nv;
+    const int32_t *faces;   /* [nt][3], device */
+    int32_t nt;
+    float lo[3];
+    float side;
+    int32_t coarse_n, fine_n;
+    float beta, d;
+    int32_t rays_per_texel;
+    float alpha;
+    uint32_t scene_id;      /* part of the ray counter (distinct scenes draw distinct rays) */
+} rtsdf_batch_scene;
+
+typedef struct rtsdf_batch_view {
+    rtsdf_grid coarse, fine;
+    int32_t *seeds, *dist2;
+    float *coarse_sdf;
+    uint8_t *mask;
+    int32_t *queue;
+    int32_t *count;
+    rtsdf_accum state;
+    float *fine_sdf;
+    rtsdf_scene *scene;
+} rtsdf_batch_view;
+
+int rtsdf_batch_create(const rtsdf_batch_scene *scenes /* host array [n] */, int32_t n, uint64_t seed,
+                       int32_t leaf_size, rtsdf_batch **out, rtsdf_stream stream);
+int rtsdf_batch_reset(rtsdf_batch *batch, rtsdf_stream stream);
+int rtsdf_batch_step(rtsdf_batch *batch, uint32_t frame, const uint32_t *frame_ptr, rtsdf_stream stream);
+int rtsdf_batch_outputs(const rtsdf_batch *batch, int32_t index, rtsdf_batch_view *out);
+/* one batch step as a captured graph: each launch runs the step for frame
+ * *frame_counter (device) and then increments it */
+int rtsdf_batch_graph_create(rtsdf_batch *batch, uint32_t *frame_counter, rtsdf_frame_graph **out,
+                             rtsdf_stream stream);
+void rtsdf_batch_destroy(rtsdf_batch *batch);
 
 /* ------------------------------------------------------------------------ */
 /* 5. Soft shadows (Sec. 2.3): for each point p, march from p towards the    */

@@ -28,3 +28,12 @@ extern "C" int rtsdf_sync_status(rtsdf_stream stream, uint32_t *bits)
     if (bits) *bits = word;
     return word ? RTSDF_EDEVICE : RTSDF_OK;
 }
+
+extern "C" int rtsdf_copy(void *dst, const void *src, size_t bytes, rtsdf_stream stream)
+{
+    if (bytes == 0) return RTSDF_OK;
+    if (!dst || !src) return RTSDF_EINVAL;
+    if (hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, rtsdf::as_stream(stream)) != hipSuccess)
+        return RTSDF_EHIP;
+    return RTSDF_OK;
+}

@@ -106,10 +106,9 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks)
 }
 
 // linear caller layout -> packed brick layout
-__global__ void __launch_bounds__(256) jfa_to_bricks(const int32_t *__restrict__ src, int32_t *__restrict__ dst,
-                                                     int n, int logn)
+__device__ __forceinline__ void jfa_to_bricks_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                                   int logn, int64_t e)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int B = n >> 2;
     const int b = (int)(e >> 6), l = (int)(e & 63);
     const int bx = b % B, by = (b / B) % B, bz = b / (B * B);
@@ -117,16 +116,23 @@ __global__ void __launch_bounds__(256) jfa_to_bricks(const int32_t *__restrict__
     dst[e] = (int32_t)pack_linear(src[x + n * (y + n * z)], logn);
 }
 
-// One pass with step k >= 4 (a multiple of the brick size).  LINEAR_IN: the
-// source is the caller's linear index array (first pass only).
+__global__ void __launch_bounds__(256) jfa_to_bricks(const int32_t *__restrict__ src, int32_t *__restrict__ dst,
+                                                     int n, int logn)
+{
+    jfa_to_bricks_body(src, dst, n, logn, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// One pass with step k >= 4 (a multiple of the brick size) for the four
+// bricks of workgroup `blk` of `nblk`.  LINEAR_IN: the source is the caller's
+// linear index array (first pass only).
 template <bool WIDE, bool LINEAR_IN>
-__global__ void __launch_bounds__(256) jfa_far(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
-                                               int logn, int kb)
+__device__ __forceinline__ void jfa_far_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                             int logn, int kb, uint32_t blk, uint32_t nblk)
 {
     const int B = n >> 2;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int b = (int)xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+    const int b = (int)xcd_remap(blk, nblk) * 4 + wave;
     const int bx = b % B, by = (b / B) % B, bz = b / (B * B);
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
     const JfaPos P = jfa_pos<WIDE>(bx * 4 + lx, by * 4 + ly, bz * 4 + lz);
@@ -151,18 +157,25 @@ __global__ void __launch_bounds__(256) jfa_far(const int32_t *__restrict__ src, 
     dst[(int64_t)b * 64 + lane] = (int32_t)key_seed(best);
 }
 
+template <bool WIDE, bool LINEAR_IN>
+__global__ void __launch_bounds__(256) jfa_far(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                               int logn, int kb)
+{
+    jfa_far_body<WIDE, LINEAR_IN>(src, dst, n, logn, kb, blockIdx.x, gridDim.x);
+}
+
 // One pass with step K in {1, 2}: eight bricks (an 8^3 block) per workgroup,
 // staged with a K-voxel halo in LDS.  FINAL writes the caller's outputs.
 template <int K, bool WIDE, bool FINAL>
-__global__ void __launch_bounds__(512) jfa_near(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
-                                                int logn, int32_t *__restrict__ dist2, float *__restrict__ sdf,
-                                                float h, float beta)
+__device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                              int logn, int32_t *__restrict__ dist2, float *__restrict__ sdf, float h,
+                                              float beta, uint32_t blk_id, uint32_t nblk)
 {
     constexpr int T = 8 + 2 * K;
     __shared__ uint32_t tile[T * T * T];
     const int B = n >> 2;
     const int TB = n >> 3;  // 8^3 blocks per axis
-    const int blk = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int blk = (int)xcd_remap(blk_id, nblk);
     const int tx0 = (blk % TB) * 8, ty0 = ((blk / TB) % TB) * 8, tz0 = (blk / (TB * TB)) * 8;
     for (int i = threadIdx.x; i < T * T * T; i += blockDim.x) {
         const int x = tx0 - K + i % T, y = ty0 - K + (i / T) % T, z = tz0 - K + i / (T * T);
@@ -203,6 +216,14 @@ __global__ void __launch_bounds__(512) jfa_near(const int32_t *__restrict__ src,
             sdf[idx] = rn_sub(rn_mul(h, rn_sqrt((float)d2)), beta);
         }
     }
+}
+
+template <int K, bool WIDE, bool FINAL>
+__global__ void __launch_bounds__(512) jfa_near(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                                int logn, int32_t *__restrict__ dist2, float *__restrict__ sdf,
+                                                float h, float beta)
+{
+    jfa_near_body<K, WIDE, FINAL>(src, dst, n, logn, dist2, sdf, h, beta, blockIdx.x, gridDim.x);
 }
 
 template <bool WIDE>

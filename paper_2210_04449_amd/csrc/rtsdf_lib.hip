@@ -7,3 +7,5 @@
 #include "scene.hip"
 #include "trace.hip"
 #include "shadow.hip"
+#include "batch.hip"
+#include "graph.hip"

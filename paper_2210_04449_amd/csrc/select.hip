@@ -37,14 +37,14 @@ __device__ __forceinline__ uint32_t wave_prefix(uint64_t mask)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__global__ void __launch_bounds__(kSelBlock) select_count(const int32_t *__restrict__ d2, int logn, int K,
-                                                          uint32_t total, uint32_t *__restrict__ block_sums)
+__device__ __forceinline__ void select_count_body(const int32_t *__restrict__ d2, int logn, int K, uint32_t total,
+                                                  uint32_t *__restrict__ block_sums, uint32_t blk)
 {
     __shared__ uint32_t wsum[kSelBlock / kWave];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t cnt = 0;
     for (int it = 0; it < kSelItems; ++it) {
-        const uint32_t m = blockIdx.x * kSelPerBlock + it * kSelBlock + threadIdx.x;
+        const uint32_t m = blk * kSelPerBlock + it * kSelBlock + threadIdx.x;
         const bool sel = m < total && coarse_selected(d2, m, logn, K);
         cnt += (uint32_t)__popcll(__ballot(sel));
     }
@@ -53,14 +53,20 @@ __global__ void __launch_bounds__(kSelBlock) select_count(const int32_t *__restr
     if (threadIdx.x == 0) {
         uint32_t s = 0;
         for (int w = 0; w < kSelBlock / kWave; ++w) s += wsum[w];
-        block_sums[blockIdx.x] = s;
+        block_sums[blk] = s;
     }
+}
+
+__global__ void __launch_bounds__(kSelBlock) select_count(const int32_t *__restrict__ d2, int logn, int K,
+                                                          uint32_t total, uint32_t *__restrict__ block_sums)
+{
+    select_count_body(d2, logn, K, total, block_sums, blockIdx.x);
 }
 
 // Exclusive scan of nblocks totals in one workgroup of 1024 lanes; also the
 // grand total -> count (texels = coarse * r3) and the overflow check.
-__global__ void __launch_bounds__(1024) select_scan(uint32_t *__restrict__ sums, uint32_t nblocks, uint32_t r3,
-                                                    int32_t *__restrict__ count, int32_t cap)
+__device__ __forceinline__ void select_scan_body(uint32_t *__restrict__ sums, uint32_t nblocks, uint32_t r3,
+                                                 int32_t *__restrict__ count, int32_t cap)
 {
     __shared__ uint32_t part[1024];
     const uint32_t t = threadIdx.x;
@@ -92,17 +98,22 @@ __global__ void __launch_bounds__(1024) select_scan(uint32_t *__restrict__ sums,
     }
 }
 
-__global__ void __launch_bounds__(kSelBlock) select_scatter(const int32_t *__restrict__ d2, int logn, int K,
-                                                            uint32_t total, const uint32_t *__restrict__ offsets,
-                                                            int logr, int nf, int32_t *__restrict__ queue,
-                                                            int32_t cap)
+__global__ void __launch_bounds__(1024) select_scan(uint32_t *__restrict__ sums, uint32_t nblocks, uint32_t r3,
+                                                    int32_t *__restrict__ count, int32_t cap)
+{
+    select_scan_body(sums, nblocks, r3, count, cap);
+}
+
+__device__ __forceinline__ void select_scatter_body(const int32_t *__restrict__ d2, int logn, int K, uint32_t total,
+                                                    const uint32_t *__restrict__ offsets, int logr, int nf,
+                                                    int32_t *__restrict__ queue, int32_t cap, uint32_t blk)
 {
     __shared__ uint32_t wsum[kSelItems][kSelBlock / kWave];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     bool sel[kSelItems];
     uint32_t rank[kSelItems];
     for (int it = 0; it < kSelItems; ++it) {
-        const uint32_t m = blockIdx.x * kSelPerBlock + it * kSelBlock + threadIdx.x;
+        const uint32_t m = blk * kSelPerBlock + it * kSelBlock + threadIdx.x;
         sel[it] = m < total && coarse_selected(d2, m, logn, K);
         const uint64_t bal = __ballot(sel[it]);
         rank[it] = wave_prefix(bal);
@@ -110,12 +121,12 @@ __global__ void __launch_bounds__(kSelBlock) select_scatter(const int32_t *__res
     }
     __syncthreads();
     const uint32_t r3 = 1u << (3 * logr);
-    uint32_t base = offsets[blockIdx.x];
+    uint32_t base = offsets[blk];
     for (int it = 0; it < kSelItems; ++it) {
         uint32_t before = 0;
         for (int w = 0; w < wave; ++w) before += wsum[it][w];
         if (sel[it]) {
-            const uint32_t m = blockIdx.x * kSelPerBlock + it * kSelBlock + threadIdx.x;
+            const uint32_t m = blk * kSelPerBlock + it * kSelBlock + threadIdx.x;
             const uint64_t pos = ((uint64_t)(base + before + rank[it])) * r3;
             const uint32_t cx = compact1by2(m), cy = compact1by2(m >> 1), cz = compact1by2(m >> 2);
             for (uint32_t c = 0; c < r3; ++c) {
@@ -129,10 +140,17 @@ __global__ void __launch_bounds__(kSelBlock) select_scatter(const int32_t *__res
     }
 }
 
-__global__ void __launch_bounds__(256) select_mask(const int32_t *__restrict__ d2, int logn, int logr, int nf, int K,
-                                                   int64_t nquads, uint32_t *__restrict__ mask4)
+__global__ void __launch_bounds__(kSelBlock) select_scatter(const int32_t *__restrict__ d2, int logn, int K,
+                                                            uint32_t total, const uint32_t *__restrict__ offsets,
+                                                            int logr, int nf, int32_t *__restrict__ queue,
+                                                            int32_t cap)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    select_scatter_body(d2, logn, K, total, offsets, logr, nf, queue, cap, blockIdx.x);
+}
+
+__device__ __forceinline__ void select_mask_body(const int32_t *__restrict__ d2, int logn, int logr, int nf, int K,
+                                                 int64_t nquads, uint32_t *__restrict__ mask4, int64_t q)
+{
     if (q >= nquads) return;
     const int64_t j = q * 4;
     const int x = (int)(j % nf), y = (int)((j / nf) % nf), z = (int)(j / ((int64_t)nf * nf));
@@ -141,6 +159,21 @@ __global__ void __launch_bounds__(256) select_mask(const int32_t *__restrict__ d
     uint32_t w = 0;
     for (int i = 0; i < 4; ++i) w |= (uint32_t)(d2[row + ((x + i) >> logr)] <= K) << (8 * i);
     mask4[q] = w;
+}
+
+__global__ void __launch_bounds__(256) select_mask(const int32_t *__restrict__ d2, int logn, int logr, int nf, int K,
+                                                   int64_t nquads, uint32_t *__restrict__ mask4)
+{
+    select_mask_body(d2, logn, logr, nf, K, nquads, mask4, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// K = floor(((d + beta) / h_c)^2), -1 if d + beta < 0
+inline int select_threshold(float hc, float beta, float d)
+{
+    const double q = ((double)d + (double)beta) / (double)hc;
+    if (q < 0) return -1;
+    const double k = floor(q * q);
+    return k > (double)INT32_MAX ? INT32_MAX : (int)k;
 }
 
 }  // namespace rtsdf
@@ -166,13 +199,7 @@ extern "C" int rtsdf_select(rtsdf_grid coarse, const int32_t *dist2, rtsdf_grid 
     if (!(beta == beta) || !(d == d)) return RTSDF_EINVAL;
     hipStream_t s = as_stream(stream);
     const int logn = ilog2(coarse.n), logr = ilog2(fine.n / coarse.n);
-    const double q = ((double)d + (double)beta) / (double)coarse.h;
-    int K;
-    if (q < 0) K = -1;
-    else {
-        const double k = floor(q * q);
-        K = k > (double)INT32_MAX ? INT32_MAX : (int)k;
-    }
+    const int K = select_threshold(coarse.h, beta, d);
     const uint32_t total = (uint32_t)((int64_t)coarse.n * coarse.n * coarse.n);
     const uint32_t nblocks = (total + kSelPerBlock - 1) / kSelPerBlock;
     uint32_t *sums = static_cast<uint32_t *>(workspace);

@@ -232,20 +232,17 @@ __device__ __forceinline__ void trav_step(const BvhView &S, const RaySetup &R, i
 
 // ------------------------------------------------------ persistent tracer ----
 
-struct TraceArgs {
+// Everything the tracer needs to know about one scene.
+struct TraceScene {
     BvhView bvh;
     int nt;
     const int32_t *queue;
     const int32_t *count;
     int32_t queue_cap;
-    int32_t *cursor;
     const float *coarse_sdf;
     int nc, logr, nf, lognf;
     float lox, loy, loz, hf;
     int rays;
-    uint32_t frame;
-    const uint32_t *frame_ptr;
-    uint64_t seed;
     uint32_t scene_id;
     float alpha;
     float *u;
@@ -253,12 +250,27 @@ struct TraceArgs {
     int32_t *arg_tri;
     int32_t *arg_ray;
     float *fine;
-    int32_t *spill;       // deep stack entries: [(depth - SL) * spill_stride + lane]
-    int64_t spill_stride; // lanes in the launch
-    int bin_directions;   // sort each tile's rays by direction bin
+};
+
+struct TraceArgs {
+    TraceScene one;              // the scene of a single-scene launch
+    const TraceScene *scenes;    // batched launch: per-scene records ...
+    const int32_t *tile_offset;  // ... and the first global tile of each scene ([nscenes + 1])
+    int nscenes;
+    int32_t *cursor;             // global tile counter
+    uint32_t frame;
+    const uint32_t *frame_ptr;
+    uint64_t seed;
+    int32_t *spill;              // deep stack entries: [(depth - SL) * spill_stride + lane]
+    int spill_stride;            // lanes in the launch
+    int bin_directions;          // sort each tile's rays by direction bin
 };
 
 constexpr int kTraceWaves = 4;
+constexpr int kTileRays = 768;  // rays per wavefront tile
+constexpr int kTileTexels = 64;
+
+__host__ __device__ __forceinline__ int tile_texels_for(int rays) { return rays >= kTileRays ? 1 : min(kTileTexels, kTileRays / rays); }
 
 typedef __attribute__((address_space(3))) int lds_int;
 
@@ -273,32 +285,32 @@ __device__ __forceinline__ const float4 *tri_ptr(const float4 *base, int tri)
 }
 
 template <int SL>
-__device__ __forceinline__ void stack_push(const TraceArgs &A, int &sp, lds_int *stk, int32_t *spill, int v)
+__device__ __forceinline__ void stack_push(int stride, int &sp, lds_int *stk, int32_t *spill, int v)
 {
     if (sp < SL) stk[sp * kWave] = v;
-    else spill[(sp - SL) * (int)A.spill_stride] = v;
+    else spill[(sp - SL) * stride] = v;
     ++sp;
 }
 
 template <int SL>
-__device__ __forceinline__ int stack_pop(const TraceArgs &A, int &sp, const lds_int *stk, const int32_t *spill)
+__device__ __forceinline__ int stack_pop(int stride, int &sp, const lds_int *stk, const int32_t *spill)
 {
     if (sp == 0) return kDone;
     --sp;
     int v;
     if (sp < SL) v = stk[sp * kWave];
-    else v = spill[(sp - SL) * (int)A.spill_stride];
+    else v = spill[(sp - SL) * stride];
     return v;
 }
 
 // One internal node: test both children's boxes, descend into the nearer hit
 // child and push the farther one; pop when neither is hit.
 template <int SL, bool STATS>
-__device__ __forceinline__ void inner_step(const TraceArgs &A, const RaySetup &R, int &node, int &sp, lds_int *stk,
-                                           int32_t *spill, float tbest, uint32_t &st_nodes)
+__device__ __forceinline__ void inner_step(const BvhView &S, int stride, const RaySetup &R, int &node, int &sp,
+                                           lds_int *stk, int32_t *spill, float tbest, uint32_t &st_nodes)
 {
     if (STATS) ++st_nodes;
-    const BvhNode *nd = node_ptr(A.bvh.nodes, node);
+    const BvhNode *nd = node_ptr(S.nodes, node);
     const float4 a = nd->xy0, b = nd->xy1, z = nd->z01;
     const int4 m = nd->meta;
     const float t0 = box_entry(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest);
@@ -306,23 +318,24 @@ __device__ __forceinline__ void inner_step(const TraceArgs &A, const RaySetup &R
     const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
     if (h0 && h1) {
         const bool first0 = t0 <= t1;
-        stack_push<SL>(A, sp, stk, spill, first0 ? m.y : m.x);
+        stack_push<SL>(stride, sp, stk, spill, first0 ? m.y : m.x);
         node = first0 ? m.x : m.y;
     } else if (h0 || h1) {
         node = h0 ? m.x : m.y;
     } else {
-        node = stack_pop<SL>(A, sp, stk, spill);
+        node = stack_pop<SL>(stride, sp, stk, spill);
     }
 }
 
 // Same, but a leaf child is opened at once (its triangle range becomes the
 // lane's current work) instead of costing an iteration of its own.
 template <int SL, bool STATS>
-__device__ __forceinline__ void node_step(const TraceArgs &A, const RaySetup &R, int &node, int &sp, lds_int *stk,
-                                          int32_t *spill, float tbest, int &tri_cur, int &tri_end, uint32_t &st_nodes)
+__device__ __forceinline__ void node_step(const BvhView &S, int stride, const RaySetup &R, int &node, int &sp,
+                                          lds_int *stk, int32_t *spill, float tbest, int &tri_cur, int &tri_end,
+                                          uint32_t &st_nodes)
 {
     if (STATS) ++st_nodes;
-    const BvhNode *nd = node_ptr(A.bvh.nodes, node);
+    const BvhNode *nd = node_ptr(S.nodes, node);
     const float4 a = nd->xy0, b = nd->xy1, z = nd->z01;
     const int4 m = nd->meta;
     const float t0 = box_entry(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest);
@@ -336,7 +349,7 @@ __device__ __forceinline__ void node_step(const TraceArgs &A, const RaySetup &R,
             tri_end = tri_cur + leaf_count(near);
             node = far;
         } else {
-            stack_push<SL>(A, sp, stk, spill, far);
+            stack_push<SL>(stride, sp, stk, spill, far);
             node = near;
         }
     } else if (h0 || h1) {
@@ -344,12 +357,12 @@ __device__ __forceinline__ void node_step(const TraceArgs &A, const RaySetup &R,
         if (c < 0) {
             tri_cur = leaf_first(c);
             tri_end = tri_cur + leaf_count(c);
-            node = stack_pop<SL>(A, sp, stk, spill);
+            node = stack_pop<SL>(stride, sp, stk, spill);
         } else {
             node = c;
         }
     } else {
-        node = stack_pop<SL>(A, sp, stk, spill);
+        node = stack_pop<SL>(stride, sp, stk, spill);
     }
 }
 
@@ -368,12 +381,8 @@ __device__ __forceinline__ int direction_bin(float3 d)
     }
     const int bu = min(7, max(0, (int)((u + 1.0f) * 4.0f)));
     const int bv = min(7, max(0, (int)((v + 1.0f) * 4.0f)));
-    return (int)((bu & 1) | ((bv & 1) << 1) | ((bu & 2) << 1) | ((bv & 2) << 2) |
-                                          ((bu & 4) << 2) | ((bv & 4) << 3));
+    return (bu & 1) | ((bv & 1) << 1) | ((bu & 2) << 1) | ((bv & 2) << 2) | ((bu & 4) << 2) | ((bv & 4) << 3);
 }
-
-constexpr int kTileRays = 768;  // rays per wavefront tile
-constexpr int kTileTexels = 64;
 
 struct WaveTile {
     int32_t tex[kTileTexels];
@@ -384,22 +393,46 @@ struct WaveTile {
     uint8_t binof[kTileRays];             // direction bin of each ray
 };
 
+// Tiles of a scene: ceil(min(count, cap) / tile texels).
+__device__ __forceinline__ int scene_tiles(const TraceScene &P)
+{
+    const int total = min(*P.count, P.queue_cap);
+    const int tt = tile_texels_for(P.rays);
+    return total > 0 ? (total + tt - 1) / tt : 0;
+}
+
+// Global tile prefix of a batch: tile_offset[s] = sum of tiles of scenes < s.
+__global__ void trace_tile_prefix(const TraceScene *scenes, int n, int32_t *tile_offset)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int acc = 0;
+    for (int s = 0; s < n; ++s) {
+        tile_offset[s] = acc;
+        acc += scene_tiles(scenes[s]);
+    }
+    tile_offset[n] = acc;
+}
+
 // Persistent tracer.  Each wavefront repeatedly takes a tile of up to 64
-// consecutive queue texels (Morton order: a compact block of the fine grid),
-// draws all their rays' directions, sorts the rays by direction bin in LDS, and
-// traces them in that order, so the lanes of a wavefront follow rays that
-// start close together and point the same way.  Results are folded per texel
-// with LDS atomics (a 64-bit min keeps the smallest distance, ties to the
-// lowest ray index, together with its triangle; an add counts front and back
-// hits), which makes them independent of the order rays complete in.  The
-// traversal itself runs in two phases per iteration (after Aila and Laine's
-// "while-while" loop with postponed leaves): every lane walks internal nodes
-// until it holds a leaf (a lane that already holds one keeps walking and
-// stops at its second), then all held leaves are tested together.
-// Instrumented runs (STATS) also count node visits, triangle tests and rays
-// into 64-bit counters at workspace offsets 8, 16 and 24.
-template <int SL, int REFILL, int LOOP, bool STATS>
-__global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_waves_per_eu(6, 8))) trace_persistent(TraceArgs A)
+// consecutive queue texels of one scene (Morton order: a compact block of the
+// fine grid), draws all their rays' directions, sorts the rays by direction
+// bin in LDS, and traces them in that order, so the lanes of a wavefront
+// follow rays that start close together and point the same way.  Results are
+// folded per texel with LDS atomics (a 64-bit min keeps the smallest distance,
+// ties to the lowest ray index, together with its triangle; an add counts
+// front and back hits), which makes them independent of the order rays
+// complete in.  Two traversal loop shapes (LOOP): 0 = phases per iteration
+// (after Aila and Laine's "while-while" loop with postponed leaves: every lane
+// walks internal nodes until it holds a leaf, then all held leaves are
+// tested); 1 = one unit of work per lane per iteration (a triangle of the
+// current leaf, else a node, else opening a popped leaf), which keeps more
+// lanes busy on wave64.  BATCHED launches serve many scenes: a global tile
+// index is mapped to its scene through the tile prefix.  Instrumented runs
+// (STATS) also count node visits, triangle tests and rays into 64-bit counters
+// at workspace offsets 8, 16 and 24.
+template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED>
+__global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_waves_per_eu(6, 8)))
+trace_persistent(TraceArgs A)
 {
     uint32_t st_nodes = 0, st_tris = 0, st_rays = 0;
     __shared__ int stack_mem[kTraceWaves * SL * kWave];
@@ -408,23 +441,38 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_wav
     lds_int *stk = (lds_int *)(stack_mem + wave * SL * kWave + lane);
     WaveTile &T = tiles[wave];
     int32_t *spill = A.spill + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = A.spill_stride;
     const uint32_t frame = A.frame_ptr ? *A.frame_ptr : A.frame;
-    const int total = min(*A.count, A.queue_cap);
-    const int nfm = A.nf - 1;
-    const int R = A.rays;
-    const int tile_texels = min(kTileTexels, kTileRays / R);
-    const uint64_t ntex_grid = (uint64_t)1 << (3 * A.lognf);
+    const int single_tiles = BATCHED ? 0 : scene_tiles(A.one);
+    const int all_tiles = BATCHED ? A.tile_offset[A.nscenes] : single_tiles;
 
     while (true) {
-        // ---- take a tile of texels
-        int base = 0;
-        if (lane == 0) base = atomicAdd(A.cursor, tile_texels);
-        base = __shfl(base, 0);
-        if (base >= total) break;
+        // ---- take a tile
+        int g = 0;
+        if (lane == 0) g = atomicAdd(A.cursor, 1);
+        g = __shfl(g, 0);
+        if (g >= all_tiles) break;
+        int s = 0;
+        if (BATCHED) {  // last scene whose first tile is <= g
+            int lo = 0, hi = A.nscenes - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (A.tile_offset[mid] <= g) lo = mid;
+                else hi = mid - 1;
+            }
+            s = __builtin_amdgcn_readfirstlane(lo);
+        }
+        const TraceScene &P = BATCHED ? A.scenes[s] : A.one;
+        const int R = P.rays;
+        const int nfm = P.nf - 1;
+        const int tile_texels = tile_texels_for(R);
+        const int total = min(*P.count, P.queue_cap);
+        const int base = (g - (BATCHED ? A.tile_offset[s] : 0)) * tile_texels;
         const int nt = min(tile_texels, total - base);
         const int nrays = nt * R;
+        const uint64_t ntex_grid = (uint64_t)1 << (3 * P.lognf);
         if (lane < nt) {
-            int j = A.queue[base + lane];
+            int j = P.queue[base + lane];
             if (j < 0 || (uint64_t)j >= ntex_grid) j = -1;
             T.tex[lane] = j;
             T.key[lane] = ~0ull;
@@ -433,14 +481,14 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_wav
         T.bin[lane] = 0u;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        // ---- bin the tile's rays by direction (16 rays per lane)
+        // ---- bin the tile's rays by direction
 #pragma unroll 1
         for (int q = lane; q < nrays; q += kWave) {
             const int slot = q / R, r = q - slot * R;
             const int j = T.tex[slot];
             int b = 0;
             if (j >= 0 && A.bin_directions)
-                b = direction_bin(sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, A.scene_id));
+                b = direction_bin(sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, P.scene_id));
             T.binof[q] = (uint8_t)b;
             atomicAdd(&T.bin[b], 1u);
         }
@@ -467,9 +515,11 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_wav
         __builtin_amdgcn_wave_barrier();
 
         // ---- trace the tile's rays in bin order
+        const BvhView S = P.bvh;
+        const int scene_nt = P.nt;
         int pool = 0;
         bool busy = false;
-        int q = 0, slot = 0, r = 0;
+        int slot = 0, r = 0;
         RaySetup Rs;
         float tbest = __builtin_inff();
         int ibest = -1, node = kDone, leaf = kDone, sp = 0;
@@ -482,17 +532,17 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_wav
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
                 const int take = min(__popcll(need), nrays - pool);
                 if (!busy && rank < take) {
-                    q = T.perm[pool + rank];
+                    const int q = T.perm[pool + rank];
                     slot = q / R;
                     r = q - slot * R;
                     const int j = T.tex[slot];
                     if (j >= 0) {
-                        const float ox = texel_coord(A.lox, j & nfm, A.hf);
-                        const float oy = texel_coord(A.loy, (j >> A.lognf) & nfm, A.hf);
-                        const float oz = texel_coord(A.loz, j >> (2 * A.lognf), A.hf);
-                        const float3 d = sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, A.scene_id);
+                        const float ox = texel_coord(P.lox, j & nfm, P.hf);
+                        const float oy = texel_coord(P.loy, (j >> P.lognf) & nfm, P.hf);
+                        const float oz = texel_coord(P.loz, j >> (2 * P.lognf), P.hf);
+                        const float3 d = sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, P.scene_id);
                         ray_setup(ox, oy, oz, d.x, d.y, d.z, Rs);
-                        node = A.nt > 0 ? 0 : kDone;
+                        node = scene_nt > 0 ? 0 : kDone;
                     } else {
                         node = kDone;
                     }
@@ -512,15 +562,15 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_wav
                 while (true) {
                     if (busy && leaf == kDone && node < 0 && node != kDone) {
                         leaf = node;
-                        node = stack_pop<SL>(A, sp, stk, spill);
+                        node = stack_pop<SL>(stride, sp, stk, spill);
                     }
                     // phase 1: internal nodes until every busy lane holds a leaf or is done
                     while (__ballot(busy && node >= 0 && leaf == kDone)) {
                         if (busy && node >= 0) {
-                            inner_step<SL, STATS>(A, Rs, node, sp, stk, spill, tbest, st_nodes);
+                            inner_step<SL, STATS>(S, stride, Rs, node, sp, stk, spill, tbest, st_nodes);
                             if (node < 0 && node != kDone && leaf == kDone) {
                                 leaf = node;
-                                node = stack_pop<SL>(A, sp, stk, spill);
+                                node = stack_pop<SL>(stride, sp, stk, spill);
                             }
                         }
                     }
@@ -528,30 +578,30 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_wav
                     if (busy && leaf != kDone) {
                         const int first = leaf_first(leaf), cnt = leaf_count(leaf);
                         if (STATS) st_tris += (uint32_t)cnt;
-                        for (int i = first; i < first + cnt; ++i)
-                            tri_test(Rs, A.bvh.tris[3 * i], A.bvh.tris[3 * i + 1], A.bvh.tris[3 * i + 2], tbest,
-                                     ibest, front);
+                        for (int i = first; i < first + cnt; ++i) {
+                            const float4 *tp = tri_ptr(S.tris, i);
+                            tri_test(Rs, tp[0], tp[1], tp[2], tbest, ibest, front);
+                        }
                         leaf = kDone;
                     }
                     const uint64_t done = __ballot(!busy || (node == kDone && leaf == kDone));
                     if (__popcll(done) >= refill_at) break;
                 }
             } else {
-                // one unit of work per lane per iteration: a triangle of the
-                // current leaf, else one internal node, else open the next leaf
                 while (true) {
                     if (busy) {
                         if (tri_cur < tri_end) {
                             if (STATS) ++st_tris;
-                            const float4 *tp = tri_ptr(A.bvh.tris, tri_cur);
+                            const float4 *tp = tri_ptr(S.tris, tri_cur);
                             tri_test(Rs, tp[0], tp[1], tp[2], tbest, ibest, front);
                             ++tri_cur;
                         } else if (node >= 0) {
-                            node_step<SL, STATS>(A, Rs, node, sp, stk, spill, tbest, tri_cur, tri_end, st_nodes);
+                            node_step<SL, STATS>(S, stride, Rs, node, sp, stk, spill, tbest, tri_cur, tri_end,
+                                                 st_nodes);
                         } else if (node != kDone) {
                             tri_cur = leaf_first(node);
                             tri_end = tri_cur + leaf_count(node);
-                            node = stack_pop<SL>(A, sp, stk, spill);
+                            node = stack_pop<SL>(stride, sp, stk, spill);
                         }
                     }
                     const uint64_t done = __ballot(!busy || (node == kDone && tri_cur >= tri_end));
@@ -580,30 +630,30 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_wav
             const uint32_t fc = T.cnt[lane];
             const float rmin = key == ~0ull ? __builtin_inff() : __uint_as_float((uint32_t)(key >> 32));
             const int argray = (int)((key >> 26) & 63u), argtri = (int)(key & ((1u << 26) - 1u));
-            const int x = j & nfm, y = (j >> A.lognf) & nfm, z = j >> (2 * A.lognf);
-            const float c = A.coarse_sdf[(x >> A.logr) + A.nc * ((y >> A.logr) + A.nc * (z >> A.logr))];
-            const float uprev = A.u[j];
-            const uint32_t h = A.hits[j];
+            const int x = j & nfm, y = (j >> P.lognf) & nfm, z = j >> (2 * P.lognf);
+            const float c = P.coarse_sdf[(x >> P.logr) + P.nc * ((y >> P.logr) + P.nc * (z >> P.logr))];
+            const float uprev = P.u[j];
+            const uint32_t h = P.hits[j];
             const uint32_t F = min((h & 0xFFFFu) + (fc & 0xFFFFu), 0xFFFFu);
             const uint32_t B = min((h >> 16) + (fc >> 16), 0xFFFFu);
             float uu;
-            if (A.alpha == 1.0f) {
+            if (P.alpha == 1.0f) {
                 uu = uprev;
             } else {
-                uu = A.alpha * uprev + (1.0f - A.alpha) * fmaxf(c, 0.0f);
+                uu = P.alpha * uprev + (1.0f - P.alpha) * fmaxf(c, 0.0f);
             }
             if (rmin < uu) {
                 uu = rmin;
-                A.arg_tri[j] = argtri;
-                A.arg_ray[j] = (int32_t)((frame << 8) | (uint32_t)argray);
-            } else if (A.alpha != 1.0f) {
-                A.arg_tri[j] = -1;
-                A.arg_ray[j] = -1;
+                P.arg_tri[j] = argtri;
+                P.arg_ray[j] = (int32_t)((frame << 8) | (uint32_t)argray);
+            } else if (P.alpha != 1.0f) {
+                P.arg_tri[j] = -1;
+                P.arg_ray[j] = -1;
             }
-            A.u[j] = uu;
-            A.hits[j] = F | (B << 16);
+            P.u[j] = uu;
+            P.hits[j] = F | (B << 16);
             const float f = isinf(uu) ? c : uu;
-            A.fine[j] = B > F ? -f : f;
+            P.fine[j] = B > F ? -f : f;
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -617,13 +667,12 @@ __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_wav
 }
 
 // Unselected texels: fine = coarse value, state reset (Eq. (1), case c > d).
-__global__ void __launch_bounds__(256) trace_fill_unselected(const uint8_t *__restrict__ mask,
-                                                             const float *__restrict__ coarse_sdf, int nc, int logr,
-                                                             int lognf, int64_t ntex, float *__restrict__ u,
-                                                             uint32_t *__restrict__ hits, int32_t *__restrict__ arg_tri,
-                                                             int32_t *__restrict__ arg_ray, float *__restrict__ fine)
+__device__ __forceinline__ void fill_unselected_body(const uint8_t *__restrict__ mask,
+                                                     const float *__restrict__ coarse_sdf, int nc, int logr, int lognf,
+                                                     int64_t ntex, float *__restrict__ u, uint32_t *__restrict__ hits,
+                                                     int32_t *__restrict__ arg_tri, int32_t *__restrict__ arg_ray,
+                                                     float *__restrict__ fine, int64_t j)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= ntex || mask[j]) return;
     const int nfm = (1 << lognf) - 1;
     const int x = (int)(j & nfm), y = (int)((j >> lognf) & nfm), z = (int)(j >> (2 * lognf));
@@ -634,6 +683,16 @@ __global__ void __launch_bounds__(256) trace_fill_unselected(const uint8_t *__re
         arg_tri[j] = -1;
         arg_ray[j] = -1;
     }
+}
+
+__global__ void __launch_bounds__(256) trace_fill_unselected(const uint8_t *__restrict__ mask,
+                                                             const float *__restrict__ coarse_sdf, int nc, int logr,
+                                                             int lognf, int64_t ntex, float *__restrict__ u,
+                                                             uint32_t *__restrict__ hits, int32_t *__restrict__ arg_tri,
+                                                             int32_t *__restrict__ arg_ray, float *__restrict__ fine)
+{
+    fill_unselected_body(mask, coarse_sdf, nc, logr, lognf, ntex, u, hits, arg_tri, arg_ray, fine,
+                         (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) accum_reset_kernel(int64_t n, float *u, uint32_t *hits, int32_t *at, int32_t *ar)
@@ -737,48 +796,50 @@ static rtsdf_trace_tuning g_tuning = {16, 0, 0, 1, 1, 12};
 constexpr int kMaxBlocksPerCu = 8;  // persistent workgroups per CU (spill area sized for this)
 constexpr int kMinShortStack = 12;  // smallest LDS stack part (spill area sized for this)
 
-template <int SL, int REFILL, int LOOP, bool STATS>
-static int launch_trace4(TraceArgs A, hipStream_t s)
+template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED>
+static int launch_trace5(TraceArgs A, hipStream_t s)
 {
     int per_cu = g_tuning.blocks_per_cu;
     if (per_cu <= 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent<SL, REFILL, LOOP, STATS>,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent<SL, REFILL, LOOP, STATS, BATCHED>,
                                                          kTraceWaves * kWave, 0) != hipSuccess ||
             per_cu <= 0)
             per_cu = 2;
     }
     per_cu = std::min(per_cu, kMaxBlocksPerCu);
     const int blocks = num_cus() * per_cu;
-    A.spill_stride = (int64_t)blocks * kTraceWaves * kWave;
-    trace_persistent<SL, REFILL, LOOP, STATS><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
+    A.spill_stride = blocks * kTraceWaves * kWave;
+    trace_persistent<SL, REFILL, LOOP, STATS, BATCHED><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
     RTSDF_CHECK_LAUNCH();
     return RTSDF_OK;
 }
 
-template <int SL, int REFILL, int LOOP>
+template <int SL, int REFILL, int LOOP, bool BATCHED>
+static int launch_trace4(const TraceArgs &A, hipStream_t s)
+{
+    return g_tuning.stats ? launch_trace5<SL, REFILL, LOOP, true, BATCHED>(A, s)
+                          : launch_trace5<SL, REFILL, LOOP, false, BATCHED>(A, s);
+}
+
+template <int SL, int REFILL, bool BATCHED>
 static int launch_trace3(const TraceArgs &A, hipStream_t s)
 {
-    return g_tuning.stats ? launch_trace4<SL, REFILL, LOOP, true>(A, s) : launch_trace4<SL, REFILL, LOOP, false>(A, s);
+    return g_tuning.loop ? launch_trace4<SL, REFILL, 1, BATCHED>(A, s) : launch_trace4<SL, REFILL, 0, BATCHED>(A, s);
 }
 
-template <int SL, int REFILL>
+template <int SL, bool BATCHED>
 static int launch_trace2(const TraceArgs &A, hipStream_t s)
 {
-    return g_tuning.loop ? launch_trace3<SL, REFILL, 1>(A, s) : launch_trace3<SL, REFILL, 0>(A, s);
+    return g_tuning.refill == 8 ? launch_trace3<SL, 8, BATCHED>(A, s) : launch_trace3<SL, 16, BATCHED>(A, s);
 }
 
-template <int SL>
-static int launch_trace1(const TraceArgs &A, hipStream_t s)
-{
-    return g_tuning.refill == 8 ? launch_trace2<SL, 8>(A, s) : launch_trace2<SL, 16>(A, s);
-}
-
+template <bool BATCHED>
 static int launch_trace(const TraceArgs &A, hipStream_t s)
 {
     switch (g_tuning.stack_lds) {
-    case 12: return launch_trace1<12>(A, s);
-    case 24: return launch_trace1<24>(A, s);
-    default: return launch_trace1<16>(A, s);
+    case 12: return launch_trace2<12, BATCHED>(A, s);
+    case 24: return launch_trace2<24, BATCHED>(A, s);
+    default: return launch_trace2<16, BATCHED>(A, s);
     }
 }
 
@@ -863,38 +924,42 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     int32_t *cursor = static_cast<int32_t *>(workspace);
     int rc = launch_fill<int32_t>(cursor, 0, g_tuning.stats ? 8 : 1, s);
     if (rc != RTSDF_OK) return rc;
-    TraceArgs A;
-    A.bvh.nodes = scene->nodes;
-    A.bvh.tris = scene->tris;
-    A.nt = scene->nt;
-    A.queue = queue;
-    A.count = count;
-    A.queue_cap = queue_cap;
+    TraceArgs A{};
+    TraceScene &P = A.one;
+    P.bvh.nodes = scene->nodes;
+    P.bvh.tris = scene->tris;
+    P.nt = scene->nt;
+    P.queue = queue;
+    P.count = count;
+    P.queue_cap = queue_cap;
+    P.coarse_sdf = coarse_sdf;
+    P.nc = coarse.n;
+    P.logr = logr;
+    P.nf = fine.n;
+    P.lognf = lognf;
+    P.lox = fine.lo[0];
+    P.loy = fine.lo[1];
+    P.loz = fine.lo[2];
+    P.hf = fine.h;
+    P.rays = rays_per_texel;
+    P.scene_id = scene_id;
+    P.alpha = alpha;
+    P.u = st.u;
+    P.hits = st.hits;
+    P.arg_tri = st.arg_tri;
+    P.arg_ray = st.arg_ray;
+    P.fine = fine_sdf;
+    A.scenes = nullptr;
+    A.tile_offset = nullptr;
+    A.nscenes = 1;
     A.cursor = cursor;
-    A.coarse_sdf = coarse_sdf;
-    A.nc = coarse.n;
-    A.logr = logr;
-    A.nf = fine.n;
-    A.lognf = lognf;
-    A.lox = fine.lo[0];
-    A.loy = fine.lo[1];
-    A.loz = fine.lo[2];
-    A.hf = fine.h;
-    A.rays = rays_per_texel;
     A.frame = frame;
     A.frame_ptr = frame_ptr;
     A.seed = seed;
-    A.scene_id = scene_id;
-    A.alpha = alpha;
-    A.u = st.u;
-    A.hits = st.hits;
-    A.arg_tri = st.arg_tri;
-    A.arg_ray = st.arg_ray;
-    A.fine = fine_sdf;
     A.spill = scene->spill;
     A.spill_stride = 0;
     A.bin_directions = g_tuning.bin_directions;
-    return launch_trace(A, s);
+    return launch_trace<false>(A, s);
 }
 
 extern "C" int rtsdf_directions(const int32_t *texel, const uint32_t *frame, const int32_t *ray, int32_t n,

@@ -109,41 +109,39 @@ __device__ __forceinline__ void vox_column(const VoxTri &T, int i, int j, int n,
     seeds[idx] = idx;
 }
 
-__global__ void __launch_bounds__(256) voxelize_kernel(const float *__restrict__ v, int nv,
-                                                       const int32_t *__restrict__ f, int nt, rtsdf_grid g,
-                                                       int32_t *__restrict__ seeds)
+// Lane part of one (triangle, axis) item: snap, set up, rasterize a small
+// projection directly; returns true when the projection is large and left to
+// the whole wavefront.
+__device__ __forceinline__ bool vox_item(const float *__restrict__ v, int nv, const int32_t *__restrict__ f, int t,
+                                         int axis, const rtsdf_grid &g, int32_t *__restrict__ seeds, VoxTri &T)
 {
-    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int n = g.n;
-    VoxTri T;
-    bool big = false;
-    if (item < 3 * (int64_t)nt) {
-        const int t = (int)(item / 3), axis = (int)(item % 3);
-        int vid[3] = {f[3 * t], f[3 * t + 1], f[3 * t + 2]};
-        bool ok = true;
-        for (int k = 0; k < 3; ++k)
-            if (vid[k] < 0 || vid[k] >= nv) ok = false;
-        if (!ok) {
+    int vid[3] = {f[3 * t], f[3 * t + 1], f[3 * t + 2]};
+    for (int k = 0; k < 3; ++k)
+        if (vid[k] < 0 || vid[k] >= nv) {
             if (axis == 0) raise_error(RTSDF_ERR_FACE_INDEX);
-        } else {
-            int64_t X[3][3];
-            for (int k = 0; k < 3; ++k)
-                if (!snap(v, vid[k], g, X[k])) ok = false;
-            if (!ok) {
-                if (axis == 0) raise_error(RTSDF_ERR_VERTEX_RANGE);
-            } else if (vox_setup(X, axis, n, T)) {
-                const int npix = (T.i1 - T.i0 + 1) * (T.j1 - T.j0 + 1);
-                if (npix <= kSmallPixels) {
-                    for (int j = T.j0; j <= T.j1; ++j)
-                        for (int i = T.i0; i <= T.i1; ++i) vox_column(T, i, j, n, seeds);
-                } else {
-                    big = true;
-                }
-            }
+            return false;
         }
+    int64_t X[3][3];
+    for (int k = 0; k < 3; ++k)
+        if (!snap(v, vid[k], g, X[k])) {
+            if (axis == 0) raise_error(RTSDF_ERR_VERTEX_RANGE);
+            return false;
+        }
+    if (!vox_setup(X, axis, g.n, T)) return false;
+    const int npix = (T.i1 - T.i0 + 1) * (T.j1 - T.j0 + 1);
+    if (npix <= kSmallPixels) {
+        for (int j = T.j0; j <= T.j1; ++j)
+            for (int i = T.i0; i <= T.i1; ++i) vox_column(T, i, j, g.n, seeds);
+        return false;
     }
-    // Large projections: the whole wavefront rasterizes each in turn.
+    return true;
+}
+
+// Large projections of the wavefront's lanes, rasterized by all 64 lanes in
+// turn; `seeds` / `n` may differ per lane (many scenes per launch).
+__device__ __forceinline__ void vox_wave_big(bool big, const VoxTri &T, int32_t *seeds, int n)
+{
+    const int lane = threadIdx.x & (kWave - 1);
     uint64_t pending = __ballot(big);
     while (pending) {
         const int src = __ffsll((unsigned long long)pending) - 1;
@@ -160,10 +158,23 @@ __global__ void __launch_bounds__(256) voxelize_kernel(const float *__restrict__
         B.j0 = __shfl(T.j0, src);
         B.j1 = __shfl(T.j1, src);
         B.axis = __shfl(T.axis, src);
+        int32_t *bs = reinterpret_cast<int32_t *>(__shfl((long long)reinterpret_cast<intptr_t>(seeds), src));
+        const int bn = __shfl(n, src);
         const int w = B.i1 - B.i0 + 1;
         const int npix = w * (B.j1 - B.j0 + 1);
-        for (int p = lane; p < npix; p += kWave) vox_column(B, B.i0 + p % w, B.j0 + p / w, n, seeds);
+        for (int p = lane; p < npix; p += kWave) vox_column(B, B.i0 + p % w, B.j0 + p / w, bn, bs);
     }
+}
+
+__global__ void __launch_bounds__(256) voxelize_kernel(const float *__restrict__ v, int nv,
+                                                       const int32_t *__restrict__ f, int nt, rtsdf_grid g,
+                                                       int32_t *__restrict__ seeds)
+{
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    VoxTri T;
+    bool big = false;
+    if (item < 3 * (int64_t)nt) big = vox_item(v, nv, f, (int)(item / 3), (int)(item % 3), g, seeds, T);
+    vox_wave_big(big, T, seeds, g.n);
 }
 
 }  // namespace rtsdf

@@ -64,6 +64,25 @@ class Pipeline:
         self.select(stream)
         self.trace(frame, stream)
 
+    def make_graph(self, first_frame: int = 0, refit: bool = False) -> "R.FrameGraph":
+        """Capture one whole update as a HIP graph; each launch advances the frame index."""
+        self.frame_counter = torch.full((1,), int(first_frame), dtype=torch.int32, device=self.device)
+        D = R.FrameDesc()
+        D.vertices, D.nv = self.vertices.data_ptr(), self.vertices.shape[0]
+        D.faces, D.nt = self.faces.data_ptr(), self.faces.shape[0]
+        D.scene, D.refit = self.scene.handle, int(bool(refit))
+        D.coarse, D.fine = self.coarse, self.fine
+        D.beta, D.d, D.rays_per_texel = self.beta, self.d, self.rays
+        D.seed, D.scene_id, D.alpha = self.seed, self.scene_id, self.alpha
+        D.seeds, D.scratch, D.dist2 = self.seeds.data_ptr(), self.scratch.data_ptr(), self.dist2.data_ptr()
+        D.coarse_sdf, D.mask = self.coarse_sdf.data_ptr(), self.mask.data_ptr()
+        D.queue, D.queue_cap, D.count = self.queue.data_ptr(), self.queue.numel(), self.count.data_ptr()
+        D.select_workspace = self.sel_ws.data_ptr()
+        D.state = self.state.struct()
+        D.fine_sdf, D.trace_workspace = self.fine_sdf.data_ptr(), self.trace_ws.data_ptr()
+        D.frame_counter = self.frame_counter.data_ptr()
+        return R.FrameGraph(D, keepalive=(self,))
+
     def set_vertices(self, vertices: torch.Tensor, stream=None):
         """New positions for the same topology (animated scenes): refit the hierarchy."""
         self.vertices.copy_(vertices)

@@ -40,6 +40,26 @@ class Accum(C.Structure):
     _fields_ = [("u", _P), ("hits", _P), ("arg_tri", _P), ("arg_ray", _P)]
 
 
+class FrameDesc(C.Structure):
+    _fields_ = [("vertices", _P), ("nv", _i32), ("faces", _P), ("nt", _i32), ("scene", _P), ("refit", _i32),
+                ("coarse", Grid), ("fine", Grid), ("beta", _f32), ("d", _f32), ("rays_per_texel", _i32),
+                ("seed", _u64), ("scene_id", _u32), ("alpha", _f32), ("seeds", _P), ("scratch", _P),
+                ("dist2", _P), ("coarse_sdf", _P), ("mask", _P), ("queue", _P), ("queue_cap", _i32),
+                ("count", _P), ("select_workspace", _P), ("state", Accum), ("fine_sdf", _P),
+                ("trace_workspace", _P), ("frame_counter", _P)]
+
+
+class BatchScene(C.Structure):
+    _fields_ = [("vertices", _P), ("nv", _i32), ("faces", _P), ("nt", _i32), ("lo", C.c_float * 3), ("side", _f32),
+                ("coarse_n", _i32), ("fine_n", _i32), ("beta", _f32), ("d", _f32), ("rays_per_texel", _i32),
+                ("alpha", _f32), ("scene_id", _u32)]
+
+
+class BatchView(C.Structure):
+    _fields_ = [("coarse", Grid), ("fine", Grid), ("seeds", _P), ("dist2", _P), ("coarse_sdf", _P), ("mask", _P),
+                ("queue", _P), ("count", _P), ("state", Accum), ("fine_sdf", _P), ("scene", _P)]
+
+
 class TraceTuning(C.Structure):
     _fields_ = [("refill", _i32), ("blocks_per_cu", _i32), ("stats", _i32), ("loop", _i32),
                 ("bin_directions", _i32), ("stack_lds", _i32)]
@@ -70,6 +90,7 @@ def _load():
         "rtsdf_status_string": ([_i32], C.c_char_p),
         "rtsdf_version": ([], _i32),
         "rtsdf_sync_status": ([_P, C.POINTER(_u32)], _i32),
+        "rtsdf_copy": ([_P, _P, _sz, _P], _i32),
         "rtsdf_voxelize": ([_P, _i32, _P, _i32, Grid, _P, _P], _i32),
         "rtsdf_jfa": ([Grid, _P, _P, _f32, _P, _P, _P], _i32),
         "rtsdf_select_workspace_size": ([_i32], _sz),
@@ -88,6 +109,15 @@ def _load():
         "rtsdf_closest_hits": ([_P, _P, _P, _i32, _P, _P, _P, _P], _i32),
         "rtsdf_trace_backward": ([_P, Grid, Accum, _P, _P, _u64, _u32, _P, _P], _i32),
         "rtsdf_shadow": ([Grid, _P, _P, _i32, _P, _f32, _f32, _i32, _f32, _f32, _P, _P], _i32),
+        "rtsdf_frame_graph_create": ([C.POINTER(FrameDesc), C.POINTER(_P), _P], _i32),
+        "rtsdf_frame_graph_launch": ([_P, _P], _i32),
+        "rtsdf_frame_graph_destroy": ([_P], None),
+        "rtsdf_batch_create": ([C.POINTER(BatchScene), _i32, _u64, _i32, C.POINTER(_P), _P], _i32),
+        "rtsdf_batch_reset": ([_P, _P], _i32),
+        "rtsdf_batch_step": ([_P, _u32, _P, _P], _i32),
+        "rtsdf_batch_outputs": ([_P, _i32, C.POINTER(BatchView)], _i32),
+        "rtsdf_batch_graph_create": ([_P, _P, C.POINTER(_P), _P], _i32),
+        "rtsdf_batch_destroy": ([_P], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -276,3 +306,113 @@ def rtsdf_shadow(fine: Grid, fine_sdf, points, light_dir, k: float, eps: float, 
     _check("rtsdf_shadow", _lib.rtsdf_shadow(fine, _ptr(fine_sdf), _ptr(points), points.shape[0], ld, float(k),
                                              float(eps), int(max_steps), float(max_step), float(max_dist),
                                              _ptr(visibility), _stream(stream)))
+
+
+class FrameGraph:
+    """Owning handle of an ``rtsdf_frame_graph`` (one captured SDF update)."""
+
+    def __init__(self, desc: FrameDesc | None, keepalive=(), stream=None, handle=None):
+        self._desc = desc
+        self._keep = keepalive
+        if handle is not None:
+            self.handle = handle
+            return
+        h = _P()
+        _check("rtsdf_frame_graph_create", _lib.rtsdf_frame_graph_create(C.byref(desc), C.byref(h), _stream(stream)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check("rtsdf_frame_graph_launch", _lib.rtsdf_frame_graph_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.rtsdf_frame_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dev_view(ptr: int, n: int, dtype: torch.dtype, device) -> torch.Tensor:
+    """A copy (on the current stream) of n elements of library-owned device memory."""
+    out = torch.empty(n, dtype=dtype, device=device)
+    _check("rtsdf_copy", _lib.rtsdf_copy(_ptr(out), int(ptr), out.numel() * out.element_size(), _stream(None)))
+    return out
+
+
+class Batch:
+    """Owning handle of an ``rtsdf_batch``: many scenes, one launch per stage."""
+
+    def __init__(self, scenes: list[dict], seed: int = 0, leaf_size: int = 2, stream=None):
+        arr = (BatchScene * len(scenes))()
+        self._keep = []
+        for i, d in enumerate(scenes):
+            v = d["vertices"].contiguous()
+            f = d["faces"].contiguous()
+            _dtype(v, torch.float32, "vertices")
+            _dtype(f, torch.int32, "faces")
+            self._keep += [v, f]
+            b = arr[i]
+            b.vertices, b.nv, b.faces, b.nt = _ptr(v), v.shape[0], _ptr(f), f.shape[0]
+            lo = d.get("lo", (0.0, 0.0, 0.0))
+            b.lo[0], b.lo[1], b.lo[2] = (float(x) for x in lo)
+            b.side = float(d.get("side", 1.0))
+            b.coarse_n, b.fine_n = int(d["coarse_n"]), int(d["fine_n"])
+            b.beta, b.d = float(d["beta"]), float(d["d"])
+            b.rays_per_texel, b.alpha, b.scene_id = int(d["rays"]), float(d.get("alpha", 1.0)), int(d.get("scene_id", i))
+        h = _P()
+        _check("rtsdf_batch_create", _lib.rtsdf_batch_create(arr, len(scenes), int(seed), int(leaf_size), C.byref(h),
+                                                             _stream(stream)))
+        self.handle = h
+        self.n = len(scenes)
+        self._keep = []  # the batch copied the meshes
+
+    def step(self, frame: int, frame_ptr=None, stream=None):
+        _check("rtsdf_batch_step", _lib.rtsdf_batch_step(self.handle, int(frame), _ptr(frame_ptr), _stream(stream)))
+
+    def reset(self, stream=None):
+        _check("rtsdf_batch_reset", _lib.rtsdf_batch_reset(self.handle, _stream(stream)))
+
+    def view(self, i: int) -> BatchView:
+        v = BatchView()
+        _check("rtsdf_batch_outputs", _lib.rtsdf_batch_outputs(self.handle, int(i), C.byref(v)))
+        return v
+
+    def tensors(self, i: int, device="cuda") -> dict:
+        """Copies of scene i's outputs as device tensors."""
+        v = self.view(i)
+        nc3, nf3 = v.coarse.n ** 3, v.fine.n ** 3
+        return {
+            "seeds": _dev_view(v.seeds, nc3, torch.int32, device),
+            "dist2": _dev_view(v.dist2, nc3, torch.int32, device),
+            "coarse_sdf": _dev_view(v.coarse_sdf, nc3, torch.float32, device),
+            "mask": _dev_view(v.mask, nf3, torch.uint8, device),
+            "count": _dev_view(v.count, 1, torch.int32, device),
+            "queue": _dev_view(v.queue, nf3, torch.int32, device),
+            "u": _dev_view(v.state.u, nf3, torch.float32, device),
+            "hits": _dev_view(v.state.hits, nf3, torch.int32, device),
+            "arg_tri": _dev_view(v.state.arg_tri, nf3, torch.int32, device),
+            "arg_ray": _dev_view(v.state.arg_ray, nf3, torch.int32, device),
+            "fine_sdf": _dev_view(v.fine_sdf, nf3, torch.float32, device),
+        }
+
+    def make_graph(self, first_frame: int = 0, stream=None) -> FrameGraph:
+        self.frame_counter = torch.full((1,), int(first_frame), dtype=torch.int32, device="cuda")
+        h = _P()
+        _check("rtsdf_batch_graph_create", _lib.rtsdf_batch_graph_create(self.handle, _ptr(self.frame_counter),
+                                                                         C.byref(h), _stream(stream)))
+        return FrameGraph(None, keepalive=(self,), handle=h)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.rtsdf_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -82,3 +82,32 @@ def test_host_validation(R):
     assert prev.as_dict() == default and R.rtsdf_trace_config_get().refill == 8
     R.rtsdf_trace_config(**default)
     assert R.rtsdf_select_workspace_size(128) >= (128 ** 3 // 1024) * 4
+
+
+def test_struct_layouts_match_header(R, tmp_path):
+    # compile a C probe against include/rtsdf.h and compare sizes / offsets
+    structs = {
+        "rtsdf_grid": (R.Grid, ["lo", "h", "n"]),
+        "rtsdf_accum": (R.Accum, ["u", "hits", "arg_tri", "arg_ray"]),
+        "rtsdf_scene_info": (R.SceneInfo, ["nv", "nt", "nodes", "max_depth", "leaf_size", "device_bytes"]),
+        "rtsdf_trace_tuning": (R.TraceTuning, ["refill", "blocks_per_cu", "stats", "loop", "bin_directions",
+                                               "stack_lds"]),
+        "rtsdf_frame_desc": (R.FrameDesc, [f for f, _ in R.FrameDesc._fields_]),
+        "rtsdf_batch_scene": (R.BatchScene, [f for f, _ in R.BatchScene._fields_]),
+        "rtsdf_batch_view": (R.BatchView, [f for f, _ in R.BatchView._fields_]),
+    }
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "rtsdf.h"', "int main(void) {"]
+    for cname, (_, fields) in structs.items():
+        src.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in fields:
+            src.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src.append("  return 0; }")
+    c = tmp_path / "probe.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, (cls, fields) in structs.items():
+        assert int(got[cname]) == C.sizeof(cls), cname
+        for f in fields:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
