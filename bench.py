@@ -41,7 +41,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="room", choices=["room", "tiny", "diff", "dynamic"])
+    ap.add_argument("--config", default="room", choices=["room", "tiny", "diff", "dynamic", "batched"])
+    ap.add_argument("--graph", type=int, default=1, choices=[0, 1],
+                    help="also time the whole update as one captured HIP graph")
+    ap.add_argument("--autotune", action="store_true", help="pick the tracer tuning by measurement first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--refill", type=int, default=16)
@@ -110,6 +113,10 @@ def main():
     from paper_2210_04449_amd.pipeline import Pipeline
     from synth.scenes import workload
 
+    if args.config == "batched":
+        return run_batched(args)
+    if args.config == "diff":
+        return run_diff(args)
     w = workload(args.config)
     tuning = dict(refill=args.refill, blocks_per_cu=args.blocks_per_cu, stats=0, loop=args.loop,
                   bin_directions=args.bin, stack_lds=args.stack_lds)
@@ -126,7 +133,22 @@ def main():
                  w.beta, w.d, w.rays, seed=0, scene_id=w.scene_seed, alpha=w.alpha, leaf_size=args.leaf_size)
     info = p.scene.info()
     stream = torch.cuda.current_stream()
+    dyn_frames = None
+    if args.config == "dynamic":
+        # animated subset moves rigidly; 8 distinct vertex sets are generated up front and cycled
+        dyn = w.extra["scene"]
+        dyn_frames = [torch.from_numpy(dyn.mesh(f).vertices).to(dev) for f in range(8)]
+
+    def update(f):
+        if dyn_frames is not None:
+            p.set_vertices(dyn_frames[f % len(dyn_frames)])
+
+    if args.autotune:
+        from paper_2210_04449_amd import autotune
+        tuned = autotune.tune(p)
+        tuning.update(tuned["tuning"])
     for f in range(args.warmup):
+        update(f)
         p.step(f)
     torch.cuda.synchronize()
     selected = p.selected()
@@ -138,6 +160,7 @@ def main():
         f = args.warmup + i
         e = ev[i]
         e[0].record(stream)
+        update(f)
         p.voxelize()
         e[1].record(stream)
         p.jfa()
@@ -166,6 +189,23 @@ def main():
     ops = rays * (OPS_RAY + nodes_per_ray * OPS_NODE + tris_per_ray * OPS_TRI)
     achieved = ops / trace_s / 1e12
 
+    graph_ms = None
+    if args.graph:
+        g = p.make_graph(first_frame=args.warmup + K + 1, refit=dyn_frames is not None)
+        g.launch()  # warm-up replay
+        torch.cuda.synchronize()
+        gs, ge = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(2, K // 2)
+        gs.record(stream)
+        for i in range(reps):
+            if dyn_frames is not None:  # the graph refits from the vertex buffer
+                p.vertices.copy_(dyn_frames[i % len(dyn_frames)])
+            g.launch()
+        ge.record(stream)
+        torch.cuda.synchronize()
+        graph_ms = gs.elapsed_time(ge) / reps
+        g.close()
+
     n3 = w.nc ** 3
     import math
     jfa_bytes = 8 * n3 * int(math.log2(w.nc)) + 12 * n3
@@ -193,6 +233,7 @@ def main():
             "rays_per_texel": w.rays,
         },
         "gpu_ms_per_step": round(gpu_ms, 3),
+        "graph_ms_per_step": None if graph_ms is None else round(graph_ms, 3),
         "stages_ms": {k: round(v, 4) for k, v in stage.items()},
         "selected_texels": selected,
         "rays_per_step": rays,
@@ -213,8 +254,132 @@ def main():
             "traffic": None,
         },
     }
-    if not args.no_cpu_baseline:
+    if dyn_frames is not None:
+        out["config"]["dynamic"] = "20% of primitives move rigidly; 8 precomputed vertex sets cycled; refit each update"
+    if not args.no_cpu_baseline and args.config != "dynamic":
         out["cpu_baseline"] = cpu_baseline(w, selected, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def _base_record(args, value_ms, config):
+    return {
+        "metric": METRIC, "value": round(value_ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(value_ms, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": config,
+    }
+
+
+def run_batched(args):
+    """64 seeded scenes of uneven size in one launch per stage, captured as one graph, against the same
+    scenes run one by one through the single-scene path."""
+    import torch
+
+    import paper_2210_04449_amd.rtsdf as R
+    from paper_2210_04449_amd.pipeline import Pipeline
+    from synth.scenes import batched_scenes
+
+    ws = batched_scenes(64)
+    dev = torch.device("cuda:0")
+    meshes = [(torch.from_numpy(w.mesh.vertices).to(dev), torch.from_numpy(w.mesh.faces).to(dev)) for w in ws]
+    B = R.Batch([dict(vertices=v, faces=f, coarse_n=w.nc, fine_n=w.nf, beta=w.beta, d=w.d, rays=w.rays,
+                      alpha=w.alpha, scene_id=w.scene_seed) for w, (v, f) in zip(ws, meshes)], seed=0)
+    if args.autotune:
+        from paper_2210_04449_amd import autotune
+        autotune.tune(B)
+    g = B.make_graph(first_frame=0)
+    for _ in range(args.warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    s0.record(stream)
+    for _ in range(args.steps):
+        g.launch()
+    s1.record(stream)
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    rays = sum(B.tensors(i)["count"].item() * w.rays for i, w in enumerate(ws))
+    # the same scenes one at a time (eager single-scene path)
+    single_ms = 0.0
+    for w, (v, f) in zip(ws, meshes):
+        p = Pipeline(v, f, w.nc, w.nf, w.beta, w.d, w.rays, scene_id=w.scene_seed, alpha=w.alpha)
+        p.step(0)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for fr in range(1, 3):
+            p.step(fr)
+        b.record(stream)
+        torch.cuda.synchronize()
+        single_ms += a.elapsed_time(b) / 2
+        p.close()
+        del p
+    out = _base_record(args, batch_ms, {
+        "workload": "batched: 64 seeded scenes, triangles log-uniform 1k-100k, coarse in {32,64,128}, fine 2x, "
+                    "beta 0.5 / d 2 coarse voxels, 8 rays/texel, one graph-captured step",
+        "scenes": len(ws), "triangles": int(sum(w.mesh.nt for w in ws))})
+    out.update({"batch_gpu_ms_per_step": round(s0.elapsed_time(s1) / args.steps, 3),
+                "sum_single_scene_ms": round(single_ms, 3), "speedup_vs_single": round(single_ms / batch_ms, 3),
+                "rays_per_step": int(rays), "rays_per_s": round(rays / (batch_ms / 1e3), 1)})
+    print(json.dumps(out), flush=True)
+
+
+def run_diff(args):
+    """Differentiable config: forward (all frames) and backward to vertex positions, against the plain forward."""
+    import numpy as np
+    import torch
+
+    from paper_2210_04449_amd.autograd import fine_sdf
+    from paper_2210_04449_amd.pipeline import Pipeline
+    from synth.scenes import workload
+
+    w = workload("diff")
+    dev = torch.device("cuda:0")
+    v0 = torch.from_numpy(w.mesh.vertices).to(dev)
+    p = Pipeline(v0, torch.from_numpy(w.mesh.faces).to(dev), w.nc, w.nf, w.beta, w.d, w.rays, scene_id=w.scene_seed)
+    j = torch.arange(w.nf ** 3, device=dev)
+    P = torch.stack([j % w.nf, (j // w.nf) % w.nf, j // w.nf ** 2], 1).float().add_(0.5).div_(w.nf)
+    target = (P - 0.5).norm(dim=1) - 0.3
+    frames = range(w.frames)
+    stream = torch.cuda.current_stream()
+
+    def plain():
+        p.set_vertices(v0)
+        p.reset()
+        for f in frames:
+            p.step(f)
+
+    def fwd_bwd():
+        v = v0.clone().requires_grad_(True)
+        f = fine_sdf(v, p, frames)
+        loss = ((f - target) ** 2).sum()
+        loss.backward()
+        return v.grad
+
+    for _ in range(args.warmup):
+        plain()
+        fwd_bwd()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    reps = max(1, args.steps // 4)
+    ev[0].record(stream)
+    for _ in range(reps):
+        plain()
+    ev[1].record(stream)
+    for _ in range(reps):
+        g = fwd_bwd()
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    plain_ms = ev[0].elapsed_time(ev[1]) / reps
+    fb_ms = ev[1].elapsed_time(ev[2]) / reps
+    out = _base_record(args, fb_ms, {
+        "workload": f"diff: perturbed geodesic sphere {w.mesh.nt} triangles, coarse {w.nc}^3 / fine {w.nf}^3, "
+                    f"{w.rays} rays x {w.frames} frames; loss sum (f - sphere SDF)^2; forward + backward",
+        "triangles": w.mesh.nt})
+    out.update({"plain_forward_ms": round(plain_ms, 3), "forward_backward_ms": round(fb_ms, 3),
+                "backward_overhead_ms": round(fb_ms - plain_ms, 3),
+                "grad_norm": float(g.norm().item())})
     print(json.dumps(out), flush=True)
 
 

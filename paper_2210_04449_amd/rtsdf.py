@@ -243,6 +243,13 @@ class AccumState:
         self.arg_ray = torch.empty(n, dtype=torch.int32, device=device)
         rtsdf_accum_reset(fine, self)
 
+    @classmethod
+    def wrap(cls, u, hits, arg_tri, arg_ray) -> "AccumState":
+        """A state over existing tensors (no reset)."""
+        s = cls.__new__(cls)
+        s.u, s.hits, s.arg_tri, s.arg_ray = u, hits, arg_tri, arg_ray
+        return s
+
     def struct(self) -> Accum:
         return Accum(_ptr(self.u), _ptr(self.hits), _ptr(self.arg_tri), _ptr(self.arg_ray))
 

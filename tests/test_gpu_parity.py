@@ -307,6 +307,31 @@ def test_trace_decay_alpha(R):
     compare_trace(p, ref)
 
 
+def test_trace_moving_scene_alpha(R):
+    """Dynamic workload in small: a room whose seeded 20% subset of primitives
+    moves every frame, refit per frame, alpha 0.9; the oracle rebuilds its
+    hierarchy for each frame's mesh and carries the accumulation state."""
+    say("trace moving scene alpha 0.9")
+    from synth.scenes import DynamicScene
+    from paper_2210_04449_amd.pipeline import Pipeline
+    dyn = DynamicScene(7, n_prims=30, detail="low")
+    nc, nf, rays, alpha = 32, 64, 4, 0.9
+    m0 = dyn.mesh(0)
+    beta, d = np.float32(0.5 / nc), np.float32(2.0 / nc)
+    p = Pipeline(cu(m0.vertices), cu(m0.faces), nc, nf, float(beta), float(d), rays, scene_id=9, alpha=alpha)
+    st = oracle.TraceState(nf)
+    for f in range(5):
+        m = dyn.mesh(f)
+        p.set_vertices(cu(m.vertices))
+        p.step(f)
+        ref = oracle.run_frames(m.vertices, m.faces, nc, nf, beta, d, rays, [f], seed=0, scene=9, alpha=alpha,
+                                state=st)
+    torch.cuda.synchronize()
+    stats = compare_trace(p, ref)
+    print(stats)
+    assert stats["texels"] > 10000
+
+
 # ------------------------------------------------------------- refit ----
 
 def test_refit_matches_moved_mesh(R):
