@@ -174,7 +174,11 @@ def main():
     ms_per_step = wall * 1e3 / K
     names = ["voxelize", "jfa", "select", "trace"]
     stage = {n: sum(ev[i][j].elapsed_time(ev[i][j + 1]) for i in range(K)) / K for j, n in enumerate(names)}
-    gpu_ms = sum(ev[i][0].elapsed_time(ev[i][4]) for i in range(K)) / K
+    per_step = sorted(ev[i][0].elapsed_time(ev[i][4]) for i in range(K))
+    gpu_ms = sum(per_step) / K
+
+    def pct(q):
+        return per_step[min(K - 1, int(round(q * (K - 1))))]
     rays = selected * w.rays
     trace_s = stage["trace"] / 1e3
 
@@ -206,6 +210,13 @@ def main():
         graph_ms = gs.elapsed_time(ge) / reps
         g.close()
 
+    # HBM bytes per trace launch from the committed PMC summary of this workload, when it was taken on the
+    # current kernel sources (else null)
+    from paper_2210_04449_amd.prof_summary import traffic_from_summary
+    tname = f"trace_persistent<{tuning['stack_lds']},{tuning['refill']},{tuning['loop']},false,false>"
+    tr = traffic_from_summary(os.path.join(ROOT, "profiles", f"pmc_{w.name}_{w.nc}_{w.nf}.txt"), tname)
+    traffic = None if tr is None else int(tr["fetch_bytes"] + tr["write_bytes"])
+
     n3 = w.nc ** 3
     import math
     jfa_bytes = 8 * n3 * int(math.log2(w.nc)) + 12 * n3
@@ -233,6 +244,7 @@ def main():
             "rays_per_texel": w.rays,
         },
         "gpu_ms_per_step": round(gpu_ms, 3),
+        "gpu_ms_p10_p50_p90": [round(pct(0.1), 3), round(pct(0.5), 3), round(pct(0.9), 3)],
         "graph_ms_per_step": None if graph_ms is None else round(graph_ms, 3),
         "stages_ms": {k: round(v, 4) for k, v in stage.items()},
         "selected_texels": selected,
@@ -251,7 +263,8 @@ def main():
             "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "TOP/s",
             "frac": round(achieved / VALU_PEAK_TOPS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
     }
     if dyn_frames is not None:

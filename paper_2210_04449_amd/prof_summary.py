@@ -2,20 +2,54 @@
 
     python -m paper_2210_04449_amd.prof_summary stats <dir>/<name>_kernel_stats.csv
     python -m paper_2210_04449_amd.prof_summary pmc <counter_collection.csv> [...]
+    python -m paper_2210_04449_amd.prof_summary hash
 
 The PMC summary reports counter values per dispatch for each kernel.  HBM
 bytes come from FETCH_SIZE and WRITE_SIZE (KiB per dispatch); each is scaled
 by what the same counter reads for the device-to-device copy of a known size
 that ``bench.py --calibrate-copy`` performs first (256 MiB read, 256 MiB
-written; the copy runs as ``__amd_rocclr_copyBuffer``).
+written; the copy runs as ``__amd_rocclr_copyBuffer``, and it is the largest
+dispatch of that kernel in the run).  The summary records the hash of the
+library's kernel sources it was measured on (``source_hash``), so a reader can
+tell whether the counters still describe the current kernels.
 """
 from __future__ import annotations
 
 import collections
 import csv
+import glob
+import hashlib
+import os
 import sys
 
 COPY_BYTES = 256 << 20
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def source_hash() -> str:
+    """sha256 over the library's kernel sources (file names and contents, sorted by name)."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
+        if f.endswith((".hip", ".hpp", ".h")):
+            h.update(os.path.basename(f).encode())
+            h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_summary(path: str, kernel_prefix: str) -> dict | None:
+    """HBM bytes per dispatch of a kernel from a PMC summary, if the summary's source hash is current."""
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    tag = next((ln.split()[-1] for ln in lines if ln.startswith("source_hash")), None)
+    if tag != source_hash():
+        return None
+    for ln in lines:
+        if ln.startswith("traffic ") and kernel_prefix in ln.split()[1]:
+            f = dict(kv.split("=") for kv in ln.split()[2:])
+            return {"fetch_bytes": float(f["fetch_bytes"]), "write_bytes": float(f["write_bytes"])}
+    return None
 
 
 def stats(path: str) -> str:
@@ -38,15 +72,21 @@ def pmc(paths: list[str]) -> str:
             names[r["Dispatch_Id"]] = r["Kernel_Name"]
         for (disp, ctr), v in acc.items():
             per[names[disp]][ctr].append(v)
-    out = []
+    out = [f"source_hash {source_hash()}"]
     scale = {}
     for k, cs in per.items():
         if "copyBuffer" in k:
             for c in ("FETCH_SIZE", "WRITE_SIZE"):
                 if c in cs:
-                    scale[c] = COPY_BYTES / (sum(cs[c]) * 1024.0)
+                    scale[c] = COPY_BYTES / (max(cs[c]) * 1024.0)
     out.append("copy calibration (256 MiB device-to-device): bytes per counted byte = "
                + ", ".join(f"{c} x{v:.3f}" for c, v in sorted(scale.items())))
+    for k, cs in sorted(per.items(), key=lambda kv: kv[0]):
+        if "FETCH_SIZE" in cs and "WRITE_SIZE" in cs and "FETCH_SIZE" in scale and "WRITE_SIZE" in scale:
+            fb = sum(cs["FETCH_SIZE"]) / len(cs["FETCH_SIZE"]) * 1024.0 * scale["FETCH_SIZE"]
+            wb = sum(cs["WRITE_SIZE"]) / len(cs["WRITE_SIZE"]) * 1024.0 * scale["WRITE_SIZE"]
+            name = k.split("(")[0].replace(" ", "")
+            out.append(f"traffic {name} fetch_bytes={fb:.0f} write_bytes={wb:.0f}")
     for k, cs in sorted(per.items(), key=lambda kv: kv[0]):
         out.append(f"\n{k}")
         for c, vals in sorted(cs.items()):
@@ -59,6 +99,9 @@ def pmc(paths: list[str]) -> str:
 
 
 def main(argv):
+    if len(argv) == 2 and argv[1] == "hash":
+        print(source_hash())
+        return 0
     if len(argv) < 3 or argv[1] not in ("stats", "pmc"):
         print(__doc__)
         return 2
