@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--refill", type=int, default=16)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
-    ap.add_argument("--loop", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--loop", type=int, default=1, choices=[0, 1, 2])
     ap.add_argument("--bin", type=int, default=1, choices=[0, 1])
     ap.add_argument("--stack-lds", type=int, default=12, choices=[12, 16, 24])
     ap.add_argument("--leaf-size", type=int, default=2)
@@ -186,7 +186,7 @@ def main():
     R.rtsdf_trace_config(**{**tuning, "stats": 1})
     p.trace(args.warmup + K)
     torch.cuda.synchronize()
-    ctr = p.trace_ws[8:32].view(torch.int64).cpu().tolist()
+    ctr = p.trace_ws[8:64].view(torch.int64).cpu().tolist()
     R.rtsdf_trace_config(**tuning)
     nodes_per_ray = ctr[0] / max(ctr[2], 1)
     tris_per_ray = ctr[1] / max(ctr[2], 1)
@@ -253,7 +253,10 @@ def main():
         "jfa": {"gbps": round(jfa_gbs, 1), "frac_hbm": round(jfa_gbs / HBM_PEAK_GBS, 4),
                 "algorithmic_bytes": jfa_bytes},
         "trace_stats": {"nodes_per_ray": round(nodes_per_ray, 2), "tris_per_ray": round(tris_per_ray, 2),
-                        "rays_counted": ctr[2], "bvh_nodes": info.nodes, "bvh_max_depth": info.max_depth,
+                        "rays_counted": ctr[2], "wave_iterations": ctr[3] // 64, "refill_rounds": ctr[4] // 64,
+                        "tiles": ctr[6] // 64,
+                        "lane_work_fraction": round(ctr[5] / max(ctr[3], 1), 4) if tuning["loop"] >= 1 else None,
+                        "bvh_nodes": info.nodes, "bvh_max_depth": info.max_depth,
                         "bvh_max_leaf": info.leaf_size, "leaf_size": args.leaf_size},
         "trace_tuning": tuning,
         "roofline": {

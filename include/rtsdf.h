@@ -235,12 +235,15 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
  *                   lanes are free (8 or 16);
  *   blocks_per_cu   persistent workgroups per compute unit (0 = as many as
  *                   fit, at most 8);
- *   stats           1: count node visits, triangle tests and rays into 64-bit
- *                   counters at byte offsets 8, 16 and 24 of the workspace
+ *   stats           1: count into 64-bit counters at byte offsets 8, 16, ...
+ *                   of the workspace: node visits, triangle tests, rays,
+ *                   traversal iterations x 64, refill rounds x 64, lane
+ *                   iterations with work (loop 1 and 2), tiles x 64
  *                   (slower; for measurement only);
  *   loop            0: two phases per iteration (walk nodes until every lane
  *                   holds a leaf, then test the leaves); 1: one unit of work
- *                   per lane per iteration (a triangle or a node);
+ *                   per lane per iteration (a triangle or a node); 2: as 1,
+ *                   with one shared stack push/pop per iteration;
  *   bin_directions  1: each wavefront's tile of rays is sorted by direction
  *                   before tracing (coherence); 0: queue order;
  *   stack_lds       traversal stack entries kept in LDS per lane (12, 16 or

@@ -17,7 +17,7 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
-    # packed fp32 instructions stay off (see the build notes)
+    # no packed fp32 VALU instructions: the kernels are written for one fp32 operation per lane and instruction
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]

@@ -99,7 +99,7 @@ struct RaySetup {
 __device__ __forceinline__ float safe_inv(float d)
 {
     const float a = fabsf(d) < 1e-12f ? copysignf(1e-12f, d) : d;
-    return 1.0f / a;
+    return __builtin_amdgcn_rcpf(a);
 }
 
 __device__ __forceinline__ void ray_setup(float ox, float oy, float oz, float dx, float dy, float dz, RaySetup &R)
@@ -125,7 +125,9 @@ __device__ __forceinline__ void ray_setup(float ox, float oy, float oz, float dx
     }
     const float dkx = kx == 0 ? d[0] : (kx == 1 ? d[1] : d[2]);
     const float dky = ky == 0 ? d[0] : (ky == 1 ? d[1] : d[2]);
-    const float Sx = dkx / dkz, Sy = dky / dkz, Sz = 1.0f / dkz;
+    // The shear only has to be the same for every triangle a ray meets (that is what makes the test
+    // watertight), not correctly rounded: one native reciprocal serves all three factors.
+    const float Sz = __builtin_amdgcn_rcpf(dkz), Sx = dkx * Sz, Sy = dky * Sz;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         R.m[0 + j] = j == kx ? 1.0f : (j == kz ? -Sx : 0.0f);
@@ -134,7 +136,7 @@ __device__ __forceinline__ void ray_setup(float ox, float oy, float oz, float dx
     }
 #pragma unroll
     for (int r = 0; r < 3; ++r) R.t[r] = -(R.m[3 * r] * o[0] + R.m[3 * r + 1] * o[1] + R.m[3 * r + 2] * o[2]);
-    R.len = sqrtf(dx * dx + dy * dy + dz * dz);
+    R.len = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
 }
 
 __device__ __forceinline__ void to_ray_space(const RaySetup &R, float4 v, float &x, float &y, float &z)
@@ -366,6 +368,33 @@ __device__ __forceinline__ void node_step(const BvhView &S, int stride, const Ra
     }
 }
 
+// Same decisions as node_step, written as selects: the caller performs the
+// (at most one) push and the (at most one) pop after the lane's work of the
+// iteration, so every lane shares one copy of the stack code.
+__device__ __forceinline__ void node_step_flat(const BvhView &S, const RaySetup &R, int &node, float tbest,
+                                               int &tri_cur, int &tri_end, bool &push, int &push_val, bool &pop)
+{
+    const BvhNode *nd = node_ptr(S.nodes, node);
+    const float4 a = nd->xy0, b = nd->xy1, z = nd->z01;
+    const int4 m = nd->meta;
+    const float t0 = box_entry(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest);
+    const float t1 = box_entry(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest);
+    const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
+    const bool any = h0 || h1, both = h0 && h1;
+    const bool first0 = h0 && (!h1 || t0 <= t1);
+    const int near = first0 ? m.x : m.y, far = first0 ? m.y : m.x;
+    const bool near_leaf = any && near < 0;
+    if (near_leaf) {
+        tri_cur = leaf_first(near);
+        tri_end = tri_cur + leaf_count(near);
+    }
+    // next: the nearer internal child; after a leaf child, the other hit child; else pop
+    push = both && !near_leaf;
+    push_val = far;
+    pop = !any || (near_leaf && !both);
+    node = near_leaf ? far : near;
+}
+
 // Octahedral direction bin (8 x 8 cells of the octahedral map, numbered in
 // Morton order so consecutive bins are neighbours on the sphere).
 constexpr int kBins = 64;
@@ -388,9 +417,11 @@ struct WaveTile {
     int32_t tex[kTileTexels];
     unsigned long long key[kTileTexels];  // min over rays of (distance bits << 32 | ray << 26 | triangle)
     uint32_t cnt[kTileTexels];            // front | back << 16 for this frame
-    uint32_t bin[kBins];                  // bin counts, then bin cursors
     uint16_t perm[kTileRays];             // ray ids (slot * R + ray) sorted by direction bin
-    uint8_t binof[kTileRays];             // direction bin of each ray
+    struct {
+        uint32_t bin[kBins];              // bin counts, then bin cursors
+        uint8_t binof[kTileRays];         // direction bin of each ray
+    } sort;
 };
 
 // Tiles of a scene: ceil(min(count, cap) / tile texels).
@@ -421,20 +452,22 @@ __global__ void trace_tile_prefix(const TraceScene *scenes, int n, int32_t *tile
 // folded per texel with LDS atomics (a 64-bit min keeps the smallest distance,
 // ties to the lowest ray index, together with its triangle; an add counts
 // front and back hits), which makes them independent of the order rays
-// complete in.  Two traversal loop shapes (LOOP): 0 = phases per iteration
+// complete in.  Three traversal loop shapes (LOOP): 0 = phases per iteration
 // (after Aila and Laine's "while-while" loop with postponed leaves: every lane
 // walks internal nodes until it holds a leaf, then all held leaves are
 // tested); 1 = one unit of work per lane per iteration (a triangle of the
 // current leaf, else a node, else opening a popped leaf), which keeps more
-// lanes busy on wave64.  BATCHED launches serve many scenes: a global tile
+// lanes busy on wave64; 2 = as 1, but each lane only requests its stack
+// push/pop and one shared copy of the stack code runs after the work.  BATCHED launches serve many scenes: a global tile
 // index is mapped to its scene through the tile prefix.  Instrumented runs
-// (STATS) also count node visits, triangle tests and rays into 64-bit counters
-// at workspace offsets 8, 16 and 24.
+// (STATS) also count into 64-bit counters at workspace offsets 8, 16, ...:
+// node visits, triangle tests, rays, traversal-loop iterations x 64, refill
+// rounds x 64, lane-iterations with work (LOOP 1 and 2), tiles x 64.
 template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED>
 __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_waves_per_eu(6, 8)))
 trace_persistent(TraceArgs A)
 {
-    uint32_t st_nodes = 0, st_tris = 0, st_rays = 0;
+    uint32_t st_nodes = 0, st_tris = 0, st_rays = 0, st_iters = 0, st_refills = 0, st_busy = 0, st_tiles = 0;
     __shared__ int stack_mem[kTraceWaves * SL * kWave];
     __shared__ WaveTile tiles[kTraceWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -463,6 +496,7 @@ trace_persistent(TraceArgs A)
             s = __builtin_amdgcn_readfirstlane(lo);
         }
         const TraceScene &P = BATCHED ? A.scenes[s] : A.one;
+        if (STATS) ++st_tiles;
         const int R = P.rays;
         const int nfm = P.nf - 1;
         const int tile_texels = tile_texels_for(R);
@@ -478,7 +512,7 @@ trace_persistent(TraceArgs A)
             T.key[lane] = ~0ull;
             T.cnt[lane] = 0u;
         }
-        T.bin[lane] = 0u;
+        T.sort.bin[lane] = 0u;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         // ---- bin the tile's rays by direction
@@ -489,26 +523,26 @@ trace_persistent(TraceArgs A)
             int b = 0;
             if (j >= 0 && A.bin_directions)
                 b = direction_bin(sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, P.scene_id));
-            T.binof[q] = (uint8_t)b;
-            atomicAdd(&T.bin[b], 1u);
+            T.sort.binof[q] = (uint8_t)b;
+            atomicAdd(&T.sort.bin[b], 1u);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         {  // exclusive scan of the 64 bin counts, one per lane
-            const uint32_t c = T.bin[lane];
+            const uint32_t c = T.sort.bin[lane];
             uint32_t x = c;
 #pragma unroll
             for (int off = 1; off < kWave; off <<= 1) {
                 const uint32_t y = __shfl_up(x, off);
                 if (lane >= off) x += y;
             }
-            T.bin[lane] = x - c;
+            T.sort.bin[lane] = x - c;
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
         for (int q = lane; q < nrays; q += kWave) {
-            const uint32_t pos = atomicAdd(&T.bin[T.binof[q]], 1u);
+            const uint32_t pos = atomicAdd(&T.sort.bin[T.sort.binof[q]], 1u);
             T.perm[pos] = (uint16_t)q;
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -528,6 +562,7 @@ trace_persistent(TraceArgs A)
         while (true) {
             const uint64_t need = __ballot(!busy);
             if (need != 0 && pool < nrays) {
+                if (STATS) ++st_refills;
                 const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
                 const int take = min(__popcll(need), nrays - pool);
@@ -587,8 +622,40 @@ trace_persistent(TraceArgs A)
                     const uint64_t done = __ballot(!busy || (node == kDone && leaf == kDone));
                     if (__popcll(done) >= refill_at) break;
                 }
+            } else if (LOOP == 2) {
+                while (true) {
+                    if (STATS) {
+                        ++st_iters;
+                        st_busy += busy && (node != kDone || tri_cur < tri_end);
+                    }
+                    bool push = false, pop = false;
+                    int push_val = 0;
+                    if (busy) {
+                        if (tri_cur < tri_end) {
+                            if (STATS) ++st_tris;
+                            const float4 *tp = tri_ptr(S.tris, tri_cur);
+                            tri_test(Rs, tp[0], tp[1], tp[2], tbest, ibest, front);
+                            ++tri_cur;
+                        } else if (node >= 0) {
+                            if (STATS) ++st_nodes;
+                            node_step_flat(S, Rs, node, tbest, tri_cur, tri_end, push, push_val, pop);
+                        } else if (node != kDone) {
+                            tri_cur = leaf_first(node);
+                            tri_end = tri_cur + leaf_count(node);
+                            pop = true;
+                        }
+                    }
+                    if (push) stack_push<SL>(stride, sp, stk, spill, push_val);
+                    if (pop) node = stack_pop<SL>(stride, sp, stk, spill);
+                    const uint64_t done = __ballot(!busy || (node == kDone && tri_cur >= tri_end));
+                    if (__popcll(done) >= refill_at) break;
+                }
             } else {
                 while (true) {
+                    if (STATS) {
+                        ++st_iters;
+                        st_busy += busy && (node != kDone || tri_cur < tri_end);
+                    }
                     if (busy) {
                         if (tri_cur < tri_end) {
                             if (STATS) ++st_tris;
@@ -663,6 +730,10 @@ trace_persistent(TraceArgs A)
         atomicAdd(&ctr[0], (unsigned long long)st_nodes);
         atomicAdd(&ctr[1], (unsigned long long)st_tris);
         atomicAdd(&ctr[2], (unsigned long long)st_rays);
+        atomicAdd(&ctr[3], (unsigned long long)st_iters);
+        atomicAdd(&ctr[4], (unsigned long long)st_refills);
+        atomicAdd(&ctr[5], (unsigned long long)st_busy);
+        atomicAdd(&ctr[6], (unsigned long long)st_tiles);
     }
 }
 
@@ -824,7 +895,11 @@ static int launch_trace4(const TraceArgs &A, hipStream_t s)
 template <int SL, int REFILL, bool BATCHED>
 static int launch_trace3(const TraceArgs &A, hipStream_t s)
 {
-    return g_tuning.loop ? launch_trace4<SL, REFILL, 1, BATCHED>(A, s) : launch_trace4<SL, REFILL, 0, BATCHED>(A, s);
+    switch (g_tuning.loop) {
+    case 0: return launch_trace4<SL, REFILL, 0, BATCHED>(A, s);
+    case 1: return launch_trace4<SL, REFILL, 1, BATCHED>(A, s);
+    default: return launch_trace4<SL, REFILL, 2, BATCHED>(A, s);
+    }
 }
 
 template <int SL, bool BATCHED>
@@ -869,7 +944,7 @@ extern "C" int rtsdf_trace_config(const rtsdf_trace_tuning *t)
     if (!t) return RTSDF_EINVAL;
     if (t->refill != 8 && t->refill != 16) return RTSDF_EINVAL;
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return RTSDF_EINVAL;
-    if (t->stats < 0 || t->stats > 1 || t->loop < 0 || t->loop > 1) return RTSDF_EINVAL;
+    if (t->stats < 0 || t->stats > 1 || t->loop < 0 || t->loop > 2) return RTSDF_EINVAL;
     if (t->bin_directions < 0 || t->bin_directions > 1) return RTSDF_EINVAL;
     if (t->stack_lds != 12 && t->stack_lds != 16 && t->stack_lds != 24) return RTSDF_EINVAL;
     rtsdf::g_tuning = *t;
@@ -922,7 +997,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
         mask, coarse_sdf, coarse.n, logr, lognf, ntex, st.u, st.hits, st.arg_tri, st.arg_ray, fine_sdf);
     RTSDF_CHECK_LAUNCH();
     int32_t *cursor = static_cast<int32_t *>(workspace);
-    int rc = launch_fill<int32_t>(cursor, 0, g_tuning.stats ? 8 : 1, s);
+    int rc = launch_fill<int32_t>(cursor, 0, g_tuning.stats ? 16 : 1, s);
     if (rc != RTSDF_OK) return rc;
     TraceArgs A{};
     TraceScene &P = A.one;

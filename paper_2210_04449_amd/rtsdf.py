@@ -83,9 +83,10 @@ class RtsdfError(RuntimeError):
 
 
 def _load():
-    if not os.path.exists(LIB):
-        raise ImportError(f"{LIB} is not built; run `python -m paper_2210_04449_amd.build` (hipcc, gfx950)")
-    L = C.CDLL(LIB)
+    path = os.environ.get("RTSDF_LIBRARY") or LIB  # another build of the same library, e.g. for A/B timing
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_2210_04449_amd.build` (hipcc, gfx950)")
+    L = C.CDLL(path)
     sig = {
         "rtsdf_status_string": ([_i32], C.c_char_p),
         "rtsdf_version": ([], _i32),

@@ -283,6 +283,34 @@ def test_trace_determinism_and_resume(R):
     assert torch.equal(a.fine_sdf, c.fine_sdf) and torch.equal(a.state.u, c.state.u)
 
 
+@pytest.mark.parametrize("case", ["tiny", "room"])
+def test_trace_tunings_agree_bitwise(R, case):
+    """The tracer's tuning (loop shape, refill threshold, LDS stack depth,
+    direction sorting, workgroups per CU) changes speed only: every setting
+    gives the default setting's state and output bit for bit."""
+    w = workload(case)
+    frames = range(3) if case == "tiny" else range(1)
+    default = R.rtsdf_trace_config_get().as_dict()
+    settings = [dict(loop=0), dict(loop=2), dict(loop=2, refill=8), dict(loop=1, stack_lds=24),
+                dict(loop=2, stack_lds=16, bin_directions=0), dict(loop=2, blocks_per_cu=2)]
+    try:
+        say("tunings", case, "default", default)
+        ref = run_gpu(R, w, frames)
+        for t in settings:
+            say("tunings", case, t)
+            R.rtsdf_trace_config(**{**default, **t})
+            p = run_gpu(R, w, frames)
+            assert R.rtsdf_sync_status() == 0
+            for a, b in ((p.fine_sdf, ref.fine_sdf), (p.state.u, ref.state.u), (p.state.hits, ref.state.hits),
+                         (p.state.arg_tri, ref.state.arg_tri), (p.state.arg_ray, ref.state.arg_ray)):
+                assert torch.equal(a, b), t
+            p.close()
+            del p
+            R.rtsdf_trace_config(**default)
+    finally:
+        R.rtsdf_trace_config(**default)
+
+
 def test_trace_room_sampled(R):
     say("trace room sampled")
     w = workload("room")
