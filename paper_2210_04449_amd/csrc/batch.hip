@@ -355,6 +355,7 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
         TraceScene &P = trace[i];
         P.bvh.nodes = sc->nodes;
         P.bvh.tris = sc->tris;
+        P.bvh.tmap = sc->tmap;
         P.nt = sc->nt;
         P.queue = B->queue + B->foff[i];
         P.count = B->counts + i;

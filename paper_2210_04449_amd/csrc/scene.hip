@@ -12,6 +12,13 @@
 //   child >= 0 is an internal node, child < 0 a leaf: -1 - (first << 5 | count)
 //   with `count` triangles starting at `first` in the reordered triangle array.
 //   triangle (48 B): (v0, id) (v1, -) (v2, -) as float4s, in leaf order.
+//   triangle map (48 B, same order): rows r0, r1, r2 of the affine map that
+//     takes v0, v1, v2 to (0,0,0), (1,0,0), (0,1,0) and v0 + n to (0,0,1),
+//     n = (v1 - v0) x (v2 - v0); a point p maps to (r_k . (p, 1))_k, so for a
+//     ray the first two coordinates at the plane crossing are barycentrics
+//     b1, b2 and the third is the signed distance along n in units of |n|.
+//     Computed in double precision from the float vertices on the device (at
+//     creation and at every refit); degenerate triangles get a map no ray hits.
 //
 // Build (host, at creation): binned surface-area heuristic (32 bins per axis),
 // leaves of at most `leaf_size` triangles, depth capped (median splits below
@@ -53,6 +60,7 @@ struct rtsdf_scene {
     int device = 0;
     rtsdf::BvhNode *nodes = nullptr;   // [nnodes]
     float4 *tris = nullptr;            // [3 nt]
+    float4 *tmap = nullptr;            // [3 nt] triangle-space maps, leaf order
     int4 *leaf_faces = nullptr;        // [nt] (i0, i1, i2, original id) in leaf order
     float *vertices = nullptr;         // [3 nv] current positions
     int32_t *faces = nullptr;          // [3 nt]
@@ -250,6 +258,35 @@ __global__ void refit_tris(const float *__restrict__ v, const int4 *__restrict__
     }
 }
 
+// Rows of [e1 e2 n]^-1 are (e2 x n, n x e1, e1 x e2) / |n|^2; the translation
+// column sends v0 to the origin.
+__global__ void tri_maps(const float4 *__restrict__ tris, float4 *__restrict__ tmap, int nt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    const float4 a = tris[3 * i], b = tris[3 * i + 1], c = tris[3 * i + 2];
+    const double v0[3] = {a.x, a.y, a.z};
+    const double e1[3] = {(double)b.x - a.x, (double)b.y - a.y, (double)b.z - a.z};
+    const double e2[3] = {(double)c.x - a.x, (double)c.y - a.y, (double)c.z - a.z};
+    const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double nn = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+    if (!(nn > 0.0) || !isfinite(nn)) {  // no plane: every point maps to z = 1, rays parallel to "it"
+        tmap[3 * i] = make_float4(0.f, 0.f, 0.f, -1.f);
+        tmap[3 * i + 1] = make_float4(0.f, 0.f, 0.f, -1.f);
+        tmap[3 * i + 2] = make_float4(0.f, 0.f, 0.f, 1.f);
+        return;
+    }
+    const double r[3][3] = {
+        {e2[1] * n[2] - e2[2] * n[1], e2[2] * n[0] - e2[0] * n[2], e2[0] * n[1] - e2[1] * n[0]},
+        {n[1] * e1[2] - n[2] * e1[1], n[2] * e1[0] - n[0] * e1[2], n[0] * e1[1] - n[1] * e1[0]},
+        {n[0], n[1], n[2]}};
+    for (int k = 0; k < 3; ++k) {
+        const double x = r[k][0] / nn, y = r[k][1] / nn, z = r[k][2] / nn;
+        const double w = -(x * v0[0] + y * v0[1] + z * v0[2]);
+        tmap[3 * i + k] = make_float4((float)x, (float)y, (float)z, (float)w);
+    }
+}
+
 __device__ __forceinline__ void leaf_box(const float4 *__restrict__ tris, int code, float pad, float lo[3], float hi[3])
 {
     for (int a = 0; a < 3; ++a) {
@@ -413,6 +450,7 @@ static int rtsdf_scene_create_impl(const float *vertices, int32_t nv, const int3
     };
     const size_t nn = std::max(sc->nnodes, 1);
     if (!alloc((void **)&sc->nodes, sizeof(BvhNode) * nn) || !alloc((void **)&sc->tris, sizeof(float4) * htri.size()) ||
+        !alloc((void **)&sc->tmap, sizeof(float4) * htri.size()) ||
         !alloc((void **)&sc->leaf_faces, sizeof(int4) * hlf.size()) ||
         !alloc((void **)&sc->vertices, sizeof(float) * 3 * std::max(nv, 1)) ||
         !alloc((void **)&sc->faces, sizeof(int32_t) * 3 * std::max(nt, 1)) ||
@@ -429,6 +467,10 @@ static int rtsdf_scene_create_impl(const float *vertices, int32_t nv, const int3
     if (nt) ok &= hipMemcpyAsync(sc->faces, hf.data(), sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s) == hipSuccess;
     if (!starts.empty())
         ok &= hipMemcpyAsync(sc->start_nodes, starts.data(), sizeof(int32_t) * starts.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    if (ok && nt > 0) {
+        tri_maps<<<dim3((nt + 255) / 256), dim3(256), 0, s>>>(sc->tris, sc->tmap, nt);
+        ok &= hipGetLastError() == hipSuccess;
+    }
     ok &= hipStreamSynchronize(s) == hipSuccess;
     if (!ok) {
         rtsdf_scene_destroy(sc.release());
@@ -467,6 +509,8 @@ extern "C" int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsd
     if (scene->nt == 0) return RTSDF_OK;
     refit_tris<<<dim3((scene->nt + 255) / 256), dim3(256), 0, s>>>(scene->vertices, scene->leaf_faces, scene->tris, scene->nt);
     RTSDF_CHECK_LAUNCH();
+    tri_maps<<<dim3((scene->nt + 255) / 256), dim3(256), 0, s>>>(scene->tris, scene->tmap, scene->nt);
+    RTSDF_CHECK_LAUNCH();
     int rc = launch_fill<int32_t>(scene->refit_counter, 0, scene->nnodes, s);
     if (rc != RTSDF_OK) return rc;
     refit_nodes<<<dim3((scene->nstart + 255) / 256), dim3(256), 0, s>>>(scene->nodes, scene->tris, scene->start_nodes,
@@ -492,6 +536,7 @@ extern "C" void rtsdf_scene_destroy(rtsdf_scene *scene)
     if (!scene) return;
     (void)hipFree(scene->nodes);
     (void)hipFree(scene->tris);
+    (void)hipFree(scene->tmap);
     (void)hipFree(scene->leaf_faces);
     (void)hipFree(scene->vertices);
     (void)hipFree(scene->faces);

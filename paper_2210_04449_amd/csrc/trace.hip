@@ -92,7 +92,8 @@ __device__ __forceinline__ float texel_coord(float lo, int i, float h)
 struct RaySetup {
     float ix, iy, iz;    // 1 / direction (zero components replaced by +-1e-12)
     float oix, oiy, oiz; // origin * inverse
-    float m[9], t[3];    // ray-space map: x'_r = m[3r] x + m[3r+1] y + m[3r+2] z + t[r]
+    float ox, oy, oz;    // origin
+    float dx, dy, dz;    // direction
     float len;           // |direction|
 };
 
@@ -110,50 +111,46 @@ __device__ __forceinline__ void ray_setup(float ox, float oy, float oz, float dx
     R.oix = ox * R.ix;
     R.oiy = oy * R.iy;
     R.oiz = oz * R.iz;
+    R.ox = ox;
+    R.oy = oy;
+    R.oz = oz;
+    R.dx = dx;
+    R.dy = dy;
+    R.dz = dz;
+    R.len = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+}
+
+// Watertight ray/triangle test (Woop, Benthin and Wald 2013): the vertices are
+// taken into a ray space where the ray is the +z axis (permute so the largest
+// direction component is z, then shear), and the three 2-D edge functions
+// decide; edges shared by two triangles get the same values in both, so no
+// ray passes between them.  Zero edge functions are recomputed in double
+// precision.  Returns t of a front-face hit, -t of a back-face hit, 0 for a
+// miss (hits have t > 0).
+__device__ __noinline__ float tri_watertight(float ox, float oy, float oz, float dx, float dy, float dz,
+                                             const float4 *tp)
+{
+    const float4 a = tp[0], b = tp[1], c = tp[2];
     const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
     int kz = ay > ax ? 1 : 0;
     if (az > fmaxf(ax, ay)) kz = 2;
     int kx = kz == 2 ? 0 : kz + 1;
     int ky = kx == 2 ? 0 : kx + 1;
     const float d[3] = {dx, dy, dz};
-    const float o[3] = {ox, oy, oz};
-    const float dkz = kz == 0 ? dx : (kz == 1 ? dy : dz);
-    if (dkz < 0.0f) {
+    if (d[kz] < 0.0f) {
         const int t = kx;
         kx = ky;
         ky = t;
     }
-    const float dkx = kx == 0 ? d[0] : (kx == 1 ? d[1] : d[2]);
-    const float dky = ky == 0 ? d[0] : (ky == 1 ? d[1] : d[2]);
-    // The shear only has to be the same for every triangle a ray meets (that is what makes the test
-    // watertight), not correctly rounded: one native reciprocal serves all three factors.
-    const float Sz = __builtin_amdgcn_rcpf(dkz), Sx = dkx * Sz, Sy = dky * Sz;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        R.m[0 + j] = j == kx ? 1.0f : (j == kz ? -Sx : 0.0f);
-        R.m[3 + j] = j == ky ? 1.0f : (j == kz ? -Sy : 0.0f);
-        R.m[6 + j] = j == kz ? Sz : 0.0f;
-    }
-#pragma unroll
-    for (int r = 0; r < 3; ++r) R.t[r] = -(R.m[3 * r] * o[0] + R.m[3 * r + 1] * o[1] + R.m[3 * r + 2] * o[2]);
-    R.len = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
-}
-
-__device__ __forceinline__ void to_ray_space(const RaySetup &R, float4 v, float &x, float &y, float &z)
-{
-    x = fmaf(R.m[0], v.x, fmaf(R.m[1], v.y, fmaf(R.m[2], v.z, R.t[0])));
-    y = fmaf(R.m[3], v.x, fmaf(R.m[4], v.y, fmaf(R.m[5], v.z, R.t[1])));
-    z = fmaf(R.m[6], v.x, fmaf(R.m[7], v.y, fmaf(R.m[8], v.z, R.t[2])));
-}
-
-// Watertight test; updates the closest hit (t, id) with ties to the lower id.
-__device__ __forceinline__ void tri_test(const RaySetup &R, float4 a, float4 b, float4 c, float &tbest, int &ibest,
-                                         bool &front)
-{
-    float Ax, Ay, Az, Bx, By, Bz, Cx, Cy, Cz;
-    to_ray_space(R, a, Ax, Ay, Az);
-    to_ray_space(R, b, Bx, By, Bz);
-    to_ray_space(R, c, Cx, Cy, Cz);
+    // the shear only has to be the same for every triangle a ray meets, not correctly rounded
+    const float Sz = __builtin_amdgcn_rcpf(d[kz]), Sx = d[kx] * Sz, Sy = d[ky] * Sz;
+    const float o[3] = {ox, oy, oz};
+    const float va[3] = {a.x - o[0], a.y - o[1], a.z - o[2]};
+    const float vb[3] = {b.x - o[0], b.y - o[1], b.z - o[2]};
+    const float vc[3] = {c.x - o[0], c.y - o[1], c.z - o[2]};
+    const float Ax = va[kx] - Sx * va[kz], Ay = va[ky] - Sy * va[kz];
+    const float Bx = vb[kx] - Sx * vb[kz], By = vb[ky] - Sy * vb[kz];
+    const float Cx = vc[kx] - Sx * vc[kz], Cy = vc[ky] - Sy * vc[kz];
     float U = Cx * By - Cy * Bx;
     float V = Ax * Cy - Ay * Cx;
     float W = Bx * Ay - By * Ax;
@@ -162,18 +159,66 @@ __device__ __forceinline__ void tri_test(const RaySetup &R, float4 a, float4 b, 
         V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
         W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
     }
-    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return;
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return 0.0f;
     const float det = U + V + W;
-    if (det == 0.0f) return;
-    const float T = U * Az + V * Bz + W * Cz;
-    const float t = T * __builtin_amdgcn_rcpf(det);
-    if (!(t > 0.0f)) return;
-    const int id = __float_as_int(a.w);
-    if (t < tbest || (t == tbest && id < ibest)) {
-        tbest = t;
-        ibest = id;
-        front = det > 0.0f;
+    if (det == 0.0f) return 0.0f;
+    const float T = U * (Sz * va[kz]) + V * (Sz * vb[kz]) + W * (Sz * vc[kz]);
+    const float t = T / det;
+    if (!(t > 0.0f)) return 0.0f;
+    return det > 0.0f ? t : -t;
+}
+
+// Fast test through the triangle's precomputed map (see the scene layout):
+// t from the plane coordinate, then the barycentrics at the crossing.  Where
+// the smallest barycentric is within a rounding margin of zero -- the ray
+// passes near an edge or a vertex -- the decision is left to the watertight
+// test, so rays cannot slip between neighbouring triangles.  Updates the
+// closest hit (t, leaf-order index) with ties going to the lower original
+// triangle id.
+constexpr float kEdgeMargin = 0x1p-12f;  // relative to the magnitude of the terms of the barycentrics
+
+__device__ __forceinline__ void tri_test(const RaySetup &R, const float4 *tmap, const float4 *tris, int i,
+                                         float &tbest, int &ibest, bool &front)
+{
+    // the whole record in one round trip, and no branch before the decision
+    const float4 *mp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tmap) + (uint32_t)i * 48u);
+    const float4 r0 = mp[0], r1 = mp[1], r2 = mp[2];
+    const float pz = fmaf(r2.x, R.ox, fmaf(r2.y, R.oy, fmaf(r2.z, R.oz, r2.w)));
+    const float qz = fmaf(r2.x, R.dx, fmaf(r2.y, R.dy, r2.z * R.dz));
+    const float p0 = fmaf(r0.x, R.ox, fmaf(r0.y, R.oy, fmaf(r0.z, R.oz, r0.w)));
+    const float q0 = fmaf(r0.x, R.dx, fmaf(r0.y, R.dy, r0.z * R.dz));
+    const float p1 = fmaf(r1.x, R.ox, fmaf(r1.y, R.oy, fmaf(r1.z, R.oz, r1.w)));
+    const float q1 = fmaf(r1.x, R.dx, fmaf(r1.y, R.dy, r1.z * R.dz));
+    float t = -pz * __builtin_amdgcn_rcpf(qz);
+    const float b1 = fmaf(t, q0, p0), b2 = fmaf(t, q1, p1);
+    const float bmin = fminf(1.0f - b1 - b2, fminf(b1, b2));
+    const float margin = kEdgeMargin * (fmaf(t, fabsf(q0) + fabsf(q1), fabsf(p0) + fabsf(p1)) + 1.0f);
+    const bool in_range = t > 0.0f && t <= fminf(tbest, 3.0e38f);
+    bool hit = in_range && bmin > margin;
+    bool fr = qz < 0.0f;
+    if (in_range && !(bmin > margin) && !(bmin < -margin)) {
+        // near an edge or a vertex (or not a number): the watertight test decides
+        const float4 *tp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + (uint32_t)i * 48u);
+        const float h = tri_watertight(R.ox, R.oy, R.oz, R.dx, R.dy, R.dz, tp);
+        t = fabsf(h);
+        fr = h > 0.0f;
+        hit = h != 0.0f && t <= tbest;
     }
+    if (!hit) return;
+    if (t == tbest) {  // equal distances: the lower original triangle id wins
+        const float4 *tp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + (uint32_t)i * 48u);
+        const float4 *tb = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + (uint32_t)ibest * 48u);
+        if (!(__float_as_int(tp[0].w) < __float_as_int(tb[0].w))) return;
+    }
+    tbest = t;
+    ibest = i;
+    front = fr;
+}
+
+// original id of the triangle at leaf-order index i
+__device__ __forceinline__ int tri_id(const float4 *tris, int i)
+{
+    return __float_as_int(reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + (uint32_t)i * 48u)->w);
 }
 
 // slab test against a padded box; returns entry distance or +inf on a miss
@@ -192,7 +237,8 @@ constexpr int kDone = INT32_MIN;
 
 struct BvhView {
     const BvhNode *nodes;
-    const float4 *tris;
+    const float4 *tris;  // vertices (v0 carrying the original id), leaf order
+    const float4 *tmap;  // triangle-space maps, leaf order
 };
 
 // One traversal step of one lane: an internal node tests both child boxes
@@ -226,8 +272,7 @@ __device__ __forceinline__ void trav_step(const BvhView &S, const RaySetup &R, i
     } else {
         const int first = leaf_first(node), cnt = leaf_count(node);
         if (STATS) *tris_tested += (uint32_t)cnt;
-        for (int i = first; i < first + cnt; ++i)
-            tri_test(R, S.tris[3 * i], S.tris[3 * i + 1], S.tris[3 * i + 2], tbest, ibest, front);
+        for (int i = first; i < first + cnt; ++i) tri_test(R, S.tmap, S.tris, i, tbest, ibest, front);
     }
     node = sp > 0 ? stk[--sp * stride] : kDone;
 }
@@ -614,8 +659,7 @@ trace_persistent(TraceArgs A)
                         const int first = leaf_first(leaf), cnt = leaf_count(leaf);
                         if (STATS) st_tris += (uint32_t)cnt;
                         for (int i = first; i < first + cnt; ++i) {
-                            const float4 *tp = tri_ptr(S.tris, i);
-                            tri_test(Rs, tp[0], tp[1], tp[2], tbest, ibest, front);
+                            tri_test(Rs, S.tmap, S.tris, i, tbest, ibest, front);
                         }
                         leaf = kDone;
                     }
@@ -633,8 +677,7 @@ trace_persistent(TraceArgs A)
                     if (busy) {
                         if (tri_cur < tri_end) {
                             if (STATS) ++st_tris;
-                            const float4 *tp = tri_ptr(S.tris, tri_cur);
-                            tri_test(Rs, tp[0], tp[1], tp[2], tbest, ibest, front);
+                            tri_test(Rs, S.tmap, S.tris, tri_cur, tbest, ibest, front);
                             ++tri_cur;
                         } else if (node >= 0) {
                             if (STATS) ++st_nodes;
@@ -659,8 +702,7 @@ trace_persistent(TraceArgs A)
                     if (busy) {
                         if (tri_cur < tri_end) {
                             if (STATS) ++st_tris;
-                            const float4 *tp = tri_ptr(S.tris, tri_cur);
-                            tri_test(Rs, tp[0], tp[1], tp[2], tbest, ibest, front);
+                            tri_test(Rs, S.tmap, S.tris, tri_cur, tbest, ibest, front);
                             ++tri_cur;
                         } else if (node >= 0) {
                             node_step<SL, STATS>(S, stride, Rs, node, sp, stk, spill, tbest, tri_cur, tri_end,
@@ -680,7 +722,8 @@ trace_persistent(TraceArgs A)
                 if (ibest >= 0) {
                     const float dist = tbest * Rs.len;
                     const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) |
-                                                   ((unsigned long long)r << 26) | (unsigned long long)ibest;
+                                                   ((unsigned long long)r << 26) |
+                                                   (unsigned long long)tri_id(S.tris, ibest);
                     atomicMin(&T.key[slot], key);
                     atomicAdd(&T.cnt[slot], front ? 1u : 0x10000u);
                 }
@@ -808,7 +851,7 @@ __global__ void __launch_bounds__(256) closest_hits_kernel(BvhView S, int nt, co
     bool front = false;
     while (node != kDone) trav_step(S, R, node, sp, stk, kWave, tbest, ibest, front);
     t_out[i] = ibest >= 0 ? tbest : __builtin_inff();
-    tri_out[i] = ibest;
+    tri_out[i] = ibest >= 0 ? tri_id(S.tris, ibest) : -1;
     front_out[i] = ibest >= 0 && front;
 }
 
@@ -1003,6 +1046,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     TraceScene &P = A.one;
     P.bvh.nodes = scene->nodes;
     P.bvh.tris = scene->tris;
+    P.bvh.tmap = scene->tmap;
     P.nt = scene->nt;
     P.queue = queue;
     P.count = count;
@@ -1056,7 +1100,7 @@ extern "C" int rtsdf_closest_hits(const rtsdf_scene *scene, const float *origins
     if (n == 0) return RTSDF_OK;
     const int sd = stack_depth_for(scene);
     if (sd > 64) return RTSDF_EINVAL;
-    BvhView S{scene->nodes, scene->tris};
+    BvhView S{scene->nodes, scene->tris, scene->tmap};
     hipStream_t s = as_stream(stream);
     const dim3 g((n + 255) / 256), b(256);
     if (sd <= 32)
