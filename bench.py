@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--refill", type=int, default=16)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
-    ap.add_argument("--loop", type=int, default=1, choices=[0, 1, 2])
+    ap.add_argument("--loop", type=int, default=3, choices=[0, 1, 2, 3])
     ap.add_argument("--bin", type=int, default=1, choices=[0, 1])
     ap.add_argument("--stack-lds", type=int, default=12, choices=[12, 16, 24])
     ap.add_argument("--leaf-size", type=int, default=2)

@@ -230,7 +230,9 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
                            rtsdf_accum state, float *fine_sdf, void *workspace, rtsdf_stream stream);
 
 /* Tuning and instrumentation of the tracer (process-wide host-side state,
- * read at each rtsdf_trace_accumulate call; results never depend on it):
+ * read at each rtsdf_trace_accumulate call; results never depend on it;
+ * defaults: refill 16, blocks_per_cu 0, stats 0, loop 3, bin_directions 1,
+ * stack_lds 12):
  *   refill          a wavefront hands out new rays once this many of its
  *                   lanes are free (8 or 16);
  *   blocks_per_cu   persistent workgroups per compute unit (0 = as many as
@@ -238,12 +240,15 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
  *   stats           1: count into 64-bit counters at byte offsets 8, 16, ...
  *                   of the workspace: node visits, triangle tests, rays,
  *                   traversal iterations x 64, refill rounds x 64, lane
- *                   iterations with work (loop 1 and 2), tiles x 64
+ *                   iterations with work (loop >= 1), tiles x 64
  *                   (slower; for measurement only);
  *   loop            0: two phases per iteration (walk nodes until every lane
  *                   holds a leaf, then test the leaves); 1: one unit of work
  *                   per lane per iteration (a triangle or a node); 2: as 1,
- *                   with one shared stack push/pop per iteration;
+ *                   with one shared stack push/pop per iteration; 3: as 2,
+ *                   with each lane's node or triangle record fetched by one
+ *                   shared load sequence (one memory wait per iteration);
+ *                   default 3;
  *   bin_directions  1: each wavefront's tile of rays is sorted by direction
  *                   before tracing (coherence); 0: queue order;
  *   stack_lds       traversal stack entries kept in LDS per lane (12, 16 or

@@ -25,7 +25,7 @@ SPACE = {
     "refill": (8, 16),
     "stack_lds": (12, 16, 24),
     "bin_directions": (0, 1),
-    "loop": (0, 1),
+    "loop": (2, 3),
     "blocks_per_cu": (0,),
 }
 

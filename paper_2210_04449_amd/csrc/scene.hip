@@ -60,7 +60,7 @@ struct rtsdf_scene {
     int device = 0;
     rtsdf::BvhNode *nodes = nullptr;   // [nnodes]
     float4 *tris = nullptr;            // [3 nt]
-    float4 *tmap = nullptr;            // [3 nt] triangle-space maps, leaf order
+    float4 *tmap = nullptr;            // [3 nt + 1] triangle-space maps, leaf order (+ 16 B padding)
     int4 *leaf_faces = nullptr;        // [nt] (i0, i1, i2, original id) in leaf order
     float *vertices = nullptr;         // [3 nv] current positions
     int32_t *faces = nullptr;          // [3 nt]
@@ -450,7 +450,7 @@ static int rtsdf_scene_create_impl(const float *vertices, int32_t nv, const int3
     };
     const size_t nn = std::max(sc->nnodes, 1);
     if (!alloc((void **)&sc->nodes, sizeof(BvhNode) * nn) || !alloc((void **)&sc->tris, sizeof(float4) * htri.size()) ||
-        !alloc((void **)&sc->tmap, sizeof(float4) * htri.size()) ||
+        !alloc((void **)&sc->tmap, sizeof(float4) * (htri.size() + 1)) ||  // +1: the tracer's fetch reads 64 B
         !alloc((void **)&sc->leaf_faces, sizeof(int4) * hlf.size()) ||
         !alloc((void **)&sc->vertices, sizeof(float) * 3 * std::max(nv, 1)) ||
         !alloc((void **)&sc->faces, sizeof(int32_t) * 3 * std::max(nt, 1)) ||

@@ -177,12 +177,9 @@ __device__ __noinline__ float tri_watertight(float ox, float oy, float oz, float
 // triangle id.
 constexpr float kEdgeMargin = 0x1p-12f;  // relative to the magnitude of the terms of the barycentrics
 
-__device__ __forceinline__ void tri_test(const RaySetup &R, const float4 *tmap, const float4 *tris, int i,
-                                         float &tbest, int &ibest, bool &front)
+__device__ __forceinline__ void tri_test_rows(const RaySetup &R, float4 r0, float4 r1, float4 r2, const float4 *tris,
+                                              int i, float &tbest, int &ibest, bool &front)
 {
-    // the whole record in one round trip, and no branch before the decision
-    const float4 *mp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tmap) + (uint32_t)i * 48u);
-    const float4 r0 = mp[0], r1 = mp[1], r2 = mp[2];
     const float pz = fmaf(r2.x, R.ox, fmaf(r2.y, R.oy, fmaf(r2.z, R.oz, r2.w)));
     const float qz = fmaf(r2.x, R.dx, fmaf(r2.y, R.dy, r2.z * R.dz));
     const float p0 = fmaf(r0.x, R.ox, fmaf(r0.y, R.oy, fmaf(r0.z, R.oz, r0.w)));
@@ -213,6 +210,14 @@ __device__ __forceinline__ void tri_test(const RaySetup &R, const float4 *tmap, 
     tbest = t;
     ibest = i;
     front = fr;
+}
+
+__device__ __forceinline__ void tri_test(const RaySetup &R, const float4 *tmap, const float4 *tris, int i,
+                                         float &tbest, int &ibest, bool &front)
+{
+    // the whole record in one round trip, and no branch before the decision
+    const float4 *mp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tmap) + (uint32_t)i * 48u);
+    tri_test_rows(R, mp[0], mp[1], mp[2], tris, i, tbest, ibest, front);
 }
 
 // original id of the triangle at leaf-order index i
@@ -416,12 +421,10 @@ __device__ __forceinline__ void node_step(const BvhView &S, int stride, const Ra
 // Same decisions as node_step, written as selects: the caller performs the
 // (at most one) push and the (at most one) pop after the lane's work of the
 // iteration, so every lane shares one copy of the stack code.
-__device__ __forceinline__ void node_step_flat(const BvhView &S, const RaySetup &R, int &node, float tbest,
-                                               int &tri_cur, int &tri_end, bool &push, int &push_val, bool &pop)
+__device__ __forceinline__ void node_step_regs(const RaySetup &R, float4 a, float4 b, float4 z, int4 m, int &node,
+                                               float tbest, int &tri_cur, int &tri_end, bool &push, int &push_val,
+                                               bool &pop)
 {
-    const BvhNode *nd = node_ptr(S.nodes, node);
-    const float4 a = nd->xy0, b = nd->xy1, z = nd->z01;
-    const int4 m = nd->meta;
     const float t0 = box_entry(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest);
     const float t1 = box_entry(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest);
     const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
@@ -438,6 +441,13 @@ __device__ __forceinline__ void node_step_flat(const BvhView &S, const RaySetup 
     push_val = far;
     pop = !any || (near_leaf && !both);
     node = near_leaf ? far : near;
+}
+
+__device__ __forceinline__ void node_step_flat(const BvhView &S, const RaySetup &R, int &node, float tbest,
+                                               int &tri_cur, int &tri_end, bool &push, int &push_val, bool &pop)
+{
+    const BvhNode *nd = node_ptr(S.nodes, node);
+    node_step_regs(R, nd->xy0, nd->xy1, nd->z01, nd->meta, node, tbest, tri_cur, tri_end, push, push_val, pop);
 }
 
 // Octahedral direction bin (8 x 8 cells of the octahedral map, numbered in
@@ -503,7 +513,10 @@ __global__ void trace_tile_prefix(const TraceScene *scenes, int n, int32_t *tile
 // tested); 1 = one unit of work per lane per iteration (a triangle of the
 // current leaf, else a node, else opening a popped leaf), which keeps more
 // lanes busy on wave64; 2 = as 1, but each lane only requests its stack
-// push/pop and one shared copy of the stack code runs after the work.  BATCHED launches serve many scenes: a global tile
+// push/pop and one shared copy of the stack code runs after the work; 3 =
+// as 2, but every lane fetches its node or its triangle's map into the same
+// registers with one shared load sequence, so an iteration waits for memory
+// once instead of once per kind of work.  BATCHED launches serve many scenes: a global tile
 // index is mapped to its scene through the tile prefix.  Instrumented runs
 // (STATS) also count into 64-bit counters at workspace offsets 8, 16, ...:
 // node visits, triangle tests, rays, traversal-loop iterations x 64, refill
@@ -664,6 +677,43 @@ trace_persistent(TraceArgs A)
                         leaf = kDone;
                     }
                     const uint64_t done = __ballot(!busy || (node == kDone && leaf == kDone));
+                    if (__popcll(done) >= refill_at) break;
+                }
+            } else if (LOOP == 3) {
+                while (true) {
+                    if (STATS) {
+                        ++st_iters;
+                        st_busy += busy && (node != kDone || tri_cur < tri_end);
+                    }
+                    // one fetch per lane and iteration: the triangle's map or the node, into the same
+                    // registers, so the wavefront waits for memory once whichever work its lanes do
+                    const bool do_tri = busy && tri_cur < tri_end;
+                    const bool do_node = busy && !do_tri && node >= 0;
+                    // (lanes with neither load the root node, which every scene allocates, and ignore it)
+                    const char *base = do_tri ? reinterpret_cast<const char *>(S.tmap) + (uint32_t)tri_cur * 48u
+                                              : reinterpret_cast<const char *>(S.nodes) +
+                                                    (uint32_t)(do_node ? node : 0) * 64u;
+                    const float4 *q = reinterpret_cast<const float4 *>(base);
+                    const float4 w0 = q[0], w1 = q[1], w2 = q[2];
+                    const int2 w3 = *reinterpret_cast<const int2 *>(q + 3);  // the map array has 16 B of padding
+                    bool push = false, pop = false;
+                    int push_val = 0;
+                    if (do_tri) {
+                        if (STATS) ++st_tris;
+                        tri_test_rows(Rs, w0, w1, w2, S.tris, tri_cur, tbest, ibest, front);
+                        ++tri_cur;
+                    } else if (do_node) {
+                        if (STATS) ++st_nodes;
+                        const int4 m = make_int4(w3.x, w3.y, 0, 0);
+                        node_step_regs(Rs, w0, w1, w2, m, node, tbest, tri_cur, tri_end, push, push_val, pop);
+                    } else if (busy && node != kDone) {
+                        tri_cur = leaf_first(node);
+                        tri_end = tri_cur + leaf_count(node);
+                        pop = true;
+                    }
+                    if (push) stack_push<SL>(stride, sp, stk, spill, push_val);
+                    if (pop) node = stack_pop<SL>(stride, sp, stk, spill);
+                    const uint64_t done = __ballot(!busy || (node == kDone && tri_cur >= tri_end));
                     if (__popcll(done) >= refill_at) break;
                 }
             } else if (LOOP == 2) {
@@ -906,7 +956,7 @@ __global__ void __launch_bounds__(256) trace_backward_kernel(const float *__rest
 
 // ------------------------------------------------------------- launch ----
 
-static rtsdf_trace_tuning g_tuning = {16, 0, 0, 1, 1, 12};
+static rtsdf_trace_tuning g_tuning = {16, 0, 0, 3, 1, 12};
 constexpr int kMaxBlocksPerCu = 8;  // persistent workgroups per CU (spill area sized for this)
 constexpr int kMinShortStack = 12;  // smallest LDS stack part (spill area sized for this)
 
@@ -941,7 +991,8 @@ static int launch_trace3(const TraceArgs &A, hipStream_t s)
     switch (g_tuning.loop) {
     case 0: return launch_trace4<SL, REFILL, 0, BATCHED>(A, s);
     case 1: return launch_trace4<SL, REFILL, 1, BATCHED>(A, s);
-    default: return launch_trace4<SL, REFILL, 2, BATCHED>(A, s);
+    case 2: return launch_trace4<SL, REFILL, 2, BATCHED>(A, s);
+    default: return launch_trace4<SL, REFILL, 3, BATCHED>(A, s);
     }
 }
 
@@ -987,7 +1038,7 @@ extern "C" int rtsdf_trace_config(const rtsdf_trace_tuning *t)
     if (!t) return RTSDF_EINVAL;
     if (t->refill != 8 && t->refill != 16) return RTSDF_EINVAL;
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return RTSDF_EINVAL;
-    if (t->stats < 0 || t->stats > 1 || t->loop < 0 || t->loop > 2) return RTSDF_EINVAL;
+    if (t->stats < 0 || t->stats > 1 || t->loop < 0 || t->loop > 3) return RTSDF_EINVAL;
     if (t->bin_directions < 0 || t->bin_directions > 1) return RTSDF_EINVAL;
     if (t->stack_lds != 12 && t->stack_lds != 16 && t->stack_lds != 24) return RTSDF_EINVAL;
     rtsdf::g_tuning = *t;

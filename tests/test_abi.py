@@ -73,7 +73,7 @@ def test_host_validation(R):
                                     dummy, dummy, None) == R.EINVAL
     ld = (C.c_float * 3)(0, 1, 0)
     assert L.rtsdf_shadow(fine, dummy, dummy, 4, ld, 8.0, 0.0, 16, 0.1, 1.0, dummy, None) == R.EINVAL  # eps 0
-    for bad in (dict(refill=3), dict(loop=3), dict(stack_lds=20), dict(bin_directions=5), dict(blocks_per_cu=-1)):
+    for bad in (dict(refill=3), dict(loop=4), dict(stack_lds=20), dict(bin_directions=5), dict(blocks_per_cu=-1)):
         t = R.TraceTuning(**{**R.rtsdf_trace_config_get().as_dict(), **bad})
         assert L.rtsdf_trace_config(C.byref(t)) == R.EINVAL
     assert L.rtsdf_trace_config(None) == R.EINVAL

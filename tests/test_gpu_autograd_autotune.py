@@ -95,7 +95,7 @@ def test_autotune_applies_valid_tuning_and_keeps_results(R, tmp_path):
         for f in range(3):
             ref.step(f)
         p = pipe(w)
-        space = {"refill": (8, 16), "stack_lds": (12, 24), "bin_directions": (0, 1), "loop": (1,),
+        space = {"refill": (8, 16), "stack_lds": (12, 24), "bin_directions": (0, 1), "loop": (3,),
                  "blocks_per_cu": (0,)}
         cache = str(tmp_path / "tune.json")
         res = autotune.tune(p, reps=1, space=space, cache=cache)

@@ -291,7 +291,7 @@ def test_trace_tunings_agree_bitwise(R, case):
     w = workload(case)
     frames = range(3) if case == "tiny" else range(1)
     default = R.rtsdf_trace_config_get().as_dict()
-    settings = [dict(loop=0), dict(loop=2), dict(loop=2, refill=8), dict(loop=1, stack_lds=24),
+    settings = [dict(loop=0), dict(loop=1), dict(loop=2), dict(loop=3, refill=8), dict(loop=1, stack_lds=24),
                 dict(loop=2, stack_lds=16, bin_directions=0), dict(loop=2, blocks_per_cu=2)]
     try:
         say("tunings", case, "default", default)
