@@ -256,7 +256,7 @@ def main():
                         "rays_counted": ctr[2], "wave_iterations": ctr[3] // 64, "refill_rounds": ctr[4] // 64,
                         "tiles": ctr[6] // 64,
                         "lane_work_fraction": round(ctr[5] / max(ctr[3], 1), 4) if tuning["loop"] >= 1 else None,
-                        "bvh_nodes": info.nodes, "bvh_max_depth": info.max_depth,
+                        "bvh_nodes": info.nodes, "bvh_references": info.references, "bvh_max_depth": info.max_depth,
                         "bvh_max_leaf": info.leaf_size, "leaf_size": args.leaf_size},
         "trace_tuning": tuning,
         "roofline": {

@@ -170,8 +170,9 @@ typedef struct rtsdf_scene_info {
     int32_t nv, nt;
     int32_t nodes;      /* internal nodes of the hierarchy */
     int32_t max_depth;  /* deepest leaf (root = 0) */
-    int32_t leaf_size;  /* largest triangle count in a leaf */
+    int32_t leaf_size;  /* largest reference count in a leaf */
     int64_t device_bytes;
+    int32_t references; /* triangle references in the leaves (>= nt: large triangles are split into pieces) */
 } rtsdf_scene_info;
 
 int rtsdf_scene_create(const float *vertices, int32_t nv, const int32_t *faces, int32_t nt,

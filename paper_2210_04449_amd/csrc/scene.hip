@@ -11,7 +11,9 @@
 //     meta = (child0, child1, parent, 0)
 //   child >= 0 is an internal node, child < 0 a leaf: -1 - (first << 5 | count)
 //   with `count` triangles starting at `first` in the reordered triangle array.
-//   triangle (48 B): (v0, id) (v1, -) (v2, -) as float4s, in leaf order.
+//   triangle (48 B): (v0, id) (v1, path) (v2, -) as float4s, one per
+//     reference, in leaf order; path = levels << 24 | (2-bit piece per level,
+//     level 0 lowest), 0 for an unsplit triangle.
 //   triangle map (48 B, same order): rows r0, r1, r2 of the affine map that
 //     takes v0, v1, v2 to (0,0,0), (1,0,0), (0,1,0) and v0 + n to (0,0,1),
 //     n = (v1 - v0) x (v2 - v0); a point p maps to (r_k . (p, 1))_k, so for a
@@ -21,8 +23,18 @@
 //     creation and at every refit); degenerate triangles get a map no ray hits.
 //
 // Build (host, at creation): binned surface-area heuristic (32 bins per axis),
-// leaves of at most `leaf_size` triangles, depth capped (median splits below
+// leaves of at most `leaf_size` references, depth capped (median splits below
 // kMaxBuildDepth) so the traversal stack of the tracer never overflows.
+// Large triangles are split into several *references* before the build (the
+// early-split idea of Ernst and Greiner 2007): a triangle whose longest edge
+// exceeds 1/16 of the scene size is subdivided at edge midpoints, recursively,
+// and each piece becomes a reference with the piece's tight box that points at
+// the whole original triangle.  Long thin boxes of big triangles otherwise
+// inflate every node above them.  Leaves store one triangle record per
+// reference (the same triangle can sit in several leaves; the closest hit is
+// the same whichever copy reports it), and the record keeps the piece's
+// subdivision path so a refit can recompute the piece's box from moved
+// vertices.
 // Boxes are padded outwards by 2^-17 * (scene scale) so the float slab test,
 // whose rounding error is far below that, never rejects a box the ray enters.
 // Refit (device): triangle records rewritten from new positions, boxes
@@ -59,9 +71,10 @@ struct rtsdf_scene {
     float pad = 0.f;
     int device = 0;
     rtsdf::BvhNode *nodes = nullptr;   // [nnodes]
-    float4 *tris = nullptr;            // [3 nt]
-    float4 *tmap = nullptr;            // [3 nt + 1] triangle-space maps, leaf order (+ 16 B padding)
-    int4 *leaf_faces = nullptr;        // [nt] (i0, i1, i2, original id) in leaf order
+    int nref = 0;                      // triangle references (>= nt: large triangles are split)
+    float4 *tris = nullptr;            // [3 nref]
+    float4 *tmap = nullptr;            // [3 nref + 1] triangle-space maps, leaf order (+ 16 B padding)
+    int4 *leaf_faces = nullptr;        // [nref] (i0, i1, i2, original id) in leaf order
     float *vertices = nullptr;         // [3 nv] current positions
     int32_t *faces = nullptr;          // [3 nt]
     int32_t *refit_counter = nullptr;  // [nnodes]
@@ -73,6 +86,31 @@ struct rtsdf_scene {
 };
 
 namespace rtsdf {
+
+constexpr int kMaxSplitLevels = 12;
+
+// piece k of the midpoint subdivision of (a, b, c): 0 (a, ab, ca), 1 (ab, b, bc), 2 (ca, bc, c), 3 (ab, bc, ca)
+template <typename T>
+__host__ __device__ __forceinline__ void split_piece(T a[3], T b[3], T c[3], int k)
+{
+    for (int i = 0; i < 3; ++i) {
+        const T ab = (a[i] + b[i]) * (T)0.5, bc = (b[i] + c[i]) * (T)0.5, ca = (c[i] + a[i]) * (T)0.5;
+        switch (k) {
+        case 0: b[i] = ab; c[i] = ca; break;
+        case 1: a[i] = ab; c[i] = bc; break;
+        case 2: a[i] = ca; b[i] = bc; break;
+        default: a[i] = ab; b[i] = bc; c[i] = ca; break;
+        }
+    }
+}
+
+// the piece of (a, b, c) a path code names
+template <typename T>
+__host__ __device__ __forceinline__ void follow_path(T a[3], T b[3], T c[3], int path)
+{
+    const int levels = (path >> 24) & 15;
+    for (int l = 0; l < levels; ++l) split_piece(a, b, c, (path >> (2 * l)) & 3);
+}
 
 namespace {
 
@@ -242,19 +280,98 @@ struct HostBuilder {
     }
 };
 
+// References of the triangles (see the header comment): pieces of midpoint
+// subdivision until the longest edge is at most 1/16 of the scene's largest
+// extent; the length doubles while the count would exceed 3 nt + 1024.
+void make_references(const std::vector<float> &hv, const std::vector<int32_t> &hf, int nt, std::vector<Aabb> &boxes,
+                     std::vector<int32_t> &ref_tri, std::vector<int32_t> &ref_path)
+{
+    boxes.clear();
+    ref_tri.clear();
+    ref_path.clear();
+    if (nt <= 0) return;
+    double slo[3] = {INFINITY, INFINITY, INFINITY}, shi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = 0; i < 3 * nt; ++i)
+        for (int a = 0; a < 3; ++a) {
+            slo[a] = std::min(slo[a], (double)hv[3 * hf[i] + a]);
+            shi[a] = std::max(shi[a], (double)hv[3 * hf[i] + a]);
+        }
+    const double extent = std::max(shi[0] - slo[0], std::max(shi[1] - slo[1], shi[2] - slo[2]));
+    const size_t cap = (size_t)std::min<int64_t>(3LL * nt + 1024, (1LL << 26) - 1);
+    struct Piece {
+        double a[3], b[3], c[3];
+        int level, path;
+    };
+    std::vector<Piece> stack;
+    for (double len = extent / 16.0;; len *= 2.0) {
+        boxes.clear();
+        ref_tri.clear();
+        ref_path.clear();
+        bool over = false;
+        for (int t = 0; t < nt && !over; ++t) {
+            Piece p0;
+            for (int a = 0; a < 3; ++a) {
+                p0.a[a] = hv[3 * hf[3 * t] + a];
+                p0.b[a] = hv[3 * hf[3 * t + 1] + a];
+                p0.c[a] = hv[3 * hf[3 * t + 2] + a];
+            }
+            p0.level = 0;
+            p0.path = 0;
+            stack.assign(1, p0);
+            while (!stack.empty()) {
+                const Piece p = stack.back();
+                stack.pop_back();
+                double e = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    e = std::max(e, std::fabs(p.a[a] - p.b[a]));
+                    e = std::max(e, std::fabs(p.b[a] - p.c[a]));
+                    e = std::max(e, std::fabs(p.c[a] - p.a[a]));
+                }
+                if (p.level < kMaxSplitLevels && e > len) {
+                    for (int k = 0; k < 4; ++k) {
+                        Piece q = p;
+                        split_piece(q.a, q.b, q.c, k);
+                        q.level = p.level + 1;
+                        q.path = p.path | (k << (2 * p.level));
+                        stack.push_back(q);
+                    }
+                    continue;
+                }
+                Aabb box;
+                for (int a = 0; a < 3; ++a) {  // float box rounded outwards
+                    const double l = std::min(p.a[a], std::min(p.b[a], p.c[a]));
+                    const double h = std::max(p.a[a], std::max(p.b[a], p.c[a]));
+                    float lf = (float)l, hf2 = (float)h;
+                    if ((double)lf > l) lf = std::nextafter(lf, -INFINITY);
+                    if ((double)hf2 < h) hf2 = std::nextafter(hf2, INFINITY);
+                    box.lo[a] = lf;
+                    box.hi[a] = hf2;
+                }
+                boxes.push_back(box);
+                ref_tri.push_back(t);
+                ref_path.push_back(p.level ? (p.level << 24) | p.path : 0);
+            }
+            over = ref_tri.size() > cap;
+        }
+        if (!over || len > 4.0 * extent) break;  // past 2 x extent nothing splits, so the loop ends
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- refit ----
 
-__global__ void refit_tris(const float *__restrict__ v, const int4 *__restrict__ lf, float4 *__restrict__ tris, int nt)
+// records rewritten from the new positions (id and subdivision path kept)
+__global__ void refit_tris(const float *__restrict__ v, const int4 *__restrict__ lf, float4 *__restrict__ tris, int nref)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nt) return;
+    if (i >= nref) return;
     const int4 q = lf[i];
+    const float path = tris[3 * i + 1].w;
     const int ids[3] = {q.x, q.y, q.z};
     for (int k = 0; k < 3; ++k) {
         const float *p = v + 3 * ids[k];
-        tris[3 * i + k] = make_float4(p[0], p[1], p[2], k == 0 ? __int_as_float(q.w) : 0.f);
+        tris[3 * i + k] = make_float4(p[0], p[1], p[2], k == 0 ? __int_as_float(q.w) : (k == 1 ? path : 0.f));
     }
 }
 
@@ -294,13 +411,15 @@ __device__ __forceinline__ void leaf_box(const float4 *__restrict__ tris, int co
         hi[a] = -INFINITY;
     }
     const int first = leaf_first(code), cnt = leaf_count(code);
-    for (int i = first; i < first + cnt; ++i)
-        for (int k = 0; k < 3; ++k) {
-            const float4 p = tris[3 * i + k];
-            lo[0] = fminf(lo[0], p.x); hi[0] = fmaxf(hi[0], p.x);
-            lo[1] = fminf(lo[1], p.y); hi[1] = fmaxf(hi[1], p.y);
-            lo[2] = fminf(lo[2], p.z); hi[2] = fmaxf(hi[2], p.z);
+    for (int i = first; i < first + cnt; ++i) {
+        const float4 pa = tris[3 * i], pb = tris[3 * i + 1], pc = tris[3 * i + 2];
+        float a[3] = {pa.x, pa.y, pa.z}, b[3] = {pb.x, pb.y, pb.z}, c[3] = {pc.x, pc.y, pc.z};
+        follow_path(a, b, c, __float_as_int(pb.w));  // the reference's piece (rounding << pad)
+        for (int ax = 0; ax < 3; ++ax) {
+            lo[ax] = fminf(lo[ax], fminf(a[ax], fminf(b[ax], c[ax])));
+            hi[ax] = fmaxf(hi[ax], fmaxf(a[ax], fmaxf(b[ax], c[ax])));
         }
+    }
     for (int a = 0; a < 3; ++a) {
         lo[a] = nextafterf(lo[a] - pad, -INFINITY);
         hi[a] = nextafterf(hi[a] + pad, INFINITY);
@@ -395,22 +514,22 @@ static int rtsdf_scene_create_impl(const float *vertices, int32_t nv, const int3
         scale = std::max(scale, std::fabs(x));
     }
     HostBuilder B{hv.data(), hf.data(), nt, leaf_size, std::ldexp(scale, -17), {}, {}, {}, {}};
-    B.tb.resize(nt);
-    B.cen.resize((size_t)3 * nt);
-    B.idx.resize(nt);
-    for (int t = 0; t < nt; ++t) {
-        B.tb[t].reset();
-        for (int k = 0; k < 3; ++k) B.tb[t].grow_pt(&hv[3 * hf[3 * t + k]]);
-        for (int a = 0; a < 3; ++a) B.cen[3 * t + a] = 0.5f * (B.tb[t].lo[a] + B.tb[t].hi[a]);
-        B.idx[t] = t;
+    std::vector<int32_t> ref_tri, ref_path;
+    make_references(hv, hf, nt, B.tb, ref_tri, ref_path);
+    const int nref = (int)ref_tri.size();
+    B.cen.resize((size_t)3 * nref);
+    B.idx.resize(nref);
+    for (int r = 0; r < nref; ++r) {
+        for (int a = 0; a < 3; ++a) B.cen[3 * r + a] = 0.5f * (B.tb[r].lo[a] + B.tb[r].hi[a]);
+        B.idx[r] = r;
     }
-    if (nt > 0) {
-        const int code = B.build(0, nt, 0);  // an internal root is node 0
+    if (nref > 0) {
+        const int code = B.build(0, nref, 0);  // an internal root is node 0
         if (code < 0) {
             // the whole mesh is one leaf: a root holding it and an empty leaf
             B.nodes.emplace_back();
             float lo[3], hi[3];
-            B.padded(B.range_box(0, nt), lo, hi);
+            B.padded(B.range_box(0, nref), lo, hi);
             BvhNode &nd = B.nodes[0];
             nd.xy0 = nd.xy1 = make_float4(lo[0], hi[0], lo[1], hi[1]);
             nd.z01 = make_float4(lo[2], hi[2], lo[2], hi[2]);
@@ -421,20 +540,22 @@ static int rtsdf_scene_create_impl(const float *vertices, int32_t nv, const int3
     std::unique_ptr<rtsdf_scene> sc(new rtsdf_scene());
     sc->nv = nv;
     sc->nt = nt;
+    sc->nref = nref;
     sc->nnodes = (int)B.nodes.size();
     sc->max_depth = B.max_depth;
     sc->max_leaf = B.max_leaf;
     sc->pad = B.pad;
     RTSDF_TRY(hipGetDevice(&sc->device));
-    std::vector<float4> htri((size_t)3 * std::max(nt, 1));
-    std::vector<int4> hlf(std::max(nt, 1));
-    for (int i = 0; i < nt; ++i) {
-        const int t = B.idx[i];
+    std::vector<float4> htri((size_t)3 * std::max(nref, 1));
+    std::vector<int4> hlf(std::max(nref, 1));
+    for (int i = 0; i < nref; ++i) {
+        const int r = B.idx[i], t = ref_tri[r];
         for (int k = 0; k < 3; ++k) {
             const float *p = &hv[3 * hf[3 * t + k]];
-            float idf = 0.f;
-            if (k == 0) std::memcpy(&idf, &t, sizeof(float));
-            htri[3 * i + k] = make_float4(p[0], p[1], p[2], idf);
+            float w = 0.f;
+            if (k == 0) std::memcpy(&w, &t, sizeof(float));
+            if (k == 1) std::memcpy(&w, &ref_path[r], sizeof(float));
+            htri[3 * i + k] = make_float4(p[0], p[1], p[2], w);
         }
         hlf[i] = make_int4(hf[3 * t], hf[3 * t + 1], hf[3 * t + 2], t);
     }
@@ -467,8 +588,8 @@ static int rtsdf_scene_create_impl(const float *vertices, int32_t nv, const int3
     if (nt) ok &= hipMemcpyAsync(sc->faces, hf.data(), sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s) == hipSuccess;
     if (!starts.empty())
         ok &= hipMemcpyAsync(sc->start_nodes, starts.data(), sizeof(int32_t) * starts.size(), hipMemcpyHostToDevice, s) == hipSuccess;
-    if (ok && nt > 0) {
-        tri_maps<<<dim3((nt + 255) / 256), dim3(256), 0, s>>>(sc->tris, sc->tmap, nt);
+    if (ok && nref > 0) {
+        tri_maps<<<dim3((nref + 255) / 256), dim3(256), 0, s>>>(sc->tris, sc->tmap, nref);
         ok &= hipGetLastError() == hipSuccess;
     }
     ok &= hipStreamSynchronize(s) == hipSuccess;
@@ -506,10 +627,11 @@ extern "C" int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsd
     hipStream_t s = as_stream(stream);
     if (scene->nv > 0 && vertices != scene->vertices)
         RTSDF_TRY(hipMemcpyAsync(scene->vertices, vertices, sizeof(float) * 3 * scene->nv, hipMemcpyDeviceToDevice, s));
-    if (scene->nt == 0) return RTSDF_OK;
-    refit_tris<<<dim3((scene->nt + 255) / 256), dim3(256), 0, s>>>(scene->vertices, scene->leaf_faces, scene->tris, scene->nt);
+    if (scene->nref == 0) return RTSDF_OK;
+    refit_tris<<<dim3((scene->nref + 255) / 256), dim3(256), 0, s>>>(scene->vertices, scene->leaf_faces, scene->tris,
+                                                                      scene->nref);
     RTSDF_CHECK_LAUNCH();
-    tri_maps<<<dim3((scene->nt + 255) / 256), dim3(256), 0, s>>>(scene->tris, scene->tmap, scene->nt);
+    tri_maps<<<dim3((scene->nref + 255) / 256), dim3(256), 0, s>>>(scene->tris, scene->tmap, scene->nref);
     RTSDF_CHECK_LAUNCH();
     int rc = launch_fill<int32_t>(scene->refit_counter, 0, scene->nnodes, s);
     if (rc != RTSDF_OK) return rc;
@@ -524,6 +646,7 @@ extern "C" int rtsdf_scene_info_get(const rtsdf_scene *scene, rtsdf_scene_info *
     if (!scene || !info) return RTSDF_EINVAL;
     info->nv = scene->nv;
     info->nt = scene->nt;
+    info->references = scene->nref;
     info->nodes = scene->nnodes;
     info->max_depth = scene->max_depth;
     info->leaf_size = scene->max_leaf;

@@ -70,7 +70,7 @@ class TraceTuning(C.Structure):
 
 class SceneInfo(C.Structure):
     _fields_ = [("nv", _i32), ("nt", _i32), ("nodes", _i32), ("max_depth", _i32), ("leaf_size", _i32),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("references", _i32)]
 
 
 class RtsdfError(RuntimeError):

@@ -89,7 +89,7 @@ def test_struct_layouts_match_header(R, tmp_path):
     structs = {
         "rtsdf_grid": (R.Grid, ["lo", "h", "n"]),
         "rtsdf_accum": (R.Accum, ["u", "hits", "arg_tri", "arg_ray"]),
-        "rtsdf_scene_info": (R.SceneInfo, ["nv", "nt", "nodes", "max_depth", "leaf_size", "device_bytes"]),
+        "rtsdf_scene_info": (R.SceneInfo, ["nv", "nt", "nodes", "max_depth", "leaf_size", "device_bytes", "references"]),
         "rtsdf_trace_tuning": (R.TraceTuning, ["refill", "blocks_per_cu", "stats", "loop", "bin_directions",
                                                "stack_lds"]),
         "rtsdf_frame_desc": (R.FrameDesc, [f for f, _ in R.FrameDesc._fields_]),
