@@ -213,7 +213,11 @@ void rtsdf_scene_destroy(rtsdf_scene *scene);
 /* frame_ptr  optional device uint32: if non-NULL the frame index is read    */
 /*            from it at run time (for captured graphs) and `frame` is       */
 /*            ignored.                                                       */
-/* workspace  rtsdf_trace_workspace_size() bytes of device memory.           */
+/* workspace  rtsdf_trace_workspace_size() bytes of device memory: 256 B of  */
+/*            counters, then per-wavefront buffers holding the directions of */
+/*            the rays each persistent wavefront is tracing (~100 MB on a     */
+/*            256-CU device; the size is that of the current device).  Calls  */
+/*            that run concurrently need separate workspaces.                 */
 /* ------------------------------------------------------------------------ */
 typedef struct rtsdf_accum {
     float *u;

@@ -181,6 +181,7 @@ struct rtsdf_batch {
     int32_t *counts = nullptr;
     int32_t *tile_offset = nullptr;
     int32_t *cursor = nullptr;  // 16 words: cursor + instrumentation counters (64-bit, from word 2)
+    float4 *dirs = nullptr;     // the tracer's per-wavefront direction buffers
     int32_t *spill = nullptr;   // the deepest scene's spill area
     // tables
     rtsdf::BatchVox *vox = nullptr;
@@ -280,7 +281,8 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
         !batch_alloc(B, &B->u, F) || !batch_alloc(B, &B->hits, F) || !batch_alloc(B, &B->arg_tri, F) ||
         !batch_alloc(B, &B->arg_ray, F) || !batch_alloc(B, &B->fine_sdf, F) ||
         !batch_alloc(B, &B->sel_sums, sel_off[n]) || !batch_alloc(B, &B->counts, n) ||
-        !batch_alloc(B, &B->tile_offset, n + 1) || !batch_alloc(B, &B->cursor, 16) || !batch_alloc(B, &B->vox, n) ||
+        !batch_alloc(B, &B->tile_offset, n + 1) || !batch_alloc(B, &B->cursor, 16) ||
+        !batch_alloc(B, &B->dirs, (int64_t)(dirs_bytes() / sizeof(float4))) || !batch_alloc(B, &B->vox, n) ||
         !batch_alloc(B, &B->plan, (int64_t)(B->max_passes + 1) * n) || !batch_alloc(B, &B->sel, n) ||
         !batch_alloc(B, &B->fill, n) || !batch_alloc(B, &B->trace, n))
         return fail(RTSDF_ENOMEM);
@@ -453,6 +455,7 @@ extern "C" int rtsdf_batch_step(rtsdf_batch *B, uint32_t frame, const uint32_t *
     A.seed = B->seed;
     A.spill = B->spill;
     A.bin_directions = g_tuning.bin_directions;
+    A.dirs = B->dirs;
     return launch_trace<true>(A, s);
 }
 

@@ -22,12 +22,12 @@
 //     Computed in double precision from the float vertices on the device (at
 //     creation and at every refit); degenerate triangles get a map no ray hits.
 //
-// Build (host, at creation): binned surface-area heuristic (32 bins per axis),
+// Build (host, at creation): binned surface-area heuristic (64 bins per axis),
 // leaves of at most `leaf_size` references, depth capped (median splits below
 // kMaxBuildDepth) so the traversal stack of the tracer never overflows.
 // Large triangles are split into several *references* before the build (the
 // early-split idea of Ernst and Greiner 2007): a triangle whose longest edge
-// exceeds 1/16 of the scene size is subdivided at edge midpoints, recursively,
+// exceeds 1/32 of the scene size is subdivided at edge midpoints, recursively,
 // and each piece becomes a reference with the piece's tight box that points at
 // the whole original triangle.  Long thin boxes of big triangles otherwise
 // inflate every node above them.  Leaves store one triangle record per
@@ -199,7 +199,7 @@ struct HostBuilder {
             });
             return build_split(b, e, mid, depth);
         }
-        constexpr int NB = 32;
+        constexpr int NB = 64;
         double best_cost = INFINITY;
         int best_axis = -1, best_bin = -1;
         for (int a = 0; a < 3; ++a) {
@@ -281,7 +281,7 @@ struct HostBuilder {
 };
 
 // References of the triangles (see the header comment): pieces of midpoint
-// subdivision until the longest edge is at most 1/16 of the scene's largest
+// subdivision until the longest edge is at most 1/32 of the scene's largest
 // extent; the length doubles while the count would exceed 3 nt + 1024.
 void make_references(const std::vector<float> &hv, const std::vector<int32_t> &hf, int nt, std::vector<Aabb> &boxes,
                      std::vector<int32_t> &ref_tri, std::vector<int32_t> &ref_path)
@@ -303,7 +303,7 @@ void make_references(const std::vector<float> &hv, const std::vector<int32_t> &h
         int level, path;
     };
     std::vector<Piece> stack;
-    for (double len = extent / 16.0;; len *= 2.0) {
+    for (double len = extent / 32.0;; len *= 2.0) {
         boxes.clear();
         ref_tri.clear();
         ref_path.clear();

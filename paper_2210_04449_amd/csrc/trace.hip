@@ -316,6 +316,7 @@ struct TraceArgs {
     int32_t *spill;              // deep stack entries: [(depth - SL) * spill_stride + lane]
     int spill_stride;            // lanes in the launch
     int bin_directions;          // sort each tile's rays by direction bin
+    float4 *dirs;                // per wavefront: kTileRays directions of its current tile
 };
 
 constexpr int kTraceWaves = 4;
@@ -528,10 +529,11 @@ trace_persistent(TraceArgs A)
     uint32_t st_nodes = 0, st_tris = 0, st_rays = 0, st_iters = 0, st_refills = 0, st_busy = 0, st_tiles = 0;
     __shared__ int stack_mem[kTraceWaves * SL * kWave];
     __shared__ WaveTile tiles[kTraceWaves];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     lds_int *stk = (lds_int *)(stack_mem + wave * SL * kWave + lane);
     WaveTile &T = tiles[wave];
     int32_t *spill = A.spill + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float4 *dirs = A.dirs + ((int64_t)blockIdx.x * kTraceWaves + wave) * kTileRays;
     const int stride = A.spill_stride;
     const uint32_t frame = A.frame_ptr ? *A.frame_ptr : A.frame;
     const int single_tiles = BATCHED ? 0 : scene_tiles(A.one);
@@ -556,6 +558,9 @@ trace_persistent(TraceArgs A)
         const TraceScene &P = BATCHED ? A.scenes[s] : A.one;
         if (STATS) ++st_tiles;
         const int R = P.rays;
+        // q / R as a multiply-high: exact for q < kTileRays and R <= 64 (the error of the rounded-up
+        // reciprocal, q / 2^32, stays below the distance 1/R of q / R from the next integer)
+        const uint32_t rdiv = R > 1 ? (uint32_t)(((1ull << 32) + (uint64_t)R - 1) / (uint64_t)R) : 0u;
         const int nfm = P.nf - 1;
         const int tile_texels = tile_texels_for(R);
         const int total = min(*P.count, P.queue_cap);
@@ -576,15 +581,19 @@ trace_persistent(TraceArgs A)
         // ---- bin the tile's rays by direction
 #pragma unroll 1
         for (int q = lane; q < nrays; q += kWave) {
-            const int slot = q / R, r = q - slot * R;
+            const int slot = R > 1 ? (int)__umulhi((uint32_t)q, rdiv) : q, r = q - slot * R;
             const int j = T.tex[slot];
             int b = 0;
-            if (j >= 0 && A.bin_directions)
-                b = direction_bin(sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, P.scene_id));
+            if (j >= 0) {
+                // drawn once at full width; the lane that later takes the ray reads it back
+                const float3 d = sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, P.scene_id);
+                dirs[q] = make_float4(d.x, d.y, d.z, 0.0f);
+                if (A.bin_directions) b = direction_bin(d);
+            }
             T.sort.binof[q] = (uint8_t)b;
             atomicAdd(&T.sort.bin[b], 1u);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");  // also orders the stored directions
         __builtin_amdgcn_wave_barrier();
         {  // exclusive scan of the 64 bin counts, one per lane
             const uint32_t c = T.sort.bin[lane];
@@ -626,14 +635,14 @@ trace_persistent(TraceArgs A)
                 const int take = min(__popcll(need), nrays - pool);
                 if (!busy && rank < take) {
                     const int q = T.perm[pool + rank];
-                    slot = q / R;
+                    slot = R > 1 ? (int)__umulhi((uint32_t)q, rdiv) : q;
                     r = q - slot * R;
                     const int j = T.tex[slot];
                     if (j >= 0) {
                         const float ox = texel_coord(P.lox, j & nfm, P.hf);
                         const float oy = texel_coord(P.loy, (j >> P.lognf) & nfm, P.hf);
                         const float oz = texel_coord(P.loz, j >> (2 * P.lognf), P.hf);
-                        const float3 d = sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, P.scene_id);
+                        const float4 d = dirs[q];
                         ray_setup(ox, oy, oz, d.x, d.y, d.z, Rs);
                         node = scene_nt > 0 ? 0 : kDone;
                     } else {
@@ -1031,6 +1040,12 @@ static int ensure_spill(rtsdf_scene *sc)
     return RTSDF_OK;
 }
 
+// trace workspace: 256 B of counters, then the wavefronts' direction buffers
+static size_t dirs_bytes()
+{
+    return (size_t)num_cus() * kMaxBlocksPerCu * kTraceWaves * kTileRays * sizeof(float4);
+}
+
 }  // namespace rtsdf
 
 extern "C" int rtsdf_trace_config(const rtsdf_trace_tuning *t)
@@ -1063,7 +1078,7 @@ extern "C" int rtsdf_accum_reset(rtsdf_grid fine, rtsdf_accum st, rtsdf_stream s
     return RTSDF_OK;
 }
 
-extern "C" size_t rtsdf_trace_workspace_size(void) { return 256; }
+extern "C" size_t rtsdf_trace_workspace_size(void) { return 256 + rtsdf::dirs_bytes(); }
 
 extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const float *coarse_sdf,
                                       rtsdf_grid fine, const uint8_t *mask, const int32_t *queue, const int32_t *count,
@@ -1129,6 +1144,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     A.spill = scene->spill;
     A.spill_stride = 0;
     A.bin_directions = g_tuning.bin_directions;
+    A.dirs = reinterpret_cast<float4 *>(static_cast<char *>(workspace) + 256);
     return launch_trace<false>(A, s);
 }
 
