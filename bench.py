@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic VALU lane-operations of the tracer:
 OPS_NODE = 39   # one two-child node: 2 x (6 slab FMAs + 12 min/max + 1 compare) + ordering
-OPS_TRI = 50    # watertight test: 27 FMAs ray-space map + 6 edge fns + tests, det, T, 1/det, t
+OPS_TRI = 33    # triangle-frame test: 18 FMAs (plane + 2 barycentric rows), 1/q, t, 2 barycentrics, margin, compares
 OPS_RAY = 360   # Philox4x64-10 (10 rounds), Marsaglia mapping, ray set-up, accumulation
 
 
