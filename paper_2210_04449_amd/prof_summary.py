@@ -10,14 +10,14 @@ by what the same counter reads for the device-to-device copy of a known size
 that ``bench.py --calibrate-copy`` performs first (256 MiB read, 256 MiB
 written; the copy runs as ``__amd_rocclr_copyBuffer``, and it is the largest
 dispatch of that kernel in the run).  The summary records the hash of the
-library's kernel sources it was measured on (``source_hash``), so a reader can
-tell whether the counters still describe the current kernels.
+tracer's sources it was measured on (``source_hash``: the tracer kernel, the
+scene layout it reads and the shared helpers), so a reader can tell whether
+the counters still describe the current tracer.
 """
 from __future__ import annotations
 
 import collections
 import csv
-import glob
 import hashlib
 import os
 import sys
@@ -26,13 +26,16 @@ COPY_BYTES = 256 << 20
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 
-def source_hash() -> str:
-    """sha256 over the library's kernel sources (file names and contents, sorted by name)."""
+# sources that determine the tracer's memory traffic: the kernel, the scene layout it reads, shared helpers
+TRACER_SOURCES = ("common.hpp", "scene.hip", "trace.hip")
+
+
+def source_hash(files=TRACER_SOURCES) -> str:
+    """sha256 over the named kernel sources (file names and contents)."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
-        if f.endswith((".hip", ".hpp", ".h")):
-            h.update(os.path.basename(f).encode())
-            h.update(open(f, "rb").read())
+    for name in sorted(files):
+        h.update(name.encode())
+        h.update(open(os.path.join(CSRC, name), "rb").read())
     return h.hexdigest()[:16]
 
 
