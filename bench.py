@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--bin", type=int, default=1, choices=[0, 1])
     ap.add_argument("--stack-lds", type=int, default=12, choices=[12, 16, 24])
     ap.add_argument("--leaf-size", type=int, default=2)
+    ap.add_argument("--jfa", default="jfa", choices=["jfa", "jfa+1", "jfa+2", "1+jfa"],
+                    help="jump-flooding pass schedule (the extra-pass variants reduce its errors)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (scale for HBM byte counters)")
     return ap.parse_args()
@@ -130,7 +132,8 @@ def main():
         del a, b
     R.rtsdf_trace_config(**tuning)
     p = Pipeline(torch.from_numpy(w.mesh.vertices).to(dev), torch.from_numpy(w.mesh.faces).to(dev), w.nc, w.nf,
-                 w.beta, w.d, w.rays, seed=0, scene_id=w.scene_seed, alpha=w.alpha, leaf_size=args.leaf_size)
+                 w.beta, w.d, w.rays, seed=0, scene_id=w.scene_seed, alpha=w.alpha, leaf_size=args.leaf_size,
+                 jfa_variant=args.jfa)
     info = p.scene.info()
     stream = torch.cuda.current_stream()
     dyn_frames = None
@@ -219,7 +222,8 @@ def main():
 
     n3 = w.nc ** 3
     import math
-    jfa_bytes = 8 * n3 * int(math.log2(w.nc)) + 12 * n3
+    jfa_passes = len(p.jfa_steps) if p.jfa_steps else int(math.log2(w.nc))
+    jfa_bytes = 8 * n3 * jfa_passes + 12 * n3
     jfa_gbs = jfa_bytes / (stage["jfa"] / 1e3) / 1e9
 
     out = {
@@ -251,7 +255,7 @@ def main():
         "rays_per_step": rays,
         "rays_per_s": round(rays / trace_s, 1),
         "jfa": {"gbps": round(jfa_gbs, 1), "frac_hbm": round(jfa_gbs / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes": jfa_bytes},
+                "algorithmic_bytes": jfa_bytes, "schedule": args.jfa},
         "trace_stats": {"nodes_per_ray": round(nodes_per_ray, 2), "tris_per_ray": round(tris_per_ray, 2),
                         "rays_counted": ctr[2], "wave_iterations": ctr[3] // 64, "refill_rounds": ctr[4] // 64,
                         "tiles": ctr[6] // 64,

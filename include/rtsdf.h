@@ -135,6 +135,18 @@ int rtsdf_voxelize(const float *vertices, int32_t nv, const int32_t *faces, int3
 int rtsdf_jfa(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, float beta,
               int32_t *dist2, float *coarse_sdf, rtsdf_stream stream);
 
+/* The same with a caller-chosen pass schedule: steps (host, [nsteps]) lists
+ * the step of every pass in order; each step a power of two in [1, n/2], the
+ * last one 1, 1 <= nsteps <= 64.  Besides n/2, ..., 1 this runs the
+ * error-reducing variants of jump flooding (Rong and Tan 2006, the method
+ * Sec. 2.1 builds on): "JFA+1" (n/2, ..., 1, 1), "JFA+2" (n/2, ..., 1, 2, 1)
+ * and "1+JFA" (1, n/2, ..., 1).  Extra passes never increase a voxel's
+ * distance.  Other arguments as rtsdf_jfa; rtsdf_jfa is this call with
+ * n/2, ..., 1.  Schedules whose brick passes would end in the wrong buffer
+ * add one device-to-device copy of n^3 int32. */
+int rtsdf_jfa_steps(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, const int32_t *steps, int32_t nsteps,
+                    float beta, int32_t *dist2, float *coarse_sdf, rtsdf_stream stream);
+
 /* ------------------------------------------------------------------------ */
 /* 3. Selection (Sec. 2.2; the case c <= d of Eq. (1)).                      */
 /*                                                                           */

@@ -49,6 +49,7 @@ def lib():
         L.oracle_voxelize.argtypes = [P, i32, P, i32, P, f32, i32, P]
         L.oracle_jfa_pass.argtypes = [i32, i32, P, P]
         L.oracle_jfa.argtypes = [i32, P, P]
+        L.oracle_jfa_steps.argtypes = [i32, P, P, i32, P]
         L.oracle_coarse.argtypes = [i32, P, f32, f32, P, P]
         L.oracle_select_threshold.argtypes = [f32, f32, f32]
         L.oracle_select.argtypes = [i32, P, i32, i32, P, P, i32, P]
@@ -109,6 +110,16 @@ def jfa(n: int, seeds: np.ndarray) -> np.ndarray:
     out = np.empty_like(s)
     if lib().oracle_jfa(int(n), _p(s), _p(out)) != 0:
         raise ValueError("oracle_jfa: n must be a power of two")
+    return out
+
+
+def jfa_steps(n: int, seeds: np.ndarray, steps) -> np.ndarray:
+    """Jump flooding with an explicit pass schedule (one oracle_jfa_pass per step, in order)."""
+    s = _c(seeds, np.int32)
+    st = np.ascontiguousarray(steps, np.int32)
+    out = np.empty_like(s)
+    if lib().oracle_jfa_steps(int(n), _p(s), _p(st), int(st.size), _p(out)) != 0:
+        raise ValueError("oracle_jfa_steps: bad schedule")
     return out
 
 

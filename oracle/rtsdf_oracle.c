@@ -200,6 +200,28 @@ void oracle_jfa_pass(int n, int k, const int *in, int *out)
     }
 }
 
+/* Jump flooding with an explicit pass schedule: the passes of oracle_jfa_pass
+ * with steps steps[0], steps[1], ... in order, each reading the previous
+ * pass's output (Sec. 2.1; the extra-pass variants JFA+1, JFA+2 and 1+JFA of
+ * Rong and Tan are schedules of this form). */
+int oracle_jfa_steps(int n, const int *seeds_in, const int *steps, int nsteps, int *seeds_out)
+{
+    if (n <= 0 || nsteps < 0) return ORC_EINVAL;
+    const size_t total = (size_t)n * n * n;
+    int *a = (int *)malloc(sizeof(int) * total), *b = (int *)malloc(sizeof(int) * total);
+    if (!a || !b) { free(a); free(b); return ORC_EINVAL; }
+    memcpy(a, seeds_in, sizeof(int) * total);
+    for (int i = 0; i < nsteps; ++i) {
+        if (steps[i] < 1) { free(a); free(b); return ORC_EINVAL; }
+        oracle_jfa_pass(n, steps[i], a, b);
+        int *t = a; a = b; b = t;
+    }
+    memcpy(seeds_out, a, sizeof(int) * total);
+    free(a);
+    free(b);
+    return ORC_OK;
+}
+
 int oracle_jfa(int n, const int *seeds_in, int *seeds_out)
 {
     if (n <= 0 || (n & (n - 1)) != 0) return ORC_EINVAL;

@@ -228,38 +228,44 @@ __global__ void __launch_bounds__(512) jfa_near(const int32_t *__restrict__ src,
 
 template <bool WIDE>
 static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float beta, int32_t *dist2, float *sdf,
-                   hipStream_t s)
+                   const int32_t *steps, int m, hipStream_t s)
 {
     const int n = g.n, logn = ilog2(n);
     const int64_t nvox = (int64_t)n * n * n;
-    const int nbrick_passes = logn - 1;  // steps n/2 .. 2; step 1 is the final pass
     const unsigned far_blocks = (unsigned)(nvox / 256);
     const unsigned near_blocks = (unsigned)(nvox / 512);
-    // Ping-pong so that the final pass reads `scratch` and writes `seeds`.
-    const int32_t *cur;
+    // Passes 0 .. m-2 go brick layout to brick layout, alternating buffers; the final pass (step 1) must read
+    // `scratch` and write the caller's linear layout to `seeds`.  A first far pass can read the linear input
+    // directly; otherwise the input is converted into `scratch` first, and copied once more when the number
+    // of brick passes would leave the last one in the wrong buffer.
+    const int npass = m - 1;
+    const bool linear_first = npass >= 1 && steps[0] >= 4 && npass % 2 == 1;
+    const int32_t *cur = seeds;
     int32_t *bufs[2] = {seeds, scratch};
-    int next;  // index into bufs of the next destination
-    bool linear_first = false;
-    if (nbrick_passes % 2 == 0) {
-        jfa_to_bricks<<<dim3((unsigned)(nvox / 256)), dim3(256), 0, s>>>(seeds, scratch, n, logn);
+    int next = 1;  // index into bufs of the next destination
+    if (!linear_first) {
+        jfa_to_bricks<<<dim3(far_blocks), dim3(256), 0, s>>>(seeds, scratch, n, logn);
         RTSDF_CHECK_LAUNCH();
         cur = scratch;
         next = 0;
-    } else {
-        cur = seeds;
-        next = 1;
-        linear_first = true;
+        if (npass % 2 == 1) {
+            RTSDF_TRY(hipMemcpyAsync(seeds, scratch, sizeof(int32_t) * nvox, hipMemcpyDeviceToDevice, s));
+            cur = seeds;
+            next = 1;
+        }
     }
-    for (int i = 1; i <= nbrick_passes; ++i) {
-        const int k = n >> i;
+    for (int i = 0; i < npass; ++i) {
+        const int k = steps[i];
         int32_t *dst = bufs[next];
         if (k >= 4) {
-            if (linear_first && i == 1)
+            if (linear_first && i == 0)
                 jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
             else
                 jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
-        } else {  // k == 2, never the first pass since n >= 8
+        } else if (k == 2) {
             jfa_near<2, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr, 0.f, 0.f);
+        } else {
+            jfa_near<1, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr, 0.f, 0.f);
         }
         RTSDF_CHECK_LAUNCH();
         cur = dst;
@@ -273,14 +279,28 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
 
 }  // namespace rtsdf
 
-extern "C" int rtsdf_jfa(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, float beta, int32_t *dist2,
-                         float *coarse_sdf, rtsdf_stream stream)
+extern "C" int rtsdf_jfa_steps(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, const int32_t *steps,
+                               int32_t nsteps, float beta, int32_t *dist2, float *coarse_sdf, rtsdf_stream stream)
 {
     using namespace rtsdf;
     if (!grid_ok(coarse) || !is_pow2(coarse.n) || coarse.n < 8 || coarse.n > 256) return RTSDF_EINVAL;
     if (!seeds || !scratch || !dist2 || !coarse_sdf || seeds == scratch) return RTSDF_EINVAL;
     if (!(beta == beta)) return RTSDF_EINVAL;
+    if (!steps || nsteps < 1 || nsteps > 64 || steps[nsteps - 1] != 1) return RTSDF_EINVAL;
+    for (int i = 0; i < nsteps; ++i)
+        if (steps[i] < 1 || steps[i] > coarse.n / 2 || !is_pow2(steps[i])) return RTSDF_EINVAL;
     hipStream_t s = as_stream(stream);
-    if (coarse.n <= 128) return jfa_run<false>(coarse, seeds, scratch, beta, dist2, coarse_sdf, s);
-    return jfa_run<true>(coarse, seeds, scratch, beta, dist2, coarse_sdf, s);
+    if (coarse.n <= 128) return jfa_run<false>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, s);
+    return jfa_run<true>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, s);
+}
+
+extern "C" int rtsdf_jfa(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, float beta, int32_t *dist2,
+                         float *coarse_sdf, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!grid_ok(coarse) || !is_pow2(coarse.n) || coarse.n < 8 || coarse.n > 256) return RTSDF_EINVAL;
+    int32_t steps[16];
+    int m = 0;
+    for (int k = coarse.n / 2; k >= 1; k /= 2) steps[m++] = k;  // n/2, ..., 2, 1
+    return rtsdf_jfa_steps(coarse, seeds, scratch, steps, m, beta, dist2, coarse_sdf, stream);
 }

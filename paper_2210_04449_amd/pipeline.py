@@ -16,7 +16,8 @@ from . import rtsdf as R
 class Pipeline:
     def __init__(self, vertices: torch.Tensor, faces: torch.Tensor, nc: int, nf: int, beta: float, d: float,
                  rays: int, seed: int = 0, scene_id: int = 0, alpha: float = 1.0, lo=(0.0, 0.0, 0.0),
-                 side: float = 1.0, leaf_size: int = 2, queue_cap: int | None = None, device="cuda"):
+                 side: float = 1.0, leaf_size: int = 2, queue_cap: int | None = None, device="cuda",
+                 jfa_variant: str = "jfa"):
         self.leaf_size = int(leaf_size)
         self.device = torch.device(device)
         self.vertices = vertices.to(self.device, torch.float32).contiguous()
@@ -24,6 +25,7 @@ class Pipeline:
         self.coarse = R.Grid.make(nc, side / nc, lo)
         self.fine = R.Grid.make(nf, side / nf, lo)
         self.nc, self.nf = nc, nf
+        self.jfa_steps = None if jfa_variant == "jfa" else R.jfa_schedule(nc, jfa_variant)
         self.beta, self.d = float(beta), float(d)
         self.rays, self.seed, self.scene_id, self.alpha = int(rays), int(seed), int(scene_id), float(alpha)
         dev = self.device
@@ -46,7 +48,11 @@ class Pipeline:
         R.rtsdf_voxelize(self.vertices, self.faces, self.coarse, self.seeds, stream)
 
     def jfa(self, stream=None):
-        R.rtsdf_jfa(self.coarse, self.seeds, self.scratch, self.beta, self.dist2, self.coarse_sdf, stream)
+        if self.jfa_steps is None:
+            R.rtsdf_jfa(self.coarse, self.seeds, self.scratch, self.beta, self.dist2, self.coarse_sdf, stream)
+        else:
+            R.rtsdf_jfa_steps(self.coarse, self.seeds, self.scratch, self.jfa_steps, self.beta, self.dist2,
+                              self.coarse_sdf, stream)
 
     def select(self, stream=None):
         R.rtsdf_select(self.coarse, self.dist2, self.fine, self.beta, self.d, self.mask, self.queue, self.count,

@@ -94,6 +94,7 @@ def _load():
         "rtsdf_copy": ([_P, _P, _sz, _P], _i32),
         "rtsdf_voxelize": ([_P, _i32, _P, _i32, Grid, _P, _P], _i32),
         "rtsdf_jfa": ([Grid, _P, _P, _f32, _P, _P, _P], _i32),
+        "rtsdf_jfa_steps": ([Grid, _P, _P, C.POINTER(_i32), _i32, _f32, _P, _P, _P], _i32),
         "rtsdf_select_workspace_size": ([_i32], _sz),
         "rtsdf_select": ([Grid, _P, Grid, _f32, _f32, _P, _P, _i32, _P, _P, _P], _i32),
         "rtsdf_scene_create": ([_P, _i32, _P, _i32, _i32, C.POINTER(_P), _P], _i32),
@@ -188,6 +189,30 @@ def rtsdf_voxelize(vertices, faces, coarse: Grid, seeds, stream=None):
 def rtsdf_jfa(coarse: Grid, seeds, scratch, beta: float, dist2, coarse_sdf, stream=None):
     _check("rtsdf_jfa", _lib.rtsdf_jfa(coarse, _ptr(seeds), _ptr(scratch), float(beta), _ptr(dist2),
                                        _ptr(coarse_sdf), _stream(stream)))
+
+
+def jfa_schedule(n: int, variant: str = "jfa") -> list[int]:
+    """Pass steps of a jump-flooding variant: "jfa" (n/2 .. 1), "jfa+1", "jfa+2", "1+jfa"."""
+    base = []
+    k = n // 2
+    while k >= 1:
+        base.append(k)
+        k //= 2
+    if variant == "jfa":
+        return base
+    if variant == "jfa+1":
+        return base + [1]
+    if variant == "jfa+2":
+        return base + [2, 1]
+    if variant == "1+jfa":
+        return [1] + base
+    raise ValueError(f"unknown jump-flooding variant {variant!r}")
+
+
+def rtsdf_jfa_steps(coarse: Grid, seeds, scratch, steps, beta: float, dist2, coarse_sdf, stream=None):
+    arr = (_i32 * len(steps))(*[int(k) for k in steps])
+    _check("rtsdf_jfa_steps", _lib.rtsdf_jfa_steps(coarse, _ptr(seeds), _ptr(scratch), arr, len(steps), float(beta),
+                                                   _ptr(dist2), _ptr(coarse_sdf), _stream(stream)))
 
 
 def rtsdf_select_workspace_size(coarse_n: int) -> int:

@@ -106,6 +106,42 @@ def test_jfa_bit_exact(R, case, n):
     assert np.array_equal(c.view(np.int32), want_c.view(np.int32))
 
 
+@pytest.mark.parametrize("variant", ["jfa+1", "jfa+2", "1+jfa"])
+@pytest.mark.parametrize("case,n", [("tiny", 8), ("tiny", 16), ("tiny", 32), ("soup", 64), ("room", 128),
+                                    ("room", 256)])
+def test_jfa_schedules_bit_exact(R, case, n, variant):
+    """The error-reducing pass schedules (extra step-1/step-2 passes) against the oracle's passes."""
+    say("jfa schedule", variant, case, n)
+    mesh = {"tiny": tiny_scene, "room": lambda: room_scene(1), "soup": lambda: random_soup(9, 400)}[case]()
+    g = R.Grid.make(n)
+    seeds0 = torch.empty(n ** 3, dtype=torch.int32, device="cuda")
+    R.rtsdf_voxelize(cu(mesh.vertices), cu(mesh.faces), g, seeds0)
+    seeds = seeds0.clone()
+    scratch, d2 = torch.empty_like(seeds), torch.empty_like(seeds)
+    c = torch.empty(n ** 3, dtype=torch.float32, device="cuda")
+    beta = np.float32(0.5) * np.float32(1.0 / n)
+    steps = R.jfa_schedule(n, variant)
+    R.rtsdf_jfa_steps(g, seeds, scratch, steps, float(beta), d2, c)
+    torch.cuda.synchronize()
+    want_s = oracle.jfa_steps(n, seeds0.cpu().numpy(), steps)
+    want_d2, want_c = oracle.coarse(n, want_s, np.float32(1.0 / n), beta)
+    got = seeds.cpu().numpy()
+    assert np.array_equal(got, want_s), int((got != want_s).sum())
+    assert np.array_equal(d2.cpu().numpy(), want_d2)
+    assert np.array_equal(c.cpu().numpy().view(np.int32), want_c.view(np.int32))
+
+
+def test_jfa_steps_rejects_bad_schedules(R):
+    n = 16
+    g = R.Grid.make(n)
+    seeds = cu(np.full(n ** 3, -1, np.int32))
+    scratch, d2 = torch.empty_like(seeds), torch.empty_like(seeds)
+    c = torch.empty(n ** 3, dtype=torch.float32, device="cuda")
+    for bad in ([], [8, 4, 2], [3, 1], [16, 1], [0, 1]):
+        with pytest.raises(R.RtsdfError):
+            R.rtsdf_jfa_steps(g, seeds, scratch, bad, 0.0, d2, c)
+
+
 def test_jfa_single_seed_and_empty(R):
     for n, q in [(8, 0), (32, 32 ** 3 - 1), (64, 12345), (256, 256 ** 3 // 2 + 77)]:
         say("jfa single seed", n, q)

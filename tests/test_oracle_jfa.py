@@ -166,3 +166,55 @@ def test_coarse_empty_grid():
     d2, c = oracle.coarse(n, s, np.float32(1 / n), np.float32(0.01))
     assert np.all(d2 == np.iinfo(np.int32).max)
     assert np.all(np.isinf(c))
+
+
+# ---------------------------------------------------- pass schedules ----
+# The error-reducing variants of jump flooding (Rong & Tan): JFA+1 adds a pass
+# with step 1, JFA+2 adds passes 2 and 1, 1+JFA runs a step-1 pass first.
+
+def schedule(n, variant):
+    base = [n >> i for i in range(1, int(np.log2(n)) + 1)]
+    return {"jfa": base, "jfa+1": base + [1], "jfa+2": base + [2, 1], "1+jfa": [1] + base}[variant]
+
+
+def test_schedule_driver_composes_passes(tiny_flood):
+    n, s0, s = tiny_flood
+    assert np.array_equal(oracle.jfa_steps(n, s0, schedule(n, "jfa")), s)
+    # two passes by hand
+    want = oracle.jfa_pass(n, 2, oracle.jfa_pass(n, 8, s0))
+    assert np.array_equal(oracle.jfa_steps(n, s0, [8, 2]), want)
+    assert np.array_equal(oracle.jfa_steps(n, s0, []), s0)
+
+
+@pytest.mark.parametrize("variant", ["jfa+1", "jfa+2", "1+jfa"])
+def test_variants_exact_on_single_seed_and_plane(variant):
+    n = 16
+    rng = np.random.default_rng(11)
+    s0 = np.full(n ** 3, -1, np.int32)
+    q = int(rng.integers(0, n ** 3))
+    s0[q] = q
+    assert np.all(oracle.jfa_steps(n, s0, schedule(n, variant)) == q)
+    s0 = np.full(n ** 3, -1, np.int32)
+    p = coords(np.arange(n ** 3), n)
+    on = p[:, 2] == 5
+    s0[on] = np.nonzero(on)[0]
+    want = p[:, 0] + n * (p[:, 1] + n * 5)
+    assert np.array_equal(oracle.jfa_steps(n, s0, schedule(n, variant)), want)
+
+
+def test_variant_error_rates_room():
+    """Extra passes never lengthen a voxel's distance (every pass keeps the
+    voxel's own seed as a candidate), so JFA+1 and JFA+2 are pointwise between
+    the exact transform and plain JFA; all variants stay >= exact."""
+    n = 64
+    m = room_scene(1, n_prims=60)
+    s0 = oracle.voxelize(m.vertices, m.faces, LO, np.float32(1 / n), n)
+    exact = np.rint(ndimage.distance_transform_edt((s0 < 0).reshape(n, n, n)).ravel() ** 2)
+    d = {v: d2_of(oracle.jfa_steps(n, s0, schedule(n, v)), n) for v in ("jfa", "jfa+1", "jfa+2", "1+jfa")}
+    rates = {v: float(np.mean(x > exact)) for v, x in d.items()}
+    print("error rates (fraction of voxels farther than the exact EDT):", rates)
+    for v, x in d.items():
+        assert np.all(x >= exact), v
+    assert np.all(d["jfa+1"] <= d["jfa"]) and np.all(d["jfa+2"] <= d["jfa"])
+    assert rates["jfa+1"] <= rates["jfa"] and rates["jfa+2"] <= rates["jfa"]
+    assert rates["jfa"] < 0.02
