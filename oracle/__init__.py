@@ -281,14 +281,15 @@ class Scene:
 
 def run_frames(mesh_v, mesh_f, nc: int, nf: int, beta: float, d: float, rays: int, frames, seed: int = 0,
                scene: int = 0, alpha: float = 1.0, lo=(0.0, 0.0, 0.0), texels=None, use_bvh: bool = True,
-               state: TraceState | None = None):
-    """Whole oracle pipeline for a static mesh over the given frame indices.
+               state: TraceState | None = None, side: float = 1.0):
+    """Whole oracle pipeline for a static mesh over the given frame indices, on
+    the cube [lo, lo + side]^3.
 
     Returns a dict with the coarse stage outputs and the final trace state.
     """
     lo = np.asarray(lo, np.float32)
-    hc = np.float32(1.0) / np.float32(nc)
-    hf = np.float32(1.0) / np.float32(nf)
+    hc = np.float32(side) / np.float32(nc)
+    hf = np.float32(side) / np.float32(nf)
     seeds0 = voxelize(mesh_v, mesh_f, lo, hc, nc)
     seeds = jfa(nc, seeds0)
     d2, c = coarse(nc, seeds, hc, beta)

@@ -790,7 +790,9 @@ void oracle_closest_hits(const oracle_scene *s, int nr, const double *orig, cons
 double oracle_eq1(double alpha, double u_prev, float c, double rt, int *src)
 {
     const double cm = c > 0.0f ? (double)c : 0.0;
-    const double decayed = alpha == 1.0 ? u_prev : alpha * u_prev + (1.0 - alpha) * cm;
+    /* alpha = 0 keeps no memory: the alpha u term is its limit 0, also for u = +inf (no history yet),
+     * where the product itself would be 0 * inf */
+    const double decayed = alpha == 1.0 ? u_prev : (alpha == 0.0 ? cm : alpha * u_prev + (1.0 - alpha) * cm);
     if (rt < decayed) { *src = 1; return rt; }
     *src = (alpha == 1.0) ? 0 : 2;
     return decayed;

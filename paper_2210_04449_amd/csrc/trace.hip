@@ -809,7 +809,8 @@ trace_persistent(TraceArgs A)
             if (P.alpha == 1.0f) {
                 uu = uprev;
             } else {
-                uu = P.alpha * uprev + (1.0f - P.alpha) * fmaxf(c, 0.0f);
+                // alpha = 0: no memory, the alpha u term is 0 even before the first hit (u = +inf)
+                uu = P.alpha == 0.0f ? fmaxf(c, 0.0f) : P.alpha * uprev + (1.0f - P.alpha) * fmaxf(c, 0.0f);
             }
             if (rmin < uu) {
                 uu = rmin;
