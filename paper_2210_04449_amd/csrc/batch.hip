@@ -97,36 +97,54 @@ __global__ void __launch_bounds__(256) voxelize_batch(const BatchVox *__restrict
     vox_wave_big(big, T, seeds, n);
 }
 
+// Flat launches: the workgroups of every scene that has work in a stage are
+// numbered consecutively; a workgroup finds its scene by a binary search over
+// the scenes' first workgroup numbers (the search is uniform per workgroup).
+// A grid sized by the largest scene times the scene count would leave most
+// workgroups of small scenes without work.
+struct FlatRange {
+    int32_t scene;
+    uint32_t first;  // first workgroup number of the scene in this launch
+    uint32_t count;  // its workgroups
+};
+
+__device__ __forceinline__ const FlatRange &flat_find(const FlatRange *__restrict__ r, int nr, uint32_t g)
+{
+    int lo = 0, hi = nr - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (r[mid].first <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return r[__builtin_amdgcn_readfirstlane(lo)];
+}
+
 template <int KIND>
 __global__ void __launch_bounds__(KIND == kJfaNear2 || KIND == kJfaFinal ? 512 : 256)
-    jfa_batch(const JfaStep *__restrict__ plan)
+    jfa_batch(const JfaStep *__restrict__ plan, const FlatRange *__restrict__ ranges, int nr)
 {
-    const JfaStep &st = plan[blockIdx.y];
-    if (st.kind != KIND) return;
-    const int64_t nvox = (int64_t)st.n * st.n * st.n;
+    const FlatRange &fr = flat_find(ranges, nr, blockIdx.x);
+    const JfaStep &st = plan[fr.scene];
+    const uint32_t blk = blockIdx.x - fr.first, nblk = fr.count;
     if (KIND == kJfaConvert) {
-        const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const int64_t nvox = (int64_t)st.n * st.n * st.n;
+        const int64_t e = (int64_t)blk * blockDim.x + threadIdx.x;
         if (e < nvox) jfa_to_bricks_body(st.src, st.dst, st.n, st.logn, e);
     } else if (KIND == kJfaFarBricks || KIND == kJfaFarLinear) {
-        const uint32_t nblk = (uint32_t)(nvox / 256);
-        if (blockIdx.x >= nblk) return;
-        jfa_far_body<false, KIND == kJfaFarLinear>(st.src, st.dst, st.n, st.logn, st.kb, blockIdx.x, nblk);
+        jfa_far_body<false, KIND == kJfaFarLinear>(st.src, st.dst, st.n, st.logn, st.kb, blk, nblk);
     } else if (KIND == kJfaNear2) {
-        const uint32_t nblk = (uint32_t)(nvox / 512);
-        if (blockIdx.x >= nblk) return;
-        jfa_near_body<2, false, false>(st.src, st.dst, st.n, st.logn, nullptr, nullptr, 0.f, 0.f, blockIdx.x, nblk);
+        jfa_near_body<2, false, false>(st.src, st.dst, st.n, st.logn, nullptr, nullptr, 0.f, 0.f, blk, nblk);
     } else {
-        const uint32_t nblk = (uint32_t)(nvox / 512);
-        if (blockIdx.x >= nblk) return;
-        jfa_near_body<1, false, true>(st.src, st.dst, st.n, st.logn, st.dist2, st.sdf, st.h, st.beta, blockIdx.x, nblk);
+        jfa_near_body<1, false, true>(st.src, st.dst, st.n, st.logn, st.dist2, st.sdf, st.h, st.beta, blk, nblk);
     }
 }
 
-__global__ void __launch_bounds__(kSelBlock) select_count_batch(const SelScene *__restrict__ sc)
+__global__ void __launch_bounds__(kSelBlock) select_count_batch(const SelScene *__restrict__ sc,
+                                                                 const FlatRange *__restrict__ ranges, int nr)
 {
-    const SelScene &S = sc[blockIdx.y];
-    if (blockIdx.x >= S.nblocks) return;
-    select_count_body(S.d2, S.logn, S.K, S.total, S.sums, blockIdx.x);
+    const FlatRange &fr = flat_find(ranges, nr, blockIdx.x);
+    const SelScene &S = sc[fr.scene];
+    select_count_body(S.d2, S.logn, S.K, S.total, S.sums, blockIdx.x - fr.first);
 }
 
 __global__ void __launch_bounds__(1024) select_scan_batch(const SelScene *__restrict__ sc)
@@ -135,27 +153,41 @@ __global__ void __launch_bounds__(1024) select_scan_batch(const SelScene *__rest
     select_scan_body(S.sums, S.nblocks, 1u << (3 * S.logr), S.count, S.cap);
 }
 
-__global__ void __launch_bounds__(kSelBlock) select_scatter_batch(const SelScene *__restrict__ sc)
+__global__ void __launch_bounds__(kSelBlock) select_scatter_batch(const SelScene *__restrict__ sc,
+                                                                   const FlatRange *__restrict__ ranges, int nr)
 {
-    const SelScene &S = sc[blockIdx.y];
-    if (blockIdx.x >= S.nblocks) return;
-    select_scatter_body(S.d2, S.logn, S.K, S.total, S.sums, S.logr, S.nf, S.queue, S.cap, blockIdx.x);
+    const FlatRange &fr = flat_find(ranges, nr, blockIdx.x);
+    const SelScene &S = sc[fr.scene];
+    select_scatter_body(S.d2, S.logn, S.K, S.total, S.sums, S.logr, S.nf, S.queue, S.cap, blockIdx.x - fr.first);
 }
 
-__global__ void __launch_bounds__(256) select_mask_batch(const SelScene *__restrict__ sc)
+__global__ void __launch_bounds__(256) select_mask_batch(const SelScene *__restrict__ sc,
+                                                         const FlatRange *__restrict__ ranges, int nr)
 {
-    const SelScene &S = sc[blockIdx.y];
-    select_mask_body(S.d2, S.logn, S.logr, S.nf, S.K, S.nquads, S.mask4, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    const FlatRange &fr = flat_find(ranges, nr, blockIdx.x);
+    const SelScene &S = sc[fr.scene];
+    select_mask_body(S.d2, S.logn, S.logr, S.nf, S.K, S.nquads, S.mask4,
+                     (int64_t)(blockIdx.x - fr.first) * blockDim.x + threadIdx.x);
 }
 
-__global__ void __launch_bounds__(256) fill_unselected_batch(const FillScene *__restrict__ sc)
+constexpr int kFillPerThread = 8;  // texels per thread of the batched fill
+
+__global__ void __launch_bounds__(256) fill_unselected_batch(const FillScene *__restrict__ sc,
+                                                             const FlatRange *__restrict__ ranges, int nr)
 {
-    const FillScene &F = sc[blockIdx.y];
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < F.ntex; j += stride)
+    const FlatRange &fr = flat_find(ranges, nr, blockIdx.x);
+    const FillScene &F = sc[fr.scene];
+    const int64_t stride = (int64_t)fr.count * blockDim.x;
+    for (int64_t j = (int64_t)(blockIdx.x - fr.first) * blockDim.x + threadIdx.x; j < F.ntex; j += stride)
         fill_unselected_body(F.mask, F.coarse_sdf, F.nc, F.logr, F.lognf, F.ntex, F.u, F.hits, F.arg_tri, F.arg_ray,
                              F.fine, j);
 }
+
+// host side: one segment of the range table per launch
+struct FlatLaunch {
+    int offset = 0, count = 0;  // entries in the device range table
+    uint32_t blocks = 0;        // workgroups of the launch
+};
 
 }  // namespace rtsdf
 
@@ -189,10 +221,9 @@ struct rtsdf_batch {
     rtsdf::SelScene *sel = nullptr;
     rtsdf::FillScene *fill = nullptr;
     rtsdf::TraceScene *trace = nullptr;
-    std::vector<std::array<bool, rtsdf::kJfaKinds>> kinds_in_pass;
-    std::vector<std::array<uint32_t, rtsdf::kJfaKinds>> grid_in_pass;
-    uint32_t max_sel_blocks = 0;
-    int64_t max_quads = 0, max_ntex = 0;
+    rtsdf::FlatRange *ranges = nullptr;  // all launches' range tables
+    std::vector<std::array<rtsdf::FlatLaunch, rtsdf::kJfaKinds>> jfa_launch;  // [pass][kind]
+    rtsdf::FlatLaunch sel_launch, mask_launch, fill_launch;
     std::vector<void *> allocations;
 };
 
@@ -292,8 +323,8 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
     std::vector<SelScene> sel(n);
     std::vector<FillScene> fill(n);
     std::vector<TraceScene> trace(n);
-    B->kinds_in_pass.assign(B->max_passes + 1, {});
-    B->grid_in_pass.assign(B->max_passes + 1, {});
+    std::vector<std::array<uint32_t, kJfaKinds>> jfa_blocks((size_t)(B->max_passes + 1) * n);  // [pass * n + scene]
+    for (auto &a : jfa_blocks) a.fill(0);
     int64_t items = 0;
     for (int i = 0; i < n; ++i) {
         const rtsdf_batch_scene &d = scenes[i];
@@ -307,8 +338,7 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
         const int64_t nvox = (int64_t)c.n * c.n * c.n;
         auto put = [&](int pass, JfaStep st, uint32_t grid) {
             plan[(size_t)pass * n + i] = st;
-            B->kinds_in_pass[pass][st.kind] = true;
-            B->grid_in_pass[pass][st.kind] = std::max(B->grid_in_pass[pass][st.kind], grid);
+            jfa_blocks[(size_t)pass * n + i][st.kind] = grid;
         };
         int32_t *bufs[2] = {seeds, scratch};
         const int32_t *cur;
@@ -347,10 +377,7 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
                           B->sel_sums + sel_off[i], sel_off[i + 1] - sel_off[i], logr, f.n, B->queue + B->foff[i],
                           (int32_t)((int64_t)f.n * f.n * f.n), B->counts + i,
                           reinterpret_cast<uint32_t *>(B->mask + B->foff[i]), (int64_t)f.n * f.n * f.n / 4};
-        B->max_sel_blocks = std::max(B->max_sel_blocks, sel[i].nblocks);
-        B->max_quads = std::max(B->max_quads, sel[i].nquads);
         const int64_t ntex = (int64_t)f.n * f.n * f.n;
-        B->max_ntex = std::max(B->max_ntex, ntex);
         fill[i] = FillScene{B->mask + B->foff[i], B->coarse_sdf + B->coff[i], c.n, logr, ilog2(f.n), ntex,
                             B->u + B->foff[i], B->hits + B->foff[i], B->arg_tri + B->foff[i], B->arg_ray + B->foff[i],
                             B->fine_sdf + B->foff[i]};
@@ -381,7 +408,32 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
         P.fine = B->fine_sdf + B->foff[i];
     }
     B->items = items;
+    // range tables of the flat launches
+    std::vector<FlatRange> ranges;
+    auto segment = [&](auto blocks_of) {
+        FlatLaunch L;
+        L.offset = (int)ranges.size();
+        for (int i = 0; i < n; ++i) {
+            const uint32_t b = blocks_of(i);
+            if (b == 0) continue;
+            ranges.push_back(FlatRange{i, L.blocks, b});
+            L.blocks += b;
+        }
+        L.count = (int)ranges.size() - L.offset;
+        return L;
+    };
+    B->jfa_launch.assign(B->max_passes + 1, {});
+    for (int p = 0; p <= B->max_passes; ++p)
+        for (int k = 1; k < kJfaKinds; ++k)
+            B->jfa_launch[p][k] = segment([&](int i) { return jfa_blocks[(size_t)p * n + i][k]; });
+    B->sel_launch = segment([&](int i) { return sel[i].nblocks; });
+    B->mask_launch = segment([&](int i) { return (uint32_t)((sel[i].nquads + 255) / 256); });
+    B->fill_launch = segment([&](int i) { return (uint32_t)((fill[i].ntex + 256 * kFillPerThread - 1) / (256 * kFillPerThread)); });
+    if (!batch_alloc(B, &B->ranges, (int64_t)std::max<size_t>(ranges.size(), 1))) return fail(RTSDF_ENOMEM);
     bool ok = hipMemcpyAsync(B->vox, vox.data(), sizeof(BatchVox) * n, hipMemcpyHostToDevice, s) == hipSuccess;
+    if (!ranges.empty())
+        ok &= hipMemcpyAsync(B->ranges, ranges.data(), sizeof(FlatRange) * ranges.size(), hipMemcpyHostToDevice, s) ==
+              hipSuccess;
     ok &= hipMemcpyAsync(B->plan, plan.data(), sizeof(JfaStep) * plan.size(), hipMemcpyHostToDevice, s) == hipSuccess;
     ok &= hipMemcpyAsync(B->sel, sel.data(), sizeof(SelScene) * n, hipMemcpyHostToDevice, s) == hipSuccess;
     ok &= hipMemcpyAsync(B->fill, fill.data(), sizeof(FillScene) * n, hipMemcpyHostToDevice, s) == hipSuccess;
@@ -422,24 +474,35 @@ extern "C" int rtsdf_batch_step(rtsdf_batch *B, uint32_t frame, const uint32_t *
     // jump flooding, pass by pass
     for (int p = 0; p <= B->max_passes; ++p) {
         const JfaStep *plan = B->plan + (size_t)p * n;
-        const auto &has = B->kinds_in_pass[p];
-        const auto &grid = B->grid_in_pass[p];
-        if (has[kJfaConvert]) jfa_batch<kJfaConvert><<<dim3(grid[kJfaConvert], n), dim3(256), 0, s>>>(plan);
-        if (has[kJfaFarLinear]) jfa_batch<kJfaFarLinear><<<dim3(grid[kJfaFarLinear], n), dim3(256), 0, s>>>(plan);
-        if (has[kJfaFarBricks]) jfa_batch<kJfaFarBricks><<<dim3(grid[kJfaFarBricks], n), dim3(256), 0, s>>>(plan);
-        if (has[kJfaNear2]) jfa_batch<kJfaNear2><<<dim3(grid[kJfaNear2], n), dim3(512), 0, s>>>(plan);
-        if (has[kJfaFinal]) jfa_batch<kJfaFinal><<<dim3(grid[kJfaFinal], n), dim3(512), 0, s>>>(plan);
+        const auto &L = B->jfa_launch[p];
+        const FlatRange *r = B->ranges;
+        if (L[kJfaConvert].blocks)
+            jfa_batch<kJfaConvert><<<dim3(L[kJfaConvert].blocks), dim3(256), 0, s>>>(
+                plan, r + L[kJfaConvert].offset, L[kJfaConvert].count);
+        if (L[kJfaFarLinear].blocks)
+            jfa_batch<kJfaFarLinear><<<dim3(L[kJfaFarLinear].blocks), dim3(256), 0, s>>>(
+                plan, r + L[kJfaFarLinear].offset, L[kJfaFarLinear].count);
+        if (L[kJfaFarBricks].blocks)
+            jfa_batch<kJfaFarBricks><<<dim3(L[kJfaFarBricks].blocks), dim3(256), 0, s>>>(
+                plan, r + L[kJfaFarBricks].offset, L[kJfaFarBricks].count);
+        if (L[kJfaNear2].blocks)
+            jfa_batch<kJfaNear2><<<dim3(L[kJfaNear2].blocks), dim3(512), 0, s>>>(plan, r + L[kJfaNear2].offset,
+                                                                                  L[kJfaNear2].count);
+        if (L[kJfaFinal].blocks)
+            jfa_batch<kJfaFinal><<<dim3(L[kJfaFinal].blocks), dim3(512), 0, s>>>(plan, r + L[kJfaFinal].offset,
+                                                                                  L[kJfaFinal].count);
         RTSDF_CHECK_LAUNCH();
     }
     // selection
-    select_count_batch<<<dim3(B->max_sel_blocks, n), dim3(kSelBlock), 0, s>>>(B->sel);
+    const FlatLaunch &SL = B->sel_launch, &ML = B->mask_launch, &FL = B->fill_launch;
+    if (SL.blocks) select_count_batch<<<dim3(SL.blocks), dim3(kSelBlock), 0, s>>>(B->sel, B->ranges + SL.offset, SL.count);
     select_scan_batch<<<dim3(1, n), dim3(1024), 0, s>>>(B->sel);
-    select_scatter_batch<<<dim3(B->max_sel_blocks, n), dim3(kSelBlock), 0, s>>>(B->sel);
-    select_mask_batch<<<dim3((unsigned)((B->max_quads + 255) / 256), n), dim3(256), 0, s>>>(B->sel);
+    if (SL.blocks)
+        select_scatter_batch<<<dim3(SL.blocks), dim3(kSelBlock), 0, s>>>(B->sel, B->ranges + SL.offset, SL.count);
+    if (ML.blocks) select_mask_batch<<<dim3(ML.blocks), dim3(256), 0, s>>>(B->sel, B->ranges + ML.offset, ML.count);
     RTSDF_CHECK_LAUNCH();
     // tracing
-    fill_unselected_batch<<<dim3((unsigned)std::min<int64_t>((B->max_ntex + 255) / 256, 4096), n), dim3(256), 0, s>>>(
-        B->fill);
+    if (FL.blocks) fill_unselected_batch<<<dim3(FL.blocks), dim3(256), 0, s>>>(B->fill, B->ranges + FL.offset, FL.count);
     RTSDF_CHECK_LAUNCH();
     trace_tile_prefix<<<dim3(1), dim3(64), 0, s>>>(B->trace, n, B->tile_offset);
     RTSDF_CHECK_LAUNCH();
