@@ -30,7 +30,7 @@ METRIC = "ms per SDF update (JFA+trace) at 128³/256³; fine-texel rays/s; JFA H
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic VALU lane-operations of the tracer:
+# Algorithmic VALU lane-operations of the tracer per unit of work:
 OPS_NODE = 39   # one two-child node: 2 x (6 slab FMAs + 12 min/max + 1 compare) + ordering
 OPS_TRI = 33    # triangle-frame test: 18 FMAs (plane + 2 barycentric rows), 1/q, t, 2 barycentrics, margin, compares
 OPS_RAY = 360   # Philox4x64-10 (10 rounds), Marsaglia mapping, ray set-up, accumulation
@@ -55,12 +55,14 @@ def parse():
     ap.add_argument("--leaf-size", type=int, default=2)
     ap.add_argument("--jfa", default="jfa", choices=["jfa", "jfa+1", "jfa+2", "1+jfa"],
                     help="jump-flooding pass schedule (the extra-pass variants reduce its errors)")
+    ap.add_argument("--sampling", default="point", choices=["point", "trilinear"],
+                    help="how a fine texel reads the coarse SDF for selection and c_t")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (scale for HBM byte counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(w, gpu_count: int, target_s: float):
+def cpu_baseline(w, gpu_count: int, target_s: float, sampling: str = "point"):
     """Oracle on the same inputs: coarse stages in full, tracing on a seeded
     sample of the selected texels (one frame), extrapolated to one update."""
     import numpy as np
@@ -73,22 +75,28 @@ def cpu_baseline(w, gpu_count: int, target_s: float):
     s0 = oracle.voxelize(w.mesh.vertices, w.mesh.faces, lo, hc, w.nc)
     s = oracle.jfa(w.nc, s0)
     d2, c = oracle.coarse(w.nc, s, hc, w.beta)
-    K = oracle.select_threshold(hc, w.beta, w.d)
-    mask, queue = oracle.select(w.nc, d2, w.nf, K)
+    if sampling == "trilinear":
+        c = oracle.coarse_trilinear(w.nc, c, w.nf)
+        mask, queue = oracle.select_field(w.nf, c, w.d)
+        nc = w.nf
+    else:
+        K = oracle.select_threshold(hc, w.beta, w.d)
+        mask, queue = oracle.select(w.nc, d2, w.nf, K)
+        nc = w.nc
     t_coarse = time.perf_counter() - t0
     sc = oracle.Scene(w.mesh.vertices, w.mesh.faces)
     st = oracle.TraceState(w.nf)
     rng = np.random.default_rng(0)
     # calibrate on a small sample, then size the main sample to ~target_s
     probe = np.sort(rng.choice(queue, min(len(queue), 4096), replace=False)).astype(np.int32)
-    sc.trace_frame(w.nc, c, w.nf, lo, hf, mask, w.rays, 0, 0, w.scene_seed, w.alpha, st, probe[:256])  # warm-up
+    sc.trace_frame(nc, c, w.nf, lo, hf, mask, w.rays, 0, 0, w.scene_seed, w.alpha, st, probe[:256])  # warm-up
     t1 = time.perf_counter()
-    sc.trace_frame(w.nc, c, w.nf, lo, hf, mask, w.rays, 0, 0, w.scene_seed, w.alpha, st, probe)
+    sc.trace_frame(nc, c, w.nf, lo, hf, mask, w.rays, 0, 0, w.scene_seed, w.alpha, st, probe)
     per_texel = (time.perf_counter() - t1) / len(probe)
     n = int(min(len(queue), max(4096, (target_s - t_coarse) / max(per_texel, 1e-9))))
     sample = np.sort(rng.choice(queue, n, replace=False)).astype(np.int32)
     t2 = time.perf_counter()
-    sc.trace_frame(w.nc, c, w.nf, lo, hf, mask, w.rays, 1, 0, w.scene_seed, w.alpha, st, sample)
+    sc.trace_frame(nc, c, w.nf, lo, hf, mask, w.rays, 1, 0, w.scene_seed, w.alpha, st, sample)
     t_trace = time.perf_counter() - t2
     est_ms = (t_coarse + t_trace * len(queue) / n) * 1e3
     return {
@@ -106,8 +114,8 @@ def cpu_baseline(w, gpu_count: int, target_s: float):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU split is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the SDF update of one scene "
+              "runs on one GPU; many scenes split across GPUs by scene)", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -133,7 +141,7 @@ def main():
     R.rtsdf_trace_config(**tuning)
     p = Pipeline(torch.from_numpy(w.mesh.vertices).to(dev), torch.from_numpy(w.mesh.faces).to(dev), w.nc, w.nf,
                  w.beta, w.d, w.rays, seed=0, scene_id=w.scene_seed, alpha=w.alpha, leaf_size=args.leaf_size,
-                 jfa_variant=args.jfa)
+                 jfa_variant=args.jfa, sampling=args.sampling)
     info = p.scene.info()
     stream = torch.cuda.current_stream()
     dyn_frames = None
@@ -246,6 +254,7 @@ def main():
             "coarse": w.nc,
             "fine": w.nf,
             "rays_per_texel": w.rays,
+            "sampling": args.sampling,
         },
         "gpu_ms_per_step": round(gpu_ms, 3),
         "gpu_ms_p10_p50_p90": [round(pct(0.1), 3), round(pct(0.5), 3), round(pct(0.9), 3)],
@@ -277,7 +286,7 @@ def main():
     if dyn_frames is not None:
         out["config"]["dynamic"] = "20% of primitives move rigidly; 8 precomputed vertex sets cycled; refit each update"
     if not args.no_cpu_baseline and args.config != "dynamic":
-        out["cpu_baseline"] = cpu_baseline(w, selected, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, selected, args.cpu_seconds, args.sampling)
     print(json.dumps(out), flush=True)
 
 

@@ -170,6 +170,39 @@ int rtsdf_select(rtsdf_grid coarse, const int32_t *dist2, rtsdf_grid fine, float
                  void *workspace, rtsdf_stream stream);
 
 /* ------------------------------------------------------------------------ */
+/* 3b. Trilinear coarse sampling (a smoother reading of the coarse value c  */
+/* that Sec. 2.2 compares with d and stores for unselected texels; Sec. 2.1 */
+/* notes the point-sampled coarse SDF is blocky).                           */
+/*                                                                           */
+/* rtsdf_coarse_trilinear writes, for every fine texel, the coarse SDF       */
+/* interpolated trilinearly at the texel centre.  Coarse values are samples  */
+/* at voxel centres; the fine centre j lies at coarse coordinate             */
+/* u = (j + 1/2) / r - 1/2 per axis (r = fine.n / coarse.n), clamped to      */
+/* [0, coarse.n - 1]; the value is lerp along x, then y, then z, each       */
+/* lerp(a, b, t) = a + t (b - a) with every float operation rounded once, so */
+/* the result is reproducible bit for bit.  A cell with an infinite corner   */
+/* (a field without seeds) gives +inf.  Grids as for rtsdf_select, with      */
+/* coarse.n <= 512.                                                          */
+/*                                                                           */
+/* coarse_sdf float32 [n_c^3] in; fine_c float32 [n_f^3] out.                */
+/*                                                                           */
+/* rtsdf_select_field selects the texels of `grid` with field <= d (a        */
+/* float32 comparison; NaN never selects), with the same mask, queue order,  */
+/* count and ERR_QUEUE_FULL behaviour as rtsdf_select at r = 1.  grid.n is a */
+/* power of two in [4, 1024]; workspace holds                                */
+/* rtsdf_select_workspace_size(grid.n) bytes.  d must not be NaN.            */
+/*                                                                           */
+/* With both, the trilinear pipeline is: rtsdf_coarse_trilinear, then        */
+/* rtsdf_select_field on the fine grid, then rtsdf_trace_accumulate with the */
+/* fine grid and fine_c passed as its coarse grid and coarse_sdf (so c_t in  */
+/* Eq. (1) and the unselected texels' value are the interpolated field).     */
+/* ------------------------------------------------------------------------ */
+int rtsdf_coarse_trilinear(rtsdf_grid coarse, const float *coarse_sdf, rtsdf_grid fine, float *fine_c,
+                           rtsdf_stream stream);
+int rtsdf_select_field(rtsdf_grid grid, const float *field, float d, uint8_t *mask, int32_t *queue,
+                       int32_t queue_cap, int32_t *count, void *workspace, rtsdf_stream stream);
+
+/* ------------------------------------------------------------------------ */
 /* Scene: the triangles and their bounding volume hierarchy, resident on    */
 /* the device.  create copies the mesh (device pointers) and builds the      */
 /* hierarchy (binned surface-area heuristic, two children per node); it      */
@@ -336,6 +369,12 @@ typedef struct rtsdf_frame_desc {
     float *fine_sdf;                  /* [n_f^3] */
     void *trace_workspace;            /* rtsdf_trace_workspace_size() bytes */
     uint32_t *frame_counter;          /* [1], device */
+    float *fine_c;                    /* NULL: point sampling.  Else [n_f^3]: trilinear sampling (rtsdf_coarse_trilinear
+                                         into fine_c, rtsdf_select_field, trace against fine_c); select_workspace then
+                                         holds rtsdf_select_workspace_size(fine.n) bytes */
+    const int32_t *jfa_steps;         /* HOST, read during create only.  NULL: n/2, ..., 1; else the pass
+                                         schedule of rtsdf_jfa_steps (jfa_nsteps entries) */
+    int32_t jfa_nsteps;
 } rtsdf_frame_desc;
 
 typedef struct rtsdf_frame_graph rtsdf_frame_graph;

@@ -8,7 +8,8 @@ builds that file with gcc and marshals numpy arrays through ctypes.
 
 Functions mirror the steps of the method (paper Sec. 2.1-2.2):
 ``voxelize``, ``jfa`` / ``jfa_pass``, ``coarse``, ``select_threshold``,
-``select``, ``philox4x64_10``, ``direction``, ``Scene.closest_hits``,
+``select``, ``coarse_trilinear``, ``select_field``, ``philox4x64_10``,
+``direction``, ``Scene.closest_hits``,
 ``Scene.trace_frame`` and ``Scene.fine_grad``.
 """
 from __future__ import annotations
@@ -53,6 +54,8 @@ def lib():
         L.oracle_coarse.argtypes = [i32, P, f32, f32, P, P]
         L.oracle_select_threshold.argtypes = [f32, f32, f32]
         L.oracle_select.argtypes = [i32, P, i32, i32, P, P, i32, P]
+        L.oracle_coarse_trilinear.argtypes = [i32, P, i32, P]
+        L.oracle_select_field.argtypes = [i32, P, f32, P, P, i32, P]
         L.oracle_philox4x64_10.argtypes = [P, P, P]
         L.oracle_direction.argtypes = [u64, u64, u32, u32, u32, P]
         L.oracle_texel_origin.argtypes = [i32, P, f32, i32, P]
@@ -143,6 +146,26 @@ def select(nc: int, dist2: np.ndarray, nf: int, K: int):
     rc = lib().oracle_select(int(nc), _p(d2), int(nf), int(K), _p(mask), _p(queue), nf ** 3, C.byref(cnt))
     if rc != 0:
         raise ValueError("oracle_select failed")
+    return mask, queue[: cnt.value].copy()
+
+
+def coarse_trilinear(nc: int, c: np.ndarray, nf: int) -> np.ndarray:
+    """Coarse SDF sampled trilinearly at the fine texel centres (float32)."""
+    cc = _c(c, np.float32)
+    out = np.empty(nf ** 3, np.float32)
+    if lib().oracle_coarse_trilinear(int(nc), _p(cc), int(nf), _p(out)) != 0:
+        raise ValueError("oracle_coarse_trilinear: invalid arguments")
+    return out
+
+
+def select_field(n: int, field: np.ndarray, d: float):
+    """Texels with field <= d: mask and Morton-ordered queue."""
+    fl = _c(field, np.float32)
+    mask = np.empty(n ** 3, np.uint8)
+    queue = np.empty(n ** 3, np.int32)
+    cnt = C.c_int(0)
+    if lib().oracle_select_field(int(n), _p(fl), float(d), _p(mask), _p(queue), n ** 3, C.byref(cnt)) != 0:
+        raise ValueError("oracle_select_field failed")
     return mask, queue[: cnt.value].copy()
 
 
@@ -281,9 +304,10 @@ class Scene:
 
 def run_frames(mesh_v, mesh_f, nc: int, nf: int, beta: float, d: float, rays: int, frames, seed: int = 0,
                scene: int = 0, alpha: float = 1.0, lo=(0.0, 0.0, 0.0), texels=None, use_bvh: bool = True,
-               state: TraceState | None = None, side: float = 1.0):
+               state: TraceState | None = None, side: float = 1.0, sampling: str = "point"):
     """Whole oracle pipeline for a static mesh over the given frame indices, on
-    the cube [lo, lo + side]^3.
+    the cube [lo, lo + side]^3.  ``sampling="trilinear"`` selects and fills
+    with the trilinearly sampled coarse SDF instead of the containing voxel's.
 
     Returns a dict with the coarse stage outputs and the final trace state.
     """
@@ -294,9 +318,20 @@ def run_frames(mesh_v, mesh_f, nc: int, nf: int, beta: float, d: float, rays: in
     seeds = jfa(nc, seeds0)
     d2, c = coarse(nc, seeds, hc, beta)
     K = select_threshold(hc, beta, d)
-    mask, queue = select(nc, d2, nf, K)
+    if sampling == "point":
+        mask, queue = select(nc, d2, nf, K)
+        ng, cg = nc, c
+    elif sampling == "trilinear":
+        cg = coarse_trilinear(nc, c, nf)
+        mask, queue = select_field(nf, cg, d)
+        ng = nf
+    else:
+        raise ValueError(f"unknown sampling {sampling!r}")
     sc = Scene(mesh_v, mesh_f, use_bvh)
     st = TraceState(nf) if state is None else state
     for fr in frames:
-        sc.trace_frame(nc, c, nf, lo, hf, mask, rays, fr, seed, scene, alpha, st, texels)
-    return dict(seeds0=seeds0, seeds=seeds, dist2=d2, coarse=c, K=K, mask=mask, queue=queue, state=st, scene=sc)
+        sc.trace_frame(ng, cg, nf, lo, hf, mask, rays, fr, seed, scene, alpha, st, texels)
+    out = dict(seeds0=seeds0, seeds=seeds, dist2=d2, coarse=c, K=K, mask=mask, queue=queue, state=st, scene=sc)
+    if sampling == "trilinear":
+        out["coarse_fine"] = cg
+    return out

@@ -329,6 +329,102 @@ int oracle_select(int nc, const int *dist2, int nf, int K,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Trilinear coarse sampling (a smoother reading of the coarse value c that  */
+/* Sec. 2.2 compares with d and stores for unselected texels; the blocky    */
+/* look of the point-sampled coarse SDF is what Sec. 2.1 remarks on).  The   */
+/* coarse values are samples at voxel centres; the fine texel centre j sits  */
+/* at coarse coordinate u = (j + 1/2)/r - 1/2 per axis (r = nf/nc), clamped  */
+/* to [0, nc - 1] (constant extension beyond the outermost centres).  The    */
+/* value is linear interpolation along x between the corner pairs, then     */
+/* along y, then along z, each step a + t (b - a) in float32 (the selection  */
+/* decision c <= d is a float32 comparison on both sides, so the value must  */
+/* be the same float); an infinite corner (an empty coarse field) gives      */
+/* +inf.                                                                     */
+/* ------------------------------------------------------------------------ */
+
+static float lerpf_plain(float a, float b, float t)
+{
+    const float diff = b - a;
+    const float step = t * diff;
+    return a + step;
+}
+
+static void clamp_axis(int j, int r, int nc, int *i0, int *i1, float *t)
+{
+    double u = ((double)j + 0.5) / (double)r - 0.5;
+    if (u < 0.0) u = 0.0;
+    if (u > (double)(nc - 1)) u = (double)(nc - 1);
+    *i0 = (int)floor(u);
+    *i1 = *i0 + 1 < nc ? *i0 + 1 : nc - 1;
+    *t = (float)(u - (double)*i0); /* a multiple of 1/(2r): exact in float */
+}
+
+int oracle_coarse_trilinear(int nc, const float *c, int nf, float *out)
+{
+    if (nc <= 0 || nf <= 0 || nf % nc != 0) return ORC_EINVAL;
+    const int r = nf / nc;
+    const int64_t total = (int64_t)nf * nf * nf;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < total; ++j) {
+        const int jx = (int)(j % nf), jy = (int)((j / nf) % nf), jz = (int)(j / ((int64_t)nf * nf));
+        int x[2], y[2], z[2];
+        float tx, ty, tz;
+        clamp_axis(jx, r, nc, &x[0], &x[1], &tx);
+        clamp_axis(jy, r, nc, &y[0], &y[1], &ty);
+        clamp_axis(jz, r, nc, &z[0], &z[1], &tz);
+        float v[2][2][2]; /* v[dz][dy][dx] */
+        int any_inf = 0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int e = 0; e < 2; ++e) {
+                    v[a][b][e] = c[x[e] + (int64_t)nc * (y[b] + (int64_t)nc * z[a])];
+                    if (isinf(v[a][b][e])) any_inf = 1;
+                }
+        if (any_inf) {
+            out[j] = INFINITY;
+            continue;
+        }
+        float vy[2][2]; /* after x: vy[dz][dy] */
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) vy[a][b] = lerpf_plain(v[a][b][0], v[a][b][1], tx);
+        float vz[2]; /* after y */
+        for (int a = 0; a < 2; ++a) vz[a] = lerpf_plain(vy[a][0], vy[a][1], ty);
+        out[j] = lerpf_plain(vz[0], vz[1], tz);
+    }
+    return ORC_OK;
+}
+
+/* Selection on a field given at the texels themselves: texel j is selected  */
+/* when field[j] <= d (float32 comparison); queue in ascending Morton order  */
+/* as for oracle_select.                                                     */
+int oracle_select_field(int n, const float *field, float d, unsigned char *mask, int *queue, int cap, int *count)
+{
+    if (n <= 0 || cap < 0) return ORC_EINVAL;
+    const size_t total = (size_t)n * n * n;
+    size_t cnt = 0;
+    for (size_t j = 0; j < total; ++j) {
+        mask[j] = (unsigned char)(field[j] <= d);
+        cnt += mask[j];
+    }
+    *count = (int)cnt;
+    keyed_t *list = (keyed_t *)malloc(sizeof(keyed_t) * (cnt ? cnt : 1));
+    if (!list) return ORC_EINVAL;
+    size_t w = 0;
+    for (size_t j = 0; j < total; ++j) {
+        if (!mask[j]) continue;
+        const int x = (int)(j % n), y = (int)((j / n) % n), z = (int)(j / ((size_t)n * n));
+        list[w].key = morton3((uint32_t)x, (uint32_t)y, (uint32_t)z);
+        list[w].idx = (int)j;
+        ++w;
+    }
+    qsort(list, cnt, sizeof(keyed_t), cmp_keyed);
+    const size_t lim = cnt < (size_t)cap ? cnt : (size_t)cap;
+    for (size_t i = 0; i < lim; ++i) queue[i] = list[i].idx;
+    free(list);
+    return cnt > (size_t)cap ? -4 : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Random sphere directions (Sec. 2.2: rays towards random points on the     */
 /* surface of a sphere).  Random bits: Philox4x64 with 10 rounds (Salmon,   */
 /* Moraes, Dror, Shaw, SC'11), key (seed, 0), counter (texel, frame*2^32 +   */

@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(kSelBlock) select_count_batch(const SelScene *
 {
     const FlatRange &fr = flat_find(ranges, nr, blockIdx.x);
     const SelScene &S = sc[fr.scene];
-    select_count_body(S.d2, S.logn, S.K, S.total, S.sums, blockIdx.x - fr.first);
+    select_count_body(SelPred{S.d2, S.K, nullptr, 0.0f}, S.logn, S.total, S.sums, blockIdx.x - fr.first);
 }
 
 __global__ void __launch_bounds__(1024) select_scan_batch(const SelScene *__restrict__ sc)
@@ -158,7 +158,8 @@ __global__ void __launch_bounds__(kSelBlock) select_scatter_batch(const SelScene
 {
     const FlatRange &fr = flat_find(ranges, nr, blockIdx.x);
     const SelScene &S = sc[fr.scene];
-    select_scatter_body(S.d2, S.logn, S.K, S.total, S.sums, S.logr, S.nf, S.queue, S.cap, blockIdx.x - fr.first);
+    select_scatter_body(SelPred{S.d2, S.K, nullptr, 0.0f}, S.logn, S.total, S.sums, S.logr, S.nf, S.queue, S.cap,
+                        blockIdx.x - fr.first);
 }
 
 __global__ void __launch_bounds__(256) select_mask_batch(const SelScene *__restrict__ sc,
@@ -166,7 +167,7 @@ __global__ void __launch_bounds__(256) select_mask_batch(const SelScene *__restr
 {
     const FlatRange &fr = flat_find(ranges, nr, blockIdx.x);
     const SelScene &S = sc[fr.scene];
-    select_mask_body(S.d2, S.logn, S.logr, S.nf, S.K, S.nquads, S.mask4,
+    select_mask_body(SelPred{S.d2, S.K, nullptr, 0.0f}, S.logn, S.logr, S.nf, S.nquads, S.mask4,
                      (int64_t)(blockIdx.x - fr.first) * blockDim.x + threadIdx.x);
 }
 

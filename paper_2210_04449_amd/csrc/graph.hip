@@ -39,12 +39,27 @@ static int record_frame(const rtsdf_frame_graph &G, hipStream_t s)
     }
     rc = rtsdf_voxelize(D.vertices, D.nv, D.faces, D.nt, D.coarse, D.seeds, s);
     if (rc != RTSDF_OK) return rc;
-    rc = rtsdf_jfa(D.coarse, D.seeds, D.scratch, D.beta, D.dist2, D.coarse_sdf, s);
+    rc = D.jfa_steps ? rtsdf_jfa_steps(D.coarse, D.seeds, D.scratch, D.jfa_steps, D.jfa_nsteps, D.beta, D.dist2,
+                                       D.coarse_sdf, s)
+                     : rtsdf_jfa(D.coarse, D.seeds, D.scratch, D.beta, D.dist2, D.coarse_sdf, s);
     if (rc != RTSDF_OK) return rc;
-    rc = rtsdf_select(D.coarse, D.dist2, D.fine, D.beta, D.d, D.mask, D.queue, D.queue_cap, D.count, D.select_workspace,
-                      s);
+    // point sampling reads the containing coarse voxel; trilinear sampling
+    // interpolates the coarse field at the fine centres and then works on the
+    // fine grid alone
+    rtsdf_grid cgrid = D.coarse;
+    const float *cfield = D.coarse_sdf;
+    if (D.fine_c) {
+        rc = rtsdf_coarse_trilinear(D.coarse, D.coarse_sdf, D.fine, D.fine_c, s);
+        if (rc != RTSDF_OK) return rc;
+        rc = rtsdf_select_field(D.fine, D.fine_c, D.d, D.mask, D.queue, D.queue_cap, D.count, D.select_workspace, s);
+        cgrid = D.fine;
+        cfield = D.fine_c;
+    } else {
+        rc = rtsdf_select(D.coarse, D.dist2, D.fine, D.beta, D.d, D.mask, D.queue, D.queue_cap, D.count,
+                          D.select_workspace, s);
+    }
     if (rc != RTSDF_OK) return rc;
-    rc = rtsdf_trace_accumulate(D.scene, D.coarse, D.coarse_sdf, D.fine, D.mask, D.queue, D.count, D.queue_cap,
+    rc = rtsdf_trace_accumulate(D.scene, cgrid, cfield, D.fine, D.mask, D.queue, D.count, D.queue_cap,
                                 D.rays_per_texel, 0, D.frame_counter, D.seed, D.scene_id, D.alpha, D.state, D.fine_sdf,
                                 D.trace_workspace, s);
     if (rc != RTSDF_OK) return rc;
@@ -88,6 +103,7 @@ extern "C" int rtsdf_frame_graph_create(const rtsdf_frame_desc *desc, rtsdf_fram
     auto *g = new rtsdf_frame_graph();
     g->desc = *desc;
     const int rc = capture_graph(g, stream);
+    g->desc.jfa_steps = nullptr;  // the caller's host schedule is valid during this call only
     if (rc != RTSDF_OK) {
         rtsdf_frame_graph_destroy(g);
         return rc;

@@ -5,8 +5,15 @@ device memory) and calls the C ABI in the order of the paper's design
 (Sec. 2): coarse SDF by voxelization + jump flooding (Sec. 2.1), selection of
 the fine texels near surfaces and ray-traced temporal accumulation
 (Sec. 2.2).
+
+``sampling`` chooses how a fine texel reads the coarse SDF for the selection
+test c <= d and for c_t of Eq. (1): ``"point"`` (the coarse voxel containing
+the texel centre) or ``"trilinear"`` (the coarse field interpolated at the
+texel centre; the tracer then works on the fine grid alone).
 """
 from __future__ import annotations
+
+import ctypes as C
 
 import torch
 
@@ -17,7 +24,10 @@ class Pipeline:
     def __init__(self, vertices: torch.Tensor, faces: torch.Tensor, nc: int, nf: int, beta: float, d: float,
                  rays: int, seed: int = 0, scene_id: int = 0, alpha: float = 1.0, lo=(0.0, 0.0, 0.0),
                  side: float = 1.0, leaf_size: int = 2, queue_cap: int | None = None, device="cuda",
-                 jfa_variant: str = "jfa"):
+                 jfa_variant: str = "jfa", sampling: str = "point"):
+        if sampling not in ("point", "trilinear"):
+            raise ValueError(f"sampling must be 'point' or 'trilinear', not {sampling!r}")
+        self.sampling = sampling
         self.leaf_size = int(leaf_size)
         self.device = torch.device(device)
         self.vertices = vertices.to(self.device, torch.float32).contiguous()
@@ -37,7 +47,9 @@ class Pipeline:
         self.mask = torch.empty(nf ** 3, dtype=torch.uint8, device=dev)
         self.queue = torch.empty(nf ** 3 if queue_cap is None else int(queue_cap), dtype=i32, device=dev)
         self.count = torch.zeros(1, dtype=i32, device=dev)
-        self.sel_ws = torch.empty(R.rtsdf_select_workspace_size(nc), dtype=torch.uint8, device=dev)
+        tri = sampling == "trilinear"
+        self.fine_c = torch.empty(nf ** 3, dtype=f32, device=dev) if tri else None
+        self.sel_ws = torch.empty(R.rtsdf_select_workspace_size(nf if tri else nc), dtype=torch.uint8, device=dev)
         self.trace_ws = torch.empty(R.rtsdf_trace_workspace_size(), dtype=torch.uint8, device=dev)
         self.fine_sdf = torch.empty(nf ** 3, dtype=f32, device=dev)
         self.state = R.AccumState(self.fine, dev)
@@ -55,11 +67,21 @@ class Pipeline:
                               self.coarse_sdf, stream)
 
     def select(self, stream=None):
-        R.rtsdf_select(self.coarse, self.dist2, self.fine, self.beta, self.d, self.mask, self.queue, self.count,
-                       self.sel_ws, stream)
+        if self.fine_c is None:
+            R.rtsdf_select(self.coarse, self.dist2, self.fine, self.beta, self.d, self.mask, self.queue, self.count,
+                           self.sel_ws, stream)
+        else:
+            R.rtsdf_coarse_trilinear(self.coarse, self.coarse_sdf, self.fine, self.fine_c, stream)
+            R.rtsdf_select_field(self.fine, self.fine_c, self.d, self.mask, self.queue, self.count, self.sel_ws,
+                                 stream)
+
+    def trace_field(self):
+        """(grid, field) the tracer reads c_t from: the coarse SDF, or its trilinear samples on the fine grid."""
+        return (self.coarse, self.coarse_sdf) if self.fine_c is None else (self.fine, self.fine_c)
 
     def trace(self, frame: int, stream=None, frame_ptr=None):
-        R.rtsdf_trace_accumulate(self.scene, self.coarse, self.coarse_sdf, self.fine, self.mask, self.queue,
+        cgrid, cfield = self.trace_field()
+        R.rtsdf_trace_accumulate(self.scene, cgrid, cfield, self.fine, self.mask, self.queue,
                                  self.count, self.rays, frame, self.seed, self.scene_id, self.alpha, self.state,
                                  self.fine_sdf, self.trace_ws, frame_ptr=frame_ptr, stream=stream)
 
@@ -87,7 +109,12 @@ class Pipeline:
         D.state = self.state.struct()
         D.fine_sdf, D.trace_workspace = self.fine_sdf.data_ptr(), self.trace_ws.data_ptr()
         D.frame_counter = self.frame_counter.data_ptr()
-        return R.FrameGraph(D, keepalive=(self,))
+        D.fine_c = None if self.fine_c is None else self.fine_c.data_ptr()
+        steps = None
+        if self.jfa_steps is not None:
+            steps = (C.c_int32 * len(self.jfa_steps))(*self.jfa_steps)  # read during create only
+            D.jfa_steps, D.jfa_nsteps = C.cast(steps, C.c_void_p), len(self.jfa_steps)
+        return R.FrameGraph(D, keepalive=(self, steps))
 
     def set_vertices(self, vertices: torch.Tensor, stream=None):
         """New positions for the same topology (animated scenes): refit the hierarchy."""

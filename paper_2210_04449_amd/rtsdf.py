@@ -46,7 +46,8 @@ class FrameDesc(C.Structure):
                 ("seed", _u64), ("scene_id", _u32), ("alpha", _f32), ("seeds", _P), ("scratch", _P),
                 ("dist2", _P), ("coarse_sdf", _P), ("mask", _P), ("queue", _P), ("queue_cap", _i32),
                 ("count", _P), ("select_workspace", _P), ("state", Accum), ("fine_sdf", _P),
-                ("trace_workspace", _P), ("frame_counter", _P)]
+                ("trace_workspace", _P), ("frame_counter", _P), ("fine_c", _P),
+                ("jfa_steps", _P), ("jfa_nsteps", _i32)]
 
 
 class BatchScene(C.Structure):
@@ -97,6 +98,8 @@ def _load():
         "rtsdf_jfa_steps": ([Grid, _P, _P, C.POINTER(_i32), _i32, _f32, _P, _P, _P], _i32),
         "rtsdf_select_workspace_size": ([_i32], _sz),
         "rtsdf_select": ([Grid, _P, Grid, _f32, _f32, _P, _P, _i32, _P, _P, _P], _i32),
+        "rtsdf_coarse_trilinear": ([Grid, _P, Grid, _P, _P], _i32),
+        "rtsdf_select_field": ([Grid, _P, _f32, _P, _P, _i32, _P, _P, _P], _i32),
         "rtsdf_scene_create": ([_P, _i32, _P, _i32, _i32, C.POINTER(_P), _P], _i32),
         "rtsdf_scene_refit": ([_P, _P, _P], _i32),
         "rtsdf_scene_info_get": ([_P, C.POINTER(SceneInfo)], _i32),
@@ -224,6 +227,17 @@ def rtsdf_select(coarse: Grid, dist2, fine: Grid, beta: float, d: float, mask, q
     cap = 0 if queue is None else queue.numel()
     _check("rtsdf_select", _lib.rtsdf_select(coarse, _ptr(dist2), fine, float(beta), float(d), _ptr(mask),
                                              _ptr(queue), cap, _ptr(count), _ptr(workspace), _stream(stream)))
+
+
+def rtsdf_coarse_trilinear(coarse: Grid, coarse_sdf, fine: Grid, fine_c, stream=None):
+    _check("rtsdf_coarse_trilinear", _lib.rtsdf_coarse_trilinear(coarse, _ptr(coarse_sdf), fine, _ptr(fine_c),
+                                                                 _stream(stream)))
+
+
+def rtsdf_select_field(grid: Grid, field, d: float, mask, queue, count, workspace, stream=None):
+    cap = 0 if queue is None else queue.numel()
+    _check("rtsdf_select_field", _lib.rtsdf_select_field(grid, _ptr(field), float(d), _ptr(mask), _ptr(queue), cap,
+                                                         _ptr(count), _ptr(workspace), _stream(stream)))
 
 
 class Scene:

@@ -72,6 +72,16 @@ def test_host_validation(R):
     assert L.rtsdf_select(g, dummy, R.Grid.make(48), 0.0, 0.1, dummy, dummy, 10, dummy, dummy, None) == R.EINVAL
     # fine grid must cover the same box as the coarse one
     assert L.rtsdf_select(g, dummy, R.Grid.make(64, 1 / 32), 0.0, 0.1, dummy, dummy, 10, dummy, dummy, None) == R.EINVAL
+    # trilinear sampling: same box, power-of-two multiple, fine.n <= 1024; field selection grid in [4, 1024]
+    assert L.rtsdf_coarse_trilinear(g, dummy, R.Grid.make(48), dummy, None) == R.EINVAL
+    assert L.rtsdf_coarse_trilinear(g, dummy, R.Grid.make(64, 1 / 32), dummy, None) == R.EINVAL
+    assert L.rtsdf_coarse_trilinear(fine, dummy, g, dummy, None) == R.EINVAL  # fine coarser than coarse
+    assert L.rtsdf_coarse_trilinear(g, None, fine, dummy, None) == R.EINVAL
+    assert L.rtsdf_select_field(R.Grid.make(2), dummy, 0.1, dummy, dummy, 10, dummy, dummy, None) == R.EINVAL
+    assert L.rtsdf_select_field(R.Grid.make(2048), dummy, 0.1, dummy, dummy, 10, dummy, dummy, None) == R.EINVAL
+    assert L.rtsdf_select_field(fine, dummy, float("nan"), dummy, dummy, 10, dummy, dummy, None) == R.EINVAL
+    assert L.rtsdf_select_field(fine, dummy, 0.1, dummy, None, 10, dummy, dummy, None) == R.EINVAL  # no queue
+    assert L.rtsdf_select_field(fine, None, 0.1, dummy, dummy, 10, dummy, dummy, None) == R.EINVAL
     acc = R.Accum(16, 16, 16, 16)
     assert L.rtsdf_trace_accumulate(dummy, g, dummy, fine, dummy, dummy, dummy, 10, 0, 0, None, 0, 0, 1.0, acc,
                                     dummy, dummy, None) == R.EINVAL  # zero rays
