@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--leaf-size", type=int, default=2)
     ap.add_argument("--jfa", default="jfa", choices=["jfa", "jfa+1", "jfa+2", "1+jfa"],
                     help="jump-flooding pass schedule (the extra-pass variants reduce its errors)")
+    ap.add_argument("--no-shadow", action="store_true", help="skip timing the soft-shadow consumer")
     ap.add_argument("--sampling", default="point", choices=["point", "trilinear"],
                     help="how a fine texel reads the coarse SDF for selection and c_t")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -221,6 +222,8 @@ def main():
         graph_ms = gs.elapsed_time(ge) / reps
         g.close()
 
+    shadow = None if args.no_shadow else time_shadow(R, p, w, stream)
+
     # HBM bytes per trace launch from the committed PMC summary of this workload, when it was taken on the
     # current kernel sources (else null)
     from paper_2210_04449_amd.prof_summary import traffic_from_summary
@@ -272,6 +275,7 @@ def main():
                         "bvh_nodes": info.nodes, "bvh_references": info.references, "bvh_max_depth": info.max_depth,
                         "bvh_max_leaf": info.leaf_size, "leaf_size": args.leaf_size},
         "trace_tuning": tuning,
+        "shadow": shadow,
         "roofline": {
             "kernel": "trace_persistent",
             "bound": "alu",
@@ -288,6 +292,49 @@ def main():
     if not args.no_cpu_baseline and args.config != "dynamic":
         out["cpu_baseline"] = cpu_baseline(w, selected, args.cpu_seconds, args.sampling)
     print(json.dumps(out), flush=True)
+
+
+def time_shadow(R, p, w, stream, npts: int = 1920 * 1080):
+    """Soft shadows (Sec. 2.3) from the fine SDF the updates produced, for one 1080p frame of shading points:
+    points drawn (seeded) from the texel centres within one to three fine texels of a surface, a fixed
+    light; cone and triangulated penumbra, jittered starts; occluders searched up to 0.3 of the domain side
+    (the room is closed, so an unbounded march from inside would always end on a wall).  Outside the timed
+    update."""
+    import torch
+
+    h = 1.0 / w.nf
+    f = p.fine_sdf
+    near = torch.nonzero((f >= h) & (f <= 3 * h)).flatten()
+    if near.numel() == 0:
+        return None
+    g = torch.Generator(device=f.device).manual_seed(1)
+    pick = near[torch.randint(0, near.numel(), (npts,), device=f.device, generator=g)]
+    nf = w.nf
+    ijk = torch.stack([pick % nf, (pick // nf) % nf, pick // (nf * nf)], 1).to(torch.float32)
+    pts = ((ijk + 0.5) * h).contiguous()
+    jit = torch.rand(npts, device=f.device, generator=g)
+    light = [0.3, 0.9, 0.2]
+    nrm = sum(x * x for x in light) ** 0.5
+    light = [x / nrm for x in light]
+    vis = torch.empty(npts, dtype=torch.float32, device=f.device)
+    out = {"points": npts, "max_steps": 96, "eps_texels": 1, "max_step_texels": 2, "max_dist": 0.3}
+    for name, pen in (("cone", 0), ("triangulated", 1)):
+        def run():
+            R.rtsdf_shadow_ex(p.fine, f, pts, light, 8.0, h, 96, 2 * h, 0.3, vis, penumbra=pen, jitter=jit,
+                              jitter_scale=2 * h)
+        run()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(5):
+            run()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 5
+        out[f"{name}_ms"] = round(ms, 4)
+        out[f"{name}_points_per_s"] = round(npts / ms * 1e3, 1)
+        out[f"{name}_mean_visibility"] = round(float(vis.mean().item()), 4)
+    return out
 
 
 def _base_record(args, value_ms, config):

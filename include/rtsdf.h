@@ -447,6 +447,32 @@ int rtsdf_shadow(rtsdf_grid fine, const float *fine_sdf, const float *points, in
                  const float light_dir[3], float k, float eps, int32_t max_steps, float max_step,
                  float max_dist, float *visibility, rtsdf_stream stream);
 
+/* The march with the two further options of Sec. 2.3.                       */
+/*  * jitter (float32 [np], device, values in [0, 1), or NULL): the march of */
+/*    point p starts at t = eps + jitter[p] * jitter_scale, i.e. its origin  */
+/*    moves towards the light (the caller draws new values per frame and     */
+/*    filters the result over time; that filter is not part of the library). */
+/*  * penumbra = 1: triangulation between consecutive samples (Aaltonen      */
+/*    2018, cited for the banding fix).  With the previous sample s_prev at   */
+/*    t_prev and the current s at t, D = t - t_prev,                         */
+/*    y = ((D*D + s*s) - s_prev*s_prev) / (D + D) clamped to [0, s],          */
+/*    d = sqrt(max(s*s - y*y, 0)), and min(vis, (k*d) / (t - y)) is folded   */
+/*    in when t - y > 0 (the first sample uses k*s/t).  penumbra = 0 is the   */
+/*    cone term of rtsdf_shadow.                                             */
+/* Every float operation is rounded once in the order written, as for       */
+/* rtsdf_shadow.  params is a host pointer; EINVAL as rtsdf_shadow, and for  */
+/* penumbra outside {0, 1} or a negative or NaN jitter_scale with jitter.    */
+typedef struct rtsdf_shadow_params {
+    float light_dir[3];
+    float k, eps;
+    int32_t max_steps;
+    float max_step, max_dist;
+    int32_t penumbra;
+    float jitter_scale;
+} rtsdf_shadow_params;
+int rtsdf_shadow_ex(rtsdf_grid fine, const float *fine_sdf, const float *points, int32_t np,
+                    const rtsdf_shadow_params *params, const float *jitter, float *visibility, rtsdf_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

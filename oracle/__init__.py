@@ -73,7 +73,7 @@ def lib():
                                          P, P, P, P, P, P, P, P, P]
         L.oracle_fine_grad.argtypes = [P, i32, P, f32, u64, u32, P, P, P, P, P, P]
         L.oracle_directions.argtypes = [i32, P, P, P, u64, u32, P]
-        L.oracle_shadow.argtypes = [i32, P, f32, P, i32, P, P, f32, f32, i32, f32, f32, P]
+        L.oracle_shadow.argtypes = [i32, P, f32, P, i32, P, P, f32, f32, i32, f32, f32, i32, P, f32, P]
         _lib = L
     return _lib
 
@@ -194,15 +194,19 @@ def directions(texel, frame, ray, seed: int = 0, scene: int = 0) -> np.ndarray:
 
 
 def shadow(n: int, lo, h: float, sdf, points, light, k: float, eps: float, max_steps: int, max_step: float,
-           max_dist: float) -> np.ndarray:
-    """Soft-shadow visibility of each point (Sec. 2.3), float32 [np]."""
+           max_dist: float, penumbra: int = 0, jitter=None, jitter_scale: float = 0.0) -> np.ndarray:
+    """Soft-shadow visibility of each point (Sec. 2.3), float32 [np].  penumbra 0: cone term k s / t;
+    1: triangulated between consecutive samples.  jitter [np] in [0, 1) moves each march's start by
+    jitter * jitter_scale towards the light."""
     lo = _c(lo, np.float32)
     s = _c(sdf, np.float32)
     pts = _c(points, np.float32).reshape(-1, 3)
     l = _c(light, np.float32)
+    jt = None if jitter is None else _c(jitter, np.float32)
     out = np.empty(pts.shape[0], np.float32)
     lib().oracle_shadow(int(n), _p(lo), float(h), _p(s), pts.shape[0], _p(pts), _p(l), float(k), float(eps),
-                        int(max_steps), float(max_step), float(max_dist), _p(out))
+                        int(max_steps), float(max_step), float(max_dist), int(penumbra), _p(jt),
+                        float(jitter_scale), _p(out))
     return out
 
 

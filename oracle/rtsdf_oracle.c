@@ -1034,6 +1034,22 @@ void oracle_directions(int n, const int *texel, const uint32_t *frame, const int
 /*   g > n - 1/2); g clamped to [0, n-1]; i = min(floor(g), n-2); f = g - i; */
 /*   lerp(a, b, f) = a + f (b - a), along x, then y, then z;                 */
 /*   vis = min(vis, (k s) / t);  t = t + max(min(s, max_step), eps).         */
+/*                                                                           */
+/* Two options of Sec. 2.3:                                                  */
+/*  * jitter: the march starts at t = eps + jitter[p] * jitter_scale, i.e.   */
+/*    the origin is moved towards the light by a per-point random amount     */
+/*    (the caller draws jitter in [0, 1), per frame, and filters over time). */
+/*  * triangulation (penumbra = 1; Aaltonen 2018, cited for the banding      */
+/*    fix): consecutive samples s_prev at t_prev and s at t are two empty    */
+/*    spheres along the ray; the nearest occluder is estimated on the circle */
+/*    where they intersect, at distance y back from the current point and    */
+/*    radius d from the ray:                                                 */
+/*      D = t - t_prev,  y = ((D D + s s) - s_prev s_prev) / (D + D),        */
+/*      y clamped to [0, s],  d = sqrt(max(s s - y y, 0)),                    */
+/*      vis = min(vis, (k d) / (t - y))  if t - y > 0.                       */
+/*    With D = s_prev (an unclamped sphere-tracing step) y = s^2/(2 s_prev), */
+/*    the published form.  The first sample has no predecessor and uses the  */
+/*    cone term k s / t.                                                     */
 /* ------------------------------------------------------------------------ */
 static int shadow_axis(float q, float lo, float h, int n, int *i, float *f)
 {
@@ -1060,11 +1076,19 @@ static float lerpf_(float a, float b, float f)
 }
 
 void oracle_shadow(int n, const float lo[3], float h, const float *sdf, int np, const float *pts, const float l[3],
-                   float k, float eps, int max_steps, float max_step, float max_dist, float *vis_out)
+                   float k, float eps, int max_steps, float max_step, float max_dist, int penumbra,
+                   const float *jitter, float jitter_scale, float *vis_out)
 {
 #pragma omp parallel for schedule(static)
     for (int p = 0; p < np; ++p) {
         float vis = 1.0f, t = eps;
+        if (jitter) {
+            volatile float off = jitter[p] * jitter_scale;
+            volatile float t0 = eps + off;
+            t = t0;
+        }
+        int have_prev = 0;
+        float t_prev = 0.0f, s_prev = 0.0f;
         for (int step = 0; step < max_steps; ++step) {
             if (t > max_dist) break;
             float q[3];
@@ -1089,9 +1113,34 @@ void oracle_shadow(int n, const float lo[3], float h, const float *sdf, int np, 
                 vis = 0.0f;
                 break;
             }
-            volatile float ks = k * s;
-            volatile float pen = ks / t;
-            if (pen < vis) vis = pen;
+            if (penumbra == 1 && have_prev) {
+                volatile float D = t - t_prev;
+                volatile float DD = D * D;
+                volatile float ss = s * s;
+                volatile float sum = DD + ss;
+                volatile float pp = s_prev * s_prev;
+                volatile float num = sum - pp;
+                volatile float den = D + D;
+                volatile float y = num / den;
+                float yc = y > 0.0f ? y : 0.0f;
+                if (yc > s) yc = s;
+                volatile float yy = yc * yc;
+                volatile float r = ss - yy;
+                const float d = sqrtf(r > 0.0f ? r : 0.0f);
+                volatile float w = t - yc;
+                if (w > 0.0f) {
+                    volatile float kd = k * d;
+                    volatile float pen = kd / w;
+                    if (pen < vis) vis = pen;
+                }
+            } else {
+                volatile float ks = k * s;
+                volatile float pen = ks / t;
+                if (pen < vis) vis = pen;
+            }
+            have_prev = 1;
+            t_prev = t;
+            s_prev = s;
             float st = s < max_step ? s : max_step;
             if (st < eps) st = eps;
             volatile float tn = t + st;

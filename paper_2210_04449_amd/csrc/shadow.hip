@@ -5,7 +5,12 @@
 // the nearest texel, and the step is capped (the paper notes the cap removes
 // banding at the price of more samples).  The penumbra term is the running
 // minimum of k * s / t (the cone estimate of the SDF shadow technique the
-// paper cites).
+// paper cites), or, with triangulation between consecutive samples (the
+// banding fix the paper takes from Aaltonen 2018), k * d / (t - y) with the
+// clearance d and position y estimated where the two samples' empty spheres
+// intersect.  The start of the march can be jittered towards the light by a
+// caller-supplied amount per point (the paper jitters the origin and filters
+// the noise over time).
 //
 // Every float operation below is an explicitly rounded intrinsic in a fixed
 // order, so the march (including its data-dependent stopping decisions) is
@@ -28,21 +33,32 @@ __device__ __forceinline__ bool grid_coord(float q, float lo, float h, int n, in
     return true;
 }
 
-__global__ void __launch_bounds__(256) shadow_kernel(rtsdf_grid g, const float *__restrict__ sdf,
-                                                     const float *__restrict__ pts, int np, float lx, float ly,
-                                                     float lz, float k, float eps, int max_steps, float max_step,
-                                                     float max_dist, float *__restrict__ vis_out)
+struct ShadowArgs {
+    rtsdf_grid g;
+    const float *sdf, *pts, *jitter;
+    int np;
+    float lx, ly, lz, k, eps, max_step, max_dist, jitter_scale;
+    int max_steps, penumbra;
+};
+
+__global__ void __launch_bounds__(256) shadow_kernel(ShadowArgs A, float *__restrict__ vis_out)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
+    if (p >= A.np) return;
+    const rtsdf_grid &g = A.g;
+    const float *__restrict__ sdf = A.sdf;
     const int n = g.n;
-    const float px = pts[3 * p], py = pts[3 * p + 1], pz = pts[3 * p + 2];
+    const float px = A.pts[3 * p], py = A.pts[3 * p + 1], pz = A.pts[3 * p + 2];
+    const float eps = A.eps, k = A.k;
     float vis = 1.0f, t = eps;
-    for (int step = 0; step < max_steps; ++step) {
-        if (t > max_dist) break;
-        const float qx = rn_add(px, rn_mul(t, lx));
-        const float qy = rn_add(py, rn_mul(t, ly));
-        const float qz = rn_add(pz, rn_mul(t, lz));
+    if (A.jitter) t = rn_add(eps, rn_mul(A.jitter[p], A.jitter_scale));
+    bool have_prev = false;
+    float t_prev = 0.0f, s_prev = 0.0f;
+    for (int step = 0; step < A.max_steps; ++step) {
+        if (t > A.max_dist) break;
+        const float qx = rn_add(px, rn_mul(t, A.lx));
+        const float qy = rn_add(py, rn_mul(t, A.ly));
+        const float qz = rn_add(pz, rn_mul(t, A.lz));
         int ix, iy, iz;
         float fx, fy, fz;
         if (!grid_coord(qx, g.lo[0], g.h, n, ix, fx) || !grid_coord(qy, g.lo[1], g.h, n, iy, fy) ||
@@ -59,26 +75,72 @@ __global__ void __launch_bounds__(256) shadow_kernel(rtsdf_grid g, const float *
             vis = 0.0f;
             break;
         }
-        vis = fminf(vis, rn_div(rn_mul(k, s), t));
-        t = rn_add(t, fmaxf(fminf(s, max_step), eps));
+        if (A.penumbra == 1 && have_prev) {
+            // the empty spheres of radius s_prev (at t_prev) and s (at t)
+            // intersect on a circle y behind the current sample; its radius d
+            // is the estimated clearance of the ray
+            const float D = rn_sub(t, t_prev);
+            const float ss = rn_mul(s, s);
+            const float num = rn_sub(rn_add(rn_mul(D, D), ss), rn_mul(s_prev, s_prev));
+            const float y = fminf(fmaxf(rn_div(num, rn_add(D, D)), 0.0f), s);
+            const float d = rn_sqrt(fmaxf(rn_sub(ss, rn_mul(y, y)), 0.0f));
+            const float w = rn_sub(t, y);
+            if (w > 0.0f) vis = fminf(vis, rn_div(rn_mul(k, d), w));
+        } else {
+            vis = fminf(vis, rn_div(rn_mul(k, s), t));
+        }
+        have_prev = true;
+        t_prev = t;
+        s_prev = s;
+        t = rn_add(t, fmaxf(fminf(s, A.max_step), eps));
     }
     vis_out[p] = fmaxf(vis, 0.0f);
 }
 
 }  // namespace rtsdf
 
+static int shadow_launch(rtsdf_grid fine, const float *fine_sdf, const float *points, int32_t np,
+                         const rtsdf_shadow_params &P, const float *jitter, float *visibility, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!grid_ok(fine) || fine.n < 2 || !fine_sdf || np < 0 || (np > 0 && (!points || !visibility)))
+        return RTSDF_EINVAL;
+    if (!(P.eps > 0.0f) || P.max_steps < 0 || !(P.max_step > 0.0f) || !(P.k > 0.0f) || !(P.max_dist >= 0.0f))
+        return RTSDF_EINVAL;
+    if (P.penumbra != 0 && P.penumbra != 1) return RTSDF_EINVAL;
+    if (jitter && !(P.jitter_scale >= 0.0f)) return RTSDF_EINVAL;
+    if (np == 0) return RTSDF_OK;
+    const ShadowArgs A{fine,         fine_sdf, points, jitter,     np,         P.light_dir[0],
+                       P.light_dir[1], P.light_dir[2], P.k, P.eps, P.max_step, P.max_dist,
+                       P.jitter_scale, P.max_steps, P.penumbra};
+    shadow_kernel<<<dim3((np + 255) / 256), dim3(256), 0, as_stream(stream)>>>(A, visibility);
+    RTSDF_CHECK_LAUNCH();
+    return RTSDF_OK;
+}
+
 extern "C" int rtsdf_shadow(rtsdf_grid fine, const float *fine_sdf, const float *points, int32_t np,
                             const float light_dir[3], float k, float eps, int32_t max_steps, float max_step,
                             float max_dist, float *visibility, rtsdf_stream stream)
 {
-    using namespace rtsdf;
-    if (!grid_ok(fine) || fine.n < 2 || !fine_sdf || np < 0 || (np > 0 && (!points || !visibility)) || !light_dir)
-        return RTSDF_EINVAL;
-    if (!(eps > 0.0f) || max_steps < 0 || !(max_step > 0.0f) || !(k > 0.0f) || !(max_dist >= 0.0f)) return RTSDF_EINVAL;
-    if (np == 0) return RTSDF_OK;
-    shadow_kernel<<<dim3((np + 255) / 256), dim3(256), 0, as_stream(stream)>>>(
-        fine, fine_sdf, points, np, light_dir[0], light_dir[1], light_dir[2], k, eps, max_steps, max_step, max_dist,
-        visibility);
-    RTSDF_CHECK_LAUNCH();
-    return RTSDF_OK;
+    if (!light_dir) return RTSDF_EINVAL;
+    rtsdf_shadow_params P{};
+    P.light_dir[0] = light_dir[0];
+    P.light_dir[1] = light_dir[1];
+    P.light_dir[2] = light_dir[2];
+    P.k = k;
+    P.eps = eps;
+    P.max_steps = max_steps;
+    P.max_step = max_step;
+    P.max_dist = max_dist;
+    P.penumbra = 0;
+    P.jitter_scale = 0.0f;
+    return shadow_launch(fine, fine_sdf, points, np, P, nullptr, visibility, stream);
+}
+
+extern "C" int rtsdf_shadow_ex(rtsdf_grid fine, const float *fine_sdf, const float *points, int32_t np,
+                               const rtsdf_shadow_params *params, const float *jitter, float *visibility,
+                               rtsdf_stream stream)
+{
+    if (!params) return RTSDF_EINVAL;
+    return shadow_launch(fine, fine_sdf, points, np, *params, jitter, visibility, stream);
 }

@@ -40,6 +40,11 @@ class Accum(C.Structure):
     _fields_ = [("u", _P), ("hits", _P), ("arg_tri", _P), ("arg_ray", _P)]
 
 
+class ShadowParams(C.Structure):
+    _fields_ = [("light_dir", _f32 * 3), ("k", _f32), ("eps", _f32), ("max_steps", _i32), ("max_step", _f32),
+                ("max_dist", _f32), ("penumbra", _i32), ("jitter_scale", _f32)]
+
+
 class FrameDesc(C.Structure):
     _fields_ = [("vertices", _P), ("nv", _i32), ("faces", _P), ("nt", _i32), ("scene", _P), ("refit", _i32),
                 ("coarse", Grid), ("fine", Grid), ("beta", _f32), ("d", _f32), ("rays_per_texel", _i32),
@@ -114,6 +119,7 @@ def _load():
         "rtsdf_closest_hits": ([_P, _P, _P, _i32, _P, _P, _P, _P], _i32),
         "rtsdf_trace_backward": ([_P, Grid, Accum, _P, _P, _u64, _u32, _P, _P], _i32),
         "rtsdf_shadow": ([Grid, _P, _P, _i32, _P, _f32, _f32, _i32, _f32, _f32, _P, _P], _i32),
+        "rtsdf_shadow_ex": ([Grid, _P, _P, _i32, C.POINTER(ShadowParams), _P, _P, _P], _i32),
         "rtsdf_frame_graph_create": ([C.POINTER(FrameDesc), C.POINTER(_P), _P], _i32),
         "rtsdf_frame_graph_launch": ([_P, _P], _i32),
         "rtsdf_frame_graph_destroy": ([_P], None),
@@ -353,6 +359,15 @@ def rtsdf_shadow(fine: Grid, fine_sdf, points, light_dir, k: float, eps: float, 
     _check("rtsdf_shadow", _lib.rtsdf_shadow(fine, _ptr(fine_sdf), _ptr(points), points.shape[0], ld, float(k),
                                              float(eps), int(max_steps), float(max_step), float(max_dist),
                                              _ptr(visibility), _stream(stream)))
+
+
+def rtsdf_shadow_ex(fine: Grid, fine_sdf, points, light_dir, k: float, eps: float, max_steps: int, max_step: float,
+                    max_dist: float, visibility, penumbra: int = 0, jitter=None, jitter_scale: float = 0.0,
+                    stream=None):
+    P = ShadowParams((_f32 * 3)(*[float(x) for x in light_dir]), float(k), float(eps), int(max_steps),
+                     float(max_step), float(max_dist), int(penumbra), float(jitter_scale))
+    _check("rtsdf_shadow_ex", _lib.rtsdf_shadow_ex(fine, _ptr(fine_sdf), _ptr(points), points.shape[0], C.byref(P),
+                                                   _ptr(jitter), _ptr(visibility), _stream(stream)))
 
 
 class FrameGraph:

@@ -91,6 +91,11 @@ def test_host_validation(R):
                                     dummy, dummy, None) == R.EINVAL
     ld = (C.c_float * 3)(0, 1, 0)
     assert L.rtsdf_shadow(fine, dummy, dummy, 4, ld, 8.0, 0.0, 16, 0.1, 1.0, dummy, None) == R.EINVAL  # eps 0
+    sp = R.ShadowParams(ld, 8.0, 0.01, 16, 0.1, 1.0, 2, 0.0)  # penumbra 2
+    assert L.rtsdf_shadow_ex(fine, dummy, dummy, 4, C.byref(sp), None, dummy, None) == R.EINVAL
+    sp.penumbra, sp.jitter_scale = 1, -1.0  # negative jitter scale with a jitter array
+    assert L.rtsdf_shadow_ex(fine, dummy, dummy, 4, C.byref(sp), dummy, dummy, None) == R.EINVAL
+    assert L.rtsdf_shadow_ex(fine, dummy, dummy, 4, None, None, dummy, None) == R.EINVAL
     for bad in (dict(refill=3), dict(loop=4), dict(stack_lds=20), dict(bin_directions=5), dict(blocks_per_cu=-1)):
         t = R.TraceTuning(**{**R.rtsdf_trace_config_get().as_dict(), **bad})
         assert L.rtsdf_trace_config(C.byref(t)) == R.EINVAL
@@ -113,6 +118,7 @@ def test_struct_layouts_match_header(R, tmp_path):
         "rtsdf_frame_desc": (R.FrameDesc, [f for f, _ in R.FrameDesc._fields_]),
         "rtsdf_batch_scene": (R.BatchScene, [f for f, _ in R.BatchScene._fields_]),
         "rtsdf_batch_view": (R.BatchView, [f for f, _ in R.BatchView._fields_]),
+        "rtsdf_shadow_params": (R.ShadowParams, [f for f, _ in R.ShadowParams._fields_]),
     }
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "rtsdf.h"', "int main(void) {"]
     for cname, (_, fields) in structs.items():

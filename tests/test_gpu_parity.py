@@ -465,3 +465,32 @@ def test_shadow_bit_exact(R):
     want = oracle.shadow(w.nf, LO, np.float32(h), sdf, pts, light, 8.0, h, 96, 2 * h, 2.0)
     assert np.array_equal(got.view(np.int32), want.view(np.int32)), int((got != want).sum())
     assert (got == 0).mean() > 0.05 and (got == 1).mean() > 0.05  # umbra and lit points both present
+
+
+@pytest.mark.parametrize("penumbra,jittered", [(0, True), (1, False), (1, True)])
+def test_shadow_triangulated_and_jittered_bit_exact(R, penumbra, jittered):
+    say("shadow ex", penumbra, jittered)
+    w = workload("tiny")
+    p = run_gpu(R, w, range(4))
+    sdf = p.fine_sdf.cpu().numpy()
+    rng = np.random.default_rng(7)
+    n = 30001  # ragged against the 256-lane workgroups
+    pts = np.column_stack([rng.uniform(0, 1, n), np.full(n, 0.16), rng.uniform(0, 1, n)]).astype(np.float32)
+    pts[:5] = [[-0.5, 0.2, 0.5], [0.5, 1.5, 0.5], [0.5, 0.16, 0.5], [0.0, 0.16, 0.0], [0.999, 0.16, 0.999]]
+    light = np.array([0.3, 0.9, 0.2], np.float32)
+    light /= np.linalg.norm(light)
+    jit = rng.uniform(0, 1, n).astype(np.float32) if jittered else None
+    h = 1.0 / w.nf
+    vis = torch.empty(n, dtype=torch.float32, device="cuda")
+    R.rtsdf_shadow_ex(p.fine, p.fine_sdf, cu(pts), light, 8.0, h, 96, 2 * h, 2.0, vis, penumbra=penumbra,
+                      jitter=None if jit is None else cu(jit), jitter_scale=2 * h)
+    got = vis.cpu().numpy()
+    want = oracle.shadow(w.nf, LO, np.float32(h), sdf, pts, light, 8.0, h, 96, 2 * h, 2.0, penumbra=penumbra,
+                         jitter=jit, jitter_scale=2 * h)
+    assert np.array_equal(got.view(np.int32), want.view(np.int32)), int((got != want).sum())
+    assert (got == 0).mean() > 0.05 and (got == 1).mean() > 0.01
+    if penumbra == 0 and not jittered:
+        return
+    # the options change the penumbra, not the umbra test
+    base = oracle.shadow(w.nf, LO, np.float32(h), sdf, pts, light, 8.0, h, 96, 2 * h, 2.0)
+    assert not np.array_equal(base, got)
