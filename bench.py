@@ -55,6 +55,11 @@ def parse():
     ap.add_argument("--leaf-size", type=int, default=2)
     ap.add_argument("--jfa", default="jfa", choices=["jfa", "jfa+1", "jfa+2", "1+jfa"],
                     help="jump-flooding pass schedule (the extra-pass variants reduce its errors)")
+    ap.add_argument("--study", default=None, choices=["alpha"],
+                    help="instead of the benchmark: decay alpha against stale history on the moving scene")
+    ap.add_argument("--alphas", type=float, nargs="+", default=[1.0, 0.95, 0.9, 0.75, 0.5])
+    ap.add_argument("--study-frames", type=int, default=24)
+    ap.add_argument("--alpha", type=float, default=None, help="override the workload's decay alpha")
     ap.add_argument("--no-shadow", action="store_true", help="skip timing the soft-shadow consumer")
     ap.add_argument("--sampling", default="point", choices=["point", "trilinear"],
                     help="how a fine texel reads the coarse SDF for selection and c_t")
@@ -124,6 +129,8 @@ def main():
     from paper_2210_04449_amd.pipeline import Pipeline
     from synth.scenes import workload
 
+    if args.study == "alpha":
+        return run_alpha_study(args)
     if args.config == "batched":
         return run_batched(args)
     if args.config == "diff":
@@ -141,7 +148,8 @@ def main():
         del a, b
     R.rtsdf_trace_config(**tuning)
     p = Pipeline(torch.from_numpy(w.mesh.vertices).to(dev), torch.from_numpy(w.mesh.faces).to(dev), w.nc, w.nf,
-                 w.beta, w.d, w.rays, seed=0, scene_id=w.scene_seed, alpha=w.alpha, leaf_size=args.leaf_size,
+                 w.beta, w.d, w.rays, seed=0, scene_id=w.scene_seed,
+                 alpha=w.alpha if args.alpha is None else args.alpha, leaf_size=args.leaf_size,
                  jfa_variant=args.jfa, sampling=args.sampling)
     info = p.scene.info()
     stream = torch.cuda.current_stream()
@@ -223,6 +231,7 @@ def main():
         g.close()
 
     shadow = None if args.no_shadow else time_shadow(R, p, w, stream)
+    acc = accuracy(R, p)
 
     # HBM bytes per trace launch from the committed PMC summary of this workload, when it was taken on the
     # current kernel sources (else null)
@@ -252,7 +261,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{w.name}: {w.mesh.nt} triangles, coarse {w.nc}^3 / fine {w.nf}^3, beta {w.beta_vox} "
-                        f"and d {w.d_vox} coarse voxels, {w.rays} rays/texel/frame, alpha {w.alpha}",
+                        f"and d {w.d_vox} coarse voxels, {w.rays} rays/texel/frame, alpha {p.alpha}",
             "triangles": w.mesh.nt,
             "coarse": w.nc,
             "fine": w.nf,
@@ -276,6 +285,7 @@ def main():
                         "bvh_max_leaf": info.leaf_size, "leaf_size": args.leaf_size},
         "trace_tuning": tuning,
         "shadow": shadow,
+        "accuracy": acc,
         "roofline": {
             "kernel": "trace_persistent",
             "bound": "alu",
@@ -335,6 +345,93 @@ def time_shadow(R, p, w, stream, npts: int = 1920 * 1080):
         out[f"{name}_points_per_s"] = round(npts / ms * 1e3, 1)
         out[f"{name}_mean_visibility"] = round(float(vis.mean().item()), 4)
     return out
+
+
+def accuracy(R, p, tol_texels: float = 0.25):
+    """Traced state u against the exact distance to the current geometry, over the selected texels.
+
+    For static geometry Eq. (1) keeps u >= min(exact, max(c, 0)): every hit is on the mesh, and the decayed
+    term never drops below the smaller of the previous u and max(c, 0).  With alpha < 1, u is pulled towards
+    max(c, 0), which lies below the exact distance (the coarse field is biased down by beta), so "below exact"
+    mixes that pull with stale history.  Stale history proper is u below min(exact, max(c, 0)): only geometry
+    that has moved away can leave it ("ghost")."""
+    import torch
+
+    n = p.selected()
+    if n == 0:
+        return None
+    q = p.queue[:n]
+    exact = torch.empty(n, dtype=torch.float32, device=q.device)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    R.rtsdf_texel_distance(p.scene, p.fine, q, exact)
+    b.record()
+    ql = q.long()
+    u = p.state.u[ql]
+    cgrid, cfield = p.trace_field()
+    if cgrid.n == p.nf:
+        c = cfield[ql]
+    else:
+        r = p.nf // cgrid.n
+        nf, ncg = p.nf, cgrid.n
+        c = cfield[(ql % nf) // r + ncg * (((ql // nf) % nf) // r + ncg * ((ql // (nf * nf)) // r))]
+    fin = torch.isfinite(u)
+    u, exact, c = u[fin].double(), exact[fin].double(), c[fin].double()
+    gap = u - exact
+    h = 1.0 / p.nf
+    floor_ = torch.minimum(exact, c.clamp(min=0))
+    ghost = (floor_ - u) > tol_texels * h
+    qs = torch.quantile(gap[torch.randperm(gap.numel(), device=gap.device)[:1 << 20]],
+                        torch.tensor([0.5, 0.95, 0.99], dtype=torch.float64, device=gap.device)).tolist()
+    torch.cuda.synchronize()
+    return {
+        "texels": n,
+        "finite_fraction": round(fin.float().mean().item(), 5),
+        "traced_minus_exact_texels": {"mean": round(gap.mean().item() / h, 4), "p50": round(qs[0] / h, 4),
+                                      "p95": round(qs[1] / h, 4), "p99": round(qs[2] / h, 4),
+                                      "max": round(gap.max().item() / h, 3)},
+        "abs_err_mean_texels": round(gap.abs().mean().item() / h, 4),
+        "below_exact_fraction": round((gap < -tol_texels * h).double().mean().item(), 6),
+        "ghost_fraction": round(ghost.double().mean().item(), 6),
+        "ghost_mean_texels": round(((floor_ - u).clamp(min=0)).mean().item() / h, 5),
+        "exact_distance_ms": round(a.elapsed_time(b), 3),
+    }
+
+
+def run_alpha_study(args):
+    """Decay alpha of Eq. (1) against stale history on the moving-scene workload: the same continuous motion
+    replayed for each alpha, then the traced state compared with the exact distance to the final geometry;
+    the same frames on the motionless scene give each alpha's error without motion."""
+    import torch
+
+    import paper_2210_04449_amd.rtsdf as R
+    from paper_2210_04449_amd.pipeline import Pipeline
+    from synth.scenes import workload
+
+    w = workload("dynamic")
+    dyn = w.extra["scene"]
+    dev = torch.device("cuda:0")
+    frames = args.study_frames
+    verts = [torch.from_numpy(dyn.mesh(f).vertices).to(dev) for f in range(frames)]
+    p = Pipeline(verts[0].clone(), torch.from_numpy(w.mesh.faces).to(dev), w.nc, w.nf, w.beta, w.d, w.rays,
+                 scene_id=w.scene_seed, alpha=1.0, leaf_size=args.leaf_size)
+    rows = []
+    for alpha in args.alphas:
+        p.alpha = float(alpha)
+        for moving in (True, False):
+            p.reset()
+            for f in range(frames):
+                p.set_vertices(verts[f] if moving else verts[-1])
+                p.step(f)
+            torch.cuda.synchronize()
+            acc = accuracy(R, p)
+            rows.append({"alpha": alpha, "moving": moving, **acc})
+            print(f"[alpha {alpha} moving {moving}] ghost {acc['ghost_fraction']:.4f}, "
+                  f"below exact {acc['below_exact_fraction']:.4f}, "
+                  f"|traced-exact| mean {acc['abs_err_mean_texels']:.3f} texels", file=sys.stderr, flush=True)
+    print(json.dumps({"study": "alpha vs stale history", "workload": w.name, "frames": frames,
+                      "fine": w.nf, "rays_per_texel": w.rays, "motion": "20% of primitives rigid, continuous",
+                      "units": "fine texels", "rows": rows}), flush=True)
 
 
 def _base_record(args, value_ms, config):

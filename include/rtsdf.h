@@ -434,6 +434,29 @@ int rtsdf_batch_graph_create(rtsdf_batch *batch, uint32_t *frame_counter, rtsdf_
 void rtsdf_batch_destroy(rtsdf_batch *batch);
 
 /* ------------------------------------------------------------------------ */
+/* Exact unsigned distance to the scene's triangles: the value the traced    */
+/* fine SDF approaches from above (Sec. 2.2: every ray hit lies on the mesh, */
+/* so for the current geometry a traced distance is never below it).  For    */
+/* measuring the method's accuracy and, in moving scenes, stale history      */
+/* (Eq. (1)'s decay alpha).  Computed in float32 by a best-first descent of  */
+/* the scene's hierarchy; whole triangles are tested (split references are   */
+/* exact: the piece holding the closest point is never pruned).              */
+/*                                                                           */
+/* rtsdf_point_distance: points float32 [n][3] -> dist float32 [n] (+inf    */
+/* for a scene without triangles), tri int32 [n] (nearest original triangle, */
+/* ties to the lowest index; -1 if none; may be NULL).                       */
+/* rtsdf_texel_distance: the same at texel centres lo + (i + 1/2) h of       */
+/* `grid` (float operations rounded once, as for the ray origins); texels    */
+/* int32 [n] linear texel indices, or NULL for all n = grid.n^3 texels in     */
+/* order.  An index outside the grid only yields a point outside it (no      */
+/* memory is read through it).                                               */
+/* ------------------------------------------------------------------------ */
+int rtsdf_point_distance(const rtsdf_scene *scene, const float *points, int32_t n, float *dist, int32_t *tri,
+                         rtsdf_stream stream);
+int rtsdf_texel_distance(const rtsdf_scene *scene, rtsdf_grid grid, const int32_t *texels, int32_t n, float *dist,
+                         int32_t *tri, rtsdf_stream stream);
+
+/* ------------------------------------------------------------------------ */
 /* 5. Soft shadows (Sec. 2.3): for each point p, march from p towards the    */
 /* light (unit direction `light_dir`, host float[3]) through the fine SDF,   */
 /* sampled trilinearly between texel centres (clamped at the border).        */

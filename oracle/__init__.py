@@ -73,6 +73,7 @@ def lib():
                                          P, P, P, P, P, P, P, P, P]
         L.oracle_fine_grad.argtypes = [P, i32, P, f32, u64, u32, P, P, P, P, P, P]
         L.oracle_directions.argtypes = [i32, P, P, P, u64, u32, P]
+        L.oracle_point_distance.argtypes = [P, i32, P, P, P]
         L.oracle_shadow.argtypes = [i32, P, f32, P, i32, P, P, f32, f32, i32, f32, f32, i32, P, f32, P]
         _lib = L
     return _lib
@@ -296,6 +297,14 @@ class Scene:
         if rc != 0:
             raise ValueError("oracle_trace_frame: invalid arguments")
         return state
+
+    def point_distance(self, points):
+        """Exact unsigned distance from each point to the mesh (float64) and the nearest triangle."""
+        pts = _c(np.asarray(points, np.float64).reshape(-1, 3), np.float64)
+        dist = np.empty(pts.shape[0])
+        tri = np.empty(pts.shape[0], np.int32)
+        lib().oracle_point_distance(self.h, pts.shape[0], _p(pts), _p(dist), _p(tri))
+        return dist, tri
 
     def fine_grad(self, nf: int, lo, hf: float, seed: int, scene: int, state: TraceState, grad_f) -> np.ndarray:
         lo = _c(lo, np.float32)

@@ -1012,6 +1012,82 @@ int oracle_fine_grad(const oracle_scene *s, int nf, const float lo[3], float hf,
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Exact unsigned distance from points to the mesh (the quantity the traced  */
+/* fine SDF of Sec. 2.2 approaches from above: every hit is on the mesh).    */
+/* Plain definition: the minimum over all triangles of the distance to the   */
+/* triangle, which is the distance to the plane when the point's projection  */
+/* lies in the closed triangle, else the distance to the nearest of its      */
+/* three edges (closest point of a segment by clamped projection).           */
+/* Zero-area triangles have only their edges.  Ties go to the lowest index.  */
+/* ------------------------------------------------------------------------ */
+static double seg_dist2_d(const double p[3], const double a[3], const double b[3])
+{
+    double e[3], ap[3];
+    for (int k = 0; k < 3; ++k) { e[k] = b[k] - a[k]; ap[k] = p[k] - a[k]; }
+    const double ee = dot3(e, e);
+    double t = ee > 0 ? dot3(ap, e) / ee : 0.0;
+    if (t < 0) t = 0;
+    if (t > 1) t = 1;
+    double d2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        const double q = a[k] + t * e[k] - p[k];
+        d2 += q * q;
+    }
+    return d2;
+}
+
+static double tri_dist2_d(const double p[3], const double a[3], const double b[3], const double c[3])
+{
+    double ab[3], ac[3], ap[3], n[3];
+    for (int k = 0; k < 3; ++k) { ab[k] = b[k] - a[k]; ac[k] = c[k] - a[k]; ap[k] = p[k] - a[k]; }
+    cross3(ab, ac, n);
+    const double nn = dot3(n, n);
+    if (nn > 0) {
+        const double h = dot3(ap, n) / nn;
+        double q[3];
+        for (int k = 0; k < 3; ++k) q[k] = p[k] - h * n[k];
+        /* q inside the closed triangle: each edge sees q on the inner side */
+        const double *v[3] = {a, b, c};
+        int inside = 1;
+        for (int e = 0; e < 3 && inside; ++e) {
+            const double *u0 = v[e], *u1 = v[(e + 1) % 3];
+            double ed[3], uq[3], cr[3];
+            for (int k = 0; k < 3; ++k) { ed[k] = u1[k] - u0[k]; uq[k] = q[k] - u0[k]; }
+            cross3(ed, uq, cr);
+            if (dot3(cr, n) < 0) inside = 0;
+        }
+        if (inside) {
+            const double d = dot3(ap, n);
+            return d * d / nn;
+        }
+    }
+    double d2 = seg_dist2_d(p, a, b);
+    const double d2b = seg_dist2_d(p, b, c), d2c = seg_dist2_d(p, c, a);
+    if (d2b < d2) d2 = d2b;
+    if (d2c < d2) d2 = d2c;
+    return d2;
+}
+
+void oracle_point_distance(const oracle_scene *s, int n, const double *pts, double *dist, int *tri)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = 0; i < n; ++i) {
+        double best = INFINITY;
+        int bid = -1;
+        for (int t = 0; t < s->nt; ++t) {
+            const double d2 = tri_dist2_d(&pts[3 * i], &s->v[3 * s->f[3 * t]], &s->v[3 * s->f[3 * t + 1]],
+                                          &s->v[3 * s->f[3 * t + 2]]);
+            if (d2 < best) {
+                best = d2;
+                bid = t;
+            }
+        }
+        dist[i] = bid >= 0 ? sqrt(best) : INFINITY;
+        if (tri) tri[i] = bid;
+    }
+}
+
 /* Directions for many keys (same rule as oracle_direction). */
 void oracle_directions(int n, const int *texel, const uint32_t *frame, const int *ray, uint64_t seed,
                        uint32_t scene, float *out)

@@ -6,6 +6,7 @@
 #include "select.hip"
 #include "scene.hip"
 #include "trace.hip"
+#include "distance.hip"
 #include "shadow.hip"
 #include "batch.hip"
 #include "graph.hip"

@@ -119,6 +119,8 @@ def _load():
         "rtsdf_closest_hits": ([_P, _P, _P, _i32, _P, _P, _P, _P], _i32),
         "rtsdf_trace_backward": ([_P, Grid, Accum, _P, _P, _u64, _u32, _P, _P], _i32),
         "rtsdf_shadow": ([Grid, _P, _P, _i32, _P, _f32, _f32, _i32, _f32, _f32, _P, _P], _i32),
+        "rtsdf_point_distance": ([_P, _P, _i32, _P, _P, _P], _i32),
+        "rtsdf_texel_distance": ([_P, Grid, _P, _i32, _P, _P, _P], _i32),
         "rtsdf_shadow_ex": ([Grid, _P, _P, _i32, C.POINTER(ShadowParams), _P, _P, _P], _i32),
         "rtsdf_frame_graph_create": ([C.POINTER(FrameDesc), C.POINTER(_P), _P], _i32),
         "rtsdf_frame_graph_launch": ([_P, _P], _i32),
@@ -359,6 +361,18 @@ def rtsdf_shadow(fine: Grid, fine_sdf, points, light_dir, k: float, eps: float, 
     _check("rtsdf_shadow", _lib.rtsdf_shadow(fine, _ptr(fine_sdf), _ptr(points), points.shape[0], ld, float(k),
                                              float(eps), int(max_steps), float(max_step), float(max_dist),
                                              _ptr(visibility), _stream(stream)))
+
+
+def rtsdf_point_distance(scene: "Scene", points, dist, tri=None, stream=None):
+    _check("rtsdf_point_distance", _lib.rtsdf_point_distance(scene.handle, _ptr(points), points.shape[0], _ptr(dist),
+                                                             _ptr(tri), _stream(stream)))
+
+
+def rtsdf_texel_distance(scene: "Scene", grid: Grid, texels, dist, tri=None, stream=None):
+    """Distance at texel centres; texels=None means every texel of the grid (n = grid.n^3)."""
+    count = grid.n ** 3 if texels is None else texels.numel()
+    _check("rtsdf_texel_distance", _lib.rtsdf_texel_distance(scene.handle, grid, _ptr(texels), count, _ptr(dist),
+                                                             _ptr(tri), _stream(stream)))
 
 
 def rtsdf_shadow_ex(fine: Grid, fine_sdf, points, light_dir, k: float, eps: float, max_steps: int, max_step: float,
