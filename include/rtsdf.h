@@ -224,6 +224,23 @@ int rtsdf_scene_create(const float *vertices, int32_t nv, const int32_t *faces, 
                        int32_t leaf_size, rtsdf_scene **out, rtsdf_stream stream);
 int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsdf_stream stream);
 int rtsdf_scene_info_get(const rtsdf_scene *scene, rtsdf_scene_info *info);
+
+/* How rtsdf_trace_accumulate signs a texel's traced distance u (texels     */
+/* without a hit output c either way):                                       */
+/*  RTSDF_SIGN_VOTE   (default) the vote of Sec. 2.2: -u when more closest   */
+/*                    hits were back faces than front faces, else u.  For    */
+/*                    closed meshes.  Open surfaces get a negative region    */
+/*                    behind them (texels that see only their back face).    */
+/*  RTSDF_SIGN_SHELL  u - shell: every surface becomes a closed slab of      */
+/*                    half-thickness `shell` (>= 0, finite; 0 is the plain   */
+/*                    unsigned distance).  For open or thin surfaces: no     */
+/*                    inside/outside guess, and a shell of at least the      */
+/*                    shadow march's eps keeps thin surfaces from being      */
+/*                    stepped through (the holes Sec. 3 reports).           */
+/* The policy is read at each rtsdf_trace_accumulate and rtsdf_trace_backward */
+/* call (the gradient of a shell value is that of u).                        */
+enum { RTSDF_SIGN_VOTE = 0, RTSDF_SIGN_SHELL = 1 };
+int rtsdf_scene_set_sign(rtsdf_scene *scene, int32_t policy, float shell);
 void rtsdf_scene_destroy(rtsdf_scene *scene);
 
 /* ------------------------------------------------------------------------ */
@@ -408,6 +425,8 @@ typedef struct rtsdf_batch_scene {
     int32_t rays_per_texel;
     float alpha;
     uint32_t scene_id;      /* part of the ray counter (distinct scenes draw distinct rays) */
+    int32_t sign_policy;    /* RTSDF_SIGN_VOTE or RTSDF_SIGN_SHELL (see rtsdf_scene_set_sign) */
+    float shell;
 } rtsdf_batch_scene;
 
 typedef struct rtsdf_batch_view {

@@ -66,12 +66,12 @@ def lib():
         L.oracle_scene_destroy.argtypes = [P]
         L.oracle_eq1.argtypes = [f64, f64, f32, f64, P]
         L.oracle_eq1.restype = f64
-        L.oracle_fine_value.argtypes = [f64, f32, i32, i32]
+        L.oracle_fine_value.argtypes = [f64, f32, i32, i32, i32, f64]
         L.oracle_fine_value.restype = f64
         L.oracle_closest_hits.argtypes = [P, i32, P, P, P, P, P, P]
         L.oracle_trace_frame.argtypes = [P, i32, P, i32, P, f32, P, P, i32, i32, u32, u64, u32, f64,
-                                         P, P, P, P, P, P, P, P, P]
-        L.oracle_fine_grad.argtypes = [P, i32, P, f32, u64, u32, P, P, P, P, P, P]
+                                         P, P, P, P, P, P, P, P, P, i32, f64]
+        L.oracle_fine_grad.argtypes = [P, i32, P, f32, u64, u32, P, P, P, P, P, P, i32]
         L.oracle_directions.argtypes = [i32, P, P, P, u64, u32, P]
         L.oracle_point_distance.argtypes = [P, i32, P, P, P]
         L.oracle_shadow.argtypes = [i32, P, f32, P, i32, P, P, f32, f32, i32, f32, f32, i32, P, f32, P]
@@ -225,8 +225,12 @@ def eq1(alpha: float, u_prev: float, c: float, r_t: float):
     return float(u), int(src.value)
 
 
-def fine_value(u: float, c: float, nfront: int, nback: int) -> float:
-    return float(lib().oracle_fine_value(float(u), float(c), int(nfront), int(nback)))
+SIGN_POLICIES = {"vote": 0, "shell": 1}
+
+
+def fine_value(u: float, c: float, nfront: int, nback: int, sign_policy: str = "vote", shell: float = 0.0) -> float:
+    return float(lib().oracle_fine_value(float(u), float(c), int(nfront), int(nback), SIGN_POLICIES[sign_policy],
+                                         float(shell)))
 
 
 class TraceState:
@@ -283,7 +287,8 @@ class Scene:
         return t, tri, front, amb
 
     def trace_frame(self, nc: int, coarse_sdf, nf: int, lo, hf: float, mask, rays: int, frame: int,
-                    seed: int, scene: int, alpha: float, state: TraceState, texels=None) -> TraceState:
+                    seed: int, scene: int, alpha: float, state: TraceState, texels=None, sign_policy: str = "vote",
+                    shell: float = 0.0) -> TraceState:
         cs = _c(coarse_sdf, np.float32)
         m = _c(mask, np.uint8)
         lo = _c(lo, np.float32)
@@ -293,7 +298,8 @@ class Scene:
             self.h, int(nc), _p(cs), int(nf), _p(lo), float(hf), _p(m), _p(tx), ntex, int(rays),
             int(frame), int(seed), int(scene), float(alpha),
             _p(state.u), _p(state.nfront), _p(state.nback), _p(state.arg_frame), _p(state.arg_ray),
-            _p(state.arg_tri), _p(state.arg_amb), _p(state.fine), _p(state.rmin))
+            _p(state.arg_tri), _p(state.arg_amb), _p(state.fine), _p(state.rmin), SIGN_POLICIES[sign_policy],
+            float(shell))
         if rc != 0:
             raise ValueError("oracle_trace_frame: invalid arguments")
         return state
@@ -306,21 +312,25 @@ class Scene:
         lib().oracle_point_distance(self.h, pts.shape[0], _p(pts), _p(dist), _p(tri))
         return dist, tri
 
-    def fine_grad(self, nf: int, lo, hf: float, seed: int, scene: int, state: TraceState, grad_f) -> np.ndarray:
+    def fine_grad(self, nf: int, lo, hf: float, seed: int, scene: int, state: TraceState, grad_f,
+                  sign_policy: str = "vote") -> np.ndarray:
         lo = _c(lo, np.float32)
         g = _c(grad_f, np.float64)
         out = np.zeros(self.v.shape[0] * 3)
         lib().oracle_fine_grad(self.h, int(nf), _p(lo), float(hf), int(seed), int(scene), _p(state.fine),
-                               _p(state.arg_frame), _p(state.arg_ray), _p(state.arg_tri), _p(g), _p(out))
+                               _p(state.arg_frame), _p(state.arg_ray), _p(state.arg_tri), _p(g), _p(out),
+                               SIGN_POLICIES[sign_policy])
         return out.reshape(-1, 3)
 
 
 def run_frames(mesh_v, mesh_f, nc: int, nf: int, beta: float, d: float, rays: int, frames, seed: int = 0,
                scene: int = 0, alpha: float = 1.0, lo=(0.0, 0.0, 0.0), texels=None, use_bvh: bool = True,
-               state: TraceState | None = None, side: float = 1.0, sampling: str = "point"):
+               state: TraceState | None = None, side: float = 1.0, sampling: str = "point",
+               sign_policy: str = "vote", shell: float = 0.0):
     """Whole oracle pipeline for a static mesh over the given frame indices, on
     the cube [lo, lo + side]^3.  ``sampling="trilinear"`` selects and fills
-    with the trilinearly sampled coarse SDF instead of the containing voxel's.
+    with the trilinearly sampled coarse SDF instead of the containing voxel's;
+    ``sign_policy``/``shell`` choose how traced distances are signed.
 
     Returns a dict with the coarse stage outputs and the final trace state.
     """
@@ -343,7 +353,7 @@ def run_frames(mesh_v, mesh_f, nc: int, nf: int, beta: float, d: float, rays: in
     sc = Scene(mesh_v, mesh_f, use_bvh)
     st = TraceState(nf) if state is None else state
     for fr in frames:
-        sc.trace_frame(ng, cg, nf, lo, hf, mask, rays, fr, seed, scene, alpha, st, texels)
+        sc.trace_frame(ng, cg, nf, lo, hf, mask, rays, fr, seed, scene, alpha, st, texels, sign_policy, shell)
     out = dict(seeds0=seeds0, seeds=seeds, dist2=d2, coarse=c, K=K, mask=mask, queue=queue, state=st, scene=sc)
     if sampling == "trilinear":
         out["coarse_fine"] = cg

@@ -897,10 +897,16 @@ double oracle_eq1(double alpha, double u_prev, float c, double rt, int *src)
 /* Output value of a selected texel: the accumulated distance if any ray has
  * hit so far, else the coarse value; negative when more closest hits were
  * back faces than front faces (Sec. 2.2). */
-double oracle_fine_value(double u, float c, int nfront, int nback)
+/* Output value of a texel.  A texel whose state holds no traced distance    */
+/* takes c.  Sign policy 0 (Sec. 2.2): negative when more closest hits were  */
+/* back faces than front faces.  Policy 1, for open or thin surfaces that    */
+/* the vote cannot sign: the unsigned distance minus a shell half-thickness, */
+/* i.e. every surface read as a closed slab of that half-thickness.          */
+double oracle_fine_value(double u, float c, int nfront, int nback, int sign_policy, double shell)
 {
-    double val = isinf(u) ? (double)c : u;
-    return nback > nfront ? -val : val;
+    if (isinf(u)) return (double)c;
+    if (sign_policy == 1) return u - shell;
+    return nback > nfront ? -u : u;
 }
 
 int oracle_trace_frame(const oracle_scene *s,
@@ -910,7 +916,7 @@ int oracle_trace_frame(const oracle_scene *s,
                        int rays, uint32_t frame, uint64_t seed, uint32_t scene, double alpha,
                        double *u, int *nfront, int *nback,
                        int *arg_frame, int *arg_ray, int *arg_tri, unsigned char *arg_amb,
-                       double *fine, double *rmin_out)
+                       double *fine, double *rmin_out, int sign_policy, double shell)
 {
     if (nc <= 0 || nf <= 0 || nf % nc != 0 || rays <= 0) return ORC_EINVAL;
     const int r = nf / nc;
@@ -964,7 +970,7 @@ int oracle_trace_frame(const oracle_scene *s,
             arg_frame[j] = arg_ray[j] = arg_tri[j] = -1;
             arg_amb[j] = 0;
         }
-        fine[j] = oracle_fine_value(u[j], c, nfront[j], nback[j]);
+        fine[j] = oracle_fine_value(u[j], c, nfront[j], nback[j], sign_policy, shell);
     }
     return ORC_OK;
 }
@@ -983,7 +989,7 @@ int oracle_trace_frame(const oracle_scene *s,
 int oracle_fine_grad(const oracle_scene *s, int nf, const float lo[3], float hf,
                      uint64_t seed, uint32_t scene, const double *fine,
                      const int *arg_frame, const int *arg_ray, const int *arg_tri,
-                     const double *grad_f, double *grad_v)
+                     const double *grad_f, double *grad_v, int sign_policy)
 {
     const long total = (long)nf * nf * nf;
     for (long j = 0; j < total; ++j) {
@@ -1003,7 +1009,7 @@ int oracle_fine_grad(const oracle_scene *s, int nf, const float lo[3], float hf,
         for (int a = 0; a < 3; ++a) { e1[a] = v1[a] - v0[a]; e2[a] = v2[a] - v0[a]; }
         cross3(e1, e2, n);
         const double nw = dot3(n, w);
-        const double sgn = fine[j] < 0 ? -1.0 : 1.0;
+        const double sgn = sign_policy == 0 && fine[j] < 0 ? -1.0 : 1.0;
         const double scale = grad_f[j] * sgn * sqrt(dot3(w, w)) / nw;
         const double b[3] = {1.0 - u - w2, u, w2};
         for (int k = 0; k < 3; ++k)

@@ -263,6 +263,8 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
         if (!is_pow2(d.fine_n) || d.fine_n < d.coarse_n || d.fine_n > 1024) return RTSDF_EINVAL;
         if (!(d.side > 0.0f) || d.rays_per_texel < 1 || d.rays_per_texel > 64) return RTSDF_EINVAL;
         if (!(d.alpha >= 0.0f && d.alpha <= 1.0f) || !(d.beta == d.beta) || !(d.d == d.d)) return RTSDF_EINVAL;
+        if (d.sign_policy != RTSDF_SIGN_VOTE && d.sign_policy != RTSDF_SIGN_SHELL) return RTSDF_EINVAL;
+        if (d.sign_policy == RTSDF_SIGN_SHELL && !(d.shell >= 0.0f && d.shell < __builtin_inff())) return RTSDF_EINVAL;
         if (d.nt >= (1 << 26)) return RTSDF_EINVAL;
     }
     hipStream_t s = as_stream(stream);
@@ -402,6 +404,8 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
         P.rays = d.rays_per_texel;
         P.scene_id = d.scene_id;
         P.alpha = d.alpha;
+        P.sign_policy = d.sign_policy;
+        P.shell = d.sign_policy == RTSDF_SIGN_SHELL ? d.shell : 0.0f;
         P.u = B->u + B->foff[i];
         P.hits = B->hits + B->foff[i];
         P.arg_tri = B->arg_tri + B->foff[i];

@@ -83,6 +83,8 @@ struct rtsdf_scene {
     int32_t *spill = nullptr;          // tracer stack entries beyond the LDS part
     int64_t spill_entries = 0;
     int64_t bytes = 0;
+    int sign_policy = RTSDF_SIGN_VOTE;  // how the tracer signs a traced distance
+    float shell = 0.f;                  // RTSDF_SIGN_SHELL: half-thickness subtracted from the distance
 };
 
 namespace rtsdf {
@@ -638,6 +640,15 @@ extern "C" int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsd
     refit_nodes<<<dim3((scene->nstart + 255) / 256), dim3(256), 0, s>>>(scene->nodes, scene->tris, scene->start_nodes,
                                                                          scene->nstart, scene->refit_counter, scene->pad);
     RTSDF_CHECK_LAUNCH();
+    return RTSDF_OK;
+}
+
+extern "C" int rtsdf_scene_set_sign(rtsdf_scene *scene, int32_t policy, float shell)
+{
+    if (!scene || (policy != RTSDF_SIGN_VOTE && policy != RTSDF_SIGN_SHELL)) return RTSDF_EINVAL;
+    if (policy == RTSDF_SIGN_SHELL && !(shell >= 0.0f && shell < __builtin_inff())) return RTSDF_EINVAL;
+    scene->sign_policy = policy;
+    scene->shell = policy == RTSDF_SIGN_SHELL ? shell : 0.0f;
     return RTSDF_OK;
 }
 

@@ -297,6 +297,8 @@ struct TraceScene {
     int rays;
     uint32_t scene_id;
     float alpha;
+    int sign_policy;  // RTSDF_SIGN_VOTE or RTSDF_SIGN_SHELL
+    float shell;
     float *u;
     uint32_t *hits;
     int32_t *arg_tri;
@@ -822,8 +824,9 @@ trace_persistent(TraceArgs A)
             }
             P.u[j] = uu;
             P.hits[j] = F | (B << 16);
-            const float f = isinf(uu) ? c : uu;
-            P.fine[j] = B > F ? -f : f;
+            if (isinf(uu)) P.fine[j] = c;
+            else if (P.sign_policy == RTSDF_SIGN_SHELL) P.fine[j] = uu - P.shell;
+            else P.fine[j] = B > F ? -uu : uu;
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -922,7 +925,7 @@ __global__ void __launch_bounds__(256) trace_backward_kernel(const float *__rest
                                                              const int32_t *__restrict__ arg_ray,
                                                              const float *__restrict__ fine,
                                                              const float *__restrict__ grad, uint64_t seed,
-                                                             uint32_t scene, float *grad_v, int64_t ntex)
+                                                             uint32_t scene, float *grad_v, int64_t ntex, bool vote)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= ntex) return;
@@ -953,7 +956,7 @@ __global__ void __launch_bounds__(256) trace_backward_kernel(const float *__rest
     const float nw = nrm.x * w.x + nrm.y * w.y + nrm.z * w.z;
     if (nw == 0.0f) return;
     const float len = sqrtf(w.x * w.x + w.y * w.y + w.z * w.z);
-    const float sgn = fine[j] < 0.0f ? -1.0f : 1.0f;
+    const float sgn = !vote || fine[j] >= 0.0f ? 1.0f : -1.0f;  // a shell value is the distance minus a constant
     const float scale = g * sgn * len / nw;
     const float b[3] = {1.0f - bu - bv, bu, bv};
     const int vid[3] = {i0, i1, i2};
@@ -1130,6 +1133,8 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     P.rays = rays_per_texel;
     P.scene_id = scene_id;
     P.alpha = alpha;
+    P.sign_policy = scene->sign_policy;
+    P.shell = scene->shell;
     P.u = st.u;
     P.hits = st.hits;
     P.arg_tri = st.arg_tri;
@@ -1189,7 +1194,7 @@ extern "C" int rtsdf_trace_backward(const rtsdf_scene *scene, rtsdf_grid fine, r
     const int64_t ntex = (int64_t)fine.n * fine.n * fine.n;
     trace_backward_kernel<<<dim3((unsigned)((ntex + 255) / 256)), dim3(256), 0, as_stream(stream)>>>(
         scene->vertices, scene->faces, scene->nt, ilog2(fine.n), fine.lo[0], fine.lo[1], fine.lo[2], fine.h, st.arg_tri,
-        st.arg_ray, fine_sdf, grad_fine, seed, scene_id, grad_v, ntex);
+        st.arg_ray, fine_sdf, grad_fine, seed, scene_id, grad_v, ntex, scene->sign_policy == RTSDF_SIGN_VOTE);
     RTSDF_CHECK_LAUNCH();
     return RTSDF_OK;
 }

@@ -9,7 +9,9 @@ the fine texels near surfaces and ray-traced temporal accumulation
 ``sampling`` chooses how a fine texel reads the coarse SDF for the selection
 test c <= d and for c_t of Eq. (1): ``"point"`` (the coarse voxel containing
 the texel centre) or ``"trilinear"`` (the coarse field interpolated at the
-texel centre; the tracer then works on the fine grid alone).
+texel centre; the tracer then works on the fine grid alone).  ``sign_policy``
+"vote" signs traced distances by the front/back vote of Sec. 2.2; "shell"
+outputs the unsigned distance minus ``shell`` (open or thin surfaces).
 """
 from __future__ import annotations
 
@@ -24,7 +26,8 @@ class Pipeline:
     def __init__(self, vertices: torch.Tensor, faces: torch.Tensor, nc: int, nf: int, beta: float, d: float,
                  rays: int, seed: int = 0, scene_id: int = 0, alpha: float = 1.0, lo=(0.0, 0.0, 0.0),
                  side: float = 1.0, leaf_size: int = 2, queue_cap: int | None = None, device="cuda",
-                 jfa_variant: str = "jfa", sampling: str = "point"):
+                 jfa_variant: str = "jfa", sampling: str = "point", sign_policy: str = "vote",
+                 shell: float = 0.0):
         if sampling not in ("point", "trilinear"):
             raise ValueError(f"sampling must be 'point' or 'trilinear', not {sampling!r}")
         self.sampling = sampling
@@ -54,6 +57,7 @@ class Pipeline:
         self.fine_sdf = torch.empty(nf ** 3, dtype=f32, device=dev)
         self.state = R.AccumState(self.fine, dev)
         self.scene = R.Scene(self.vertices, self.faces, leaf_size)
+        self.scene.set_sign(sign_policy, shell)
 
     # -- stages ----------------------------------------------------------
     def voxelize(self, stream=None):

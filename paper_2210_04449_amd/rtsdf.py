@@ -58,7 +58,7 @@ class FrameDesc(C.Structure):
 class BatchScene(C.Structure):
     _fields_ = [("vertices", _P), ("nv", _i32), ("faces", _P), ("nt", _i32), ("lo", C.c_float * 3), ("side", _f32),
                 ("coarse_n", _i32), ("fine_n", _i32), ("beta", _f32), ("d", _f32), ("rays_per_texel", _i32),
-                ("alpha", _f32), ("scene_id", _u32)]
+                ("alpha", _f32), ("scene_id", _u32), ("sign_policy", _i32), ("shell", _f32)]
 
 
 class BatchView(C.Structure):
@@ -119,6 +119,7 @@ def _load():
         "rtsdf_closest_hits": ([_P, _P, _P, _i32, _P, _P, _P, _P], _i32),
         "rtsdf_trace_backward": ([_P, Grid, Accum, _P, _P, _u64, _u32, _P, _P], _i32),
         "rtsdf_shadow": ([Grid, _P, _P, _i32, _P, _f32, _f32, _i32, _f32, _f32, _P, _P], _i32),
+        "rtsdf_scene_set_sign": ([_P, _i32, _f32], _i32),
         "rtsdf_point_distance": ([_P, _P, _i32, _P, _P, _P], _i32),
         "rtsdf_texel_distance": ([_P, Grid, _P, _i32, _P, _P, _P], _i32),
         "rtsdf_shadow_ex": ([Grid, _P, _P, _i32, C.POINTER(ShadowParams), _P, _P, _P], _i32),
@@ -248,6 +249,9 @@ def rtsdf_select_field(grid: Grid, field, d: float, mask, queue, count, workspac
                                                          _ptr(count), _ptr(workspace), _stream(stream)))
 
 
+SIGN_POLICIES = {"vote": 0, "shell": 1}  # RTSDF_SIGN_VOTE, RTSDF_SIGN_SHELL
+
+
 class Scene:
     """Owning handle of an ``rtsdf_scene`` (device triangles + hierarchy)."""
 
@@ -262,6 +266,10 @@ class Scene:
 
     def refit(self, vertices, stream=None):
         _check("rtsdf_scene_refit", _lib.rtsdf_scene_refit(self.handle, _ptr(vertices), _stream(stream)))
+
+    def set_sign(self, policy: str = "vote", shell: float = 0.0):
+        """How traced distances are signed: "vote" (front/back hit counts) or "shell" (distance - shell)."""
+        _check("rtsdf_scene_set_sign", _lib.rtsdf_scene_set_sign(self.handle, SIGN_POLICIES[policy], float(shell)))
 
     def info(self) -> SceneInfo:
         inf = SceneInfo()
@@ -439,6 +447,8 @@ class Batch:
             b.coarse_n, b.fine_n = int(d["coarse_n"]), int(d["fine_n"])
             b.beta, b.d = float(d["beta"]), float(d["d"])
             b.rays_per_texel, b.alpha, b.scene_id = int(d["rays"]), float(d.get("alpha", 1.0)), int(d.get("scene_id", i))
+            b.sign_policy = SIGN_POLICIES[d.get("sign_policy", "vote")]
+            b.shell = float(d.get("shell", 0.0))
         h = _P()
         _check("rtsdf_batch_create", _lib.rtsdf_batch_create(arr, len(scenes), int(seed), int(leaf_size), C.byref(h),
                                                              _stream(stream)))

@@ -100,6 +100,7 @@ def test_host_validation(R):
         t = R.TraceTuning(**{**R.rtsdf_trace_config_get().as_dict(), **bad})
         assert L.rtsdf_trace_config(C.byref(t)) == R.EINVAL
     assert L.rtsdf_trace_config(None) == R.EINVAL
+    assert L.rtsdf_scene_set_sign(None, 0, 0.0) == R.EINVAL
     default = R.rtsdf_trace_config_get().as_dict()
     prev = R.rtsdf_trace_config(refill=8, stack_lds=24)
     assert prev.as_dict() == default and R.rtsdf_trace_config_get().refill == 8

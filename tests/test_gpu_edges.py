@@ -144,3 +144,73 @@ def test_ray_count_limits_and_pure_decay(R, rays, alpha):
     torch.cuda.synchronize()
     ref = oracle.run_frames(s.vertices, s.faces, nc, nf, beta, d, rays, range(3), alpha=alpha)
     assert check_against(p, ref) > 1000
+
+
+def test_shell_sign_policy_against_oracle(R):
+    """Shell policy (open or thin surfaces): fine = u - shell for traced texels, the coarse value elsewhere; the
+    one-sided ground quad of the tiny scene no longer leaves a negative region below it."""
+    say("shell sign policy")
+    w = workload("tiny")
+    shell = 1.0 / 128
+    p = pipe(w.mesh.vertices, w.mesh.faces, w.nc, w.nf, w.beta, w.d, w.rays, scene_id=w.scene_seed,
+             sign_policy="shell", shell=shell)
+    for fr in range(w.frames):
+        p.step(fr)
+    torch.cuda.synchronize()
+    ref = oracle.run_frames(w.mesh.vertices, w.mesh.faces, w.nc, w.nf, w.beta, w.d, w.rays, range(w.frames),
+                            scene=w.scene_seed, sign_policy="shell", shell=shell)
+    st = ref["state"]
+    mask = p.mask.cpu().numpy()
+    assert np.array_equal(mask, ref["mask"])
+    fine = p.fine_sdf.cpu().numpy().astype(np.float64)
+    sel = np.nonzero(mask)[0]
+    good = sel[st.arg_amb[sel] == 0]
+    assert np.max(np.abs(fine[good] - st.fine[good])) <= TOL
+    unsel = np.nonzero(mask == 0)[0]
+    assert np.array_equal(fine[unsel], st.fine[unsel])
+    assert fine[sel].min() >= -shell - TOL  # nothing is inside a shell deeper than its half-thickness
+    # the vote run of the same frames: same state, signed output
+    v = pipe(w.mesh.vertices, w.mesh.faces, w.nc, w.nf, w.beta, w.d, w.rays, scene_id=w.scene_seed)
+    for fr in range(w.frames):
+        v.step(fr)
+    torch.cuda.synchronize()
+    assert torch.equal(v.state.u, p.state.u) and torch.equal(v.state.hits, p.state.hits)
+    assert (v.fine_sdf < -shell).sum().item() > 1000
+
+
+def test_shell_gradient_and_batch(R):
+    say("shell gradient / batch")
+    from synth.scenes import Workload
+    nc, nf, rays, frames = 32, 64, 8, 3
+    s = icosphere(2, 0.28, (0.5, 0.5, 0.5))
+    w = Workload("g", s, nc, nf, 0.5, 2.0, rays, frames)
+    shell = 0.01
+    p = pipe(s.vertices, s.faces, nc, nf, w.beta, w.d, rays, sign_policy="shell", shell=shell)
+    for fr in range(frames):
+        p.step(fr)
+    ref = oracle.run_frames(s.vertices, s.faces, nc, nf, w.beta, w.d, rays, range(frames), sign_policy="shell",
+                            shell=shell)
+    st = ref["state"]
+    at, ar = p.state.arg_tri.cpu().numpy(), p.state.arg_ray.cpu().numpy()
+    agree = (at == st.arg_tri) & (ar == ((st.arg_frame << 8) | np.maximum(st.arg_ray, 0))) & (st.arg_amb == 0)
+    fine = p.fine_sdf.cpu().numpy().astype(np.float64)
+    gf = np.where(agree & (p.mask.cpu().numpy() == 1), 2 * fine, 0.0)
+    gv = torch.zeros(s.nv * 3, dtype=torch.float32, device="cuda")
+    R.rtsdf_trace_backward(p.scene, p.fine, p.state, p.fine_sdf, torch.from_numpy(gf.astype(np.float32)).cuda(),
+                           0, 0, gv)
+    got = gv.cpu().numpy().reshape(-1, 3).astype(np.float64)
+    want = oracle.Scene(s.vertices, s.faces).fine_grad(nf, np.zeros(3, np.float32), np.float32(1 / nf), 0, 0, st, gf,
+                                                       sign_policy="shell")
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print("shell grad rel L2", rel)
+    assert rel <= 1e-4
+    # a batched scene with the shell policy equals its single-scene run bit for bit
+    B = R.Batch([dict(vertices=torch.from_numpy(s.vertices).cuda(), faces=torch.from_numpy(s.faces).cuda(),
+                      coarse_n=nc, fine_n=nf, beta=w.beta, d=w.d, rays=rays, scene_id=0, sign_policy="shell",
+                      shell=shell)], seed=0)
+    for fr in range(frames):
+        B.step(fr)
+    t = B.tensors(0)
+    torch.cuda.synchronize()
+    assert torch.equal(t["fine_sdf"], p.fine_sdf) and torch.equal(t["u"], p.state.u)
+    B.close()

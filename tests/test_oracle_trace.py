@@ -295,3 +295,24 @@ def test_gradient_matches_central_differences():
         assert abs(fd - an) <= 1e-5 * max(abs(fd), abs(an)) + 1e-9, (vi, ax, fd, an)
         checked += 1
     assert checked >= 6
+
+
+def test_shell_sign_policy(tiny_run):
+    """Shell policy: the output is the unsigned traced distance minus the shell half-thickness, so the one-sided
+    ground quad no longer makes the region below it negative; the state and the hits are the vote run's."""
+    r, m = tiny_run
+    shell = 1.0 / 128
+    rs = oracle.run_frames(m.vertices, m.faces, 32, 64, np.float32(0.5 / 32), np.float32(2 / 32), 4, range(8),
+                           sign_policy="shell", shell=shell)
+    a, b = r["state"], rs["state"]
+    assert np.array_equal(a.u, b.u) and np.array_equal(a.nfront, b.nfront) and np.array_equal(a.arg_tri, b.arg_tri)
+    traced = np.isfinite(a.u)
+    assert np.array_equal(b.fine[traced], np.abs(a.fine[traced]) - shell)
+    assert np.array_equal(b.fine[~traced], a.fine[~traced])
+    nf = 64
+    sel = np.nonzero(r["mask"].astype(bool) & traced)[0]
+    P = (np.stack([sel % nf, (sel // nf) % nf, sel // nf ** 2], 1) + 0.5) / nf
+    below = P[:, 1] < 0.149
+    assert np.all(a.fine[sel[below]] < 0) and np.all(b.fine[sel[below]] > -shell)
+    assert oracle.fine_value(0.25, 0.5, 1, 3, "shell", 0.0625) == 0.1875
+    assert oracle.fine_value(np.inf, 0.5, 1, 3, "shell", 0.0625) == 0.5
