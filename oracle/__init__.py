@@ -74,6 +74,7 @@ def lib():
         L.oracle_fine_grad.argtypes = [P, i32, P, f32, u64, u32, P, P, P, P, P, P, i32]
         L.oracle_directions.argtypes = [i32, P, P, P, u64, u32, P]
         L.oracle_point_distance.argtypes = [P, i32, P, P, P]
+        L.oracle_instance_world.argtypes = [i32, P, P, P, P]
         L.oracle_shadow.argtypes = [i32, P, f32, P, i32, P, P, f32, f32, i32, f32, f32, i32, P, f32, P]
         _lib = L
     return _lib
@@ -168,6 +169,16 @@ def select_field(n: int, field: np.ndarray, d: float):
     if lib().oracle_select_field(int(n), _p(fl), float(d), _p(mask), _p(queue), n ** 3, C.byref(cnt)) != 0:
         raise ValueError("oracle_select_field failed")
     return mask, queue[: cnt.value].copy()
+
+
+def instance_world(obj_vertices, part, transforms) -> np.ndarray:
+    """World positions (float32 [nv, 3]) of vertices given in their part's object space."""
+    o = _c(np.asarray(obj_vertices, np.float32).reshape(-1, 3), np.float32)
+    pa = _c(part, np.int32)
+    T = _c(np.asarray(transforms, np.float32).reshape(-1, 12), np.float32)
+    out = np.empty_like(o)
+    lib().oracle_instance_world(o.shape[0], _p(o), _p(pa), _p(T), _p(out))
+    return out
 
 
 def philox4x64_10(counter, key) -> np.ndarray:

@@ -1094,6 +1094,37 @@ void oracle_point_distance(const oracle_scene *s, int n, const double *pts, doub
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* World positions of rigid parts (a scene given as parts in object space    */
+/* and one object-to-world transform per part, rows r_a = (r_a0, r_a1,       */
+/* r_a2, t_a)).  Defined in float32 with the operation order                 */
+/* ((r_a0 x + r_a1 y) + r_a2 z) + t_a, each operation rounded once, because */
+/* voxelization and selection downstream must see the same float positions  */
+/* on both sides.  part[v] < 0 leaves a vertex where it is.                  */
+/* ------------------------------------------------------------------------ */
+void oracle_instance_world(int nv, const float *obj, const int *part, const float *T, float *out)
+{
+    for (int v = 0; v < nv; ++v) {
+        const float x = obj[3 * v], y = obj[3 * v + 1], z = obj[3 * v + 2];
+        if (part[v] < 0) {
+            out[3 * v] = x;
+            out[3 * v + 1] = y;
+            out[3 * v + 2] = z;
+            continue;
+        }
+        const float *m = &T[12 * part[v]];
+        for (int a = 0; a < 3; ++a) {
+            volatile float px = m[4 * a] * x;
+            volatile float py = m[4 * a + 1] * y;
+            volatile float pz = m[4 * a + 2] * z;
+            volatile float s1 = px + py;
+            volatile float s2 = s1 + pz;
+            volatile float s3 = s2 + m[4 * a + 3];
+            out[3 * v + a] = s3;
+        }
+    }
+}
+
 /* Directions for many keys (same rule as oracle_direction). */
 void oracle_directions(int n, const int *texel, const uint32_t *frame, const int *ray, uint64_t seed,
                        uint32_t scene, float *out)

@@ -163,6 +163,7 @@ __global__ void __launch_bounds__(kDistBlock) point_distance_kernel(BvhView S, i
 static int point_distance_launch(const rtsdf_scene *scene, const float *points, rtsdf_grid g, bool texel_mode,
                                  const int32_t *texels, int32_t n, float *dist, int32_t *tri, rtsdf_stream stream)
 {
+    if (scene->ninst > 0) return RTSDF_EINVAL;  // single-level scenes only
     if (n == 0) return RTSDF_OK;
     const int sd = stack_depth_for(scene);
     if (sd > 64) return RTSDF_EINVAL;

@@ -1,0 +1,448 @@
+// Two-level scenes: parts that move rigidly keep their own hierarchy.
+//
+// Refitting one hierarchy over moving geometry keeps its topology while the
+// boxes of moving parts grow and overlap, so tracing slows frame after frame.
+// When the scene is a set of rigid parts (instances), each part's hierarchy
+// is built once in its object space and stays tight; a small top-level tree
+// over the parts' world boxes is refit per frame from their transforms.
+//
+// Node array: [top-level internal nodes (ninst - 1)] [instance nodes (ninst)]
+// [hierarchy of instance 0] [hierarchy of instance 1] ...  Top-level children
+// are node indices (internal or instance nodes).  An instance node carries
+// the rows of its world-to-object transform in the three box slots and
+// (root of the part's hierarchy, kInstTag) as its children: the tracer that
+// reaches it moves its ray into object space, pushes kReturn and descends;
+// reaching kReturn, once the last leaf of the part is tested, brings the ray
+// back to world space.  The transforms are
+// rigid (rotation and translation), so the ray parameter t, and with it the
+// closest-hit order, is the same in both spaces.  Triangle records carry the
+// global face index, so hits, the argmin record and the gradient name faces
+// of the whole mesh.  World vertex positions (for voxelization and the
+// gradient) are recomputed from the object positions at every transform
+// update, each coordinate as ((r0 x + r1 y) + r2 z) + t with every float
+// operation rounded once.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+
+namespace rtsdf {
+
+constexpr float kRigidTol = 1e-4f;  // |R R^T - I| entries and |det R - 1| accepted as rigid
+
+__host__ __device__ inline bool rigid_ok(const float *m)
+{
+    float err = 0.0f;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const float d = m[4 * a] * m[4 * b] + m[4 * a + 1] * m[4 * b + 1] + m[4 * a + 2] * m[4 * b + 2];
+            err = fmaxf(err, fabsf(d - (a == b ? 1.0f : 0.0f)));
+        }
+    const float det = m[0] * (m[5] * m[10] - m[6] * m[9]) - m[1] * (m[4] * m[10] - m[6] * m[8]) +
+                      m[2] * (m[4] * m[9] - m[5] * m[8]);
+    return err <= kRigidTol && fabsf(det - 1.0f) <= kRigidTol;
+}
+
+// world-to-object rows into each instance node; world box of each part's hierarchy
+__global__ void inst_update(const float *__restrict__ T, int n, BvhNode *nodes, int inst_base,
+                            const float *__restrict__ obj_box, float *__restrict__ world_box, float pad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float m[12];
+    for (int k = 0; k < 12; ++k) m[k] = T[12 * i + k];
+    if (!rigid_ok(m)) raise_error(RTSDF_ERR_TRANSFORM);
+    float inv[12];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) inv[4 * r + c] = m[4 * c + r];
+        inv[4 * r + 3] = -(m[r] * m[3] + m[4 + r] * m[7] + m[8 + r] * m[11]);
+    }
+    BvhNode *nd = &nodes[inst_base + i];
+    nd->xy0 = make_float4(inv[0], inv[1], inv[2], inv[3]);
+    nd->xy1 = make_float4(inv[4], inv[5], inv[6], inv[7]);
+    nd->z01 = make_float4(inv[8], inv[9], inv[10], inv[11]);
+    float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+    float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+    const float *b = obj_box + 6 * i;
+    for (int corner = 0; corner < 8; ++corner) {
+        const float p[3] = {b[(corner & 1) ? 3 : 0], b[(corner & 2) ? 4 : 1], b[(corner & 4) ? 5 : 2]};
+        for (int a = 0; a < 3; ++a) {
+            const float w = m[4 * a] * p[0] + m[4 * a + 1] * p[1] + m[4 * a + 2] * p[2] + m[4 * a + 3];
+            lo[a] = fminf(lo[a], w);
+            hi[a] = fmaxf(hi[a], w);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        world_box[6 * i + a] = nextafterf(lo[a] - pad, -__builtin_inff());
+        world_box[6 * i + 3 + a] = nextafterf(hi[a] + pad, __builtin_inff());
+    }
+}
+
+// top-level boxes, children before parents (nodes are numbered in preorder)
+__global__ void tlas_refit(BvhNode *nodes, int ntop, int inst_base, const float *__restrict__ world_box)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int id = ntop - 1; id >= 0; --id) {
+        BvhNode *p = &nodes[id];
+        const int c[2] = {p->meta.x, p->meta.y};
+        for (int s = 0; s < 2; ++s) {
+            float lo[3], hi[3];
+            if (c[s] >= inst_base) {
+                const float *b = world_box + 6 * (c[s] - inst_base);
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = b[a];
+                    hi[a] = b[3 + a];
+                }
+            } else {
+                float l2[3], h2[3];
+                get_slot(&nodes[c[s]], 0, lo, hi);
+                get_slot(&nodes[c[s]], 1, l2, h2);
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = fminf(lo[a], l2[a]);
+                    hi[a] = fmaxf(hi[a], h2[a]);
+                }
+            }
+            set_slot(p, s, lo, hi);
+        }
+    }
+}
+
+__global__ void inst_world_vertices(const float *__restrict__ obj, const int32_t *__restrict__ vinst,
+                                    const float *__restrict__ T, int nv, float *__restrict__ world,
+                                    float *__restrict__ out)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const float x = obj[3 * v], y = obj[3 * v + 1], z = obj[3 * v + 2];
+    const int i = vinst[v];
+    float w[3] = {x, y, z};
+    if (i >= 0) {
+        const float *m = T + 12 * i;
+        for (int a = 0; a < 3; ++a)
+            w[a] = rn_add(rn_add(rn_add(rn_mul(m[4 * a], x), rn_mul(m[4 * a + 1], y)), rn_mul(m[4 * a + 2], z)),
+                          m[4 * a + 3]);
+    }
+    for (int a = 0; a < 3; ++a) {
+        world[3 * v + a] = w[a];
+        if (out) out[3 * v + a] = w[a];
+    }
+}
+
+namespace {
+
+// top level over the parts' world boxes: median split on the longest axis of the centres, preorder numbering
+struct TopBuilder {
+    const std::vector<Aabb> &box;
+    int inst_base;
+    std::vector<BvhNode> nodes;
+    int depth = 0;
+
+    int build(std::vector<int> &ids, int b, int e, int d)
+    {
+        if (e - b == 1) {
+            depth = std::max(depth, d);
+            return inst_base + ids[b];
+        }
+        Aabb cb;
+        cb.reset();
+        for (int k = b; k < e; ++k) {
+            float c[3];
+            for (int a = 0; a < 3; ++a) c[a] = 0.5f * (box[ids[k]].lo[a] + box[ids[k]].hi[a]);
+            cb.grow_pt(c);
+        }
+        int axis = 0;
+        for (int a = 1; a < 3; ++a)
+            if (cb.hi[a] - cb.lo[a] > cb.hi[axis] - cb.lo[axis]) axis = a;
+        const int mid = b + (e - b) / 2;
+        std::nth_element(ids.begin() + b, ids.begin() + mid, ids.begin() + e, [&](int x, int y) {
+            const float cx = box[x].lo[axis] + box[x].hi[axis], cy = box[y].lo[axis] + box[y].hi[axis];
+            return cx < cy || (cx == cy && x < y);
+        });
+        const int id = (int)nodes.size();
+        nodes.emplace_back();
+        const int c0 = build(ids, b, mid, d + 1);
+        const int c1 = build(ids, mid, e, d + 1);
+        nodes[id].meta = make_int4(c0, c1, -1, 0);
+        if (c0 < inst_base) nodes[c0].meta.z = id;
+        if (c1 < inst_base) nodes[c1].meta.z = id;
+        return id;
+    }
+};
+
+}  // namespace
+
+static int launch_transforms(rtsdf_scene *sc, float *world_out, hipStream_t s)
+{
+    const int n = sc->ninst;
+    inst_update<<<dim3((n + 63) / 64), dim3(64), 0, s>>>(sc->transforms, n, sc->nodes, sc->inst_base,
+                                                         sc->inst_obj_box, sc->inst_world_box, sc->pad);
+    RTSDF_CHECK_LAUNCH();
+    if (sc->inst_base > 0) {
+        tlas_refit<<<dim3(1), dim3(64), 0, s>>>(sc->nodes, sc->inst_base, sc->inst_base, sc->inst_world_box);
+        RTSDF_CHECK_LAUNCH();
+    }
+    if (sc->nv > 0) {
+        inst_world_vertices<<<dim3((sc->nv + 255) / 256), dim3(256), 0, s>>>(sc->obj_vertices, sc->vert_inst,
+                                                                              sc->transforms, sc->nv, sc->vertices,
+                                                                              world_out);
+        RTSDF_CHECK_LAUNCH();
+    }
+    return RTSDF_OK;
+}
+
+}  // namespace rtsdf
+
+static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, const int32_t *faces, int32_t nt,
+                                             const int32_t *instance_faces, int32_t ninst, const float *transforms,
+                                             int32_t leaf_size, rtsdf_scene **out, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!out || !instance_faces || !transforms || ninst < 1 || nv < 1 || nt < 1 || !vertices || !faces)
+        return RTSDF_EINVAL;
+    if (leaf_size <= 0) leaf_size = 4;
+    if (leaf_size > kMaxLeaf || (int64_t)nt >= (int64_t)1 << 26 || ninst > (1 << 20)) return RTSDF_EINVAL;
+    if (instance_faces[0] != 0 || instance_faces[ninst] != nt) return RTSDF_EINVAL;
+    for (int i = 0; i < ninst; ++i)
+        if (instance_faces[i + 1] <= instance_faces[i]) return RTSDF_EINVAL;  // every part has a face
+    *out = nullptr;
+    hipStream_t s = as_stream(stream);
+    std::vector<float> hv((size_t)3 * nv), hT((size_t)12 * ninst);
+    std::vector<int32_t> hf((size_t)3 * nt);
+    RTSDF_TRY(hipMemcpyAsync(hv.data(), vertices, sizeof(float) * hv.size(), hipMemcpyDeviceToHost, s));
+    RTSDF_TRY(hipMemcpyAsync(hf.data(), faces, sizeof(int32_t) * hf.size(), hipMemcpyDeviceToHost, s));
+    RTSDF_TRY(hipMemcpyAsync(hT.data(), transforms, sizeof(float) * hT.size(), hipMemcpyDeviceToHost, s));
+    RTSDF_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> vinst(nv, -1);
+    for (int i = 0; i < ninst; ++i)
+        for (int t = instance_faces[i]; t < instance_faces[i + 1]; ++t)
+            for (int k = 0; k < 3; ++k) {
+                const int v = hf[3 * t + k];
+                if (v < 0 || v >= nv) return RTSDF_EINVAL;
+                if (vinst[v] >= 0 && vinst[v] != i) return RTSDF_EINVAL;  // a vertex belongs to one part
+                vinst[v] = i;
+            }
+    float obj_scale = 1.0f;
+    for (float x : hv) {
+        if (!std::isfinite(x)) return RTSDF_EINVAL;
+        obj_scale = std::max(obj_scale, std::fabs(x));
+    }
+    float scale = obj_scale;  // bounds world coordinates: |R p + t| <= |p| + |t|
+    for (int i = 0; i < ninst; ++i) {
+        for (int k = 0; k < 12; ++k)
+            if (!std::isfinite(hT[12 * i + k])) return RTSDF_EINVAL;
+        if (!rigid_ok(&hT[12 * i])) return RTSDF_EINVAL;
+        for (int a = 0; a < 3; ++a) scale = std::max(scale, obj_scale + std::fabs(hT[12 * i + 4 * a + 3]));
+    }
+    const float pad = std::ldexp(scale, -17);
+
+    // each part's own hierarchy, in object space
+    struct Part {
+        std::vector<BvhNode> nodes;
+        std::vector<int32_t> ref_face, ref_path;  // leaf order, global face index
+        int depth = 0, max_leaf = 0;
+        Aabb box;
+    };
+    std::vector<Part> parts(ninst);
+    for (int i = 0; i < ninst; ++i) {
+        const int f0 = instance_faces[i], nti = instance_faces[i + 1] - f0;
+        std::vector<int32_t> sub(hf.begin() + 3 * (size_t)f0, hf.begin() + 3 * (size_t)(f0 + nti));
+        HostBuilder B{hv.data(), sub.data(), nti, leaf_size, pad, {}, {}, {}, {}};
+        std::vector<int32_t> ref_tri, ref_path;
+        make_references(hv, sub, nti, B.tb, ref_tri, ref_path);
+        const int nref = (int)ref_tri.size();
+        B.cen.resize((size_t)3 * nref);
+        B.idx.resize(nref);
+        for (int r = 0; r < nref; ++r) {
+            for (int a = 0; a < 3; ++a) B.cen[3 * r + a] = 0.5f * (B.tb[r].lo[a] + B.tb[r].hi[a]);
+            B.idx[r] = r;
+        }
+        const int code = B.build(0, nref, 0);
+        if (code < 0) {  // the whole part is one leaf: a root holding it and an empty leaf
+            B.nodes.emplace_back();
+            float lo[3], hi[3];
+            B.padded(B.range_box(0, nref), lo, hi);
+            BvhNode &nd = B.nodes[0];
+            nd.xy0 = nd.xy1 = make_float4(lo[0], hi[0], lo[1], hi[1]);
+            nd.z01 = make_float4(lo[2], hi[2], lo[2], hi[2]);
+            nd.meta = make_int4(code, leaf_code(0, 0), -1, 0);
+            B.max_depth = 1;
+        }
+        Part &P = parts[i];
+        P.nodes = std::move(B.nodes);
+        P.depth = B.max_depth;
+        P.max_leaf = B.max_leaf;
+        for (int k = 0; k < nref; ++k) {
+            P.ref_face.push_back(f0 + ref_tri[B.idx[k]]);
+            P.ref_path.push_back(ref_path[B.idx[k]]);
+        }
+        const BvhNode &r0 = P.nodes[0];  // the part's box: both slots of its root
+        P.box.reset();
+        const float lo0[3] = {r0.xy0.x, r0.xy0.z, r0.z01.x}, hi0[3] = {r0.xy0.y, r0.xy0.w, r0.z01.y};
+        const float lo1[3] = {r0.xy1.x, r0.xy1.z, r0.z01.z}, hi1[3] = {r0.xy1.y, r0.xy1.w, r0.z01.w};
+        P.box.grow_pt(lo0);  // (a one-leaf part repeats its box in both slots)
+        P.box.grow_pt(hi0);
+        P.box.grow_pt(lo1);
+        P.box.grow_pt(hi1);
+    }
+
+    // top level over the initial world boxes (refit from the transforms on the device)
+    std::vector<Aabb> wbox(ninst);
+    for (int i = 0; i < ninst; ++i) {
+        const float *m = &hT[12 * i];
+        wbox[i].reset();
+        for (int corner = 0; corner < 8; ++corner) {
+            const float p[3] = {(corner & 1) ? parts[i].box.hi[0] : parts[i].box.lo[0],
+                                (corner & 2) ? parts[i].box.hi[1] : parts[i].box.lo[1],
+                                (corner & 4) ? parts[i].box.hi[2] : parts[i].box.lo[2]};
+            float w[3];
+            for (int a = 0; a < 3; ++a) w[a] = m[4 * a] * p[0] + m[4 * a + 1] * p[1] + m[4 * a + 2] * p[2] + m[4 * a + 3];
+            wbox[i].grow_pt(w);
+        }
+    }
+    const int inst_base = ninst - 1;
+    TopBuilder top{wbox, inst_base, {}, 0};
+    std::vector<int> ids(ninst);
+    for (int i = 0; i < ninst; ++i) ids[i] = i;
+    if (ninst > 1) top.build(ids, 0, ninst, 0);
+
+    // concatenate: top nodes, instance nodes, parts
+    std::vector<BvhNode> nodes(top.nodes);
+    nodes.resize((size_t)inst_base + ninst);
+    std::vector<int> inst_parent(ninst, -1);
+    for (int id = 0; id < inst_base; ++id)
+        for (int c : {nodes[id].meta.x, nodes[id].meta.y})
+            if (c >= inst_base) inst_parent[c - inst_base] = id;
+    std::vector<float4> htri;
+    std::vector<int4> hlf;
+    int max_depth = 0, max_leaf = 0;
+    for (int i = 0; i < ninst; ++i) {
+        const int nbase = (int)nodes.size(), rbase = (int)hlf.size();
+        for (const BvhNode &b : parts[i].nodes) {
+            BvhNode nd = b;
+            int *ch[2] = {&nd.meta.x, &nd.meta.y};
+            for (int *c : ch) *c = *c >= 0 ? *c + nbase : leaf_code(leaf_first(*c) + rbase, leaf_count(*c));
+            if (nd.meta.z >= 0) nd.meta.z += nbase;
+            nodes.push_back(nd);
+        }
+        BvhNode &inode = nodes[inst_base + i];
+        inode.xy0 = inode.xy1 = inode.z01 = make_float4(0.f, 0.f, 0.f, 0.f);  // rows written on the device
+        inode.meta = make_int4(nbase, kInstTag, inst_parent[i], i);
+        for (size_t k = 0; k < parts[i].ref_face.size(); ++k) {
+            const int t = parts[i].ref_face[k], path = parts[i].ref_path[k];
+            for (int c = 0; c < 3; ++c) {
+                const float *p = &hv[3 * hf[3 * t + c]];
+                float w = 0.f;
+                if (c == 0) std::memcpy(&w, &t, sizeof(float));
+                if (c == 1) std::memcpy(&w, &path, sizeof(float));
+                htri.push_back(make_float4(p[0], p[1], p[2], w));
+            }
+            hlf.push_back(make_int4(hf[3 * t], hf[3 * t + 1], hf[3 * t + 2], t));
+        }
+        max_depth = std::max(max_depth, parts[i].depth);
+        max_leaf = std::max(max_leaf, parts[i].max_leaf);
+    }
+    const int nref = (int)hlf.size();
+    if ((int64_t)nref >= ((int64_t)1 << 26) - 1) return RTSDF_EINVAL;
+    std::vector<float> obox((size_t)6 * ninst);
+    for (int i = 0; i < ninst; ++i)
+        for (int a = 0; a < 3; ++a) {
+            obox[6 * i + a] = parts[i].box.lo[a];
+            obox[6 * i + 3 + a] = parts[i].box.hi[a];
+        }
+
+    std::unique_ptr<rtsdf_scene> sc(new rtsdf_scene());
+    sc->nv = nv;
+    sc->nt = nt;
+    sc->nref = nref;
+    sc->nnodes = (int)nodes.size();
+    // stack: pending top-level entries, the return marker, then the part's own entries
+    sc->max_depth = top.depth + 2 + max_depth;
+    sc->max_leaf = max_leaf;
+    sc->pad = pad;
+    sc->ninst = ninst;
+    sc->inst_base = inst_base;
+    RTSDF_TRY(hipGetDevice(&sc->device));
+    auto alloc = [&](void **p, size_t bytes) -> bool {
+        if (bytes == 0) bytes = 16;
+        if (hipMalloc(p, bytes) != hipSuccess) return false;
+        sc->bytes += (int64_t)bytes;
+        return true;
+    };
+    if (!alloc((void **)&sc->nodes, sizeof(BvhNode) * nodes.size()) ||
+        !alloc((void **)&sc->tris, sizeof(float4) * htri.size()) ||
+        !alloc((void **)&sc->tmap, sizeof(float4) * (htri.size() + 1)) ||  // +1: the tracer's fetch reads 64 B
+        !alloc((void **)&sc->leaf_faces, sizeof(int4) * hlf.size()) ||
+        !alloc((void **)&sc->vertices, sizeof(float) * 3 * nv) || !alloc((void **)&sc->faces, sizeof(int32_t) * 3 * nt) ||
+        !alloc((void **)&sc->refit_counter, sizeof(int32_t)) || !alloc((void **)&sc->start_nodes, sizeof(int32_t)) ||
+        !alloc((void **)&sc->obj_vertices, sizeof(float) * 3 * nv) ||
+        !alloc((void **)&sc->vert_inst, sizeof(int32_t) * nv) ||
+        !alloc((void **)&sc->inst_obj_box, sizeof(float) * obox.size()) ||
+        !alloc((void **)&sc->inst_world_box, sizeof(float) * obox.size()) ||
+        !alloc((void **)&sc->transforms, sizeof(float) * hT.size())) {
+        rtsdf_scene_destroy(sc.release());
+        return RTSDF_ENOMEM;
+    }
+    bool ok = true;
+    ok &= hipMemcpyAsync(sc->nodes, nodes.data(), sizeof(BvhNode) * nodes.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    ok &= hipMemcpyAsync(sc->tris, htri.data(), sizeof(float4) * htri.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    ok &= hipMemcpyAsync(sc->leaf_faces, hlf.data(), sizeof(int4) * hlf.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    ok &= hipMemcpyAsync(sc->obj_vertices, hv.data(), sizeof(float) * hv.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    ok &= hipMemcpyAsync(sc->faces, hf.data(), sizeof(int32_t) * hf.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    ok &= hipMemcpyAsync(sc->vert_inst, vinst.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, s) == hipSuccess;
+    ok &= hipMemcpyAsync(sc->inst_obj_box, obox.data(), sizeof(float) * obox.size(), hipMemcpyHostToDevice, s) ==
+          hipSuccess;
+    ok &= hipMemcpyAsync(sc->transforms, hT.data(), sizeof(float) * hT.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    if (ok) {
+        tri_maps<<<dim3((nref + 255) / 256), dim3(256), 0, s>>>(sc->tris, sc->tmap, nref);
+        ok &= hipGetLastError() == hipSuccess;
+    }
+    if (ok) ok = launch_transforms(sc.get(), nullptr, s) == RTSDF_OK;
+    ok &= hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+        rtsdf_scene_destroy(sc.release());
+        return RTSDF_EHIP;
+    }
+    *out = sc.release();
+    return RTSDF_OK;
+}
+
+extern "C" int rtsdf_scene_create_instanced(const float *vertices, int32_t nv, const int32_t *faces, int32_t nt,
+                                            const int32_t *instance_faces, int32_t ninst, const float *transforms,
+                                            int32_t leaf_size, rtsdf_scene **out, rtsdf_stream stream)
+{
+    int rc = rtsdf_scene_create_instanced_impl(vertices, nv, faces, nt, instance_faces, ninst, transforms, leaf_size,
+                                               out, stream);
+    if (rc != RTSDF_OK) return rc;
+    if ((*out)->max_depth + 1 > 64) rc = RTSDF_EINVAL;  // deeper than the tracer's stack
+    if (rc == RTSDF_OK) rc = rtsdf::ensure_spill(*out);
+    if (rc != RTSDF_OK) {
+        rtsdf_scene_destroy(*out);
+        *out = nullptr;
+    }
+    return rc;
+}
+
+extern "C" int rtsdf_scene_set_transforms(rtsdf_scene *scene, const float *transforms, float *world_vertices,
+                                          rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!scene || scene->ninst == 0 || !transforms) return RTSDF_EINVAL;
+    hipStream_t s = as_stream(stream);
+    if (transforms != scene->transforms)
+        RTSDF_TRY(hipMemcpyAsync(scene->transforms, transforms, sizeof(float) * 12 * scene->ninst,
+                                 hipMemcpyDeviceToDevice, s));
+    return launch_transforms(scene, world_vertices, s);
+}
+
+extern "C" int rtsdf_scene_world_vertices(const rtsdf_scene *scene, float *out, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!scene || (scene->nv > 0 && !out)) return RTSDF_EINVAL;
+    if (scene->nv == 0) return RTSDF_OK;
+    RTSDF_TRY(hipMemcpyAsync(out, scene->vertices, sizeof(float) * 3 * scene->nv, hipMemcpyDeviceToDevice,
+                             as_stream(stream)));
+    return RTSDF_OK;
+}

@@ -5,6 +5,7 @@
 #include "jfa.hip"
 #include "select.hip"
 #include "scene.hip"
+#include "instance.hip"
 #include "trace.hip"
 #include "distance.hip"
 #include "shadow.hip"

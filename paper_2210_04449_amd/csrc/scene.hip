@@ -51,6 +51,10 @@ namespace rtsdf {
 
 constexpr int kMaxBuildDepth = 48;  // median splits below; stack depth <= 63
 constexpr int kMaxLeaf = 31;
+// second child code of an instance node (no leaf code reaches it: references stay below 2^26 - 1)
+constexpr int kInstTag = INT32_MIN;
+// stack entry marking the return from an instance to world space
+constexpr int kReturn = INT32_MIN + 1;
 
 struct alignas(16) BvhNode {
     float4 xy0, xy1, z01;
@@ -85,6 +89,15 @@ struct rtsdf_scene {
     int64_t bytes = 0;
     int sign_policy = RTSDF_SIGN_VOTE;  // how the tracer signs a traced distance
     float shell = 0.f;                  // RTSDF_SIGN_SHELL: half-thickness subtracted from the distance
+    // two-level scenes (rtsdf_scene_create_instanced): nodes = [top-level internal nodes (ninst - 1)]
+    // [instance nodes (ninst)] [each instance's own hierarchy]; `vertices` holds world positions
+    int ninst = 0;
+    int inst_base = 0;                 // node index of instance 0's instance node
+    float *obj_vertices = nullptr;     // [3 nv] object-space positions
+    int32_t *vert_inst = nullptr;      // [nv] instance of each vertex, -1 for vertices no face uses
+    float *inst_obj_box = nullptr;     // [ninst][6] object-space box of each instance's hierarchy
+    float *inst_world_box = nullptr;   // [ninst][6]
+    float *transforms = nullptr;       // [ninst][12] current object-to-world rows
 };
 
 namespace rtsdf {
@@ -626,6 +639,7 @@ extern "C" int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsd
 {
     using namespace rtsdf;
     if (!scene || (scene->nv > 0 && !vertices)) return RTSDF_EINVAL;
+    if (scene->ninst > 0) return RTSDF_EINVAL;  // two-level scenes move by rtsdf_scene_set_transforms
     hipStream_t s = as_stream(stream);
     if (scene->nv > 0 && vertices != scene->vertices)
         RTSDF_TRY(hipMemcpyAsync(scene->vertices, vertices, sizeof(float) * 3 * scene->nv, hipMemcpyDeviceToDevice, s));
@@ -662,12 +676,18 @@ extern "C" int rtsdf_scene_info_get(const rtsdf_scene *scene, rtsdf_scene_info *
     info->max_depth = scene->max_depth;
     info->leaf_size = scene->max_leaf;
     info->device_bytes = scene->bytes;
+    info->instances = scene->ninst;
     return RTSDF_OK;
 }
 
 extern "C" void rtsdf_scene_destroy(rtsdf_scene *scene)
 {
     if (!scene) return;
+    (void)hipFree(scene->obj_vertices);
+    (void)hipFree(scene->vert_inst);
+    (void)hipFree(scene->inst_obj_box);
+    (void)hipFree(scene->inst_world_box);
+    (void)hipFree(scene->transforms);
     (void)hipFree(scene->nodes);
     (void)hipFree(scene->tris);
     (void)hipFree(scene->tmap);

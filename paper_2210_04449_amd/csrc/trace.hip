@@ -524,7 +524,7 @@ __global__ void trace_tile_prefix(const TraceScene *scenes, int n, int32_t *tile
 // (STATS) also count into 64-bit counters at workspace offsets 8, 16, ...:
 // node visits, triangle tests, rays, traversal-loop iterations x 64, refill
 // rounds x 64, lane-iterations with work (LOOP 1 and 2), tiles x 64.
-template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED>
+template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED, bool INST = false>
 __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_waves_per_eu(6, 8)))
 trace_persistent(TraceArgs A)
 {
@@ -715,8 +715,30 @@ trace_persistent(TraceArgs A)
                         ++tri_cur;
                     } else if (do_node) {
                         if (STATS) ++st_nodes;
-                        const int4 m = make_int4(w3.x, w3.y, 0, 0);
-                        node_step_regs(Rs, w0, w1, w2, m, node, tbest, tri_cur, tri_end, push, push_val, pop);
+                        if (INST && w3.y == kInstTag) {
+                            // instance node of a two-level scene: its rows take the (world) ray into the
+                            // part's object space; the return marker restores it
+                            const float ox = w0.x * Rs.ox + w0.y * Rs.oy + w0.z * Rs.oz + w0.w;
+                            const float oy = w1.x * Rs.ox + w1.y * Rs.oy + w1.z * Rs.oz + w1.w;
+                            const float oz = w2.x * Rs.ox + w2.y * Rs.oy + w2.z * Rs.oz + w2.w;
+                            const float dx = w0.x * Rs.dx + w0.y * Rs.dy + w0.z * Rs.dz;
+                            const float dy = w1.x * Rs.dx + w1.y * Rs.dy + w1.z * Rs.dz;
+                            const float dz = w2.x * Rs.dx + w2.y * Rs.dy + w2.z * Rs.dz;
+                            ray_setup(ox, oy, oz, dx, dy, dz, Rs);
+                            push = true;
+                            push_val = kReturn;
+                            node = w3.x;
+                        } else {
+                            const int4 m = make_int4(w3.x, w3.y, 0, 0);
+                            node_step_regs(Rs, w0, w1, w2, m, node, tbest, tri_cur, tri_end, push, push_val, pop);
+                        }
+                    } else if (INST && busy && node == kReturn) {
+                        // the part is done (its last leaf's triangles too): the world ray again, as drawn
+                        const int j = T.tex[slot];
+                        const float4 d = dirs[slot * R + r];
+                        ray_setup(texel_coord(P.lox, j & nfm, P.hf), texel_coord(P.loy, (j >> P.lognf) & nfm, P.hf),
+                                  texel_coord(P.loz, j >> (2 * P.lognf), P.hf), d.x, d.y, d.z, Rs);
+                        pop = true;
                     } else if (busy && node != kDone) {
                         tri_cur = leaf_first(node);
                         tri_end = tri_cur + leaf_count(node);
@@ -973,7 +995,7 @@ static rtsdf_trace_tuning g_tuning = {16, 0, 0, 3, 1, 12};
 constexpr int kMaxBlocksPerCu = 8;  // persistent workgroups per CU (spill area sized for this)
 constexpr int kMinShortStack = 12;  // smallest LDS stack part (spill area sized for this)
 
-template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED>
+template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED, bool INST = false>
 static int launch_trace5(TraceArgs A, hipStream_t s)
 {
     int per_cu = g_tuning.blocks_per_cu;
@@ -986,7 +1008,7 @@ static int launch_trace5(TraceArgs A, hipStream_t s)
     per_cu = std::min(per_cu, kMaxBlocksPerCu);
     const int blocks = num_cus() * per_cu;
     A.spill_stride = blocks * kTraceWaves * kWave;
-    trace_persistent<SL, REFILL, LOOP, STATS, BATCHED><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
+    trace_persistent<SL, REFILL, LOOP, STATS, BATCHED, INST><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
     RTSDF_CHECK_LAUNCH();
     return RTSDF_OK;
 }
@@ -1013,6 +1035,29 @@ template <int SL, bool BATCHED>
 static int launch_trace2(const TraceArgs &A, hipStream_t s)
 {
     return g_tuning.refill == 8 ? launch_trace3<SL, 8, BATCHED>(A, s) : launch_trace3<SL, 16, BATCHED>(A, s);
+}
+
+// two-level scenes: the one-fetch loop only
+template <int SL, int REFILL>
+static int launch_trace_inst2(const TraceArgs &A, hipStream_t s)
+{
+    return g_tuning.stats ? launch_trace5<SL, REFILL, 3, true, false, true>(A, s)
+                          : launch_trace5<SL, REFILL, 3, false, false, true>(A, s);
+}
+
+template <int SL>
+static int launch_trace_inst1(const TraceArgs &A, hipStream_t s)
+{
+    return g_tuning.refill == 8 ? launch_trace_inst2<SL, 8>(A, s) : launch_trace_inst2<SL, 16>(A, s);
+}
+
+static int launch_trace_inst(const TraceArgs &A, hipStream_t s)
+{
+    switch (g_tuning.stack_lds) {
+    case 12: return launch_trace_inst1<12>(A, s);
+    case 24: return launch_trace_inst1<24>(A, s);
+    default: return launch_trace_inst1<16>(A, s);
+    }
 }
 
 template <bool BATCHED>
@@ -1151,7 +1196,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     A.spill_stride = 0;
     A.bin_directions = g_tuning.bin_directions;
     A.dirs = reinterpret_cast<float4 *>(static_cast<char *>(workspace) + 256);
-    return launch_trace<false>(A, s);
+    return scene->ninst > 0 ? launch_trace_inst(A, s) : launch_trace<false>(A, s);
 }
 
 extern "C" int rtsdf_directions(const int32_t *texel, const uint32_t *frame, const int32_t *ray, int32_t n,
@@ -1170,6 +1215,7 @@ extern "C" int rtsdf_closest_hits(const rtsdf_scene *scene, const float *origins
 {
     using namespace rtsdf;
     if (!scene || n < 0 || (n > 0 && (!origins || !dirs || !t_out || !tri_out || !front_out))) return RTSDF_EINVAL;
+    if (scene->ninst > 0) return RTSDF_EINVAL;  // single-level scenes only
     if (n == 0) return RTSDF_OK;
     const int sd = stack_depth_for(scene);
     if (sd > 64) return RTSDF_EINVAL;

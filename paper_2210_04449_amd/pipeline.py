@@ -12,6 +12,8 @@ the texel centre) or ``"trilinear"`` (the coarse field interpolated at the
 texel centre; the tracer then works on the fine grid alone).  ``sign_policy``
 "vote" signs traced distances by the front/back vote of Sec. 2.2; "shell"
 outputs the unsigned distance minus ``shell`` (open or thin surfaces).
+``parts=(part_faces, transforms)`` builds a two-level scene of rigid parts
+(vertices in object space; ``set_transforms`` moves them).
 """
 from __future__ import annotations
 
@@ -27,7 +29,7 @@ class Pipeline:
                  rays: int, seed: int = 0, scene_id: int = 0, alpha: float = 1.0, lo=(0.0, 0.0, 0.0),
                  side: float = 1.0, leaf_size: int = 2, queue_cap: int | None = None, device="cuda",
                  jfa_variant: str = "jfa", sampling: str = "point", sign_policy: str = "vote",
-                 shell: float = 0.0):
+                 shell: float = 0.0, parts=None):
         if sampling not in ("point", "trilinear"):
             raise ValueError(f"sampling must be 'point' or 'trilinear', not {sampling!r}")
         self.sampling = sampling
@@ -56,7 +58,18 @@ class Pipeline:
         self.trace_ws = torch.empty(R.rtsdf_trace_workspace_size(), dtype=torch.uint8, device=dev)
         self.fine_sdf = torch.empty(nf ** 3, dtype=f32, device=dev)
         self.state = R.AccumState(self.fine, dev)
-        self.scene = R.Scene(self.vertices, self.faces, leaf_size)
+        if parts is None:
+            self.scene = R.Scene(self.vertices, self.faces, leaf_size)
+        else:
+            # rigid parts: `vertices` are in object space; voxelization reads the world positions the scene
+            # computes from the transforms
+            part_faces, transforms = parts
+            self.obj_vertices = self.vertices
+            self.vertices = torch.empty_like(self.obj_vertices)
+            self.scene = R.Scene.instanced(self.obj_vertices, self.faces, part_faces,
+                                           transforms.to(self.device, torch.float32).contiguous(), leaf_size)
+            self.scene.world_vertices(self.vertices)
+        self.parts = parts is not None
         self.scene.set_sign(sign_policy, shell)
 
     # -- stages ----------------------------------------------------------
@@ -98,6 +111,8 @@ class Pipeline:
 
     def make_graph(self, first_frame: int = 0, refit: bool = False) -> "R.FrameGraph":
         """Capture one whole update as a HIP graph; each launch advances the frame index."""
+        if refit and self.parts:
+            raise RuntimeError("captured updates refit from vertices; a scene of rigid parts moves by set_transforms")
         self.frame_counter = torch.full((1,), int(first_frame), dtype=torch.int32, device=self.device)
         D = R.FrameDesc()
         D.vertices, D.nv = self.vertices.data_ptr(), self.vertices.shape[0]
@@ -122,8 +137,16 @@ class Pipeline:
 
     def set_vertices(self, vertices: torch.Tensor, stream=None):
         """New positions for the same topology (animated scenes): refit the hierarchy."""
+        if self.parts:
+            raise RuntimeError("a scene of rigid parts moves by set_transforms")
         self.vertices.copy_(vertices)
         self.scene.refit(self.vertices, stream)
+
+    def set_transforms(self, transforms: torch.Tensor, stream=None):
+        """New object-to-world transforms of the rigid parts: top-level refit and world positions."""
+        if not self.parts:
+            raise RuntimeError("set_transforms needs a scene of rigid parts")
+        self.scene.set_transforms(transforms, self.vertices, stream)
 
     def reset(self):
         R.rtsdf_accum_reset(self.fine, self.state)

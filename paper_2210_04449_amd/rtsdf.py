@@ -19,7 +19,7 @@ _P = C.c_void_p
 _i32, _u32, _u64, _f32, _sz = C.c_int32, C.c_uint32, C.c_uint64, C.c_float, C.c_size_t
 
 OK, EINVAL, ENOMEM, EHIP, EDEVICE = 0, -1, -2, -3, -4
-ERR_FACE_INDEX, ERR_VERTEX_RANGE, ERR_QUEUE_FULL, ERR_BATCH = 1, 2, 4, 8
+ERR_FACE_INDEX, ERR_VERTEX_RANGE, ERR_QUEUE_FULL, ERR_BATCH, ERR_TRANSFORM = 1, 2, 4, 8, 16
 
 
 class Grid(C.Structure):
@@ -76,7 +76,7 @@ class TraceTuning(C.Structure):
 
 class SceneInfo(C.Structure):
     _fields_ = [("nv", _i32), ("nt", _i32), ("nodes", _i32), ("max_depth", _i32), ("leaf_size", _i32),
-                ("device_bytes", C.c_int64), ("references", _i32)]
+                ("device_bytes", C.c_int64), ("references", _i32), ("instances", _i32)]
 
 
 class RtsdfError(RuntimeError):
@@ -120,6 +120,10 @@ def _load():
         "rtsdf_trace_backward": ([_P, Grid, Accum, _P, _P, _u64, _u32, _P, _P], _i32),
         "rtsdf_shadow": ([Grid, _P, _P, _i32, _P, _f32, _f32, _i32, _f32, _f32, _P, _P], _i32),
         "rtsdf_scene_set_sign": ([_P, _i32, _f32], _i32),
+        "rtsdf_scene_create_instanced": ([_P, _i32, _P, _i32, C.POINTER(_i32), _i32, _P, _i32, C.POINTER(_P), _P],
+                                         _i32),
+        "rtsdf_scene_set_transforms": ([_P, _P, _P, _P], _i32),
+        "rtsdf_scene_world_vertices": ([_P, _P, _P], _i32),
         "rtsdf_point_distance": ([_P, _P, _i32, _P, _P, _P], _i32),
         "rtsdf_texel_distance": ([_P, Grid, _P, _i32, _P, _P, _P], _i32),
         "rtsdf_shadow_ex": ([Grid, _P, _P, _i32, C.POINTER(ShadowParams), _P, _P, _P], _i32),
@@ -266,6 +270,30 @@ class Scene:
 
     def refit(self, vertices, stream=None):
         _check("rtsdf_scene_refit", _lib.rtsdf_scene_refit(self.handle, _ptr(vertices), _stream(stream)))
+
+    @classmethod
+    def instanced(cls, vertices, faces, instance_faces, transforms, leaf_size: int = 4, stream=None) -> "Scene":
+        """Two-level scene of rigid parts: part i owns faces instance_faces[i]:instance_faces[i+1] (host ints),
+        vertices are in object space, transforms float32 [ninst, 12] (device) are object-to-world rows."""
+        _dtype(vertices, torch.float32, "vertices")
+        _dtype(faces, torch.int32, "faces")
+        _dtype(transforms, torch.float32, "transforms")
+        offs = [int(x) for x in instance_faces]
+        arr = (_i32 * len(offs))(*offs)
+        h = _P()
+        _check("rtsdf_scene_create_instanced", _lib.rtsdf_scene_create_instanced(
+            _ptr(vertices), vertices.shape[0], _ptr(faces), faces.shape[0], arr, len(offs) - 1, _ptr(transforms),
+            int(leaf_size), C.byref(h), _stream(stream)))
+        self = cls.__new__(cls)
+        self.handle = h
+        return self
+
+    def set_transforms(self, transforms, world_vertices=None, stream=None):
+        _check("rtsdf_scene_set_transforms", _lib.rtsdf_scene_set_transforms(self.handle, _ptr(transforms),
+                                                                             _ptr(world_vertices), _stream(stream)))
+
+    def world_vertices(self, out, stream=None):
+        _check("rtsdf_scene_world_vertices", _lib.rtsdf_scene_world_vertices(self.handle, _ptr(out), _stream(stream)))
 
     def set_sign(self, policy: str = "vote", shell: float = 0.0):
         """How traced distances are signed: "vote" (front/back hit counts) or "shell" (distance - shell)."""

@@ -360,6 +360,57 @@ class DynamicScene:
         return _as_mesh(*_merge(parts))
 
 
+    def moving_transform(self, i: int, frame: int) -> np.ndarray:
+        """Rigid object-to-world rows (3 x 4) taking moving primitive i from its frame-0 placement to frame
+        ``frame``: x_f = rot_f (x_0 - c - s_0) + c + s_f."""
+        p = self.placements[i]
+        rot = axis_rotation(self.axes[i], self.rates[i] * frame)
+        s0 = self.radii[i] * np.array([math.cos(self.phases[i]), 0.0, math.sin(self.phases[i])])
+        ph = self.phases[i] + 0.05 * frame
+        sf = self.radii[i] * np.array([math.cos(ph), 0.0, math.sin(ph)])
+        t = p.center + sf - rot @ (p.center + s0)
+        return np.concatenate([rot, t[:, None]], axis=1)
+
+    def parts(self):
+        """The same scene as rigid parts: part 0 is everything static (identity transform), parts 1.. are the
+        moving primitives at their frame-0 placement.  Returns (vertices, faces, part face offsets, moving ids)."""
+        static = [room_box()] + [self._static[i] for i in range(len(self.placements)) if i not in self.moving]
+        moving = sorted(self.moving)
+        chunks = [_merge(static)] + [place(self.placements[i].kind, self.detail, self.placements[i],
+                                           rot=np.eye(3), shift=self.radii[i] * np.array(
+                                               [math.cos(self.phases[i]), 0.0, math.sin(self.phases[i])]))
+                                     for i in moving]
+        offs = [0]
+        for _, f in chunks:
+            offs.append(offs[-1] + len(f))
+        v, f = _merge(chunks)
+        return v.astype(np.float32), f.astype(np.int32), offs, moving
+
+    def part_transforms(self, frame: int) -> np.ndarray:
+        """float32 [1 + moving, 12]: identity for the static part, then each moving primitive's transform."""
+        rows = [np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)]
+        rows += [self.moving_transform(i, frame) for i in sorted(self.moving)]
+        return np.stack([r.reshape(12) for r in rows]).astype(np.float32)
+
+
+def rigid_parts(seed: int = 6):
+    """A small scene of three rigid parts for tests: a ground quad (part 0), an icosphere and a torus, with
+    seeded rigid transforms.  Returns (object vertices, faces, part face offsets, transforms [3, 12])."""
+    rng = np.random.default_rng(seed)
+    quad = ground_quad(0.15)
+    sph = _unit_icosphere(2)
+    tor = _unit_torus(24, 8, 0.3)
+    parts = [(quad.vertices.astype(np.float64), quad.faces), (sph[0] * 0.18, sph[1]), (tor[0] * 0.12, tor[1])]
+    offs = [0]
+    for _, f in parts:
+        offs.append(offs[-1] + len(f))
+    v, f = _merge(parts)
+    T = [np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)]
+    for c in ((0.35, 0.45, 0.5), (0.7, 0.4, 0.55)):
+        T.append(np.concatenate([random_rotation(rng), np.asarray(c)[:, None]], axis=1))
+    return v.astype(np.float32), f.astype(np.int32), offs, np.stack([t.reshape(12) for t in T]).astype(np.float32)
+
+
 def batched_scenes(n_scenes: int = 64, seed0: int = 3) -> list[Workload]:
     """``n_scenes`` independent scenes of uneven size (1k-100k triangles, log-uniform)."""
     out = []

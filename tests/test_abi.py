@@ -101,6 +101,14 @@ def test_host_validation(R):
         assert L.rtsdf_trace_config(C.byref(t)) == R.EINVAL
     assert L.rtsdf_trace_config(None) == R.EINVAL
     assert L.rtsdf_scene_set_sign(None, 0, 0.0) == R.EINVAL
+    offs = (C.c_int32 * 3)(0, 1, 2)
+    h = C.c_void_p()
+    # host checks of a two-level scene: no parts, offsets not ending at nt, an empty part
+    assert L.rtsdf_scene_create_instanced(dummy, 3, dummy, 2, offs, 0, dummy, 2, C.byref(h), None) == R.EINVAL
+    assert L.rtsdf_scene_create_instanced(dummy, 3, dummy, 3, offs, 2, dummy, 2, C.byref(h), None) == R.EINVAL
+    bad = (C.c_int32 * 3)(0, 0, 2)
+    assert L.rtsdf_scene_create_instanced(dummy, 3, dummy, 2, bad, 2, dummy, 2, C.byref(h), None) == R.EINVAL
+    assert L.rtsdf_scene_set_transforms(None, dummy, None, None) == R.EINVAL
     default = R.rtsdf_trace_config_get().as_dict()
     prev = R.rtsdf_trace_config(refill=8, stack_lds=24)
     assert prev.as_dict() == default and R.rtsdf_trace_config_get().refill == 8
@@ -113,7 +121,8 @@ def test_struct_layouts_match_header(R, tmp_path):
     structs = {
         "rtsdf_grid": (R.Grid, ["lo", "h", "n"]),
         "rtsdf_accum": (R.Accum, ["u", "hits", "arg_tri", "arg_ray"]),
-        "rtsdf_scene_info": (R.SceneInfo, ["nv", "nt", "nodes", "max_depth", "leaf_size", "device_bytes", "references"]),
+        "rtsdf_scene_info": (R.SceneInfo, ["nv", "nt", "nodes", "max_depth", "leaf_size", "device_bytes", "references",
+                                            "instances"]),
         "rtsdf_trace_tuning": (R.TraceTuning, ["refill", "blocks_per_cu", "stats", "loop", "bin_directions",
                                                "stack_lds"]),
         "rtsdf_frame_desc": (R.FrameDesc, [f for f, _ in R.FrameDesc._fields_]),
