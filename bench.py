@@ -55,11 +55,14 @@ def parse():
     ap.add_argument("--leaf-size", type=int, default=2)
     ap.add_argument("--jfa", default="jfa", choices=["jfa", "jfa+1", "jfa+2", "1+jfa"],
                     help="jump-flooding pass schedule (the extra-pass variants reduce its errors)")
-    ap.add_argument("--study", default=None, choices=["alpha"],
-                    help="instead of the benchmark: decay alpha against stale history on the moving scene")
+    ap.add_argument("--study", default=None, choices=["alpha", "refit"],
+                    help="instead of the benchmark: decay alpha against stale history on the moving scene, or one "
+                         "refitted hierarchy against a two-level scene over a continuous animation")
     ap.add_argument("--alphas", type=float, nargs="+", default=[1.0, 0.95, 0.9, 0.75, 0.5])
     ap.add_argument("--study-frames", type=int, default=24)
     ap.add_argument("--alpha", type=float, default=None, help="override the workload's decay alpha")
+    ap.add_argument("--parts", action="store_true",
+                    help="dynamic workload as a two-level scene of rigid parts instead of one refitted hierarchy")
     ap.add_argument("--no-shadow", action="store_true", help="skip timing the soft-shadow consumer")
     ap.add_argument("--sampling", default="point", choices=["point", "trilinear"],
                     help="how a fine texel reads the coarse SDF for selection and c_t")
@@ -131,6 +134,8 @@ def main():
 
     if args.study == "alpha":
         return run_alpha_study(args)
+    if args.study == "refit":
+        return run_refit_study(args)
     if args.config == "batched":
         return run_batched(args)
     if args.config == "diff":
@@ -147,21 +152,32 @@ def main():
         torch.cuda.synchronize()
         del a, b
     R.rtsdf_trace_config(**tuning)
-    p = Pipeline(torch.from_numpy(w.mesh.vertices).to(dev), torch.from_numpy(w.mesh.faces).to(dev), w.nc, w.nf,
-                 w.beta, w.d, w.rays, seed=0, scene_id=w.scene_seed,
-                 alpha=w.alpha if args.alpha is None else args.alpha, leaf_size=args.leaf_size,
-                 jfa_variant=args.jfa, sampling=args.sampling)
+    use_parts = args.parts and args.config == "dynamic"
+    kw = dict(seed=0, scene_id=w.scene_seed, alpha=w.alpha if args.alpha is None else args.alpha,
+              leaf_size=args.leaf_size, jfa_variant=args.jfa, sampling=args.sampling)
+    dyn_frames = dyn_T = None
+    if use_parts:
+        # the moving primitives as rigid parts of a two-level scene; 8 transform sets cycled
+        dyn = w.extra["scene"]
+        pv, pf, offs, _ = dyn.parts()
+        dyn_T = [torch.from_numpy(dyn.part_transforms(f)).to(dev) for f in range(8)]
+        p = Pipeline(torch.from_numpy(pv).to(dev), torch.from_numpy(pf).to(dev), w.nc, w.nf, w.beta, w.d, w.rays,
+                     parts=(offs, dyn_T[0]), **kw)
+    else:
+        p = Pipeline(torch.from_numpy(w.mesh.vertices).to(dev), torch.from_numpy(w.mesh.faces).to(dev), w.nc, w.nf,
+                     w.beta, w.d, w.rays, **kw)
+        if args.config == "dynamic":
+            # animated subset moves rigidly; 8 distinct vertex sets are generated up front and cycled
+            dyn = w.extra["scene"]
+            dyn_frames = [torch.from_numpy(dyn.mesh(f).vertices).to(dev) for f in range(8)]
     info = p.scene.info()
     stream = torch.cuda.current_stream()
-    dyn_frames = None
-    if args.config == "dynamic":
-        # animated subset moves rigidly; 8 distinct vertex sets are generated up front and cycled
-        dyn = w.extra["scene"]
-        dyn_frames = [torch.from_numpy(dyn.mesh(f).vertices).to(dev) for f in range(8)]
 
     def update(f):
         if dyn_frames is not None:
             p.set_vertices(dyn_frames[f % len(dyn_frames)])
+        if dyn_T is not None:
+            p.set_transforms(dyn_T[f % len(dyn_T)])
 
     if args.autotune:
         from paper_2210_04449_amd import autotune
@@ -214,7 +230,7 @@ def main():
     achieved = ops / trace_s / 1e12
 
     graph_ms = None
-    if args.graph:
+    if args.graph and not use_parts:  # captured updates move geometry by refitting from vertices
         g = p.make_graph(first_frame=args.warmup + K + 1, refit=dyn_frames is not None)
         g.launch()  # warm-up replay
         torch.cuda.synchronize()
@@ -299,6 +315,9 @@ def main():
     }
     if dyn_frames is not None:
         out["config"]["dynamic"] = "20% of primitives move rigidly; 8 precomputed vertex sets cycled; refit each update"
+    if use_parts:
+        out["config"]["dynamic"] = ("20% of primitives move rigidly, as parts of a two-level scene; 8 precomputed "
+                                    "transform sets cycled; top-level refit and world positions each update")
     if not args.no_cpu_baseline and args.config != "dynamic":
         out["cpu_baseline"] = cpu_baseline(w, selected, args.cpu_seconds, args.sampling)
     print(json.dumps(out), flush=True)
@@ -362,9 +381,11 @@ def accuracy(R, p, tol_texels: float = 0.25):
         return None
     q = p.queue[:n]
     exact = torch.empty(n, dtype=torch.float32, device=q.device)
+    # distance queries take single-level scenes: a two-level scene is asked through its world mesh
+    dscene = R.Scene(p.vertices, p.faces) if p.parts else p.scene
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
-    R.rtsdf_texel_distance(p.scene, p.fine, q, exact)
+    R.rtsdf_texel_distance(dscene, p.fine, q, exact)
     b.record()
     ql = q.long()
     u = p.state.u[ql]
@@ -384,6 +405,8 @@ def accuracy(R, p, tol_texels: float = 0.25):
     qs = torch.quantile(gap[torch.randperm(gap.numel(), device=gap.device)[:1 << 20]],
                         torch.tensor([0.5, 0.95, 0.99], dtype=torch.float64, device=gap.device)).tolist()
     torch.cuda.synchronize()
+    if dscene is not p.scene:
+        dscene.close()
     return {
         "texels": n,
         "finite_fraction": round(fin.float().mean().item(), 5),
@@ -432,6 +455,61 @@ def run_alpha_study(args):
     print(json.dumps({"study": "alpha vs stale history", "workload": w.name, "frames": frames,
                       "fine": w.nf, "rays_per_texel": w.rays, "motion": "20% of primitives rigid, continuous",
                       "units": "fine texels", "rows": rows}), flush=True)
+
+
+def run_refit_study(args):
+    """One refitted hierarchy against a two-level scene of rigid parts on the moving-scene workload, over a
+    continuous animation: per-update time (geometry update + the whole SDF update) frame by frame."""
+    import torch
+
+    import paper_2210_04449_amd.rtsdf as R
+    from paper_2210_04449_amd.pipeline import Pipeline
+    from synth.scenes import workload
+
+    w = workload("dynamic")
+    dyn = w.extra["scene"]
+    dev = torch.device("cuda:0")
+    frames = args.study_frames
+    stream = torch.cuda.current_stream()
+    pv, pf, offs, _ = dyn.parts()
+    rows = {}
+    for kind in ("refit", "parts"):
+        if kind == "refit":
+            verts = [torch.from_numpy(dyn.mesh(f).vertices).to(dev) for f in range(frames)]
+            p = Pipeline(verts[0].clone(), torch.from_numpy(w.mesh.faces).to(dev), w.nc, w.nf, w.beta, w.d, w.rays,
+                         scene_id=w.scene_seed, alpha=w.alpha, leaf_size=args.leaf_size)
+            move = lambda f: p.set_vertices(verts[f])  # noqa: E731
+        else:
+            Ts = [torch.from_numpy(dyn.part_transforms(f)).to(dev) for f in range(frames)]
+            p = Pipeline(torch.from_numpy(pv).to(dev), torch.from_numpy(pf).to(dev), w.nc, w.nf, w.beta, w.d, w.rays,
+                         scene_id=w.scene_seed, alpha=w.alpha, leaf_size=args.leaf_size, parts=(offs, Ts[0]))
+            move = lambda f: p.set_transforms(Ts[f])  # noqa: E731
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(frames)]
+        for f in range(frames):
+            ev[f][0].record(stream)
+            move(f)
+            p.voxelize()
+            p.jfa()
+            p.select()
+            ev[f][1].record(stream)
+            p.trace(f)
+            ev[f][2].record(stream)
+        torch.cuda.synchronize()
+        total = [a.elapsed_time(c) for a, _, c in ev]
+        trace = [b.elapsed_time(c) for _, b, c in ev]
+        rows[kind] = {"ms_per_update": [round(x, 2) for x in total], "trace_ms": [round(x, 2) for x in trace],
+                      "mean_ms": round(sum(total) / frames, 2), "first4_ms": round(sum(total[:4]) / 4, 2),
+                      "last4_ms": round(sum(total[-4:]) / 4, 2), "triangles": int(p.faces.shape[0]),
+                      "selected_last": p.selected()}
+        print(f"[{kind}] mean {rows[kind]['mean_ms']} ms, first 4 {rows[kind]['first4_ms']}, "
+              f"last 4 {rows[kind]['last4_ms']}", file=sys.stderr, flush=True)
+        p.close()
+        del p
+        torch.cuda.empty_cache()
+    print(json.dumps({"study": "refit vs two-level", "workload": w.name, "frames": frames, "fine": w.nf,
+                      "rays_per_texel": w.rays, "motion": "20% of primitives rigid, continuous", "rows": rows}),
+          flush=True)
 
 
 def _base_record(args, value_ms, config):

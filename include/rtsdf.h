@@ -227,28 +227,30 @@ int rtsdf_scene_create(const float *vertices, int32_t nv, const int32_t *faces, 
 int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsdf_stream stream);
 int rtsdf_scene_info_get(const rtsdf_scene *scene, rtsdf_scene_info *info);
 
-/* Two-level scene of rigid parts (for scenes whose moving geometry moves   */
-/* rigidly; refitting one hierarchy loosens it frame by frame, see the      */
-/* moving-scene workload).  Part i owns faces [instance_faces[i],           */
-/* instance_faces[i + 1]) (host array of ninst + 1 offsets, 0 first, nt     */
-/* last, every part at least one face) and the vertices they use (a vertex  */
-/* used by two parts is EINVAL).  vertices are in each part's object space; */
-/* transforms (device, float32 [ninst][12]) are the parts' object-to-world  */
-/* rows (r00 r01 r02 t0, r10 r11 r12 t1, r20 r21 r22 t2) and must be rigid: */
-/* R R^T = I and det R = 1 within 1e-4 (EINVAL at create, ERR_TRANSFORM at  */
-/* set_transforms).  Each part gets its own hierarchy, built once in object */
-/* space; a top-level tree over the parts' world boxes (median splits,      */
-/* topology fixed at create) is refit by rtsdf_scene_set_transforms, which  */
-/* also recomputes the world positions of every vertex (each coordinate     */
-/* ((r0 x + r1 y) + r2 z) + t, float operations rounded once) into the      */
-/* scene and, if world_vertices is non-NULL, into that caller buffer        */
-/* (float32 [nv][3], e.g. for rtsdf_voxelize).  Triangle ids (hits, argmin  */
-/* records, gradients) are global face indices; rtsdf_trace_backward gives  */
-/* gradients with respect to the world positions.  The tracer uses its one- */
-/* fetch loop (tuning loop 3) for two-level scenes whatever the tuning says; */
-/* rtsdf_scene_refit, rtsdf_closest_hits, rtsdf_point_distance and          */
-/* rtsdf_texel_distance return EINVAL for them, and batches do not take     */
-/* them.  rtsdf_scene_world_vertices copies the current world positions.    */
+/* Two-level scene: a static world plus rigidly moving parts (refitting one */
+/* hierarchy over moving geometry loosens it frame after frame).  Part i     */
+/* owns faces [instance_faces[i], instance_faces[i + 1]) (host array of      */
+/* ninst + 1 offsets, 0 first, nt last) and the vertices they use (a vertex  */
+/* used by two parts is EINVAL).  Part 0 is the static world (world          */
+/* coordinates, may have no faces); parts 1.. move and have at least one     */
+/* face each, their vertices in object space.  transforms (device, float32   */
+/* [ninst][12], row 0 unused) are the parts' object-to-world rows            */
+/* (r00 r01 r02 t0, r10 r11 r12 t1, r20 r21 r22 t2) and must be rigid:       */
+/* R R^T = I and det R = 1 within 1e-4 (EINVAL at create, ERR_TRANSFORM at   */
+/* set_transforms).  Each moving part gets its own hierarchy, built once in  */
+/* object space; the top level is one surface-area-heuristic tree over the   */
+/* static triangles and the moving parts' world boxes, whose nodes above the */
+/* moving parts rtsdf_scene_set_transforms refits.  set_transforms also     */
+/* recomputes the world position of every vertex (each coordinate            */
+/* ((r0 x + r1 y) + r2 z) + t, float operations rounded once) into the scene */
+/* and, if world_vertices is non-NULL, into that caller buffer (float32      */
+/* [nv][3], e.g. for rtsdf_voxelize).  Triangle ids (hits, argmin records,   */
+/* gradients) are global face indices; rtsdf_trace_backward gives gradients  */
+/* with respect to the world positions.  The tracer uses its one-fetch loop  */
+/* (tuning loop 3) for two-level scenes whatever the tuning says;            */
+/* rtsdf_scene_refit, rtsdf_closest_hits, rtsdf_point_distance and           */
+/* rtsdf_texel_distance return EINVAL for them, and batches do not take      */
+/* them.  rtsdf_scene_world_vertices copies the current world positions.     */
 int rtsdf_scene_create_instanced(const float *vertices, int32_t nv, const int32_t *faces, int32_t nt,
                                  const int32_t *instance_faces, int32_t ninst, const float *transforms,
                                  int32_t leaf_size, rtsdf_scene **out, rtsdf_stream stream);

@@ -1,26 +1,29 @@
-// Two-level scenes: parts that move rigidly keep their own hierarchy.
+// Two-level scenes: a static world plus parts that move rigidly.
 //
 // Refitting one hierarchy over moving geometry keeps its topology while the
-// boxes of moving parts grow and overlap, so tracing slows frame after frame.
-// When the scene is a set of rigid parts (instances), each part's hierarchy
-// is built once in its object space and stays tight; a small top-level tree
-// over the parts' world boxes is refit per frame from their transforms.
+// boxes of moving parts sweep through their neighbours', so tracing slows
+// frame after frame (on the moving-scene workload an update takes 20x longer
+// after 48 frames of continuous motion).  Here part 0 is the static world and
+// parts 1.. move rigidly: each moving part's hierarchy is built once in its
+// object space and stays tight, and the top level is one surface-area-
+// heuristic tree over the static triangles (references, as in a single-level
+// scene) and the moving parts' world boxes, each moving part a child of its
+// own.  Per frame only the moving parts' boxes change: the nodes above them
+// are refit level by level, deepest first.
 //
-// Node array: [top-level internal nodes (ninst - 1)] [instance nodes (ninst)]
-// [hierarchy of instance 0] [hierarchy of instance 1] ...  Top-level children
-// are node indices (internal or instance nodes).  An instance node carries
-// the rows of its world-to-object transform in the three box slots and
-// (root of the part's hierarchy, kInstTag) as its children: the tracer that
-// reaches it moves its ray into object space, pushes kReturn and descends;
-// reaching kReturn, once the last leaf of the part is tested, brings the ray
-// back to world space.  The transforms are
-// rigid (rotation and translation), so the ray parameter t, and with it the
-// closest-hit order, is the same in both spaces.  Triangle records carry the
-// global face index, so hits, the argmin record and the gradient name faces
-// of the whole mesh.  World vertex positions (for voxelization and the
-// gradient) are recomputed from the object positions at every transform
-// update, each coordinate as ((r0 x + r1 y) + r2 z) + t with every float
-// operation rounded once.
+// Node array: [top level] [instance nodes (one per moving part)] [hierarchy of
+// moving part 1] [part 2] ...  An instance node carries the rows of its
+// world-to-object transform in the three box slots and (root of the part's
+// hierarchy, kInstTag) as its children: the tracer that reaches it moves its
+// ray into object space, pushes kReturn and descends; reaching kReturn, once
+// the part's last leaf is tested, brings the ray back to world space.  The
+// transforms are rigid (rotation and translation), so the ray parameter t,
+// and with it the closest-hit order, is the same in both spaces.  Triangle
+// records carry the global face index, so hits, the argmin record and the
+// gradient name faces of the whole mesh.  World vertex positions (for
+// voxelization and the gradient) are recomputed from the object positions at
+// every transform update, each coordinate as ((r0 x + r1 y) + r2 z) + t with
+// every float operation rounded once.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -46,27 +49,27 @@ __host__ __device__ inline bool rigid_ok(const float *m)
     return err <= kRigidTol && fabsf(det - 1.0f) <= kRigidTol;
 }
 
-// world-to-object rows into each instance node; world box of each part's hierarchy
-__global__ void inst_update(const float *__restrict__ T, int n, BvhNode *nodes, int inst_base,
+// moving part k (part k + 1): world-to-object rows into its instance node, world box of its hierarchy
+__global__ void inst_update(const float *__restrict__ T, int nmov, BvhNode *nodes, int inst_base,
                             const float *__restrict__ obj_box, float *__restrict__ world_box, float pad)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nmov) return;
     float m[12];
-    for (int k = 0; k < 12; ++k) m[k] = T[12 * i + k];
+    for (int q = 0; q < 12; ++q) m[q] = T[12 * (k + 1) + q];
     if (!rigid_ok(m)) raise_error(RTSDF_ERR_TRANSFORM);
     float inv[12];
     for (int r = 0; r < 3; ++r) {
         for (int c = 0; c < 3; ++c) inv[4 * r + c] = m[4 * c + r];
         inv[4 * r + 3] = -(m[r] * m[3] + m[4 + r] * m[7] + m[8 + r] * m[11]);
     }
-    BvhNode *nd = &nodes[inst_base + i];
+    BvhNode *nd = &nodes[inst_base + k];
     nd->xy0 = make_float4(inv[0], inv[1], inv[2], inv[3]);
     nd->xy1 = make_float4(inv[4], inv[5], inv[6], inv[7]);
     nd->z01 = make_float4(inv[8], inv[9], inv[10], inv[11]);
     float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
     float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-    const float *b = obj_box + 6 * i;
+    const float *b = obj_box + 6 * k;
     for (int corner = 0; corner < 8; ++corner) {
         const float p[3] = {b[(corner & 1) ? 3 : 0], b[(corner & 2) ? 4 : 1], b[(corner & 4) ? 5 : 2]};
         for (int a = 0; a < 3; ++a) {
@@ -76,37 +79,43 @@ __global__ void inst_update(const float *__restrict__ T, int n, BvhNode *nodes, 
         }
     }
     for (int a = 0; a < 3; ++a) {
-        world_box[6 * i + a] = nextafterf(lo[a] - pad, -__builtin_inff());
-        world_box[6 * i + 3 + a] = nextafterf(hi[a] + pad, __builtin_inff());
+        world_box[6 * k + a] = nextafterf(lo[a] - pad, -__builtin_inff());
+        world_box[6 * k + 3 + a] = nextafterf(hi[a] + pad, __builtin_inff());
     }
 }
 
-// top-level boxes, children before parents (nodes are numbered in preorder)
-__global__ void tlas_refit(BvhNode *nodes, int ntop, int inst_base, const float *__restrict__ world_box)
+// the top-level nodes above moving parts, one level at a time from the deepest (one workgroup); a slot whose
+// child is a leaf of static triangles keeps its box
+__global__ void __launch_bounds__(256) top_refit(BvhNode *nodes, const int32_t *__restrict__ dirty,
+                                                 const int32_t *__restrict__ level_off, int nlevels, int inst_base,
+                                                 int nmov, const float *__restrict__ world_box)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int id = ntop - 1; id >= 0; --id) {
-        BvhNode *p = &nodes[id];
-        const int c[2] = {p->meta.x, p->meta.y};
-        for (int s = 0; s < 2; ++s) {
-            float lo[3], hi[3];
-            if (c[s] >= inst_base) {
-                const float *b = world_box + 6 * (c[s] - inst_base);
-                for (int a = 0; a < 3; ++a) {
-                    lo[a] = b[a];
-                    hi[a] = b[3 + a];
+    for (int L = 0; L < nlevels; ++L) {
+        for (int k = level_off[L] + (int)threadIdx.x; k < level_off[L + 1]; k += blockDim.x) {
+            BvhNode *p = &nodes[dirty[k]];
+            const int c[2] = {p->meta.x, p->meta.y};
+            for (int s = 0; s < 2; ++s) {
+                if (c[s] < 0) continue;
+                float lo[3], hi[3];
+                if (c[s] >= inst_base && c[s] < inst_base + nmov) {
+                    const float *b = world_box + 6 * (c[s] - inst_base);
+                    for (int a = 0; a < 3; ++a) {
+                        lo[a] = b[a];
+                        hi[a] = b[3 + a];
+                    }
+                } else {
+                    float l2[3], h2[3];
+                    get_slot(&nodes[c[s]], 0, lo, hi);
+                    get_slot(&nodes[c[s]], 1, l2, h2);
+                    for (int a = 0; a < 3; ++a) {
+                        lo[a] = fminf(lo[a], l2[a]);
+                        hi[a] = fmaxf(hi[a], h2[a]);
+                    }
                 }
-            } else {
-                float l2[3], h2[3];
-                get_slot(&nodes[c[s]], 0, lo, hi);
-                get_slot(&nodes[c[s]], 1, l2, h2);
-                for (int a = 0; a < 3; ++a) {
-                    lo[a] = fminf(lo[a], l2[a]);
-                    hi[a] = fmaxf(hi[a], h2[a]);
-                }
+                set_slot(p, s, lo, hi);
             }
-            set_slot(p, s, lo, hi);
         }
+        __syncthreads();
     }
 }
 
@@ -119,7 +128,7 @@ __global__ void inst_world_vertices(const float *__restrict__ obj, const int32_t
     const float x = obj[3 * v], y = obj[3 * v + 1], z = obj[3 * v + 2];
     const int i = vinst[v];
     float w[3] = {x, y, z};
-    if (i >= 0) {
+    if (i > 0) {  // part 0 is the static world
         const float *m = T + 12 * i;
         for (int a = 0; a < 3; ++a)
             w[a] = rn_add(rn_add(rn_add(rn_mul(m[4 * a], x), rn_mul(m[4 * a + 1], y)), rn_mul(m[4 * a + 2], z)),
@@ -131,57 +140,15 @@ __global__ void inst_world_vertices(const float *__restrict__ obj, const int32_t
     }
 }
 
-namespace {
-
-// top level over the parts' world boxes: median split on the longest axis of the centres, preorder numbering
-struct TopBuilder {
-    const std::vector<Aabb> &box;
-    int inst_base;
-    std::vector<BvhNode> nodes;
-    int depth = 0;
-
-    int build(std::vector<int> &ids, int b, int e, int d)
-    {
-        if (e - b == 1) {
-            depth = std::max(depth, d);
-            return inst_base + ids[b];
-        }
-        Aabb cb;
-        cb.reset();
-        for (int k = b; k < e; ++k) {
-            float c[3];
-            for (int a = 0; a < 3; ++a) c[a] = 0.5f * (box[ids[k]].lo[a] + box[ids[k]].hi[a]);
-            cb.grow_pt(c);
-        }
-        int axis = 0;
-        for (int a = 1; a < 3; ++a)
-            if (cb.hi[a] - cb.lo[a] > cb.hi[axis] - cb.lo[axis]) axis = a;
-        const int mid = b + (e - b) / 2;
-        std::nth_element(ids.begin() + b, ids.begin() + mid, ids.begin() + e, [&](int x, int y) {
-            const float cx = box[x].lo[axis] + box[x].hi[axis], cy = box[y].lo[axis] + box[y].hi[axis];
-            return cx < cy || (cx == cy && x < y);
-        });
-        const int id = (int)nodes.size();
-        nodes.emplace_back();
-        const int c0 = build(ids, b, mid, d + 1);
-        const int c1 = build(ids, mid, e, d + 1);
-        nodes[id].meta = make_int4(c0, c1, -1, 0);
-        if (c0 < inst_base) nodes[c0].meta.z = id;
-        if (c1 < inst_base) nodes[c1].meta.z = id;
-        return id;
-    }
-};
-
-}  // namespace
-
 static int launch_transforms(rtsdf_scene *sc, float *world_out, hipStream_t s)
 {
-    const int n = sc->ninst;
-    inst_update<<<dim3((n + 63) / 64), dim3(64), 0, s>>>(sc->transforms, n, sc->nodes, sc->inst_base,
-                                                         sc->inst_obj_box, sc->inst_world_box, sc->pad);
-    RTSDF_CHECK_LAUNCH();
-    if (sc->inst_base > 0) {
-        tlas_refit<<<dim3(1), dim3(64), 0, s>>>(sc->nodes, sc->inst_base, sc->inst_base, sc->inst_world_box);
+    const int nmov = sc->ninst - 1;
+    if (nmov > 0) {
+        inst_update<<<dim3((nmov + 63) / 64), dim3(64), 0, s>>>(sc->transforms, nmov, sc->nodes, sc->inst_base,
+                                                                sc->inst_obj_box, sc->inst_world_box, sc->pad);
+        RTSDF_CHECK_LAUNCH();
+        top_refit<<<dim3(1), dim3(256), 0, s>>>(sc->nodes, sc->top_dirty, sc->top_level_off, sc->top_levels,
+                                                sc->inst_base, nmov, sc->inst_world_box);
         RTSDF_CHECK_LAUNCH();
     }
     if (sc->nv > 0) {
@@ -204,11 +171,12 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
         return RTSDF_EINVAL;
     if (leaf_size <= 0) leaf_size = 4;
     if (leaf_size > kMaxLeaf || (int64_t)nt >= (int64_t)1 << 26 || ninst > (1 << 20)) return RTSDF_EINVAL;
-    if (instance_faces[0] != 0 || instance_faces[ninst] != nt) return RTSDF_EINVAL;
-    for (int i = 0; i < ninst; ++i)
-        if (instance_faces[i + 1] <= instance_faces[i]) return RTSDF_EINVAL;  // every part has a face
+    if (instance_faces[0] != 0 || instance_faces[ninst] != nt || instance_faces[1] < 0) return RTSDF_EINVAL;
+    for (int i = 1; i < ninst; ++i)
+        if (instance_faces[i + 1] <= instance_faces[i]) return RTSDF_EINVAL;  // every moving part has a face
     *out = nullptr;
     hipStream_t s = as_stream(stream);
+    const int nmov = ninst - 1;
     std::vector<float> hv((size_t)3 * nv), hT((size_t)12 * ninst);
     std::vector<int32_t> hf((size_t)3 * nt);
     RTSDF_TRY(hipMemcpyAsync(hv.data(), vertices, sizeof(float) * hv.size(), hipMemcpyDeviceToHost, s));
@@ -230,7 +198,7 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
         obj_scale = std::max(obj_scale, std::fabs(x));
     }
     float scale = obj_scale;  // bounds world coordinates: |R p + t| <= |p| + |t|
-    for (int i = 0; i < ninst; ++i) {
+    for (int i = 1; i < ninst; ++i) {
         for (int k = 0; k < 12; ++k)
             if (!std::isfinite(hT[12 * i + k])) return RTSDF_EINVAL;
         if (!rigid_ok(&hT[12 * i])) return RTSDF_EINVAL;
@@ -238,16 +206,26 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
     }
     const float pad = std::ldexp(scale, -17);
 
-    // each part's own hierarchy, in object space
+    // each moving part's own hierarchy, in object space
     struct Part {
         std::vector<BvhNode> nodes;
         std::vector<int32_t> ref_face, ref_path;  // leaf order, global face index
         int depth = 0, max_leaf = 0;
         Aabb box;
     };
-    std::vector<Part> parts(ninst);
-    for (int i = 0; i < ninst; ++i) {
-        const int f0 = instance_faces[i], nti = instance_faces[i + 1] - f0;
+    auto one_leaf_root = [&](HostBuilder &B, int code, int nitems) {  // a root holding one child and an empty leaf
+        B.nodes.emplace_back();
+        float lo[3], hi[3];
+        B.padded(B.range_box(0, nitems), lo, hi);
+        BvhNode &nd = B.nodes[0];
+        nd.xy0 = nd.xy1 = make_float4(lo[0], hi[0], lo[1], hi[1]);
+        nd.z01 = make_float4(lo[2], hi[2], lo[2], hi[2]);
+        nd.meta = make_int4(code, leaf_code(0, 0), -1, 0);
+        B.max_depth = std::max(B.max_depth, 1);
+    };
+    std::vector<Part> parts(nmov);
+    for (int k = 0; k < nmov; ++k) {
+        const int f0 = instance_faces[k + 1], nti = instance_faces[k + 2] - f0;
         std::vector<int32_t> sub(hf.begin() + 3 * (size_t)f0, hf.begin() + 3 * (size_t)(f0 + nti));
         HostBuilder B{hv.data(), sub.data(), nti, leaf_size, pad, {}, {}, {}, {}};
         std::vector<int32_t> ref_tri, ref_path;
@@ -260,78 +238,133 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
             B.idx[r] = r;
         }
         const int code = B.build(0, nref, 0);
-        if (code < 0) {  // the whole part is one leaf: a root holding it and an empty leaf
-            B.nodes.emplace_back();
-            float lo[3], hi[3];
-            B.padded(B.range_box(0, nref), lo, hi);
-            BvhNode &nd = B.nodes[0];
-            nd.xy0 = nd.xy1 = make_float4(lo[0], hi[0], lo[1], hi[1]);
-            nd.z01 = make_float4(lo[2], hi[2], lo[2], hi[2]);
-            nd.meta = make_int4(code, leaf_code(0, 0), -1, 0);
-            B.max_depth = 1;
-        }
-        Part &P = parts[i];
+        if (code < 0) one_leaf_root(B, code, nref);
+        Part &P = parts[k];
         P.nodes = std::move(B.nodes);
         P.depth = B.max_depth;
         P.max_leaf = B.max_leaf;
-        for (int k = 0; k < nref; ++k) {
-            P.ref_face.push_back(f0 + ref_tri[B.idx[k]]);
-            P.ref_path.push_back(ref_path[B.idx[k]]);
+        for (int q = 0; q < nref; ++q) {
+            P.ref_face.push_back(f0 + ref_tri[B.idx[q]]);
+            P.ref_path.push_back(ref_path[B.idx[q]]);
         }
         const BvhNode &r0 = P.nodes[0];  // the part's box: both slots of its root
-        P.box.reset();
         const float lo0[3] = {r0.xy0.x, r0.xy0.z, r0.z01.x}, hi0[3] = {r0.xy0.y, r0.xy0.w, r0.z01.y};
         const float lo1[3] = {r0.xy1.x, r0.xy1.z, r0.z01.z}, hi1[3] = {r0.xy1.y, r0.xy1.w, r0.z01.w};
+        P.box.reset();
         P.box.grow_pt(lo0);  // (a one-leaf part repeats its box in both slots)
         P.box.grow_pt(hi0);
         P.box.grow_pt(lo1);
         P.box.grow_pt(hi1);
     }
 
-    // top level over the initial world boxes (refit from the transforms on the device)
-    std::vector<Aabb> wbox(ninst);
-    for (int i = 0; i < ninst; ++i) {
-        const float *m = &hT[12 * i];
-        wbox[i].reset();
+    // the top level: static triangle references and the moving parts' world boxes, one tree
+    const int f_static = instance_faces[1];
+    std::vector<int32_t> sub0(hf.begin(), hf.begin() + 3 * (size_t)f_static);
+    HostBuilder T{hv.data(), sub0.data(), f_static, leaf_size, pad, {}, {}, {}, {}};
+    std::vector<int32_t> ref_tri, ref_path;
+    make_references(hv, sub0, f_static, T.tb, ref_tri, ref_path);
+    const int nsref = (int)ref_tri.size();
+    std::vector<int> item_part(nsref, -1);
+    for (int k = 0; k < nmov; ++k) {
+        const float *m = &hT[12 * (k + 1)];
+        Aabb wb;
+        wb.reset();
         for (int corner = 0; corner < 8; ++corner) {
-            const float p[3] = {(corner & 1) ? parts[i].box.hi[0] : parts[i].box.lo[0],
-                                (corner & 2) ? parts[i].box.hi[1] : parts[i].box.lo[1],
-                                (corner & 4) ? parts[i].box.hi[2] : parts[i].box.lo[2]};
+            const float p[3] = {(corner & 1) ? parts[k].box.hi[0] : parts[k].box.lo[0],
+                                (corner & 2) ? parts[k].box.hi[1] : parts[k].box.lo[1],
+                                (corner & 4) ? parts[k].box.hi[2] : parts[k].box.lo[2]};
             float w[3];
             for (int a = 0; a < 3; ++a) w[a] = m[4 * a] * p[0] + m[4 * a + 1] * p[1] + m[4 * a + 2] * p[2] + m[4 * a + 3];
-            wbox[i].grow_pt(w);
+            wb.grow_pt(w);
         }
+        T.tb.push_back(wb);
+        item_part.push_back(k);
     }
-    const int inst_base = ninst - 1;
-    TopBuilder top{wbox, inst_base, {}, 0};
-    std::vector<int> ids(ninst);
-    for (int i = 0; i < ninst; ++i) ids[i] = i;
-    if (ninst > 1) top.build(ids, 0, ninst, 0);
-
-    // concatenate: top nodes, instance nodes, parts
-    std::vector<BvhNode> nodes(top.nodes);
-    nodes.resize((size_t)inst_base + ninst);
-    std::vector<int> inst_parent(ninst, -1);
-    for (int id = 0; id < inst_base; ++id)
-        for (int c : {nodes[id].meta.x, nodes[id].meta.y})
-            if (c >= inst_base) inst_parent[c - inst_base] = id;
+    const int nitems = (int)T.tb.size();
+    T.cen.resize((size_t)3 * nitems);
+    T.idx.resize(nitems);
+    for (int r = 0; r < nitems; ++r) {
+        for (int a = 0; a < 3; ++a) T.cen[3 * r + a] = 0.5f * (T.tb[r].lo[a] + T.tb[r].hi[a]);
+        T.idx[r] = r;
+    }
+    T.item_part = &item_part;
+    const int tcode = T.build(0, nitems, 0);
+    if (tcode < 0 || tcode >= HostBuilder::kInstItem) one_leaf_root(T, tcode, nitems);
+    const int ntop = (int)T.nodes.size(), inst_base = ntop;
+    std::vector<BvhNode> nodes(T.nodes);
+    std::vector<int> inst_parent(nmov, -1);
+    for (int id = 0; id < ntop; ++id) {
+        int *ch[2] = {&nodes[id].meta.x, &nodes[id].meta.y};
+        for (int *c : ch)
+            if (*c >= HostBuilder::kInstItem) {
+                inst_parent[*c - HostBuilder::kInstItem] = id;
+                *c = inst_base + (*c - HostBuilder::kInstItem);
+            }
+    }
+    // top-level records in item order; the positions of moving parts hold no triangle (no leaf points there)
     std::vector<float4> htri;
     std::vector<int4> hlf;
-    int max_depth = 0, max_leaf = 0;
-    for (int i = 0; i < ninst; ++i) {
+    for (int q = 0; q < nitems; ++q) {
+        const int item = T.idx[q];
+        if (item >= nsref) {
+            const int none = -1;
+            float w = 0.f;
+            std::memcpy(&w, &none, sizeof(float));
+            htri.push_back(make_float4(0.f, 0.f, 0.f, w));
+            htri.push_back(make_float4(0.f, 0.f, 0.f, 0.f));
+            htri.push_back(make_float4(0.f, 0.f, 0.f, 0.f));
+            hlf.push_back(make_int4(0, 0, 0, -1));
+            continue;
+        }
+        const int t = ref_tri[item], path = ref_path[item];
+        for (int c = 0; c < 3; ++c) {
+            const float *p = &hv[3 * hf[3 * t + c]];
+            float w = 0.f;
+            if (c == 0) std::memcpy(&w, &t, sizeof(float));
+            if (c == 1) std::memcpy(&w, &path, sizeof(float));
+            htri.push_back(make_float4(p[0], p[1], p[2], w));
+        }
+        hlf.push_back(make_int4(hf[3 * t], hf[3 * t + 1], hf[3 * t + 2], t));
+    }
+    // nodes above moving parts, grouped by depth, deepest first
+    std::vector<int> depth(ntop, 0);
+    for (int id = 0; id < ntop; ++id)  // preorder: a parent comes before its children
+        for (int c : {nodes[id].meta.x, nodes[id].meta.y})
+            if (c >= 0 && c < ntop) depth[c] = depth[id] + 1;
+    std::vector<char> is_dirty(ntop, 0);
+    int max_top = 0;
+    for (int k = 0; k < nmov; ++k) {
+        max_top = std::max(max_top, depth[inst_parent[k]] + 1);
+        for (int id = inst_parent[k]; id >= 0 && !is_dirty[id]; id = nodes[id].meta.z) is_dirty[id] = 1;
+    }
+    std::vector<int32_t> dirty, level_off;
+    int max_d = 0;
+    for (int id = 0; id < ntop; ++id)
+        if (is_dirty[id]) max_d = std::max(max_d, depth[id]);
+    for (int d = max_d; d >= 0; --d) {
+        level_off.push_back((int)dirty.size());
+        for (int id = 0; id < ntop; ++id)
+            if (is_dirty[id] && depth[id] == d) dirty.push_back(id);
+    }
+    level_off.push_back((int)dirty.size());
+    if (dirty.empty()) level_off.assign(1, 0);
+    // instance nodes, then each moving part's hierarchy
+    nodes.resize((size_t)inst_base + nmov);
+    int max_part = 0, max_leaf = T.max_leaf;
+    for (int k = 0; k < nmov; ++k) {
         const int nbase = (int)nodes.size(), rbase = (int)hlf.size();
-        for (const BvhNode &b : parts[i].nodes) {
+        for (const BvhNode &b : parts[k].nodes) {
             BvhNode nd = b;
             int *ch[2] = {&nd.meta.x, &nd.meta.y};
             for (int *c : ch) *c = *c >= 0 ? *c + nbase : leaf_code(leaf_first(*c) + rbase, leaf_count(*c));
             if (nd.meta.z >= 0) nd.meta.z += nbase;
             nodes.push_back(nd);
         }
-        BvhNode &inode = nodes[inst_base + i];
+        BvhNode &inode = nodes[inst_base + k];
         inode.xy0 = inode.xy1 = inode.z01 = make_float4(0.f, 0.f, 0.f, 0.f);  // rows written on the device
-        inode.meta = make_int4(nbase, kInstTag, inst_parent[i], i);
-        for (size_t k = 0; k < parts[i].ref_face.size(); ++k) {
-            const int t = parts[i].ref_face[k], path = parts[i].ref_path[k];
+        inode.meta = make_int4(nbase, kInstTag, inst_parent[k], k + 1);
+        for (size_t q = 0; q < parts[k].ref_face.size(); ++q) {
+            const int t = parts[k].ref_face[q], path = parts[k].ref_path[q];
             for (int c = 0; c < 3; ++c) {
                 const float *p = &hv[3 * hf[3 * t + c]];
                 float w = 0.f;
@@ -341,16 +374,16 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
             }
             hlf.push_back(make_int4(hf[3 * t], hf[3 * t + 1], hf[3 * t + 2], t));
         }
-        max_depth = std::max(max_depth, parts[i].depth);
-        max_leaf = std::max(max_leaf, parts[i].max_leaf);
+        max_part = std::max(max_part, parts[k].depth);
+        max_leaf = std::max(max_leaf, parts[k].max_leaf);
     }
     const int nref = (int)hlf.size();
     if ((int64_t)nref >= ((int64_t)1 << 26) - 1) return RTSDF_EINVAL;
-    std::vector<float> obox((size_t)6 * ninst);
-    for (int i = 0; i < ninst; ++i)
+    std::vector<float> obox((size_t)6 * std::max(nmov, 1));
+    for (int k = 0; k < nmov; ++k)
         for (int a = 0; a < 3; ++a) {
-            obox[6 * i + a] = parts[i].box.lo[a];
-            obox[6 * i + 3 + a] = parts[i].box.hi[a];
+            obox[6 * k + a] = parts[k].box.lo[a];
+            obox[6 * k + 3 + a] = parts[k].box.hi[a];
         }
 
     std::unique_ptr<rtsdf_scene> sc(new rtsdf_scene());
@@ -359,11 +392,12 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
     sc->nref = nref;
     sc->nnodes = (int)nodes.size();
     // stack: pending top-level entries, the return marker, then the part's own entries
-    sc->max_depth = top.depth + 2 + max_depth;
+    sc->max_depth = std::max(T.max_depth, max_top) + 2 + max_part;
     sc->max_leaf = max_leaf;
     sc->pad = pad;
     sc->ninst = ninst;
     sc->inst_base = inst_base;
+    sc->top_levels = (int)level_off.size() - 1;
     RTSDF_TRY(hipGetDevice(&sc->device));
     auto alloc = [&](void **p, size_t bytes) -> bool {
         if (bytes == 0) bytes = 16;
@@ -381,20 +415,26 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
         !alloc((void **)&sc->vert_inst, sizeof(int32_t) * nv) ||
         !alloc((void **)&sc->inst_obj_box, sizeof(float) * obox.size()) ||
         !alloc((void **)&sc->inst_world_box, sizeof(float) * obox.size()) ||
-        !alloc((void **)&sc->transforms, sizeof(float) * hT.size())) {
+        !alloc((void **)&sc->transforms, sizeof(float) * hT.size()) ||
+        !alloc((void **)&sc->top_dirty, sizeof(int32_t) * std::max<size_t>(dirty.size(), 1)) ||
+        !alloc((void **)&sc->top_level_off, sizeof(int32_t) * level_off.size())) {
         rtsdf_scene_destroy(sc.release());
         return RTSDF_ENOMEM;
     }
     bool ok = true;
-    ok &= hipMemcpyAsync(sc->nodes, nodes.data(), sizeof(BvhNode) * nodes.size(), hipMemcpyHostToDevice, s) == hipSuccess;
-    ok &= hipMemcpyAsync(sc->tris, htri.data(), sizeof(float4) * htri.size(), hipMemcpyHostToDevice, s) == hipSuccess;
-    ok &= hipMemcpyAsync(sc->leaf_faces, hlf.data(), sizeof(int4) * hlf.size(), hipMemcpyHostToDevice, s) == hipSuccess;
-    ok &= hipMemcpyAsync(sc->obj_vertices, hv.data(), sizeof(float) * hv.size(), hipMemcpyHostToDevice, s) == hipSuccess;
-    ok &= hipMemcpyAsync(sc->faces, hf.data(), sizeof(int32_t) * hf.size(), hipMemcpyHostToDevice, s) == hipSuccess;
-    ok &= hipMemcpyAsync(sc->vert_inst, vinst.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok &= hipMemcpyAsync(sc->inst_obj_box, obox.data(), sizeof(float) * obox.size(), hipMemcpyHostToDevice, s) ==
-          hipSuccess;
-    ok &= hipMemcpyAsync(sc->transforms, hT.data(), sizeof(float) * hT.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (bytes) ok &= hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+    };
+    up(sc->nodes, nodes.data(), sizeof(BvhNode) * nodes.size());
+    up(sc->tris, htri.data(), sizeof(float4) * htri.size());
+    up(sc->leaf_faces, hlf.data(), sizeof(int4) * hlf.size());
+    up(sc->obj_vertices, hv.data(), sizeof(float) * hv.size());
+    up(sc->faces, hf.data(), sizeof(int32_t) * hf.size());
+    up(sc->vert_inst, vinst.data(), sizeof(int32_t) * nv);
+    up(sc->inst_obj_box, obox.data(), sizeof(float) * obox.size());
+    up(sc->transforms, hT.data(), sizeof(float) * hT.size());
+    up(sc->top_dirty, dirty.data(), sizeof(int32_t) * dirty.size());
+    up(sc->top_level_off, level_off.data(), sizeof(int32_t) * level_off.size());
     if (ok) {
         tri_maps<<<dim3((nref + 255) / 256), dim3(256), 0, s>>>(sc->tris, sc->tmap, nref);
         ok &= hipGetLastError() == hipSuccess;

@@ -89,15 +89,18 @@ struct rtsdf_scene {
     int64_t bytes = 0;
     int sign_policy = RTSDF_SIGN_VOTE;  // how the tracer signs a traced distance
     float shell = 0.f;                  // RTSDF_SIGN_SHELL: half-thickness subtracted from the distance
-    // two-level scenes (rtsdf_scene_create_instanced): nodes = [top-level internal nodes (ninst - 1)]
-    // [instance nodes (ninst)] [each instance's own hierarchy]; `vertices` holds world positions
+    // two-level scenes (rtsdf_scene_create_instanced): nodes = [top level over static triangles and moving
+    // parts] [instance nodes (ninst - 1)] [each moving part's own hierarchy]; `vertices` holds world positions
     int ninst = 0;
-    int inst_base = 0;                 // node index of instance 0's instance node
+    int inst_base = 0;                 // node index of the instance node of part 1 (the first moving part)
     float *obj_vertices = nullptr;     // [3 nv] object-space positions
     int32_t *vert_inst = nullptr;      // [nv] instance of each vertex, -1 for vertices no face uses
-    float *inst_obj_box = nullptr;     // [ninst][6] object-space box of each instance's hierarchy
-    float *inst_world_box = nullptr;   // [ninst][6]
-    float *transforms = nullptr;       // [ninst][12] current object-to-world rows
+    float *inst_obj_box = nullptr;     // [ninst - 1][6] object-space box of each moving part's hierarchy
+    float *inst_world_box = nullptr;   // [ninst - 1][6]
+    float *transforms = nullptr;       // [ninst][12] current object-to-world rows (row 0, the static world, unused)
+    int32_t *top_dirty = nullptr;      // top-level nodes above moving parts, deepest level first
+    int32_t *top_level_off = nullptr;  // [top_levels + 1] offsets of the levels in top_dirty
+    int top_levels = 0;
 };
 
 namespace rtsdf {
@@ -171,6 +174,23 @@ struct HostBuilder {
     std::vector<int> idx;
     std::vector<BvhNode> nodes;
     int max_depth = 0, max_leaf = 0;
+    // two-level scenes: the top level mixes triangle references with moving parts; item_part[item] is the
+    // moving part's index (-1 for a triangle reference) and such an item becomes the child code
+    // kInstItem + index, remapped to its instance node once the node count is known
+    const std::vector<int> *item_part = nullptr;
+    static constexpr int kInstItem = 1 << 30;
+
+    int movers_in(int b, int e, int &one) const
+    {
+        if (!item_part) return 0;
+        int n = 0;
+        for (int i = b; i < e; ++i)
+            if ((*item_part)[idx[i]] >= 0) {
+                ++n;
+                one = (*item_part)[idx[i]];
+            }
+        return n;
+    }
 
     Aabb range_box(int b, int e) const
     {
@@ -192,7 +212,14 @@ struct HostBuilder {
     int build(int b, int e, int depth)
     {
         const int count = e - b;
-        if (count <= leaf_size || depth >= kMaxBuildDepth + 14) {
+        int one = -1;
+        const int movers = movers_in(b, e, one);
+        if (movers > 0) {  // a moving part is a child of its own; leaves hold triangle references only
+            if (count == 1) {
+                max_depth = std::max(max_depth, depth);
+                return kInstItem + one;
+            }
+        } else if (count <= leaf_size || depth >= kMaxBuildDepth + 14) {
             if (count > kMaxLeaf) {  // cannot happen unless the depth cap bites; split by index
                 return build_split(b, e, b + count / 2, depth);
             }
@@ -258,7 +285,7 @@ struct HostBuilder {
         if (best_axis < 0) return build_split(b, e, b + count / 2, depth);
         const Aabb box = range_box(b, e);
         const double leaf_cost = box.area() * count;
-        if (count <= 2 * leaf_size && best_cost + box.area() >= leaf_cost) {
+        if (movers == 0 && count <= 2 * leaf_size && best_cost + box.area() >= leaf_cost) {
             max_depth = std::max(max_depth, depth);
             max_leaf = std::max(max_leaf, count);
             return leaf_code(b, count);
@@ -289,8 +316,8 @@ struct HostBuilder {
         nd.xy1 = make_float4(lo1[0], hi1[0], lo1[1], hi1[1]);
         nd.z01 = make_float4(lo0[2], hi0[2], lo1[2], hi1[2]);
         nd.meta = make_int4(c0, c1, -1, 0);
-        if (c0 >= 0) nodes[c0].meta.z = id;
-        if (c1 >= 0) nodes[c1].meta.z = id;
+        if (c0 >= 0 && c0 < kInstItem) nodes[c0].meta.z = id;
+        if (c1 >= 0 && c1 < kInstItem) nodes[c1].meta.z = id;
         return id;
     }
 };
@@ -688,6 +715,8 @@ extern "C" void rtsdf_scene_destroy(rtsdf_scene *scene)
     (void)hipFree(scene->inst_obj_box);
     (void)hipFree(scene->inst_world_box);
     (void)hipFree(scene->transforms);
+    (void)hipFree(scene->top_dirty);
+    (void)hipFree(scene->top_level_off);
     (void)hipFree(scene->nodes);
     (void)hipFree(scene->tris);
     (void)hipFree(scene->tmap);

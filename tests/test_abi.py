@@ -103,10 +103,11 @@ def test_host_validation(R):
     assert L.rtsdf_scene_set_sign(None, 0, 0.0) == R.EINVAL
     offs = (C.c_int32 * 3)(0, 1, 2)
     h = C.c_void_p()
-    # host checks of a two-level scene: no parts, offsets not ending at nt, an empty part
+    # host checks of a two-level scene: no parts, offsets not ending at nt, an empty moving part (all rejected
+    # before any device access)
     assert L.rtsdf_scene_create_instanced(dummy, 3, dummy, 2, offs, 0, dummy, 2, C.byref(h), None) == R.EINVAL
     assert L.rtsdf_scene_create_instanced(dummy, 3, dummy, 3, offs, 2, dummy, 2, C.byref(h), None) == R.EINVAL
-    bad = (C.c_int32 * 3)(0, 0, 2)
+    bad = (C.c_int32 * 3)(0, 2, 2)  # the moving part 1 has no face
     assert L.rtsdf_scene_create_instanced(dummy, 3, dummy, 2, bad, 2, dummy, 2, C.byref(h), None) == R.EINVAL
     assert L.rtsdf_scene_set_transforms(None, dummy, None, None) == R.EINVAL
     default = R.rtsdf_trace_config_get().as_dict()

@@ -147,3 +147,29 @@ def test_parts_bad_input(R):
     with pytest.raises(R.RtsdfError):
         sc.refit(cu(v))
     sc.close()
+
+
+def test_parts_without_static_world_and_without_movers(R):
+    """Part 0 may be empty (every part moves), and a scene may have no moving part (static world only): both
+    trace as the oracle on the world mesh."""
+    say("parts edge layouts")
+    from paper_2210_04449_amd.pipeline import Pipeline
+    v, f, offs, T = rigid_parts()
+    nc, nf, rays, frames = 32, 64, 4, 2
+    beta, d = np.float32(0.5 / nc), np.float32(2.0 / nc)
+    # drop the ground quad: parts = [empty static world, sphere, torus]
+    keep = f[offs[1]:]
+    used = np.unique(keep)
+    remap = np.full(len(v), -1, np.int64)
+    remap[used] = np.arange(len(used))
+    v2, f2 = v[used], remap[keep].astype(np.int32)
+    offs2 = [0, 0, offs[2] - offs[1], len(f2)]
+    for verts, faces, o, tr in ((v2, f2, offs2, T), (v[:4], f[:2], [0, 2], T[:1])):
+        p = Pipeline(cu(verts), cu(faces), nc, nf, float(beta), float(d), rays, scene_id=5, parts=(o, cu(tr)))
+        for fr in range(frames):
+            p.step(fr)
+        torch.cuda.synchronize()
+        w = oracle.instance_world(verts, part_of_vertex(len(verts), faces, o), tr)
+        ref = oracle.run_frames(w, faces, nc, nf, beta, d, rays, range(frames), scene=5)
+        print(len(o) - 1, "parts:", compare(p, ref))
+        p.close()
