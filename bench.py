@@ -252,7 +252,8 @@ def main():
     # HBM bytes per trace launch from the committed PMC summary of this workload, when it was taken on the
     # current kernel sources (else null)
     from paper_2210_04449_amd.prof_summary import traffic_from_summary
-    tname = f"trace_persistent<{tuning['stack_lds']},{tuning['refill']},{tuning['loop']},false,false>"
+    inst = "true" if use_parts else "false"
+    tname = f"trace_persistent<{tuning['stack_lds']},{tuning['refill']},{tuning['loop']},false,false,{inst}>"
     tr = traffic_from_summary(os.path.join(ROOT, "profiles", f"pmc_{w.name}_{w.nc}_{w.nf}.txt"), tname)
     traffic = None if tr is None else int(tr["fetch_bytes"] + tr["write_bytes"])
 
