@@ -7,14 +7,15 @@
 // parts 1.. move rigidly: each moving part's hierarchy is built once in its
 // object space and stays tight, and the top level is one surface-area-
 // heuristic tree over the static triangles (references, as in a single-level
-// scene) and the moving parts' world boxes, each moving part a child of its
-// own.  Per frame only the moving parts' boxes change: the nodes above them
-// are refit level by level, deepest first.
+// scene) and *entries*: a moving part enters as kCutEntries subtrees of its
+// own hierarchy (its cut opened largest box first, the re-braiding idea of
+// Benthin et al. 2017), each a child of its own.  Per frame only the entries'
+// boxes change: the nodes above them are refit level by level, deepest first.
 //
-// Node array: [top level] [instance nodes (one per moving part)] [hierarchy of
+// Node array: [top level] [instance nodes (one per entry)] [hierarchy of
 // moving part 1] [part 2] ...  An instance node carries the rows of its
-// world-to-object transform in the three box slots and (root of the part's
-// hierarchy, kInstTag) as its children: the tracer that reaches it moves its
+// part's world-to-object transform in the three box slots and (root of the
+// entry's subtree, kInstTag) as its children: the tracer that reaches it moves its
 // ray into object space, pushes kReturn and descends; reaching kReturn, once
 // the part's last leaf is tested, brings the ray back to world space.  The
 // transforms are rigid (rotation and translation), so the ray parameter t,
@@ -35,6 +36,10 @@
 namespace rtsdf {
 
 constexpr float kRigidTol = 1e-4f;  // |R R^T - I| entries and |det R - 1| accepted as rigid
+// subtrees per moving part in the top level.  One: with rotating parts, opened pieces sweep the part's whole
+// sphere and loosen the top level over time (8 pieces: 6 % faster on the first frame of the moving-scene
+// workload, 44 % slower after 48 frames of motion)
+constexpr int kCutEntries = 1;
 
 __host__ __device__ inline bool rigid_ok(const float *m)
 {
@@ -49,14 +54,15 @@ __host__ __device__ inline bool rigid_ok(const float *m)
     return err <= kRigidTol && fabsf(det - 1.0f) <= kRigidTol;
 }
 
-// moving part k (part k + 1): world-to-object rows into its instance node, world box of its hierarchy
-__global__ void inst_update(const float *__restrict__ T, int nmov, BvhNode *nodes, int inst_base,
-                            const float *__restrict__ obj_box, float *__restrict__ world_box, float pad)
+// entry k (a subtree of moving part part[k]): world-to-object rows into its instance node, its world box
+__global__ void inst_update(const float *__restrict__ T, const int32_t *__restrict__ part, int nent, BvhNode *nodes,
+                            int inst_base, const float *__restrict__ obj_box, float *__restrict__ world_box,
+                            float pad)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nmov) return;
+    if (k >= nent) return;
     float m[12];
-    for (int q = 0; q < 12; ++q) m[q] = T[12 * (k + 1) + q];
+    for (int q = 0; q < 12; ++q) m[q] = T[12 * part[k] + q];
     if (!rigid_ok(m)) raise_error(RTSDF_ERR_TRANSFORM);
     float inv[12];
     for (int r = 0; r < 3; ++r) {
@@ -88,7 +94,7 @@ __global__ void inst_update(const float *__restrict__ T, int nmov, BvhNode *node
 // child is a leaf of static triangles keeps its box
 __global__ void __launch_bounds__(256) top_refit(BvhNode *nodes, const int32_t *__restrict__ dirty,
                                                  const int32_t *__restrict__ level_off, int nlevels, int inst_base,
-                                                 int nmov, const float *__restrict__ world_box)
+                                                 int nent, const float *__restrict__ world_box)
 {
     for (int L = 0; L < nlevels; ++L) {
         for (int k = level_off[L] + (int)threadIdx.x; k < level_off[L + 1]; k += blockDim.x) {
@@ -97,7 +103,7 @@ __global__ void __launch_bounds__(256) top_refit(BvhNode *nodes, const int32_t *
             for (int s = 0; s < 2; ++s) {
                 if (c[s] < 0) continue;
                 float lo[3], hi[3];
-                if (c[s] >= inst_base && c[s] < inst_base + nmov) {
+                if (c[s] >= inst_base && c[s] < inst_base + nent) {
                     const float *b = world_box + 6 * (c[s] - inst_base);
                     for (int a = 0; a < 3; ++a) {
                         lo[a] = b[a];
@@ -142,13 +148,14 @@ __global__ void inst_world_vertices(const float *__restrict__ obj, const int32_t
 
 static int launch_transforms(rtsdf_scene *sc, float *world_out, hipStream_t s)
 {
-    const int nmov = sc->ninst - 1;
-    if (nmov > 0) {
-        inst_update<<<dim3((nmov + 63) / 64), dim3(64), 0, s>>>(sc->transforms, nmov, sc->nodes, sc->inst_base,
-                                                                sc->inst_obj_box, sc->inst_world_box, sc->pad);
+    const int nent = sc->nentries;
+    if (nent > 0) {
+        inst_update<<<dim3((nent + 63) / 64), dim3(64), 0, s>>>(sc->transforms, sc->entry_part, nent, sc->nodes,
+                                                                sc->inst_base, sc->inst_obj_box, sc->inst_world_box,
+                                                                sc->pad);
         RTSDF_CHECK_LAUNCH();
         top_refit<<<dim3(1), dim3(256), 0, s>>>(sc->nodes, sc->top_dirty, sc->top_level_off, sc->top_levels,
-                                                sc->inst_base, nmov, sc->inst_world_box);
+                                                sc->inst_base, nent, sc->inst_world_box);
         RTSDF_CHECK_LAUNCH();
     }
     if (sc->nv > 0) {
@@ -257,7 +264,49 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
         P.box.grow_pt(hi1);
     }
 
-    // the top level: static triangle references and the moving parts' world boxes, one tree
+    // entries: each moving part enters the top level as a few subtrees of its own hierarchy, the cut opened
+    // largest object-space box first (re-braiding, after Benthin et al. 2017), so the top level can separate
+    // a large part's pieces instead of testing one loose box around all of it
+    struct Entry {
+        int part;  // moving part index k (part k + 1)
+        int code;  // subtree root in the part's own numbering: node index or leaf code
+        Aabb box;  // object space
+    };
+    std::vector<Entry> entries;
+    auto slot_box = [](const BvhNode &nd, int s) {
+        Aabb b;
+        b.reset();
+        const float lo[3] = {s ? nd.xy1.x : nd.xy0.x, s ? nd.xy1.z : nd.xy0.z, s ? nd.z01.z : nd.z01.x};
+        const float hi[3] = {s ? nd.xy1.y : nd.xy0.y, s ? nd.xy1.w : nd.xy0.w, s ? nd.z01.w : nd.z01.y};
+        b.grow_pt(lo);
+        b.grow_pt(hi);
+        return b;
+    };
+    for (int k = 0; k < nmov; ++k) {
+        std::vector<Entry> cut;
+        auto add_children = [&](int node) {
+            const BvhNode &nd = parts[k].nodes[node];
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const int c = s2 ? nd.meta.y : nd.meta.x;
+                if (c < 0 && leaf_count(c) == 0) continue;  // the empty leaf of a one-leaf part
+                cut.push_back(Entry{k, c, slot_box(nd, s2)});
+            }
+        };
+        cut.push_back(Entry{k, 0, parts[k].box});  // the whole part, then opened while the budget allows
+        while ((int)cut.size() < kCutEntries) {
+            int best = -1;
+            for (int q = 0; q < (int)cut.size(); ++q)
+                if (cut[q].code >= 0 && (best < 0 || cut[q].box.area() > cut[best].box.area())) best = q;
+            if (best < 0) break;
+            const int node = cut[best].code;
+            cut.erase(cut.begin() + best);
+            add_children(node);
+        }
+        entries.insert(entries.end(), cut.begin(), cut.end());
+    }
+    const int nent = (int)entries.size();
+
+    // the top level: static triangle references and the entries' world boxes, one tree
     const int f_static = instance_faces[1];
     std::vector<int32_t> sub0(hf.begin(), hf.begin() + 3 * (size_t)f_static);
     HostBuilder T{hv.data(), sub0.data(), f_static, leaf_size, pad, {}, {}, {}, {}};
@@ -265,20 +314,20 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
     make_references(hv, sub0, f_static, T.tb, ref_tri, ref_path);
     const int nsref = (int)ref_tri.size();
     std::vector<int> item_part(nsref, -1);
-    for (int k = 0; k < nmov; ++k) {
-        const float *m = &hT[12 * (k + 1)];
+    for (int e = 0; e < nent; ++e) {
+        const float *m = &hT[12 * (entries[e].part + 1)];
+        const Aabb &ob = entries[e].box;
         Aabb wb;
         wb.reset();
         for (int corner = 0; corner < 8; ++corner) {
-            const float p[3] = {(corner & 1) ? parts[k].box.hi[0] : parts[k].box.lo[0],
-                                (corner & 2) ? parts[k].box.hi[1] : parts[k].box.lo[1],
-                                (corner & 4) ? parts[k].box.hi[2] : parts[k].box.lo[2]};
+            const float p[3] = {(corner & 1) ? ob.hi[0] : ob.lo[0], (corner & 2) ? ob.hi[1] : ob.lo[1],
+                                (corner & 4) ? ob.hi[2] : ob.lo[2]};
             float w[3];
             for (int a = 0; a < 3; ++a) w[a] = m[4 * a] * p[0] + m[4 * a + 1] * p[1] + m[4 * a + 2] * p[2] + m[4 * a + 3];
             wb.grow_pt(w);
         }
         T.tb.push_back(wb);
-        item_part.push_back(k);
+        item_part.push_back(e);
     }
     const int nitems = (int)T.tb.size();
     T.cen.resize((size_t)3 * nitems);
@@ -292,7 +341,7 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
     if (tcode < 0 || tcode >= HostBuilder::kInstItem) one_leaf_root(T, tcode, nitems);
     const int ntop = (int)T.nodes.size(), inst_base = ntop;
     std::vector<BvhNode> nodes(T.nodes);
-    std::vector<int> inst_parent(nmov, -1);
+    std::vector<int> inst_parent(nent, -1);
     for (int id = 0; id < ntop; ++id) {
         int *ch[2] = {&nodes[id].meta.x, &nodes[id].meta.y};
         for (int *c : ch)
@@ -333,9 +382,9 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
             if (c >= 0 && c < ntop) depth[c] = depth[id] + 1;
     std::vector<char> is_dirty(ntop, 0);
     int max_top = 0;
-    for (int k = 0; k < nmov; ++k) {
-        max_top = std::max(max_top, depth[inst_parent[k]] + 1);
-        for (int id = inst_parent[k]; id >= 0 && !is_dirty[id]; id = nodes[id].meta.z) is_dirty[id] = 1;
+    for (int e = 0; e < nent; ++e) {
+        max_top = std::max(max_top, depth[inst_parent[e]] + 1);
+        for (int id = inst_parent[e]; id >= 0 && !is_dirty[id]; id = nodes[id].meta.z) is_dirty[id] = 1;
     }
     std::vector<int32_t> dirty, level_off;
     int max_d = 0;
@@ -348,11 +397,14 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
     }
     level_off.push_back((int)dirty.size());
     if (dirty.empty()) level_off.assign(1, 0);
-    // instance nodes, then each moving part's hierarchy
-    nodes.resize((size_t)inst_base + nmov);
+    // instance nodes (one per entry), then each moving part's hierarchy
+    nodes.resize((size_t)inst_base + nent);
     int max_part = 0, max_leaf = T.max_leaf;
+    std::vector<int> part_nbase(nmov), part_rbase(nmov);
     for (int k = 0; k < nmov; ++k) {
         const int nbase = (int)nodes.size(), rbase = (int)hlf.size();
+        part_nbase[k] = nbase;
+        part_rbase[k] = rbase;
         for (const BvhNode &b : parts[k].nodes) {
             BvhNode nd = b;
             int *ch[2] = {&nd.meta.x, &nd.meta.y};
@@ -360,9 +412,6 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
             if (nd.meta.z >= 0) nd.meta.z += nbase;
             nodes.push_back(nd);
         }
-        BvhNode &inode = nodes[inst_base + k];
-        inode.xy0 = inode.xy1 = inode.z01 = make_float4(0.f, 0.f, 0.f, 0.f);  // rows written on the device
-        inode.meta = make_int4(nbase, kInstTag, inst_parent[k], k + 1);
         for (size_t q = 0; q < parts[k].ref_face.size(); ++q) {
             const int t = parts[k].ref_face[q], path = parts[k].ref_path[q];
             for (int c = 0; c < 3; ++c) {
@@ -377,14 +426,26 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
         max_part = std::max(max_part, parts[k].depth);
         max_leaf = std::max(max_leaf, parts[k].max_leaf);
     }
+    for (int e = 0; e < nent; ++e) {
+        const Entry &E = entries[e];
+        const int k = E.part;
+        const int root = E.code >= 0 ? E.code + part_nbase[k]
+                                     : leaf_code(leaf_first(E.code) + part_rbase[k], leaf_count(E.code));
+        BvhNode &inode = nodes[inst_base + e];
+        inode.xy0 = inode.xy1 = inode.z01 = make_float4(0.f, 0.f, 0.f, 0.f);  // rows written on the device
+        inode.meta = make_int4(root, kInstTag, inst_parent[e], k + 1);
+    }
     const int nref = (int)hlf.size();
     if ((int64_t)nref >= ((int64_t)1 << 26) - 1) return RTSDF_EINVAL;
-    std::vector<float> obox((size_t)6 * std::max(nmov, 1));
-    for (int k = 0; k < nmov; ++k)
+    std::vector<float> obox((size_t)6 * std::max(nent, 1));
+    std::vector<int32_t> epart(std::max(nent, 1), 0);
+    for (int e = 0; e < nent; ++e) {
+        epart[e] = entries[e].part + 1;
         for (int a = 0; a < 3; ++a) {
-            obox[6 * k + a] = parts[k].box.lo[a];
-            obox[6 * k + 3 + a] = parts[k].box.hi[a];
+            obox[6 * e + a] = entries[e].box.lo[a];
+            obox[6 * e + 3 + a] = entries[e].box.hi[a];
         }
+    }
 
     std::unique_ptr<rtsdf_scene> sc(new rtsdf_scene());
     sc->nv = nv;
@@ -398,6 +459,7 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
     sc->ninst = ninst;
     sc->inst_base = inst_base;
     sc->top_levels = (int)level_off.size() - 1;
+    sc->nentries = nent;
     RTSDF_TRY(hipGetDevice(&sc->device));
     auto alloc = [&](void **p, size_t bytes) -> bool {
         if (bytes == 0) bytes = 16;
@@ -417,7 +479,8 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
         !alloc((void **)&sc->inst_world_box, sizeof(float) * obox.size()) ||
         !alloc((void **)&sc->transforms, sizeof(float) * hT.size()) ||
         !alloc((void **)&sc->top_dirty, sizeof(int32_t) * std::max<size_t>(dirty.size(), 1)) ||
-        !alloc((void **)&sc->top_level_off, sizeof(int32_t) * level_off.size())) {
+        !alloc((void **)&sc->top_level_off, sizeof(int32_t) * level_off.size()) ||
+        !alloc((void **)&sc->entry_part, sizeof(int32_t) * epart.size())) {
         rtsdf_scene_destroy(sc.release());
         return RTSDF_ENOMEM;
     }
@@ -435,6 +498,7 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
     up(sc->transforms, hT.data(), sizeof(float) * hT.size());
     up(sc->top_dirty, dirty.data(), sizeof(int32_t) * dirty.size());
     up(sc->top_level_off, level_off.data(), sizeof(int32_t) * level_off.size());
+    up(sc->entry_part, epart.data(), sizeof(int32_t) * epart.size());
     if (ok) {
         tri_maps<<<dim3((nref + 255) / 256), dim3(256), 0, s>>>(sc->tris, sc->tmap, nref);
         ok &= hipGetLastError() == hipSuccess;

@@ -92,15 +92,17 @@ struct rtsdf_scene {
     // two-level scenes (rtsdf_scene_create_instanced): nodes = [top level over static triangles and moving
     // parts] [instance nodes (ninst - 1)] [each moving part's own hierarchy]; `vertices` holds world positions
     int ninst = 0;
-    int inst_base = 0;                 // node index of the instance node of part 1 (the first moving part)
+    int inst_base = 0;                 // node index of the first instance node
     float *obj_vertices = nullptr;     // [3 nv] object-space positions
     int32_t *vert_inst = nullptr;      // [nv] instance of each vertex, -1 for vertices no face uses
-    float *inst_obj_box = nullptr;     // [ninst - 1][6] object-space box of each moving part's hierarchy
-    float *inst_world_box = nullptr;   // [ninst - 1][6]
+    float *inst_obj_box = nullptr;     // [nentries][6] object-space box of each entry (a subtree of a moving part)
+    float *inst_world_box = nullptr;   // [nentries][6]
     float *transforms = nullptr;       // [ninst][12] current object-to-world rows (row 0, the static world, unused)
     int32_t *top_dirty = nullptr;      // top-level nodes above moving parts, deepest level first
     int32_t *top_level_off = nullptr;  // [top_levels + 1] offsets of the levels in top_dirty
     int top_levels = 0;
+    int nentries = 0;                  // subtrees of moving parts that the top level holds
+    int32_t *entry_part = nullptr;     // [nentries] part of each (1..ninst-1)
 };
 
 namespace rtsdf {
@@ -717,6 +719,7 @@ extern "C" void rtsdf_scene_destroy(rtsdf_scene *scene)
     (void)hipFree(scene->transforms);
     (void)hipFree(scene->top_dirty);
     (void)hipFree(scene->top_level_off);
+    (void)hipFree(scene->entry_part);
     (void)hipFree(scene->nodes);
     (void)hipFree(scene->tris);
     (void)hipFree(scene->tmap);
