@@ -222,7 +222,7 @@ def main():
     R.rtsdf_trace_config(**{**tuning, "stats": 1})
     p.trace(args.warmup + K)
     torch.cuda.synchronize()
-    ctr = p.trace_ws[8:64].view(torch.int64).cpu().tolist()
+    ctr = p.trace_ws[8:72].view(torch.int64).cpu().tolist()
     R.rtsdf_trace_config(**tuning)
     nodes_per_ray = ctr[0] / max(ctr[2], 1)
     tris_per_ray = ctr[1] / max(ctr[2], 1)
@@ -297,6 +297,7 @@ def main():
         "trace_stats": {"nodes_per_ray": round(nodes_per_ray, 2), "tris_per_ray": round(tris_per_ray, 2),
                         "rays_counted": ctr[2], "wave_iterations": ctr[3] // 64, "refill_rounds": ctr[4] // 64,
                         "tiles": ctr[6] // 64,
+                        "empty_node_fraction": round(ctr[7] / max(ctr[0], 1), 4) if tuning["loop"] == 3 else None,
                         "lane_work_fraction": round(ctr[5] / max(ctr[3], 1), 4) if tuning["loop"] >= 1 else None,
                         "bvh_nodes": info.nodes, "bvh_references": info.references, "bvh_max_depth": info.max_depth,
                         "bvh_max_leaf": info.leaf_size, "leaf_size": args.leaf_size},

@@ -340,7 +340,8 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
  *   stats           1: count into 64-bit counters at byte offsets 8, 16, ...
  *                   of the workspace: node visits, triangle tests, rays,
  *                   traversal iterations x 64, refill rounds x 64, lane
- *                   iterations with work (loop >= 1), tiles x 64
+ *                   iterations with work (loop >= 1), tiles x 64, node
+ *                   visits entering neither child box (loop 3)
  *                   (slower; for measurement only);
  *   loop            0: two phases per iteration (walk nodes until every lane
  *                   holds a leaf, then test the leaves); 1: one unit of work

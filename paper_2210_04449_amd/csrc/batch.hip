@@ -213,7 +213,7 @@ struct rtsdf_batch {
     uint32_t *sel_sums = nullptr;
     int32_t *counts = nullptr;
     int32_t *tile_offset = nullptr;
-    int32_t *cursor = nullptr;  // 16 words: cursor + instrumentation counters (64-bit, from word 2)
+    int32_t *cursor = nullptr;  // 32 words: cursor + instrumentation counters (64-bit, from word 2)
     float4 *dirs = nullptr;     // the tracer's per-wavefront direction buffers
     int32_t *spill = nullptr;   // the deepest scene's spill area
     // tables
@@ -315,7 +315,7 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
         !batch_alloc(B, &B->u, F) || !batch_alloc(B, &B->hits, F) || !batch_alloc(B, &B->arg_tri, F) ||
         !batch_alloc(B, &B->arg_ray, F) || !batch_alloc(B, &B->fine_sdf, F) ||
         !batch_alloc(B, &B->sel_sums, sel_off[n]) || !batch_alloc(B, &B->counts, n) ||
-        !batch_alloc(B, &B->tile_offset, n + 1) || !batch_alloc(B, &B->cursor, 16) ||
+        !batch_alloc(B, &B->tile_offset, n + 1) || !batch_alloc(B, &B->cursor, 32) ||
         !batch_alloc(B, &B->dirs, (int64_t)(dirs_bytes() / sizeof(float4))) || !batch_alloc(B, &B->vox, n) ||
         !batch_alloc(B, &B->plan, (int64_t)(B->max_passes + 1) * n) || !batch_alloc(B, &B->sel, n) ||
         !batch_alloc(B, &B->fill, n) || !batch_alloc(B, &B->trace, n))
@@ -511,7 +511,7 @@ extern "C" int rtsdf_batch_step(rtsdf_batch *B, uint32_t frame, const uint32_t *
     RTSDF_CHECK_LAUNCH();
     trace_tile_prefix<<<dim3(1), dim3(64), 0, s>>>(B->trace, n, B->tile_offset);
     RTSDF_CHECK_LAUNCH();
-    rc = launch_fill<int32_t>(B->cursor, 0, g_tuning.stats ? 16 : 1, s);
+    rc = launch_fill<int32_t>(B->cursor, 0, g_tuning.stats ? 32 : 1, s);
     if (rc != RTSDF_OK) return rc;
     TraceArgs A{};
     A.scenes = B->trace;

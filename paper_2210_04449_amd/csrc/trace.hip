@@ -523,12 +523,14 @@ __global__ void trace_tile_prefix(const TraceScene *scenes, int n, int32_t *tile
 // index is mapped to its scene through the tile prefix.  Instrumented runs
 // (STATS) also count into 64-bit counters at workspace offsets 8, 16, ...:
 // node visits, triangle tests, rays, traversal-loop iterations x 64, refill
-// rounds x 64, lane-iterations with work (LOOP 1 and 2), tiles x 64.
+// rounds x 64, lane-iterations with work (LOOP 1 and 2), tiles x 64, node
+// visits that entered neither child box (LOOP 3).
 template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED, bool INST = false>
 __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_waves_per_eu(6, 8)))
 trace_persistent(TraceArgs A)
 {
     uint32_t st_nodes = 0, st_tris = 0, st_rays = 0, st_iters = 0, st_refills = 0, st_busy = 0, st_tiles = 0;
+    uint32_t st_empty = 0;
     __shared__ int stack_mem[kTraceWaves * SL * kWave];
     __shared__ WaveTile tiles[kTraceWaves];
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -731,6 +733,7 @@ trace_persistent(TraceArgs A)
                         } else {
                             const int4 m = make_int4(w3.x, w3.y, 0, 0);
                             node_step_regs(Rs, w0, w1, w2, m, node, tbest, tri_cur, tri_end, push, push_val, pop);
+                            if (STATS) st_empty += pop && tri_cur >= tri_end;  // neither child box was entered
                         }
                     } else if (INST && busy && node == kReturn) {
                         // the part is done (its last leaf's triangles too): the world ray again, as drawn
@@ -862,6 +865,7 @@ trace_persistent(TraceArgs A)
         atomicAdd(&ctr[4], (unsigned long long)st_refills);
         atomicAdd(&ctr[5], (unsigned long long)st_busy);
         atomicAdd(&ctr[6], (unsigned long long)st_tiles);
+        atomicAdd(&ctr[7], (unsigned long long)st_empty);
     }
 }
 
@@ -1155,7 +1159,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
         mask, coarse_sdf, coarse.n, logr, lognf, ntex, st.u, st.hits, st.arg_tri, st.arg_ray, fine_sdf);
     RTSDF_CHECK_LAUNCH();
     int32_t *cursor = static_cast<int32_t *>(workspace);
-    int rc = launch_fill<int32_t>(cursor, 0, g_tuning.stats ? 16 : 1, s);
+    int rc = launch_fill<int32_t>(cursor, 0, g_tuning.stats ? 32 : 1, s);
     if (rc != RTSDF_OK) return rc;
     TraceArgs A{};
     TraceScene &P = A.one;
