@@ -327,7 +327,7 @@ def main():
 
 def time_shadow(R, p, w, stream, npts: int = 1920 * 1080):
     """Soft shadows (Sec. 2.3) from the fine SDF the updates produced, for one 1080p frame of shading points:
-    points drawn (seeded) from the texel centres within one to three fine texels of a surface, a fixed
+    points drawn (seeded) from the texel centres within one to three fine texels of a surface, in texel order, a fixed
     light; cone and triangulated penumbra, jittered starts; occluders searched up to 0.3 of the domain side
     (the room is closed, so an unbounded march from inside would always end on a wall).  Outside the timed
     update."""
@@ -339,7 +339,8 @@ def time_shadow(R, p, w, stream, npts: int = 1920 * 1080):
     if near.numel() == 0:
         return None
     g = torch.Generator(device=f.device).manual_seed(1)
-    pick = near[torch.randint(0, near.numel(), (npts,), device=f.device, generator=g)]
+    # in texel order, as a frame's shading points are coherent in screen space and hence in space
+    pick = near[torch.randint(0, near.numel(), (npts,), device=f.device, generator=g)].sort().values
     nf = w.nf
     ijk = torch.stack([pick % nf, (pick // nf) % nf, pick // (nf * nf)], 1).to(torch.float32)
     pts = ((ijk + 0.5) * h).contiguous()
