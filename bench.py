@@ -230,8 +230,8 @@ def main():
     achieved = ops / trace_s / 1e12
 
     graph_ms = None
-    if args.graph and not use_parts:  # captured updates move geometry by refitting from vertices
-        g = p.make_graph(first_frame=args.warmup + K + 1, refit=dyn_frames is not None)
+    if args.graph:
+        g = p.make_graph(first_frame=args.warmup + K + 1, refit=dyn_frames is not None or dyn_T is not None)
         g.launch()  # warm-up replay
         torch.cuda.synchronize()
         gs, ge = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -240,6 +240,8 @@ def main():
         for i in range(reps):
             if dyn_frames is not None:  # the graph refits from the vertex buffer
                 p.vertices.copy_(dyn_frames[i % len(dyn_frames)])
+            if dyn_T is not None:  # the graph applies the transform buffer
+                p.transforms.copy_(dyn_T[i % len(dyn_T)])
             g.launch()
         ge.record(stream)
         torch.cuda.synchronize()

@@ -426,6 +426,10 @@ typedef struct rtsdf_frame_desc {
     const int32_t *jfa_steps;         /* HOST, read during create only.  NULL: n/2, ..., 1; else the pass
                                          schedule of rtsdf_jfa_steps (jfa_nsteps entries) */
     int32_t jfa_nsteps;
+    const float *transforms;          /* two-level scene with refit != 0: [ninst][12], read every launch and
+                                         applied with rtsdf_scene_set_transforms, which writes the world
+                                         positions into world_vertices [nv][3]; voxelization then reads those */
+    float *world_vertices;
 } rtsdf_frame_desc;
 
 typedef struct rtsdf_frame_graph rtsdf_frame_graph;

@@ -33,11 +33,16 @@ static int record_frame(const rtsdf_frame_graph &G, hipStream_t s)
     }
     const rtsdf_frame_desc &D = G.desc;
     int rc;
-    if (D.refit) {
+    const float *verts = D.vertices;
+    if (D.refit && D.transforms) {  // a two-level scene moves its parts
+        rc = rtsdf_scene_set_transforms(D.scene, D.transforms, D.world_vertices, s);
+        if (rc != RTSDF_OK) return rc;
+        verts = D.world_vertices;
+    } else if (D.refit) {
         rc = rtsdf_scene_refit(D.scene, D.vertices, s);
         if (rc != RTSDF_OK) return rc;
     }
-    rc = rtsdf_voxelize(D.vertices, D.nv, D.faces, D.nt, D.coarse, D.seeds, s);
+    rc = rtsdf_voxelize(verts, D.nv, D.faces, D.nt, D.coarse, D.seeds, s);
     if (rc != RTSDF_OK) return rc;
     rc = D.jfa_steps ? rtsdf_jfa_steps(D.coarse, D.seeds, D.scratch, D.jfa_steps, D.jfa_nsteps, D.beta, D.dist2,
                                        D.coarse_sdf, s)
@@ -99,6 +104,7 @@ static int capture_graph(rtsdf_frame_graph *g, rtsdf_stream stream)
 extern "C" int rtsdf_frame_graph_create(const rtsdf_frame_desc *desc, rtsdf_frame_graph **out, rtsdf_stream stream)
 {
     if (!desc || !out || !desc->frame_counter || !desc->scene) return RTSDF_EINVAL;
+    if (desc->refit && desc->transforms && !desc->world_vertices) return RTSDF_EINVAL;
     *out = nullptr;
     auto *g = new rtsdf_frame_graph();
     g->desc = *desc;

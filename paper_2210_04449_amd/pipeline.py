@@ -66,8 +66,8 @@ class Pipeline:
             part_faces, transforms = parts
             self.obj_vertices = self.vertices
             self.vertices = torch.empty_like(self.obj_vertices)
-            self.scene = R.Scene.instanced(self.obj_vertices, self.faces, part_faces,
-                                           transforms.to(self.device, torch.float32).contiguous(), leaf_size)
+            self.transforms = transforms.to(self.device, torch.float32).contiguous().clone()  # read by graphs
+            self.scene = R.Scene.instanced(self.obj_vertices, self.faces, part_faces, self.transforms, leaf_size)
             self.scene.world_vertices(self.vertices)
         self.parts = parts is not None
         self.scene.set_sign(sign_policy, shell)
@@ -110,9 +110,8 @@ class Pipeline:
         self.trace(frame, stream)
 
     def make_graph(self, first_frame: int = 0, refit: bool = False) -> "R.FrameGraph":
-        """Capture one whole update as a HIP graph; each launch advances the frame index."""
-        if refit and self.parts:
-            raise RuntimeError("captured updates refit from vertices; a scene of rigid parts moves by set_transforms")
+        """Capture one whole update as a HIP graph; each launch advances the frame index.  With refit, each
+        launch refits from `self.vertices`, or for rigid parts applies `self.transforms`, as they are then."""
         self.frame_counter = torch.full((1,), int(first_frame), dtype=torch.int32, device=self.device)
         D = R.FrameDesc()
         D.vertices, D.nv = self.vertices.data_ptr(), self.vertices.shape[0]
@@ -129,6 +128,8 @@ class Pipeline:
         D.fine_sdf, D.trace_workspace = self.fine_sdf.data_ptr(), self.trace_ws.data_ptr()
         D.frame_counter = self.frame_counter.data_ptr()
         D.fine_c = None if self.fine_c is None else self.fine_c.data_ptr()
+        if self.parts:  # each launch applies self.transforms (update it in place between launches)
+            D.transforms, D.world_vertices = self.transforms.data_ptr(), self.vertices.data_ptr()
         steps = None
         if self.jfa_steps is not None:
             steps = (C.c_int32 * len(self.jfa_steps))(*self.jfa_steps)  # read during create only
@@ -146,7 +147,9 @@ class Pipeline:
         """New object-to-world transforms of the rigid parts: top-level refit and world positions."""
         if not self.parts:
             raise RuntimeError("set_transforms needs a scene of rigid parts")
-        self.scene.set_transforms(transforms, self.vertices, stream)
+        if transforms.data_ptr() != self.transforms.data_ptr():
+            self.transforms.copy_(transforms)
+        self.scene.set_transforms(self.transforms, self.vertices, stream)
 
     def reset(self):
         R.rtsdf_accum_reset(self.fine, self.state)

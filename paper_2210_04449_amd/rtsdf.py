@@ -52,7 +52,7 @@ class FrameDesc(C.Structure):
                 ("dist2", _P), ("coarse_sdf", _P), ("mask", _P), ("queue", _P), ("queue_cap", _i32),
                 ("count", _P), ("select_workspace", _P), ("state", Accum), ("fine_sdf", _P),
                 ("trace_workspace", _P), ("frame_counter", _P), ("fine_c", _P),
-                ("jfa_steps", _P), ("jfa_nsteps", _i32)]
+                ("jfa_steps", _P), ("jfa_nsteps", _i32), ("transforms", _P), ("world_vertices", _P)]
 
 
 class BatchScene(C.Structure):

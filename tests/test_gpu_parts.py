@@ -173,3 +173,28 @@ def test_parts_without_static_world_and_without_movers(R):
         ref = oracle.run_frames(w, faces, nc, nf, beta, d, rays, range(frames), scene=5)
         print(len(o) - 1, "parts:", compare(p, ref))
         p.close()
+
+
+def test_parts_graph_replays_eager(R):
+    """A captured update of a two-level scene applies the transform buffer at each launch: replays equal the
+    eager updates bit for bit while the parts move."""
+    say("parts graph")
+    from paper_2210_04449_amd.pipeline import Pipeline
+    dyn = DynamicScene(7, n_prims=30, detail="low")
+    v, f, offs, _ = dyn.parts()
+    nc, nf, rays = 32, 64, 4
+    beta, d = 0.5 / nc, 2.0 / nc
+    mk = lambda: Pipeline(cu(v), cu(f), nc, nf, beta, d, rays, scene_id=9, alpha=0.9,  # noqa: E731
+                          parts=(offs, cu(dyn.part_transforms(0))))
+    eager, cap = mk(), mk()
+    g = cap.make_graph(first_frame=0, refit=True)
+    for fr in range(4):
+        T = cu(dyn.part_transforms(fr + 1))
+        eager.set_transforms(T)
+        eager.step(fr)
+        cap.transforms.copy_(T)
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(eager.vertices, cap.vertices) and torch.equal(eager.fine_sdf, cap.fine_sdf), fr
+        assert torch.equal(eager.state.hits, cap.state.hits) and torch.equal(eager.mask, cap.mask), fr
+    g.close()
