@@ -75,12 +75,15 @@ struct FillScene {
 
 __global__ void __launch_bounds__(256) voxelize_batch(const BatchVox *__restrict__ sc, int ns, int64_t items)
 {
-    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the same strided dealing of items to wavefronts as the single-scene kernel
+    const int64_t waves = (items + kWave - 1) / kWave;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t item = (gid & (kWave - 1)) * waves + (gid >> 6);
     VoxTri T;
     bool big = false;
     int32_t *seeds = nullptr;
     int n = 0;
-    if (item < items) {
+    if ((gid >> 6) < waves && item < items) {
         int lo = 0, hi = ns - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;

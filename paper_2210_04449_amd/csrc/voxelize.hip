@@ -7,7 +7,8 @@
 // column covered when its centre is inside or on the projected triangle, and
 // the voxel holding the triangle's depth at that centre marked.
 //
-// Work mapping: one lane per (triangle, axis).  A lane rasterizes its own
+// Work mapping: one lane per (triangle, axis), dealt to wavefronts with a
+// stride.  A lane rasterizes its own
 // projection when the bounding box holds at most kSmallPixels column centres;
 // larger projections (room walls cover whole faces of the grid) are flagged
 // and then rasterized by the whole wavefront, one after another, with the 64
@@ -170,10 +171,16 @@ __global__ void __launch_bounds__(256) voxelize_kernel(const float *__restrict__
                                                        const int32_t *__restrict__ f, int nt, rtsdf_grid g,
                                                        int32_t *__restrict__ seeds)
 {
-    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // items are dealt to wavefronts with a stride (lane l of wavefront w takes item l * waves + w), so the
+    // large projections of consecutive triangles (the walls of a room come one after another) land in
+    // different wavefronts instead of queueing in one
+    const int64_t total = 3 * (int64_t)nt;
+    const int64_t waves = (total + kWave - 1) / kWave;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t item = (gid & (kWave - 1)) * waves + (gid >> 6);
     VoxTri T;
     bool big = false;
-    if (item < 3 * (int64_t)nt) big = vox_item(v, nv, f, (int)(item / 3), (int)(item % 3), g, seeds, T);
+    if ((gid >> 6) < waves && item < total) big = vox_item(v, nv, f, (int)(item / 3), (int)(item % 3), g, seeds, T);
     vox_wave_big(big, T, seeds, g.n);
 }
 
