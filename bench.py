@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--alphas", type=float, nargs="+", default=[1.0, 0.95, 0.9, 0.75, 0.5])
     ap.add_argument("--study-frames", type=int, default=24)
     ap.add_argument("--alpha", type=float, default=None, help="override the workload's decay alpha")
+    ap.add_argument("--rebuild", action="store_true",
+                    help="dynamic workload: rebuild the hierarchy on the device every update instead of refitting")
     ap.add_argument("--parts", action="store_true",
                     help="dynamic workload as a two-level scene of rigid parts instead of one refitted hierarchy")
     ap.add_argument("--no-shadow", action="store_true", help="skip timing the soft-shadow consumer")
@@ -155,6 +157,8 @@ def main():
     use_parts = args.parts and args.config == "dynamic"
     kw = dict(seed=0, scene_id=w.scene_seed, alpha=w.alpha if args.alpha is None else args.alpha,
               leaf_size=args.leaf_size, jfa_variant=args.jfa, sampling=args.sampling)
+    if args.rebuild:
+        kw["rebuild"] = True
     dyn_frames = dyn_T = None
     if use_parts:
         # the moving primitives as rigid parts of a two-level scene; 8 transform sets cycled
@@ -230,7 +234,7 @@ def main():
     achieved = ops / trace_s / 1e12
 
     graph_ms = None
-    if args.graph:
+    if args.graph and not args.rebuild:  # a captured update refits (the rebuild's sort stays out of graphs)
         g = p.make_graph(first_frame=args.warmup + K + 1, refit=dyn_frames is not None or dyn_T is not None)
         g.launch()  # warm-up replay
         torch.cuda.synchronize()
@@ -318,7 +322,8 @@ def main():
         },
     }
     if dyn_frames is not None:
-        out["config"]["dynamic"] = "20% of primitives move rigidly; 8 precomputed vertex sets cycled; refit each update"
+        how = "device rebuild" if args.rebuild else "refit"
+        out["config"]["dynamic"] = f"20% of primitives move rigidly; 8 precomputed vertex sets cycled; {how} each update"
     if use_parts:
         out["config"]["dynamic"] = ("20% of primitives move rigidly, as parts of a two-level scene; 8 precomputed "
                                     "transform sets cycled; top-level refit and world positions each update")
@@ -463,8 +468,9 @@ def run_alpha_study(args):
 
 
 def run_refit_study(args):
-    """One refitted hierarchy against a two-level scene of rigid parts on the moving-scene workload, over a
-    continuous animation: per-update time (geometry update + the whole SDF update) frame by frame."""
+    """One refitted hierarchy, one rebuilt on the device every frame, and a two-level scene of rigid parts on the
+    moving-scene workload, over a continuous animation: per-update time (geometry update + the whole SDF update)
+    frame by frame."""
     import torch
 
     import paper_2210_04449_amd.rtsdf as R
@@ -478,11 +484,11 @@ def run_refit_study(args):
     stream = torch.cuda.current_stream()
     pv, pf, offs, _ = dyn.parts()
     rows = {}
-    for kind in ("refit", "parts"):
-        if kind == "refit":
-            verts = [torch.from_numpy(dyn.mesh(f).vertices).to(dev) for f in range(frames)]
+    verts = [torch.from_numpy(dyn.mesh(f).vertices).to(dev) for f in range(frames)]
+    for kind in ("refit", "rebuild", "parts"):
+        if kind in ("refit", "rebuild"):
             p = Pipeline(verts[0].clone(), torch.from_numpy(w.mesh.faces).to(dev), w.nc, w.nf, w.beta, w.d, w.rays,
-                         scene_id=w.scene_seed, alpha=w.alpha, leaf_size=args.leaf_size)
+                         scene_id=w.scene_seed, alpha=w.alpha, leaf_size=args.leaf_size, rebuild=kind == "rebuild")
             move = lambda f: p.set_vertices(verts[f])  # noqa: E731
         else:
             Ts = [torch.from_numpy(dyn.part_transforms(f)).to(dev) for f in range(frames)]
@@ -512,7 +518,7 @@ def run_refit_study(args):
         p.close()
         del p
         torch.cuda.empty_cache()
-    print(json.dumps({"study": "refit vs two-level", "workload": w.name, "frames": frames, "fine": w.nf,
+    print(json.dumps({"study": "refit vs rebuild vs two-level", "workload": w.name, "frames": frames, "fine": w.nf,
                       "rays_per_texel": w.rays, "motion": "20% of primitives rigid, continuous", "rows": rows}),
           flush=True)
 

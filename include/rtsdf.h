@@ -227,6 +227,24 @@ int rtsdf_scene_create(const float *vertices, int32_t nv, const int32_t *faces, 
 int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsdf_stream stream);
 int rtsdf_scene_info_get(const rtsdf_scene *scene, rtsdf_scene_info *info);
 
+/* Rebuilding the hierarchy on the device (for geometry that moves far from  */
+/* where it was built, which a refit only loosens).  enable_rebuild          */
+/* allocates the rebuild buffers (it allocates, like create, and             */
+/* synchronises `stream`) and replaces the creation hierarchy with a linear  */
+/* BVH built on the device over the same triangle references: 30-bit Morton  */
+/* codes of the reference centres, a radix sort, the binary radix tree of    */
+/* Karras (HPG 2012), one reference per leaf, boxes bottom-up.  rebuild      */
+/* takes new positions for the same topology (as refit) and rebuilds it; a   */
+/* refit of such a scene refits the rebuilt tree.  Traced results are those */
+/* of the creation hierarchy except for rays whose closest hit is within     */
+/* float rounding of another triangle's (the test order may pick the other). */
+/* EINVAL for two-level scenes and for scenes with                           */
+/* fewer than two references; rebuild before enable_rebuild is EINVAL.       */
+/* rebuild uses a library sort that may record memset operations, so do not */
+/* capture it in a graph.                                                    */
+int rtsdf_scene_enable_rebuild(rtsdf_scene *scene, rtsdf_stream stream);
+int rtsdf_scene_rebuild(rtsdf_scene *scene, const float *vertices, rtsdf_stream stream);
+
 /* Two-level scene: a static world plus rigidly moving parts (refitting one */
 /* hierarchy over moving geometry loosens it frame after frame).  Part i     */
 /* owns faces [instance_faces[i], instance_faces[i + 1]) (host array of      */

@@ -1,0 +1,365 @@
+// Rebuilding the hierarchy on the device (linear BVH).
+//
+// Refitting keeps the topology built at creation; when geometry moves far
+// from where it was, boxes overlap more and more and tracing slows (20x after
+// 48 frames of continuous motion on the moving-scene workload).  A rebuild
+// from scratch on the host costs seconds for a million triangles; this builds
+// a new hierarchy on the device every frame instead, in the node format the
+// tracer reads, over the scene's references (split pieces of large triangles
+// keep their subdivision paths, so a rebuild re-derives each piece's box from
+// the current vertices):
+//
+//   1. reference boxes from the current vertices, and the bounds of their
+//      centres (atomic min/max on order-preserving integer images of floats);
+//   2. 30-bit Morton codes of the centres in those bounds;
+//   3. radix sort of (code, reference) pairs (hipCUB); equal codes keep the
+//      reference order, so (code, position) keys are distinct;
+//   4. the binary radix tree over the sorted keys (Karras, "Maximizing
+//      Parallelism in the Construction of BVHs, Octrees, and k-d Trees",
+//      HPG 2012): internal node i finds its key range from the common-prefix
+//      lengths of its neighbours and splits where the prefix changes; one
+//      reference per leaf; node 0 is the root;
+//   5. boxes bottom-up: one thread per leaf climbs, the second thread to
+//      arrive at a node writes its two child boxes and goes on;
+//   6. the triangle records and affine maps in leaf order.
+// The tree depth is at most 30 + ceil(log2 n) (each level consumes one bit of
+// the distinct 30-bit code + position key), which sizes the traversal stack.
+// A refit of a rebuilt scene reuses steps 1 and 5 on the same tree.
+//
+// The closest hit a ray finds is the minimum over all references of a value
+// computed from the reference alone, so a rebuilt scene traces like the
+// original one; only where two candidates lie within float rounding of each
+// other (a ray through an edge) can the order of the tests, which follows
+// the hierarchy, pick the other one.
+#include <hipcub/hipcub.hpp>
+
+#include "common.hpp"
+
+namespace rtsdf {
+
+// float <-> unsigned keeping the order of all finite values
+__device__ __forceinline__ unsigned ordered_bits(float f)
+{
+    const unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float from_ordered(unsigned u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// step 1: reference boxes (padded) and centre bounds; bounds[0..2] min, [3..5] max (ordered integers)
+__global__ void __launch_bounds__(256) lbvh_ref_boxes(const float *__restrict__ v, const int32_t *__restrict__ f,
+                                                      const int32_t *__restrict__ ref_tri,
+                                                      const int32_t *__restrict__ ref_path, int nref, float pad,
+                                                      float *__restrict__ box, unsigned *__restrict__ bounds)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    float c[3] = {0.f, 0.f, 0.f};
+    const bool ok = i < nref;
+    if (ok) {
+        const int t = ref_tri[i];
+        float a[3], b[3], cc[3];
+        for (int k = 0; k < 3; ++k) {
+            a[k] = v[3 * f[3 * t] + k];
+            b[k] = v[3 * f[3 * t + 1] + k];
+            cc[k] = v[3 * f[3 * t + 2] + k];
+        }
+        follow_path(a, b, cc, ref_path[i]);
+        for (int k = 0; k < 3; ++k) {
+            const float lo = nextafterf(fminf(a[k], fminf(b[k], cc[k])) - pad, -__builtin_inff());
+            const float hi = nextafterf(fmaxf(a[k], fmaxf(b[k], cc[k])) + pad, __builtin_inff());
+            box[6 * i + k] = lo;
+            box[6 * i + 3 + k] = hi;
+            c[k] = 0.5f * (lo + hi);
+        }
+    }
+    // wavefront min/max, then one atomic per wavefront
+    for (int k = 0; k < 3; ++k) {
+        unsigned mn = ok ? ordered_bits(c[k]) : 0xffffffffu, mx = ok ? ordered_bits(c[k]) : 0u;
+        for (int off = 32; off > 0; off >>= 1) {
+            mn = min(mn, (unsigned)__shfl_xor((int)mn, off));
+            mx = max(mx, (unsigned)__shfl_xor((int)mx, off));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(&bounds[k], mn);
+            atomicMax(&bounds[3 + k], mx);
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t morton30(float x, float y, float z)
+{
+    const uint32_t X = (uint32_t)fminf(fmaxf(x * 1024.0f, 0.0f), 1023.0f);
+    const uint32_t Y = (uint32_t)fminf(fmaxf(y * 1024.0f, 0.0f), 1023.0f);
+    const uint32_t Z = (uint32_t)fminf(fmaxf(z * 1024.0f, 0.0f), 1023.0f);
+    return morton3(X, Y, Z);
+}
+
+// step 2
+__global__ void __launch_bounds__(256) lbvh_codes(const float *__restrict__ box, int nref,
+                                                  const unsigned *__restrict__ bounds, uint32_t *__restrict__ code,
+                                                  int32_t *__restrict__ id)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nref) return;
+    float q[3];
+    for (int k = 0; k < 3; ++k) {
+        const float lo = from_ordered(bounds[k]), hi = from_ordered(bounds[3 + k]);
+        const float ext = hi - lo;
+        const float c = 0.5f * (box[6 * i + k] + box[6 * i + 3 + k]);
+        q[k] = ext > 0.0f ? (c - lo) / ext : 0.5f;
+    }
+    code[i] = morton30(q[0], q[1], q[2]);
+    id[i] = i;
+}
+
+// common-prefix length of the keys (code, position) at positions i and j; -1 outside [0, n)
+__device__ __forceinline__ int lbvh_delta(const uint32_t *__restrict__ code, int n, int i, int j)
+{
+    if (j < 0 || j >= n) return -1;
+    const uint32_t a = code[i], b = code[j];
+    if (a != b) return __clz(a ^ b) - 2;  // 30-bit codes in 32-bit words
+    return 30 + __clz((uint32_t)i ^ (uint32_t)j);
+}
+
+// step 4: internal node i of the radix tree over n sorted keys
+__global__ void __launch_bounds__(256) lbvh_internal(const uint32_t *__restrict__ code, int n, BvhNode *nodes,
+                                                     int32_t *__restrict__ leaf_parent)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int d = lbvh_delta(code, n, i, i + 1) - lbvh_delta(code, n, i, i - 1) >= 0 ? 1 : -1;
+    const int dmin = lbvh_delta(code, n, i, i - d);
+    int lmax = 2;
+    while (lbvh_delta(code, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (lbvh_delta(code, n, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = lbvh_delta(code, n, i, j);
+    int s = 0;
+    for (int t = (l + 1) >> 1;; t = (t + 1) >> 1) {
+        if (lbvh_delta(code, n, i, i + (s + t) * d) > dnode) s += t;
+        if (t == 1) break;
+    }
+    const int gamma = i + s * d + min(d, 0);
+    const int lo = min(i, j), hi = max(i, j);
+    const bool left_leaf = lo == gamma, right_leaf = hi == gamma + 1;
+    BvhNode &nd = nodes[i];
+    const int c0 = left_leaf ? leaf_code(gamma, 1) : gamma;
+    const int c1 = right_leaf ? leaf_code(gamma + 1, 1) : gamma + 1;
+    nd.meta.x = c0;
+    nd.meta.y = c1;
+    nd.meta.w = 0;
+    if (left_leaf) leaf_parent[gamma] = i;
+    else nodes[gamma].meta.z = i;
+    if (right_leaf) leaf_parent[gamma + 1] = i;
+    else nodes[gamma + 1].meta.z = i;
+    if (i == 0) nd.meta.z = -1;
+}
+
+// step 5: boxes bottom-up; leaf k holds the reference sorted to position k (ids[k])
+__global__ void __launch_bounds__(256) lbvh_boxes(BvhNode *nodes, const int32_t *__restrict__ leaf_parent,
+                                                  const int32_t *__restrict__ ids, const float *__restrict__ box,
+                                                  int n, int32_t *counter)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int node = leaf_parent[k];
+    while (node >= 0) {
+        __threadfence();
+        if (atomicAdd(&counter[node], 1) == 0) return;  // the other child is not done; its thread goes on
+        __threadfence();
+        BvhNode *nd = &nodes[node];
+        const int c[2] = {nd->meta.x, nd->meta.y};
+        for (int s = 0; s < 2; ++s) {
+            float lo[3], hi[3];
+            if (c[s] < 0) {
+                const float *b = box + 6 * ids[leaf_first(c[s])];
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = b[a];
+                    hi[a] = b[3 + a];
+                }
+            } else {
+                const BvhNode *ch = &nodes[c[s]];
+                float l2[3], h2[3];
+                get_slot(ch, 0, lo, hi);
+                get_slot(ch, 1, l2, h2);
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = fminf(lo[a], l2[a]);
+                    hi[a] = fmaxf(hi[a], h2[a]);
+                }
+            }
+            set_slot(nd, s, lo, hi);
+        }
+        node = nd->meta.z;
+    }
+}
+
+// step 6: triangle records in leaf order (whole triangle, global id, the piece's path)
+__global__ void __launch_bounds__(256) lbvh_records(const float *__restrict__ v, const int32_t *__restrict__ f,
+                                                    const int32_t *__restrict__ ref_tri,
+                                                    const int32_t *__restrict__ ref_path,
+                                                    const int32_t *__restrict__ ids, int n, float4 *__restrict__ tris,
+                                                    int4 *__restrict__ leaf_faces)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int r = ids[k], t = ref_tri[r], path = ref_path[r];
+    const int vid[3] = {f[3 * t], f[3 * t + 1], f[3 * t + 2]};
+    for (int q = 0; q < 3; ++q) {
+        const float *p = v + 3 * vid[q];
+        tris[3 * k + q] = make_float4(p[0], p[1], p[2], q == 0 ? __int_as_float(t) : (q == 1 ? __int_as_float(path)
+                                                                                           : 0.f));
+    }
+    leaf_faces[k] = make_int4(vid[0], vid[1], vid[2], t);
+}
+
+__global__ void lbvh_init_bounds(unsigned *bounds)
+{
+    const int k = threadIdx.x;
+    if (k < 3) bounds[k] = 0xffffffffu;
+    else if (k < 6) bounds[k] = 0u;
+}
+
+}  // namespace rtsdf
+
+// device buffers of a rebuildable scene (allocated by rtsdf_scene_enable_rebuild)
+struct rtsdf_lbvh {
+    int32_t *ref_tri = nullptr, *ref_path = nullptr;  // [nref] the references, in creation order
+    float *box = nullptr;                              // [nref][6]
+    unsigned *bounds = nullptr;                        // [6]
+    uint32_t *code = nullptr, *code_sorted = nullptr;  // [nref]
+    int32_t *id = nullptr, *id_sorted = nullptr;       // [nref]
+    int32_t *leaf_parent = nullptr;                    // [nref]
+    void *sort_tmp = nullptr;
+    size_t sort_bytes = 0;
+};
+
+static void lbvh_free(rtsdf_lbvh *L)
+{
+    if (!L) return;
+    for (void *p : {(void *)L->ref_tri, (void *)L->ref_path, (void *)L->box, (void *)L->bounds, (void *)L->code,
+                    (void *)L->code_sorted, (void *)L->id, (void *)L->id_sorted, (void *)L->leaf_parent, L->sort_tmp})
+        (void)hipFree(p);
+    delete L;
+}
+
+namespace rtsdf {
+
+// steps 1 and 5 on the current tree (refit), or 1-6 (rebuild)
+static int lbvh_run(rtsdf_scene *sc, bool rebuild, hipStream_t s)
+{
+    rtsdf_lbvh *L = sc->lbvh;
+    const int n = sc->nref;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    lbvh_init_bounds<<<dim3(1), dim3(64), 0, s>>>(L->bounds);
+    RTSDF_CHECK_LAUNCH();
+    lbvh_ref_boxes<<<dim3(blocks), dim3(256), 0, s>>>(sc->vertices, sc->faces, L->ref_tri, L->ref_path, n, sc->pad,
+                                                       L->box, L->bounds);
+    RTSDF_CHECK_LAUNCH();
+    if (rebuild) {
+        lbvh_codes<<<dim3(blocks), dim3(256), 0, s>>>(L->box, n, L->bounds, L->code, L->id);
+        RTSDF_CHECK_LAUNCH();
+        size_t bytes = L->sort_bytes;
+        if (hipcub::DeviceRadixSort::SortPairs(L->sort_tmp, bytes, L->code, L->code_sorted, L->id, L->id_sorted, n, 0,
+                                               30, s) != hipSuccess)
+            return RTSDF_EHIP;
+        lbvh_internal<<<dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s>>>(L->code_sorted, n, sc->nodes,
+                                                                                  L->leaf_parent);
+        RTSDF_CHECK_LAUNCH();
+        lbvh_records<<<dim3(blocks), dim3(256), 0, s>>>(sc->vertices, sc->faces, L->ref_tri, L->ref_path,
+                                                         L->id_sorted, n, sc->tris, sc->leaf_faces);
+        RTSDF_CHECK_LAUNCH();
+    } else {
+        refit_tris<<<dim3(blocks), dim3(256), 0, s>>>(sc->vertices, sc->leaf_faces, sc->tris, n);
+        RTSDF_CHECK_LAUNCH();
+    }
+    tri_maps<<<dim3(blocks), dim3(256), 0, s>>>(sc->tris, sc->tmap, n);
+    RTSDF_CHECK_LAUNCH();
+    int rc = launch_fill<int32_t>(sc->refit_counter, 0, n - 1, s);
+    if (rc != RTSDF_OK) return rc;
+    lbvh_boxes<<<dim3(blocks), dim3(256), 0, s>>>(sc->nodes, L->leaf_parent, L->id_sorted, L->box, n,
+                                                   sc->refit_counter);
+    RTSDF_CHECK_LAUNCH();
+    return RTSDF_OK;
+}
+
+}  // namespace rtsdf
+
+extern "C" int rtsdf_scene_enable_rebuild(rtsdf_scene *sc, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!sc || sc->ninst > 0) return RTSDF_EINVAL;
+    if (sc->lbvh) return RTSDF_OK;
+    const int n = sc->nref;
+    if (n < 2) return RTSDF_EINVAL;  // a one-reference scene has nothing to rebuild
+    int bits = 0;
+    while ((1ll << bits) < (int64_t)n) ++bits;
+    const int depth = 30 + bits + 1;  // leaves included
+    if (depth + 1 > 64) return RTSDF_EINVAL;
+    hipStream_t s = as_stream(stream);
+    // the references in leaf order now; their (triangle, path) identities are what every rebuild sorts
+    std::vector<float4> htri((size_t)3 * n);
+    RTSDF_TRY(hipMemcpyAsync(htri.data(), sc->tris, sizeof(float4) * htri.size(), hipMemcpyDeviceToHost, s));
+    RTSDF_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> rt(n), rp(n);
+    for (int i = 0; i < n; ++i) {
+        rt[i] = __builtin_bit_cast(int32_t, htri[3 * i].w);
+        rp[i] = __builtin_bit_cast(int32_t, htri[3 * i + 1].w);
+    }
+    auto *L = new rtsdf_lbvh();
+    int64_t bytes = 0;
+    auto alloc = [&](void **p, size_t b) -> bool {
+        if (hipMalloc(p, b ? b : 16) != hipSuccess) return false;
+        bytes += (int64_t)b;
+        return true;
+    };
+    BvhNode *nodes = nullptr;
+    int32_t *counter = nullptr;
+    bool ok = alloc((void **)&L->ref_tri, sizeof(int32_t) * n) && alloc((void **)&L->ref_path, sizeof(int32_t) * n) &&
+              alloc((void **)&L->box, sizeof(float) * 6 * n) && alloc((void **)&L->bounds, sizeof(unsigned) * 6) &&
+              alloc((void **)&L->code, sizeof(uint32_t) * n) && alloc((void **)&L->code_sorted, sizeof(uint32_t) * n) &&
+              alloc((void **)&L->id, sizeof(int32_t) * n) && alloc((void **)&L->id_sorted, sizeof(int32_t) * n) &&
+              alloc((void **)&L->leaf_parent, sizeof(int32_t) * n) &&
+              alloc((void **)&nodes, sizeof(BvhNode) * (n - 1)) && alloc((void **)&counter, sizeof(int32_t) * (n - 1));
+    if (ok) {
+        ok = hipcub::DeviceRadixSort::SortPairs(nullptr, L->sort_bytes, L->code, L->code_sorted, L->id, L->id_sorted,
+                                                n, 0, 30, s) == hipSuccess &&
+             alloc(&L->sort_tmp, L->sort_bytes);
+    }
+    ok = ok && hipMemcpyAsync(L->ref_tri, rt.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) == hipSuccess &&
+         hipMemcpyAsync(L->ref_path, rp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) == hipSuccess &&
+         hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+        lbvh_free(L);
+        (void)hipFree(nodes);
+        (void)hipFree(counter);
+        return RTSDF_ENOMEM;
+    }
+    // the rebuilt tree replaces the creation hierarchy (and the refit tables that went with it)
+    (void)hipFree(sc->nodes);
+    (void)hipFree(sc->refit_counter);
+    sc->nodes = nodes;
+    sc->refit_counter = counter;
+    sc->nnodes = n - 1;
+    sc->nstart = 0;
+    sc->max_depth = depth;
+    sc->max_leaf = 1;
+    sc->bytes += bytes;
+    sc->lbvh = L;
+    int rc = ensure_spill(sc);
+    if (rc == RTSDF_OK) rc = lbvh_run(sc, true, s);
+    return rc;
+}
+
+extern "C" int rtsdf_scene_rebuild(rtsdf_scene *scene, const float *vertices, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!scene || !scene->lbvh || (scene->nv > 0 && !vertices)) return RTSDF_EINVAL;
+    hipStream_t s = as_stream(stream);
+    if (scene->nv > 0 && vertices != scene->vertices)
+        RTSDF_TRY(hipMemcpyAsync(scene->vertices, vertices, sizeof(float) * 3 * scene->nv, hipMemcpyDeviceToDevice, s));
+    return lbvh_run(scene, true, s);
+}

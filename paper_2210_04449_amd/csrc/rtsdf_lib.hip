@@ -7,6 +7,7 @@
 #include "scene.hip"
 #include "instance.hip"
 #include "trace.hip"
+#include "lbvh.hip"
 #include "distance.hip"
 #include "shadow.hip"
 #include "batch.hip"

@@ -67,6 +67,8 @@ __host__ __device__ __forceinline__ int leaf_count(int code) { return (-1 - code
 
 }  // namespace rtsdf
 
+struct rtsdf_lbvh;  // device rebuild buffers (rtsdf_scene_enable_rebuild)
+
 struct rtsdf_scene {
     int nv = 0, nt = 0;
     int nnodes = 0;
@@ -103,7 +105,10 @@ struct rtsdf_scene {
     int top_levels = 0;
     int nentries = 0;                  // subtrees of moving parts that the top level holds
     int32_t *entry_part = nullptr;     // [nentries] part of each (1..ninst-1)
+    rtsdf_lbvh *lbvh = nullptr;        // set once the scene rebuilds its hierarchy on the device
 };
+
+static void lbvh_free(rtsdf_lbvh *L);
 
 namespace rtsdf {
 
@@ -647,6 +652,7 @@ static int rtsdf_scene_create_impl(const float *vertices, int32_t nv, const int3
 
 namespace rtsdf {
 static int ensure_spill(rtsdf_scene *sc);
+static int lbvh_run(rtsdf_scene *sc, bool rebuild, hipStream_t s);
 }
 
 // The tracer's spill area depends on the hierarchy depth; it is allocated
@@ -673,6 +679,7 @@ extern "C" int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsd
     if (scene->nv > 0 && vertices != scene->vertices)
         RTSDF_TRY(hipMemcpyAsync(scene->vertices, vertices, sizeof(float) * 3 * scene->nv, hipMemcpyDeviceToDevice, s));
     if (scene->nref == 0) return RTSDF_OK;
+    if (scene->lbvh) return lbvh_run(scene, false, s);  // a rebuilt tree refits through its own tables
     refit_tris<<<dim3((scene->nref + 255) / 256), dim3(256), 0, s>>>(scene->vertices, scene->leaf_faces, scene->tris,
                                                                       scene->nref);
     RTSDF_CHECK_LAUNCH();
@@ -712,6 +719,7 @@ extern "C" int rtsdf_scene_info_get(const rtsdf_scene *scene, rtsdf_scene_info *
 extern "C" void rtsdf_scene_destroy(rtsdf_scene *scene)
 {
     if (!scene) return;
+    lbvh_free(scene->lbvh);
     (void)hipFree(scene->obj_vertices);
     (void)hipFree(scene->vert_inst);
     (void)hipFree(scene->inst_obj_box);

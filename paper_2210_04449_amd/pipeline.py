@@ -13,7 +13,9 @@ texel centre; the tracer then works on the fine grid alone).  ``sign_policy``
 "vote" signs traced distances by the front/back vote of Sec. 2.2; "shell"
 outputs the unsigned distance minus ``shell`` (open or thin surfaces).
 ``parts=(part_faces, transforms)`` builds a two-level scene of rigid parts
-(vertices in object space; ``set_transforms`` moves them).
+(vertices in object space; ``set_transforms`` moves them); ``rebuild=True``
+rebuilds the hierarchy on the device at every ``set_vertices`` instead of
+refitting it.
 """
 from __future__ import annotations
 
@@ -29,7 +31,7 @@ class Pipeline:
                  rays: int, seed: int = 0, scene_id: int = 0, alpha: float = 1.0, lo=(0.0, 0.0, 0.0),
                  side: float = 1.0, leaf_size: int = 2, queue_cap: int | None = None, device="cuda",
                  jfa_variant: str = "jfa", sampling: str = "point", sign_policy: str = "vote",
-                 shell: float = 0.0, parts=None):
+                 shell: float = 0.0, parts=None, rebuild: bool = False):
         if sampling not in ("point", "trilinear"):
             raise ValueError(f"sampling must be 'point' or 'trilinear', not {sampling!r}")
         self.sampling = sampling
@@ -70,6 +72,9 @@ class Pipeline:
             self.scene = R.Scene.instanced(self.obj_vertices, self.faces, part_faces, self.transforms, leaf_size)
             self.scene.world_vertices(self.vertices)
         self.parts = parts is not None
+        self.rebuild = bool(rebuild)
+        if self.rebuild:  # set_vertices rebuilds the hierarchy on the device instead of refitting it
+            self.scene.enable_rebuild()
         self.scene.set_sign(sign_policy, shell)
 
     # -- stages ----------------------------------------------------------
@@ -141,7 +146,10 @@ class Pipeline:
         if self.parts:
             raise RuntimeError("a scene of rigid parts moves by set_transforms")
         self.vertices.copy_(vertices)
-        self.scene.refit(self.vertices, stream)
+        if self.rebuild:
+            self.scene.rebuild(self.vertices, stream)
+        else:
+            self.scene.refit(self.vertices, stream)
 
     def set_transforms(self, transforms: torch.Tensor, stream=None):
         """New object-to-world transforms of the rigid parts: top-level refit and world positions."""

@@ -120,6 +120,8 @@ def _load():
         "rtsdf_trace_backward": ([_P, Grid, Accum, _P, _P, _u64, _u32, _P, _P], _i32),
         "rtsdf_shadow": ([Grid, _P, _P, _i32, _P, _f32, _f32, _i32, _f32, _f32, _P, _P], _i32),
         "rtsdf_scene_set_sign": ([_P, _i32, _f32], _i32),
+        "rtsdf_scene_enable_rebuild": ([_P, _P], _i32),
+        "rtsdf_scene_rebuild": ([_P, _P, _P], _i32),
         "rtsdf_scene_create_instanced": ([_P, _i32, _P, _i32, C.POINTER(_i32), _i32, _P, _i32, C.POINTER(_P), _P],
                                          _i32),
         "rtsdf_scene_set_transforms": ([_P, _P, _P, _P], _i32),
@@ -298,6 +300,13 @@ class Scene:
     def set_sign(self, policy: str = "vote", shell: float = 0.0):
         """How traced distances are signed: "vote" (front/back hit counts) or "shell" (distance - shell)."""
         _check("rtsdf_scene_set_sign", _lib.rtsdf_scene_set_sign(self.handle, SIGN_POLICIES[policy], float(shell)))
+
+    def enable_rebuild(self, stream=None):
+        """Replace the hierarchy by one rebuilt on the device (linear BVH); later rebuild() calls redo it."""
+        _check("rtsdf_scene_enable_rebuild", _lib.rtsdf_scene_enable_rebuild(self.handle, _stream(stream)))
+
+    def rebuild(self, vertices, stream=None):
+        _check("rtsdf_scene_rebuild", _lib.rtsdf_scene_rebuild(self.handle, _ptr(vertices), _stream(stream)))
 
     def info(self) -> SceneInfo:
         inf = SceneInfo()

@@ -1,0 +1,122 @@
+"""Hierarchies rebuilt on the device (linear BVH over the scene's references).
+
+The closest hit of a ray is a minimum over references of values computed from
+each reference alone, so a rebuilt scene traces like the scene built on the
+host, static or after the vertices moved (rebuild against refit), and a refit
+of a rebuilt tree too: identical texels except where a ray's two best
+candidates lie within float rounding (the order of tests, which follows the
+hierarchy, may then pick the other; about one texel in ten million on the
+room), and those within the trace tolerance.  The moving scene is also
+checked against the oracle, and bad calls are refused.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth.scenes import DynamicScene, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2210_04449_amd.rtsdf as R
+    return R
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def same(a, b, tol=1e-5):
+    """At most one texel in 10^5 differs in any state field (none on small scenes), by at most tol."""
+    diff = ((a.fine_sdf != b.fine_sdf) | (a.state.u != b.state.u) | (a.state.hits != b.state.hits)
+            | (a.state.arg_tri != b.state.arg_tri) | (a.state.arg_ray != b.state.arg_ray))
+    n = int(diff.sum())
+    if n:
+        fa, fb = a.fine_sdf[diff].abs(), b.fine_sdf[diff].abs()
+        print("texels differing:", n, "max |f| difference", float((fa - fb).abs().max()))
+        if float((fa - fb).abs().max()) > tol:
+            return False
+    return n <= max(1, diff.numel() // 100000)
+
+
+@pytest.mark.parametrize("case", ["tiny", "room"])
+def test_rebuilt_scene_traces_like_the_host_build(R, case):
+    say("rebuild static", case)
+    from paper_2210_04449_amd.pipeline import Pipeline
+    w = workload(case)
+    frames = range(3) if case == "tiny" else range(1)
+    mk = lambda rb: Pipeline(cu(w.mesh.vertices), cu(w.mesh.faces), w.nc, w.nf, w.beta, w.d, w.rays,  # noqa: E731
+                             scene_id=w.scene_seed, rebuild=rb)
+    a, b = mk(False), mk(True)
+    ia, ib = a.scene.info(), b.scene.info()
+    assert ib.references == ia.references and ib.nodes == ia.references - 1 and ib.leaf_size == 1
+    bits = int(np.ceil(np.log2(ia.references)))
+    assert ib.max_depth == 30 + bits + 1
+    for f in frames:
+        a.step(f)
+        b.step(f)
+    torch.cuda.synchronize()
+    assert R.rtsdf_sync_status() == 0
+    assert same(a, b)
+
+
+def test_rebuild_refit_and_oracle_on_a_moving_scene(R):
+    say("rebuild moving")
+    from paper_2210_04449_amd.pipeline import Pipeline
+    dyn = DynamicScene(7, n_prims=30, detail="low")
+    nc, nf, rays, alpha = 32, 64, 4, 0.9
+    beta, d = np.float32(0.5 / nc), np.float32(2.0 / nc)
+    m0 = dyn.mesh(0)
+    mk = lambda rb: Pipeline(cu(m0.vertices), cu(m0.faces), nc, nf, float(beta), float(d), rays,  # noqa: E731
+                             scene_id=9, alpha=alpha, rebuild=rb)
+    refit, rebuilt = mk(False), mk(True)
+    # a rebuilt scene whose later frames only refit its own tree
+    refit_of_rebuilt = mk(True)
+    refit_of_rebuilt.rebuild = False
+    st = oracle.TraceState(nf)
+    for f in range(6):
+        m = dyn.mesh(f)
+        for p in (refit, rebuilt, refit_of_rebuilt):
+            p.set_vertices(cu(m.vertices))
+            p.step(f)
+        ref = oracle.run_frames(m.vertices, m.faces, nc, nf, beta, d, rays, [f], seed=0, scene=9, alpha=alpha,
+                                state=st)
+    torch.cuda.synchronize()
+    assert R.rtsdf_sync_status() == 0
+    assert same(refit, rebuilt) and same(refit, refit_of_rebuilt)
+    from test_gpu_parity import compare_trace
+    print(compare_trace(rebuilt, ref))
+
+
+def test_rebuild_refusals(R):
+    say("rebuild refusals")
+    from synth.scenes import rigid_parts
+    w = workload("tiny")
+    sc = R.Scene(cu(w.mesh.vertices), cu(w.mesh.faces))
+    with pytest.raises(R.RtsdfError):
+        sc.rebuild(cu(w.mesh.vertices))  # not enabled
+    sc.enable_rebuild()
+    sc.enable_rebuild()  # a second call keeps the buffers
+    sc.rebuild(cu(w.mesh.vertices))
+    torch.cuda.synchronize()
+    sc.close()
+    v, f, offs, T = rigid_parts()
+    ps = R.Scene.instanced(cu(v), cu(f), offs, cu(T))
+    with pytest.raises(R.RtsdfError):
+        ps.enable_rebuild()
+    ps.close()
+    empty = R.Scene(torch.zeros((3, 3), device="cuda"), torch.zeros((0, 3), dtype=torch.int32, device="cuda"))
+    with pytest.raises(R.RtsdfError):
+        empty.enable_rebuild()  # no reference: nothing to rebuild
+    empty.close()
