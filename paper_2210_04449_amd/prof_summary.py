@@ -98,7 +98,24 @@ def pmc(paths: list[str]) -> str:
             if c in scale:
                 line += f"  -> {mean * 1024.0 * scale[c] / 1e6:.2f} MB"
             out.append(line)
+        out.extend(derived(cs))
     return "\n".join(out)
+
+
+def derived(cs) -> list[str]:
+    """Ratios of the counters of one kernel (means per dispatch): L2 hit rate, the share of VALU instruction
+    slots' lanes that were active, VALU instructions per wavefront, SALU per VALU instruction."""
+    m = {c: sum(v) / len(v) for c, v in cs.items()}
+    out = []
+    if m.get("TCC_HIT_sum", 0) + m.get("TCC_MISS_sum", 0) > 0:
+        out.append(f"  derived L2 hit rate {m['TCC_HIT_sum'] / (m['TCC_HIT_sum'] + m['TCC_MISS_sum']):.3f}")
+    if m.get("SQ_ACTIVE_INST_VALU", 0) > 0 and "SQ_THREAD_CYCLES_VALU" in m:
+        out.append(f"  derived VALU active-lane fraction {m['SQ_THREAD_CYCLES_VALU'] / (64 * m['SQ_ACTIVE_INST_VALU']):.3f}")
+    if m.get("SQ_WAVES", 0) > 0 and "SQ_INSTS_VALU" in m:
+        out.append(f"  derived VALU instructions per wavefront {m['SQ_INSTS_VALU'] / m['SQ_WAVES']:.0f}")
+    if m.get("SQ_INSTS_VALU", 0) > 0 and "SQ_INSTS_SALU" in m:
+        out.append(f"  derived SALU per VALU instruction {m['SQ_INSTS_SALU'] / m['SQ_INSTS_VALU']:.3f}")
+    return out
 
 
 def main(argv):
