@@ -227,6 +227,18 @@ int rtsdf_scene_create(const float *vertices, int32_t nv, const int32_t *faces, 
 int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsdf_stream stream);
 int rtsdf_scene_info_get(const rtsdf_scene *scene, rtsdf_scene_info *info);
 
+/* Copy of a single-level scene's hierarchy to host memory (for inspection   */
+/* and tests).  Node 0 is the root; node i has two child slots s = 0, 1:     */
+/* boxes[i][s] = (lo x, lo y, lo z, hi x, hi y, hi z) (float32 [cap][2][6]), */
+/* links[i][s] = (j, 0) for internal node j, or (-1 - first, count) for a    */
+/* leaf holding references [first, first + count) of the scene's reference  */
+/* order (int32 [cap][2][2]; count 0 marks the empty second slot of a        */
+/* one-reference scene), parents[i] the parent node, -1 for the root (int32 */
+/* [cap], may be NULL).  All three are host buffers; synchronises `stream`.  */
+/* EINVAL for two-level scenes or cap < rtsdf_scene_info.nodes.             */
+int rtsdf_scene_hierarchy(const rtsdf_scene *scene, int32_t cap, float *boxes, int32_t *links, int32_t *parents,
+                          rtsdf_stream stream);
+
 /* Rebuilding the hierarchy on the device (for geometry that moves far from  */
 /* where it was built, which a refit only loosens).  enable_rebuild          */
 /* allocates the rebuild buffers (it allocates, like create, and             */

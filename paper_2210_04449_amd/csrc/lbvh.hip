@@ -20,7 +20,16 @@
 //      lengths of its neighbours and splits where the prefix changes; one
 //      reference per leaf; node 0 is the root;
 //   5. boxes bottom-up: one thread per leaf climbs, the second thread to
-//      arrive at a node writes its two child boxes and goes on;
+//      arrive at a node writes its two child boxes and goes on.  A node's
+//      leaves are a contiguous run of the sorted order, so the climb runs in
+//      two passes: workgroups of kChunk threads own kChunk consecutive leaves
+//      and finish every node whose run lies inside their chunk (counters and
+//      boxes in LDS, workgroup-scope ordering); the few nodes whose run
+//      crosses a chunk border are finished by a single workgroup from a queue
+//      of the children the first pass completed.  No pass needs ordering
+//      across workgroups, which on this GPU costs an L2 write-back and
+//      invalidate per fence (the eight L2 caches are not coherent with each
+//      other within a kernel);
 //   6. the triangle records and affine maps in leaf order.
 // The tree depth is at most 30 + ceil(log2 n) (each level consumes one bit of
 // the distinct 30-bit code + position key), which sizes the traversal stack.
@@ -125,7 +134,7 @@ __device__ __forceinline__ int lbvh_delta(const uint32_t *__restrict__ code, int
 
 // step 4: internal node i of the radix tree over n sorted keys
 __global__ void __launch_bounds__(256) lbvh_internal(const uint32_t *__restrict__ code, int n, BvhNode *nodes,
-                                                     int32_t *__restrict__ leaf_parent)
+                                                     int32_t *__restrict__ leaf_parent, int2 *__restrict__ range)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
@@ -145,6 +154,7 @@ __global__ void __launch_bounds__(256) lbvh_internal(const uint32_t *__restrict_
     }
     const int gamma = i + s * d + min(d, 0);
     const int lo = min(i, j), hi = max(i, j);
+    range[i] = make_int2(lo, hi);
     const bool left_leaf = lo == gamma, right_leaf = hi == gamma + 1;
     BvhNode &nd = nodes[i];
     const int c0 = left_leaf ? leaf_code(gamma, 1) : gamma;
@@ -159,41 +169,116 @@ __global__ void __launch_bounds__(256) lbvh_internal(const uint32_t *__restrict_
     if (i == 0) nd.meta.z = -1;
 }
 
-// step 5: boxes bottom-up; leaf k holds the reference sorted to position k (ids[k])
-__global__ void __launch_bounds__(256) lbvh_boxes(BvhNode *nodes, const int32_t *__restrict__ leaf_parent,
-                                                  const int32_t *__restrict__ ids, const float *__restrict__ box,
-                                                  int n, int32_t *counter)
+// step 5, first pass.  Workgroup b owns leaves [c0, c1) = [b kChunk, min(n, (b + 1) kChunk)); an internal
+// node whose leaf run [lo, hi] lies inside the chunk has its index in [c0, c1) (a node's index is one end of
+// its run), which addresses its counter and box in LDS.  A climb that reaches a node whose run crosses the
+// chunk border stops and queues the child it finished.
+constexpr int kChunk = 1024;
+
+__device__ __forceinline__ void leaf_ref_box(const float *__restrict__ box, const int32_t *__restrict__ ids, int k,
+                                             float lo[3], float hi[3])
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const float *b = box + 6 * ids[k];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = b[a];
+        hi[a] = b[3 + a];
+    }
+}
+
+__global__ void __launch_bounds__(kChunk) lbvh_boxes_local(BvhNode *nodes, const int32_t *__restrict__ leaf_parent,
+                                                          const int2 *__restrict__ range,
+                                                          const int32_t *__restrict__ ids,
+                                                          const float *__restrict__ box, int n,
+                                                          int32_t *__restrict__ counter, int32_t *__restrict__ queue,
+                                                          int32_t *qcount)
+{
+    __shared__ int cnt[kChunk];
+    __shared__ float lbox[6][kChunk];
+    const int c0 = blockIdx.x * kChunk, c1 = min(n, c0 + kChunk);
+    const int t = threadIdx.x, k = c0 + t;
+    cnt[t] = 0;
+    if (k < n - 1) counter[k] = 0;  // the second pass's counters, one per internal node
+    __syncthreads();
     if (k >= n) return;
+    float lo[3], hi[3];
+    leaf_ref_box(box, ids, k, lo, hi);
+    int child = leaf_code(k, 1);
     int node = leaf_parent[k];
     while (node >= 0) {
-        __threadfence();
-        if (atomicAdd(&counter[node], 1) == 0) return;  // the other child is not done; its thread goes on
-        __threadfence();
+        const int2 r = range[node];
+        if (r.x < c0 || r.y >= c1) {
+            queue[atomicAdd(qcount, 1)] = child;
+            return;
+        }
+        // publish the finished child's box (an internal child's: in LDS), then arrive
+        if (child >= 0)
+            for (int a = 0; a < 3; ++a) {
+                lbox[a][child - c0] = lo[a];
+                lbox[3 + a][child - c0] = hi[a];
+            }
+        if (__hip_atomic_fetch_add(&cnt[node - c0], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+            return;  // the sibling's thread is still climbing; it goes on from here
         BvhNode *nd = &nodes[node];
         const int c[2] = {nd->meta.x, nd->meta.y};
+        const float own_lo[3] = {lo[0], lo[1], lo[2]}, own_hi[3] = {hi[0], hi[1], hi[2]};
         for (int s = 0; s < 2; ++s) {
-            float lo[3], hi[3];
-            if (c[s] < 0) {
-                const float *b = box + 6 * ids[leaf_first(c[s])];
-                for (int a = 0; a < 3; ++a) {
-                    lo[a] = b[a];
-                    hi[a] = b[3 + a];
-                }
+            float l[3], h[3];
+            if (c[s] == child) {
+                for (int a = 0; a < 3; ++a) l[a] = own_lo[a], h[a] = own_hi[a];
+            } else if (c[s] < 0) {
+                leaf_ref_box(box, ids, leaf_first(c[s]), l, h);
             } else {
-                const BvhNode *ch = &nodes[c[s]];
-                float l2[3], h2[3];
-                get_slot(ch, 0, lo, hi);
-                get_slot(ch, 1, l2, h2);
                 for (int a = 0; a < 3; ++a) {
-                    lo[a] = fminf(lo[a], l2[a]);
-                    hi[a] = fmaxf(hi[a], h2[a]);
+                    l[a] = lbox[a][c[s] - c0];
+                    h[a] = lbox[3 + a][c[s] - c0];
                 }
             }
-            set_slot(nd, s, lo, hi);
+            set_slot(nd, s, l, h);
+            if (c[s] != child)
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = fminf(lo[a], l[a]);
+                    hi[a] = fmaxf(hi[a], h[a]);
+                }
         }
+        child = node;
         node = nd->meta.z;
+    }
+}
+
+// step 5, second pass: one workgroup climbs from the queued children through the nodes that cross chunk
+// borders (their counters were cleared by the first pass); all of its ordering is within the workgroup
+__global__ void __launch_bounds__(1024) lbvh_boxes_top(BvhNode *nodes, const int32_t *__restrict__ leaf_parent,
+                                                      const int32_t *__restrict__ ids, const float *__restrict__ box,
+                                                      int32_t *counter, const int32_t *__restrict__ queue,
+                                                      const int32_t *__restrict__ qcount)
+{
+    const int nq = *qcount;
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+        const int first = queue[q];
+        int node = first < 0 ? leaf_parent[leaf_first(first)] : nodes[first].meta.z;
+        while (node >= 0) {
+            if (__hip_atomic_fetch_add(&counter[node], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+                break;  // the other child is not done; its thread goes on
+            BvhNode *nd = &nodes[node];
+            const int c[2] = {nd->meta.x, nd->meta.y};
+            for (int s = 0; s < 2; ++s) {
+                float lo[3], hi[3];
+                if (c[s] < 0) {
+                    leaf_ref_box(box, ids, leaf_first(c[s]), lo, hi);
+                } else {
+                    const BvhNode *ch = &nodes[c[s]];
+                    float l2[3], h2[3];
+                    get_slot(ch, 0, lo, hi);
+                    get_slot(ch, 1, l2, h2);
+                    for (int a = 0; a < 3; ++a) {
+                        lo[a] = fminf(lo[a], l2[a]);
+                        hi[a] = fmaxf(hi[a], h2[a]);
+                    }
+                }
+                set_slot(nd, s, lo, hi);
+            }
+            node = nd->meta.z;
+        }
     }
 }
 
@@ -216,11 +301,12 @@ __global__ void __launch_bounds__(256) lbvh_records(const float *__restrict__ v,
     leaf_faces[k] = make_int4(vid[0], vid[1], vid[2], t);
 }
 
-__global__ void lbvh_init_bounds(unsigned *bounds)
+__global__ void lbvh_init_bounds(unsigned *bounds, int32_t *qcount)
 {
     const int k = threadIdx.x;
     if (k < 3) bounds[k] = 0xffffffffu;
     else if (k < 6) bounds[k] = 0u;
+    else if (k == 6) *qcount = 0;
 }
 
 }  // namespace rtsdf
@@ -233,6 +319,8 @@ struct rtsdf_lbvh {
     uint32_t *code = nullptr, *code_sorted = nullptr;  // [nref]
     int32_t *id = nullptr, *id_sorted = nullptr;       // [nref]
     int32_t *leaf_parent = nullptr;                    // [nref]
+    int2 *range = nullptr;                             // [nref - 1] leaf run of each internal node
+    int32_t *queue = nullptr, *qcount = nullptr;       // [nref], [1] children handed to the top pass
     void *sort_tmp = nullptr;
     size_t sort_bytes = 0;
 };
@@ -241,7 +329,8 @@ static void lbvh_free(rtsdf_lbvh *L)
 {
     if (!L) return;
     for (void *p : {(void *)L->ref_tri, (void *)L->ref_path, (void *)L->box, (void *)L->bounds, (void *)L->code,
-                    (void *)L->code_sorted, (void *)L->id, (void *)L->id_sorted, (void *)L->leaf_parent, L->sort_tmp})
+                    (void *)L->code_sorted, (void *)L->id, (void *)L->id_sorted, (void *)L->leaf_parent, (void *)L->range, (void *)L->queue,
+                    (void *)L->qcount, L->sort_tmp})
         (void)hipFree(p);
     delete L;
 }
@@ -254,7 +343,7 @@ static int lbvh_run(rtsdf_scene *sc, bool rebuild, hipStream_t s)
     rtsdf_lbvh *L = sc->lbvh;
     const int n = sc->nref;
     const unsigned blocks = (unsigned)((n + 255) / 256);
-    lbvh_init_bounds<<<dim3(1), dim3(64), 0, s>>>(L->bounds);
+    lbvh_init_bounds<<<dim3(1), dim3(64), 0, s>>>(L->bounds, L->qcount);
     RTSDF_CHECK_LAUNCH();
     lbvh_ref_boxes<<<dim3(blocks), dim3(256), 0, s>>>(sc->vertices, sc->faces, L->ref_tri, L->ref_path, n, sc->pad,
                                                        L->box, L->bounds);
@@ -267,7 +356,7 @@ static int lbvh_run(rtsdf_scene *sc, bool rebuild, hipStream_t s)
                                                30, s) != hipSuccess)
             return RTSDF_EHIP;
         lbvh_internal<<<dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s>>>(L->code_sorted, n, sc->nodes,
-                                                                                  L->leaf_parent);
+                                                                                  L->leaf_parent, L->range);
         RTSDF_CHECK_LAUNCH();
         lbvh_records<<<dim3(blocks), dim3(256), 0, s>>>(sc->vertices, sc->faces, L->ref_tri, L->ref_path,
                                                          L->id_sorted, n, sc->tris, sc->leaf_faces);
@@ -278,10 +367,11 @@ static int lbvh_run(rtsdf_scene *sc, bool rebuild, hipStream_t s)
     }
     tri_maps<<<dim3(blocks), dim3(256), 0, s>>>(sc->tris, sc->tmap, n);
     RTSDF_CHECK_LAUNCH();
-    int rc = launch_fill<int32_t>(sc->refit_counter, 0, n - 1, s);
-    if (rc != RTSDF_OK) return rc;
-    lbvh_boxes<<<dim3(blocks), dim3(256), 0, s>>>(sc->nodes, L->leaf_parent, L->id_sorted, L->box, n,
-                                                   sc->refit_counter);
+    lbvh_boxes_local<<<dim3((unsigned)((n + kChunk - 1) / kChunk)), dim3(kChunk), 0, s>>>(
+        sc->nodes, L->leaf_parent, L->range, L->id_sorted, L->box, n, sc->refit_counter, L->queue, L->qcount);
+    RTSDF_CHECK_LAUNCH();
+    lbvh_boxes_top<<<dim3(1), dim3(1024), 0, s>>>(sc->nodes, L->leaf_parent, L->id_sorted, L->box,
+                                                   sc->refit_counter, L->queue, L->qcount);
     RTSDF_CHECK_LAUNCH();
     return RTSDF_OK;
 }
@@ -322,7 +412,8 @@ extern "C" int rtsdf_scene_enable_rebuild(rtsdf_scene *sc, rtsdf_stream stream)
               alloc((void **)&L->box, sizeof(float) * 6 * n) && alloc((void **)&L->bounds, sizeof(unsigned) * 6) &&
               alloc((void **)&L->code, sizeof(uint32_t) * n) && alloc((void **)&L->code_sorted, sizeof(uint32_t) * n) &&
               alloc((void **)&L->id, sizeof(int32_t) * n) && alloc((void **)&L->id_sorted, sizeof(int32_t) * n) &&
-              alloc((void **)&L->leaf_parent, sizeof(int32_t) * n) &&
+              alloc((void **)&L->leaf_parent, sizeof(int32_t) * n) && alloc((void **)&L->range, sizeof(int2) * n) &&
+              alloc((void **)&L->queue, sizeof(int32_t) * n) && alloc((void **)&L->qcount, sizeof(int32_t)) &&
               alloc((void **)&nodes, sizeof(BvhNode) * (n - 1)) && alloc((void **)&counter, sizeof(int32_t) * (n - 1));
     if (ok) {
         ok = hipcub::DeviceRadixSort::SortPairs(nullptr, L->sort_bytes, L->code, L->code_sorted, L->id, L->id_sorted,

@@ -716,6 +716,36 @@ extern "C" int rtsdf_scene_info_get(const rtsdf_scene *scene, rtsdf_scene_info *
     return RTSDF_OK;
 }
 
+extern "C" int rtsdf_scene_hierarchy(const rtsdf_scene *scene, int32_t cap, float *boxes, int32_t *links,
+                                     int32_t *parents, rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!scene || scene->ninst > 0 || cap < scene->nnodes || (scene->nnodes > 0 && (!boxes || !links)))
+        return RTSDF_EINVAL;
+    const int n = scene->nnodes;
+    if (n == 0) return RTSDF_OK;
+    std::vector<BvhNode> h(n);
+    hipStream_t s = as_stream(stream);
+    RTSDF_TRY(hipMemcpyAsync(h.data(), scene->nodes, sizeof(BvhNode) * n, hipMemcpyDeviceToHost, s));
+    RTSDF_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i) {
+        const BvhNode &nd = h[i];
+        const float xy[2][4] = {{nd.xy0.x, nd.xy0.y, nd.xy0.z, nd.xy0.w}, {nd.xy1.x, nd.xy1.y, nd.xy1.z, nd.xy1.w}};
+        const float z[4] = {nd.z01.x, nd.z01.y, nd.z01.z, nd.z01.w};
+        const int c[2] = {nd.meta.x, nd.meta.y};
+        for (int sl = 0; sl < 2; ++sl) {
+            float *b = boxes + 12 * (size_t)i + 6 * sl;
+            b[0] = xy[sl][0], b[1] = xy[sl][2], b[2] = z[2 * sl];          // lo x, y, z
+            b[3] = xy[sl][1], b[4] = xy[sl][3], b[5] = z[2 * sl + 1];      // hi x, y, z
+            int32_t *l = links + 4 * (size_t)i + 2 * sl;
+            if (c[sl] >= 0) l[0] = c[sl], l[1] = 0;
+            else l[0] = -1 - leaf_first(c[sl]), l[1] = leaf_count(c[sl]);
+        }
+        if (parents) parents[i] = nd.meta.z;
+    }
+    return RTSDF_OK;
+}
+
 extern "C" void rtsdf_scene_destroy(rtsdf_scene *scene)
 {
     if (!scene) return;

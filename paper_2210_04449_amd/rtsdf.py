@@ -108,6 +108,7 @@ def _load():
         "rtsdf_scene_create": ([_P, _i32, _P, _i32, _i32, C.POINTER(_P), _P], _i32),
         "rtsdf_scene_refit": ([_P, _P, _P], _i32),
         "rtsdf_scene_info_get": ([_P, C.POINTER(SceneInfo)], _i32),
+        "rtsdf_scene_hierarchy": ([_P, _i32, _P, _P, _P, _P], _i32),
         "rtsdf_scene_destroy": ([_P], None),
         "rtsdf_accum_reset": ([Grid, Accum, _P], _i32),
         "rtsdf_trace_workspace_size": ([], _sz),
@@ -312,6 +313,19 @@ class Scene:
         inf = SceneInfo()
         _check("rtsdf_scene_info_get", _lib.rtsdf_scene_info_get(self.handle, C.byref(inf)))
         return inf
+
+    def hierarchy(self, stream=None):
+        """Host copy of the hierarchy: boxes float32 [nodes, 2, 6] (lo xyz, hi xyz per child slot), links int32
+        [nodes, 2, 2] ((j, 0) internal child j, (-1 - first, count) leaf), parents int32 [nodes]."""
+        import numpy as np
+        n = self.info().nodes
+        boxes = np.zeros((max(n, 1), 2, 6), np.float32)
+        links = np.zeros((max(n, 1), 2, 2), np.int32)
+        parents = np.zeros(max(n, 1), np.int32)
+        _check("rtsdf_scene_hierarchy", _lib.rtsdf_scene_hierarchy(
+            self.handle, n, boxes.ctypes.data_as(_P), links.ctypes.data_as(_P), parents.ctypes.data_as(_P),
+            _stream(stream)))
+        return boxes[:n], links[:n], parents[:n]
 
     def close(self):
         if getattr(self, "handle", None):

@@ -120,3 +120,83 @@ def test_rebuild_refusals(R):
     with pytest.raises(R.RtsdfError):
         empty.enable_rebuild()  # no reference: nothing to rebuild
     empty.close()
+
+
+def check_tree(boxes, links, parents, nref):
+    """A valid binary tree over references 0..nref-1 whose every internal slot is exactly the union of that
+    child's two slots (tight boxes, not only conservative ones). Returns the leaf slots' boxes by reference."""
+    n = len(parents)
+    assert parents[0] == -1
+    internal = links[:, :, 0] >= 0
+    child = np.where(internal, links[:, :, 0], 0)
+    # every node other than the root is the child of exactly one slot, and its parent link names that node
+    seen = np.zeros(n, np.int64)
+    np.add.at(seen, child[internal], 1)
+    assert seen[0] == 0 and (seen[1:] == 1).all()
+    owner = np.repeat(np.arange(n), 2).reshape(n, 2)
+    assert (parents[child[internal]] == owner[internal]).all()
+    # internal slots: union of the child's slots
+    kids = boxes[child]                                      # [n, 2, 2, 6]
+    union = np.concatenate([kids[..., :3].min(axis=2), kids[..., 3:].max(axis=2)], axis=-1)
+    assert np.array_equal(boxes[internal], union[internal])
+    # leaves: each reference in exactly one leaf
+    leaf = ~internal & (links[:, :, 1] > 0)
+    first, cnt = -1 - links[:, :, 0][leaf], links[:, :, 1][leaf]
+    cover = np.zeros(nref, np.int64)
+    for fi, c in zip(first, cnt):
+        cover[fi:fi + c] += 1
+    assert (cover == 1).all()
+    return first, cnt, boxes[leaf]
+
+
+def sub_multiset(a, b):
+    """Every row of a occurs in b at least as often as in a (rows compared bit for bit)."""
+    view = lambda x: np.ascontiguousarray(x).view(np.dtype((np.void, x.dtype.itemsize * x.shape[1]))).ravel()  # noqa: E731
+    ua, ca = np.unique(view(a), return_counts=True)
+    ub, cb = np.unique(view(b), return_counts=True)
+    pos = np.searchsorted(ub, ua)
+    pos = np.minimum(pos, len(ub) - 1)
+    return bool((ub[pos] == ua).all() and (cb[pos] >= ca).all())
+
+
+@pytest.mark.parametrize("case", ["moving", "room"])
+def test_rebuilt_boxes_are_exact(R, case):
+    """The rebuilt tree (several chunks of the two-pass box climb, and the pass across chunks) against a
+    host-built tree of one reference per leaf refitted on the device: same reference boxes, both trees tight."""
+    say("rebuild boxes", case)
+    if case == "moving":
+        dyn = DynamicScene(7, n_prims=30, detail="low")
+        meshes = [dyn.mesh(0), dyn.mesh(3)]
+    else:
+        meshes = [workload("room").mesh]
+    v0, faces = cu(meshes[0].vertices), cu(meshes[0].faces)
+    host = R.Scene(v0, faces, leaf_size=1)
+    dev = R.Scene(v0, faces)
+    dev.enable_rebuild()
+    nref = dev.info().references
+    assert host.info().references == nref and nref > 4 * 1024
+    for i, m in enumerate(meshes):
+        v = cu(m.vertices)
+        host.refit(v)
+        dev.rebuild(v)
+        torch.cuda.synchronize()
+        assert R.rtsdf_sync_status() == 0
+        hb, hl, hp = host.hierarchy()
+        db, dl, dp = dev.hierarchy()
+        assert len(db) == nref - 1
+        _, hc, hleaf = check_tree(hb, hl, hp, nref)
+        _, dc, dleaf = check_tree(db, dl, dp, nref)
+        assert (dc == 1).all() and (hc == 1).sum() >= 1000  # the host SAH also makes two-reference leaves
+        # the same reference boxes (the references are the same, in another order): the host tree's
+        # one-reference leaves are among the rebuilt tree's leaves, and both roots bound the same set
+        assert sub_multiset(hleaf[hc == 1], dleaf), i
+        root = lambda b: np.concatenate([b[0, :, :3].min(axis=0), b[0, :, 3:].max(axis=0)])  # noqa: E731
+        assert np.array_equal(root(hb), root(db)), i
+        if i == 0:
+            # a refit of the rebuilt tree keeps its topology and its boxes
+            dev.refit(v)
+            torch.cuda.synchronize()
+            rb, rl, rp = dev.hierarchy()
+            assert np.array_equal(rl, dl) and np.array_equal(rp, dp) and np.array_equal(rb, db)
+    host.close()
+    dev.close()
