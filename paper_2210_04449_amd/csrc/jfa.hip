@@ -13,15 +13,18 @@
 // x | y << 8 | z << 16 (0xFFFFFFFF = none); packed order equals linear-index
 // order, so ties compare the packed word directly.
 //
-// Candidate key: the 64-bit word (D^2 << 32 | packed seed), read as a float64.
-// Its exponent field is zero (D^2 < 2^20), so it is a non-negative denormal
-// whose order is the integer order, and one v_min_f64 keeps the better of two
-// keys.  A missing seed gets bits 0x7F000000 in the high word (a large finite
-// double) and always loses.  D^2 itself is formed with byte/short dot
-// products: for n <= 128 the three 7-bit coordinate differences fit signed
-// bytes, ((P + 128) - S) ^ 0x808080 per byte, and one v_dot4_i32_i8 squares and
-// sums them; for n = 256 x and y go through packed 16-bit lanes and
-// v_dot2_i32_i16, z separately.
+// Candidate key: the 64-bit word (D^2 << 32 | low), read as a float64, where
+// low increases with the packed seed.  Its exponent field is zero (D^2 <
+// 2^20), so it is a non-negative denormal whose order is the integer order,
+// and one v_min_f64 keeps the better of two keys.  A missing seed gets bits
+// 0x7F000000 in the high word (a large finite double) and always loses.  D^2
+// itself is formed with byte/short dot products: for n <= 128 the voxel
+// constant C holds 128 - x, 128 - y, 128 - z in its bytes, so u = S + C holds
+// (s - x) + 128 etc. in [1, 255] per byte without carries: u is the key's low
+// word (S = u - C), u ^ 0x808080 the signed byte differences, and one
+// v_dot4_i32_i8 squares and sums them; for n = 256 the low word is the seed
+// itself, x and y go through packed 16-bit lanes and v_dot2_i32_i16, z
+// separately.
 //
 // Steps k >= 4 read whole neighbour bricks straight from global memory (an
 // out-of-grid neighbour reads a constant all-empty brick, chosen with a scalar
@@ -42,8 +45,8 @@ __device__ int32_t g_empty_brick[64] = {
 
 typedef short jfa_short2 __attribute__((ext_vector_type(2)));
 
-// Voxel-side constant for the distance: 7-bit path: biased packed position;
-// 8-bit path: x | y << 16 (low word) and z (high word).
+// Voxel-side constant for the distance: 7-bit path: C = (128 - x) | (128 - y)
+// << 8 | (128 - z) << 16; 8-bit path: x | y << 16 (low word) and z (high word).
 struct JfaPos {
     uint32_t a, b;
 };
@@ -53,7 +56,7 @@ __device__ __forceinline__ JfaPos jfa_pos(int x, int y, int z)
 {
     JfaPos p;
     if (!WIDE) {
-        p.a = (uint32_t)(x + 128) | ((uint32_t)(y + 128) << 8) | ((uint32_t)(z + 128) << 16);
+        p.a = (uint32_t)(128 - x) | ((uint32_t)(128 - y) << 8) | ((uint32_t)(128 - z) << 16);
         p.b = 0;
     } else {
         p.a = (uint32_t)x | ((uint32_t)y << 16);
@@ -65,22 +68,32 @@ __device__ __forceinline__ JfaPos jfa_pos(int x, int y, int z)
 template <bool WIDE>
 __device__ __forceinline__ double jfa_key(JfaPos p, uint32_t s)
 {
-    int d2;
+    uint32_t low = s, hi;
     if (!WIDE) {
-        const int d = (int)((p.a - s) ^ 0x00808080u);
-        d2 = __builtin_amdgcn_sdot4(d, d, 0, false);
+        low = s + p.a;
+        const int d = (int)(low ^ 0x00808080u);
+        // the missing-seed bits have zero low 24 bits and D^2 < 2^24, so adding them is or-ing them
+        hi = (uint32_t)__builtin_amdgcn_sdot4(d, d, (int)(s & 0x7F000000u), false);
     } else {
         const jfa_short2 sxy = __builtin_bit_cast(jfa_short2, __builtin_amdgcn_perm(0u, s, 0x0C010C00u));
         const jfa_short2 dxy = __builtin_bit_cast(jfa_short2, p.a) - sxy;
         const int dz = (int)p.b - (int)((s >> 16) & 0xFFu);
-        d2 = __builtin_amdgcn_sdot2(dxy, dxy, dz * dz, false);
+        // |dz| < 2^8: a 24-bit multiply-add (full rate, unlike the 32-bit multiply) into the accumulator
+        hi = (uint32_t)__builtin_amdgcn_sdot2(dxy, dxy, (int)(s & 0x7F000000u) + __mul24(dz, dz), false);
     }
-    const uint32_t hi = (s & 0x7F000000u) | (uint32_t)d2;
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)s);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)low);
 }
 
-__device__ __forceinline__ uint32_t key_seed(double k) { return (uint32_t)__builtin_bit_cast(uint64_t, k); }
 __device__ __forceinline__ uint32_t key_d2(double k) { return (uint32_t)(__builtin_bit_cast(uint64_t, k) >> 32); }
+
+// the packed seed of the best key (kNoSeed if no candidate had one)
+template <bool WIDE>
+__device__ __forceinline__ uint32_t key_seed(JfaPos p, double k)
+{
+    if (key_d2(k) >= 0x7F000000u) return kNoSeed;
+    const uint32_t low = (uint32_t)__builtin_bit_cast(uint64_t, k);
+    return WIDE ? low : low - p.a;
+}
 
 __device__ __forceinline__ uint32_t pack_linear(int32_t s, int logn)
 {
@@ -129,32 +142,48 @@ template <bool WIDE, bool LINEAR_IN>
 __device__ __forceinline__ void jfa_far_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
                                              int logn, int kb, uint32_t blk, uint32_t nblk)
 {
-    const int B = n >> 2;
+    // n is a power of two, so brick coordinates are bit fields of the brick index, and a neighbour brick's
+    // index is the own one plus one stride per axis (all wave-uniform, kept in scalar registers).  An axis
+    // offset that would leave the grid is replaced by 0: the brick read is then the candidate whose offset on
+    // that axis is 0, which the set already holds, and a duplicate cannot change the minimum.  So every read
+    // is in the grid and needs no select.
+    const int logB = logn - 2, B = 1 << logB;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int b = (int)xcd_remap(blk, nblk) * 4 + wave;
-    const int bx = b % B, by = (b / B) % B, bz = b / (B * B);
+    const int bx = b & (B - 1), by = (b >> logB) & (B - 1), bz = b >> (2 * logB);
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
     const JfaPos P = jfa_pos<WIDE>(bx * 4 + lx, by * 4 + ly, bz * 4 + lz);
     double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
     uint32_t cand[27];
+    if (!LINEAR_IN) {
+        const int sy = kb << logB, sz = kb << (2 * logB);
+        const int dx[3] = {bx >= kb ? -kb : 0, 0, bx + kb < B ? kb : 0};
+        const int dy[3] = {by >= kb ? -sy : 0, 0, by + kb < B ? sy : 0};
+        const int dz[3] = {bz >= kb ? -sz : 0, 0, bz + kb < B ? sz : 0};
+        // raw buffer loads: the lane's byte offset is one vector register shared by all 27 reads, the brick's
+        // byte offset a scalar (every read lies in the n^3-word buffer; gfx9 descriptor word 3)
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(src), (short)0, (n * n * n) * 4, 0x00020000);
 #pragma unroll
-    for (int o = 0; o < 27; ++o) {
-        const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-        const int nx = bx + ox * kb, ny = by + oy * kb, nz = bz + oz * kb;
-        const bool valid = nx >= 0 && ny >= 0 && nz >= 0 && nx < B && ny < B && nz < B;
-        if (!LINEAR_IN) {
-            const int32_t *p = valid ? src + (int64_t)(nx + B * (ny + B * nz)) * 64 : g_empty_brick;
-            cand[o] = (uint32_t)p[lane];
-        } else {
-            const int x = nx * 4 + lx, y = ny * 4 + ly, z = nz * 4 + lz;
-            const int32_t *p = valid ? src + (x + n * (y + n * z)) : g_empty_brick;
-            cand[o] = pack_linear(p[0], logn);
+        for (int o = 0; o < 27; ++o) {
+            const int off = (b + dx[o % 3] + dy[(o / 3) % 3] + dz[o / 9]) << 8;
+            cand[o] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, lane * 4, off, 0);
+        }
+    } else {
+        const int dx[3] = {bx >= kb ? -kb : 0, 0, bx + kb < B ? kb : 0};
+        const int dy[3] = {by >= kb ? -kb : 0, 0, by + kb < B ? kb : 0};
+        const int dz[3] = {bz >= kb ? -kb : 0, 0, bz + kb < B ? kb : 0};
+#pragma unroll
+        for (int o = 0; o < 27; ++o) {
+            const int x = (bx + dx[o % 3]) * 4 + lx, y = (by + dy[(o / 3) % 3]) * 4 + ly;
+            const int z = (bz + dz[o / 9]) * 4 + lz;
+            cand[o] = pack_linear(src[x + (y << logn) + (z << (2 * logn))], logn);
         }
     }
 #pragma unroll
     for (int o = 0; o < 27; ++o) best = __builtin_fmin(best, jfa_key<WIDE>(P, cand[o]));
-    dst[(int64_t)b * 64 + lane] = (int32_t)key_seed(best);
+    dst[(int64_t)b * 64 + lane] = (int32_t)key_seed<WIDE>(P, best);
 }
 
 template <bool WIDE, bool LINEAR_IN>
@@ -201,9 +230,9 @@ __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, i
     }
     if (!FINAL) {
         const int b = (x >> 2) + B * ((y >> 2) + B * (z >> 2));
-        dst[(int64_t)b * 64 + (x & 3) + 4 * (y & 3) + 16 * (z & 3)] = (int32_t)key_seed(best);
+        dst[(int64_t)b * 64 + (x & 3) + 4 * (y & 3) + 16 * (z & 3)] = (int32_t)key_seed<WIDE>(P, best);
     } else {
-        const uint32_t s = key_seed(best);
+        const uint32_t s = key_seed<WIDE>(P, best);
         const int64_t idx = x + (int64_t)n * (y + (int64_t)n * z);
         if (s == kNoSeed) {
             dst[idx] = -1;

@@ -226,16 +226,18 @@ __device__ __forceinline__ int tri_id(const float4 *tris, int i)
     return __float_as_int(reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + (uint32_t)i * 48u)->w);
 }
 
-// slab test against a padded box; returns entry distance or +inf on a miss
-__device__ __forceinline__ float box_entry(const RaySetup &R, float lx, float hx, float ly, float hy, float lz, float hz,
-                                           float tbest)
+// slab test against a padded box: whether the ray meets it before tbest (a NaN slab misses), and the entry
+// distance
+__device__ __forceinline__ bool box_hit(const RaySetup &R, float lx, float hx, float ly, float hy, float lz, float hz,
+                                        float tbest, float &t_entry)
 {
     const float x0 = fmaf(lx, R.ix, -R.oix), x1 = fmaf(hx, R.ix, -R.oix);
     const float y0 = fmaf(ly, R.iy, -R.oiy), y1 = fmaf(hy, R.iy, -R.oiy);
     const float z0 = fmaf(lz, R.iz, -R.oiz), z1 = fmaf(hz, R.iz, -R.oiz);
     const float tmin = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
     const float tmax = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tbest));
-    return tmin <= tmax ? tmin : __builtin_inff();
+    t_entry = tmin;
+    return tmin <= tmax;
 }
 
 constexpr int kDone = INT32_MIN;
@@ -260,9 +262,9 @@ __device__ __forceinline__ void trav_step(const BvhView &S, const RaySetup &R, i
         const BvhNode *nd = S.nodes + node;
         const float4 a = nd->xy0, b = nd->xy1, z = nd->z01;
         const int4 m = nd->meta;
-        const float t0 = box_entry(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest);
-        const float t1 = box_entry(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest);
-        const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
+        float t0, t1;
+        const bool h0 = box_hit(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest, t0);
+        const bool h1 = box_hit(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest, t1);
         if (h0 && h1) {
             const bool first0 = t0 <= t1;
             stk[sp * stride] = first0 ? m.y : m.x;
@@ -368,9 +370,9 @@ __device__ __forceinline__ void inner_step(const BvhView &S, int stride, const R
     const BvhNode *nd = node_ptr(S.nodes, node);
     const float4 a = nd->xy0, b = nd->xy1, z = nd->z01;
     const int4 m = nd->meta;
-    const float t0 = box_entry(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest);
-    const float t1 = box_entry(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest);
-    const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
+    float t0, t1;
+    const bool h0 = box_hit(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest, t0);
+    const bool h1 = box_hit(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest, t1);
     if (h0 && h1) {
         const bool first0 = t0 <= t1;
         stack_push<SL>(stride, sp, stk, spill, first0 ? m.y : m.x);
@@ -393,9 +395,9 @@ __device__ __forceinline__ void node_step(const BvhView &S, int stride, const Ra
     const BvhNode *nd = node_ptr(S.nodes, node);
     const float4 a = nd->xy0, b = nd->xy1, z = nd->z01;
     const int4 m = nd->meta;
-    const float t0 = box_entry(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest);
-    const float t1 = box_entry(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest);
-    const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
+    float t0, t1;
+    const bool h0 = box_hit(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest, t0);
+    const bool h1 = box_hit(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest, t1);
     if (h0 && h1) {
         const bool first0 = t0 <= t1;
         const int near = first0 ? m.x : m.y, far = first0 ? m.y : m.x;
@@ -428,9 +430,9 @@ __device__ __forceinline__ void node_step_regs(const RaySetup &R, float4 a, floa
                                                float tbest, int &tri_cur, int &tri_end, bool &push, int &push_val,
                                                bool &pop)
 {
-    const float t0 = box_entry(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest);
-    const float t1 = box_entry(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest);
-    const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
+    float t0, t1;
+    const bool h0 = box_hit(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest, t0);
+    const bool h1 = box_hit(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest, t1);
     const bool any = h0 || h1, both = h0 && h1;
     const bool first0 = h0 && (!h1 || t0 <= t1);
     const int near = first0 ? m.x : m.y, far = first0 ? m.y : m.x;
