@@ -110,6 +110,9 @@ def test_host_validation(R):
     bad = (C.c_int32 * 3)(0, 2, 2)  # the moving part 1 has no face
     assert L.rtsdf_scene_create_instanced(dummy, 3, dummy, 2, bad, 2, dummy, 2, C.byref(h), None) == R.EINVAL
     assert L.rtsdf_scene_set_transforms(None, dummy, None, None) == R.EINVAL
+    assert L.rtsdf_scene_hierarchy(None, 10, dummy, dummy, None, None) == R.EINVAL
+    assert L.rtsdf_scene_enable_rebuild(None, None) == R.EINVAL
+    assert L.rtsdf_scene_rebuild(None, dummy, None) == R.EINVAL
     default = R.rtsdf_trace_config_get().as_dict()
     prev = R.rtsdf_trace_config(refill=8, stack_lds=24)
     assert prev.as_dict() == default and R.rtsdf_trace_config_get().refill == 8

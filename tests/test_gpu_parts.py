@@ -146,6 +146,8 @@ def test_parts_bad_input(R):
         R.rtsdf_point_distance(sc, o, t)
     with pytest.raises(R.RtsdfError):
         sc.refit(cu(v))
+    with pytest.raises(R.RtsdfError):
+        sc.hierarchy()  # the export takes single-level scenes
     sc.close()
 
 

@@ -198,5 +198,10 @@ def test_rebuilt_boxes_are_exact(R, case):
             torch.cuda.synchronize()
             rb, rl, rp = dev.hierarchy()
             assert np.array_equal(rl, dl) and np.array_equal(rp, dp) and np.array_equal(rb, db)
+    # a buffer smaller than the hierarchy is refused
+    n = dev.info().nodes
+    buf = np.zeros((n - 1, 2, 6), np.float32)
+    lnk = np.zeros((n - 1, 2, 2), np.int32)
+    assert R._lib.rtsdf_scene_hierarchy(dev.handle, n - 1, buf.ctypes.data, lnk.ctypes.data, None, None) == R.EINVAL
     host.close()
     dev.close()
