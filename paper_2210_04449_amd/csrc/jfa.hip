@@ -202,16 +202,16 @@ __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, i
 {
     constexpr int T = 8 + 2 * K;
     __shared__ uint32_t tile[T * T * T];
-    const int B = n >> 2;
-    const int TB = n >> 3;  // 8^3 blocks per axis
+    // n is a power of two: block and brick coordinates are bit fields (shifts and masks, no divisions)
+    const int logB = logn - 2, logTB = logn - 3, TB = 1 << logTB;  // 8^3 blocks per axis
     const int blk = (int)xcd_remap(blk_id, nblk);
-    const int tx0 = (blk % TB) * 8, ty0 = ((blk / TB) % TB) * 8, tz0 = (blk / (TB * TB)) * 8;
+    const int tx0 = (blk & (TB - 1)) * 8, ty0 = ((blk >> logTB) & (TB - 1)) * 8, tz0 = (blk >> (2 * logTB)) * 8;
     for (int i = threadIdx.x; i < T * T * T; i += blockDim.x) {
         const int x = tx0 - K + i % T, y = ty0 - K + (i / T) % T, z = tz0 - K + i / (T * T);
         uint32_t v = kNoSeed;
-        if (x >= 0 && y >= 0 && z >= 0 && x < n && y < n && z < n) {
-            const int b = (x >> 2) + B * ((y >> 2) + B * (z >> 2));
-            v = (uint32_t)src[(int64_t)b * 64 + (x & 3) + 4 * (y & 3) + 16 * (z & 3)];
+        if ((unsigned)x < (unsigned)n && (unsigned)y < (unsigned)n && (unsigned)z < (unsigned)n) {
+            const int b = (x >> 2) | ((y >> 2) << logB) | ((z >> 2) << (2 * logB));
+            v = (uint32_t)src[(b << 6) | (x & 3) | ((y & 3) << 2) | ((z & 3) << 4)];
         }
         tile[i] = v;
     }
@@ -229,11 +229,11 @@ __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, i
         best = __builtin_fmin(best, jfa_key<WIDE>(P, tile[c + K * (ox + T * (oy + T * oz))]));
     }
     if (!FINAL) {
-        const int b = (x >> 2) + B * ((y >> 2) + B * (z >> 2));
-        dst[(int64_t)b * 64 + (x & 3) + 4 * (y & 3) + 16 * (z & 3)] = (int32_t)key_seed<WIDE>(P, best);
+        const int b = (x >> 2) | ((y >> 2) << logB) | ((z >> 2) << (2 * logB));
+        dst[(b << 6) | (x & 3) | ((y & 3) << 2) | ((z & 3) << 4)] = (int32_t)key_seed<WIDE>(P, best);
     } else {
         const uint32_t s = key_seed<WIDE>(P, best);
-        const int64_t idx = x + (int64_t)n * (y + (int64_t)n * z);
+        const int idx = x | (y << logn) | (z << (2 * logn));  // n <= 256: below 2^24
         if (s == kNoSeed) {
             dst[idx] = -1;
             dist2[idx] = INT32_MAX;
