@@ -27,8 +27,8 @@
 // separately.
 //
 // Steps k >= 4 read whole neighbour bricks straight from global memory (an
-// out-of-grid neighbour reads a constant all-empty brick, chosen with a scalar
-// select).  Steps 2 and 1 stage an (8 + 2k)^3 block of voxels (eight bricks
+// axis offset that would leave the grid reads the brick with offset 0 on that
+// axis, a candidate the set already holds).  Steps 2 and 1 stage an (8 + 2k)^3 block of voxels (eight bricks
 // plus halo) in LDS; candidates then sit at compile-time LDS offsets and
 // out-of-grid halo entries are empty.  The k = 1 pass writes the final seeds,
 // D^2 and c in the caller's linear layout.
@@ -37,11 +37,6 @@
 namespace rtsdf {
 
 constexpr uint32_t kNoSeed = 0xFFFFFFFFu;
-
-__device__ int32_t g_empty_brick[64] = {
-    -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
-    -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
-    -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
 
 typedef short jfa_short2 __attribute__((ext_vector_type(2)));
 
