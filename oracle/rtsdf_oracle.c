@@ -563,11 +563,13 @@ static void tri_bounds(const oracle_scene *s, int t, double lo[3], double hi[3])
     }
 }
 
-static double *g_centroid_axis; /* qsort context (build is single-threaded) */
+static const double *g_centroids; /* qsort context (build is single-threaded): [nt][3] centroids */
+static int g_centroid_axis;        /* and the axis being sorted on */
 
 static int cmp_centroid(const void *a, const void *b)
 {
-    const double x = g_centroid_axis[*(const int *)a], y = g_centroid_axis[*(const int *)b];
+    const double x = g_centroids[3 * *(const int *)a + g_centroid_axis];
+    const double y = g_centroids[3 * *(const int *)b + g_centroid_axis];
     if (x < y) return -1;
     if (x > y) return 1;
     return (*(const int *)a > *(const int *)b) - (*(const int *)a < *(const int *)b);
@@ -614,11 +616,9 @@ static int build_rec(oracle_scene *s, double *cent, int start, int count, int *c
     int axis = 0;
     for (int a = 1; a < 3; ++a)
         if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
-    double *key = (double *)malloc(sizeof(double) * (size_t)s->nt);
-    for (int t = 0; t < s->nt; ++t) key[t] = cent[3 * t + axis];
-    g_centroid_axis = key;
+    g_centroids = cent;
+    g_centroid_axis = axis;
     qsort(&s->perm[start], (size_t)count, sizeof(int), cmp_centroid);
-    free(key);
     const int half = count / 2;
     nd.count = 0;
     s->nodes[id] = nd;
