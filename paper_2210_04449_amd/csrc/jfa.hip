@@ -130,66 +130,59 @@ __global__ void __launch_bounds__(256) jfa_to_bricks(const int32_t *__restrict__
     jfa_to_bricks_body(src, dst, n, logn, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// One pass with step k >= 4 (a multiple of the brick size) for the four
-// bricks of workgroup `blk` of `nblk`.  LINEAR_IN: the source is the caller's
-// linear index array (first pass only).  NC candidates per axis: 3 in general;
-// 2 for the pass with k = n/2 (kb = B/2), where exactly one of the offsets -kb
-// and +kb stays in the grid on every axis, so only 8 of the 27 candidate
-// bricks are distinct (the other 19 repeat one of them, see below).
-template <bool WIDE, bool LINEAR_IN, int NC = 3>
-__device__ __forceinline__ void jfa_far_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
-                                             int logn, int kb, uint32_t blk, uint32_t nblk)
+// The distinct offsets along one axis of a pass with step k = 4 kb >= 4 (brick coordinate c, in units of
+// the stride st).  An offset that would leave the grid is replaced by 0: the brick read is then the candidate
+// whose offset on that axis is 0, which the set already holds, and a duplicate cannot change the minimum.  So
+// an axis where one side leaves the grid (at most one can, unless kb = B/2, where exactly one does) has two
+// distinct offsets, {0, the side that stays}, and an axis where neither does has three.
+template <int N>
+__device__ __forceinline__ void jfa_axis(int c, int kb, int st, int (&d)[N])
 {
-    // n is a power of two, so brick coordinates are bit fields of the brick index, and a neighbour brick's
-    // index is the own one plus one stride per axis (all wave-uniform, kept in scalar registers).  An axis
-    // offset that would leave the grid is replaced by 0: the brick read is then the candidate whose offset on
-    // that axis is 0, which the set already holds, and a duplicate cannot change the minimum.  So every read
-    // is in the grid and needs no select.
-    static_assert(NC == 2 || NC == 3, "candidates per axis");
-    constexpr int NCAND = NC * NC * NC;
+    if (N == 3) {
+        d[0] = -st;
+        d[1] = 0;
+        d[N - 1] = st;
+    } else {
+        d[0] = 0;
+        d[N - 1] = c >= kb ? -st : st;
+    }
+}
+
+// The candidates of brick b: NX * NY * NZ distinct neighbour bricks, every read in the grid.
+template <bool WIDE, bool LINEAR_IN, int NX, int NY, int NZ>
+__device__ __forceinline__ void jfa_far_brick(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                              int logn, int kb, int b, int lane)
+{
+    constexpr int NCAND = NX * NY * NZ;
     const int logB = logn - 2, B = 1 << logB;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int b = (int)xcd_remap(blk, nblk) * 4 + wave;
     const int bx = b & (B - 1), by = (b >> logB) & (B - 1), bz = b >> (2 * logB);
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
     const JfaPos P = jfa_pos<WIDE>(bx * 4 + lx, by * 4 + ly, bz * 4 + lz);
-    // the distinct offsets along one axis (brick coordinate c), each a multiple of the stride st
-    auto axis = [&](int c, int st, int (&d)[NC]) {
-        if (NC == 3) {
-            d[0] = c >= kb ? -st : 0;
-            d[1] = 0;
-            d[NC - 1] = c + kb < B ? st : 0;
-        } else {
-            d[0] = 0;
-            d[NC - 1] = c >= kb ? -st : st;  // kb = B/2: -kb leaves the grid iff +kb stays in it
-        }
-    };
     double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
     uint32_t cand[NCAND];
     if (!LINEAR_IN) {
-        int dx[NC], dy[NC], dz[NC];
-        axis(bx, kb, dx);
-        axis(by, kb << logB, dy);
-        axis(bz, kb << (2 * logB), dz);
+        int dx[NX], dy[NY], dz[NZ];
+        jfa_axis(bx, kb, kb, dx);
+        jfa_axis(by, kb, kb << logB, dy);
+        jfa_axis(bz, kb, kb << (2 * logB), dz);
         // raw buffer loads: the lane's byte offset is one vector register shared by all the reads, the brick's
         // byte offset a scalar (every read lies in the n^3-word buffer; gfx9 descriptor word 3)
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(src), (short)0, (n * n * n) * 4, 0x00020000);
 #pragma unroll
         for (int o = 0; o < NCAND; ++o) {
-            const int off = (b + dx[o % NC] + dy[(o / NC) % NC] + dz[o / (NC * NC)]) << 8;
+            const int off = (b + dx[o % NX] + dy[(o / NX) % NY] + dz[o / (NX * NY)]) << 8;
             cand[o] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, lane * 4, off, 0);
         }
     } else {
-        int dx[NC], dy[NC], dz[NC];
-        axis(bx, kb, dx);
-        axis(by, kb, dy);
-        axis(bz, kb, dz);
+        int dx[NX], dy[NY], dz[NZ];
+        jfa_axis(bx, kb, kb, dx);
+        jfa_axis(by, kb, kb, dy);
+        jfa_axis(bz, kb, kb, dz);
 #pragma unroll
         for (int o = 0; o < NCAND; ++o) {
-            const int x = (bx + dx[o % NC]) * 4 + lx, y = (by + dy[(o / NC) % NC]) * 4 + ly;
-            const int z = (bz + dz[o / (NC * NC)]) * 4 + lz;
+            const int x = (bx + dx[o % NX]) * 4 + lx, y = (by + dy[(o / NX) % NY]) * 4 + ly;
+            const int z = (bz + dz[o / (NX * NY)]) * 4 + lz;
             cand[o] = pack_linear(src[x + (y << logn) + (z << (2 * logn))], logn);
         }
     }
@@ -198,11 +191,38 @@ __device__ __forceinline__ void jfa_far_body(const int32_t *__restrict__ src, in
     dst[(int64_t)b * 64 + lane] = (int32_t)key_seed<WIDE>(P, best);
 }
 
-template <bool WIDE, bool LINEAR_IN, int NC>
+// One pass with step k >= 4 (a multiple of the brick size) for the four
+// bricks of workgroup `blk` of `nblk`.  LINEAR_IN: the source is the caller's
+// linear index array (first pass only).  Each wavefront (one brick) takes the
+// unrolled body for its own distinct-offset counts per axis: a wave-uniform
+// branch, so every body keeps all its reads in flight together.
+template <bool WIDE, bool LINEAR_IN>
+__device__ __forceinline__ void jfa_far_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                             int logn, int kb, uint32_t blk, uint32_t nblk)
+{
+    const int logB = logn - 2, B = 1 << logB;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int b = (int)xcd_remap(blk, nblk) * 4 + wave;
+    const int bx = b & (B - 1), by = (b >> logB) & (B - 1), bz = b >> (2 * logB);
+    const auto two = [&](int c) { return c < kb || c + kb >= B; };  // one side leaves the grid
+    switch ((two(bx) ? 1 : 0) | (two(by) ? 2 : 0) | (two(bz) ? 4 : 0)) {
+    case 0: jfa_far_brick<WIDE, LINEAR_IN, 3, 3, 3>(src, dst, n, logn, kb, b, lane); break;
+    case 1: jfa_far_brick<WIDE, LINEAR_IN, 2, 3, 3>(src, dst, n, logn, kb, b, lane); break;
+    case 2: jfa_far_brick<WIDE, LINEAR_IN, 3, 2, 3>(src, dst, n, logn, kb, b, lane); break;
+    case 3: jfa_far_brick<WIDE, LINEAR_IN, 2, 2, 3>(src, dst, n, logn, kb, b, lane); break;
+    case 4: jfa_far_brick<WIDE, LINEAR_IN, 3, 3, 2>(src, dst, n, logn, kb, b, lane); break;
+    case 5: jfa_far_brick<WIDE, LINEAR_IN, 2, 3, 2>(src, dst, n, logn, kb, b, lane); break;
+    case 6: jfa_far_brick<WIDE, LINEAR_IN, 3, 2, 2>(src, dst, n, logn, kb, b, lane); break;
+    default: jfa_far_brick<WIDE, LINEAR_IN, 2, 2, 2>(src, dst, n, logn, kb, b, lane); break;
+    }
+}
+
+template <bool WIDE, bool LINEAR_IN>
 __global__ void __launch_bounds__(256) jfa_far(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
                                                int logn, int kb)
 {
-    jfa_far_body<WIDE, LINEAR_IN, NC>(src, dst, n, logn, kb, blockIdx.x, gridDim.x);
+    jfa_far_body<WIDE, LINEAR_IN>(src, dst, n, logn, kb, blockIdx.x, gridDim.x);
 }
 
 // One pass with step K in {1, 2}: eight bricks (an 8^3 block) per workgroup,
@@ -299,15 +319,10 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
         const int k = steps[i];
         int32_t *dst = bufs[next];
         if (k >= 4) {
-            const bool lin = linear_first && i == 0, half = k == n / 2;  // half: kb = B/2, 8 distinct candidates
-            if (lin && half)
-                jfa_far<WIDE, true, 2><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
-            else if (lin)
-                jfa_far<WIDE, true, 3><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
-            else if (half)
-                jfa_far<WIDE, false, 2><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
+            if (linear_first && i == 0)
+                jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
             else
-                jfa_far<WIDE, false, 3><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
+                jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
         } else if (k == 2) {
             jfa_near<2, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr, 0.f, 0.f);
         } else {
