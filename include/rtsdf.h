@@ -128,7 +128,9 @@ int rtsdf_voxelize(const float *vertices, int32_t nv, const int32_t *faces, int3
 /* scratch   int32 [n^3] workspace (contents destroyed).                     */
 /* beta      bias subtracted from the distance (world units).                */
 /* dist2     int32 [n^3] out: squared distance in voxels to the seed         */
-/*           (INT32_MAX if none).                                            */
+/*           (INT32_MAX if none); also a work buffer during the passes.     */
+/*           seeds, scratch and dist2 must be three distinct arrays         */
+/*           (EINVAL if two of the pointers are equal).                      */
 /* coarse_sdf float32 [n^3] out: h * sqrt(dist2) - beta, each float          */
 /*           operation rounded once (+inf if no seed).                       */
 /* n must be a power of two in [8, 256].                                     */
@@ -143,8 +145,9 @@ int rtsdf_jfa(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, float beta,
  * Sec. 2.1 builds on): "JFA+1" (n/2, ..., 1, 1), "JFA+2" (n/2, ..., 1, 2, 1)
  * and "1+JFA" (1, n/2, ..., 1).  Extra passes never increase a voxel's
  * distance.  Other arguments as rtsdf_jfa; rtsdf_jfa is this call with
- * n/2, ..., 1.  Schedules whose brick passes would end in the wrong buffer
- * add one device-to-device copy of n^3 int32. */
+ * n/2, ..., 1.  A schedule that starts with a step below 4 converts the
+ * input to the internal layout first, and adds one device-to-device copy of
+ * n^3 int32 when its passes would end in the wrong buffer. */
 int rtsdf_jfa_steps(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, const int32_t *steps, int32_t nsteps,
                     float beta, int32_t *dist2, float *coarse_sdf, rtsdf_stream stream);
 

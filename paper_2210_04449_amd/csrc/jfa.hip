@@ -295,42 +295,60 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
     const int64_t nvox = (int64_t)n * n * n;
     const unsigned far_blocks = (unsigned)(nvox / 256);
     const unsigned near_blocks = (unsigned)(nvox / 512);
-    // Passes 0 .. m-2 go brick layout to brick layout, alternating buffers; the final pass (step 1) must read
-    // `scratch` and write the caller's linear layout to `seeds`.  A first far pass can read the linear input
-    // directly; otherwise the input is converted into `scratch` first, and copied once more when the number
-    // of brick passes would leave the last one in the wrong buffer.
+    // Passes 0 .. m-2 go brick layout to brick layout; the final pass (step 1) must read `scratch` and write the
+    // caller's linear layout to `seeds` (and `dist2`, `sdf`).  When the first step is a far one it reads the
+    // linear input directly, and the brick passes alternate between `dist2` (written only by the final pass,
+    // and distinct from `seeds` and `scratch` since that pass reads one and writes the other) and `scratch`,
+    // chosen so that the last one lands in `scratch`.  Otherwise the input is converted into `scratch` first,
+    // and copied once more when the number of brick passes would leave the last one in the wrong buffer.
     const int npass = m - 1;
-    const bool linear_first = npass >= 1 && steps[0] >= 4 && npass % 2 == 1;
     const int32_t *cur = seeds;
-    int32_t *bufs[2] = {seeds, scratch};
-    int next = 1;  // index into bufs of the next destination
-    if (!linear_first) {
+    if (npass >= 1 && steps[0] >= 4) {
+        for (int i = 0; i < npass; ++i) {
+            const int k = steps[i];
+            int32_t *dst = (npass - 1 - i) % 2 == 0 ? scratch : dist2;
+            if (k >= 4) {
+                if (i == 0)
+                    jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
+                else
+                    jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
+            } else if (k == 2) {
+                jfa_near<2, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
+                                                                                 0.f, 0.f);
+            } else {
+                jfa_near<1, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
+                                                                                 0.f, 0.f);
+            }
+            RTSDF_CHECK_LAUNCH();
+            cur = dst;
+        }
+    } else {
+        int32_t *bufs[2] = {seeds, scratch};
+        int next = 0;  // index into bufs of the next destination
         jfa_to_bricks<<<dim3(far_blocks), dim3(256), 0, s>>>(seeds, scratch, n, logn);
         RTSDF_CHECK_LAUNCH();
         cur = scratch;
-        next = 0;
         if (npass % 2 == 1) {
             RTSDF_TRY(hipMemcpyAsync(seeds, scratch, sizeof(int32_t) * nvox, hipMemcpyDeviceToDevice, s));
             cur = seeds;
             next = 1;
         }
-    }
-    for (int i = 0; i < npass; ++i) {
-        const int k = steps[i];
-        int32_t *dst = bufs[next];
-        if (k >= 4) {
-            if (linear_first && i == 0)
-                jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
-            else
+        for (int i = 0; i < npass; ++i) {
+            const int k = steps[i];
+            int32_t *dst = bufs[next];
+            if (k >= 4) {
                 jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
-        } else if (k == 2) {
-            jfa_near<2, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr, 0.f, 0.f);
-        } else {
-            jfa_near<1, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr, 0.f, 0.f);
+            } else if (k == 2) {
+                jfa_near<2, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
+                                                                                 0.f, 0.f);
+            } else {
+                jfa_near<1, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
+                                                                                 0.f, 0.f);
+            }
+            RTSDF_CHECK_LAUNCH();
+            cur = dst;
+            next ^= 1;
         }
-        RTSDF_CHECK_LAUNCH();
-        cur = dst;
-        next ^= 1;
     }
     // cur == scratch here by construction
     jfa_near<1, WIDE, true><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, seeds, n, logn, dist2, sdf, g.h, beta);
@@ -345,7 +363,8 @@ extern "C" int rtsdf_jfa_steps(rtsdf_grid coarse, int32_t *seeds, int32_t *scrat
 {
     using namespace rtsdf;
     if (!grid_ok(coarse) || !is_pow2(coarse.n) || coarse.n < 8 || coarse.n > 256) return RTSDF_EINVAL;
-    if (!seeds || !scratch || !dist2 || !coarse_sdf || seeds == scratch) return RTSDF_EINVAL;
+    if (!seeds || !scratch || !dist2 || !coarse_sdf || seeds == scratch || dist2 == seeds || dist2 == scratch)
+        return RTSDF_EINVAL;
     if (!(beta == beta)) return RTSDF_EINVAL;
     if (!steps || nsteps < 1 || nsteps > 64 || steps[nsteps - 1] != 1) return RTSDF_EINVAL;
     for (int i = 0; i < nsteps; ++i)

@@ -60,13 +60,16 @@ def test_host_validation(R):
     assert L.rtsdf_voxelize(dummy, 3, dummy, 1, g, None, None) == R.EINVAL
     assert L.rtsdf_jfa(g, dummy, dummy, 0.0, dummy, dummy, None) == R.EINVAL  # seeds == scratch
     assert L.rtsdf_jfa(R.Grid.make(4), dummy, C.c_void_p(32), 0.0, dummy, dummy, None) == R.EINVAL
-    other = C.c_void_p(32)
+    other, d2p = C.c_void_p(32), C.c_void_p(48)
     for bad in ([], [8, 4, 2], [3, 1], [32, 1], [0, 1], [16, -4, 1]):
         arr = (C.c_int32 * max(len(bad), 1))(*bad)
-        assert L.rtsdf_jfa_steps(g, dummy, other, arr, len(bad), 0.0, dummy, dummy, None) == R.EINVAL, bad
+        assert L.rtsdf_jfa_steps(g, dummy, other, arr, len(bad), 0.0, d2p, dummy, None) == R.EINVAL, bad
     ok = (C.c_int32 * 2)(16, 1)
-    assert L.rtsdf_jfa_steps(g, dummy, other, None, 2, 0.0, dummy, dummy, None) == R.EINVAL  # no schedule
-    assert L.rtsdf_jfa_steps(g, dummy, dummy, ok, 2, 0.0, dummy, dummy, None) == R.EINVAL  # seeds == scratch
+    assert L.rtsdf_jfa_steps(g, dummy, other, None, 2, 0.0, d2p, dummy, None) == R.EINVAL  # no schedule
+    assert L.rtsdf_jfa_steps(g, dummy, dummy, ok, 2, 0.0, d2p, dummy, None) == R.EINVAL  # seeds == scratch
+    # dist2 is also a work buffer: it may be neither seeds nor scratch
+    assert L.rtsdf_jfa_steps(g, dummy, other, ok, 2, 0.0, dummy, dummy, None) == R.EINVAL
+    assert L.rtsdf_jfa_steps(g, dummy, other, ok, 2, 0.0, other, dummy, None) == R.EINVAL
     assert R.jfa_schedule(32, "jfa+2") == [16, 8, 4, 2, 1, 2, 1] and R.jfa_schedule(16, "1+jfa") == [1, 8, 4, 2, 1]
     fine = R.Grid.make(64)
     assert L.rtsdf_select(g, dummy, R.Grid.make(48), 0.0, 0.1, dummy, dummy, 10, dummy, dummy, None) == R.EINVAL
