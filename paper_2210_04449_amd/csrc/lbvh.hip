@@ -3,7 +3,7 @@
 // Refitting keeps the topology built at creation; when geometry moves far
 // from where it was, boxes overlap more and more and tracing slows (20x after
 // 48 frames of continuous motion on the moving-scene workload).  A rebuild
-// from scratch on the host costs seconds for a million triangles; this builds
+// from scratch on the host costs seconds for a million triangles; the kernels here build
 // a new hierarchy on the device every frame instead, in the node format the
 // tracer reads, over the scene's references (split pieces of large triangles
 // keep their subdivision paths, so a rebuild re-derives each piece's box from
