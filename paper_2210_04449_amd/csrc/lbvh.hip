@@ -25,11 +25,12 @@
 //      two passes: workgroups of kChunk threads own kChunk consecutive leaves
 //      and finish every node whose run lies inside their chunk (counters and
 //      boxes in LDS, workgroup-scope ordering); the few nodes whose run
-//      crosses a chunk border are finished by a single workgroup from a queue
-//      of the children the first pass completed.  No pass needs ordering
-//      across workgroups, which on this GPU costs an L2 write-back and
-//      invalidate per fence (the eight L2 caches are not coherent with each
-//      other within a kernel);
+//      crosses a chunk border (about 10 per chunk) are finished by a second
+//      pass that climbs from a queue of the children the first pass
+//      completed, with device-scope ordering.  Ordering across workgroups
+//      costs an L2 write-back and invalidate per fence on this GPU (the eight
+//      L2 caches are not coherent with each other within a kernel): 7.0 ms
+//      when every leaf's climb paid it, 0.1 ms for the crossing nodes alone;
 //   6. the triangle records and affine maps in leaf order.
 // The tree depth is at most 30 + ceil(log2 n) (each level consumes one bit of
 // the distinct 30-bit code + position key), which sizes the traversal stack.
@@ -258,19 +259,19 @@ __global__ void __launch_bounds__(kChunk) lbvh_boxes_local(BvhNode *nodes, const
     }
 }
 
-// step 5, second pass: one workgroup climbs from the queued children through the nodes that cross chunk
-// borders (their counters were cleared by the first pass); all of its ordering is within the workgroup
-__global__ void __launch_bounds__(1024) lbvh_boxes_top(BvhNode *nodes, const int32_t *__restrict__ leaf_parent,
+// step 5, second pass: threads climb from the queued children through the nodes that cross chunk borders
+// (their counters were cleared by the first pass); the arrival counter orders the boxes at device scope
+__global__ void __launch_bounds__(256) lbvh_boxes_top(BvhNode *nodes, const int32_t *__restrict__ leaf_parent,
                                                       const int32_t *__restrict__ ids, const float *__restrict__ box,
                                                       int32_t *counter, const int32_t *__restrict__ queue,
                                                       const int32_t *__restrict__ qcount)
 {
     const int nq = *qcount;
-    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         const int first = queue[q];
         int node = first < 0 ? leaf_parent[leaf_first(first)] : nodes[first].meta.z;
         while (node >= 0) {
-            if (__hip_atomic_fetch_add(&counter[node], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+            if (__hip_atomic_fetch_add(&counter[node], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 0)
                 break;  // the other child is not done; its thread goes on
             BvhNode *nd = &nodes[node];
             const int c[2] = {nd->meta.x, nd->meta.y};
@@ -383,7 +384,7 @@ static int lbvh_run(rtsdf_scene *sc, bool rebuild, hipStream_t s)
     lbvh_boxes_local<<<dim3((unsigned)((n + kChunk - 1) / kChunk)), dim3(kChunk), 0, s>>>(
         sc->nodes, L->leaf_parent, L->range, L->id_sorted, L->box, n, sc->refit_counter, L->queue, L->qcount);
     RTSDF_CHECK_LAUNCH();
-    lbvh_boxes_top<<<dim3(1), dim3(1024), 0, s>>>(sc->nodes, L->leaf_parent, L->id_sorted, L->box,
+    lbvh_boxes_top<<<dim3(64), dim3(256), 0, s>>>(sc->nodes, L->leaf_parent, L->id_sorted, L->box,
                                                    sc->refit_counter, L->queue, L->qcount);
     RTSDF_CHECK_LAUNCH();
     return RTSDF_OK;
