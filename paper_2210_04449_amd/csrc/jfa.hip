@@ -79,6 +79,16 @@ __device__ __forceinline__ double jfa_key(JfaPos p, uint32_t s)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)low);
 }
 
+// The same key for n <= 128 from a staged pair (s, s & 0x7F000000): the missing-seed bits are computed once per
+// staged value instead of once per candidate.
+__device__ __forceinline__ double jfa_key_pair(JfaPos p, uint2 e)
+{
+    const uint32_t low = e.x + p.a;
+    const int d = (int)(low ^ 0x00808080u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_sdot4(d, d, (int)e.y, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)low);
+}
+
 __device__ __forceinline__ uint32_t key_d2(double k) { return (uint32_t)(__builtin_bit_cast(uint64_t, k) >> 32); }
 
 // the packed seed of the best key (kNoSeed if no candidate had one)
@@ -233,7 +243,9 @@ __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, i
                                               float beta, uint32_t blk_id, uint32_t nblk)
 {
     constexpr int T = 8 + 2 * K;
-    __shared__ uint32_t tile[T * T * T];
+    // n <= 128: each entry staged as the pair (s, s & 0x7F000000); n = 256: the seed alone
+    __shared__ uint32_t tile[(WIDE ? 1 : 2) * T * T * T];
+    uint2 *tile2 = reinterpret_cast<uint2 *>(tile);
     // n is a power of two: block and brick coordinates are bit fields (shifts and masks, no divisions)
     const int logB = logn - 2, logTB = logn - 3, TB = 1 << logTB;  // 8^3 blocks per axis
     const int blk = (int)xcd_remap(blk_id, nblk);
@@ -245,7 +257,8 @@ __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, i
             const int b = (x >> 2) | ((y >> 2) << logB) | ((z >> 2) << (2 * logB));
             v = (uint32_t)src[(b << 6) | (x & 3) | ((y & 3) << 2) | ((z & 3) << 4)];
         }
-        tile[i] = v;
+        if (WIDE) tile[i] = v;
+        else tile2[i] = make_uint2(v, v & 0x7F000000u);
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -258,7 +271,8 @@ __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, i
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
         const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-        best = __builtin_fmin(best, jfa_key<WIDE>(P, tile[c + K * (ox + T * (oy + T * oz))]));
+        const int e = c + K * (ox + T * (oy + T * oz));
+        best = __builtin_fmin(best, WIDE ? jfa_key<WIDE>(P, tile[e]) : jfa_key_pair(P, tile2[e]));
     }
     if (!FINAL) {
         const int b = (x >> 2) | ((y >> 2) << logB) | ((z >> 2) << (2 * logB));
