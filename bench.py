@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--parts", action="store_true",
                     help="dynamic workload as a two-level scene of rigid parts instead of one refitted hierarchy")
     ap.add_argument("--no-shadow", action="store_true", help="skip timing the soft-shadow consumer")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="room workload: skip the batched and differentiable comparison records")
     ap.add_argument("--sampling", default="point", choices=["point", "trilinear"],
                     help="how a fine texel reads the coarse SDF for selection and c_t")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -329,6 +331,19 @@ def main():
                                     "transform sets cycled; top-level refit and world positions each update")
     if not args.no_cpu_baseline and args.config != "dynamic":
         out["cpu_baseline"] = cpu_baseline(w, selected, args.cpu_seconds, args.sampling)
+    if args.config == "room" and not args.no_extras:
+        # the batched and differentiable forms against their plain single-scene forward, a few steps each
+        p.close()
+        del p
+        torch.cuda.empty_cache()
+        b = batched_record(args, 4, 1)
+        out["batched"] = {"workload": b["config"]["workload"], "triangles": b["config"]["triangles"],
+                          **{k: v for k, v in b.items() if k not in ("config", "batch_ms_per_step")},
+                          "batch_ms_per_step": round(b["batch_ms_per_step"], 3)}
+        torch.cuda.empty_cache()
+        d = diff_record(args, 8, 1)
+        out["diff"] = {"workload": d["config"]["workload"],
+                       **{k: v for k, v in d.items() if k not in ("config", "forward_backward_ms_value")}}
     print(json.dumps(out), flush=True)
 
 
@@ -532,6 +547,13 @@ def _base_record(args, value_ms, config):
 
 
 def run_batched(args):
+    rec = batched_record(args, args.steps, args.warmup)
+    out = _base_record(args, rec.pop("batch_ms_per_step"), rec.pop("config"))
+    out.update(rec)
+    print(json.dumps(out), flush=True)
+
+
+def batched_record(args, steps: int, warmup: int) -> dict:
     """64 seeded scenes of uneven size in one launch per stage, captured as one graph, against the same
     scenes run one by one through the single-scene path."""
     import torch
@@ -549,18 +571,18 @@ def run_batched(args):
         from paper_2210_04449_amd import autotune
         autotune.tune(B)
     g = B.make_graph(first_frame=0)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         g.launch()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     s0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         g.launch()
     s1.record(stream)
     torch.cuda.synchronize()
-    batch_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    batch_ms = (time.perf_counter() - t0) * 1e3 / steps
     rays = sum(B.tensors(i)["count"].item() * w.rays for i, w in enumerate(ws))
     # the same scenes one at a time (eager single-scene path)
     single_ms = 0.0
@@ -577,19 +599,27 @@ def run_batched(args):
         single_ms += a.elapsed_time(b) / 2
         p.close()
         del p
-    out = _base_record(args, batch_ms, {
+    g.close()
+    B.close()
+    return {"config": {
         "workload": "batched: 64 seeded scenes, triangles log-uniform 1k-100k, coarse in {32,64,128}, fine 2x, "
                     "beta 0.5 / d 2 coarse voxels, 8 rays/texel, one graph-captured step",
-        "scenes": len(ws), "triangles": int(sum(w.mesh.nt for w in ws))})
-    out.update({"batch_gpu_ms_per_step": round(s0.elapsed_time(s1) / args.steps, 3),
-                "sum_single_scene_ms": round(single_ms, 3), "speedup_vs_single": round(single_ms / batch_ms, 3),
-                "rays_per_step": int(rays), "rays_per_s": round(rays / (batch_ms / 1e3), 1)})
-    print(json.dumps(out), flush=True)
+        "scenes": len(ws), "triangles": int(sum(w.mesh.nt for w in ws))},
+        "batch_ms_per_step": batch_ms, "steps": steps,
+        "batch_gpu_ms_per_step": round(s0.elapsed_time(s1) / steps, 3),
+        "sum_single_scene_ms": round(single_ms, 3), "speedup_vs_single": round(single_ms / batch_ms, 3),
+        "rays_per_step": int(rays), "rays_per_s": round(rays / (batch_ms / 1e3), 1)}
 
 
 def run_diff(args):
+    rec = diff_record(args, args.steps, args.warmup)
+    out = _base_record(args, rec.pop("forward_backward_ms_value"), rec.pop("config"))
+    out.update(rec)
+    print(json.dumps(out), flush=True)
+
+
+def diff_record(args, steps: int, warmup: int) -> dict:
     """Differentiable config: forward (all frames) and backward to vertex positions, against the plain forward."""
-    import numpy as np
     import torch
 
     from paper_2210_04449_amd.autograd import fine_sdf
@@ -619,12 +649,12 @@ def run_diff(args):
         loss.backward()
         return v.grad
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         plain()
         fwd_bwd()
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    reps = max(1, args.steps // 4)
+    reps = max(1, steps // 4)
     ev[0].record(stream)
     for _ in range(reps):
         plain()
@@ -635,14 +665,16 @@ def run_diff(args):
     torch.cuda.synchronize()
     plain_ms = ev[0].elapsed_time(ev[1]) / reps
     fb_ms = ev[1].elapsed_time(ev[2]) / reps
-    out = _base_record(args, fb_ms, {
+    p.close()
+    return {"config": {
         "workload": f"diff: perturbed geodesic sphere {w.mesh.nt} triangles, coarse {w.nc}^3 / fine {w.nf}^3, "
                     f"{w.rays} rays x {w.frames} frames; loss sum (f - sphere SDF)^2; forward + backward",
-        "triangles": w.mesh.nt})
-    out.update({"plain_forward_ms": round(plain_ms, 3), "forward_backward_ms": round(fb_ms, 3),
-                "backward_overhead_ms": round(fb_ms - plain_ms, 3),
-                "grad_norm": float(g.norm().item())})
-    print(json.dumps(out), flush=True)
+        "triangles": w.mesh.nt},
+        "forward_backward_ms_value": fb_ms, "reps": reps,
+        "plain_forward_ms": round(plain_ms, 3), "forward_backward_ms": round(fb_ms, 3),
+        "backward_overhead_ms": round(fb_ms - plain_ms, 3),
+        "backward_vs_forward": round(fb_ms / plain_ms, 4),
+        "grad_norm": float(g.norm().item())}
 
 
 if __name__ == "__main__":

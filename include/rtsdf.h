@@ -45,6 +45,10 @@
  *    fastest (index x + n (y + n z)).
  *  * Lengths (h, beta, d, distances) are in world units.
  *  * Calls that share an output or a workspace must not run concurrently.
+ *    Read-only inputs may be shared: traces of one scene on several streams
+ *    are safe with separate workspaces and outputs (a scene holds no
+ *    per-trace scratch).  Calls that modify a scene (refit, rebuild,
+ *    set_transforms, set_sign, set_tuning) must not overlap its traces.
  */
 #ifndef RTSDF_H
 #define RTSDF_H
@@ -78,7 +82,8 @@ enum {
     RTSDF_ERR_VERTEX_RANGE = 2,/* a vertex farther than one domain side outside the grid */
     RTSDF_ERR_QUEUE_FULL = 4,  /* rtsdf_select: more selected texels than queue_cap */
     RTSDF_ERR_BATCH = 8,       /* rtsdf_batch_step: inconsistent batch tables */
-    RTSDF_ERR_TRANSFORM = 16   /* rtsdf_scene_set_transforms: a transform that is not rigid */
+    RTSDF_ERR_TRANSFORM = 16,  /* rtsdf_scene_set_transforms: a transform that is not rigid */
+    RTSDF_ERR_FRAME = 32       /* a tracer read a frame index >= 2^23 through frame_ptr (that frame was not traced) */
 };
 
 const char *rtsdf_status_string(int status);
@@ -340,12 +345,18 @@ void rtsdf_scene_destroy(rtsdf_scene *scene);
 /* rays_per_texel in [1, 64]; alpha in [0, 1].                               */
 /* frame_ptr  optional device uint32: if non-NULL the frame index is read    */
 /*            from it at run time (for captured graphs) and `frame` is       */
-/*            ignored.                                                       */
+/*            ignored.  A value >= 2^23 (past the argmin record's frame      */
+/*            field) traces nothing: the state and the selected texels'      */
+/*            fine values keep the previous frame's, and ERR_FRAME is raised. */
+/*            `frame` itself must be < 2^23 (EINVAL).                        */
 /* workspace  rtsdf_trace_workspace_size() bytes of device memory: 256 B of  */
-/*            counters, then per-wavefront buffers holding the directions of */
-/*            the rays each persistent wavefront is tracing (~100 MB on a     */
-/*            256-CU device; the size is that of the current device).  Calls  */
-/*            that run concurrently need separate workspaces.                 */
+/*            counters, per-wavefront buffers holding the directions of the  */
+/*            rays each persistent wavefront is tracing, and the spill area  */
+/*            of the traversal stacks (entries deeper than the LDS part, for */
+/*            hierarchies up to depth 64); ~210 MB on a 256-CU device (the   */
+/*            size is that of the current device).  Calls that run          */
+/*            concurrently need separate workspaces; they may trace the same */
+/*            scene.                                                         */
 /* ------------------------------------------------------------------------ */
 typedef struct rtsdf_accum {
     float *u;
@@ -362,14 +373,19 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
                            const uint32_t *frame_ptr, uint64_t seed, uint32_t scene_id, float alpha,
                            rtsdf_accum state, float *fine_sdf, void *workspace, rtsdf_stream stream);
 
-/* Tuning and instrumentation of the tracer (process-wide host-side state,
- * read at each rtsdf_trace_accumulate call; results never depend on it;
- * defaults: refill 16, blocks_per_cu 0, stats 0, loop 3, bin_directions 1,
- * stack_lds 12):
+/* Tuning and instrumentation of the tracer.  Results never depend on it,
+ * only speed does.  rtsdf_trace_config sets the process default (host-side
+ * state read at each trace call); rtsdf_scene_set_tuning gives one scene its
+ * own tuning (NULL: back to the process default) and rtsdf_batch_set_tuning
+ * one batch, so callers tracing different scenes do not share it.
+ * rtsdf_scene_get_tuning returns the tuning a trace of the scene uses.
+ * Defaults: refill 16, blocks_per_cu 0, stats 0, loop 3, bin_directions 1,
+ * stack_lds 12, tile_texels 64:
  *   refill          a wavefront hands out new rays once this many of its
  *                   lanes are free (8 or 16);
- *   blocks_per_cu   persistent workgroups per compute unit (0 = as many as
- *                   fit, at most 8);
+ *   blocks_per_cu   persistent workgroups of four wavefronts per compute
+ *                   unit, i.e. traversal wavefronts per SIMD (0 = as many as
+ *                   fit: 6 with the default LDS stack; 1 to 8);
  *   stats           1: count into 64-bit counters at byte offsets 8, 16, ...
  *                   of the workspace: node visits, triangle tests, rays,
  *                   traversal iterations x 64, refill rounds x 64, lane
@@ -386,13 +402,17 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
  *   bin_directions  1: each wavefront's tile of rays is sorted by direction
  *                   before tracing (coherence); 0: queue order;
  *   stack_lds       traversal stack entries kept in LDS per lane (12, 16 or
- *                   24); deeper entries go to a spill area of the scene.
- * rtsdf_trace_config rejects values outside these sets with RTSDF_EINVAL. */
+ *                   24); deeper entries go to the workspace's spill area;
+ *   tile_texels     texels per wavefront tile at most (16, 32 or 64; a tile
+ *                   also holds at most 768 rays, i.e. 768 / rays texels).
+ * Values outside these sets are rejected with RTSDF_EINVAL. */
 typedef struct rtsdf_trace_tuning {
-    int32_t refill, blocks_per_cu, stats, loop, bin_directions, stack_lds;
+    int32_t refill, blocks_per_cu, stats, loop, bin_directions, stack_lds, tile_texels;
 } rtsdf_trace_tuning;
 int rtsdf_trace_config(const rtsdf_trace_tuning *tuning);
 int rtsdf_trace_config_get(rtsdf_trace_tuning *tuning);
+int rtsdf_scene_set_tuning(rtsdf_scene *scene, const rtsdf_trace_tuning *tuning);
+int rtsdf_scene_get_tuning(const rtsdf_scene *scene, rtsdf_trace_tuning *tuning);
 
 /* Ray directions exactly as rtsdf_trace_accumulate draws them, for n keys  */
 /* (texel[i], frame[i], ray[i]) with one seed and scene id: out float32      */
@@ -517,6 +537,9 @@ int rtsdf_batch_create(const rtsdf_batch_scene *scenes /* host array [n] */, int
 int rtsdf_batch_reset(rtsdf_batch *batch, rtsdf_stream stream);
 int rtsdf_batch_step(rtsdf_batch *batch, uint32_t frame, const uint32_t *frame_ptr, rtsdf_stream stream);
 int rtsdf_batch_outputs(const rtsdf_batch *batch, int32_t index, rtsdf_batch_view *out);
+/* the batch's own tracer tuning (NULL: the process default; see
+ * rtsdf_trace_config) */
+int rtsdf_batch_set_tuning(rtsdf_batch *batch, const rtsdf_trace_tuning *tuning);
 /* one batch step as a captured graph: each launch runs the step for frame
  * *frame_counter (device) and then increments it */
 int rtsdf_batch_graph_create(rtsdf_batch *batch, uint32_t *frame_counter, rtsdf_frame_graph **out,

@@ -8,6 +8,13 @@ ray regenerates that ray and scatters dL/df * sign * |w| * b_i * n / (n . w) int
 the three vertices of the hit triangle.  Voxelization, jump flooding,
 selection, the sign and the identity of the closest ray are piecewise constant
 and carry no gradient; texels that took the coarse value have none either.
+
+Only alpha = 1 (the running minimum of Eq. (1)) is differentiated: with
+alpha < 1 a texel's value can be the decayed term alpha u_{t-1} +
+(1 - alpha) max(c, 0), which depends on earlier traced distances through
+u_{t-1}, and the argmin record the backward follows is cleared whenever that
+term wins, so the gradient would silently miss those contributions.  The
+forward raises ValueError for a pipeline with alpha != 1.
 """
 from __future__ import annotations
 
@@ -20,6 +27,9 @@ class FineSDF(torch.autograd.Function):
     @staticmethod
     def forward(ctx, vertices: torch.Tensor, pipeline, frames):
         p = pipeline
+        if p.alpha != 1.0:
+            raise ValueError(f"FineSDF differentiates the running minimum of Eq. (1) only (alpha = 1); "
+                             f"the pipeline has alpha = {p.alpha}")
         p.set_vertices(vertices.detach().to(p.device, torch.float32).contiguous())
         p.reset()
         for f in frames:

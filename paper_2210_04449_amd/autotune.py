@@ -2,9 +2,27 @@
 
 The tracer's results never depend on its tuning (rtsdf_trace_tuning), only its
 speed does.  `tune` times candidate settings on the caller's own pipeline (or
-batch) with HIP events, keeps the fastest, applies it with
-``rtsdf_trace_config`` and remembers it in a JSON cache keyed by GPU
-architecture, fine-grid size, triangle-count bucket and rays per texel.  The
+batch) with HIP events and keeps the fastest.  The knobs:
+
+* ``blocks_per_cu``  persistent workgroups of four wavefronts per compute unit,
+  i.e. traversal wavefronts per SIMD (0 = as many as fit, 6 with the default
+  LDS stack);
+* ``tile_texels``    texels per wavefront tile (a compact Morton block of the
+  fine grid; at most 768 rays);
+* ``refill``         free lanes at which a wavefront takes new rays;
+* ``stack_lds``      traversal stack entries per lane kept in LDS;
+* ``bin_directions`` sorting a tile's rays by direction;
+* ``loop``           traversal loop shape.
+
+The search is coordinate descent from the target's current tuning: each knob
+in turn takes each of its values with the others fixed, a change is kept when
+it is at least 0.5 % faster, and sweeps repeat until one changes nothing (or
+the product of a small space is timed exhaustively).  The winner is applied
+to the target only -- the scene of a Pipeline (``rtsdf_scene_set_tuning``) or
+the Batch (``rtsdf_batch_set_tuning``) -- never to the process default, and is
+remembered in a JSON cache keyed by GPU architecture and workload shape (fine
+size, triangle-count bucket and rays per texel; for batches the scene count,
+total fine texels, total triangles and the set of ray counts).  The
 accumulation state touched while timing is reset afterwards.
 """
 from __future__ import annotations
@@ -21,12 +39,14 @@ from . import rtsdf as R
 DEFAULT_CACHE = os.environ.get("RTSDF_AUTOTUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "rtsdf_autotune.json"))
 
+# first value of each knob = the library default
 SPACE = {
-    "refill": (8, 16),
+    "blocks_per_cu": (0, 3, 4, 5),
+    "tile_texels": (64, 32, 16),
+    "refill": (16, 8),
     "stack_lds": (12, 16, 24),
-    "bin_directions": (0, 1),
-    "loop": (2, 3),
-    "blocks_per_cu": (0,),
+    "bin_directions": (1, 0),
+    "loop": (3, 2),
 }
 
 
@@ -37,9 +57,20 @@ def _arch() -> str:
         return "unknown"
 
 
+def _bucket(x: int) -> int:
+    return int(math.log2(max(int(x), 1)))
+
+
 def cache_key(nf: int, triangles: int, rays: int) -> str:
-    bucket = int(math.log2(max(triangles, 1)))
-    return f"{_arch()}|nf{nf}|tri2^{bucket}|r{rays}"
+    return f"{_arch()}|nf{nf}|tri2^{_bucket(triangles)}|r{rays}"
+
+
+def batch_cache_key(batch) -> str:
+    d = batch.descriptors
+    texels = sum(s["fine_n"] ** 3 for s in d)
+    tris = sum(s["nt"] for s in d)
+    rays = sorted({s["rays"] for s in d})
+    return f"{_arch()}|batch{batch.n}|tex2^{_bucket(texels)}|tri2^{_bucket(tris)}|r{','.join(map(str, rays))}"
 
 
 def load_cache(path: str = DEFAULT_CACHE) -> dict:
@@ -76,15 +107,53 @@ def _time(fn, reps: int) -> float:
     return start.elapsed_time(stop) / reps
 
 
-def tune(target, reps: int = 2, space: dict = SPACE, cache: str | None = DEFAULT_CACHE, force: bool = False) -> dict:
-    """Pick the fastest tracer tuning for `target` (a Pipeline or a rtsdf.Batch).
+def search(measure, start: dict, space: dict = SPACE, sweeps: int = 3, exhaustive: bool | None = None,
+           min_gain: float = 0.005):
+    """Minimise measure(tuning) over `space`; returns (best, ms, trials).
 
-    Returns {"tuning": {...}, "ms": best time, "trials": [(tuning, ms), ...]}.
+    Coordinate descent from `start` (which must hold a value for every knob of the space); with
+    `exhaustive` (default: when the space has at most 16 points) every point of the product is timed."""
+    if exhaustive is None:
+        exhaustive = math.prod(len(v) for v in space.values()) <= 16
+    trials = []
+    if exhaustive:
+        for cand in candidates(space):
+            trials.append((cand, measure(cand)))
+        best, ms = min(trials, key=lambda t: t[1])
+        return best, ms, trials
+    best = {k: start[k] for k in space}
+    ms = measure(best)
+    trials.append((dict(best), ms))
+    seen = {tuple(sorted(best.items()))}
+    for _ in range(sweeps):
+        changed = False
+        for knob, values in space.items():
+            for v in values:
+                cand = {**best, knob: v}
+                key = tuple(sorted(cand.items()))
+                if key in seen:
+                    continue
+                seen.add(key)
+                t = measure(cand)
+                trials.append((cand, t))
+                if t < ms * (1.0 - min_gain):
+                    best, ms, changed = cand, t, True
+        if not changed:
+            break
+    return best, ms, trials
+
+
+def tune(target, reps: int = 2, space: dict = SPACE, cache: str | None = DEFAULT_CACHE, force: bool = False,
+         sweeps: int = 3, exhaustive: bool | None = None) -> dict:
+    """Pick the fastest tracer tuning for `target` (a Pipeline or a rtsdf.Batch) and apply it to that target.
+
+    Returns {"tuning": {...}, "ms": best time, "trials": [(tuning, ms), ...], "cached": bool, "key": str}.
     """
     from .pipeline import Pipeline
 
     if isinstance(target, Pipeline):
         key = cache_key(target.nf, int(target.faces.shape[0]), target.rays)
+        current = target.scene.tuning().as_dict()
         target.step(0)  # coarse stages and selection once; timing repeats the trace only
         frame = [1]
 
@@ -92,33 +161,36 @@ def tune(target, reps: int = 2, space: dict = SPACE, cache: str | None = DEFAULT
             target.trace(frame[0])
             frame[0] += 1
 
-        def reset():
-            target.reset()
+        def apply(t):
+            target.scene.set_tuning(**t, stats=0)
     else:
-        key = f"{_arch()}|batch{target.n}"
+        key = batch_cache_key(target)
+        current = {**R.rtsdf_trace_config_get().as_dict(), **getattr(target, "_tuning", {})}
         frame = [0]
 
         def run():
             target.step(frame[0])
             frame[0] += 1
 
-        def reset():
-            target.reset()
+        def apply(t):
+            target.set_tuning(**t, stats=0)
 
     entries = load_cache(cache) if cache else {}
     if not force and key in entries:
         best = entries[key]["tuning"]
-        R.rtsdf_trace_config(**best, stats=0)
-        return {"tuning": best, "ms": entries[key]["ms"], "trials": [], "cached": True}
-    trials = []
-    for cand in candidates(space):
-        R.rtsdf_trace_config(**cand, stats=0)
-        trials.append((cand, _time(run, reps)))
-    best, ms = min(trials, key=lambda t: t[1])
-    R.rtsdf_trace_config(**best, stats=0)
-    reset()
+        apply(best)
+        return {"tuning": best, "ms": entries[key]["ms"], "trials": [], "cached": True, "key": key}
+
+    def measure(t):
+        apply(t)
+        return _time(run, reps)
+
+    start = {k: current.get(k, v[0]) for k, v in space.items()}
+    best, ms, trials = search(measure, start, space, sweeps=sweeps, exhaustive=exhaustive)
+    apply(best)
+    target.reset()
     torch.cuda.synchronize()
     if cache:
         entries[key] = {"tuning": best, "ms": ms}
         save_cache(entries, cache)
-    return {"tuning": best, "ms": ms, "trials": trials, "cached": False}
+    return {"tuning": best, "ms": ms, "trials": trials, "cached": False, "key": key}

@@ -218,7 +218,9 @@ struct rtsdf_batch {
     int32_t *tile_offset = nullptr;
     int32_t *cursor = nullptr;  // 32 words: cursor + instrumentation counters (64-bit, from word 2)
     float4 *dirs = nullptr;     // the tracer's per-wavefront direction buffers
-    int32_t *spill = nullptr;   // the deepest scene's spill area
+    int32_t *spill = nullptr;   // the tracer's spill area (stack entries deeper than its LDS part)
+    bool has_tuning = false;    // tracer tuning of this batch (rtsdf_batch_set_tuning); else the process default
+    rtsdf_trace_tuning tuning{};
     // tables
     rtsdf::BatchVox *vox = nullptr;
     rtsdf::JfaStep *plan = nullptr;  // [max_passes + 1][n]
@@ -280,17 +282,12 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
         delete B;
         return rc;
     };
-    int max_depth = -1, deepest = -1;
     for (int i = 0; i < n; ++i) {
         const rtsdf_batch_scene &d = scenes[i];
         rtsdf_scene *sc = nullptr;
         const int rc = rtsdf_scene_create(d.vertices, d.nv, d.faces, d.nt, leaf_size, &sc, stream);
         if (rc != RTSDF_OK) return fail(rc);
         B->scenes.push_back(sc);
-        if (sc->max_depth > max_depth) {
-            max_depth = sc->max_depth;
-            deepest = i;
-        }
         if (sc->max_depth + 1 > 64) return fail(RTSDF_EINVAL);
         rtsdf_grid c, f;
         for (int a = 0; a < 3; ++a) c.lo[a] = f.lo[a] = d.lo[a];
@@ -306,7 +303,6 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
         B->ftotal += (int64_t)f.n * f.n * f.n;
         B->max_passes = std::max(B->max_passes, ilog2(c.n));
     }
-    B->spill = B->scenes[deepest]->spill;
     const int64_t C = B->ctotal, F = B->ftotal;
     std::vector<uint32_t> sel_off(n + 1, 0);
     for (int i = 0; i < n; ++i) {
@@ -319,7 +315,8 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
         !batch_alloc(B, &B->arg_ray, F) || !batch_alloc(B, &B->fine_sdf, F) ||
         !batch_alloc(B, &B->sel_sums, sel_off[n]) || !batch_alloc(B, &B->counts, n) ||
         !batch_alloc(B, &B->tile_offset, n + 1) || !batch_alloc(B, &B->cursor, 32) ||
-        !batch_alloc(B, &B->dirs, (int64_t)(dirs_bytes() / sizeof(float4))) || !batch_alloc(B, &B->vox, n) ||
+        !batch_alloc(B, &B->dirs, (int64_t)(dirs_bytes() / sizeof(float4))) ||
+        !batch_alloc(B, &B->spill, (int64_t)(spill_bytes() / sizeof(int32_t))) || !batch_alloc(B, &B->vox, n) ||
         !batch_alloc(B, &B->plan, (int64_t)(B->max_passes + 1) * n) || !batch_alloc(B, &B->sel, n) ||
         !batch_alloc(B, &B->fill, n) || !batch_alloc(B, &B->trace, n))
         return fail(RTSDF_ENOMEM);
@@ -469,9 +466,10 @@ extern "C" int rtsdf_batch_step(rtsdf_batch *B, uint32_t frame, const uint32_t *
 {
     using namespace rtsdf;
     if (!B) return RTSDF_EINVAL;
-    if (frame >= (1u << 23) && !frame_ptr) return RTSDF_EINVAL;
+    if (frame >= kMaxFrame && !frame_ptr) return RTSDF_EINVAL;
     hipStream_t s = as_stream(stream);
     const int n = B->n;
+    const rtsdf_trace_tuning &T = B->has_tuning ? B->tuning : g_tuning;
     // voxelize
     int rc = launch_fill<int32_t>(B->seeds, -1, B->ctotal, s);
     if (rc != RTSDF_OK) return rc;
@@ -512,9 +510,9 @@ extern "C" int rtsdf_batch_step(rtsdf_batch *B, uint32_t frame, const uint32_t *
     // tracing
     if (FL.blocks) fill_unselected_batch<<<dim3(FL.blocks), dim3(256), 0, s>>>(B->fill, B->ranges + FL.offset, FL.count);
     RTSDF_CHECK_LAUNCH();
-    trace_tile_prefix<<<dim3(1), dim3(64), 0, s>>>(B->trace, n, B->tile_offset);
+    trace_tile_prefix<<<dim3(1), dim3(64), 0, s>>>(B->trace, n, T.tile_texels, B->tile_offset);
     RTSDF_CHECK_LAUNCH();
-    rc = launch_fill<int32_t>(B->cursor, 0, g_tuning.stats ? 32 : 1, s);
+    rc = launch_fill<int32_t>(B->cursor, 0, T.stats ? 32 : 1, s);
     if (rc != RTSDF_OK) return rc;
     TraceArgs A{};
     A.scenes = B->trace;
@@ -525,9 +523,16 @@ extern "C" int rtsdf_batch_step(rtsdf_batch *B, uint32_t frame, const uint32_t *
     A.frame_ptr = frame_ptr;
     A.seed = B->seed;
     A.spill = B->spill;
-    A.bin_directions = g_tuning.bin_directions;
     A.dirs = B->dirs;
-    return launch_trace<true>(A, s);
+    return launch_trace<true>(A, T, s);
+}
+
+extern "C" int rtsdf_batch_set_tuning(rtsdf_batch *B, const rtsdf_trace_tuning *t)
+{
+    if (!B || (t && !rtsdf::tuning_ok(*t))) return RTSDF_EINVAL;
+    B->has_tuning = t != nullptr;
+    if (t) B->tuning = *t;
+    return RTSDF_OK;
 }
 
 extern "C" int rtsdf_batch_outputs(const rtsdf_batch *B, int32_t i, rtsdf_batch_view *out)

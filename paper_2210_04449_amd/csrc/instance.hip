@@ -521,7 +521,6 @@ extern "C" int rtsdf_scene_create_instanced(const float *vertices, int32_t nv, c
                                                out, stream);
     if (rc != RTSDF_OK) return rc;
     if ((*out)->max_depth + 1 > 64) rc = RTSDF_EINVAL;  // deeper than the tracer's stack
-    if (rc == RTSDF_OK) rc = rtsdf::ensure_spill(*out);
     if (rc != RTSDF_OK) {
         rtsdf_scene_destroy(*out);
         *out = nullptr;

@@ -454,9 +454,7 @@ extern "C" int rtsdf_scene_enable_rebuild(rtsdf_scene *sc, rtsdf_stream stream)
     sc->max_leaf = 1;
     sc->bytes += bytes;
     sc->lbvh = L;
-    int rc = ensure_spill(sc);
-    if (rc == RTSDF_OK) rc = lbvh_run(sc, true, s);
-    return rc;
+    return lbvh_run(sc, true, s);
 }
 
 extern "C" int rtsdf_scene_rebuild(rtsdf_scene *scene, const float *vertices, rtsdf_stream stream)

@@ -86,8 +86,8 @@ struct rtsdf_scene {
     int32_t *refit_counter = nullptr;  // [nnodes]
     int32_t *start_nodes = nullptr;    // internal nodes with two leaf children
     int nstart = 0;
-    int32_t *spill = nullptr;          // tracer stack entries beyond the LDS part
-    int64_t spill_entries = 0;
+    bool has_tuning = false;           // tracer tuning of this scene (rtsdf_scene_set_tuning); else the
+    rtsdf_trace_tuning tuning{};       // process default of rtsdf_trace_config
     int64_t bytes = 0;
     int sign_policy = RTSDF_SIGN_VOTE;  // how the tracer signs a traced distance
     float shell = 0.f;                  // RTSDF_SIGN_SHELL: half-thickness subtracted from the distance
@@ -651,23 +651,13 @@ static int rtsdf_scene_create_impl(const float *vertices, int32_t nv, const int3
 }
 
 namespace rtsdf {
-static int ensure_spill(rtsdf_scene *sc);
 static int lbvh_run(rtsdf_scene *sc, bool rebuild, hipStream_t s);
 }
 
-// The tracer's spill area depends on the hierarchy depth; it is allocated
-// here, at creation, so trace calls never allocate.
 extern "C" int rtsdf_scene_create(const float *vertices, int32_t nv, const int32_t *faces, int32_t nt,
                                   int32_t leaf_size, rtsdf_scene **out, rtsdf_stream stream)
 {
-    int rc = rtsdf_scene_create_impl(vertices, nv, faces, nt, leaf_size, out, stream);
-    if (rc != RTSDF_OK) return rc;
-    rc = rtsdf::ensure_spill(*out);
-    if (rc != RTSDF_OK) {
-        rtsdf_scene_destroy(*out);
-        *out = nullptr;
-    }
-    return rc;
+    return rtsdf_scene_create_impl(vertices, nv, faces, nt, leaf_size, out, stream);
 }
 
 extern "C" int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsdf_stream stream)
@@ -766,6 +756,5 @@ extern "C" void rtsdf_scene_destroy(rtsdf_scene *scene)
     (void)hipFree(scene->faces);
     (void)hipFree(scene->refit_counter);
     (void)hipFree(scene->start_nodes);
-    (void)hipFree(scene->spill);
     delete scene;
 }

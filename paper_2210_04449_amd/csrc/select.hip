@@ -17,6 +17,8 @@
 //                  entries per selected voxel
 //   select_mask    the linear uint8 mask, four texels per lane
 // No workgroup ever waits on another, and the queue order is deterministic.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace rtsdf {
@@ -244,6 +246,45 @@ inline int select_threshold(float hc, float beta, float d)
     return k > (double)INT32_MAX ? INT32_MAX : (int)k;
 }
 
+
+// Point-sampled selection with the block sums in `sums` (at least
+// rtsdf_select_workspace_size(coarse.n) bytes).  Every sum the launches read
+// is written earlier in the same sequence (count, then scan), so `sums` needs
+// no clearing.
+static int select_run(rtsdf_grid coarse, const int32_t *dist2, rtsdf_grid fine, float beta, float d, uint8_t *mask,
+                      int32_t *queue, int32_t queue_cap, int32_t *count, uint32_t *sums, hipStream_t s)
+{
+    const int logn = ilog2(coarse.n), logr = ilog2(fine.n / coarse.n);
+    const int K = select_threshold(coarse.h, beta, d);
+    const uint32_t total = (uint32_t)((int64_t)coarse.n * coarse.n * coarse.n);
+    const uint32_t nblocks = (total + kSelPerBlock - 1) / kSelPerBlock;
+    const SelPred pr{dist2, K, nullptr, 0.0f};
+    select_count<false><<<dim3(nblocks), dim3(kSelBlock), 0, s>>>(pr, logn, total, sums);
+    RTSDF_CHECK_LAUNCH();
+    select_scan<<<dim3(1), dim3(1024), 0, s>>>(sums, nblocks, 1u << (3 * logr), count, queue_cap);
+    RTSDF_CHECK_LAUNCH();
+    select_scatter<false><<<dim3(nblocks), dim3(kSelBlock), 0, s>>>(pr, logn, total, sums, logr, fine.n, queue,
+                                                                     queue_cap);
+    RTSDF_CHECK_LAUNCH();
+    const int64_t nquads = (int64_t)fine.n * fine.n * fine.n / 4;
+    select_mask<false><<<dim3((unsigned)((nquads + 255) / 256)), dim3(256), 0, s>>>(
+        pr, logn, logr, fine.n, nquads, reinterpret_cast<uint32_t *>(mask));
+    RTSDF_CHECK_LAUNCH();
+    return RTSDF_OK;
+}
+
+static bool select_args_ok(rtsdf_grid coarse, const int32_t *dist2, rtsdf_grid fine, float beta, float d,
+                           const uint8_t *mask, const int32_t *queue, int32_t queue_cap, const int32_t *count)
+{
+    if (!grid_ok(coarse) || !grid_ok(fine) || !is_pow2(coarse.n) || coarse.n > 512) return false;
+    if (!is_pow2(fine.n) || fine.n < coarse.n || fine.n > 1024 || fine.n < 4) return false;
+    if ((double)fine.h * fine.n != (double)coarse.h * coarse.n) return false;
+    if (fine.lo[0] != coarse.lo[0] || fine.lo[1] != coarse.lo[1] || fine.lo[2] != coarse.lo[2]) return false;
+    if (!dist2 || !mask || !count || queue_cap < 0 || (queue_cap > 0 && !queue)) return false;
+    if (!(beta == beta) || !(d == d)) return false;
+    return true;
+}
+
 }  // namespace rtsdf
 
 extern "C" size_t rtsdf_select_workspace_size(int32_t coarse_n)
@@ -259,31 +300,10 @@ extern "C" int rtsdf_select(rtsdf_grid coarse, const int32_t *dist2, rtsdf_grid 
                             rtsdf_stream stream)
 {
     using namespace rtsdf;
-    if (!grid_ok(coarse) || !grid_ok(fine) || !is_pow2(coarse.n) || coarse.n > 512) return RTSDF_EINVAL;
-    if (!is_pow2(fine.n) || fine.n < coarse.n || fine.n > 1024 || fine.n < 4) return RTSDF_EINVAL;
-    if ((double)fine.h * fine.n != (double)coarse.h * coarse.n) return RTSDF_EINVAL;
-    if (fine.lo[0] != coarse.lo[0] || fine.lo[1] != coarse.lo[1] || fine.lo[2] != coarse.lo[2]) return RTSDF_EINVAL;
-    if (!dist2 || !mask || !count || !workspace || queue_cap < 0 || (queue_cap > 0 && !queue)) return RTSDF_EINVAL;
-    if (!(beta == beta) || !(d == d)) return RTSDF_EINVAL;
-    hipStream_t s = as_stream(stream);
-    const int logn = ilog2(coarse.n), logr = ilog2(fine.n / coarse.n);
-    const int K = select_threshold(coarse.h, beta, d);
-    const uint32_t total = (uint32_t)((int64_t)coarse.n * coarse.n * coarse.n);
-    const uint32_t nblocks = (total + kSelPerBlock - 1) / kSelPerBlock;
-    uint32_t *sums = static_cast<uint32_t *>(workspace);
-    const SelPred pr{dist2, K, nullptr, 0.0f};
-    select_count<false><<<dim3(nblocks), dim3(kSelBlock), 0, s>>>(pr, logn, total, sums);
-    RTSDF_CHECK_LAUNCH();
-    select_scan<<<dim3(1), dim3(1024), 0, s>>>(sums, nblocks, 1u << (3 * logr), count, queue_cap);
-    RTSDF_CHECK_LAUNCH();
-    select_scatter<false><<<dim3(nblocks), dim3(kSelBlock), 0, s>>>(pr, logn, total, sums, logr, fine.n, queue,
-                                                                     queue_cap);
-    RTSDF_CHECK_LAUNCH();
-    const int64_t nquads = (int64_t)fine.n * fine.n * fine.n / 4;
-    select_mask<false><<<dim3((unsigned)((nquads + 255) / 256)), dim3(256), 0, s>>>(
-        pr, logn, logr, fine.n, nquads, reinterpret_cast<uint32_t *>(mask));
-    RTSDF_CHECK_LAUNCH();
-    return RTSDF_OK;
+    if (!select_args_ok(coarse, dist2, fine, beta, d, mask, queue, queue_cap, count) || !workspace)
+        return RTSDF_EINVAL;
+    return select_run(coarse, dist2, fine, beta, d, mask, queue, queue_cap, count, static_cast<uint32_t *>(workspace),
+                      as_stream(stream));
 }
 
 extern "C" int rtsdf_coarse_trilinear(rtsdf_grid coarse, const float *coarse_sdf, rtsdf_grid fine, float *fine_c,

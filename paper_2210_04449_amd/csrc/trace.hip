@@ -320,6 +320,7 @@ struct TraceArgs {
     int32_t *spill;              // deep stack entries: [(depth - SL) * spill_stride + lane]
     int spill_stride;            // lanes in the launch
     int bin_directions;          // sort each tile's rays by direction bin
+    int tile_cap;                // texels per wavefront tile at most (16, 32 or 64)
     float4 *dirs;                // per wavefront: kTileRays directions of its current tile
 };
 
@@ -327,7 +328,13 @@ constexpr int kTraceWaves = 4;
 constexpr int kTileRays = 768;  // rays per wavefront tile
 constexpr int kTileTexels = 64;
 
-__host__ __device__ __forceinline__ int tile_texels_for(int rays) { return rays >= kTileRays ? 1 : min(kTileTexels, kTileRays / rays); }
+// frame indices share the argmin record with the ray index (frame << 8 | ray)
+constexpr uint32_t kMaxFrame = 1u << 23;
+
+__host__ __device__ __forceinline__ int tile_texels_for(int rays, int cap)
+{
+    return rays >= kTileRays ? 1 : min(cap, kTileRays / rays);
+}
 
 typedef __attribute__((address_space(3))) int lds_int;
 
@@ -485,21 +492,21 @@ struct WaveTile {
 };
 
 // Tiles of a scene: ceil(min(count, cap) / tile texels).
-__device__ __forceinline__ int scene_tiles(const TraceScene &P)
+__device__ __forceinline__ int scene_tiles(const TraceScene &P, int cap)
 {
     const int total = min(*P.count, P.queue_cap);
-    const int tt = tile_texels_for(P.rays);
+    const int tt = tile_texels_for(P.rays, cap);
     return total > 0 ? (total + tt - 1) / tt : 0;
 }
 
 // Global tile prefix of a batch: tile_offset[s] = sum of tiles of scenes < s.
-__global__ void trace_tile_prefix(const TraceScene *scenes, int n, int32_t *tile_offset)
+__global__ void trace_tile_prefix(const TraceScene *scenes, int n, int cap, int32_t *tile_offset)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int acc = 0;
     for (int s = 0; s < n; ++s) {
         tile_offset[s] = acc;
-        acc += scene_tiles(scenes[s]);
+        acc += scene_tiles(scenes[s], cap);
     }
     tile_offset[n] = acc;
 }
@@ -542,7 +549,13 @@ trace_persistent(TraceArgs A)
     float4 *dirs = A.dirs + ((int64_t)blockIdx.x * kTraceWaves + wave) * kTileRays;
     const int stride = A.spill_stride;
     const uint32_t frame = A.frame_ptr ? *A.frame_ptr : A.frame;
-    const int single_tiles = BATCHED ? 0 : scene_tiles(A.one);
+    if (frame >= kMaxFrame) {
+        // a device frame counter past the argmin record's range: trace nothing (the state keeps the
+        // previous frame's values) and report it
+        if (blockIdx.x == 0 && threadIdx.x == 0) raise_error(RTSDF_ERR_FRAME);
+        return;
+    }
+    const int single_tiles = BATCHED ? 0 : scene_tiles(A.one, A.tile_cap);
     const int all_tiles = BATCHED ? A.tile_offset[A.nscenes] : single_tiles;
 
     while (true) {
@@ -568,7 +581,7 @@ trace_persistent(TraceArgs A)
         // reciprocal, q / 2^32, stays below the distance 1/R of q / R from the next integer)
         const uint32_t rdiv = R > 1 ? (uint32_t)(((1ull << 32) + (uint64_t)R - 1) / (uint64_t)R) : 0u;
         const int nfm = P.nf - 1;
-        const int tile_texels = tile_texels_for(R);
+        const int tile_texels = tile_texels_for(R, A.tile_cap);
         const int total = min(*P.count, P.queue_cap);
         const int base = (g - (BATCHED ? A.tile_offset[s] : 0)) * tile_texels;
         const int nt = min(tile_texels, total - base);
@@ -997,14 +1010,26 @@ __global__ void __launch_bounds__(256) trace_backward_kernel(const float *__rest
 
 // ------------------------------------------------------------- launch ----
 
-static rtsdf_trace_tuning g_tuning = {16, 0, 0, 3, 1, 12};
-constexpr int kMaxBlocksPerCu = 8;  // persistent workgroups per CU (spill area sized for this)
+static rtsdf_trace_tuning g_tuning = {16, 0, 0, 3, 1, 12, 64};
+constexpr int kMaxBlocksPerCu = 8;  // persistent workgroups per CU (direction buffers and spill area sized for this)
 constexpr int kMinShortStack = 12;  // smallest LDS stack part (spill area sized for this)
+constexpr int kMaxStackDepth = 64;  // deepest hierarchy the tracer takes
+
+static bool tuning_ok(const rtsdf_trace_tuning &t)
+{
+    if (t.refill != 8 && t.refill != 16) return false;
+    if (t.blocks_per_cu < 0 || t.blocks_per_cu > kMaxBlocksPerCu) return false;
+    if (t.stats < 0 || t.stats > 1 || t.loop < 0 || t.loop > 3) return false;
+    if (t.bin_directions < 0 || t.bin_directions > 1) return false;
+    if (t.stack_lds != 12 && t.stack_lds != 16 && t.stack_lds != 24) return false;
+    if (t.tile_texels != 16 && t.tile_texels != 32 && t.tile_texels != 64) return false;
+    return true;
+}
 
 template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED, bool INST = false>
-static int launch_trace5(TraceArgs A, hipStream_t s)
+static int launch_trace5(TraceArgs A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
-    int per_cu = g_tuning.blocks_per_cu;
+    int per_cu = T.blocks_per_cu;
     if (per_cu <= 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent<SL, REFILL, LOOP, STATS, BATCHED>,
                                                          kTraceWaves * kWave, 0) != hipSuccess ||
@@ -1014,104 +1039,111 @@ static int launch_trace5(TraceArgs A, hipStream_t s)
     per_cu = std::min(per_cu, kMaxBlocksPerCu);
     const int blocks = num_cus() * per_cu;
     A.spill_stride = blocks * kTraceWaves * kWave;
+    A.bin_directions = T.bin_directions;
+    A.tile_cap = T.tile_texels;
     trace_persistent<SL, REFILL, LOOP, STATS, BATCHED, INST><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
     RTSDF_CHECK_LAUNCH();
     return RTSDF_OK;
 }
 
 template <int SL, int REFILL, int LOOP, bool BATCHED>
-static int launch_trace4(const TraceArgs &A, hipStream_t s)
+static int launch_trace4(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
-    return g_tuning.stats ? launch_trace5<SL, REFILL, LOOP, true, BATCHED>(A, s)
-                          : launch_trace5<SL, REFILL, LOOP, false, BATCHED>(A, s);
+    return T.stats ? launch_trace5<SL, REFILL, LOOP, true, BATCHED>(A, T, s)
+                   : launch_trace5<SL, REFILL, LOOP, false, BATCHED>(A, T, s);
 }
 
 template <int SL, int REFILL, bool BATCHED>
-static int launch_trace3(const TraceArgs &A, hipStream_t s)
+static int launch_trace3(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
-    switch (g_tuning.loop) {
-    case 0: return launch_trace4<SL, REFILL, 0, BATCHED>(A, s);
-    case 1: return launch_trace4<SL, REFILL, 1, BATCHED>(A, s);
-    case 2: return launch_trace4<SL, REFILL, 2, BATCHED>(A, s);
-    default: return launch_trace4<SL, REFILL, 3, BATCHED>(A, s);
+    switch (T.loop) {
+    case 0: return launch_trace4<SL, REFILL, 0, BATCHED>(A, T, s);
+    case 1: return launch_trace4<SL, REFILL, 1, BATCHED>(A, T, s);
+    case 2: return launch_trace4<SL, REFILL, 2, BATCHED>(A, T, s);
+    default: return launch_trace4<SL, REFILL, 3, BATCHED>(A, T, s);
     }
 }
 
 template <int SL, bool BATCHED>
-static int launch_trace2(const TraceArgs &A, hipStream_t s)
+static int launch_trace2(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
-    return g_tuning.refill == 8 ? launch_trace3<SL, 8, BATCHED>(A, s) : launch_trace3<SL, 16, BATCHED>(A, s);
+    return T.refill == 8 ? launch_trace3<SL, 8, BATCHED>(A, T, s) : launch_trace3<SL, 16, BATCHED>(A, T, s);
 }
 
 // two-level scenes: the one-fetch loop only
 template <int SL, int REFILL>
-static int launch_trace_inst2(const TraceArgs &A, hipStream_t s)
+static int launch_trace_inst2(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
-    return g_tuning.stats ? launch_trace5<SL, REFILL, 3, true, false, true>(A, s)
-                          : launch_trace5<SL, REFILL, 3, false, false, true>(A, s);
+    return T.stats ? launch_trace5<SL, REFILL, 3, true, false, true>(A, T, s)
+                   : launch_trace5<SL, REFILL, 3, false, false, true>(A, T, s);
 }
 
 template <int SL>
-static int launch_trace_inst1(const TraceArgs &A, hipStream_t s)
+static int launch_trace_inst1(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
-    return g_tuning.refill == 8 ? launch_trace_inst2<SL, 8>(A, s) : launch_trace_inst2<SL, 16>(A, s);
+    return T.refill == 8 ? launch_trace_inst2<SL, 8>(A, T, s) : launch_trace_inst2<SL, 16>(A, T, s);
 }
 
-static int launch_trace_inst(const TraceArgs &A, hipStream_t s)
+static int launch_trace_inst(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
-    switch (g_tuning.stack_lds) {
-    case 12: return launch_trace_inst1<12>(A, s);
-    case 24: return launch_trace_inst1<24>(A, s);
-    default: return launch_trace_inst1<16>(A, s);
+    switch (T.stack_lds) {
+    case 12: return launch_trace_inst1<12>(A, T, s);
+    case 24: return launch_trace_inst1<24>(A, T, s);
+    default: return launch_trace_inst1<16>(A, T, s);
     }
 }
 
 template <bool BATCHED>
-static int launch_trace(const TraceArgs &A, hipStream_t s)
+static int launch_trace(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
-    switch (g_tuning.stack_lds) {
-    case 12: return launch_trace2<12, BATCHED>(A, s);
-    case 24: return launch_trace2<24, BATCHED>(A, s);
-    default: return launch_trace2<16, BATCHED>(A, s);
+    switch (T.stack_lds) {
+    case 12: return launch_trace2<12, BATCHED>(A, T, s);
+    case 24: return launch_trace2<24, BATCHED>(A, T, s);
+    default: return launch_trace2<16, BATCHED>(A, T, s);
     }
 }
 
 static int stack_depth_for(const rtsdf_scene *sc) { return sc->max_depth + 1; }
 
-// spill area for stack entries beyond the LDS part (allocated once per scene)
-static int ensure_spill(rtsdf_scene *sc)
+// the tuning a trace of this scene uses: its own if set, else the process default
+static const rtsdf_trace_tuning &tuning_for(const rtsdf_scene *sc)
 {
-    const int deep = stack_depth_for(sc) - kMinShortStack;
-    if (deep <= 0) return RTSDF_OK;
-    const int64_t lanes = (int64_t)num_cus() * kMaxBlocksPerCu * kTraceWaves * kWave;
-    const int64_t need = lanes * deep;
-    if (sc->spill && sc->spill_entries >= need) return RTSDF_OK;
-    if (sc->spill) (void)hipFree(sc->spill);
-    sc->spill = nullptr;
-    sc->spill_entries = 0;
-    if (hipMalloc((void **)&sc->spill, sizeof(int32_t) * need) != hipSuccess) return RTSDF_ENOMEM;
-    sc->spill_entries = need;
-    sc->bytes += (int64_t)sizeof(int32_t) * need;
-    return RTSDF_OK;
+    return sc->has_tuning ? sc->tuning : g_tuning;
 }
 
-// trace workspace: 256 B of counters, then the wavefronts' direction buffers
-static size_t dirs_bytes()
-{
-    return (size_t)num_cus() * kMaxBlocksPerCu * kTraceWaves * kTileRays * sizeof(float4);
-}
+// Trace workspace: 256 B of counters, the wavefronts' direction buffers, then
+// the spill area for stack entries deeper than the LDS part (per lane of the
+// largest launch, for the deepest hierarchy the tracer takes).  Everything a
+// launch writes besides its outputs lives here, so launches with separate
+// workspaces can run concurrently, on one scene too.
+static size_t trace_lanes_max() { return (size_t)num_cus() * kMaxBlocksPerCu * kTraceWaves * kWave; }
+static size_t dirs_bytes() { return (size_t)num_cus() * kMaxBlocksPerCu * kTraceWaves * kTileRays * sizeof(float4); }
+static size_t spill_bytes() { return trace_lanes_max() * (kMaxStackDepth - kMinShortStack) * sizeof(int32_t); }
+static size_t trace_ws_bytes() { return 256 + dirs_bytes() + spill_bytes(); }
+static float4 *ws_dirs(void *ws) { return reinterpret_cast<float4 *>(static_cast<char *>(ws) + 256); }
+static int32_t *ws_spill(void *ws) { return reinterpret_cast<int32_t *>(static_cast<char *>(ws) + 256 + dirs_bytes()); }
 
 }  // namespace rtsdf
 
 extern "C" int rtsdf_trace_config(const rtsdf_trace_tuning *t)
 {
-    if (!t) return RTSDF_EINVAL;
-    if (t->refill != 8 && t->refill != 16) return RTSDF_EINVAL;
-    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return RTSDF_EINVAL;
-    if (t->stats < 0 || t->stats > 1 || t->loop < 0 || t->loop > 3) return RTSDF_EINVAL;
-    if (t->bin_directions < 0 || t->bin_directions > 1) return RTSDF_EINVAL;
-    if (t->stack_lds != 12 && t->stack_lds != 16 && t->stack_lds != 24) return RTSDF_EINVAL;
+    if (!t || !rtsdf::tuning_ok(*t)) return RTSDF_EINVAL;
     rtsdf::g_tuning = *t;
+    return RTSDF_OK;
+}
+
+extern "C" int rtsdf_scene_set_tuning(rtsdf_scene *scene, const rtsdf_trace_tuning *t)
+{
+    if (!scene || (t && !rtsdf::tuning_ok(*t))) return RTSDF_EINVAL;
+    scene->has_tuning = t != nullptr;
+    if (t) scene->tuning = *t;
+    return RTSDF_OK;
+}
+
+extern "C" int rtsdf_scene_get_tuning(const rtsdf_scene *scene, rtsdf_trace_tuning *t)
+{
+    if (!scene || !t) return RTSDF_EINVAL;
+    *t = rtsdf::tuning_for(scene);
     return RTSDF_OK;
 }
 
@@ -1133,7 +1165,7 @@ extern "C" int rtsdf_accum_reset(rtsdf_grid fine, rtsdf_accum st, rtsdf_stream s
     return RTSDF_OK;
 }
 
-extern "C" size_t rtsdf_trace_workspace_size(void) { return 256 + rtsdf::dirs_bytes(); }
+extern "C" size_t rtsdf_trace_workspace_size(void) { return rtsdf::trace_ws_bytes(); }
 
 extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const float *coarse_sdf,
                                       rtsdf_grid fine, const uint8_t *mask, const int32_t *queue, const int32_t *count,
@@ -1149,10 +1181,10 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     if (queue_cap < 0 || (queue_cap > 0 && !queue)) return RTSDF_EINVAL;
     if (rays_per_texel < 1 || rays_per_texel > 64) return RTSDF_EINVAL;
     if (!(alpha >= 0.0f && alpha <= 1.0f)) return RTSDF_EINVAL;
-    if (frame >= (1u << 23) && !frame_ptr) return RTSDF_EINVAL;
+    if (frame >= kMaxFrame && !frame_ptr) return RTSDF_EINVAL;
     const int sd = stack_depth_for(scene);
-    if (sd > 64) return RTSDF_EINVAL;
-    if (!scene->spill && sd > kMinShortStack) return RTSDF_EINVAL;  // created without its spill area
+    if (sd > kMaxStackDepth) return RTSDF_EINVAL;
+    const rtsdf_trace_tuning &T = tuning_for(scene);
     if (scene->nt >= (1 << 26)) return RTSDF_EINVAL;  // triangle ids share a 64-bit key with the distance
     hipStream_t s = as_stream(stream);
     const int lognf = ilog2(fine.n), logr = ilog2(fine.n / coarse.n);
@@ -1161,7 +1193,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
         mask, coarse_sdf, coarse.n, logr, lognf, ntex, st.u, st.hits, st.arg_tri, st.arg_ray, fine_sdf);
     RTSDF_CHECK_LAUNCH();
     int32_t *cursor = static_cast<int32_t *>(workspace);
-    int rc = launch_fill<int32_t>(cursor, 0, g_tuning.stats ? 32 : 1, s);
+    int rc = launch_fill<int32_t>(cursor, 0, T.stats ? 32 : 1, s);
     if (rc != RTSDF_OK) return rc;
     TraceArgs A{};
     TraceScene &P = A.one;
@@ -1198,11 +1230,10 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     A.frame = frame;
     A.frame_ptr = frame_ptr;
     A.seed = seed;
-    A.spill = scene->spill;
+    A.spill = ws_spill(workspace);
     A.spill_stride = 0;
-    A.bin_directions = g_tuning.bin_directions;
-    A.dirs = reinterpret_cast<float4 *>(static_cast<char *>(workspace) + 256);
-    return scene->ninst > 0 ? launch_trace_inst(A, s) : launch_trace<false>(A, s);
+    A.dirs = ws_dirs(workspace);
+    return scene->ninst > 0 ? launch_trace_inst(A, T, s) : launch_trace<false>(A, T, s);
 }
 
 extern "C" int rtsdf_directions(const int32_t *texel, const uint32_t *frame, const int32_t *ray, int32_t n,
@@ -1224,7 +1255,7 @@ extern "C" int rtsdf_closest_hits(const rtsdf_scene *scene, const float *origins
     if (scene->ninst > 0) return RTSDF_EINVAL;  // single-level scenes only
     if (n == 0) return RTSDF_OK;
     const int sd = stack_depth_for(scene);
-    if (sd > 64) return RTSDF_EINVAL;
+    if (sd > kMaxStackDepth) return RTSDF_EINVAL;
     BvhView S{scene->nodes, scene->tris, scene->tmap};
     hipStream_t s = as_stream(stream);
     const dim3 g((n + 255) / 256), b(256);

@@ -19,7 +19,7 @@ _P = C.c_void_p
 _i32, _u32, _u64, _f32, _sz = C.c_int32, C.c_uint32, C.c_uint64, C.c_float, C.c_size_t
 
 OK, EINVAL, ENOMEM, EHIP, EDEVICE = 0, -1, -2, -3, -4
-ERR_FACE_INDEX, ERR_VERTEX_RANGE, ERR_QUEUE_FULL, ERR_BATCH, ERR_TRANSFORM = 1, 2, 4, 8, 16
+ERR_FACE_INDEX, ERR_VERTEX_RANGE, ERR_QUEUE_FULL, ERR_BATCH, ERR_TRANSFORM, ERR_FRAME = 1, 2, 4, 8, 16, 32
 
 
 class Grid(C.Structure):
@@ -68,7 +68,7 @@ class BatchView(C.Structure):
 
 class TraceTuning(C.Structure):
     _fields_ = [("refill", _i32), ("blocks_per_cu", _i32), ("stats", _i32), ("loop", _i32),
-                ("bin_directions", _i32), ("stack_lds", _i32)]
+                ("bin_directions", _i32), ("stack_lds", _i32), ("tile_texels", _i32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -89,7 +89,7 @@ class RtsdfError(RuntimeError):
 
 
 def _load():
-    path = os.environ.get("RTSDF_LIBRARY") or LIB  # another build of the same library, e.g. for A/B timing
+    path = LIB  # always the in-tree build of the checked-out sources
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_2210_04449_amd.build` (hipcc, gfx950)")
     L = C.CDLL(path)
@@ -116,6 +116,9 @@ def _load():
                                     Accum, _P, _P, _P], _i32),
         "rtsdf_trace_config": ([C.POINTER(TraceTuning)], _i32),
         "rtsdf_trace_config_get": ([C.POINTER(TraceTuning)], _i32),
+        "rtsdf_scene_set_tuning": ([_P, C.POINTER(TraceTuning)], _i32),
+        "rtsdf_scene_get_tuning": ([_P, C.POINTER(TraceTuning)], _i32),
+        "rtsdf_batch_set_tuning": ([_P, C.POINTER(TraceTuning)], _i32),
         "rtsdf_directions": ([_P, _P, _P, _i32, _u64, _u32, _P, _P], _i32),
         "rtsdf_closest_hits": ([_P, _P, _P, _i32, _P, _P, _P, _P], _i32),
         "rtsdf_trace_backward": ([_P, Grid, Accum, _P, _P, _u64, _u32, _P, _P], _i32),
@@ -308,6 +311,20 @@ class Scene:
 
     def rebuild(self, vertices, stream=None):
         _check("rtsdf_scene_rebuild", _lib.rtsdf_scene_rebuild(self.handle, _ptr(vertices), _stream(stream)))
+
+    def set_tuning(self, **kw):
+        """Give this scene its own tracer tuning (fields of rtsdf_trace_tuning over the tuning it uses now);
+        clear_tuning() goes back to the process default."""
+        t = TraceTuning(**{**self.tuning().as_dict(), **kw})
+        _check("rtsdf_scene_set_tuning", _lib.rtsdf_scene_set_tuning(self.handle, C.byref(t)))
+
+    def clear_tuning(self):
+        _check("rtsdf_scene_set_tuning", _lib.rtsdf_scene_set_tuning(self.handle, None))
+
+    def tuning(self) -> TraceTuning:
+        t = TraceTuning()
+        _check("rtsdf_scene_get_tuning", _lib.rtsdf_scene_get_tuning(self.handle, C.byref(t)))
+        return t
 
     def info(self) -> SceneInfo:
         inf = SceneInfo()
@@ -505,10 +522,22 @@ class Batch:
                                                              _stream(stream)))
         self.handle = h
         self.n = len(scenes)
+        self.descriptors = [dict(fine_n=int(d["fine_n"]), coarse_n=int(d["coarse_n"]), nt=int(d["faces"].shape[0]),
+                                 rays=int(d["rays"])) for d in scenes]
         self._keep = []  # the batch copied the meshes
 
     def step(self, frame: int, frame_ptr=None, stream=None):
         _check("rtsdf_batch_step", _lib.rtsdf_batch_step(self.handle, int(frame), _ptr(frame_ptr), _stream(stream)))
+
+    def set_tuning(self, **kw):
+        """Give this batch its own tracer tuning (fields of rtsdf_trace_tuning over the process default)."""
+        t = TraceTuning(**{**rtsdf_trace_config_get().as_dict(), **getattr(self, "_tuning", {}), **kw})
+        _check("rtsdf_batch_set_tuning", _lib.rtsdf_batch_set_tuning(self.handle, C.byref(t)))
+        self._tuning = t.as_dict()
+
+    def clear_tuning(self):
+        _check("rtsdf_batch_set_tuning", _lib.rtsdf_batch_set_tuning(self.handle, None))
+        self._tuning = {}
 
     def reset(self, stream=None):
         _check("rtsdf_batch_reset", _lib.rtsdf_batch_reset(self.handle, _stream(stream)))

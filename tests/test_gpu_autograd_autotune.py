@@ -90,25 +90,67 @@ def test_autotune_applies_valid_tuning_and_keeps_results(R, tmp_path):
     from paper_2210_04449_amd import autotune
     w = workload("tiny")
     default = R.rtsdf_trace_config_get().as_dict()
-    try:
-        ref = pipe(w)
-        for f in range(3):
-            ref.step(f)
-        p = pipe(w)
-        space = {"refill": (8, 16), "stack_lds": (12, 24), "bin_directions": (0, 1), "loop": (3,),
-                 "blocks_per_cu": (0,)}
-        cache = str(tmp_path / "tune.json")
-        res = autotune.tune(p, reps=1, space=space, cache=cache)
-        assert not res["cached"] and len(res["trials"]) == 8
-        got = R.rtsdf_trace_config_get().as_dict()
-        for k, v in res["tuning"].items():
-            assert got[k] == v, k
-        # state was reset: a fresh run under the tuned config equals the default run bitwise
-        for f in range(3):
-            p.step(f)
-        torch.cuda.synchronize()
-        assert torch.equal(p.fine_sdf, ref.fine_sdf) and torch.equal(p.state.arg_tri, ref.state.arg_tri)
-        again = autotune.tune(p, cache=cache)
-        assert again["cached"] and again["tuning"] == res["tuning"]
-    finally:
-        R.rtsdf_trace_config(**default)
+    ref = pipe(w)
+    for f in range(3):
+        ref.step(f)
+    p = pipe(w)
+    space = {"blocks_per_cu": (0, 3), "tile_texels": (64, 16), "stack_lds": (12, 24), "loop": (3,)}
+    cache = str(tmp_path / "tune.json")
+    res = autotune.tune(p, reps=1, space=space, cache=cache)
+    assert not res["cached"] and len(res["trials"]) == 8
+    got = p.scene.tuning().as_dict()
+    for k, v in res["tuning"].items():
+        assert got[k] == v, k
+    assert R.rtsdf_trace_config_get().as_dict() == default  # applied to the scene, not the process
+    # state was reset: a fresh run under the tuned config equals the default run bitwise
+    for f in range(3):
+        p.step(f)
+    torch.cuda.synchronize()
+    assert torch.equal(p.fine_sdf, ref.fine_sdf) and torch.equal(p.state.arg_tri, ref.state.arg_tri)
+    again = autotune.tune(p, cache=cache)
+    assert again["cached"] and again["tuning"] == res["tuning"]
+    # the default space by coordinate descent: every knob is tried, results unchanged
+    p2 = pipe(w)
+    res2 = autotune.tune(p2, reps=1, cache=None)
+    tried = {k: {t[k] for t, _ in res2["trials"]} for k in autotune.SPACE}
+    for k, vals in autotune.SPACE.items():
+        assert tried[k] == set(vals), (k, tried[k])
+    for f in range(3):
+        p2.step(f)
+    torch.cuda.synchronize()
+    assert torch.equal(p2.fine_sdf, ref.fine_sdf) and torch.equal(p2.state.u, ref.state.u)
+
+
+def test_batch_autotune_applies_to_the_batch(R, tmp_path):
+    say("batch autotune")
+    from paper_2210_04449_amd import autotune
+    from synth.scenes import batched_scenes
+    ws = batched_scenes(4)
+    dev = torch.device("cuda:0")
+    descs = [dict(vertices=torch.from_numpy(w.mesh.vertices).to(dev), faces=torch.from_numpy(w.mesh.faces).to(dev),
+                  coarse_n=w.nc, fine_n=w.nf, beta=w.beta, d=w.d, rays=w.rays, scene_id=w.scene_seed) for w in ws]
+    B0, B1 = R.Batch(descs, seed=0), R.Batch(descs, seed=0)
+    for f in range(2):
+        B0.step(f)
+    default = R.rtsdf_trace_config_get().as_dict()
+    res = autotune.tune(B1, reps=1, space={"tile_texels": (64, 16), "blocks_per_cu": (0, 4)},
+                        cache=str(tmp_path / "b.json"))
+    assert "batch4" in res["key"] and len(res["trials"]) == 4
+    assert R.rtsdf_trace_config_get().as_dict() == default
+    for f in range(2):
+        B1.step(f)
+    torch.cuda.synchronize()
+    for i in range(len(ws)):
+        a, b = B0.tensors(i), B1.tensors(i)
+        assert torch.equal(a["fine_sdf"], b["fine_sdf"]) and torch.equal(a["u"], b["u"]), i
+
+
+def test_fine_sdf_refuses_decay(R):
+    say("FineSDF alpha")
+    from paper_2210_04449_amd.autograd import fine_sdf
+    w = workload("tiny")
+    p = pipe(w)
+    p.alpha = 0.9
+    v = p.vertices.clone().requires_grad_(True)
+    with pytest.raises(ValueError):
+        fine_sdf(v, p, range(2))

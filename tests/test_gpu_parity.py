@@ -322,13 +322,15 @@ def test_trace_determinism_and_resume(R):
 @pytest.mark.parametrize("case", ["tiny", "room"])
 def test_trace_tunings_agree_bitwise(R, case):
     """The tracer's tuning (loop shape, refill threshold, LDS stack depth,
-    direction sorting, workgroups per CU) changes speed only: every setting
+    direction sorting, workgroups per CU, tile size) changes speed only: every setting
     gives the default setting's state and output bit for bit."""
     w = workload(case)
     frames = range(3) if case == "tiny" else range(1)
     default = R.rtsdf_trace_config_get().as_dict()
     settings = [dict(loop=0), dict(loop=1), dict(loop=2), dict(loop=3, refill=8), dict(loop=1, stack_lds=24),
-                dict(loop=2, stack_lds=16, bin_directions=0), dict(loop=2, blocks_per_cu=2)]
+                dict(loop=2, stack_lds=16, bin_directions=0), dict(loop=2, blocks_per_cu=2),
+                dict(tile_texels=16, blocks_per_cu=3), dict(tile_texels=32, blocks_per_cu=5, stack_lds=16),
+                dict(blocks_per_cu=4, refill=8, tile_texels=16)]
     try:
         say("tunings", case, "default", default)
         ref = run_gpu(R, w, frames)
