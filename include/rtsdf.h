@@ -420,6 +420,12 @@ int rtsdf_scene_get_tuning(const rtsdf_scene *scene, rtsdf_trace_tuning *tuning)
 int rtsdf_directions(const int32_t *texel, const uint32_t *frame, const int32_t *ray, int32_t n,
                      uint64_t seed, uint32_t scene_id, float *out, rtsdf_stream stream);
 
+/* The float32 square root every stage takes (ray directions, coarse SDF,   */
+/* shadow triangulation), correctly rounded: out[i] = sqrt(x[i]) for n      */
+/* values (device arrays).  Exported so callers and tests can check it     */
+/* bit for bit against another IEEE implementation.                         */
+int rtsdf_sqrt(const float *x, int64_t n, float *out, rtsdf_stream stream);
+
 /* Closest hits of arbitrary rays (float32 origins and directions [n][3]):   */
 /* t_out float32 (+inf on a miss), tri_out int32 (-1 on a miss), front_out   */
 /* int32 (1 front, 0 back or miss).  Same traversal as the tracer.           */

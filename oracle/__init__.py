@@ -70,7 +70,7 @@ def lib():
         L.oracle_fine_value.restype = f64
         L.oracle_closest_hits.argtypes = [P, i32, P, P, P, P, P, P]
         L.oracle_trace_frame.argtypes = [P, i32, P, i32, P, f32, P, P, i32, i32, u32, u64, u32, f64,
-                                         P, P, P, P, P, P, P, P, P, i32, f64]
+                                         P, P, P, P, P, P, P, P, P, P, i32, f64]
         L.oracle_fine_grad.argtypes = [P, i32, P, f32, u64, u32, P, P, P, P, P, P, i32]
         L.oracle_directions.argtypes = [i32, P, P, P, u64, u32, P]
         L.oracle_point_distance.argtypes = [P, i32, P, P, P]
@@ -256,6 +256,7 @@ class TraceState:
         self.arg_ray = np.full(n, -1, np.int32)
         self.arg_tri = np.full(n, -1, np.int32)
         self.arg_amb = np.zeros(n, np.uint8)
+        self.texel_amb = np.zeros(n, np.uint8)
         self.fine = np.zeros(n)
         self.rmin = np.full(n, np.inf)
 
@@ -309,7 +310,8 @@ class Scene:
             self.h, int(nc), _p(cs), int(nf), _p(lo), float(hf), _p(m), _p(tx), ntex, int(rays),
             int(frame), int(seed), int(scene), float(alpha),
             _p(state.u), _p(state.nfront), _p(state.nback), _p(state.arg_frame), _p(state.arg_ray),
-            _p(state.arg_tri), _p(state.arg_amb), _p(state.fine), _p(state.rmin), SIGN_POLICIES[sign_policy],
+            _p(state.arg_tri), _p(state.arg_amb), _p(state.texel_amb), _p(state.fine), _p(state.rmin),
+            SIGN_POLICIES[sign_policy],
             float(shell))
         if rc != 0:
             raise ValueError("oracle_trace_frame: invalid arguments")

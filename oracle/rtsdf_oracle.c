@@ -532,7 +532,9 @@ void oracle_texel_origin(int nf, const float lo[3], float h, int j, float o[3])
 /* A ray is flagged ambiguous when a float32 evaluation could legitimately   */
 /* pick a different closest triangle: some triangle whose plane is crossed   */
 /* no farther than the closest hit (plus a margin) is crossed within 1e-6 of */
-/* one of its edges, or the closest hit grazes its triangle (|cos| < 1e-2).  */
+/* one of its edges, another triangle is hit within that margin of the      */
+/* closest hit (two surfaces meeting there), or the closest hit grazes its   */
+/* triangle (|cos| < 1e-2).                                                  */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -761,14 +763,20 @@ static void test_tri(const oracle_scene *s, int t, const double o[3], const doub
     }
 }
 
-/* second sweep over candidates for the ambiguity flag */
-static void amb_tri(const oracle_scene *s, int t, const double o[3], const double d[3], double tlim, int *amb)
+/* second sweep over candidates for the ambiguity flag: a crossing near an   */
+/* edge, or a second triangle hit no farther than the margin past the best   */
+static void amb_tri(const oracle_scene *s, int t, const double o[3], const double d[3], double tlim, int best_tri,
+                    int *amb)
 {
     const double *v0 = &s->v[3 * s->f[3 * t]], *v1 = &s->v[3 * s->f[3 * t + 1]], *v2 = &s->v[3 * s->f[3 * t + 2]];
     double tt, u, w;
     int valid;
-    mt_intersect(o, d, v0, v1, v2, &tt, &u, &w, &valid);
+    const int hit = mt_intersect(o, d, v0, v1, v2, &tt, &u, &w, &valid);
     if (!valid || !(tt > -1e-6) || tt > tlim) return;
+    if (hit && t != best_tri) {
+        *amb = 1;
+        return;
+    }
     const double tol = -1e-3; /* only crossings close to the triangle matter */
     if (u < tol || w < tol || u + w > 1.0 - tol) return;
     if (near_edge(v0, v1, v2, u, w)) *amb = 1;
@@ -796,7 +804,7 @@ static void visit(const oracle_scene *s, const double o[3], const double d[3], o
 {
     if (!s->use_bvh) {
         for (int t = 0; t < s->nt; ++t) {
-            if (amb_pass) amb_tri(s, t, o, d, tlim, amb);
+            if (amb_pass) amb_tri(s, t, o, d, tlim, best->tri, amb);
             else test_tri(s, t, o, d, best);
         }
         return;
@@ -810,7 +818,7 @@ static void visit(const oracle_scene *s, const double o[3], const double d[3], o
         if (!box_hit(nd, o, d, lim)) continue;
         if (nd->count > 0) {
             for (int i = nd->start; i < nd->start + nd->count; ++i) {
-                if (amb_pass) amb_tri(s, s->perm[i], o, d, tlim, amb);
+                if (amb_pass) amb_tri(s, s->perm[i], o, d, tlim, best->tri, amb);
                 else test_tri(s, s->perm[i], o, d, best);
             }
         } else {
@@ -909,6 +917,24 @@ double oracle_fine_value(double u, float c, int nfront, int nback, int sign_poli
     return nback > nfront ? -u : u;
 }
 
+/* Two distances closer than this (relative) may compare either way once     */
+/* evaluated in float32: the texel's argmin record is then not unique.       */
+#define TIE_REL 3e-5
+
+static int near_tie(double a, double b)
+{
+    if (!isfinite(a) || !isfinite(b)) return 0;
+    const double m = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
+    return fabs(a - b) <= TIE_REL * m;
+}
+
+/* texel_amb (sticky while the texel stays selected) marks texels whose      */
+/* sign, front/back counts or argmin record a float32 evaluation could       */
+/* legitimately get differently: one of their rays was ambiguous (above), or */
+/* a frame's two smallest ray distances, or its r_t and the value it was     */
+/* compared with in Eq. (1), are within TIE_REL of each other.  Every other  */
+/* texel's state is unique.  arg_amb marks only texels whose argmin ray      */
+/* itself is ambiguous (their distance may differ beyond rounding).          */
 int oracle_trace_frame(const oracle_scene *s,
                        int nc, const float *coarse_sdf,
                        int nf, const float lo[3], float hf,
@@ -916,6 +942,7 @@ int oracle_trace_frame(const oracle_scene *s,
                        int rays, uint32_t frame, uint64_t seed, uint32_t scene, double alpha,
                        double *u, int *nfront, int *nback,
                        int *arg_frame, int *arg_ray, int *arg_tri, unsigned char *arg_amb,
+                       unsigned char *texel_amb,
                        double *fine, double *rmin_out, int sign_policy, double shell)
 {
     if (nc <= 0 || nf <= 0 || nf % nc != 0 || rays <= 0) return ORC_EINVAL;
@@ -932,6 +959,7 @@ int oracle_trace_frame(const oracle_scene *s,
             nfront[j] = nback[j] = 0;
             arg_frame[j] = arg_ray[j] = arg_tri[j] = -1;
             arg_amb[j] = 0;
+            texel_amb[j] = 0;
             fine[j] = (double)c;
             if (rmin_out) rmin_out[j] = INFINITY;
             continue;
@@ -939,7 +967,7 @@ int oracle_trace_frame(const oracle_scene *s,
         float of[3];
         texel_origin(nf, lo, hf, j, of);
         const double o[3] = {of[0], of[1], of[2]};
-        double rt = INFINITY;
+        double rt = INFINITY, rt2 = INFINITY; /* smallest and second smallest ray distance */
         int best_ray = -1, best_tri = -1, best_amb = 0;
         for (int k = 0; k < rays; ++k) {
             float wf[3];
@@ -947,18 +975,29 @@ int oracle_trace_frame(const oracle_scene *s,
             const double w[3] = {wf[0], wf[1], wf[2]};
             ohit_t h;
             closest_hit(s, o, w, &h);
+            if (h.ambiguous) texel_amb[j] = 1;
             if (h.tri < 0) continue;
             if (h.front) nfront[j] += 1;
             else nback[j] += 1;
             const double dist = h.t * sqrt(dot3(w, w));
             if (dist < rt) {
+                rt2 = rt;
                 rt = dist;
                 best_ray = k;
                 best_tri = h.tri;
                 best_amb = h.ambiguous;
+            } else if (dist < rt2) {
+                rt2 = dist;
             }
         }
         if (rmin_out) rmin_out[j] = rt;
+        if (near_tie(rt, rt2)) texel_amb[j] = 1;
+        {
+            /* the value r_t is compared with in Eq. (1) */
+            int src0;
+            const double decayed = oracle_eq1(alpha, u[j], c, INFINITY, &src0);
+            if (near_tie(rt, decayed)) texel_amb[j] = 1;
+        }
         int src;
         u[j] = oracle_eq1(alpha, u[j], c, rt, &src);
         if (src == 1) {

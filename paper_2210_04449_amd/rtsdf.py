@@ -119,6 +119,7 @@ def _load():
         "rtsdf_scene_set_tuning": ([_P, C.POINTER(TraceTuning)], _i32),
         "rtsdf_scene_get_tuning": ([_P, C.POINTER(TraceTuning)], _i32),
         "rtsdf_batch_set_tuning": ([_P, C.POINTER(TraceTuning)], _i32),
+        "rtsdf_sqrt": ([_P, C.c_int64, _P, _P], _i32),
         "rtsdf_directions": ([_P, _P, _P, _i32, _u64, _u32, _P, _P], _i32),
         "rtsdf_closest_hits": ([_P, _P, _P, _i32, _P, _P, _P, _P], _i32),
         "rtsdf_trace_backward": ([_P, Grid, Accum, _P, _P, _u64, _u32, _P, _P], _i32),
@@ -410,6 +411,15 @@ def rtsdf_trace_accumulate(scene: Scene, coarse: Grid, coarse_sdf, fine: Grid, m
         scene.handle, coarse, _ptr(coarse_sdf), fine, _ptr(mask), _ptr(queue), _ptr(count), queue.numel(),
         int(rays_per_texel), int(frame), _ptr(frame_ptr), int(seed), int(scene_id), float(alpha), state.struct(),
         _ptr(fine_sdf), _ptr(workspace), _stream(stream)))
+
+
+def rtsdf_sqrt(x, out, stream=None):
+    """The library's float32 square root (the one every stage uses), element-wise."""
+    _dtype(x, torch.float32, "x")
+    _dtype(out, torch.float32, "out")
+    if out.numel() < x.numel():
+        raise ValueError("rtsdf_sqrt: out is shorter than x")
+    _check("rtsdf_sqrt", _lib.rtsdf_sqrt(_ptr(x), x.numel(), _ptr(out), _stream(stream)))
 
 
 def rtsdf_directions(texel, frame, ray, seed: int, scene_id: int, out, stream=None):

@@ -106,6 +106,8 @@ def test_host_validation(R):
         assert L.rtsdf_scene_set_tuning(dummy, C.byref(t)) == R.EINVAL  # rejected before the scene is read
         assert L.rtsdf_batch_set_tuning(dummy, C.byref(t)) == R.EINVAL
     assert L.rtsdf_trace_config(None) == R.EINVAL
+    assert L.rtsdf_sqrt(None, 4, dummy, None) == R.EINVAL and L.rtsdf_sqrt(dummy, -1, dummy, None) == R.EINVAL
+    assert L.rtsdf_sqrt(None, 0, None, None) == R.OK  # nothing to do
     good = R.rtsdf_trace_config_get()
     assert L.rtsdf_scene_set_tuning(None, C.byref(good)) == R.EINVAL
     assert L.rtsdf_scene_get_tuning(None, C.byref(good)) == R.EINVAL

@@ -40,18 +40,8 @@ def pipe(v, f, nc, nf, beta, d, rays, **kw):
 
 
 def check_against(p, ref, side=1.0):
-    st = ref["state"]
-    mask = p.mask.cpu().numpy()
-    assert np.array_equal(mask, ref["mask"])
-    fine = p.fine_sdf.cpu().numpy().astype(np.float64)
-    sel = np.nonzero(mask)[0]
-    unsel = np.nonzero(mask == 0)[0]
-    assert np.array_equal(fine[unsel], st.fine[unsel])
-    good = sel[st.arg_amb[sel] == 0]
-    err = np.abs(np.abs(fine[good]) - np.abs(st.fine[good]))
-    assert err.max(initial=0) <= TOL * side, err.max()
-    assert np.mean(np.sign(fine[good]) == np.sign(st.fine[good])) > 0.999
-    return len(sel)
+    from test_gpu_parity import compare_trace
+    return compare_trace(p, ref, tol=TOL * side)["texels"]
 
 
 def test_scene_without_triangles(R):

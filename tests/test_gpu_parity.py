@@ -4,7 +4,10 @@ Bit-exact: voxel occupancy, jump-flooding seeds, D^2 and the coarse SDF, the
 selection mask / queue / count, the ray directions, shadow visibility.
 Within 1e-5 x scene extent (the unit cube): traced fine-SDF values against
 the oracle's float64 distances, excluding texels whose argmin ray the oracle
-flags as ambiguous for a float32 evaluation (those are counted).
+flags as ambiguous for a float32 evaluation (those are counted).  Exact:
+sign, front/back hit counts and the argmin record (frame, ray, triangle) of
+every traced texel the oracle does not flag (a flagged texel had an
+ambiguous ray or two candidate distances within float rounding).
 """
 import math
 import sys
@@ -268,12 +271,19 @@ def run_gpu(R, w, frames, seed=0, alpha=None):
     return p
 
 
-def compare_trace(p, ref, sample=None):
+def compare_trace(p, ref, sample=None, max_flagged=0.02, tol=TOL):
+    """GPU trace state against the oracle's.
+
+    Texels the oracle flags (``texel_amb``: an ambiguous ray, or two candidate distances within float
+    rounding of each other) may legitimately differ in sign, hit counts and argmin; every other selected
+    texel must agree exactly in all of them and in its signed value within the tolerance.  The distance
+    |f| is also checked on flagged texels unless their argmin ray itself is ambiguous (``arg_amb``)."""
     st = ref["state"]
     fine = p.fine_sdf.cpu().numpy()
     u = p.state.u.cpu().numpy()
     hits = p.state.hits.cpu().numpy().view(np.uint32)
     at = p.state.arg_tri.cpu().numpy()
+    ar = p.state.arg_ray.cpu().numpy()
     mask = p.mask.cpu().numpy()
     assert np.array_equal(mask, ref["mask"])
     idx = np.nonzero(mask)[0] if sample is None else sample
@@ -283,15 +293,30 @@ def compare_trace(p, ref, sample=None):
     amb = st.arg_amb[sel] == 1
     good = sel[~amb]
     err = np.abs(np.abs(fine[good].astype(np.float64)) - np.abs(st.fine[good]))
-    assert err.max(initial=0) <= TOL, (err.max(), np.sum(err > TOL))
+    assert err.max(initial=0) <= tol, (err.max(), np.sum(err > tol))
     fin = np.isfinite(st.u[good])
     assert np.array_equal(np.isfinite(u[good]), fin)
-    sign_agree = np.mean(np.sign(fine[good]) == np.sign(st.fine[good]))
-    hit_agree = np.mean((hits[good] & 0xFFFF) == st.nfront[good]) * 0.5 + np.mean((hits[good] >> 16) == st.nback[good]) * 0.5
-    arg_agree = np.mean(at[good] == st.arg_tri[good])
-    assert sign_agree > 0.999 and hit_agree > 0.999 and arg_agree > 0.999, (sign_agree, hit_agree, arg_agree)
-    return dict(texels=len(sel), ambiguous=int(amb.sum()), max_err=float(err.max(initial=0)), sign=sign_agree,
-                hits=hit_agree, arg=arg_agree)
+    flagged = st.texel_amb[sel] == 1
+    assert flagged.mean() <= max_flagged, flagged.mean()
+    ex = sel[~flagged]
+    bad = {
+        "sign": np.sign(fine[ex]) != np.sign(st.fine[ex]),
+        "front": (hits[ex] & 0xFFFF) != st.nfront[ex],
+        "back": (hits[ex] >> 16) != st.nback[ex],
+        "arg_tri": at[ex] != st.arg_tri[ex],
+        "arg_ray": ar[ex] != np.where(st.arg_tri[ex] >= 0, (st.arg_frame[ex] << 8) | np.maximum(st.arg_ray[ex], 0),
+                                      -1),
+        "signed_value": np.abs(fine[ex].astype(np.float64) - st.fine[ex]) > tol,
+    }
+    for k, b in bad.items():
+        if b.any():
+            i = ex[np.argmax(b)]
+            raise AssertionError(f"{k}: {int(b.sum())} of {len(ex)} unflagged texels differ; first texel {i}: "
+                                 f"gpu f {fine[i]} hits {hits[i] & 0xFFFF}/{hits[i] >> 16} arg {at[i]}/{ar[i]}; "
+                                 f"oracle f {st.fine[i]} hits {st.nfront[i]}/{st.nback[i]} "
+                                 f"arg {st.arg_tri[i]}/{st.arg_frame[i]}/{st.arg_ray[i]}")
+    return dict(texels=len(sel), exact=len(ex), flagged=int(flagged.sum()), ambiguous_argmin=int(amb.sum()),
+                max_err=float(err.max(initial=0)))
 
 
 def test_trace_tiny_all_texels(R):
@@ -350,9 +375,9 @@ def test_trace_tunings_agree_bitwise(R, case):
 
 
 def test_trace_room_sampled(R):
-    say("trace room sampled")
+    say("trace room sampled, 8 frames")
     w = workload("room")
-    frames = range(2)
+    frames = range(8)
     p = run_gpu(R, w, frames)
     mask = p.mask.cpu().numpy()
     rng = np.random.default_rng(3)

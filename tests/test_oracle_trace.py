@@ -316,3 +316,61 @@ def test_shell_sign_policy(tiny_run):
     assert np.all(a.fine[sel[below]] < 0) and np.all(b.fine[sel[below]] > -shell)
     assert oracle.fine_value(0.25, 0.5, 1, 3, "shell", 0.0625) == 0.1875
     assert oracle.fine_value(np.inf, 0.5, 1, 3, "shell", 0.0625) == 0.5
+
+
+def test_ambiguity_second_surface_at_the_same_distance():
+    """A ray whose closest hit has another triangle at the same distance (a duplicated quad) is ambiguous,
+    wherever it crosses; with the duplicate removed the same rays are not (away from the diagonal edge)."""
+    q = ground_quad(0.15)
+    dup = np.concatenate([q.faces, q.faces[:, ::-1]]).astype(np.int32)  # same plane, both windings
+    rng = np.random.default_rng(11)
+    o = np.column_stack([rng.uniform(0.3, 0.7, 3000), np.full(3000, 0.5), rng.uniform(0.3, 0.7, 3000)])
+    d = np.column_stack([rng.uniform(-0.2, 0.2, 3000), -np.ones(3000), rng.uniform(-0.2, 0.2, 3000)])
+    hit = np.abs(np.abs(o[:, 0] + (0.35 / 1) * d[:, 0] - (o[:, 2] + 0.35 * d[:, 2])))  # distance to the diagonal
+    _, tri1, _, amb1 = oracle.Scene(q.vertices, q.faces, use_bvh=False).closest_hits(o, d)
+    _, tri2, _, amb2 = oracle.Scene(q.vertices, dup, use_bvh=False).closest_hits(o, d)
+    assert np.all(tri1 >= 0) and np.all(tri2 >= 0)
+    assert np.all(amb2 == 1)
+    assert np.all(amb1[hit > 1e-3] == 0)
+
+
+def test_ambiguity_interpenetrating_surfaces():
+    """Two planes crossing along a line: rays hitting near the crossing line (within the tie margin of the
+    other plane) are ambiguous, rays far from it are not."""
+    y0 = 0.4
+    a = np.array([[0, y0, 0], [1, y0, 0], [1, y0, 1], [0, y0, 1]], np.float32)  # horizontal
+    b = np.array([[0.5, 0, 0], [0.5, 0, 1], [0.5, 1, 1], [0.5, 1, 0]], np.float32)  # vertical x = 0.5
+    v = np.concatenate([a, b])
+    f = np.array([[0, 2, 1], [0, 3, 2], [4, 6, 5], [4, 7, 6]], np.int32)
+    sc = oracle.Scene(v, f, use_bvh=False)
+    xs = np.array([0.5 + 1e-9, 0.5 + 1e-8, 0.45, 0.3])
+    o = np.column_stack([xs - 0.3, np.full(4, y0 + 0.3), np.full(4, 0.37)])
+    d = np.tile([0.3, -0.3, 0.0], (4, 1))  # crosses y0 at x = xs, lands just past the vertical plane or away
+    t, tri, _, amb = sc.closest_hits(o, d)
+    assert list(amb) == [1, 1, 0, 0], amb
+
+
+def test_texel_flags_near_tied_rays_and_history():
+    """The per-texel flag: set when two rays of a frame land within the tie margin, kept while the texel
+    stays selected, reset when it is unselected; and on the tiny scene only a small fraction is flagged."""
+    w = tiny_scene()
+    nc, nf, rays = 32, 64, 4
+    r = oracle.run_frames(w.vertices, w.faces, nc, nf, np.float32(0.5 / nc), np.float32(2 / nc), rays, range(4))
+    st, mask = r["state"], r["mask"]
+    sel = np.nonzero(mask)[0]
+    assert np.all(st.texel_amb[mask == 0] == 0)
+    assert np.all(st.texel_amb[sel] >= st.arg_amb[sel])  # an ambiguous argmin ray flags its texel
+    frac = st.texel_amb[sel].mean()
+    assert 0 < frac < 0.02, frac
+    # the flag is sticky over frames: a fresh state over frames 0..1 flags a subset of frames 0..3's
+    r2 = oracle.run_frames(w.vertices, w.faces, nc, nf, np.float32(0.5 / nc), np.float32(2 / nc), rays, range(2))
+    assert np.all(r2["state"].texel_amb[sel] <= st.texel_amb[sel])
+    # a texel traced with two identical frames: every ray ties with the history -> flagged
+    st3 = oracle.TraceState(nf)
+    sc = r["scene"]
+    t = sel[:200].astype(np.int32)
+    lo, hf = np.zeros(3, np.float32), np.float32(1 / nf)
+    sc.trace_frame(nc, r["coarse"], nf, lo, hf, mask, rays, 5, 0, 0, 1.0, st3, t)
+    finite = np.isfinite(st3.u[t])
+    sc.trace_frame(nc, r["coarse"], nf, lo, hf, mask, rays, 5, 0, 0, 1.0, st3, t)
+    assert np.all(st3.texel_amb[t][finite] == 1)
