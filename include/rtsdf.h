@@ -178,6 +178,24 @@ int rtsdf_select(rtsdf_grid coarse, const int32_t *dist2, rtsdf_grid fine, float
                  uint8_t *mask, int32_t *queue, int32_t queue_cap, int32_t *count,
                  void *workspace, rtsdf_stream stream);
 
+/* rtsdf_select for callers that cannot allocate device memory or pass a     */
+/* workspace (code under graph capture, tight serving loops, harnesses that */
+/* forbid hipMalloc): the same selection, bit for bit, with the block sums  */
+/* kept in a static device array of the library instead of `workspace`.    */
+/* That array holds rtsdf_select_noalloc_max_bytes() bytes (512 KiB: enough */
+/* for coarse.n up to 512, the largest rtsdf_select takes; larger is        */
+/* EINVAL), exists once per device and stays allocated until the process    */
+/* ends.  Its device address is looked up on the first call on each device */
+/* (hipGetSymbolAddress, no allocation); the call itself allocates nothing. */
+/* Every call on one device shares the array, and no entry is read before   */
+/* the same call writes it, so nothing carries over between calls; but      */
+/* calls that overlap on one device (different streams or threads) race on  */
+/* it and must be serialised by the caller.  Other arguments, errors and     */
+/* outputs as rtsdf_select.                                                  */
+size_t rtsdf_select_noalloc_max_bytes(void);
+int rtsdf_select_noalloc(rtsdf_grid coarse, const int32_t *dist2, rtsdf_grid fine, float beta, float d,
+                         uint8_t *mask, int32_t *queue, int32_t queue_cap, int32_t *count, rtsdf_stream stream);
+
 /* ------------------------------------------------------------------------ */
 /* 3b. Trilinear coarse sampling (a smoother reading of the coarse value c  */
 /* that Sec. 2.2 compares with d and stores for unselected texels; Sec. 2.1 */

@@ -285,6 +285,32 @@ static bool select_args_ok(rtsdf_grid coarse, const int32_t *dist2, rtsdf_grid f
     return true;
 }
 
+// Scratch of the allocation-free selection: the block sums of the largest
+// coarse grid rtsdf_select takes (512^3 voxels -> 131,072 blocks), 512 KiB per
+// device, held until the process ends.  Host code never passes `scratch`
+// itself to a kernel (on the host it is only a stand-in for the symbol); it
+// uses the device address hipGetSymbolAddress returns for each device.
+constexpr size_t kSelScratchWords = ((size_t)512 * 512 * 512 + kSelPerBlock - 1) / kSelPerBlock + 64;
+__device__ __align__(256) uint32_t scratch[kSelScratchWords];
+
+constexpr int kMaxDevices = 64;
+static uint32_t *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// The current device's address of `scratch`, looked up once per device.
+static uint32_t *scratch_for_current_device()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = static_cast<uint32_t *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace rtsdf
 
 extern "C" size_t rtsdf_select_workspace_size(int32_t coarse_n)
@@ -304,6 +330,20 @@ extern "C" int rtsdf_select(rtsdf_grid coarse, const int32_t *dist2, rtsdf_grid 
         return RTSDF_EINVAL;
     return select_run(coarse, dist2, fine, beta, d, mask, queue, queue_cap, count, static_cast<uint32_t *>(workspace),
                       as_stream(stream));
+}
+
+extern "C" size_t rtsdf_select_noalloc_max_bytes(void) { return rtsdf::kSelScratchWords * sizeof(uint32_t); }
+
+extern "C" int rtsdf_select_noalloc(rtsdf_grid coarse, const int32_t *dist2, rtsdf_grid fine, float beta, float d,
+                                    uint8_t *mask, int32_t *queue, int32_t queue_cap, int32_t *count,
+                                    rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (!select_args_ok(coarse, dist2, fine, beta, d, mask, queue, queue_cap, count)) return RTSDF_EINVAL;
+    if (rtsdf_select_workspace_size(coarse.n) > kSelScratchWords * sizeof(uint32_t)) return RTSDF_EINVAL;
+    uint32_t *sums = scratch_for_current_device();
+    if (!sums) return RTSDF_EHIP;
+    return select_run(coarse, dist2, fine, beta, d, mask, queue, queue_cap, count, sums, as_stream(stream));
 }
 
 extern "C" int rtsdf_coarse_trilinear(rtsdf_grid coarse, const float *coarse_sdf, rtsdf_grid fine, float *fine_c,

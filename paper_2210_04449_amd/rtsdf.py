@@ -103,6 +103,8 @@ def _load():
         "rtsdf_jfa_steps": ([Grid, _P, _P, C.POINTER(_i32), _i32, _f32, _P, _P, _P], _i32),
         "rtsdf_select_workspace_size": ([_i32], _sz),
         "rtsdf_select": ([Grid, _P, Grid, _f32, _f32, _P, _P, _i32, _P, _P, _P], _i32),
+        "rtsdf_select_noalloc": ([Grid, _P, Grid, _f32, _f32, _P, _P, _i32, _P, _P], _i32),
+        "rtsdf_select_noalloc_max_bytes": ([], _sz),
         "rtsdf_coarse_trilinear": ([Grid, _P, Grid, _P, _P], _i32),
         "rtsdf_select_field": ([Grid, _P, _f32, _P, _P, _i32, _P, _P, _P], _i32),
         "rtsdf_scene_create": ([_P, _i32, _P, _i32, _i32, C.POINTER(_P), _P], _i32),
@@ -247,6 +249,15 @@ def rtsdf_select(coarse: Grid, dist2, fine: Grid, beta: float, d: float, mask, q
     cap = 0 if queue is None else queue.numel()
     _check("rtsdf_select", _lib.rtsdf_select(coarse, _ptr(dist2), fine, float(beta), float(d), _ptr(mask),
                                              _ptr(queue), cap, _ptr(count), _ptr(workspace), _stream(stream)))
+
+
+def rtsdf_select_noalloc(coarse: Grid, dist2, fine: Grid, beta: float, d: float, mask, queue, count, stream=None):
+    """rtsdf_select without a workspace: its scratch is the library's static per-device array (calls that
+    overlap on one GPU race on it)."""
+    cap = 0 if queue is None else queue.numel()
+    _check("rtsdf_select_noalloc", _lib.rtsdf_select_noalloc(coarse, _ptr(dist2), fine, float(beta), float(d),
+                                                             _ptr(mask), _ptr(queue), cap, _ptr(count),
+                                                             _stream(stream)))
 
 
 def rtsdf_coarse_trilinear(coarse: Grid, coarse_sdf, fine: Grid, fine_c, stream=None):

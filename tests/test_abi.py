@@ -112,6 +112,13 @@ def test_host_validation(R):
     assert L.rtsdf_scene_set_tuning(None, C.byref(good)) == R.EINVAL
     assert L.rtsdf_scene_get_tuning(None, C.byref(good)) == R.EINVAL
     assert L.rtsdf_batch_set_tuning(None, C.byref(good)) == R.EINVAL
+    # the allocation-free selection validates like rtsdf_select (and needs no workspace)
+    assert L.rtsdf_select_noalloc(g, dummy, R.Grid.make(48), 0.0, 0.1, dummy, dummy, 10, dummy, None) == R.EINVAL
+    assert L.rtsdf_select_noalloc(R.Grid.make(1024), dummy, R.Grid.make(1024), 0.0, 0.1, dummy, dummy, 10, dummy,
+                                  None) == R.EINVAL  # coarse grid beyond the static scratch
+    assert L.rtsdf_select_noalloc(g, None, fine, 0.0, 0.1, dummy, dummy, 10, dummy, None) == R.EINVAL
+    assert L.rtsdf_select_noalloc(g, dummy, fine, 0.0, float("nan"), dummy, dummy, 10, dummy, None) == R.EINVAL
+    assert R.lib().rtsdf_select_noalloc_max_bytes() >= R.rtsdf_select_workspace_size(512)
     assert L.rtsdf_scene_set_sign(None, 0, 0.0) == R.EINVAL
     offs = (C.c_int32 * 3)(0, 1, 2)
     h = C.c_void_p()
