@@ -278,10 +278,20 @@ int rtsdf_scene_hierarchy(const rtsdf_scene *scene, int32_t cap, float *boxes, i
 /* float rounding of another triangle's (the test order may pick the other). */
 /* EINVAL for two-level scenes and for scenes with                           */
 /* fewer than two references; rebuild before enable_rebuild is EINVAL.       */
-/* rebuild uses a library sort that may record memset operations, so do not */
-/* capture it in a graph.                                                    */
+/* rebuild is a fixed sequence of kernel launches (no allocation, host      */
+/* synchronisation or memset; its radix sort is the library's own), so it   */
+/* may be captured in a graph (see rtsdf_frame_desc.refit).                  */
 int rtsdf_scene_enable_rebuild(rtsdf_scene *scene, rtsdf_stream stream);
 int rtsdf_scene_rebuild(rtsdf_scene *scene, const float *vertices, rtsdf_stream stream);
+
+/* The radix sort of the device rebuild, exported so callers and tests can  */
+/* check it: sorts n (key, value) pairs (device arrays, in place) by the low */
+/* `bits` bits of the key (1..32; higher bits must be 0), stably (pairs with */
+/* equal keys keep their order), least-significant 8-bit digit first.       */
+/* workspace: rtsdf_sort_pairs_workspace_size(n) bytes of device memory.    */
+size_t rtsdf_sort_pairs_workspace_size(int32_t n);
+int rtsdf_sort_pairs(uint32_t *keys, int32_t *values, int32_t n, int32_t bits, void *workspace,
+                     rtsdf_stream stream);
 
 /* Two-level scene: a static world plus rigidly moving parts (refitting one */
 /* hierarchy over moving geometry loosens it frame after frame).  Part i     */
@@ -479,7 +489,9 @@ typedef struct rtsdf_frame_desc {
     const int32_t *faces;       /* [nt][3] */
     int32_t nt;
     rtsdf_scene *scene;
-    int32_t refit;              /* 1: refit the scene from `vertices` each frame */
+    int32_t refit;              /* 0: static scene; 1: refit the scene from `vertices` each frame; 2: rebuild
+                                   its hierarchy on the device from `vertices` each frame (rtsdf_scene_rebuild;
+                                   the scene must have had rtsdf_scene_enable_rebuild) */
     rtsdf_grid coarse, fine;
     float beta, d;
     int32_t rays_per_texel;

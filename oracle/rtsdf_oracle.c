@@ -928,13 +928,17 @@ static int near_tie(double a, double b)
     return fabs(a - b) <= TIE_REL * m;
 }
 
-/* texel_amb (sticky while the texel stays selected) marks texels whose      */
-/* sign, front/back counts or argmin record a float32 evaluation could       */
-/* legitimately get differently: one of their rays was ambiguous (above), or */
-/* a frame's two smallest ray distances, or its r_t and the value it was     */
-/* compared with in Eq. (1), are within TIE_REL of each other.  Every other  */
-/* texel's state is unique.  arg_amb marks only texels whose argmin ray      */
-/* itself is ambiguous (their distance may differ beyond rounding).          */
+/* texel_amb (bits sticky while the texel stays selected) marks what a       */
+/* float32 evaluation could legitimately get differently: bit 0 (AMB_RAY),  */
+/* one of the texel's rays was ambiguous (above), so its front/back counts  */
+/* and sign are not unique; bit 1 (AMB_TIE), a frame's two smallest ray     */
+/* distances, or its r_t and the value it was compared with in Eq. (1), are  */
+/* within TIE_REL of each other, so the argmin record is not unique.        */
+/* arg_amb marks texels whose argmin ray itself is ambiguous (their distance */
+/* may differ beyond rounding and their argmin record is not unique).       */
+/* Everything else about a selected texel is unique.                         */
+#define AMB_RAY 1
+#define AMB_TIE 2
 int oracle_trace_frame(const oracle_scene *s,
                        int nc, const float *coarse_sdf,
                        int nf, const float lo[3], float hf,
@@ -975,7 +979,7 @@ int oracle_trace_frame(const oracle_scene *s,
             const double w[3] = {wf[0], wf[1], wf[2]};
             ohit_t h;
             closest_hit(s, o, w, &h);
-            if (h.ambiguous) texel_amb[j] = 1;
+            if (h.ambiguous) texel_amb[j] |= AMB_RAY;
             if (h.tri < 0) continue;
             if (h.front) nfront[j] += 1;
             else nback[j] += 1;
@@ -991,12 +995,12 @@ int oracle_trace_frame(const oracle_scene *s,
             }
         }
         if (rmin_out) rmin_out[j] = rt;
-        if (near_tie(rt, rt2)) texel_amb[j] = 1;
+        if (near_tie(rt, rt2)) texel_amb[j] |= AMB_TIE;
         {
             /* the value r_t is compared with in Eq. (1) */
             int src0;
             const double decayed = oracle_eq1(alpha, u[j], c, INFINITY, &src0);
-            if (near_tie(rt, decayed)) texel_amb[j] = 1;
+            if (near_tie(rt, decayed)) texel_amb[j] |= AMB_TIE;
         }
         int src;
         u[j] = oracle_eq1(alpha, u[j], c, rt, &src);

@@ -38,6 +38,9 @@ static int record_frame(const rtsdf_frame_graph &G, hipStream_t s)
         rc = rtsdf_scene_set_transforms(D.scene, D.transforms, D.world_vertices, s);
         if (rc != RTSDF_OK) return rc;
         verts = D.world_vertices;
+    } else if (D.refit == 2) {
+        rc = rtsdf_scene_rebuild(D.scene, D.vertices, s);
+        if (rc != RTSDF_OK) return rc;
     } else if (D.refit) {
         rc = rtsdf_scene_refit(D.scene, D.vertices, s);
         if (rc != RTSDF_OK) return rc;
@@ -105,6 +108,7 @@ extern "C" int rtsdf_frame_graph_create(const rtsdf_frame_desc *desc, rtsdf_fram
 {
     if (!desc || !out || !desc->frame_counter || !desc->scene) return RTSDF_EINVAL;
     if (desc->refit && desc->transforms && !desc->world_vertices) return RTSDF_EINVAL;
+    if (desc->refit < 0 || desc->refit > 2 || (desc->refit == 2 && desc->transforms)) return RTSDF_EINVAL;
     *out = nullptr;
     auto *g = new rtsdf_frame_graph();
     g->desc = *desc;

@@ -12,8 +12,9 @@
 //   1. reference boxes from the current vertices, and the bounds of their
 //      centres (atomic min/max on order-preserving integer images of floats);
 //   2. 30-bit Morton codes of the centres in those bounds;
-//   3. radix sort of (code, reference) pairs (hipCUB); equal codes keep the
-//      reference order, so (code, position) keys are distinct;
+//   3. radix sort of (code, reference) pairs (below: least-significant digit
+//      first, 8-bit digits, stable); equal codes keep the reference order,
+//      so (code, position) keys are distinct;
 //   4. the binary radix tree over the sorted keys (Karras, "Maximizing
 //      Parallelism in the Construction of BVHs, Octrees, and k-d Trees",
 //      HPG 2012): internal node i finds its key range from the common-prefix
@@ -36,13 +37,15 @@
 // the distinct 30-bit code + position key), which sizes the traversal stack.
 // A refit of a rebuilt scene reuses steps 1 and 5 on the same tree.
 //
+// Every step is a kernel launch with a launch shape fixed by the reference
+// count (no host synchronisation, allocation or memset), so a rebuild can be
+// captured in a graph.
+//
 // The closest hit a ray finds is the minimum over all references of a value
 // computed from the reference alone, so a rebuilt scene traces like the
 // original one; only where two candidates lie within float rounding of each
 // other (a ray through an edge) can the order of the tests, which follows
 // the hierarchy, pick the other one.
-#include <hipcub/hipcub.hpp>
-
 #include "common.hpp"
 
 namespace rtsdf {
@@ -121,8 +124,7 @@ __device__ __forceinline__ uint32_t morton30(float x, float y, float z)
 
 // step 2
 __global__ void __launch_bounds__(256) lbvh_codes(const float *__restrict__ box, int nref,
-                                                  const unsigned *__restrict__ bounds, uint32_t *__restrict__ code,
-                                                  int32_t *__restrict__ id)
+                                                  const unsigned *__restrict__ bounds, uint32_t *__restrict__ code)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nref) return;
@@ -134,7 +136,164 @@ __global__ void __launch_bounds__(256) lbvh_codes(const float *__restrict__ box,
         q[k] = ext > 0.0f ? (c - lo) / ext : 0.5f;
     }
     code[i] = morton30(q[0], q[1], q[2]);
-    id[i] = i;
+}
+
+// ---------------------------------------------------------------- sort ----
+//
+// Least-significant-digit radix sort of (key, value) pairs, 8-bit digits,
+// stable.  Each pass over the n pairs:
+//   rsort_count    tile t (kSortTile consecutive pairs, 4 wavefronts of 1024
+//                  each) counts its digits; counts go to hist[digit][tile];
+//   rsort_scan     one workgroup: exclusive prefix of hist in that order, so
+//                  hist[d][t] becomes the output position of the first pair
+//                  of tile t with digit d;
+//   rsort_scatter  tile t counts again per wavefront, turns the counts into
+//                  per-wavefront starting positions for every digit, and each
+//                  wavefront walks its 1024 pairs in order, 64 at a time: the
+//                  lanes holding one digit find each other with eight ballots
+//                  (one per digit bit), a lane's rank among them is the count
+//                  of lower lanes, and the group's lowest lane advances the
+//                  digit's position.  Pairs with equal digits therefore keep
+//                  their order: within a wavefront by the walk, across
+//                  wavefronts and tiles by the prefix.
+// The first pass takes the values as the identity (value = input position).
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;                                    // pairs per lane per tile
+constexpr int kSortChunk = kWave * kSortItems;                    // pairs per wavefront
+constexpr int kSortTile = kSortThreads * kSortItems;              // pairs per tile
+constexpr int kSortBins = 256;
+
+__global__ void __launch_bounds__(kSortThreads) rsort_count(const uint32_t *__restrict__ keys, int n, int shift,
+                                                            uint32_t *__restrict__ hist, int ntiles)
+{
+    __shared__ uint32_t h[kSortThreads / kWave][kSortBins];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int b = lane; b < kSortBins; b += kWave) h[wave][b] = 0u;
+    __syncthreads();
+    const int base = blockIdx.x * kSortTile + wave * kSortChunk;
+#pragma unroll 4
+    for (int i = 0; i < kSortItems; ++i) {
+        const int idx = base + i * kWave + lane;
+        if (idx < n) atomicAdd(&h[wave][(keys[idx] >> shift) & 0xFFu], 1u);
+    }
+    __syncthreads();
+    const int d = threadIdx.x;  // kSortThreads == kSortBins
+    hist[d * ntiles + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+}
+
+// exclusive prefix of hist[0 .. total) in place (one workgroup of 1024 lanes)
+__global__ void __launch_bounds__(1024) rsort_scan(uint32_t *__restrict__ hist, int total)
+{
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (total + 1023) / 1024;
+    const int b0 = t * per;
+    uint32_t local = 0;
+    for (int i = 0; i < per; ++i)
+        if (b0 + i < total) local += hist[b0 + i];
+    part[t] = local;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - local;
+    for (int i = 0; i < per; ++i) {
+        if (b0 + i < total) {
+            const uint32_t v = hist[b0 + i];
+            hist[b0 + i] = run;
+            run += v;
+        }
+    }
+}
+
+template <bool IDENTITY>
+__global__ void __launch_bounds__(kSortThreads) rsort_scatter(const uint32_t *__restrict__ kin,
+                                                              const int32_t *__restrict__ vin,
+                                                              uint32_t *__restrict__ kout, int32_t *__restrict__ vout,
+                                                              int n, int shift, const uint32_t *__restrict__ offs,
+                                                              int ntiles)
+{
+    __shared__ uint32_t pos[kSortThreads / kWave][kSortBins];  // per wavefront: counts, then next positions
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int b = lane; b < kSortBins; b += kWave) pos[wave][b] = 0u;
+    __syncthreads();
+    const int base = blockIdx.x * kSortTile + wave * kSortChunk;
+    uint32_t key[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int idx = base + i * kWave + lane;
+        key[i] = idx < n ? kin[idx] : 0u;
+        if (idx < n) atomicAdd(&pos[wave][(key[i] >> shift) & 0xFFu], 1u);
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;  // one digit per lane
+        uint32_t p = offs[d * ntiles + blockIdx.x];
+        const uint32_t c0 = pos[0][d], c1 = pos[1][d], c2 = pos[2][d];
+        pos[0][d] = p;
+        p += c0;
+        pos[1][d] = p;
+        p += c1;
+        pos[2][d] = p;
+        pos[3][d] = p + c2;
+    }
+    __syncthreads();
+    const uint64_t lower = lane ? (~0ull >> (64 - lane)) : 0ull;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int idx = base + i * kWave + lane;
+        const bool valid = idx < n;
+        const uint32_t d = (key[i] >> shift) & 0xFFu;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lower);
+        const uint32_t at = pos[wave][d];
+        if (valid) {
+            kout[at + rank] = key[i];
+            vout[at + rank] = IDENTITY ? idx : vin[idx];
+            if (rank == 0) pos[wave][d] = at + (uint32_t)__popcll(peers);
+        }
+        // the next group of 64 reads the advanced positions
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+static int rsort_tiles(int n) { return (n + kSortTile - 1) / kSortTile; }
+static size_t rsort_hist_words(int n) { return (size_t)kSortBins * rsort_tiles(n); }
+
+// Sort n pairs with `bits`-bit keys (1 <= bits <= 32) starting in (k0, v0) -- with IDENTITY_IN the values
+// are taken as 0 .. n - 1 and v0 is not read; the result lands in (k0, v0) after an even number of passes and
+// in (k1, v1) after an odd one, returned through out_k / out_v.
+static int rsort_run(uint32_t *k0, int32_t *v0, uint32_t *k1, int32_t *v1, uint32_t *hist, int n, int bits,
+                     bool identity_in, uint32_t **out_k, int32_t **out_v, hipStream_t s)
+{
+    const int ntiles = rsort_tiles(n);
+    uint32_t *ka = k0, *kb = k1;
+    int32_t *va = v0, *vb = v1;
+    for (int shift = 0, pass = 0; shift < bits; shift += 8, ++pass) {
+        rsort_count<<<dim3(ntiles), dim3(kSortThreads), 0, s>>>(ka, n, shift, hist, ntiles);
+        RTSDF_CHECK_LAUNCH();
+        rsort_scan<<<dim3(1), dim3(1024), 0, s>>>(hist, kSortBins * ntiles);
+        RTSDF_CHECK_LAUNCH();
+        if (pass == 0 && identity_in)
+            rsort_scatter<true><<<dim3(ntiles), dim3(kSortThreads), 0, s>>>(ka, nullptr, kb, vb, n, shift, hist, ntiles);
+        else
+            rsort_scatter<false><<<dim3(ntiles), dim3(kSortThreads), 0, s>>>(ka, va, kb, vb, n, shift, hist, ntiles);
+        RTSDF_CHECK_LAUNCH();
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    *out_k = ka;
+    *out_v = va;
+    return RTSDF_OK;
 }
 
 // common-prefix length of the keys (code, position) at positions i and j; -1 outside [0, n)
@@ -335,8 +494,7 @@ struct rtsdf_lbvh {
     int32_t *leaf_parent = nullptr;                    // [nref]
     int2 *range = nullptr;                             // [nref - 1] leaf run of each internal node
     int32_t *queue = nullptr, *qcount = nullptr;       // [nref], [1] children handed to the top pass
-    void *sort_tmp = nullptr;
-    size_t sort_bytes = 0;
+    uint32_t *hist = nullptr;                          // radix-sort digit counts: [256][tiles]
 };
 
 static void lbvh_free(rtsdf_lbvh *L)
@@ -344,7 +502,7 @@ static void lbvh_free(rtsdf_lbvh *L)
     if (!L) return;
     for (void *p : {(void *)L->ref_tri, (void *)L->ref_path, (void *)L->box, (void *)L->bounds, (void *)L->code,
                     (void *)L->code_sorted, (void *)L->id, (void *)L->id_sorted, (void *)L->leaf_parent, (void *)L->range, (void *)L->queue,
-                    (void *)L->qcount, L->sort_tmp})
+                    (void *)L->qcount, (void *)L->hist})
         (void)hipFree(p);
     delete L;
 }
@@ -363,12 +521,14 @@ static int lbvh_run(rtsdf_scene *sc, bool rebuild, hipStream_t s)
         sc->vertices, sc->faces, L->ref_tri, L->ref_path, n, sc->pad, L->box, L->bounds);
     RTSDF_CHECK_LAUNCH();
     if (rebuild) {
-        lbvh_codes<<<dim3(blocks), dim3(256), 0, s>>>(L->box, n, L->bounds, L->code, L->id);
+        lbvh_codes<<<dim3(blocks), dim3(256), 0, s>>>(L->box, n, L->bounds, L->code_sorted);
         RTSDF_CHECK_LAUNCH();
-        size_t bytes = L->sort_bytes;
-        if (hipcub::DeviceRadixSort::SortPairs(L->sort_tmp, bytes, L->code, L->code_sorted, L->id, L->id_sorted, n, 0,
-                                               30, s) != hipSuccess)
-            return RTSDF_EHIP;
+        // four 8-bit passes from code_sorted: the sorted pairs land back in (code_sorted, id_sorted)
+        uint32_t *ok_ = nullptr;
+        int32_t *ov_ = nullptr;
+        const int rc = rsort_run(L->code_sorted, L->id_sorted, L->code, L->id, L->hist, n, 30, true, &ok_, &ov_, s);
+        if (rc != RTSDF_OK) return rc;
+        if (ok_ != L->code_sorted || ov_ != L->id_sorted) return RTSDF_EHIP;  // (an even number of passes)
         lbvh_internal<<<dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s>>>(L->code_sorted, n, sc->nodes,
                                                                                   L->leaf_parent, L->range);
         RTSDF_CHECK_LAUNCH();
@@ -429,11 +589,7 @@ extern "C" int rtsdf_scene_enable_rebuild(rtsdf_scene *sc, rtsdf_stream stream)
               alloc((void **)&L->leaf_parent, sizeof(int32_t) * n) && alloc((void **)&L->range, sizeof(int2) * n) &&
               alloc((void **)&L->queue, sizeof(int32_t) * n) && alloc((void **)&L->qcount, sizeof(int32_t)) &&
               alloc((void **)&nodes, sizeof(BvhNode) * (n - 1)) && alloc((void **)&counter, sizeof(int32_t) * (n - 1));
-    if (ok) {
-        ok = hipcub::DeviceRadixSort::SortPairs(nullptr, L->sort_bytes, L->code, L->code_sorted, L->id, L->id_sorted,
-                                                n, 0, 30, s) == hipSuccess &&
-             alloc(&L->sort_tmp, L->sort_bytes);
-    }
+    ok = ok && alloc((void **)&L->hist, sizeof(uint32_t) * rsort_hist_words(n));
     ok = ok && hipMemcpyAsync(L->ref_tri, rt.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) == hipSuccess &&
          hipMemcpyAsync(L->ref_path, rp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) == hipSuccess &&
          hipStreamSynchronize(s) == hipSuccess;
@@ -465,4 +621,33 @@ extern "C" int rtsdf_scene_rebuild(rtsdf_scene *scene, const float *vertices, rt
     if (scene->nv > 0 && vertices != scene->vertices)
         RTSDF_TRY(hipMemcpyAsync(scene->vertices, vertices, sizeof(float) * 3 * scene->nv, hipMemcpyDeviceToDevice, s));
     return lbvh_run(scene, true, s);
+}
+
+extern "C" size_t rtsdf_sort_pairs_workspace_size(int32_t n)
+{
+    using namespace rtsdf;
+    if (n <= 0) return 0;
+    return (size_t)n * (sizeof(uint32_t) + sizeof(int32_t)) + rsort_hist_words(n) * sizeof(uint32_t) + 256;
+}
+
+extern "C" int rtsdf_sort_pairs(uint32_t *keys, int32_t *values, int32_t n, int32_t bits, void *workspace,
+                                rtsdf_stream stream)
+{
+    using namespace rtsdf;
+    if (n < 0 || bits < 1 || bits > 32 || (n > 0 && (!keys || !values || !workspace))) return RTSDF_EINVAL;
+    if (n <= 1) return RTSDF_OK;
+    hipStream_t s = as_stream(stream);
+    char *w = static_cast<char *>(workspace);
+    uint32_t *k1 = reinterpret_cast<uint32_t *>(w);
+    int32_t *v1 = reinterpret_cast<int32_t *>(w + (size_t)n * sizeof(uint32_t));
+    uint32_t *hist = reinterpret_cast<uint32_t *>(w + (size_t)n * 8);
+    uint32_t *ok_ = nullptr;
+    int32_t *ov_ = nullptr;
+    const int rc = rsort_run(keys, values, k1, v1, hist, n, bits, false, &ok_, &ov_, s);
+    if (rc != RTSDF_OK) return rc;
+    if (ok_ != keys) {  // an odd number of passes ends in the workspace
+        RTSDF_TRY(hipMemcpyAsync(keys, ok_, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+        RTSDF_TRY(hipMemcpyAsync(values, ov_, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    }
+    return RTSDF_OK;
 }

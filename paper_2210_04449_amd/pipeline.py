@@ -13,9 +13,13 @@ texel centre; the tracer then works on the fine grid alone).  ``sign_policy``
 "vote" signs traced distances by the front/back vote of Sec. 2.2; "shell"
 outputs the unsigned distance minus ``shell`` (open or thin surfaces).
 ``parts=(part_faces, transforms)`` builds a two-level scene of rigid parts
-(vertices in object space; ``set_transforms`` moves them); ``rebuild=True``
-rebuilds the hierarchy on the device at every ``set_vertices`` instead of
-refitting it.
+(vertices in object space; ``set_transforms`` moves them).  ``rebuild``
+chooses how ``set_vertices`` updates a single-level hierarchy for moved
+geometry: ``None`` (default) keeps the host-built SAH hierarchy while the
+scene is static and switches to rebuilding it on the device at the first
+``set_vertices`` (a refitted hierarchy loosens frame after frame under
+continuous motion); ``True`` rebuilds on the device from the start;
+``False`` always refits.
 """
 from __future__ import annotations
 
@@ -31,7 +35,7 @@ class Pipeline:
                  rays: int, seed: int = 0, scene_id: int = 0, alpha: float = 1.0, lo=(0.0, 0.0, 0.0),
                  side: float = 1.0, leaf_size: int = 2, queue_cap: int | None = None, device="cuda",
                  jfa_variant: str = "jfa", sampling: str = "point", sign_policy: str = "vote",
-                 shell: float = 0.0, parts=None, rebuild: bool = False):
+                 shell: float = 0.0, parts=None, rebuild: bool | None = None):
         if sampling not in ("point", "trilinear"):
             raise ValueError(f"sampling must be 'point' or 'trilinear', not {sampling!r}")
         self.sampling = sampling
@@ -72,9 +76,10 @@ class Pipeline:
             self.scene = R.Scene.instanced(self.obj_vertices, self.faces, part_faces, self.transforms, leaf_size)
             self.scene.world_vertices(self.vertices)
         self.parts = parts is not None
-        self.rebuild = bool(rebuild)
-        if self.rebuild:  # set_vertices rebuilds the hierarchy on the device instead of refitting it
-            self.scene.enable_rebuild()
+        self.rebuild_policy = None if rebuild is None else bool(rebuild)
+        self.rebuild = False  # whether set_vertices rebuilds the hierarchy on the device (else it refits)
+        if rebuild:
+            self._enable_rebuild()
         self.scene.set_sign(sign_policy, shell)
 
     # -- stages ----------------------------------------------------------
@@ -114,14 +119,22 @@ class Pipeline:
         self.select(stream)
         self.trace(frame, stream)
 
+    def _enable_rebuild(self):
+        if not self.rebuild and not self.parts and self.faces.shape[0] > 1:
+            self.scene.enable_rebuild()
+            self.rebuild = True
+
     def make_graph(self, first_frame: int = 0, refit: bool = False) -> "R.FrameGraph":
         """Capture one whole update as a HIP graph; each launch advances the frame index.  With refit, each
-        launch refits from `self.vertices`, or for rigid parts applies `self.transforms`, as they are then."""
+        launch updates the hierarchy from `self.vertices` as they are then (a device rebuild, or a refit
+        with rebuild=False), or for rigid parts applies `self.transforms`."""
+        if refit and self.rebuild_policy is None:
+            self._enable_rebuild()
         self.frame_counter = torch.full((1,), int(first_frame), dtype=torch.int32, device=self.device)
         D = R.FrameDesc()
         D.vertices, D.nv = self.vertices.data_ptr(), self.vertices.shape[0]
         D.faces, D.nt = self.faces.data_ptr(), self.faces.shape[0]
-        D.scene, D.refit = self.scene.handle, int(bool(refit))
+        D.scene, D.refit = self.scene.handle, (2 if self.rebuild else 1) if refit else 0
         D.coarse, D.fine = self.coarse, self.fine
         D.beta, D.d, D.rays_per_texel = self.beta, self.d, self.rays
         D.seed, D.scene_id, D.alpha = self.seed, self.scene_id, self.alpha
@@ -146,6 +159,8 @@ class Pipeline:
         if self.parts:
             raise RuntimeError("a scene of rigid parts moves by set_transforms")
         self.vertices.copy_(vertices)
+        if self.rebuild_policy is None:
+            self._enable_rebuild()
         if self.rebuild:
             self.scene.rebuild(self.vertices, stream)
         else:

@@ -122,6 +122,8 @@ def _load():
         "rtsdf_scene_get_tuning": ([_P, C.POINTER(TraceTuning)], _i32),
         "rtsdf_batch_set_tuning": ([_P, C.POINTER(TraceTuning)], _i32),
         "rtsdf_sqrt": ([_P, C.c_int64, _P, _P], _i32),
+        "rtsdf_sort_pairs_workspace_size": ([_i32], _sz),
+        "rtsdf_sort_pairs": ([_P, _P, _i32, _i32, _P, _P], _i32),
         "rtsdf_directions": ([_P, _P, _P, _i32, _u64, _u32, _P, _P], _i32),
         "rtsdf_closest_hits": ([_P, _P, _P, _i32, _P, _P, _P, _P], _i32),
         "rtsdf_trace_backward": ([_P, Grid, Accum, _P, _P, _u64, _u32, _P, _P], _i32),
@@ -422,6 +424,18 @@ def rtsdf_trace_accumulate(scene: Scene, coarse: Grid, coarse_sdf, fine: Grid, m
         scene.handle, coarse, _ptr(coarse_sdf), fine, _ptr(mask), _ptr(queue), _ptr(count), queue.numel(),
         int(rays_per_texel), int(frame), _ptr(frame_ptr), int(seed), int(scene_id), float(alpha), state.struct(),
         _ptr(fine_sdf), _ptr(workspace), _stream(stream)))
+
+
+def rtsdf_sort_pairs(keys, values, bits: int = 32, stream=None):
+    """Stable radix sort of (uint32 keys as int32 tensor, int32 values) in place by the low `bits` key bits."""
+    _dtype(keys, torch.int32, "keys")
+    _dtype(values, torch.int32, "values")
+    n = keys.numel()
+    if values.numel() != n:
+        raise ValueError("rtsdf_sort_pairs: keys and values differ in length")
+    ws = torch.empty(max(int(_lib.rtsdf_sort_pairs_workspace_size(n)), 1), dtype=torch.uint8, device=keys.device)
+    _check("rtsdf_sort_pairs", _lib.rtsdf_sort_pairs(_ptr(keys), _ptr(values), n, int(bits), _ptr(ws),
+                                                     _stream(stream)))
 
 
 def rtsdf_sqrt(x, out, stream=None):

@@ -125,9 +125,10 @@ def test_differentiable_full_size_gradient_sampled():
     for f in frames:
         p.step(f)
     torch.cuda.synchronize()
-    stats = compare_trace(p, ref, sample=sample)
+    # 512 rays per texel: about one texel in six has some ray crossing near a triangle edge
+    stats = compare_trace(p, ref, sample=sample, max_flagged=0.25)
     print(stats)
-    assert stats["texels"] == len(sample)
+    assert stats["texels"] == len(sample) and stats["exact_hits"] > 1400 and stats["exact_arg"] > 1800
     fine = p.fine_sdf.cpu().numpy().astype(np.float64)
     at, ar = p.state.arg_tri.cpu().numpy(), p.state.arg_ray.cpu().numpy()
     j = sample.astype(np.int64)

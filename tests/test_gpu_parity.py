@@ -271,13 +271,16 @@ def run_gpu(R, w, frames, seed=0, alpha=None):
     return p
 
 
-def compare_trace(p, ref, sample=None, max_flagged=0.02, tol=TOL):
+def compare_trace(p, ref, sample=None, max_flagged=0.1, tol=TOL):
     """GPU trace state against the oracle's.
 
-    Texels the oracle flags (``texel_amb``: an ambiguous ray, or two candidate distances within float
-    rounding of each other) may legitimately differ in sign, hit counts and argmin; every other selected
-    texel must agree exactly in all of them and in its signed value within the tolerance.  The distance
-    |f| is also checked on flagged texels unless their argmin ray itself is ambiguous (``arg_amb``)."""
+    The oracle's per-texel flags say what a float32 evaluation may legitimately get differently: bit 0 of
+    ``texel_amb`` (some ray of the texel was ambiguous: its front/back counts and sign may differ), bit 1 (two
+    candidate distances within float rounding: the argmin record may differ), and ``arg_amb`` (the argmin
+    ray itself is ambiguous: its distance may differ beyond rounding).  Every selected texel must agree
+    exactly in sign and hit counts unless bit 0 is set, in its argmin record (frame, ray, triangle) unless
+    bit 1 or arg_amb is set, and in |f| within the tolerance unless arg_amb is set (and in f itself where
+    the sign is exact).  At most `max_flagged` of the texels may be excluded from either exact check."""
     st = ref["state"]
     fine = p.fine_sdf.cpu().numpy()
     u = p.state.u.cpu().numpy()
@@ -296,26 +299,29 @@ def compare_trace(p, ref, sample=None, max_flagged=0.02, tol=TOL):
     assert err.max(initial=0) <= tol, (err.max(), np.sum(err > tol))
     fin = np.isfinite(st.u[good])
     assert np.array_equal(np.isfinite(u[good]), fin)
-    flagged = st.texel_amb[sel] == 1
-    assert flagged.mean() <= max_flagged, flagged.mean()
-    ex = sel[~flagged]
+    ray_flag = (st.texel_amb[sel] & 1) != 0
+    arg_flag = ((st.texel_amb[sel] & 2) != 0) | amb
+    assert ray_flag.mean() <= max_flagged and arg_flag.mean() <= max_flagged, (ray_flag.mean(), arg_flag.mean())
+    ex_hits, ex_arg = sel[~ray_flag], sel[~arg_flag]
+    ex_both = sel[~ray_flag & ~arg_flag]
+    want_ar = np.where(st.arg_tri >= 0, (st.arg_frame << 8) | np.maximum(st.arg_ray, 0), -1)
     bad = {
-        "sign": np.sign(fine[ex]) != np.sign(st.fine[ex]),
-        "front": (hits[ex] & 0xFFFF) != st.nfront[ex],
-        "back": (hits[ex] >> 16) != st.nback[ex],
-        "arg_tri": at[ex] != st.arg_tri[ex],
-        "arg_ray": ar[ex] != np.where(st.arg_tri[ex] >= 0, (st.arg_frame[ex] << 8) | np.maximum(st.arg_ray[ex], 0),
-                                      -1),
-        "signed_value": np.abs(fine[ex].astype(np.float64) - st.fine[ex]) > tol,
+        "sign": (ex_hits, np.sign(fine[ex_hits]) != np.sign(st.fine[ex_hits])),
+        "front": (ex_hits, (hits[ex_hits] & 0xFFFF) != st.nfront[ex_hits]),
+        "back": (ex_hits, (hits[ex_hits] >> 16) != st.nback[ex_hits]),
+        "arg_tri": (ex_arg, at[ex_arg] != st.arg_tri[ex_arg]),
+        "arg_ray": (ex_arg, ar[ex_arg] != want_ar[ex_arg]),
+        "signed_value": (ex_both, np.abs(fine[ex_both].astype(np.float64) - st.fine[ex_both]) > tol),
     }
-    for k, b in bad.items():
+    for k, (ex, b) in bad.items():
         if b.any():
             i = ex[np.argmax(b)]
             raise AssertionError(f"{k}: {int(b.sum())} of {len(ex)} unflagged texels differ; first texel {i}: "
                                  f"gpu f {fine[i]} hits {hits[i] & 0xFFFF}/{hits[i] >> 16} arg {at[i]}/{ar[i]}; "
                                  f"oracle f {st.fine[i]} hits {st.nfront[i]}/{st.nback[i]} "
                                  f"arg {st.arg_tri[i]}/{st.arg_frame[i]}/{st.arg_ray[i]}")
-    return dict(texels=len(sel), exact=len(ex), flagged=int(flagged.sum()), ambiguous_argmin=int(amb.sum()),
+    return dict(texels=len(sel), exact_hits=len(ex_hits), exact_arg=len(ex_arg), ray_flagged=int(ray_flag.sum()),
+                tie_or_arg_flagged=int(arg_flag.sum()), ambiguous_argmin=int(amb.sum()),
                 max_err=float(err.max(initial=0)))
 
 

@@ -359,12 +359,12 @@ def test_texel_flags_near_tied_rays_and_history():
     st, mask = r["state"], r["mask"]
     sel = np.nonzero(mask)[0]
     assert np.all(st.texel_amb[mask == 0] == 0)
-    assert np.all(st.texel_amb[sel] >= st.arg_amb[sel])  # an ambiguous argmin ray flags its texel
-    frac = st.texel_amb[sel].mean()
+    assert np.all((st.texel_amb[sel] & 1) >= st.arg_amb[sel])  # an ambiguous argmin ray flags its texel
+    frac = (st.texel_amb[sel] != 0).mean()
     assert 0 < frac < 0.02, frac
     # the flag is sticky over frames: a fresh state over frames 0..1 flags a subset of frames 0..3's
     r2 = oracle.run_frames(w.vertices, w.faces, nc, nf, np.float32(0.5 / nc), np.float32(2 / nc), rays, range(2))
-    assert np.all(r2["state"].texel_amb[sel] <= st.texel_amb[sel])
+    assert np.all((r2["state"].texel_amb[sel] & ~st.texel_amb[sel]) == 0)
     # a texel traced with two identical frames: every ray ties with the history -> flagged
     st3 = oracle.TraceState(nf)
     sc = r["scene"]
@@ -373,4 +373,4 @@ def test_texel_flags_near_tied_rays_and_history():
     sc.trace_frame(nc, r["coarse"], nf, lo, hf, mask, rays, 5, 0, 0, 1.0, st3, t)
     finite = np.isfinite(st3.u[t])
     sc.trace_frame(nc, r["coarse"], nf, lo, hf, mask, rays, 5, 0, 0, 1.0, st3, t)
-    assert np.all(st3.texel_amb[t][finite] == 1)
+    assert np.all((st3.texel_amb[t][finite] & 2) == 2)
