@@ -40,8 +40,7 @@ enum JfaKind { kJfaNone = 0, kJfaConvert, kJfaFarBricks, kJfaFarLinear, kJfaNear
 
 struct JfaStep {
     int kind;
-    int n, logn, logkb;  // far passes: log2 of the step in bricks
-    int cull;            // far passes: skip staged bricks without seeds (the first passes)
+    int n, logn, kb;
     const int32_t *src;
     int32_t *dst;
     int32_t *dist2;
@@ -124,7 +123,7 @@ __device__ __forceinline__ const FlatRange &flat_find(const FlatRange *__restric
 }
 
 template <int KIND>
-__global__ void __launch_bounds__(KIND == kJfaConvert ? 256 : 512)
+__global__ void __launch_bounds__(KIND == kJfaNear2 || KIND == kJfaFinal ? 512 : 256)
     jfa_batch(const JfaStep *__restrict__ plan, const FlatRange *__restrict__ ranges, int nr)
 {
     const FlatRange &fr = flat_find(ranges, nr, blockIdx.x);
@@ -135,12 +134,11 @@ __global__ void __launch_bounds__(KIND == kJfaConvert ? 256 : 512)
         const int64_t e = (int64_t)blk * blockDim.x + threadIdx.x;
         if (e < nvox) jfa_to_bricks_body(st.src, st.dst, st.n, st.logn, e);
     } else if (KIND == kJfaFarBricks || KIND == kJfaFarLinear) {
-        if (st.cull) jfa_far_body<KIND == kJfaFarLinear, true>(st.src, st.dst, st.n, st.logn, st.logkb, blk, nblk);
-        else jfa_far_body<KIND == kJfaFarLinear, false>(st.src, st.dst, st.n, st.logn, st.logkb, blk, nblk);
+        jfa_far_body<false, KIND == kJfaFarLinear>(st.src, st.dst, st.n, st.logn, st.kb, blk, nblk);
     } else if (KIND == kJfaNear2) {
-        jfa_near_body<2, false>(st.src, st.dst, st.n, st.logn, nullptr, nullptr, 0.f, 0.f, blk, nblk);
+        jfa_near_body<2, false, false>(st.src, st.dst, st.n, st.logn, nullptr, nullptr, 0.f, 0.f, blk, nblk);
     } else {
-        jfa_near_body<1, true>(st.src, st.dst, st.n, st.logn, st.dist2, st.sdf, st.h, st.beta, blk, nblk);
+        jfa_near_body<1, false, true>(st.src, st.dst, st.n, st.logn, st.dist2, st.sdf, st.h, st.beta, blk, nblk);
     }
 }
 
@@ -350,7 +348,7 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
         int next;
         bool linear_first = false;
         if (nbp % 2 == 0) {
-            put(first - 1, JfaStep{kJfaConvert, c.n, L, 0, 0, seeds, scratch, nullptr, nullptr, 0.f, 0.f},
+            put(first - 1, JfaStep{kJfaConvert, c.n, L, 0, seeds, scratch, nullptr, nullptr, 0.f, 0.f},
                 (uint32_t)(nvox / 256));
             cur = scratch;
             next = 0;
@@ -364,18 +362,17 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
             int32_t *dst = bufs[next];
             if (k >= 4)
                 put(first + j - 1,
-                    JfaStep{(linear_first && j == 1) ? kJfaFarLinear : kJfaFarBricks, c.n, L, ilog2(k / 4),
-                            j <= kCullPasses ? 1 : 0, cur, dst, nullptr, nullptr, 0.f, 0.f},
-                    (uint32_t)(nvox / 512));
+                    JfaStep{(linear_first && j == 1) ? kJfaFarLinear : kJfaFarBricks, c.n, L, k / 4, cur, dst, nullptr,
+                            nullptr, 0.f, 0.f},
+                    (uint32_t)(nvox / 256));
             else
-                put(first + j - 1, JfaStep{kJfaNear2, c.n, L, 0, 0, cur, dst, nullptr, nullptr, 0.f, 0.f},
+                put(first + j - 1, JfaStep{kJfaNear2, c.n, L, 0, cur, dst, nullptr, nullptr, 0.f, 0.f},
                     (uint32_t)(nvox / 512));
             cur = dst;
             next ^= 1;
         }
         put(B->max_passes,
-            JfaStep{kJfaFinal, c.n, L, 0, 0, cur, seeds, B->dist2 + B->coff[i], B->coarse_sdf + B->coff[i], c.h,
-                    d.beta},
+            JfaStep{kJfaFinal, c.n, L, 0, cur, seeds, B->dist2 + B->coff[i], B->coarse_sdf + B->coff[i], c.h, d.beta},
             (uint32_t)(nvox / 512));
         // selection
         const int logr = ilog2(f.n / c.n);
@@ -489,10 +486,10 @@ extern "C" int rtsdf_batch_step(rtsdf_batch *B, uint32_t frame, const uint32_t *
             jfa_batch<kJfaConvert><<<dim3(L[kJfaConvert].blocks), dim3(256), 0, s>>>(
                 plan, r + L[kJfaConvert].offset, L[kJfaConvert].count);
         if (L[kJfaFarLinear].blocks)
-            jfa_batch<kJfaFarLinear><<<dim3(L[kJfaFarLinear].blocks), dim3(512), 0, s>>>(
+            jfa_batch<kJfaFarLinear><<<dim3(L[kJfaFarLinear].blocks), dim3(256), 0, s>>>(
                 plan, r + L[kJfaFarLinear].offset, L[kJfaFarLinear].count);
         if (L[kJfaFarBricks].blocks)
-            jfa_batch<kJfaFarBricks><<<dim3(L[kJfaFarBricks].blocks), dim3(512), 0, s>>>(
+            jfa_batch<kJfaFarBricks><<<dim3(L[kJfaFarBricks].blocks), dim3(256), 0, s>>>(
                 plan, r + L[kJfaFarBricks].offset, L[kJfaFarBricks].count);
         if (L[kJfaNear2].blocks)
             jfa_batch<kJfaNear2><<<dim3(L[kJfaNear2].blocks), dim3(512), 0, s>>>(plan, r + L[kJfaNear2].offset,
