@@ -32,6 +32,7 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic VALU lane-operations of the tracer per unit of work:
 OPS_NODE = 39   # one two-child node: 2 x (6 slab FMAs + 12 min/max + 1 compare) + ordering
+OPS_NODE4 = 103  # one 4-wide node: 4 x 19.5 (the same slab test per child) + a 5-comparator sort (5 x 5)
 OPS_TRI = 33    # triangle-frame test: 18 FMAs (plane + 2 barycentric rows), 1/q, t, 2 barycentrics, margin, compares
 OPS_RAY = 360   # Philox4x64-10 (10 rounds), Marsaglia mapping, ray set-up, accumulation
 
@@ -52,6 +53,9 @@ def parse():
     ap.add_argument("--loop", type=int, default=3, choices=[0, 1, 2, 3])
     ap.add_argument("--bin", type=int, default=1, choices=[0, 1])
     ap.add_argument("--stack-lds", type=int, default=12, choices=[12, 16, 24])
+    ap.add_argument("--tile-texels", type=int, default=64, choices=[16, 32, 64])
+    ap.add_argument("--bvh-width", type=int, default=2, choices=[2, 4],
+                    help="trace the two-child hierarchy or its 4-wide copy (static and refitted scenes)")
     ap.add_argument("--leaf-size", type=int, default=2)
     ap.add_argument("--jfa", default="jfa", choices=["jfa", "jfa+1", "jfa+2", "1+jfa"],
                     help="jump-flooding pass schedule (the extra-pass variants reduce its errors)")
@@ -149,7 +153,8 @@ def main():
         return run_diff(args)
     w = workload(args.config)
     tuning = dict(refill=args.refill, blocks_per_cu=args.blocks_per_cu, stats=0, loop=args.loop,
-                  bin_directions=args.bin, stack_lds=args.stack_lds)
+                  bin_directions=args.bin, stack_lds=args.stack_lds, tile_texels=args.tile_texels,
+                  bvh_width=args.bvh_width)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.calibrate_copy:
@@ -158,7 +163,6 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    R.rtsdf_trace_config(**tuning)
     use_parts = args.parts and args.config == "dynamic"
     kw = dict(seed=0, scene_id=w.scene_seed, alpha=w.alpha if args.alpha is None else args.alpha,
               leaf_size=args.leaf_size, jfa_variant=args.jfa, sampling=args.sampling)
@@ -182,6 +186,9 @@ def main():
             # the animated subset moves rigidly
             dyn = w.extra["scene"]
             dyn_frames = [torch.from_numpy(dyn.mesh(f).vertices).to(dev) for f in range(nfr)]
+    if args.bvh_width == 4 and (use_parts or p.rebuild or args.config == "dynamic"):
+        tuning["bvh_width"] = 2  # the 4-wide copy serves static and refitted single-level scenes
+    p.scene.set_tuning(**tuning)  # this scene's tracer tuning (builds the 4-wide copy if asked for)
     info = p.scene.info()
     stream = torch.cuda.current_stream()
 
@@ -231,14 +238,15 @@ def main():
     trace_s = stage["trace"] / 1e3
 
     # instrumented frame (untimed): node visits and triangle tests per ray
-    R.rtsdf_trace_config(**{**tuning, "stats": 1})
+    p.scene.set_tuning(**{**tuning, "stats": 1})
     p.trace(args.warmup + K)
     torch.cuda.synchronize()
     ctr = p.trace_ws[8:72].view(torch.int64).cpu().tolist()
-    R.rtsdf_trace_config(**tuning)
+    p.scene.set_tuning(**tuning)
     nodes_per_ray = ctr[0] / max(ctr[2], 1)
     tris_per_ray = ctr[1] / max(ctr[2], 1)
-    ops = rays * (OPS_RAY + nodes_per_ray * OPS_NODE + tris_per_ray * OPS_TRI)
+    ops_node = OPS_NODE4 if tuning["bvh_width"] == 4 else OPS_NODE
+    ops = rays * (OPS_RAY + nodes_per_ray * ops_node + tris_per_ray * OPS_TRI)
     achieved = ops / trace_s / 1e12
 
     graph_ms = None
@@ -267,7 +275,10 @@ def main():
     # current kernel sources (else null)
     from paper_2210_04449_amd.prof_summary import traffic_from_summary
     inst = "true" if use_parts else "false"
-    tname = f"trace_persistent<{tuning['stack_lds']},{tuning['refill']},{tuning['loop']},false,false,{inst}>"
+    if tuning["bvh_width"] == 4:
+        tname = f"trace_persistent<{tuning['stack_lds']},{tuning['refill']},3,false,false,false,true>"
+    else:
+        tname = f"trace_persistent<{tuning['stack_lds']},{tuning['refill']},{tuning['loop']},false,false,{inst}>"
     tr = traffic_from_summary(os.path.join(ROOT, "profiles", f"pmc_{w.name}_{w.nc}_{w.nf}.txt"), tname)
     traffic = None if tr is None else int(tr["fetch_bytes"] + tr["write_bytes"])
 

@@ -408,7 +408,7 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
  * one batch, so callers tracing different scenes do not share it.
  * rtsdf_scene_get_tuning returns the tuning a trace of the scene uses.
  * Defaults: refill 16, blocks_per_cu 0, stats 0, loop 3, bin_directions 1,
- * stack_lds 12, tile_texels 64:
+ * stack_lds 12, tile_texels 64, bvh_width 2:
  *   refill          a wavefront hands out new rays once this many of its
  *                   lanes are free (8 or 16);
  *   blocks_per_cu   persistent workgroups of four wavefronts per compute
@@ -432,10 +432,21 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
  *   stack_lds       traversal stack entries kept in LDS per lane (12, 16 or
  *                   24); deeper entries go to the workspace's spill area;
  *   tile_texels     texels per wavefront tile at most (16, 32 or 64; a tile
- *                   also holds at most 768 rays, i.e. 768 / rays texels).
+ *                   also holds at most 768 rays, i.e. 768 / rays texels);
+ *   bvh_width       2: traverse the two-child hierarchy; 4: a 4-wide copy of
+ *                   it (each wide node takes up to four descendants of a
+ *                   two-child node, greedily by box area; the boxes are the
+ *                   same, and a refit updates both), with the one-fetch loop.
+ *                   rtsdf_scene_set_tuning with bvh_width 4 builds a
+ *                   single-level scene's 4-wide copy on first use (it
+ *                   allocates and synchronises the device); EINVAL for
+ *                   two-level scenes, scenes that rebuild on the device
+ *                   (enable_rebuild drops the copy) and copies too deep for
+ *                   the traversal stack.  Scenes without the copy, and
+ *                   batches, trace with width 2 whatever the tuning says.
  * Values outside these sets are rejected with RTSDF_EINVAL. */
 typedef struct rtsdf_trace_tuning {
-    int32_t refill, blocks_per_cu, stats, loop, bin_directions, stack_lds, tile_texels;
+    int32_t refill, blocks_per_cu, stats, loop, bin_directions, stack_lds, tile_texels, bvh_width;
 } rtsdf_trace_tuning;
 int rtsdf_trace_config(const rtsdf_trace_tuning *tuning);
 int rtsdf_trace_config_get(rtsdf_trace_tuning *tuning);

@@ -12,7 +12,10 @@ batch) with HIP events and keeps the fastest.  The knobs:
 * ``refill``         free lanes at which a wavefront takes new rays;
 * ``stack_lds``      traversal stack entries per lane kept in LDS;
 * ``bin_directions`` sorting a tile's rays by direction;
-* ``loop``           traversal loop shape.
+* ``loop``           traversal loop shape;
+* ``bvh_width``      the two-child hierarchy or its 4-wide copy (single-level
+  scenes that refit or stay static; batches and device-rebuilt or two-level
+  scenes trace two-wide and skip this knob).
 
 The search is coordinate descent from the target's current tuning: each knob
 in turn takes each of its values with the others fixed, a change is kept when
@@ -47,6 +50,7 @@ SPACE = {
     "stack_lds": (12, 16, 24),
     "bin_directions": (1, 0),
     "loop": (3, 2),
+    "bvh_width": (2, 4),
 }
 
 
@@ -152,6 +156,8 @@ def tune(target, reps: int = 2, space: dict = SPACE, cache: str | None = DEFAULT
     from .pipeline import Pipeline
 
     if isinstance(target, Pipeline):
+        if target.parts or target.rebuild:  # two-level and device-rebuilt scenes trace two-wide
+            space = {k: v for k, v in space.items() if k != "bvh_width"}
         key = cache_key(target.nf, int(target.faces.shape[0]), target.rays)
         current = target.scene.tuning().as_dict()
         target.step(0)  # coarse stages and selection once; timing repeats the trace only
@@ -164,6 +170,7 @@ def tune(target, reps: int = 2, space: dict = SPACE, cache: str | None = DEFAULT
         def apply(t):
             target.scene.set_tuning(**t, stats=0)
     else:
+        space = {k: v for k, v in space.items() if k != "bvh_width"}  # batches trace two-wide
         key = batch_cache_key(target)
         current = {**R.rtsdf_trace_config_get().as_dict(), **getattr(target, "_tuning", {})}
         frame = [0]

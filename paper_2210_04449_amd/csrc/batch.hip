@@ -388,6 +388,7 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
         P.bvh.nodes = sc->nodes;
         P.bvh.tris = sc->tris;
         P.bvh.tmap = sc->tmap;
+        P.nodes4 = nullptr;  // batches trace the two-child hierarchy
         P.nt = sc->nt;
         P.queue = B->queue + B->foff[i];
         P.count = B->counts + i;

@@ -599,7 +599,8 @@ extern "C" int rtsdf_scene_enable_rebuild(rtsdf_scene *sc, rtsdf_stream stream)
         (void)hipFree(counter);
         return RTSDF_ENOMEM;
     }
-    // the rebuilt tree replaces the creation hierarchy (and the refit tables that went with it)
+    // the rebuilt tree replaces the creation hierarchy (and the refit tables and 4-wide copy that went with it)
+    wide_free(sc);
     (void)hipFree(sc->nodes);
     (void)hipFree(sc->refit_counter);
     sc->nodes = nodes;

@@ -106,6 +106,13 @@ struct rtsdf_scene {
     int nentries = 0;                  // subtrees of moving parts that the top level holds
     int32_t *entry_part = nullptr;     // [nentries] part of each (1..ninst-1)
     rtsdf_lbvh *lbvh = nullptr;        // set once the scene rebuilds its hierarchy on the device
+    // 4-wide copy of the hierarchy for the tracer (rtsdf_scene_set_tuning with bvh_width 4): node j is the two
+    // records 2 j (children 0, 1) and 2 j + 1 (children 2, 3) in the two-child format; map4[4 j + k] is the
+    // two-child slot (node << 1 | slot) whose box child k mirrors, -1 for an empty child
+    rtsdf::BvhNode *nodes4 = nullptr;
+    int32_t *map4 = nullptr;
+    int nnodes4 = 0;
+    int depth4 = 0;                    // deepest wide level (root = 0)
 };
 
 static void lbvh_free(rtsdf_lbvh *L);
@@ -493,6 +500,20 @@ __device__ __forceinline__ void get_slot(const BvhNode *nd, int slot, float lo[3
     hi[2] = z[2 * slot + 1];
 }
 
+// 4-wide copy: child k of wide node i takes the box of the two-child slot map[4 i + k] (after a refit of
+// the two-child hierarchy).  Children 2 r and 2 r + 1 share a record but write different words.
+__global__ void __launch_bounds__(256) wide_gather(BvhNode *__restrict__ wide, const int32_t *__restrict__ map,
+                                                   const BvhNode *__restrict__ nodes, int nslots)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nslots) return;
+    const int m = map[i];
+    if (m < 0) return;
+    float lo[3], hi[3];
+    get_slot(&nodes[m >> 1], m & 1, lo, hi);
+    set_slot(&wide[i >> 1], i & 1, lo, hi);
+}
+
 // Every thread starts at an internal node whose children are both leaves and
 // climbs; at a node with two internal children only the second arrival goes on.
 __global__ void refit_nodes(BvhNode *nodes, const float4 *__restrict__ tris, const int32_t *__restrict__ starts,
@@ -680,8 +701,135 @@ extern "C" int rtsdf_scene_refit(rtsdf_scene *scene, const float *vertices, rtsd
     refit_nodes<<<dim3((scene->nstart + 255) / 256), dim3(256), 0, s>>>(scene->nodes, scene->tris, scene->start_nodes,
                                                                          scene->nstart, scene->refit_counter, scene->pad);
     RTSDF_CHECK_LAUNCH();
+    if (scene->nodes4) {
+        const int nslots = 4 * scene->nnodes4;
+        wide_gather<<<dim3((nslots + 255) / 256), dim3(256), 0, s>>>(scene->nodes4, scene->map4, scene->nodes, nslots);
+        RTSDF_CHECK_LAUNCH();
+    }
     return RTSDF_OK;
 }
+
+namespace rtsdf {
+
+// Collapse the two-child hierarchy into a 4-wide one (host): a wide node takes
+// the two children of its two-child node and keeps replacing its internal
+// child of largest box area by that child's two children while it has fewer
+// than four (the usual greedy collapse); leaves stay where they are.  The
+// boxes are copies of two-child slots, so a hit in the wide tree is a hit in
+// the two-child tree and traversal finds the same closest hit.
+static int wide_build(rtsdf_scene *sc, hipStream_t s)
+{
+    if (sc->nodes4) return RTSDF_OK;
+    if (sc->ninst > 0 || sc->lbvh || sc->nnodes < 1 || sc->nref < 1) return RTSDF_EINVAL;
+    std::vector<BvhNode> h(sc->nnodes);
+    RTSDF_TRY(hipMemcpyAsync(h.data(), sc->nodes, sizeof(BvhNode) * h.size(), hipMemcpyDeviceToHost, s));
+    RTSDF_TRY(hipStreamSynchronize(s));
+    std::vector<BvhNode> w;
+    std::vector<int32_t> map;
+    int depth4 = 0;
+    struct Slot {
+        int node, slot;
+    };
+    auto code_of = [&](const Slot &q) { return q.slot ? h[q.node].meta.y : h[q.node].meta.x; };
+    auto area_of = [&](const Slot &q) {
+        const BvhNode &nd = h[q.node];
+        const float4 xy = q.slot ? nd.xy1 : nd.xy0;
+        const float lz = q.slot ? nd.z01.z : nd.z01.x, hz = q.slot ? nd.z01.w : nd.z01.y;
+        const double dx = std::max(0.0, (double)xy.y - xy.x), dy = std::max(0.0, (double)xy.w - xy.z),
+                     dz = std::max(0.0, (double)hz - lz);
+        return dx * dy + dy * dz + dz * dx;
+    };
+    // iterative: (two-child node, wide index) pairs still to fill; wide nodes are allocated when first referenced
+    struct Todo {
+        int node2, wide, depth;
+    };
+    std::vector<Todo> todo{{0, 0, 0}};
+    w.resize(2);
+    map.resize(4, -1);
+    while (!todo.empty()) {
+        const Todo t = todo.back();
+        todo.pop_back();
+        depth4 = std::max(depth4, t.depth);
+        std::vector<Slot> kids{{t.node2, 0}, {t.node2, 1}};
+        while (kids.size() < 4) {
+            int best = -1;
+            double best_area = -1.0;
+            for (int k = 0; k < (int)kids.size(); ++k)
+                if (code_of(kids[k]) >= 0 && area_of(kids[k]) > best_area) {
+                    best = k;
+                    best_area = area_of(kids[k]);
+                }
+            if (best < 0) break;
+            const int c = code_of(kids[best]);
+            kids[best] = Slot{c, 0};
+            kids.insert(kids.begin() + best + 1, Slot{c, 1});
+        }
+        for (int k = 0; k < 4; ++k) {
+            BvhNode &rec = w[2 * t.wide + (k >> 1)];
+            float *xy = (k & 1) ? &rec.xy1.x : &rec.xy0.x;
+            float *z = &rec.z01.x;
+            int *m = (k & 1) ? &rec.meta.y : &rec.meta.x;
+            if (k < (int)kids.size()) {
+                const Slot &q = kids[k];
+                const BvhNode &nd = h[q.node];
+                const float4 sxy = q.slot ? nd.xy1 : nd.xy0;
+                xy[0] = sxy.x; xy[1] = sxy.y; xy[2] = sxy.z; xy[3] = sxy.w;
+                z[2 * (k & 1)] = q.slot ? nd.z01.z : nd.z01.x;
+                z[2 * (k & 1) + 1] = q.slot ? nd.z01.w : nd.z01.y;
+                map[4 * t.wide + k] = q.node << 1 | q.slot;
+                const int c = code_of(q);
+                if (c >= 0) {  // an internal child: a new wide node, filled later
+                    const int wi = (int)w.size() / 2;
+                    *m = wi;
+                    todo.push_back(Todo{c, wi, t.depth + 1});
+                    w.resize(w.size() + 2);
+                    map.resize(map.size() + 4, -1);
+                } else {
+                    *m = c;
+                }
+            } else {
+                // empty child: a point box far outside the scene (finite, so every slab distance stays finite
+                // for any ray set-up; entered only by a ray aimed exactly at it, and then an empty leaf)
+                xy[0] = xy[1] = xy[2] = xy[3] = 1e18f;
+                z[2 * (k & 1)] = z[2 * (k & 1) + 1] = 1e18f;
+                *m = leaf_code(0, 0);
+            }
+        }
+    }
+    const int nw = (int)w.size() / 2;
+    BvhNode *dn = nullptr;
+    int32_t *dm = nullptr;
+    if (hipMalloc((void **)&dn, sizeof(BvhNode) * w.size()) != hipSuccess) return RTSDF_ENOMEM;
+    if (hipMalloc((void **)&dm, sizeof(int32_t) * map.size()) != hipSuccess) {
+        (void)hipFree(dn);
+        return RTSDF_ENOMEM;
+    }
+    if (hipMemcpyAsync(dn, w.data(), sizeof(BvhNode) * w.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(dm, map.data(), sizeof(int32_t) * map.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipFree(dn);
+        (void)hipFree(dm);
+        return RTSDF_EHIP;
+    }
+    sc->nodes4 = dn;
+    sc->map4 = dm;
+    sc->nnodes4 = nw;
+    sc->depth4 = depth4;
+    sc->bytes += (int64_t)(sizeof(BvhNode) * w.size() + sizeof(int32_t) * map.size());
+    return RTSDF_OK;
+}
+
+static void wide_free(rtsdf_scene *sc)
+{
+    (void)hipFree(sc->nodes4);
+    (void)hipFree(sc->map4);
+    sc->nodes4 = nullptr;
+    sc->map4 = nullptr;
+    sc->nnodes4 = 0;
+    sc->depth4 = 0;
+}
+
+}  // namespace rtsdf
 
 extern "C" int rtsdf_scene_set_sign(rtsdf_scene *scene, int32_t policy, float shell)
 {
@@ -756,5 +904,6 @@ extern "C" void rtsdf_scene_destroy(rtsdf_scene *scene)
     (void)hipFree(scene->faces);
     (void)hipFree(scene->refit_counter);
     (void)hipFree(scene->start_nodes);
+    rtsdf::wide_free(scene);
     delete scene;
 }

@@ -289,6 +289,7 @@ __device__ __forceinline__ void trav_step(const BvhView &S, const RaySetup &R, i
 // Everything the tracer needs to know about one scene.
 struct TraceScene {
     BvhView bvh;
+    const BvhNode *nodes4;  // 4-wide copy (WIDE launches)
     int nt;
     const int32_t *queue;
     const int32_t *count;
@@ -430,6 +431,56 @@ __device__ __forceinline__ void node_step(const BvhView &S, int stride, const Ra
     }
 }
 
+// One 4-wide node (two records: children 0, 1 in a, b, z, m and 2, 3 in a2,
+// b2, z2, m2): test the four boxes, order the hit children by entry
+// distance (a five-comparator sorting network), go to the nearest (a leaf
+// becomes the triangle range at once, the next nearest child is then next)
+// and request pushes of the other hit children, farthest first.
+__device__ __forceinline__ void swap_if_greater(float &ta, int &ca, float &tb, int &cb)
+{
+    const bool sw = ta > tb;
+    const float t = sw ? tb : ta;
+    tb = sw ? ta : tb;
+    ta = t;
+    const int c = sw ? cb : ca;
+    cb = sw ? ca : cb;
+    ca = c;
+}
+
+__device__ __forceinline__ void node4_step_regs(const RaySetup &R, float4 a, float4 b, float4 z, int2 m, float4 a2,
+                                                float4 b2, float4 z2, int2 m2, int &node, float tbest, int &tri_cur,
+                                                int &tri_end, bool &p1, bool &p2, bool &p3, int &v1, int &v2, int &v3,
+                                                bool &pop)
+{
+    const float inf = __builtin_inff();
+    float t0, t1, t2, t3;
+    const bool h0 = box_hit(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest, t0);
+    const bool h1 = box_hit(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest, t1);
+    const bool h2 = box_hit(R, a2.x, a2.y, a2.z, a2.w, z2.x, z2.y, tbest, t2);
+    const bool h3 = box_hit(R, b2.x, b2.y, b2.z, b2.w, z2.z, z2.w, tbest, t3);
+    float e0 = h0 ? t0 : inf, e1 = h1 ? t1 : inf, e2 = h2 ? t2 : inf, e3 = h3 ? t3 : inf;
+    int c0 = m.x, c1 = m.y, c2 = m2.x, c3 = m2.y;
+    swap_if_greater(e0, c0, e1, c1);
+    swap_if_greater(e2, c2, e3, c3);
+    swap_if_greater(e0, c0, e2, c2);
+    swap_if_greater(e1, c1, e3, c3);
+    swap_if_greater(e1, c1, e2, c2);
+    const bool any = e0 < inf;
+    const bool leaf0 = any && c0 < 0;
+    if (leaf0) {
+        tri_cur = leaf_first(c0);
+        tri_end = tri_cur + leaf_count(c0);
+    }
+    node = leaf0 ? c1 : c0;
+    pop = !any || (leaf0 && !(e1 < inf));
+    p3 = e3 < inf;
+    p2 = e2 < inf;
+    p1 = e1 < inf && !leaf0;
+    v1 = c1;
+    v2 = c2;
+    v3 = c3;
+}
+
 // Same decisions as node_step, written as selects: the caller performs the
 // (at most one) push and the (at most one) pop after the lane's work of the
 // iteration, so every lane shares one copy of the stack code.
@@ -534,7 +585,7 @@ __global__ void trace_tile_prefix(const TraceScene *scenes, int n, int cap, int3
 // node visits, triangle tests, rays, traversal-loop iterations x 64, refill
 // rounds x 64, lane-iterations with work (LOOP 1 and 2), tiles x 64, node
 // visits that entered neither child box (LOOP 3).
-template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED, bool INST = false>
+template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED, bool INST = false, bool WIDE = false>
 __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_waves_per_eu(6, 8)))
 trace_persistent(TraceArgs A)
 {
@@ -718,14 +769,27 @@ trace_persistent(TraceArgs A)
                     const bool do_tri = busy && tri_cur < tri_end;
                     const bool do_node = busy && !do_tri && node >= 0;
                     // (lanes with neither load the root node, which every scene allocates, and ignore it)
-                    const char *base = do_tri ? reinterpret_cast<const char *>(S.tmap) + (uint32_t)tri_cur * 48u
-                                              : reinterpret_cast<const char *>(S.nodes) +
-                                                    (uint32_t)(do_node ? node : 0) * 64u;
+                    const char *base =
+                        do_tri ? reinterpret_cast<const char *>(S.tmap) + (uint32_t)tri_cur * 48u
+                               : WIDE ? reinterpret_cast<const char *>(P.nodes4) + (uint32_t)(do_node ? node : 0) * 128u
+                                      : reinterpret_cast<const char *>(S.nodes) + (uint32_t)(do_node ? node : 0) * 64u;
                     const float4 *q = reinterpret_cast<const float4 *>(base);
                     const float4 w0 = q[0], w1 = q[1], w2 = q[2];
                     const int2 w3 = *reinterpret_cast<const int2 *>(q + 3);  // the map array has 16 B of padding
+                    // a wide node's second record (other lanes re-read their first 64 bytes)
+                    float4 w4, w5, w6;
+                    int2 w7;
+                    if (WIDE) {
+                        const float4 *q2 = do_node ? q + 4 : q;
+                        w4 = q2[0];
+                        w5 = q2[1];
+                        w6 = q2[2];
+                        w7 = *reinterpret_cast<const int2 *>(q2 + 3);
+                    }
                     bool push = false, pop = false;
                     int push_val = 0;
+                    bool p1 = false, p2 = false, p3 = false;
+                    int v1 = 0, v2 = 0, v3 = 0;
                     if (do_tri) {
                         if (STATS) ++st_tris;
                         tri_test_rows(Rs, w0, w1, w2, S.tris, tri_cur, tbest, ibest, front);
@@ -745,6 +809,10 @@ trace_persistent(TraceArgs A)
                             push = true;
                             push_val = kReturn;
                             node = w3.x;
+                        } else if (WIDE) {
+                            node4_step_regs(Rs, w0, w1, w2, w3, w4, w5, w6, w7, node, tbest, tri_cur, tri_end, p1, p2,
+                                            p3, v1, v2, v3, pop);
+                            if (STATS) st_empty += pop && tri_cur >= tri_end;  // no child box was entered
                         } else {
                             const int4 m = make_int4(w3.x, w3.y, 0, 0);
                             node_step_regs(Rs, w0, w1, w2, m, node, tbest, tri_cur, tri_end, push, push_val, pop);
@@ -761,6 +829,11 @@ trace_persistent(TraceArgs A)
                         tri_cur = leaf_first(node);
                         tri_end = tri_cur + leaf_count(node);
                         pop = true;
+                    }
+                    if (WIDE) {  // farthest first, so the nearest is popped first
+                        if (p3) stack_push<SL>(stride, sp, stk, spill, v3);
+                        if (p2) stack_push<SL>(stride, sp, stk, spill, v2);
+                        if (p1) stack_push<SL>(stride, sp, stk, spill, v1);
                     }
                     if (push) stack_push<SL>(stride, sp, stk, spill, push_val);
                     if (pop) node = stack_pop<SL>(stride, sp, stk, spill);
@@ -1010,7 +1083,7 @@ __global__ void __launch_bounds__(256) trace_backward_kernel(const float *__rest
 
 // ------------------------------------------------------------- launch ----
 
-static rtsdf_trace_tuning g_tuning = {16, 0, 0, 3, 1, 12, 64};
+static rtsdf_trace_tuning g_tuning = {16, 0, 0, 3, 1, 12, 64, 2};
 constexpr int kMaxBlocksPerCu = 8;  // persistent workgroups per CU (direction buffers and spill area sized for this)
 constexpr int kMinShortStack = 12;  // smallest LDS stack part (spill area sized for this)
 constexpr int kMaxStackDepth = 64;  // deepest hierarchy the tracer takes
@@ -1023,10 +1096,11 @@ static bool tuning_ok(const rtsdf_trace_tuning &t)
     if (t.bin_directions < 0 || t.bin_directions > 1) return false;
     if (t.stack_lds != 12 && t.stack_lds != 16 && t.stack_lds != 24) return false;
     if (t.tile_texels != 16 && t.tile_texels != 32 && t.tile_texels != 64) return false;
+    if (t.bvh_width != 2 && t.bvh_width != 4) return false;
     return true;
 }
 
-template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED, bool INST = false>
+template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED, bool INST = false, bool WIDE = false>
 static int launch_trace5(TraceArgs A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
     int per_cu = T.blocks_per_cu;
@@ -1041,7 +1115,7 @@ static int launch_trace5(TraceArgs A, const rtsdf_trace_tuning &T, hipStream_t s
     A.spill_stride = blocks * kTraceWaves * kWave;
     A.bin_directions = T.bin_directions;
     A.tile_cap = T.tile_texels;
-    trace_persistent<SL, REFILL, LOOP, STATS, BATCHED, INST><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
+    trace_persistent<SL, REFILL, LOOP, STATS, BATCHED, INST, WIDE><<<dim3(blocks), dim3(kTraceWaves * kWave), 0, s>>>(A);
     RTSDF_CHECK_LAUNCH();
     return RTSDF_OK;
 }
@@ -1093,6 +1167,23 @@ static int launch_trace_inst(const TraceArgs &A, const rtsdf_trace_tuning &T, hi
     }
 }
 
+// 4-wide single-scene launches: the one-fetch loop only
+template <int SL, int REFILL>
+static int launch_trace_wide2(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
+{
+    return T.stats ? launch_trace5<SL, REFILL, 3, true, false, false, true>(A, T, s)
+                   : launch_trace5<SL, REFILL, 3, false, false, false, true>(A, T, s);
+}
+
+static int launch_trace_wide(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
+{
+    switch (T.stack_lds) {
+    case 12: return T.refill == 8 ? launch_trace_wide2<12, 8>(A, T, s) : launch_trace_wide2<12, 16>(A, T, s);
+    case 24: return T.refill == 8 ? launch_trace_wide2<24, 8>(A, T, s) : launch_trace_wide2<24, 16>(A, T, s);
+    default: return T.refill == 8 ? launch_trace_wide2<16, 8>(A, T, s) : launch_trace_wide2<16, 16>(A, T, s);
+    }
+}
+
 template <bool BATCHED>
 static int launch_trace(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
@@ -1104,6 +1195,16 @@ static int launch_trace(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStre
 }
 
 static int stack_depth_for(const rtsdf_scene *sc) { return sc->max_depth + 1; }
+
+// stack entries a 4-wide traversal can hold at once: up to three pushed at each wide level on the path
+// (levels 0 .. depth4), plus one
+static int wide_stack_depth(const rtsdf_scene *sc) { return 3 * (sc->depth4 + 1) + 1; }
+
+// whether a trace of this scene with tuning T runs the 4-wide loop
+static bool trace_wide(const rtsdf_scene *sc, const rtsdf_trace_tuning &T)
+{
+    return T.bvh_width == 4 && sc->nodes4 && sc->ninst == 0 && wide_stack_depth(sc) <= kMaxStackDepth;
+}
 
 // the tuning a trace of this scene uses: its own if set, else the process default
 static const rtsdf_trace_tuning &tuning_for(const rtsdf_scene *sc)
@@ -1135,6 +1236,11 @@ extern "C" int rtsdf_trace_config(const rtsdf_trace_tuning *t)
 extern "C" int rtsdf_scene_set_tuning(rtsdf_scene *scene, const rtsdf_trace_tuning *t)
 {
     if (!scene || (t && !rtsdf::tuning_ok(*t))) return RTSDF_EINVAL;
+    if (t && t->bvh_width == 4 && !scene->nodes4) {  // the 4-wide copy is built on first use
+        const int rc = rtsdf::wide_build(scene, nullptr);
+        if (rc != RTSDF_OK) return rc;
+        if (rtsdf::wide_stack_depth(scene) > rtsdf::kMaxStackDepth) return RTSDF_EINVAL;
+    }
     scene->has_tuning = t != nullptr;
     if (t) scene->tuning = *t;
     return RTSDF_OK;
@@ -1200,6 +1306,7 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     P.bvh.nodes = scene->nodes;
     P.bvh.tris = scene->tris;
     P.bvh.tmap = scene->tmap;
+    P.nodes4 = scene->nodes4;
     P.nt = scene->nt;
     P.queue = queue;
     P.count = count;
@@ -1233,7 +1340,8 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     A.spill = ws_spill(workspace);
     A.spill_stride = 0;
     A.dirs = ws_dirs(workspace);
-    return scene->ninst > 0 ? launch_trace_inst(A, T, s) : launch_trace<false>(A, T, s);
+    if (scene->ninst > 0) return launch_trace_inst(A, T, s);
+    return trace_wide(scene, T) ? launch_trace_wide(A, T, s) : launch_trace<false>(A, T, s);
 }
 
 extern "C" int rtsdf_directions(const int32_t *texel, const uint32_t *frame, const int32_t *ray, int32_t n,

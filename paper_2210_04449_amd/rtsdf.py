@@ -68,7 +68,7 @@ class BatchView(C.Structure):
 
 class TraceTuning(C.Structure):
     _fields_ = [("refill", _i32), ("blocks_per_cu", _i32), ("stats", _i32), ("loop", _i32),
-                ("bin_directions", _i32), ("stack_lds", _i32), ("tile_texels", _i32)]
+                ("bin_directions", _i32), ("stack_lds", _i32), ("tile_texels", _i32), ("bvh_width", _i32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

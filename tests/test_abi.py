@@ -100,7 +100,8 @@ def test_host_validation(R):
     assert L.rtsdf_shadow_ex(fine, dummy, dummy, 4, C.byref(sp), dummy, dummy, None) == R.EINVAL
     assert L.rtsdf_shadow_ex(fine, dummy, dummy, 4, None, None, dummy, None) == R.EINVAL
     for bad in (dict(refill=3), dict(loop=4), dict(stack_lds=20), dict(bin_directions=5), dict(blocks_per_cu=-1),
-                dict(blocks_per_cu=9), dict(tile_texels=48), dict(tile_texels=0)):
+                dict(blocks_per_cu=9), dict(tile_texels=48), dict(tile_texels=0), dict(bvh_width=3),
+                dict(bvh_width=8)):
         t = R.TraceTuning(**{**R.rtsdf_trace_config_get().as_dict(), **bad})
         assert L.rtsdf_trace_config(C.byref(t)) == R.EINVAL
         assert L.rtsdf_scene_set_tuning(dummy, C.byref(t)) == R.EINVAL  # rejected before the scene is read
@@ -147,7 +148,7 @@ def test_struct_layouts_match_header(R, tmp_path):
         "rtsdf_scene_info": (R.SceneInfo, ["nv", "nt", "nodes", "max_depth", "leaf_size", "device_bytes", "references",
                                             "instances"]),
         "rtsdf_trace_tuning": (R.TraceTuning, ["refill", "blocks_per_cu", "stats", "loop", "bin_directions",
-                                               "stack_lds", "tile_texels"]),
+                                               "stack_lds", "tile_texels", "bvh_width"]),
         "rtsdf_frame_desc": (R.FrameDesc, [f for f, _ in R.FrameDesc._fields_]),
         "rtsdf_batch_scene": (R.BatchScene, [f for f, _ in R.BatchScene._fields_]),
         "rtsdf_batch_view": (R.BatchView, [f for f, _ in R.BatchView._fields_]),
