@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--refill", type=int, default=16)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
-    ap.add_argument("--loop", type=int, default=3, choices=[0, 1, 2, 3])
+    ap.add_argument("--loop", type=int, default=4, choices=[0, 1, 2, 3, 4])
     ap.add_argument("--bin", type=int, default=1, choices=[0, 1])
     ap.add_argument("--stack-lds", type=int, default=12, choices=[12, 16, 24])
     ap.add_argument("--tile-texels", type=int, default=64, choices=[16, 32, 64])
@@ -238,13 +238,20 @@ def main():
     trace_s = stage["trace"] / 1e3
 
     # instrumented frame (untimed): node visits and triangle tests per ray
-    p.scene.set_tuning(**{**tuning, "stats": 1})
-    p.trace(args.warmup + K)
-    torch.cuda.synchronize()
-    ctr = p.trace_ws[8:72].view(torch.int64).cpu().tolist()
-    p.scene.set_tuning(**tuning)
-    nodes_per_ray = ctr[0] / max(ctr[2], 1)
-    tris_per_ray = ctr[1] / max(ctr[2], 1)
+    def counters(t):
+        p.scene.set_tuning(**{**t, "stats": 1})
+        p.trace(args.warmup + K)
+        torch.cuda.synchronize()
+        c = p.trace_ws[8:72].view(torch.int64).cpu().tolist()
+        p.scene.set_tuning(**tuning)
+        return c
+    ctr = counters(tuning)
+    # algorithmic work: the visits and tests of a traversal that culls with its ray's current best distance
+    # (the one-fetch loop); the queued loop's extra ones, culled against the best as of the last flush, are
+    # overhead and are reported beside them
+    alg = counters({**tuning, "loop": 3}) if tuning["loop"] == 4 else ctr
+    nodes_per_ray = alg[0] / max(alg[2], 1)
+    tris_per_ray = alg[1] / max(alg[2], 1)
     ops_node = OPS_NODE4 if tuning["bvh_width"] == 4 else OPS_NODE
     ops = rays * (OPS_RAY + nodes_per_ray * ops_node + tris_per_ray * OPS_TRI)
     achieved = ops / trace_s / 1e12
@@ -320,9 +327,11 @@ def main():
         "jfa": {"gbps": round(jfa_gbs, 1), "frac_hbm": round(jfa_gbs / HBM_PEAK_GBS, 4),
                 "algorithmic_bytes": jfa_bytes, "schedule": args.jfa},
         "trace_stats": {"nodes_per_ray": round(nodes_per_ray, 2), "tris_per_ray": round(tris_per_ray, 2),
+                        "run_nodes_per_ray": round(ctr[0] / max(ctr[2], 1), 2),
+                        "run_tris_per_ray": round(ctr[1] / max(ctr[2], 1), 2),
                         "rays_counted": ctr[2], "wave_iterations": ctr[3] // 64, "refill_rounds": ctr[4] // 64,
                         "tiles": ctr[6] // 64,
-                        "empty_node_fraction": round(ctr[7] / max(ctr[0], 1), 4) if tuning["loop"] == 3 else None,
+                        "empty_node_fraction": round(ctr[7] / max(ctr[0], 1), 4) if tuning["loop"] in (3, 4) else None,
                         "lane_work_fraction": round(ctr[5] / max(ctr[3], 1), 4) if tuning["loop"] >= 1 else None,
                         "bvh_nodes": info.nodes, "bvh_references": info.references, "bvh_max_depth": info.max_depth,
                         "bvh_max_leaf": info.leaf_size, "leaf_size": args.leaf_size},

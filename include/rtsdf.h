@@ -407,7 +407,7 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
  * own tuning (NULL: back to the process default) and rtsdf_batch_set_tuning
  * one batch, so callers tracing different scenes do not share it.
  * rtsdf_scene_get_tuning returns the tuning a trace of the scene uses.
- * Defaults: refill 16, blocks_per_cu 0, stats 0, loop 3, bin_directions 1,
+ * Defaults: refill 16, blocks_per_cu 0, stats 0, loop 4, bin_directions 1,
  * stack_lds 12, tile_texels 64, bvh_width 2:
  *   refill          a wavefront hands out new rays once this many of its
  *                   lanes are free (8 or 16);
@@ -418,7 +418,7 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
  *                   of the workspace: node visits, triangle tests, rays,
  *                   traversal iterations x 64, refill rounds x 64, lane
  *                   iterations with work (loop >= 1), tiles x 64, node
- *                   visits entering neither child box (loop 3)
+ *                   visits entering neither child box (loop 3, 4)
  *                   (slower; for measurement only);
  *   loop            0: two phases per iteration (walk nodes until every lane
  *                   holds a leaf, then test the leaves); 1: one unit of work
@@ -426,7 +426,14 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
  *                   with one shared stack push/pop per iteration; 3: as 2,
  *                   with each lane's node or triangle record fetched by one
  *                   shared load sequence (one memory wait per iteration);
- *                   default 3;
+ *                   4: queued: lanes fetch and step nodes only and append
+ *                   the triangles of the leaves they reach to a queue of
+ *                   their wavefront; each time 64 tests are queued, every
+ *                   lane takes one (of any lane's ray); traversals cull
+ *                   with their ray's best distance as of the last queue
+ *                   flush.  Two-level scenes, 4-wide traversals and scenes
+ *                   of 2^26 or more triangle references use 3 instead;
+ *                   default 4;
  *   bin_directions  1: each wavefront's tile of rays is sorted by direction
  *                   before tracing (coherence); 0: queue order;
  *   stack_lds       traversal stack entries kept in LDS per lane (12, 16 or

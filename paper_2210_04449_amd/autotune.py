@@ -12,7 +12,7 @@ batch) with HIP events and keeps the fastest.  The knobs:
 * ``refill``         free lanes at which a wavefront takes new rays;
 * ``stack_lds``      traversal stack entries per lane kept in LDS;
 * ``bin_directions`` sorting a tile's rays by direction;
-* ``loop``           traversal loop shape;
+* ``loop``           traversal loop shape (queued triangle tests or the one-fetch loop);
 * ``bvh_width``      the two-child hierarchy or its 4-wide copy (single-level
   scenes that refit or stay static; batches and device-rebuilt or two-level
   scenes trace two-wide and skip this knob).
@@ -49,7 +49,7 @@ SPACE = {
     "refill": (16, 8),
     "stack_lds": (12, 16, 24),
     "bin_directions": (1, 0),
-    "loop": (3, 2),
+    "loop": (4, 3),
     "bvh_width": (2, 4),
 }
 

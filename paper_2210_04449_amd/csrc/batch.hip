@@ -470,7 +470,10 @@ extern "C" int rtsdf_batch_step(rtsdf_batch *B, uint32_t frame, const uint32_t *
     if (frame >= kMaxFrame && !frame_ptr) return RTSDF_EINVAL;
     hipStream_t s = as_stream(stream);
     const int n = B->n;
-    const rtsdf_trace_tuning &T = B->has_tuning ? B->tuning : g_tuning;
+    rtsdf_trace_tuning T = B->has_tuning ? B->tuning : g_tuning;
+    if (T.loop == 4)
+        for (int i = 0; i < n; ++i)
+            if (B->scenes[i]->nref >= kMaxQueuedRefs) T.loop = 3;  // queue entries hold 26-bit indices
     // voxelize
     int rc = launch_fill<int32_t>(B->seeds, -1, B->ctotal, s);
     if (rc != RTSDF_OK) return rc;

@@ -177,31 +177,44 @@ __device__ __noinline__ float tri_watertight(float ox, float oy, float oz, float
 // triangle id.
 constexpr float kEdgeMargin = 0x1p-12f;  // relative to the magnitude of the terms of the barycentrics
 
-__device__ __forceinline__ void tri_test_rows(const RaySetup &R, float4 r0, float4 r1, float4 r2, const float4 *tris,
-                                              int i, float &tbest, int &ibest, bool &front)
+// Whether the ray (origin o, direction d) meets the triangle at leaf-order index i (rows r0, r1, r2 of its
+// map) at some 0 < t <= tlim; the distance t and the facing (front: the ray meets the front face).  The
+// decision and t do not depend on tlim, which only filters the result: whichever bound a traversal holds when
+// it tests the triangle, the closest hit over all tested triangles is the same.
+__device__ __forceinline__ bool tri_hit_rows(float ox, float oy, float oz, float dx, float dy, float dz, float4 r0,
+                                             float4 r1, float4 r2, const float4 *tris, int i, float tlim, float &t,
+                                             bool &fr)
 {
-    const float pz = fmaf(r2.x, R.ox, fmaf(r2.y, R.oy, fmaf(r2.z, R.oz, r2.w)));
-    const float qz = fmaf(r2.x, R.dx, fmaf(r2.y, R.dy, r2.z * R.dz));
-    const float p0 = fmaf(r0.x, R.ox, fmaf(r0.y, R.oy, fmaf(r0.z, R.oz, r0.w)));
-    const float q0 = fmaf(r0.x, R.dx, fmaf(r0.y, R.dy, r0.z * R.dz));
-    const float p1 = fmaf(r1.x, R.ox, fmaf(r1.y, R.oy, fmaf(r1.z, R.oz, r1.w)));
-    const float q1 = fmaf(r1.x, R.dx, fmaf(r1.y, R.dy, r1.z * R.dz));
-    float t = -pz * __builtin_amdgcn_rcpf(qz);
+    const float pz = fmaf(r2.x, ox, fmaf(r2.y, oy, fmaf(r2.z, oz, r2.w)));
+    const float qz = fmaf(r2.x, dx, fmaf(r2.y, dy, r2.z * dz));
+    const float p0 = fmaf(r0.x, ox, fmaf(r0.y, oy, fmaf(r0.z, oz, r0.w)));
+    const float q0 = fmaf(r0.x, dx, fmaf(r0.y, dy, r0.z * dz));
+    const float p1 = fmaf(r1.x, ox, fmaf(r1.y, oy, fmaf(r1.z, oz, r1.w)));
+    const float q1 = fmaf(r1.x, dx, fmaf(r1.y, dy, r1.z * dz));
+    t = -pz * __builtin_amdgcn_rcpf(qz);
     const float b1 = fmaf(t, q0, p0), b2 = fmaf(t, q1, p1);
     const float bmin = fminf(1.0f - b1 - b2, fminf(b1, b2));
     const float margin = kEdgeMargin * (fmaf(t, fabsf(q0) + fabsf(q1), fabsf(p0) + fabsf(p1)) + 1.0f);
-    const bool in_range = t > 0.0f && t <= fminf(tbest, 3.0e38f);
+    const bool in_range = t > 0.0f && t <= 3.0e38f;
     bool hit = in_range && bmin > margin;
-    bool fr = qz < 0.0f;
+    fr = qz < 0.0f;
     if (in_range && !(bmin > margin) && !(bmin < -margin)) {
         // near an edge or a vertex (or not a number): the watertight test decides
         const float4 *tp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + (uint32_t)i * 48u);
-        const float h = tri_watertight(R.ox, R.oy, R.oz, R.dx, R.dy, R.dz, tp);
+        const float h = tri_watertight(ox, oy, oz, dx, dy, dz, tp);
         t = fabsf(h);
         fr = h > 0.0f;
-        hit = h != 0.0f && t <= tbest;
+        hit = h != 0.0f;
     }
-    if (!hit) return;
+    return hit && t <= tlim;
+}
+
+__device__ __forceinline__ void tri_test_rows(const RaySetup &R, float4 r0, float4 r1, float4 r2, const float4 *tris,
+                                              int i, float &tbest, int &ibest, bool &front)
+{
+    float t;
+    bool fr;
+    if (!tri_hit_rows(R.ox, R.oy, R.oz, R.dx, R.dy, R.dz, r0, r1, r2, tris, i, tbest, t, fr)) return;
     if (t == tbest) {  // equal distances: the lower original triangle id wins
         const float4 *tp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + (uint32_t)i * 48u);
         const float4 *tb = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + (uint32_t)ibest * 48u);
@@ -531,15 +544,28 @@ __device__ __forceinline__ int direction_bin(float3 d)
     return (bu & 1) | ((bv & 1) << 1) | ((bu & 2) << 1) | ((bv & 2) << 2) | ((bu & 4) << 2) | ((bv & 4) << 3);
 }
 
+// queued loop: triangle tests queued per wavefront (a power of two, at least two wavefronts' worth)
+constexpr int kQueueCap = 128;
+constexpr unsigned long long kBestInit = 0x7F800000FFFFFFFFull;  // t = +inf, no triangle
+constexpr int kMaxQueuedRefs = 1 << 26;  // queue entries: leaf-order index << 6 | lane
+static_assert(2 * kWave <= kQueueCap && (kQueueCap & (kQueueCap - 1)) == 0, "queue size");
+static_assert(kWave * 8 + kQueueCap * 4 <= kBins * 4 + kTileRays, "the queue reuses the sort area");
+
 struct WaveTile {
     int32_t tex[kTileTexels];
     unsigned long long key[kTileTexels];  // min over rays of (distance bits << 32 | ray << 26 | triangle)
     uint32_t cnt[kTileTexels];            // front | back << 16 for this frame
     uint16_t perm[kTileRays];             // ray ids (slot * R + ray) sorted by direction bin
-    struct {
-        uint32_t bin[kBins];              // bin counts, then bin cursors
-        uint8_t binof[kTileRays];         // direction bin of each ray
-    } sort;
+    union {
+        struct {
+            uint32_t bin[kBins];          // bin counts, then bin cursors
+            uint8_t binof[kTileRays];     // direction bin of each ray
+        } sort;                           // before the tile's rays are traced
+        struct {
+            unsigned long long best[kWave];  // each lane's ray: min of (t bits << 32 | triangle id << 1 | front)
+            uint32_t q[kQueueCap];           // queued triangle tests: leaf-order index << 6 | lane of the ray
+        } tq;                             // while they are traced (queued loop)
+    };
 };
 
 // Tiles of a scene: ceil(min(count, cap) / tile texels).
@@ -721,6 +747,7 @@ trace_persistent(TraceArgs A)
                     tbest = __builtin_inff();
                     ibest = -1;
                     front = false;
+                    if (LOOP == 4) T.tq.best[lane] = kBestInit;
                     leaf = kDone;
                     tri_cur = tri_end = 0;
                     sp = 0;
@@ -840,6 +867,91 @@ trace_persistent(TraceArgs A)
                     const uint64_t done = __ballot(!busy || (node == kDone && tri_cur >= tri_end));
                     if (__popcll(done) >= refill_at) break;
                 }
+            } else if (LOOP == 4) {
+                // Queued loop: a lane that reaches a leaf appends its triangles to the wavefront's queue
+                // in LDS (two per iteration at most) and goes on with its traversal; once a wavefront's
+                // worth of tests is queued, every lane takes one, whichever ray it belongs to, so the
+                // triangle code runs at full width instead of in nearly every iteration for a few lanes.
+                // Between flushes a lane culls boxes against its ray's best distance as of the last flush
+                // (a larger bound only enters more boxes); the closest hit is the minimum of the
+                // (t, triangle id, facing) keys of all tests, as in the other loops.
+                int qh = 0, qt = 0;  // wave-uniform head and tail (entries at index & (kQueueCap - 1))
+                const auto flush = [&](int nf) {
+                    const bool act = lane < nf;
+                    const uint32_t e = act ? T.tq.q[(qh + lane) & (kQueueCap - 1)] : (uint32_t)lane;
+                    const int owner = (int)(e & 63u), addr = owner << 2;
+                    // the owner's ray, from its registers (every lane takes part in the permutes)
+                    const float ox = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(Rs.ox)));
+                    const float oy = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(Rs.oy)));
+                    const float oz = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(Rs.oz)));
+                    const float dx = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(Rs.dx)));
+                    const float dy = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(Rs.dy)));
+                    const float dz = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(Rs.dz)));
+                    const float tb = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(tbest)));
+                    if (act) {
+                        if (STATS) ++st_tris;
+                        const int i = (int)(e >> 6);
+                        const float4 *mp = tri_ptr(S.tmap, i);
+                        float t;
+                        bool fr;
+                        if (tri_hit_rows(ox, oy, oz, dx, dy, dz, mp[0], mp[1], mp[2], S.tris, i, tb, t, fr)) {
+                            const unsigned long long key = ((unsigned long long)__float_as_uint(t) << 32) |
+                                                           ((uint32_t)tri_id(S.tris, i) << 1) | (fr ? 1u : 0u);
+                            atomicMin(&T.tq.best[owner], key);
+                        }
+                    }
+                    qh += nf;
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    tbest = __uint_as_float((uint32_t)(T.tq.best[lane] >> 32));
+                };
+                while (true) {
+                    if (STATS) {
+                        ++st_iters;
+                        st_busy += busy && (node != kDone || tri_cur < tri_end);
+                    }
+                    // ---- append up to two of the lane's pending triangles, as far as the queue has room
+                    const int c = busy ? min(tri_end - tri_cur, 2) : 0;
+                    const uint64_t b1 = __ballot(c >= 1), b2 = __ballot(c >= 2);
+                    const int pos = (int)(__builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0u)) +
+                                          __builtin_amdgcn_mbcnt_hi((uint32_t)(b2 >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)b2, 0u)));
+                    const int g = pos + c <= kQueueCap - (qt - qh) ? c : 0;  // granted lanes are a prefix
+                    if (g > 0) {
+                        T.tq.q[(qt + pos) & (kQueueCap - 1)] = ((uint32_t)tri_cur << 6) | (uint32_t)lane;
+                        if (g > 1) T.tq.q[(qt + pos + 1) & (kQueueCap - 1)] = ((uint32_t)(tri_cur + 1) << 6) | (uint32_t)lane;
+                        tri_cur += g;
+                    }
+                    qt += (int)(__popcll(__ballot(g >= 1)) + __popcll(__ballot(g >= 2)));
+                    // ---- the lane's traversal step: a node, or opening a popped leaf
+                    const bool idle = busy && tri_cur >= tri_end;
+                    const bool do_node = idle && node >= 0;
+                    const float4 *q = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(S.nodes) +
+                                                                       (uint32_t)(do_node ? node : 0) * 64u);
+                    const float4 w0 = q[0], w1 = q[1], w2 = q[2];
+                    const int2 w3 = *reinterpret_cast<const int2 *>(q + 3);
+                    bool push = false, pop = false;
+                    int push_val = 0;
+                    if (do_node) {
+                        if (STATS) ++st_nodes;
+                        const int4 m = make_int4(w3.x, w3.y, 0, 0);
+                        node_step_regs(Rs, w0, w1, w2, m, node, tbest, tri_cur, tri_end, push, push_val, pop);
+                        if (STATS) st_empty += pop && tri_cur >= tri_end;
+                    } else if (idle && node != kDone) {
+                        tri_cur = leaf_first(node);
+                        tri_end = tri_cur + leaf_count(node);
+                        pop = true;
+                    }
+                    if (push) stack_push<SL>(stride, sp, stk, spill, push_val);
+                    if (pop) node = stack_pop<SL>(stride, sp, stk, spill);
+                    // ---- a wavefront's worth of tests
+                    if (qt - qh >= kWave) flush(kWave);
+                    const uint64_t done = __ballot(!busy || (node == kDone && tri_cur >= tri_end));
+                    if (__popcll(done) >= refill_at) break;
+                }
+                // the rest of the queue (the finished rays' tests among them)
+                while (qt - qh > 0) flush(min(qt - qh, kWave));
             } else if (LOOP == 2) {
                 while (true) {
                     if (STATS) {
@@ -893,11 +1005,21 @@ trace_persistent(TraceArgs A)
             }
             if (busy && node == kDone && leaf == kDone && tri_cur >= tri_end) {
                 if (STATS) ++st_rays;
-                if (ibest >= 0) {
+                int id = -1;
+                if (LOOP == 4) {
+                    const unsigned long long kb = T.tq.best[lane];
+                    if (kb != kBestInit) {
+                        tbest = __uint_as_float((uint32_t)(kb >> 32));
+                        id = (int)((uint32_t)kb >> 1);
+                        front = (kb & 1u) != 0u;
+                    }
+                } else if (ibest >= 0) {
+                    id = tri_id(S.tris, ibest);
+                }
+                if (id >= 0) {
                     const float dist = tbest * Rs.len;
                     const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) |
-                                                   ((unsigned long long)r << 26) |
-                                                   (unsigned long long)tri_id(S.tris, ibest);
+                                                   ((unsigned long long)r << 26) | (unsigned long long)id;
                     atomicMin(&T.key[slot], key);
                     atomicAdd(&T.cnt[slot], front ? 1u : 0x10000u);
                 }
@@ -1083,7 +1205,7 @@ __global__ void __launch_bounds__(256) trace_backward_kernel(const float *__rest
 
 // ------------------------------------------------------------- launch ----
 
-static rtsdf_trace_tuning g_tuning = {16, 0, 0, 3, 1, 12, 64, 2};
+static rtsdf_trace_tuning g_tuning = {16, 0, 0, 4, 1, 12, 64, 2};
 constexpr int kMaxBlocksPerCu = 8;  // persistent workgroups per CU (direction buffers and spill area sized for this)
 constexpr int kMinShortStack = 12;  // smallest LDS stack part (spill area sized for this)
 constexpr int kMaxStackDepth = 64;  // deepest hierarchy the tracer takes
@@ -1092,7 +1214,7 @@ static bool tuning_ok(const rtsdf_trace_tuning &t)
 {
     if (t.refill != 8 && t.refill != 16) return false;
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > kMaxBlocksPerCu) return false;
-    if (t.stats < 0 || t.stats > 1 || t.loop < 0 || t.loop > 3) return false;
+    if (t.stats < 0 || t.stats > 1 || t.loop < 0 || t.loop > 4) return false;
     if (t.bin_directions < 0 || t.bin_directions > 1) return false;
     if (t.stack_lds != 12 && t.stack_lds != 16 && t.stack_lds != 24) return false;
     if (t.tile_texels != 16 && t.tile_texels != 32 && t.tile_texels != 64) return false;
@@ -1134,6 +1256,7 @@ static int launch_trace3(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStr
     case 0: return launch_trace4<SL, REFILL, 0, BATCHED>(A, T, s);
     case 1: return launch_trace4<SL, REFILL, 1, BATCHED>(A, T, s);
     case 2: return launch_trace4<SL, REFILL, 2, BATCHED>(A, T, s);
+    case 4: return launch_trace4<SL, REFILL, 4, BATCHED>(A, T, s);
     default: return launch_trace4<SL, REFILL, 3, BATCHED>(A, T, s);
     }
 }
@@ -1290,8 +1413,9 @@ extern "C" int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coars
     if (frame >= kMaxFrame && !frame_ptr) return RTSDF_EINVAL;
     const int sd = stack_depth_for(scene);
     if (sd > kMaxStackDepth) return RTSDF_EINVAL;
-    const rtsdf_trace_tuning &T = tuning_for(scene);
+    rtsdf_trace_tuning T = tuning_for(scene);
     if (scene->nt >= (1 << 26)) return RTSDF_EINVAL;  // triangle ids share a 64-bit key with the distance
+    if (T.loop == 4 && scene->nref >= kMaxQueuedRefs) T.loop = 3;  // queue entries hold 26-bit indices
     hipStream_t s = as_stream(stream);
     const int lognf = ilog2(fine.n), logr = ilog2(fine.n / coarse.n);
     const int64_t ntex = (int64_t)fine.n * fine.n * fine.n;
