@@ -233,7 +233,9 @@ int rtsdf_select_field(rtsdf_grid grid, const float *field, float d, uint8_t *ma
 /* Scene: the triangles and their bounding volume hierarchy, resident on    */
 /* the device.  create copies the mesh (device pointers) and builds the      */
 /* hierarchy (binned surface-area heuristic, two children per node); it      */
-/* synchronises `stream`.  refit takes new positions for the same topology   */
+/* synchronises `stream`.  EINVAL for 2^26 or more triangles or 2^24 or more */
+/* triangle references after large triangles are split.  refit takes new    */
+/* positions for the same topology                                           */
 /* and recomputes every box bottom-up on the device, asynchronously.         */
 /* ------------------------------------------------------------------------ */
 typedef struct rtsdf_scene rtsdf_scene;

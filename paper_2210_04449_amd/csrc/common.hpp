@@ -11,6 +11,10 @@
 namespace rtsdf {
 
 constexpr int kWave = 64;
+// triangle references of a scene (after splitting) at most: record offsets (48 B each) are formed with the
+// full-rate 24-bit multiply
+constexpr int kMaxRefs = 1 << 24;
+__device__ __forceinline__ uint32_t rec48(int i) { return __umul24((uint32_t)i, 48u); }
 
 // Per-device error word (bits RTSDF_ERR_*), set by kernels, read and cleared
 // by rtsdf_sync_status.

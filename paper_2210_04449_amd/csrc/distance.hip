@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(kDistBlock) point_distance_kernel(BvhView S, i
             const int first = leaf_first(node), cnt = leaf_count(node);
             for (int k = first; k < first + cnt; ++k) {
                 const float4 *tp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(S.tris) +
-                                                                    (uint32_t)k * 48u);
+                                                                    rec48(k));
                 const float4 A = tp[0], B = tp[1], Cv = tp[2];
                 const int id = __float_as_int(A.w);
                 const float d2 = point_tri_dist2(px, py, pz, A, B, Cv);

@@ -436,7 +436,7 @@ static int rtsdf_scene_create_instanced_impl(const float *vertices, int32_t nv, 
         inode.meta = make_int4(root, kInstTag, inst_parent[e], k + 1);
     }
     const int nref = (int)hlf.size();
-    if ((int64_t)nref >= ((int64_t)1 << 26) - 1) return RTSDF_EINVAL;
+    if (nref >= kMaxRefs) return RTSDF_EINVAL;
     std::vector<float> obox((size_t)6 * std::max(nent, 1));
     std::vector<int32_t> epart(std::max(nent, 1), 0);
     for (int e = 0; e < nent; ++e) {

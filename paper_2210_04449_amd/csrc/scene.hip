@@ -587,6 +587,7 @@ static int rtsdf_scene_create_impl(const float *vertices, int32_t nv, const int3
     std::vector<int32_t> ref_tri, ref_path;
     make_references(hv, hf, nt, B.tb, ref_tri, ref_path);
     const int nref = (int)ref_tri.size();
+    if (nref >= kMaxRefs) return RTSDF_EINVAL;
     B.cen.resize((size_t)3 * nref);
     B.idx.resize(nref);
     for (int r = 0; r < nref; ++r) {

@@ -200,7 +200,7 @@ __device__ __forceinline__ bool tri_hit_rows(float ox, float oy, float oz, float
     fr = qz < 0.0f;
     if (in_range && !(bmin > margin) && !(bmin < -margin)) {
         // near an edge or a vertex (or not a number): the watertight test decides
-        const float4 *tp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + (uint32_t)i * 48u);
+        const float4 *tp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + rec48(i));
         const float h = tri_watertight(ox, oy, oz, dx, dy, dz, tp);
         t = fabsf(h);
         fr = h > 0.0f;
@@ -216,8 +216,8 @@ __device__ __forceinline__ void tri_test_rows(const RaySetup &R, float4 r0, floa
     bool fr;
     if (!tri_hit_rows(R.ox, R.oy, R.oz, R.dx, R.dy, R.dz, r0, r1, r2, tris, i, tbest, t, fr)) return;
     if (t == tbest) {  // equal distances: the lower original triangle id wins
-        const float4 *tp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + (uint32_t)i * 48u);
-        const float4 *tb = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + (uint32_t)ibest * 48u);
+        const float4 *tp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + rec48(i));
+        const float4 *tb = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + rec48(ibest));
         if (!(__float_as_int(tp[0].w) < __float_as_int(tb[0].w))) return;
     }
     tbest = t;
@@ -229,14 +229,14 @@ __device__ __forceinline__ void tri_test(const RaySetup &R, const float4 *tmap, 
                                          float &tbest, int &ibest, bool &front)
 {
     // the whole record in one round trip, and no branch before the decision
-    const float4 *mp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tmap) + (uint32_t)i * 48u);
+    const float4 *mp = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tmap) + rec48(i));
     tri_test_rows(R, mp[0], mp[1], mp[2], tris, i, tbest, ibest, front);
 }
 
 // original id of the triangle at leaf-order index i
 __device__ __forceinline__ int tri_id(const float4 *tris, int i)
 {
-    return __float_as_int(reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + (uint32_t)i * 48u)->w);
+    return __float_as_int(reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + rec48(i))->w);
 }
 
 // slab test against a padded box: whether the ray meets it before tbest (a NaN slab misses), and the entry
@@ -359,14 +359,14 @@ __device__ __forceinline__ const BvhNode *node_ptr(const BvhNode *base, int node
 
 __device__ __forceinline__ const float4 *tri_ptr(const float4 *base, int tri)
 {
-    return reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + (uint32_t)tri * 48u);
+    return reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + rec48(tri));
 }
 
 template <int SL>
 __device__ __forceinline__ void stack_push(int stride, int &sp, lds_int *stk, int32_t *spill, int v)
 {
     if (sp < SL) stk[sp * kWave] = v;
-    else spill[(sp - SL) * stride] = v;
+    else spill[__umul24((uint32_t)(sp - SL), (uint32_t)stride)] = v;  // stride < 2^24 lanes
     ++sp;
 }
 
@@ -377,7 +377,7 @@ __device__ __forceinline__ int stack_pop(int stride, int &sp, const lds_int *stk
     --sp;
     int v;
     if (sp < SL) v = stk[sp * kWave];
-    else v = spill[(sp - SL) * stride];
+    else v = spill[__umul24((uint32_t)(sp - SL), (uint32_t)stride)];
     return v;
 }
 
@@ -497,13 +497,9 @@ __device__ __forceinline__ void node4_step_regs(const RaySetup &R, float4 a, flo
 // Same decisions as node_step, written as selects: the caller performs the
 // (at most one) push and the (at most one) pop after the lane's work of the
 // iteration, so every lane shares one copy of the stack code.
-__device__ __forceinline__ void node_step_regs(const RaySetup &R, float4 a, float4 b, float4 z, int4 m, int &node,
-                                               float tbest, int &tri_cur, int &tri_end, bool &push, int &push_val,
-                                               bool &pop)
+__device__ __forceinline__ void node_decide(bool h0, float t0, bool h1, float t1, int4 m, int &node, int &tri_cur,
+                                            int &tri_end, bool &push, int &push_val, bool &pop)
 {
-    float t0, t1;
-    const bool h0 = box_hit(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest, t0);
-    const bool h1 = box_hit(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest, t1);
     const bool any = h0 || h1, both = h0 && h1;
     const bool first0 = h0 && (!h1 || t0 <= t1);
     const int near = first0 ? m.x : m.y, far = first0 ? m.y : m.x;
@@ -517,6 +513,16 @@ __device__ __forceinline__ void node_step_regs(const RaySetup &R, float4 a, floa
     push_val = far;
     pop = !any || (near_leaf && !both);
     node = near_leaf ? far : near;
+}
+
+__device__ __forceinline__ void node_step_regs(const RaySetup &R, float4 a, float4 b, float4 z, int4 m, int &node,
+                                               float tbest, int &tri_cur, int &tri_end, bool &push, int &push_val,
+                                               bool &pop)
+{
+    float t0, t1;
+    const bool h0 = box_hit(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest, t0);
+    const bool h1 = box_hit(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest, t1);
+    node_decide(h0, t0, h1, t1, m, node, tri_cur, tri_end, push, push_val, pop);
 }
 
 __device__ __forceinline__ void node_step_flat(const BvhView &S, const RaySetup &R, int &node, float tbest,
@@ -723,7 +729,7 @@ trace_persistent(TraceArgs A)
         int tri_cur = 0, tri_end = 0;
         bool front = false;
         while (true) {
-            const uint64_t need = __ballot(!busy);
+            const uint64_t need = __builtin_amdgcn_ballot_w64(!busy);
             if (need != 0 && pool < nrays) {
                 if (STATS) ++st_refills;
                 const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
@@ -755,8 +761,8 @@ trace_persistent(TraceArgs A)
                 }
                 pool += take;
             }
-            if (__ballot(busy) == 0) break;
-            const int refill_at = pool < nrays ? REFILL : kWave;
+            if (__builtin_amdgcn_ballot_w64(busy) == 0) break;
+            const int refill_at = __builtin_amdgcn_readfirstlane(pool < nrays ? REFILL : kWave);
             if (LOOP == 0) {
                 while (true) {
                     if (busy && leaf == kDone && node < 0 && node != kDone) {
@@ -797,7 +803,7 @@ trace_persistent(TraceArgs A)
                     const bool do_node = busy && !do_tri && node >= 0;
                     // (lanes with neither load the root node, which every scene allocates, and ignore it)
                     const char *base =
-                        do_tri ? reinterpret_cast<const char *>(S.tmap) + (uint32_t)tri_cur * 48u
+                        do_tri ? reinterpret_cast<const char *>(S.tmap) + rec48(tri_cur)
                                : WIDE ? reinterpret_cast<const char *>(P.nodes4) + (uint32_t)(do_node ? node : 0) * 128u
                                       : reinterpret_cast<const char *>(S.nodes) + (uint32_t)(do_node ? node : 0) * 64u;
                     const float4 *q = reinterpret_cast<const float4 *>(base);
@@ -911,19 +917,27 @@ trace_persistent(TraceArgs A)
                         st_busy += busy && (node != kDone || tri_cur < tri_end);
                     }
                     // ---- append up to two of the lane's pending triangles, as far as the queue has room
-                    const int c = busy ? min(tri_end - tri_cur, 2) : 0;
-                    const uint64_t b1 = __ballot(c >= 1), b2 = __ballot(c >= 2);
-                    const int pos = (int)(__builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0u)) +
-                                          __builtin_amdgcn_mbcnt_hi((uint32_t)(b2 >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)b2, 0u)));
-                    const int g = pos + c <= kQueueCap - (qt - qh) ? c : 0;  // granted lanes are a prefix
+                    // (lanes without a ray hold an empty range)
+                    const int c = min(tri_end - tri_cur, 2);
+                    const uint64_t b1 = __builtin_amdgcn_ballot_w64(c >= 1), b2 = __builtin_amdgcn_ballot_w64(c >= 2);
+                    // the lane's position: the requests of the lanes below it
+                    const int pos = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(b2 >> 32),
+                        __builtin_amdgcn_mbcnt_lo(
+                            (uint32_t)b2, __builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0u))));
+                    int total = (int)(__popcll(b1) + __popcll(b2)), g = c;
+                    if (qt - qh + total > kQueueCap) {  // rare: grant a prefix of the lanes
+                        g = pos + c <= kQueueCap - (qt - qh) ? c : 0;
+                        total = (int)(__popcll(__builtin_amdgcn_ballot_w64(g >= 1)) + __popcll(__builtin_amdgcn_ballot_w64(g >= 2)));
+                    }
                     if (g > 0) {
-                        T.tq.q[(qt + pos) & (kQueueCap - 1)] = ((uint32_t)tri_cur << 6) | (uint32_t)lane;
-                        if (g > 1) T.tq.q[(qt + pos + 1) & (kQueueCap - 1)] = ((uint32_t)(tri_cur + 1) << 6) | (uint32_t)lane;
+                        const uint32_t e = ((uint32_t)tri_cur << 6) | (uint32_t)lane;
+                        T.tq.q[(qt + pos) & (kQueueCap - 1)] = e;
+                        if (g > 1) T.tq.q[(qt + pos + 1) & (kQueueCap - 1)] = e + 64u;
                         tri_cur += g;
                     }
-                    qt += (int)(__popcll(__ballot(g >= 1)) + __popcll(__ballot(g >= 2)));
+                    qt += total;
                     // ---- the lane's traversal step: a node, or opening a popped leaf
                     const bool idle = busy && tri_cur >= tri_end;
                     const bool do_node = idle && node >= 0;
@@ -947,7 +961,7 @@ trace_persistent(TraceArgs A)
                     if (pop) node = stack_pop<SL>(stride, sp, stk, spill);
                     // ---- a wavefront's worth of tests
                     if (qt - qh >= kWave) flush(kWave);
-                    const uint64_t done = __ballot(!busy || (node == kDone && tri_cur >= tri_end));
+                    const uint64_t done = __builtin_amdgcn_ballot_w64(!busy || (node == kDone && tri_cur >= tri_end));
                     if (__popcll(done) >= refill_at) break;
                 }
                 // the rest of the queue (the finished rays' tests among them)
