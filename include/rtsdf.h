@@ -156,6 +156,23 @@ int rtsdf_jfa(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, float beta,
 int rtsdf_jfa_steps(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, const int32_t *steps, int32_t nsteps,
                     float beta, int32_t *dist2, float *coarse_sdf, rtsdf_stream stream);
 
+/* How the step-2 and step-1 passes stage their (8 + 2k)^3 block in LDS, per
+ * grid size (the results are the same; only speed differs):
+ *   near_stage 0  automatic (the default): 2;
+ *              1  the seed alone (the candidate's distance key is formed
+ *                 from it: 4 B per entry, 4 integer instructions per
+ *                 candidate);
+ *              2  the pair (seed, |seed|^2 term) (8 B per entry, 2).
+ * rtsdf_jfa_config sets it for grids of side n (a power of two in [8, 256];
+ * EINVAL otherwise or for values outside the set); the setting is process
+ * state read at each rtsdf_jfa / rtsdf_jfa_steps call (calls that overlap
+ * with a change may see either).  rtsdf_jfa_config_get reads it back. */
+typedef struct rtsdf_jfa_tuning {
+    int32_t near_stage;
+} rtsdf_jfa_tuning;
+int rtsdf_jfa_config(int32_t n, const rtsdf_jfa_tuning *t);
+int rtsdf_jfa_config_get(int32_t n, rtsdf_jfa_tuning *t);
+
 /* ------------------------------------------------------------------------ */
 /* 3. Selection (Sec. 2.2; the case c <= d of Eq. (1)).                      */
 /*                                                                           */

@@ -17,6 +17,10 @@ batch) with HIP events and keeps the fastest.  The knobs:
   scenes that refit or stay static; batches and device-rebuilt or two-level
   scenes trace two-wide and skip this knob).
 
+For a Pipeline the jump flooding's near-pass staging (``rtsdf_jfa_config``:
+seeds alone or seed pairs in LDS) is timed too and the faster one kept for
+the pipeline's coarse grid size.
+
 The search is coordinate descent from the target's current tuning: each knob
 in turn takes each of its values with the others fixed, a change is kept when
 it is at least 0.5 % faster, and sweeps repeat until one changes nothing (or
@@ -186,7 +190,10 @@ def tune(target, reps: int = 2, space: dict = SPACE, cache: str | None = DEFAULT
     if not force and key in entries:
         best = entries[key]["tuning"]
         apply(best)
-        return {"tuning": best, "ms": entries[key]["ms"], "trials": [], "cached": True, "key": key}
+        if "jfa_near_stage" in entries[key]:
+            R.rtsdf_jfa_config(target.nc, entries[key]["jfa_near_stage"])
+        return {"tuning": best, "ms": entries[key]["ms"], "trials": [], "cached": True, "key": key,
+                "jfa": entries[key].get("jfa")}
 
     def measure(t):
         apply(t)
@@ -195,9 +202,30 @@ def tune(target, reps: int = 2, space: dict = SPACE, cache: str | None = DEFAULT
     start = {k: current.get(k, v[0]) for k, v in space.items()}
     best, ms, trials = search(measure, start, space, sweeps=sweeps, exhaustive=exhaustive)
     apply(best)
+    jfa = tune_jfa(target, reps=max(reps, 3)) if isinstance(target, Pipeline) else None
     target.reset()
     torch.cuda.synchronize()
     if cache:
         entries[key] = {"tuning": best, "ms": ms}
+        if jfa is not None:
+            entries[key].update(jfa_near_stage=jfa["near_stage"], jfa=jfa)
         save_cache(entries, cache)
-    return {"tuning": best, "ms": ms, "trials": trials, "cached": False, "key": key}
+    return {"tuning": best, "ms": ms, "trials": trials, "cached": False, "key": key, "jfa": jfa}
+
+
+def tune_jfa(p, reps: int = 3) -> dict:
+    """Time the jump flooding of pipeline `p` with each near-pass staging (rtsdf_jfa_config: seeds alone or seed
+    pairs; the results are the same) and keep the faster for grids of p's coarse size (process-wide setting).
+    Each timed run voxelizes first, the same work for both."""
+    n = p.nc
+    times = {}
+    for stage in (1, 2):
+        R.rtsdf_jfa_config(n, stage)
+
+        def run():
+            p.voxelize()
+            p.jfa()
+        times[stage] = _time(run, reps)
+    best = min(times, key=times.get)
+    R.rtsdf_jfa_config(n, best)
+    return {"near_stage": best, "ms": times}

@@ -124,7 +124,7 @@ __device__ __forceinline__ const FlatRange &flat_find(const FlatRange *__restric
 
 template <int KIND>
 __global__ void __launch_bounds__(KIND == kJfaNear2 || KIND == kJfaFinal ? 512 : 256)
-    jfa_batch(const JfaStep *__restrict__ plan, const FlatRange *__restrict__ ranges, int nr)
+    jfa_batch(const JfaStep *__restrict__ plan, const FlatRange *__restrict__ ranges, int nr, int neg2)
 {
     const FlatRange &fr = flat_find(ranges, nr, blockIdx.x);
     const JfaStep &st = plan[fr.scene];
@@ -134,11 +134,12 @@ __global__ void __launch_bounds__(KIND == kJfaNear2 || KIND == kJfaFinal ? 512 :
         const int64_t e = (int64_t)blk * blockDim.x + threadIdx.x;
         if (e < nvox) jfa_to_bricks_body(st.src, st.dst, st.n, st.logn, e);
     } else if (KIND == kJfaFarBricks || KIND == kJfaFarLinear) {
-        jfa_far_body<false, KIND == kJfaFarLinear>(st.src, st.dst, st.n, st.logn, st.kb, blk, nblk);
+        jfa_far_body<false, KIND == kJfaFarLinear>(st.src, st.dst, st.n, st.logn, st.kb, blk, nblk, neg2);
     } else if (KIND == kJfaNear2) {
-        jfa_near_body<2, false, false>(st.src, st.dst, st.n, st.logn, nullptr, nullptr, 0.f, 0.f, blk, nblk);
+        jfa_near_body<2, true, false>(st.src, st.dst, st.n, st.logn, nullptr, nullptr, 0.f, 0.f, blk, nblk, neg2);
     } else {
-        jfa_near_body<1, false, true>(st.src, st.dst, st.n, st.logn, st.dist2, st.sdf, st.h, st.beta, blk, nblk);
+        jfa_near_body<1, true, true>(st.src, st.dst, st.n, st.logn, st.dist2, st.sdf, st.h, st.beta, blk, nblk,
+                                     neg2);
     }
 }
 
@@ -488,19 +489,19 @@ extern "C" int rtsdf_batch_step(rtsdf_batch *B, uint32_t frame, const uint32_t *
         const FlatRange *r = B->ranges;
         if (L[kJfaConvert].blocks)
             jfa_batch<kJfaConvert><<<dim3(L[kJfaConvert].blocks), dim3(256), 0, s>>>(
-                plan, r + L[kJfaConvert].offset, L[kJfaConvert].count);
+                plan, r + L[kJfaConvert].offset, L[kJfaConvert].count, -2);
         if (L[kJfaFarLinear].blocks)
             jfa_batch<kJfaFarLinear><<<dim3(L[kJfaFarLinear].blocks), dim3(256), 0, s>>>(
-                plan, r + L[kJfaFarLinear].offset, L[kJfaFarLinear].count);
+                plan, r + L[kJfaFarLinear].offset, L[kJfaFarLinear].count, -2);
         if (L[kJfaFarBricks].blocks)
             jfa_batch<kJfaFarBricks><<<dim3(L[kJfaFarBricks].blocks), dim3(256), 0, s>>>(
-                plan, r + L[kJfaFarBricks].offset, L[kJfaFarBricks].count);
+                plan, r + L[kJfaFarBricks].offset, L[kJfaFarBricks].count, -2);
         if (L[kJfaNear2].blocks)
             jfa_batch<kJfaNear2><<<dim3(L[kJfaNear2].blocks), dim3(512), 0, s>>>(plan, r + L[kJfaNear2].offset,
-                                                                                  L[kJfaNear2].count);
+                                                                                  L[kJfaNear2].count, -2);
         if (L[kJfaFinal].blocks)
             jfa_batch<kJfaFinal><<<dim3(L[kJfaFinal].blocks), dim3(512), 0, s>>>(plan, r + L[kJfaFinal].offset,
-                                                                                  L[kJfaFinal].count);
+                                                                                  L[kJfaFinal].count, -2);
         RTSDF_CHECK_LAUNCH();
     }
     // selection

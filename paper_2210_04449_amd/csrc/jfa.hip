@@ -13,18 +13,21 @@
 // x | y << 8 | z << 16 (0xFFFFFFFF = none); packed order equals linear-index
 // order, so ties compare the packed word directly.
 //
-// Candidate key: the 64-bit word (D^2 << 32 | low), read as a float64, where
-// low increases with the packed seed.  Its exponent field is zero (D^2 <
-// 2^20), so it is a non-negative denormal whose order is the integer order,
-// and one v_min_f64 keeps the better of two keys.  A missing seed gets bits
-// 0x7F000000 in the high word (a large finite double) and always loses.  D^2
-// itself is formed with byte/short dot products: for n <= 128 the voxel
-// constant C holds 128 - x, 128 - y, 128 - z in its bytes, so u = S + C holds
-// (s - x) + 128 etc. in [1, 255] per byte without carries: u is the key's low
-// word (S = u - C), u ^ 0x808080 the signed byte differences, and one
-// v_dot4_i32_i8 squares and sums them; for n = 256 the low word is the seed
-// itself, x and y go through packed 16-bit lanes and v_dot2_i32_i16, z
-// separately.
+// Candidate key: the 64-bit word (hi << 32 | low), read as a float64, where hi
+// orders the candidates by D^2 and low increases with the packed seed.  Its
+// exponent field is zero (hi < 2^20), so it is a non-negative denormal whose
+// order is the integer order, and one v_min_f64 keeps the better of two keys.
+// A missing seed gets bits 0x7F000000 in the high word (a large finite
+// double) and always loses.  Two key forms, both from byte dot products:
+// * 7-bit (far passes, n <= 128): hi = D^2.  The voxel constant C holds
+//   128 - x, 128 - y, 128 - z in its bytes, so u = S + C holds (s - x) + 128
+//   etc. in [1, 255] per byte without carries: u is the key's low word
+//   (S = u - C), u ^ 0x808080 the signed byte differences, and one
+//   v_dot4_i32_i8 squares and sums them.
+// * byte-dot (every pass at n = 256, the near passes at every n): hi =
+//   |S|^2 - 2 S.p + 2^18 = D^2 - |p|^2 + 2^18 for the voxel p, low = S: two
+//   v_dot4_u32_u8 and one 24-bit multiply-add, or, with w(S) = |S|^2 staged
+//   beside each seed, one of each.
 //
 // Steps k >= 4 read whole neighbour bricks straight from global memory (an
 // axis offset that would leave the grid reads the brick with offset 0 on that
@@ -32,6 +35,8 @@
 // plus halo) in LDS; candidates then sit at compile-time LDS offsets and
 // out-of-grid halo entries are empty.  The k = 1 pass writes the final seeds,
 // D^2 and c in the caller's linear layout.
+#include <atomic>
+
 #include "common.hpp"
 
 namespace rtsdf {
@@ -40,65 +45,65 @@ constexpr uint32_t kNoSeed = 0xFFFFFFFFu;
 
 typedef short jfa_short2 __attribute__((ext_vector_type(2)));
 
-// Voxel-side constant for the distance: 7-bit path: C = (128 - x) | (128 - y)
-// << 8 | (128 - z) << 16; 8-bit path: x | y << 16 (low word) and z (high word).
+// Voxel-side constants.  a: the 7-bit key's C = (128 - x) | (128 - y) << 8 | (128 - z) << 16 (n <= 128);
+// p = x | y << 8 | z << 16 and pp = |p|^2 for the byte-dot key; neg2 = -2, a kernel argument (a constant
+// multiplier would be strength-reduced to a shift and a subtraction instead of one 24-bit multiply-add).
 struct JfaPos {
-    uint32_t a, b;
+    uint32_t a, p;
+    int32_t pp, neg2;
 };
 
-template <bool WIDE>
-__device__ __forceinline__ JfaPos jfa_pos(int x, int y, int z)
+__device__ __forceinline__ JfaPos jfa_pos(int x, int y, int z, int neg2)
 {
-    JfaPos p;
-    if (!WIDE) {
-        p.a = (uint32_t)(128 - x) | ((uint32_t)(128 - y) << 8) | ((uint32_t)(128 - z) << 16);
-        p.b = 0;
-    } else {
-        p.a = (uint32_t)x | ((uint32_t)y << 16);
-        p.b = (uint32_t)z;
-    }
-    return p;
+    JfaPos P;
+    P.a = (uint32_t)(128 - x) | ((uint32_t)(128 - y) << 8) | ((uint32_t)(128 - z) << 16);
+    P.p = (uint32_t)x | ((uint32_t)y << 8) | ((uint32_t)z << 16);
+    P.pp = x * x + y * y + z * z;
+    P.neg2 = neg2;
+    return P;
 }
 
-template <bool WIDE>
-__device__ __forceinline__ double jfa_key(JfaPos p, uint32_t s)
+// 7-bit key (n <= 128): high word D^2 from the signed byte differences, low word u = S + C.
+__device__ __forceinline__ double jfa_key7(JfaPos P, uint32_t s)
 {
-    uint32_t low = s, hi;
-    if (!WIDE) {
-        low = s + p.a;
-        const int d = (int)(low ^ 0x00808080u);
-        // the missing-seed bits have zero low 24 bits and D^2 < 2^24, so adding them is or-ing them
-        hi = (uint32_t)__builtin_amdgcn_sdot4(d, d, (int)(s & 0x7F000000u), false);
-    } else {
-        const jfa_short2 sxy = __builtin_bit_cast(jfa_short2, __builtin_amdgcn_perm(0u, s, 0x0C010C00u));
-        const jfa_short2 dxy = __builtin_bit_cast(jfa_short2, p.a) - sxy;
-        const int dz = (int)p.b - (int)((s >> 16) & 0xFFu);
-        // |dz| < 2^8: a 24-bit multiply-add (full rate, unlike the 32-bit multiply) into the accumulator
-        hi = (uint32_t)__builtin_amdgcn_sdot2(dxy, dxy, (int)(s & 0x7F000000u) + __mul24(dz, dz), false);
-    }
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)low);
-}
-
-// The same key for n <= 128 from a staged pair (s, s & 0x7F000000): the missing-seed bits are computed once per
-// staged value instead of once per candidate.
-__device__ __forceinline__ double jfa_key_pair(JfaPos p, uint2 e)
-{
-    const uint32_t low = e.x + p.a;
+    const uint32_t low = s + P.a;
     const int d = (int)(low ^ 0x00808080u);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_sdot4(d, d, (int)e.y, false);
+    // the missing-seed bits have zero low 24 bits and D^2 < 2^24, so adding them is or-ing them
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_sdot4(d, d, (int)(s & 0x7F000000u), false);
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)low);
 }
 
-__device__ __forceinline__ uint32_t key_d2(double k) { return (uint32_t)(__builtin_bit_cast(uint64_t, k) >> 32); }
-
-// the packed seed of the best key (kNoSeed if no candidate had one)
-template <bool WIDE>
-__device__ __forceinline__ uint32_t key_seed(JfaPos p, double k)
+// Byte-dot key (n <= 256): high word |S|^2 - 2 S.p + 2^18 = D^2 - |p|^2 + 2^18 (in [2^18 - 3 * 255^2,
+// 2^18 + 3 * 255^2], the same order as D^2 for one voxel) plus the missing-seed bits, low word the seed.  w(S)
+// = |S|^2 + missing bits depends on the seed alone, so staged seeds carry it; the 2^18 enters as -2^17 in
+// the accumulator of S.p (S.p - 2^17 in [-2^17, 2^16): a 24-bit operand of the multiply-add by -2).
+__device__ __forceinline__ uint32_t jfa_w(uint32_t s)
 {
-    if (key_d2(k) >= 0x7F000000u) return kNoSeed;
-    const uint32_t low = (uint32_t)__builtin_bit_cast(uint64_t, k);
-    return WIDE ? low : low - p.a;
+    return __builtin_amdgcn_udot4(s, s, s & 0x7F000000u, false);
 }
+
+__device__ __forceinline__ double jfa_keyd_w(JfaPos P, uint32_t s, uint32_t w)
+{
+    const int sp = (int)__builtin_amdgcn_udot4(s, P.p, 0xFFFE0000u, false);  // S.p - 2^17 (wraps)
+    const uint32_t hi = (uint32_t)(__mul24(sp, P.neg2) + (int)w);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)s);
+}
+
+__device__ __forceinline__ double jfa_keyd(JfaPos P, uint32_t s) { return jfa_keyd_w(P, s, jfa_w(s)); }
+
+__device__ __forceinline__ uint32_t key_hi(double k) { return (uint32_t)(__builtin_bit_cast(uint64_t, k) >> 32); }
+
+// the packed seed of the best key (kNoSeed if no candidate had one); BYTEDOT: which key formula made it
+template <bool BYTEDOT>
+__device__ __forceinline__ uint32_t key_seed(JfaPos P, double k)
+{
+    if (key_hi(k) >= 0x7F000000u) return kNoSeed;
+    const uint32_t low = (uint32_t)__builtin_bit_cast(uint64_t, k);
+    return BYTEDOT ? low : low - P.a;
+}
+
+// D^2 of a byte-dot key with a seed
+__device__ __forceinline__ uint32_t keyd_d2(JfaPos P, double k) { return key_hi(k) - 0x40000u + (uint32_t)P.pp; }
 
 __device__ __forceinline__ uint32_t pack_linear(int32_t s, int logn)
 {
@@ -161,13 +166,13 @@ __device__ __forceinline__ void jfa_axis(int c, int kb, int st, int (&d)[N])
 // The candidates of brick b: NX * NY * NZ distinct neighbour bricks, every read in the grid.
 template <bool WIDE, bool LINEAR_IN, int NX, int NY, int NZ>
 __device__ __forceinline__ void jfa_far_brick(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
-                                              int logn, int kb, int b, int lane)
+                                              int logn, int kb, int b, int lane, int neg2)
 {
     constexpr int NCAND = NX * NY * NZ;
     const int logB = logn - 2, B = 1 << logB;
     const int bx = b & (B - 1), by = (b >> logB) & (B - 1), bz = b >> (2 * logB);
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
-    const JfaPos P = jfa_pos<WIDE>(bx * 4 + lx, by * 4 + ly, bz * 4 + lz);
+    const JfaPos P = jfa_pos(bx * 4 + lx, by * 4 + ly, bz * 4 + lz, neg2);
     double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
     uint32_t cand[NCAND];
     if (!LINEAR_IN) {
@@ -197,7 +202,7 @@ __device__ __forceinline__ void jfa_far_brick(const int32_t *__restrict__ src, i
         }
     }
 #pragma unroll
-    for (int o = 0; o < NCAND; ++o) best = __builtin_fmin(best, jfa_key<WIDE>(P, cand[o]));
+    for (int o = 0; o < NCAND; ++o) best = __builtin_fmin(best, WIDE ? jfa_keyd(P, cand[o]) : jfa_key7(P, cand[o]));
     dst[(int64_t)b * 64 + lane] = (int32_t)key_seed<WIDE>(P, best);
 }
 
@@ -208,7 +213,7 @@ __device__ __forceinline__ void jfa_far_brick(const int32_t *__restrict__ src, i
 // branch, so every body keeps all its reads in flight together.
 template <bool WIDE, bool LINEAR_IN>
 __device__ __forceinline__ void jfa_far_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
-                                             int logn, int kb, uint32_t blk, uint32_t nblk)
+                                             int logn, int kb, uint32_t blk, uint32_t nblk, int neg2)
 {
     const int logB = logn - 2, B = 1 << logB;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -217,34 +222,34 @@ __device__ __forceinline__ void jfa_far_body(const int32_t *__restrict__ src, in
     const int bx = b & (B - 1), by = (b >> logB) & (B - 1), bz = b >> (2 * logB);
     const auto two = [&](int c) { return c < kb || c + kb >= B; };  // one side leaves the grid
     switch ((two(bx) ? 1 : 0) | (two(by) ? 2 : 0) | (two(bz) ? 4 : 0)) {
-    case 0: jfa_far_brick<WIDE, LINEAR_IN, 3, 3, 3>(src, dst, n, logn, kb, b, lane); break;
-    case 1: jfa_far_brick<WIDE, LINEAR_IN, 2, 3, 3>(src, dst, n, logn, kb, b, lane); break;
-    case 2: jfa_far_brick<WIDE, LINEAR_IN, 3, 2, 3>(src, dst, n, logn, kb, b, lane); break;
-    case 3: jfa_far_brick<WIDE, LINEAR_IN, 2, 2, 3>(src, dst, n, logn, kb, b, lane); break;
-    case 4: jfa_far_brick<WIDE, LINEAR_IN, 3, 3, 2>(src, dst, n, logn, kb, b, lane); break;
-    case 5: jfa_far_brick<WIDE, LINEAR_IN, 2, 3, 2>(src, dst, n, logn, kb, b, lane); break;
-    case 6: jfa_far_brick<WIDE, LINEAR_IN, 3, 2, 2>(src, dst, n, logn, kb, b, lane); break;
-    default: jfa_far_brick<WIDE, LINEAR_IN, 2, 2, 2>(src, dst, n, logn, kb, b, lane); break;
+    case 0: jfa_far_brick<WIDE, LINEAR_IN, 3, 3, 3>(src, dst, n, logn, kb, b, lane, neg2); break;
+    case 1: jfa_far_brick<WIDE, LINEAR_IN, 2, 3, 3>(src, dst, n, logn, kb, b, lane, neg2); break;
+    case 2: jfa_far_brick<WIDE, LINEAR_IN, 3, 2, 3>(src, dst, n, logn, kb, b, lane, neg2); break;
+    case 3: jfa_far_brick<WIDE, LINEAR_IN, 2, 2, 3>(src, dst, n, logn, kb, b, lane, neg2); break;
+    case 4: jfa_far_brick<WIDE, LINEAR_IN, 3, 3, 2>(src, dst, n, logn, kb, b, lane, neg2); break;
+    case 5: jfa_far_brick<WIDE, LINEAR_IN, 2, 3, 2>(src, dst, n, logn, kb, b, lane, neg2); break;
+    case 6: jfa_far_brick<WIDE, LINEAR_IN, 3, 2, 2>(src, dst, n, logn, kb, b, lane, neg2); break;
+    default: jfa_far_brick<WIDE, LINEAR_IN, 2, 2, 2>(src, dst, n, logn, kb, b, lane, neg2); break;
     }
 }
 
 template <bool WIDE, bool LINEAR_IN>
 __global__ void __launch_bounds__(256) jfa_far(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
-                                               int logn, int kb)
+                                               int logn, int kb, int neg2)
 {
-    jfa_far_body<WIDE, LINEAR_IN>(src, dst, n, logn, kb, blockIdx.x, gridDim.x);
+    jfa_far_body<WIDE, LINEAR_IN>(src, dst, n, logn, kb, blockIdx.x, gridDim.x, neg2);
 }
 
 // One pass with step K in {1, 2}: eight bricks (an 8^3 block) per workgroup,
 // staged with a K-voxel halo in LDS.  FINAL writes the caller's outputs.
-template <int K, bool WIDE, bool FINAL>
+template <int K, bool PAIRS, bool FINAL>
 __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
                                               int logn, int32_t *__restrict__ dist2, float *__restrict__ sdf, float h,
-                                              float beta, uint32_t blk_id, uint32_t nblk)
+                                              float beta, uint32_t blk_id, uint32_t nblk, int neg2)
 {
     constexpr int T = 8 + 2 * K;
-    // n <= 128: each entry staged as the pair (s, s & 0x7F000000); n = 256: the seed alone
-    __shared__ uint32_t tile[(WIDE ? 1 : 2) * T * T * T];
+    // PAIRS: each entry staged as the pair (s, w(s)); else the seed alone (w formed per candidate)
+    __shared__ uint32_t tile[(PAIRS ? 2 : 1) * T * T * T];
     uint2 *tile2 = reinterpret_cast<uint2 *>(tile);
     // n is a power of two: block and brick coordinates are bit fields (shifts and masks, no divisions)
     const int logB = logn - 2, logTB = logn - 3, TB = 1 << logTB;  // 8^3 blocks per axis
@@ -257,35 +262,35 @@ __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, i
             const int b = (x >> 2) | ((y >> 2) << logB) | ((z >> 2) << (2 * logB));
             v = (uint32_t)src[(b << 6) | (x & 3) | ((y & 3) << 2) | ((z & 3) << 4)];
         }
-        if (WIDE) tile[i] = v;
-        else tile2[i] = make_uint2(v, v & 0x7F000000u);
+        if (PAIRS) tile2[i] = make_uint2(v, jfa_w(v));
+        else tile[i] = v;
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lx = (wave & 1) * 4 + (lane & 3), ly = ((wave >> 1) & 1) * 4 + ((lane >> 2) & 3),
               lz = (wave >> 2) * 4 + (lane >> 4);
     const int x = tx0 + lx, y = ty0 + ly, z = tz0 + lz;
-    const JfaPos P = jfa_pos<WIDE>(x, y, z);
+    const JfaPos P = jfa_pos(x, y, z, neg2);
     const int c = (lx + K) + T * ((ly + K) + T * (lz + K));
     double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
         const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
         const int e = c + K * (ox + T * (oy + T * oz));
-        best = __builtin_fmin(best, WIDE ? jfa_key<WIDE>(P, tile[e]) : jfa_key_pair(P, tile2[e]));
+        best = __builtin_fmin(best, PAIRS ? jfa_keyd_w(P, tile2[e].x, tile2[e].y) : jfa_keyd(P, tile[e]));
     }
     if (!FINAL) {
         const int b = (x >> 2) | ((y >> 2) << logB) | ((z >> 2) << (2 * logB));
-        dst[(b << 6) | (x & 3) | ((y & 3) << 2) | ((z & 3) << 4)] = (int32_t)key_seed<WIDE>(P, best);
+        dst[(b << 6) | (x & 3) | ((y & 3) << 2) | ((z & 3) << 4)] = (int32_t)key_seed<true>(P, best);
     } else {
-        const uint32_t s = key_seed<WIDE>(P, best);
+        const uint32_t s = key_seed<true>(P, best);
         const int idx = x | (y << logn) | (z << (2 * logn));  // n <= 256: below 2^24
         if (s == kNoSeed) {
             dst[idx] = -1;
             dist2[idx] = INT32_MAX;
             sdf[idx] = __builtin_inff();
         } else {
-            const int d2 = (int)key_d2(best);
+            const int d2 = (int)keyd_d2(P, best);
             dst[idx] = unpack_linear(s, logn);
             dist2[idx] = d2;
             sdf[idx] = rn_sub(rn_mul(h, rn_sqrt((float)d2)), beta);
@@ -293,15 +298,15 @@ __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, i
     }
 }
 
-template <int K, bool WIDE, bool FINAL>
+template <int K, bool PAIRS, bool FINAL>
 __global__ void __launch_bounds__(512) jfa_near(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
                                                 int logn, int32_t *__restrict__ dist2, float *__restrict__ sdf,
-                                                float h, float beta)
+                                                float h, float beta, int neg2)
 {
-    jfa_near_body<K, WIDE, FINAL>(src, dst, n, logn, dist2, sdf, h, beta, blockIdx.x, gridDim.x);
+    jfa_near_body<K, PAIRS, FINAL>(src, dst, n, logn, dist2, sdf, h, beta, blockIdx.x, gridDim.x, neg2);
 }
 
-template <bool WIDE>
+template <bool WIDE, bool PAIRS>
 static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float beta, int32_t *dist2, float *sdf,
                    const int32_t *steps, int m, hipStream_t s)
 {
@@ -323,15 +328,15 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
             int32_t *dst = (npass - 1 - i) % 2 == 0 ? scratch : dist2;
             if (k >= 4) {
                 if (i == 0)
-                    jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
+                    jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
                 else
-                    jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
+                    jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
             } else if (k == 2) {
-                jfa_near<2, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
-                                                                                 0.f, 0.f);
+                jfa_near<2, PAIRS, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
+                                                                                 0.f, 0.f, -2);
             } else {
-                jfa_near<1, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
-                                                                                 0.f, 0.f);
+                jfa_near<1, PAIRS, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
+                                                                                 0.f, 0.f, -2);
             }
             RTSDF_CHECK_LAUNCH();
             cur = dst;
@@ -351,13 +356,13 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
             const int k = steps[i];
             int32_t *dst = bufs[next];
             if (k >= 4) {
-                jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4);
+                jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
             } else if (k == 2) {
-                jfa_near<2, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
-                                                                                 0.f, 0.f);
+                jfa_near<2, PAIRS, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
+                                                                                 0.f, 0.f, -2);
             } else {
-                jfa_near<1, WIDE, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
-                                                                                 0.f, 0.f);
+                jfa_near<1, PAIRS, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
+                                                                                 0.f, 0.f, -2);
             }
             RTSDF_CHECK_LAUNCH();
             cur = dst;
@@ -365,12 +370,30 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
         }
     }
     // cur == scratch here by construction
-    jfa_near<1, WIDE, true><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, seeds, n, logn, dist2, sdf, g.h, beta);
+    jfa_near<1, PAIRS, true><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, seeds, n, logn, dist2, sdf, g.h, beta,
+                                                                      -2);
     RTSDF_CHECK_LAUNCH();
     return RTSDF_OK;
 }
 
 }  // namespace rtsdf
+
+// near-pass staging per grid size (index log2 n - 3: n = 8 .. 256)
+static std::atomic<int> g_near_stage[6];
+
+extern "C" int rtsdf_jfa_config(int32_t n, const rtsdf_jfa_tuning *t)
+{
+    if (!t || n < 8 || n > 256 || !rtsdf::is_pow2(n) || t->near_stage < 0 || t->near_stage > 2) return RTSDF_EINVAL;
+    g_near_stage[rtsdf::ilog2(n) - 3].store(t->near_stage);
+    return RTSDF_OK;
+}
+
+extern "C" int rtsdf_jfa_config_get(int32_t n, rtsdf_jfa_tuning *t)
+{
+    if (!t || n < 8 || n > 256 || !rtsdf::is_pow2(n)) return RTSDF_EINVAL;
+    t->near_stage = g_near_stage[rtsdf::ilog2(n) - 3].load();
+    return RTSDF_OK;
+}
 
 extern "C" int rtsdf_jfa_steps(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, const int32_t *steps,
                                int32_t nsteps, float beta, int32_t *dist2, float *coarse_sdf, rtsdf_stream stream)
@@ -384,8 +407,13 @@ extern "C" int rtsdf_jfa_steps(rtsdf_grid coarse, int32_t *seeds, int32_t *scrat
     for (int i = 0; i < nsteps; ++i)
         if (steps[i] < 1 || steps[i] > coarse.n / 2 || !is_pow2(steps[i])) return RTSDF_EINVAL;
     hipStream_t s = as_stream(stream);
-    if (coarse.n <= 128) return jfa_run<false>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, s);
-    return jfa_run<true>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, s);
+    const int stage = g_near_stage[ilog2(coarse.n) - 3].load();
+    const bool pairs = stage != 1;
+    if (coarse.n <= 128)
+        return pairs ? jfa_run<false, true>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, s)
+                     : jfa_run<false, false>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, s);
+    return pairs ? jfa_run<true, true>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, s)
+                 : jfa_run<true, false>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, s);
 }
 
 extern "C" int rtsdf_jfa(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, float beta, int32_t *dist2,

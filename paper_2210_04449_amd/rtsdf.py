@@ -74,6 +74,10 @@ class TraceTuning(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class JfaTuning(C.Structure):
+    _fields_ = [("near_stage", _i32)]
+
+
 class SceneInfo(C.Structure):
     _fields_ = [("nv", _i32), ("nt", _i32), ("nodes", _i32), ("max_depth", _i32), ("leaf_size", _i32),
                 ("device_bytes", C.c_int64), ("references", _i32), ("instances", _i32)]
@@ -118,6 +122,8 @@ def _load():
                                     Accum, _P, _P, _P], _i32),
         "rtsdf_trace_config": ([C.POINTER(TraceTuning)], _i32),
         "rtsdf_trace_config_get": ([C.POINTER(TraceTuning)], _i32),
+        "rtsdf_jfa_config": ([_i32, C.POINTER(JfaTuning)], _i32),
+        "rtsdf_jfa_config_get": ([_i32, C.POINTER(JfaTuning)], _i32),
         "rtsdf_scene_set_tuning": ([_P, C.POINTER(TraceTuning)], _i32),
         "rtsdf_scene_get_tuning": ([_P, C.POINTER(TraceTuning)], _i32),
         "rtsdf_batch_set_tuning": ([_P, C.POINTER(TraceTuning)], _i32),
@@ -414,6 +420,20 @@ def rtsdf_trace_config(**kw) -> TraceTuning:
     old = rtsdf_trace_config_get()
     t = TraceTuning(**{**old.as_dict(), **kw})
     _check("rtsdf_trace_config", _lib.rtsdf_trace_config(C.byref(t)))
+    return old
+
+
+def rtsdf_jfa_config_get(n: int) -> int:
+    """The near-pass staging used for grids of side n (0 automatic, 1 seeds, 2 seed pairs)."""
+    t = JfaTuning()
+    _check("rtsdf_jfa_config_get", _lib.rtsdf_jfa_config_get(int(n), C.byref(t)))
+    return t.near_stage
+
+
+def rtsdf_jfa_config(n: int, near_stage: int) -> int:
+    """Set the near-pass staging for grids of side n; returns the previous setting."""
+    old = rtsdf_jfa_config_get(n)
+    _check("rtsdf_jfa_config", _lib.rtsdf_jfa_config(int(n), C.byref(JfaTuning(int(near_stage)))))
     return old
 
 

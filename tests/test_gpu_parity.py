@@ -109,6 +109,26 @@ def test_jfa_bit_exact(R, case, n):
     assert np.array_equal(c.view(np.int32), want_c.view(np.int32))
 
 
+@pytest.mark.parametrize("stage", [1, 2])
+@pytest.mark.parametrize("case,n", [("tiny", 8), ("tiny", 32), ("room", 128), ("room", 256)])
+def test_jfa_near_stagings_bit_exact(R, case, n, stage):
+    """Both stagings of the step-2 and step-1 passes (seeds alone, or seed pairs) give the oracle's seeds, D^2
+    and coarse SDF."""
+    say("jfa near staging", stage, case, n)
+    mesh = {"tiny": tiny_scene, "room": lambda: room_scene(1)}[case]()
+    old = R.rtsdf_jfa_config(n, stage)
+    try:
+        s0, s, d2, c = gpu_coarse(R, mesh, n)
+    finally:
+        R.rtsdf_jfa_config(n, old)
+    want_s = oracle.jfa(n, s0)
+    beta = np.float32(0.5) * np.float32(1.0 / n)
+    want_d2, want_c = oracle.coarse(n, want_s, np.float32(1.0 / n), beta)
+    assert np.array_equal(s, want_s), int((s != want_s).sum())
+    assert np.array_equal(d2, want_d2)
+    assert np.array_equal(c.view(np.int32), want_c.view(np.int32))
+
+
 @pytest.mark.parametrize("variant", ["jfa+1", "jfa+2", "1+jfa"])
 @pytest.mark.parametrize("case,n", [("tiny", 8), ("tiny", 16), ("tiny", 32), ("soup", 64), ("room", 128),
                                     ("room", 256)])
