@@ -181,31 +181,56 @@ __global__ void __launch_bounds__(kSortThreads) rsort_count(const uint32_t *__re
     hist[d * ntiles + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
-// exclusive prefix of hist[0 .. total) in place (one workgroup of 1024 lanes)
+// exclusive prefix of hist[0 .. total) in place (one workgroup of 1024 lanes): rounds of 4096 consecutive
+// counts, four per lane (one 16-byte load and store), lane sums scanned within each wavefront by shuffles and
+// across the 16 wavefronts through LDS; the running total of earlier rounds is carried along
 __global__ void __launch_bounds__(1024) rsort_scan(uint32_t *__restrict__ hist, int total)
 {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int per = (total + 1023) / 1024;
-    const int b0 = t * per;
-    uint32_t local = 0;
-    for (int i = 0; i < per; ++i)
-        if (b0 + i < total) local += hist[b0 + i];
-    part[t] = local;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
-        const uint32_t v = t >= off ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[t] - local;
-    for (int i = 0; i < per; ++i) {
-        if (b0 + i < total) {
-            const uint32_t v = hist[b0 + i];
-            hist[b0 + i] = run;
-            run += v;
+    __shared__ uint32_t wsum[1024 / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), wave = t >> 6;
+    uint32_t carry = 0;
+    for (int base = 0; base < total; base += 4 * 1024) {
+        const int i0 = base + 4 * t;
+        uint32_t v[4] = {0u, 0u, 0u, 0u};
+        if (i0 + 3 < total) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(hist + i0);
+            v[0] = q.x;
+            v[1] = q.y;
+            v[2] = q.z;
+            v[3] = q.w;
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (i0 + k < total) v[k] = hist[i0 + k];
         }
+        const uint32_t s = v[0] + v[1] + v[2] + v[3];
+        uint32_t x = s;  // inclusive scan of the lane sums within the wavefront
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == kWave - 1) wsum[wave] = x;
+        __syncthreads();
+        uint32_t before = 0, round = 0;
+        for (int k = 0; k < 1024 / kWave; ++k) {
+            const uint32_t w = wsum[k];
+            before += k < wave ? w : 0u;
+            round += w;
+        }
+        uint32_t e = carry + before + x - s;  // exclusive prefix of the lane's first count
+        uint32_t o[4];
+        for (int k = 0; k < 4; ++k) {
+            o[k] = e;
+            e += v[k];
+        }
+        if (i0 + 3 < total) {
+            *reinterpret_cast<uint4 *>(hist + i0) = make_uint4(o[0], o[1], o[2], o[3]);
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (i0 + k < total) hist[i0 + k] = o[k];
+        }
+        carry += round;
+        __syncthreads();  // wsum is rewritten next round
     }
 }
 
@@ -641,7 +666,9 @@ extern "C" int rtsdf_sort_pairs(uint32_t *keys, int32_t *values, int32_t n, int3
     char *w = static_cast<char *>(workspace);
     uint32_t *k1 = reinterpret_cast<uint32_t *>(w);
     int32_t *v1 = reinterpret_cast<int32_t *>(w + (size_t)n * sizeof(uint32_t));
-    uint32_t *hist = reinterpret_cast<uint32_t *>(w + (size_t)n * 8);
+    // the scan moves 16-byte groups of counts: align them (the size has 256 bytes of slack)
+    uint32_t *hist = reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(w + (size_t)n * 8) + 15) &
+                                                  ~(uintptr_t)15);
     uint32_t *ok_ = nullptr;
     int32_t *ov_ = nullptr;
     const int rc = rsort_run(keys, values, k1, v1, hist, n, bits, false, &ok_, &ov_, s);

@@ -4,6 +4,9 @@
     python -m paper_2210_04449_amd.prof_summary pmc <counter_collection.csv> [...]
     python -m paper_2210_04449_amd.prof_summary hash
 
+Only this library's kernels (and the calibration copy) are listed unless
+``--all`` is given.
+
 The PMC summary reports counter values per dispatch for each kernel.  HBM
 bytes come from FETCH_SIZE and WRITE_SIZE (KiB per dispatch); each is scaled
 by what the same counter reads for the device-to-device copy of a known size
@@ -55,8 +58,13 @@ def traffic_from_summary(path: str, kernel_prefix: str) -> dict | None:
     return None
 
 
-def stats(path: str) -> str:
-    rows = list(csv.DictReader(open(path)))
+def ours(name: str) -> bool:
+    """Kernels of this library, and the device-to-device copy the counters are calibrated with."""
+    return "rtsdf::" in name or "copyBuffer" in name
+
+
+def stats(path: str, keep=ours) -> str:
+    rows = [r for r in csv.DictReader(open(path)) if keep(r["Name"])]
     out = [f"{'kernel':<100} {'calls':>5} {'avg_us':>12} {'min_us':>11} {'max_us':>11}"]
     for r in rows:
         out.append(f"{r['Name'][:100]:<100} {r['Calls']:>5} {float(r['AverageNs']) / 1e3:>12.1f} "
@@ -64,12 +72,14 @@ def stats(path: str) -> str:
     return "\n".join(out)
 
 
-def pmc(paths: list[str]) -> str:
+def pmc(paths: list[str], keep=ours) -> str:
     per = collections.defaultdict(lambda: collections.defaultdict(list))  # kernel -> counter -> per dispatch
     for p in paths:
         acc = collections.defaultdict(float)
         names = {}
         for r in csv.DictReader(open(p)):
+            if not keep(r["Kernel_Name"]):
+                continue
             key = (r["Dispatch_Id"], r["Counter_Name"])
             acc[key] += float(r["Counter_Value"])
             names[r["Dispatch_Id"]] = r["Kernel_Name"]
@@ -122,10 +132,14 @@ def main(argv):
     if len(argv) == 2 and argv[1] == "hash":
         print(source_hash())
         return 0
+    keep = ours
+    if "--all" in argv:  # every kernel of the run (torch's too)
+        argv = [a for a in argv if a != "--all"]
+        keep = lambda name: True  # noqa: E731
     if len(argv) < 3 or argv[1] not in ("stats", "pmc"):
         print(__doc__)
         return 2
-    print(stats(argv[2]) if argv[1] == "stats" else pmc(argv[2:]))
+    print(stats(argv[2], keep) if argv[1] == "stats" else pmc(argv[2:], keep))
     return 0
 
 
