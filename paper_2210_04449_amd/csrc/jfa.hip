@@ -240,6 +240,45 @@ __global__ void __launch_bounds__(256) jfa_far(const int32_t *__restrict__ src, 
     jfa_far_body<WIDE, LINEAR_IN>(src, dst, n, logn, kb, blockIdx.x, gridDim.x, neg2);
 }
 
+// The first pass of plain jump flooding (step n/2) from the caller's linear seeds.  At that step one side of
+// every axis leaves the grid, so a voxel's distinct candidates are its own seed and the seeds at p XOR n/2 on
+// any subset of the axes: the same eight voxels for all eight members of such an orbit, and brick b's
+// candidates sit at the same lane in the bricks b XOR B/2 on those axes.  A workgroup of eight wavefronts
+// takes one orbit of bricks: each wavefront stages its brick once in LDS, and every lane keys the eight staged
+// candidates of its voxel (instead of each wavefront reading all eight bricks from memory).
+template <bool WIDE>
+__device__ __forceinline__ void jfa_first_orbit_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst,
+                                                     int n, int logn, int neg2, uint32_t blk_id, uint32_t nblk)
+{
+    __shared__ uint32_t tile[8][kWave];
+    const int logB = logn - 2, logH = logB - 1, H = 1 << logH;  // orbits: H^3 workgroups, H = B / 2
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = (int)xcd_remap(blk_id, nblk);
+    const int gx = g & (H - 1), gy = (g >> logH) & (H - 1), gz = g >> (2 * logH);
+    // this wavefront's brick: the orbit member (wave bit 0: +B/2 in x, bit 1: in y, bit 2: in z)
+    const int bx = gx + ((wave & 1) << logH), by = gy + (((wave >> 1) & 1) << logH), bz = gz + ((wave >> 2) << logH);
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+    const int x = bx * 4 + lx, y = by * 4 + ly, z = bz * 4 + lz;
+    tile[wave][lane] = pack_linear(src[x + (y << logn) + (z << (2 * logn))], logn);
+    __syncthreads();
+    const JfaPos P = jfa_pos(x, y, z, neg2);
+    double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        const uint32_t c = tile[wave ^ o][lane];
+        best = __builtin_fmin(best, WIDE ? jfa_keyd(P, c) : jfa_key7(P, c));
+    }
+    const int b = bx | (by << logB) | (bz << (2 * logB));
+    dst[((int64_t)b << 6) | lane] = (int32_t)key_seed<WIDE>(P, best);
+}
+
+template <bool WIDE>
+__global__ void __launch_bounds__(512) jfa_first_orbit(const int32_t *__restrict__ src, int32_t *__restrict__ dst,
+                                                       int n, int logn, int neg2)
+{
+    jfa_first_orbit_body<WIDE>(src, dst, n, logn, neg2, blockIdx.x, gridDim.x);
+}
+
 // One pass with step K in {1, 2}: eight bricks (an 8^3 block) per workgroup,
 // staged with a K-voxel halo in LDS.  FINAL writes the caller's outputs.
 template <int K, bool PAIRS, bool FINAL>
@@ -314,6 +353,7 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
     const int64_t nvox = (int64_t)n * n * n;
     const unsigned far_blocks = (unsigned)(nvox / 256);
     const unsigned near_blocks = (unsigned)(nvox / 512);
+    const unsigned orbit_blocks = (unsigned)(nvox / 512);  // one orbit of eight bricks per workgroup
     // Passes 0 .. m-2 go brick layout to brick layout; the final pass (step 1) must read `scratch` and write the
     // caller's linear layout to `seeds` (and `dist2`, `sdf`).  When the first step is a far one it reads the
     // linear input directly, and the brick passes alternate between `dist2` (written only by the final pass,
@@ -327,7 +367,9 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
             const int k = steps[i];
             int32_t *dst = (npass - 1 - i) % 2 == 0 ? scratch : dist2;
             if (k >= 4) {
-                if (i == 0)
+                if (i == 0 && k == n / 2)
+                    jfa_first_orbit<WIDE><<<dim3(orbit_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, -2);
+                else if (i == 0)
                     jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
                 else
                     jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
