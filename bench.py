@@ -202,6 +202,8 @@ def main():
         from paper_2210_04449_amd import autotune
         tuned = autotune.tune(p)
         tuning.update(tuned["tuning"])
+        print(f"[autotune] {tuned['key']}: {tuned['tuning']} {tuned['ms']:.3f} ms, {len(tuned['trials'])} trials"
+              f"{' (cached)' if tuned['cached'] else ''}; jfa {tuned.get('jfa')}", file=sys.stderr, flush=True)
     for f in range(args.warmup):
         update(f)
         p.step(f)
