@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--tile-texels", type=int, default=64, choices=[16, 32, 64])
     ap.add_argument("--bvh-width", type=int, default=2, choices=[2, 4],
                     help="trace the two-child hierarchy or its 4-wide copy (static and refitted scenes)")
-    ap.add_argument("--leaf-size", type=int, default=2)
+    ap.add_argument("--leaf-size", type=int, default=4)
     ap.add_argument("--jfa", default="jfa", choices=["jfa", "jfa+1", "jfa+2", "1+jfa"],
                     help="jump-flooding pass schedule (the extra-pass variants reduce its errors)")
     ap.add_argument("--study", default=None, choices=["alpha", "refit", "motion"],

@@ -280,6 +280,8 @@ int rtsdf_scene_info_get(const rtsdf_scene *scene, rtsdf_scene_info *info);
 /* order (int32 [cap][2][2]; count 0 marks the empty second slot of a        */
 /* one-reference scene), parents[i] the parent node, -1 for the root (int32 */
 /* [cap], may be NULL).  All three are host buffers; synchronises `stream`.  */
+/* A rebuilt hierarchy may hold nodes that no slot references (below its    */
+/* leaves of several references); read the tree from the root.              */
 /* EINVAL for two-level scenes or cap < rtsdf_scene_info.nodes.             */
 int rtsdf_scene_hierarchy(const rtsdf_scene *scene, int32_t cap, float *boxes, int32_t *links, int32_t *parents,
                           rtsdf_stream stream);
@@ -290,11 +292,12 @@ int rtsdf_scene_hierarchy(const rtsdf_scene *scene, int32_t cap, float *boxes, i
 /* synchronises `stream`) and replaces the creation hierarchy with a linear  */
 /* BVH built on the device over the same triangle references: 30-bit Morton  */
 /* codes of the reference centres, a radix sort, the binary radix tree of    */
-/* Karras (HPG 2012), one reference per leaf, boxes bottom-up.  rebuild      */
-/* takes new positions for the same topology (as refit) and rebuilds it; a   */
-/* refit of such a scene refits the rebuilt tree.  Traced results are those */
-/* of the creation hierarchy except for rays whose closest hit is within     */
-/* float rounding of another triangle's (the test order may pick the other). */
+/* Karras (HPG 2012) whose subtrees of at most the scene's creation leaf    */
+/* size (capped at 8) references become single leaves, boxes bottom-up.     */
+/* rebuild takes new positions for the same topology (as refit) and         */
+/* rebuilds it; a refit of such a scene refits the rebuilt tree.  Traced     */
+/* results are those of the creation hierarchy: a triangle's hit test does  */
+/* not depend on the order the hierarchy tests it in.                       */
 /* EINVAL for two-level scenes and for scenes with                           */
 /* fewer than two references; rebuild before enable_rebuild is EINVAL.       */
 /* rebuild is a fixed sequence of kernel launches (no allocation, host      */

@@ -330,9 +330,13 @@ __device__ __forceinline__ int lbvh_delta(const uint32_t *__restrict__ code, int
     return 30 + __clz((uint32_t)i ^ (uint32_t)j);
 }
 
-// step 4: internal node i of the radix tree over n sorted keys
-__global__ void __launch_bounds__(256) lbvh_internal(const uint32_t *__restrict__ code, int n, BvhNode *nodes,
-                                                     int32_t *__restrict__ leaf_parent, int2 *__restrict__ range)
+// step 4: internal node i of the radix tree over n sorted keys.  A child whose leaf run holds at most
+// max_leaf references is referenced as one leaf of that run (the run is consecutive in the sorted order); the
+// internal nodes below it stay in the array, unreferenced, so the bottom-up box passes climb through them as
+// before (their parent pointers follow the full radix tree).
+__global__ void __launch_bounds__(256) lbvh_internal(const uint32_t *__restrict__ code, int n, int max_leaf,
+                                                     BvhNode *nodes, int32_t *__restrict__ leaf_parent,
+                                                     int2 *__restrict__ range)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
@@ -355,8 +359,9 @@ __global__ void __launch_bounds__(256) lbvh_internal(const uint32_t *__restrict_
     range[i] = make_int2(lo, hi);
     const bool left_leaf = lo == gamma, right_leaf = hi == gamma + 1;
     BvhNode &nd = nodes[i];
-    const int c0 = left_leaf ? leaf_code(gamma, 1) : gamma;
-    const int c1 = right_leaf ? leaf_code(gamma + 1, 1) : gamma + 1;
+    const int nl = gamma - lo + 1, nr = hi - gamma;  // references under each child
+    const int c0 = nl <= max_leaf ? leaf_code(lo, nl) : gamma;
+    const int c1 = nr <= max_leaf ? leaf_code(gamma + 1, nr) : gamma + 1;
     nd.meta.x = c0;
     nd.meta.y = c1;
     nd.meta.w = 0;
@@ -372,6 +377,7 @@ __global__ void __launch_bounds__(256) lbvh_internal(const uint32_t *__restrict_
 // its run), which addresses its counter and box in LDS.  A climb that reaches a node whose run crosses the
 // chunk border stops and queues the child it finished.
 constexpr int kChunk = 1024;
+constexpr int kMaxRebuildLeaf = 8;  // references per leaf of a rebuilt hierarchy at most
 
 __device__ __forceinline__ void leaf_ref_box(const float *__restrict__ box, const int32_t *__restrict__ ids, int k,
                                              float lo[3], float hi[3])
@@ -380,6 +386,22 @@ __device__ __forceinline__ void leaf_ref_box(const float *__restrict__ box, cons
     for (int a = 0; a < 3; ++a) {
         lo[a] = b[a];
         hi[a] = b[3 + a];
+    }
+}
+
+// the box of a leaf child (code c): the union of its references' boxes
+__device__ __forceinline__ void leaf_box(const float *__restrict__ box, const int32_t *__restrict__ ids, int c,
+                                         float lo[3], float hi[3])
+{
+    const int first = leaf_first(c), cnt = leaf_count(c);
+    leaf_ref_box(box, ids, first, lo, hi);
+    for (int k = first + 1; k < first + cnt; ++k) {
+        float l[3], h[3];
+        leaf_ref_box(box, ids, k, l, h);
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], l[a]);
+            hi[a] = fmaxf(hi[a], h[a]);
+        }
     }
 }
 
@@ -424,7 +446,7 @@ __global__ void __launch_bounds__(kChunk) lbvh_boxes_local(BvhNode *nodes, const
             if (c[s] == child) {
                 for (int a = 0; a < 3; ++a) l[a] = own_lo[a], h[a] = own_hi[a];
             } else if (c[s] < 0) {
-                leaf_ref_box(box, ids, leaf_first(c[s]), l, h);
+                leaf_box(box, ids, c[s], l, h);
             } else {
                 for (int a = 0; a < 3; ++a) {
                     l[a] = lbox[a][c[s] - c0];
@@ -462,7 +484,7 @@ __global__ void __launch_bounds__(256) lbvh_boxes_top(BvhNode *nodes, const int3
             for (int s = 0; s < 2; ++s) {
                 float lo[3], hi[3];
                 if (c[s] < 0) {
-                    leaf_ref_box(box, ids, leaf_first(c[s]), lo, hi);
+                    leaf_box(box, ids, c[s], lo, hi);
                 } else {
                     const BvhNode *ch = &nodes[c[s]];
                     float l2[3], h2[3];
@@ -554,8 +576,8 @@ static int lbvh_run(rtsdf_scene *sc, bool rebuild, hipStream_t s)
         const int rc = rsort_run(L->code_sorted, L->id_sorted, L->code, L->id, L->hist, n, 30, true, &ok_, &ov_, s);
         if (rc != RTSDF_OK) return rc;
         if (ok_ != L->code_sorted || ov_ != L->id_sorted) return RTSDF_EHIP;  // (an even number of passes)
-        lbvh_internal<<<dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s>>>(L->code_sorted, n, sc->nodes,
-                                                                                  L->leaf_parent, L->range);
+        lbvh_internal<<<dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s>>>(L->code_sorted, n, sc->max_leaf,
+                                                                                  sc->nodes, L->leaf_parent, L->range);
         RTSDF_CHECK_LAUNCH();
         lbvh_records<<<dim3(blocks), dim3(256), 0, s>>>(sc->vertices, sc->faces, L->ref_tri, L->ref_path,
                                                          L->id_sorted, n, sc->tris, sc->leaf_faces);
@@ -633,7 +655,7 @@ extern "C" int rtsdf_scene_enable_rebuild(rtsdf_scene *sc, rtsdf_stream stream)
     sc->nnodes = n - 1;
     sc->nstart = 0;
     sc->max_depth = depth;
-    sc->max_leaf = 1;
+    sc->max_leaf = std::max(1, std::min(sc->leaf_size, kMaxRebuildLeaf));
     sc->bytes += bytes;
     sc->lbvh = L;
     return lbvh_run(sc, true, s);

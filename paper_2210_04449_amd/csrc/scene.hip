@@ -74,6 +74,7 @@ struct rtsdf_scene {
     int nnodes = 0;
     int max_depth = 0;
     int max_leaf = 0;
+    int leaf_size = 0;                 // the leaf size asked for at creation (device rebuilds use it too)
     float pad = 0.f;
     int device = 0;
     rtsdf::BvhNode *nodes = nullptr;   // [nnodes]
@@ -615,6 +616,7 @@ static int rtsdf_scene_create_impl(const float *vertices, int32_t nv, const int3
     sc->nnodes = (int)B.nodes.size();
     sc->max_depth = B.max_depth;
     sc->max_leaf = B.max_leaf;
+    sc->leaf_size = leaf_size;
     sc->pad = B.pad;
     RTSDF_TRY(hipGetDevice(&sc->device));
     std::vector<float4> htri((size_t)3 * std::max(nref, 1));

@@ -33,7 +33,7 @@ from . import rtsdf as R
 class Pipeline:
     def __init__(self, vertices: torch.Tensor, faces: torch.Tensor, nc: int, nf: int, beta: float, d: float,
                  rays: int, seed: int = 0, scene_id: int = 0, alpha: float = 1.0, lo=(0.0, 0.0, 0.0),
-                 side: float = 1.0, leaf_size: int = 2, queue_cap: int | None = None, device="cuda",
+                 side: float = 1.0, leaf_size: int = 4, queue_cap: int | None = None, device="cuda",
                  jfa_variant: str = "jfa", sampling: str = "point", sign_policy: str = "vote",
                  shell: float = 0.0, parts=None, rebuild: bool | None = None):
         if sampling not in ("point", "trilinear"):

@@ -553,7 +553,7 @@ def _dev_view(ptr: int, n: int, dtype: torch.dtype, device) -> torch.Tensor:
 class Batch:
     """Owning handle of an ``rtsdf_batch``: many scenes, one launch per stage."""
 
-    def __init__(self, scenes: list[dict], seed: int = 0, leaf_size: int = 2, stream=None):
+    def __init__(self, scenes: list[dict], seed: int = 0, leaf_size: int = 4, stream=None):
         arr = (BatchScene * len(scenes))()
         self._keep = []
         for i, d in enumerate(scenes):
