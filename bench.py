@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--refit", action="store_true",
                     help="dynamic workload: refit the hierarchy every update instead of rebuilding it on the device "
                          "(the default for moving geometry)")
+    ap.add_argument("--device-build", action="store_true",
+                    help="build the hierarchy on the device (as moving scenes do) also for a static scene")
     ap.add_argument("--parts", action="store_true",
                     help="dynamic workload as a two-level scene of rigid parts instead of one refitted hierarchy")
     ap.add_argument("--no-shadow", action="store_true", help="skip timing the soft-shadow consumer")
@@ -168,6 +170,8 @@ def main():
               leaf_size=args.leaf_size, jfa_variant=args.jfa, sampling=args.sampling)
     if args.refit:
         kw["rebuild"] = False
+    if args.device_build:
+        kw["rebuild"] = True
     dyn_frames = dyn_T = None
     # moving scenes move continuously: one geometry per update (warm-up, timed updates, the instrumented frame and
     # the graph replays), generated up front
