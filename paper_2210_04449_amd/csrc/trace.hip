@@ -239,10 +239,10 @@ __device__ __forceinline__ int tri_id(const float4 *tris, int i)
     return __float_as_int(reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tris) + rec48(i))->w);
 }
 
-// slab test against a padded box: whether the ray meets it before tbest (a NaN slab misses), and the entry
-// distance
-__device__ __forceinline__ bool box_hit(const RaySetup &R, float lx, float hx, float ly, float hy, float lz, float hz,
-                                        float tbest, float &t_entry)
+// slab test against a padded box: whether the ray meets it before tbest (a NaN slab misses), the entry
+// distance and the exit distance (capped at tbest)
+__device__ __forceinline__ bool box_hit2(const RaySetup &R, float lx, float hx, float ly, float hy, float lz, float hz,
+                                         float tbest, float &t_entry, float &t_exit)
 {
     const float x0 = fmaf(lx, R.ix, -R.oix), x1 = fmaf(hx, R.ix, -R.oix);
     const float y0 = fmaf(ly, R.iy, -R.oiy), y1 = fmaf(hy, R.iy, -R.oiy);
@@ -250,7 +250,15 @@ __device__ __forceinline__ bool box_hit(const RaySetup &R, float lx, float hx, f
     const float tmin = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
     const float tmax = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tbest));
     t_entry = tmin;
+    t_exit = tmax;
     return tmin <= tmax;
+}
+
+__device__ __forceinline__ bool box_hit(const RaySetup &R, float lx, float hx, float ly, float hy, float lz, float hz,
+                                        float tbest, float &t_entry)
+{
+    float t_exit;
+    return box_hit2(R, lx, hx, ly, hy, lz, hz, tbest, t_entry, t_exit);
 }
 
 constexpr int kDone = INT32_MIN;
@@ -519,10 +527,12 @@ __device__ __forceinline__ void node_step_regs(const RaySetup &R, float4 a, floa
                                                float tbest, int &tri_cur, int &tri_end, bool &push, int &push_val,
                                                bool &pop)
 {
-    float t0, t1;
-    const bool h0 = box_hit(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest, t0);
-    const bool h1 = box_hit(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest, t1);
-    node_decide(h0, t0, h1, t1, m, node, tri_cur, tri_end, push, push_val, pop);
+    float t0, t1, e0, e1;
+    const bool h0 = box_hit2(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest, t0, e0);
+    const bool h1 = box_hit2(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest, t1, e1);
+    // equal entries (the origin inside both boxes): the child the ray leaves first first
+    const float k0 = t0 == t1 ? e0 : t0, k1 = t0 == t1 ? e1 : t1;
+    node_decide(h0, k0, h1, k1, m, node, tri_cur, tri_end, push, push_val, pop);
 }
 
 __device__ __forceinline__ void node_step_flat(const BvhView &S, const RaySetup &R, int &node, float tbest,
