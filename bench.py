@@ -291,7 +291,7 @@ def main():
     if tuning["bvh_width"] == 4:
         tname = f"trace_persistent<{tuning['stack_lds']},{tuning['refill']},3,false,false,false,true>"
     else:
-        tname = f"trace_persistent<{tuning['stack_lds']},{tuning['refill']},{tuning['loop']},false,false,{inst}>"
+        tname = f"trace_persistent<{tuning['stack_lds']},{tuning['refill']},{tuning['loop']},false,false,{inst},false>"
     tr = traffic_from_summary(os.path.join(ROOT, "profiles", f"pmc_{w.name}_{w.nc}_{w.nf}.txt"), tname)
     traffic = None if tr is None else int(tr["fetch_bytes"] + tr["write_bytes"])
 
