@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="pick the tracer tuning by measurement first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
-    ap.add_argument("--refill", type=int, default=16)
+    ap.add_argument("--refill", type=int, default=28, choices=[16, 28])
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--loop", type=int, default=4, choices=[0, 1, 2, 3, 4])
     ap.add_argument("--bin", type=int, default=1, choices=[0, 1])
@@ -640,6 +640,8 @@ def batched_record(args, steps: int, warmup: int) -> dict:
     if args.autotune:
         from paper_2210_04449_amd import autotune
         autotune.tune(B)
+    elif args.config == "batched" and args.refill != 28:
+        B.set_tuning(refill=args.refill)
     g = B.make_graph(first_frame=0)
     for _ in range(warmup):
         g.launch()

@@ -401,10 +401,11 @@ void rtsdf_scene_destroy(rtsdf_scene *scene);
 /*            `frame` itself must be < 2^23 (EINVAL).                        */
 /* workspace  rtsdf_trace_workspace_size() bytes of device memory: 256 B of  */
 /*            counters, per-wavefront buffers holding the directions of the  */
-/*            rays each persistent wavefront is tracing, and the spill area  */
-/*            of the traversal stacks (entries deeper than the LDS part, for */
-/*            hierarchies up to depth 64); ~210 MB on a 256-CU device (the   */
-/*            size is that of the current device).  Calls that run          */
+/*            rays of each persistent wavefront's tile (drawn, then sorted   */
+/*            by direction bin), and the spill area of the traversal stacks  */
+/*            (entries deeper than the LDS part, for hierarchies up to depth */
+/*            64); ~310 MB on a 256-CU device (the size is that of the       */
+/*            current device).  Calls that run                               */
 /*            concurrently need separate workspaces; they may trace the same */
 /*            scene.                                                         */
 /* ------------------------------------------------------------------------ */
@@ -429,10 +430,10 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
  * own tuning (NULL: back to the process default) and rtsdf_batch_set_tuning
  * one batch, so callers tracing different scenes do not share it.
  * rtsdf_scene_get_tuning returns the tuning a trace of the scene uses.
- * Defaults: refill 16, blocks_per_cu 0, stats 0, loop 4, bin_directions 1,
+ * Defaults: refill 28, blocks_per_cu 0, stats 0, loop 4, bin_directions 1,
  * stack_lds 12, tile_texels 64, bvh_width 2:
  *   refill          a wavefront hands out new rays once this many of its
- *                   lanes are free (8 or 16);
+ *                   lanes are free (16 or 28);
  *   blocks_per_cu   persistent workgroups of four wavefronts per compute
  *                   unit, i.e. traversal wavefronts per SIMD (0 = as many as
  *                   fit: 6 with the default LDS stack; 1 to 8);

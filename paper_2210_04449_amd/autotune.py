@@ -50,7 +50,7 @@ DEFAULT_CACHE = os.environ.get("RTSDF_AUTOTUNE_CACHE",
 SPACE = {
     "blocks_per_cu": (0, 3, 4, 5),
     "tile_texels": (64, 32, 16),
-    "refill": (16, 8),
+    "refill": (28, 16),
     "stack_lds": (12, 16, 24),
     "bin_directions": (1, 0),
     "loop": (4, 3),

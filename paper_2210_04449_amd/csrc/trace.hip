@@ -94,8 +94,15 @@ struct RaySetup {
     float oix, oiy, oiz; // origin * inverse
     float ox, oy, oz;    // origin
     float dx, dy, dz;    // direction
-    float len;           // |direction|
 };
+
+// |direction|, which turns a hit's ray parameter into a distance (computed where it is needed, from the
+// stored direction, so the traversal loop does not keep it; the fused multiply-adds are spelled out so every
+// kernel rounds it alike)
+__device__ __forceinline__ float ray_len(const RaySetup &R)
+{
+    return __builtin_amdgcn_sqrtf(fmaf(R.dz, R.dz, fmaf(R.dy, R.dy, R.dx * R.dx)));
+}
 
 __device__ __forceinline__ float safe_inv(float d)
 {
@@ -117,7 +124,6 @@ __device__ __forceinline__ void ray_setup(float ox, float oy, float oz, float dx
     R.dx = dx;
     R.dy = dy;
     R.dz = dz;
-    R.len = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
 }
 
 // Watertight ray/triangle test (Woop, Benthin and Wald 2013): the vertices are
@@ -565,22 +571,20 @@ constexpr int kQueueCap = 128;
 constexpr unsigned long long kBestInit = 0x7F800000FFFFFFFFull;  // t = +inf, no triangle
 constexpr int kMaxQueuedRefs = 1 << 26;  // queue entries: leaf-order index << 6 | lane
 static_assert(2 * kWave <= kQueueCap && (kQueueCap & (kQueueCap - 1)) == 0, "queue size");
-static_assert(kWave * 8 + kQueueCap * 4 <= kBins * 4 + kTileRays, "the queue reuses the sort area");
+static_assert(kBins <= kQueueCap, "the bin counters share the queue's words");
 
+// A wavefront's LDS: the texel results of two tile contexts (the tile whose rays are handed out and the one
+// before it, whose last rays may still be in flight; context c holds entries c * kTileTexels + slot), each
+// lane's best hit key (queued loop) and the triangle-test queue, whose words hold the direction-bin counters
+// while a tile's rays are sorted (the queue is empty then).
 struct WaveTile {
-    int32_t tex[kTileTexels];
-    unsigned long long key[kTileTexels];  // min over rays of (distance bits << 32 | ray << 26 | triangle)
-    uint32_t cnt[kTileTexels];            // front | back << 16 for this frame
-    uint16_t perm[kTileRays];             // ray ids (slot * R + ray) sorted by direction bin
+    int32_t tex[2 * kTileTexels];
+    unsigned long long key[2 * kTileTexels];  // min over rays of (distance bits << 32 | ray << 26 | triangle)
+    uint32_t cnt[2 * kTileTexels];            // front | back << 16 for this frame
+    unsigned long long best[kWave];  // each lane's ray: min of (t bits << 32 | triangle id << 1 | front)
     union {
-        struct {
-            uint32_t bin[kBins];          // bin counts, then bin cursors
-            uint8_t binof[kTileRays];     // direction bin of each ray
-        } sort;                           // before the tile's rays are traced
-        struct {
-            unsigned long long best[kWave];  // each lane's ray: min of (t bits << 32 | triangle id << 1 | front)
-            uint32_t q[kQueueCap];           // queued triangle tests: leaf-order index << 6 | lane of the ray
-        } tq;                             // while they are traced (queued loop)
+        uint32_t q[kQueueCap];       // queued triangle tests: leaf-order index << 6 | lane of the ray
+        uint32_t bin[kBins];         // bin counts, then bin cursors
     };
 };
 
@@ -607,12 +611,20 @@ __global__ void trace_tile_prefix(const TraceScene *scenes, int n, int cap, int3
 // Persistent tracer.  Each wavefront repeatedly takes a tile of up to 64
 // consecutive queue texels of one scene (Morton order: a compact block of the
 // fine grid), draws all their rays' directions, sorts the rays by direction
-// bin in LDS, and traces them in that order, so the lanes of a wavefront
-// follow rays that start close together and point the same way.  Results are
-// folded per texel with LDS atomics (a 64-bit min keeps the smallest distance,
-// ties to the lowest ray index, together with its triangle; an add counts
-// front and back hits), which makes them independent of the order rays
-// complete in.  Three traversal loop shapes (LOOP): 0 = phases per iteration
+// bin, and traces them in that order, so the lanes of a wavefront follow rays
+// that start close together and point the same way.  Results are folded per
+// texel with LDS atomics (a 64-bit min keeps the smallest distance, ties to
+// the lowest ray index, together with its triangle; an add counts front and
+// back hits), which makes them independent of the order rays complete in.  A
+// wavefront holds two tile contexts: once its tile has handed out its last
+// ray, it sorts the next tile's rays into the other context and refills its
+// lanes from there while the first tile's last rays are still traced (a
+// tile's Eq. (1) epilogue runs once its last ray is done), so lanes do not
+// wait for the slowest ray of each tile.  Two-level scenes, and a next tile
+// of another scene in a batch, start only once every lane is done (a part's
+// exit re-reads its ray's direction by ray id; the traversal takes the
+// scene's hierarchy as a wave-uniform value).
+// Loop shapes (LOOP): 0 = phases per iteration
 // (after Aila and Laine's "while-while" loop with postponed leaves: every lane
 // walks internal nodes until it holds a leaf, then all held leaves are
 // tested); 1 = one unit of work per lane per iteration (a triangle of the
@@ -621,7 +633,8 @@ __global__ void trace_tile_prefix(const TraceScene *scenes, int n, int cap, int3
 // push/pop and one shared copy of the stack code runs after the work; 3 =
 // as 2, but every lane fetches its node or its triangle's map into the same
 // registers with one shared load sequence, so an iteration waits for memory
-// once instead of once per kind of work.  BATCHED launches serve many scenes: a global tile
+// once instead of once per kind of work; 4 = queued triangle tests (below).
+// BATCHED launches serve many scenes: a global tile
 // index is mapped to its scene through the tile prefix.  Instrumented runs
 // (STATS) also count into 64-bit counters at workspace offsets 8, 16, ...:
 // node visits, triangle tests, rays, traversal-loop iterations x 64, refill
@@ -639,7 +652,10 @@ trace_persistent(TraceArgs A)
     lds_int *stk = (lds_int *)(stack_mem + wave * SL * kWave + lane);
     WaveTile &T = tiles[wave];
     int32_t *spill = A.spill + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float4 *dirs = A.dirs + ((int64_t)blockIdx.x * kTraceWaves + wave) * kTileRays;
+    // the wavefront's two direction buffers: by ray id (slot * R + ray), and the same rays in bin order as
+    // (direction, ray id) records
+    float4 *dirs = A.dirs + ((int64_t)blockIdx.x * kTraceWaves + wave) * (2 * kTileRays);
+    float4 *recs = dirs + kTileRays;
     const int stride = A.spill_stride;
     const uint32_t frame = A.frame_ptr ? *A.frame_ptr : A.frame;
     if (frame >= kMaxFrame) {
@@ -650,95 +666,120 @@ trace_persistent(TraceArgs A)
     }
     const int single_tiles = BATCHED ? 0 : scene_tiles(A.one, A.tile_cap);
     const int all_tiles = BATCHED ? A.tile_offset[A.nscenes] : single_tiles;
+    const auto scene_of = [&](int g) {  // last scene whose first tile is <= g
+        int lo = 0, hi = A.nscenes - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (A.tile_offset[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        return __builtin_amdgcn_readfirstlane(lo);
+    };
+
+    // wave-uniform context state: -1 free, else rays not yet finished | texels << 16; and the scene (batches)
+    int cstate[2] = {-1, -1}, cscene[2] = {0, 0};
+    int cur = 0, pool = 0, nrays = 0;  // the context rays are handed out from
+    uint32_t rdiv = 0;                 // its q / R multiplier (below)
+    int gnext = -2;                    // the next tile: -2 not taken yet, -1 none left
+    // lane state
+    bool busy = false;
+    int rid = 0;  // the lane's ray: (context * kTileTexels + texel slot) << 6 | ray index
+    RaySetup Rs;
+    float tbest = __builtin_inff();
+    int ibest = -1, node = kDone, leaf = kDone, sp = 0;
+    int tri_cur = 0, tri_end = 0;
+    bool front = false;
 
     while (true) {
-        // ---- take a tile
-        int g = 0;
-        if (lane == 0) g = atomicAdd(A.cursor, 1);
-        g = __shfl(g, 0);
-        if (g >= all_tiles) break;
-        int s = 0;
-        if (BATCHED) {  // last scene whose first tile is <= g
-            int lo = 0, hi = A.nscenes - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (A.tile_offset[mid] <= g) lo = mid;
-                else hi = mid - 1;
+        // ---- start the next tile once the current one has handed out its last ray
+        const bool any_busy = __builtin_amdgcn_ballot_w64(busy) != 0;
+        if (pool >= nrays && cstate[cur ^ 1] < 0 && gnext != -1) {
+            if (gnext == -2) {
+                int g = 0;
+                if (lane == 0) g = atomicAdd(A.cursor, 1);
+                g = __builtin_amdgcn_readlane(g, 0);  // a wave-uniform (scalar) value
+                gnext = g < all_tiles ? g : -1;
             }
-            s = __builtin_amdgcn_readfirstlane(lo);
-        }
-        const TraceScene &P = BATCHED ? A.scenes[s] : A.one;
-        if (STATS) ++st_tiles;
-        const int R = P.rays;
-        // q / R as a multiply-high: exact for q < kTileRays and R <= 64 (the error of the rounded-up
-        // reciprocal, q / 2^32, stays below the distance 1/R of q / R from the next integer)
-        const uint32_t rdiv = R > 1 ? (uint32_t)(((1ull << 32) + (uint64_t)R - 1) / (uint64_t)R) : 0u;
-        const int nfm = P.nf - 1;
-        const int tile_texels = tile_texels_for(R, A.tile_cap);
-        const int total = min(*P.count, P.queue_cap);
-        const int base = (g - (BATCHED ? A.tile_offset[s] : 0)) * tile_texels;
-        const int nt = min(tile_texels, total - base);
-        const int nrays = nt * R;
-        const uint64_t ntex_grid = (uint64_t)1 << (3 * P.lognf);
-        if (lane < nt) {
-            int j = P.queue[base + lane];
-            if (j < 0 || (uint64_t)j >= ntex_grid) j = -1;
-            T.tex[lane] = j;
-            T.key[lane] = ~0ull;
-            T.cnt[lane] = 0u;
-        }
-        T.sort.bin[lane] = 0u;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        // ---- bin the tile's rays by direction
+            const int sn = gnext >= 0 && BATCHED ? scene_of(gnext) : 0;
+            if (gnext >= 0 && (!any_busy || (!INST && (!BATCHED || sn == cscene[cur])))) {
+                const int c = cur ^ 1, g = gnext;
+                gnext = -2;
+                const TraceScene &P = BATCHED ? A.scenes[sn] : A.one;
+                if (STATS) ++st_tiles;
+                const int R = P.rays;
+                // q / R as a multiply-high: exact for q < kTileRays and R <= 64 (the error of the rounded-up
+                // reciprocal, q / 2^32, stays below the distance 1/R of q / R from the next integer)
+                rdiv = R > 1 ? (uint32_t)(((1ull << 32) + (uint64_t)R - 1) / (uint64_t)R) : 0u;
+                const int tile_texels = tile_texels_for(R, A.tile_cap);
+                const int total = min(*P.count, P.queue_cap);
+                const int base = (g - (BATCHED ? A.tile_offset[sn] : 0)) * tile_texels;
+                const int nt = min(tile_texels, total - base);
+                const uint64_t ntex_grid = (uint64_t)1 << (3 * P.lognf);
+                const int c0 = c * kTileTexels;
+                if (lane < nt) {
+                    int j = P.queue[base + lane];
+                    if (j < 0 || (uint64_t)j >= ntex_grid) j = -1;
+                    T.tex[c0 + lane] = j;
+                    T.key[c0 + lane] = ~0ull;
+                    T.cnt[c0 + lane] = 0u;
+                }
+                T.bin[lane] = 0u;  // the queue is empty between traversal rounds
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                // ---- bin the tile's rays by direction (the bin rides in the direction record's w)
+                nrays = nt * R;
 #pragma unroll 1
-        for (int q = lane; q < nrays; q += kWave) {
-            const int slot = R > 1 ? (int)__umulhi((uint32_t)q, rdiv) : q, r = q - slot * R;
-            const int j = T.tex[slot];
-            int b = 0;
-            if (j >= 0) {
-                // drawn once at full width; the lane that later takes the ray reads it back
-                const float3 d = sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)r, P.scene_id);
-                dirs[q] = make_float4(d.x, d.y, d.z, 0.0f);
-                if (A.bin_directions) b = direction_bin(d);
-            }
-            T.sort.binof[q] = (uint8_t)b;
-            atomicAdd(&T.sort.bin[b], 1u);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");  // also orders the stored directions
-        __builtin_amdgcn_wave_barrier();
-        {  // exclusive scan of the 64 bin counts, one per lane
-            const uint32_t c = T.sort.bin[lane];
-            uint32_t x = c;
+                for (int q = lane; q < nrays; q += kWave) {
+                    const int qs = R > 1 ? (int)__umulhi((uint32_t)q, rdiv) : q, qr = q - qs * R;
+                    const int j = T.tex[c0 + qs];
+                    int b = 0;
+                    if (j >= 0) {
+                        // drawn once at full width; the lane that later takes the ray reads it back
+                        const float3 d = sphere_dir(A.seed, (uint32_t)j, frame, (uint32_t)qr, P.scene_id);
+                        if (A.bin_directions) b = direction_bin(d);
+                        dirs[q] = make_float4(d.x, d.y, d.z, __int_as_float(b));
+                    }
+                    atomicAdd(&T.bin[b], 1u);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                {  // exclusive scan of the 64 bin counts, one per lane
+                    const uint32_t cb = T.bin[lane];
+                    uint32_t x = cb;
 #pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const uint32_t y = __shfl_up(x, off);
-                if (lane >= off) x += y;
-            }
-            T.sort.bin[lane] = x - c;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+                    for (int off = 1; off < kWave; off <<= 1) {
+                        const uint32_t y = __shfl_up(x, off);
+                        if (lane >= off) x += y;
+                    }
+                    T.bin[lane] = x - cb;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                // ---- the records in bin order (each lane re-reads the directions it stored)
 #pragma unroll 1
-        for (int q = lane; q < nrays; q += kWave) {
-            const uint32_t pos = atomicAdd(&T.sort.bin[T.sort.binof[q]], 1u);
-            T.perm[pos] = (uint16_t)q;
+                for (int q = lane; q < nrays; q += kWave) {
+                    const int qs = R > 1 ? (int)__umulhi((uint32_t)q, rdiv) : q;
+                    float4 d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if (T.tex[c0 + qs] >= 0) d = dirs[q];
+                    const uint32_t pos = atomicAdd(&T.bin[__float_as_int(d.w)], 1u);
+                    recs[pos] = make_float4(d.x, d.y, d.z, __int_as_float(q));
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");  // also orders the stored records
+                __builtin_amdgcn_wave_barrier();
+                cstate[c] = nrays | nt << 16;
+                cscene[c] = sn;
+                cur = c;
+                pool = 0;
+            }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
 
-        // ---- trace the tile's rays in bin order
+        // ---- refill idle lanes from the current tile, in bin order
+        const TraceScene &P = BATCHED ? A.scenes[cscene[cur]] : A.one;
+        const int R = P.rays;
+        const int nfm = P.nf - 1;
         const BvhView S = P.bvh;
         const int scene_nt = P.nt;
-        int pool = 0;
-        bool busy = false;
-        int slot = 0, r = 0;
-        RaySetup Rs;
-        float tbest = __builtin_inff();
-        int ibest = -1, node = kDone, leaf = kDone, sp = 0;
-        int tri_cur = 0, tri_end = 0;
-        bool front = false;
-        while (true) {
+        {
             const uint64_t need = __builtin_amdgcn_ballot_w64(!busy);
             if (need != 0 && pool < nrays) {
                 if (STATS) ++st_refills;
@@ -746,15 +787,15 @@ trace_persistent(TraceArgs A)
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
                 const int take = min(__popcll(need), nrays - pool);
                 if (!busy && rank < take) {
-                    const int q = T.perm[pool + rank];
-                    slot = R > 1 ? (int)__umulhi((uint32_t)q, rdiv) : q;
-                    r = q - slot * R;
-                    const int j = T.tex[slot];
+                    const float4 d = recs[pool + rank];
+                    const int q = __float_as_int(d.w);
+                    const int qs = R > 1 ? (int)__umulhi((uint32_t)q, rdiv) : q;
+                    rid = (cur * kTileTexels + qs) << 6 | (q - qs * R);
+                    const int j = T.tex[cur * kTileTexels + qs];
                     if (j >= 0) {
                         const float ox = texel_coord(P.lox, j & nfm, P.hf);
                         const float oy = texel_coord(P.loy, (j >> P.lognf) & nfm, P.hf);
                         const float oz = texel_coord(P.loz, j >> (2 * P.lognf), P.hf);
-                        const float4 d = dirs[q];
                         ray_setup(ox, oy, oz, d.x, d.y, d.z, Rs);
                         node = scene_nt > 0 ? 0 : kDone;
                     } else {
@@ -763,7 +804,7 @@ trace_persistent(TraceArgs A)
                     tbest = __builtin_inff();
                     ibest = -1;
                     front = false;
-                    if (LOOP == 4) T.tq.best[lane] = kBestInit;
+                    if (LOOP == 4) T.best[lane] = kBestInit;
                     leaf = kDone;
                     tri_cur = tri_end = 0;
                     sp = 0;
@@ -771,8 +812,18 @@ trace_persistent(TraceArgs A)
                 }
                 pool += take;
             }
-            if (__builtin_amdgcn_ballot_w64(busy) == 0) break;
-            const int refill_at = __builtin_amdgcn_readfirstlane(pool < nrays ? REFILL : kWave);
+        }
+        if (__builtin_amdgcn_ballot_w64(busy) == 0) {
+            // every context is finished (a context's epilogue runs when its last ray is done)
+            if (pool >= nrays && gnext == -1) break;
+            continue;
+        }
+        {
+            // refill rounds go on while this tile has rays or the next one can start before every lane is
+            // done; otherwise every lane finishes first
+            const bool early = !INST && cstate[cur ^ 1] < 0 &&
+                               (gnext == -2 || (gnext >= 0 && (!BATCHED || scene_of(gnext) == cscene[cur])));
+            const int refill_at = __builtin_amdgcn_readfirstlane(pool < nrays || early ? REFILL : kWave);
             if (LOOP == 0) {
                 while (true) {
                     if (busy && leaf == kDone && node < 0 && node != kDone) {
@@ -863,8 +914,8 @@ trace_persistent(TraceArgs A)
                         }
                     } else if (INST && busy && node == kReturn) {
                         // the part is done (its last leaf's triangles too): the world ray again, as drawn
-                        const int j = T.tex[slot];
-                        const float4 d = dirs[slot * R + r];
+                        const int j = T.tex[rid >> 6];
+                        const float4 d = dirs[((rid >> 6) & (kTileTexels - 1)) * R + (rid & 63)];
                         ray_setup(texel_coord(P.lox, j & nfm, P.hf), texel_coord(P.loy, (j >> P.lognf) & nfm, P.hf),
                                   texel_coord(P.loz, j >> (2 * P.lognf), P.hf), d.x, d.y, d.z, Rs);
                         pop = true;
@@ -894,7 +945,7 @@ trace_persistent(TraceArgs A)
                 int qh = 0, qt = 0;  // wave-uniform head and tail (entries at index & (kQueueCap - 1))
                 const auto flush = [&](int nf) {
                     const bool act = lane < nf;
-                    const uint32_t e = act ? T.tq.q[(qh + lane) & (kQueueCap - 1)] : (uint32_t)lane;
+                    const uint32_t e = act ? T.q[(qh + lane) & (kQueueCap - 1)] : (uint32_t)lane;
                     const int owner = (int)(e & 63u), addr = owner << 2;
                     // the owner's ray, from its registers (every lane takes part in the permutes)
                     const float ox = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(Rs.ox)));
@@ -913,13 +964,13 @@ trace_persistent(TraceArgs A)
                         if (tri_hit_rows(ox, oy, oz, dx, dy, dz, mp[0], mp[1], mp[2], S.tris, i, tb, t, fr)) {
                             const unsigned long long key = ((unsigned long long)__float_as_uint(t) << 32) |
                                                            ((uint32_t)tri_id(S.tris, i) << 1) | (fr ? 1u : 0u);
-                            atomicMin(&T.tq.best[owner], key);
+                            atomicMin(&T.best[owner], key);
                         }
                     }
                     qh += nf;
                     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                     __builtin_amdgcn_wave_barrier();
-                    tbest = __uint_as_float((uint32_t)(T.tq.best[lane] >> 32));
+                    tbest = __uint_as_float((uint32_t)(T.best[lane] >> 32));
                 };
                 while (true) {
                     if (STATS) {
@@ -943,8 +994,8 @@ trace_persistent(TraceArgs A)
                     }
                     if (g > 0) {
                         const uint32_t e = ((uint32_t)tri_cur << 6) | (uint32_t)lane;
-                        T.tq.q[(qt + pos) & (kQueueCap - 1)] = e;
-                        if (g > 1) T.tq.q[(qt + pos + 1) & (kQueueCap - 1)] = e + 64u;
+                        T.q[(qt + pos) & (kQueueCap - 1)] = e;
+                        if (g > 1) T.q[(qt + pos + 1) & (kQueueCap - 1)] = e + 64u;
                         tri_cur += g;
                     }
                     qt += total;
@@ -1027,11 +1078,12 @@ trace_persistent(TraceArgs A)
                     if (__popcll(done) >= refill_at) break;
                 }
             }
-            if (busy && node == kDone && leaf == kDone && tri_cur >= tri_end) {
+            const bool fin = busy && node == kDone && leaf == kDone && tri_cur >= tri_end;
+            if (fin) {
                 if (STATS) ++st_rays;
                 int id = -1;
                 if (LOOP == 4) {
-                    const unsigned long long kb = T.tq.best[lane];
+                    const unsigned long long kb = T.best[lane];
                     if (kb != kBestInit) {
                         tbest = __uint_as_float((uint32_t)(kb >> 32));
                         id = (int)((uint32_t)kb >> 1);
@@ -1041,54 +1093,65 @@ trace_persistent(TraceArgs A)
                     id = tri_id(S.tris, ibest);
                 }
                 if (id >= 0) {
-                    const float dist = tbest * Rs.len;
+                    const float dist = tbest * ray_len(Rs);
                     const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) |
-                                                   ((unsigned long long)r << 26) | (unsigned long long)id;
-                    atomicMin(&T.key[slot], key);
-                    atomicAdd(&T.cnt[slot], front ? 1u : 0x10000u);
+                                                   ((unsigned long long)(rid & 63) << 26) | (unsigned long long)id;
+                    atomicMin(&T.key[rid >> 6], key);
+                    atomicAdd(&T.cnt[rid >> 6], front ? 1u : 0x10000u);
                 }
                 busy = false;
             }
+            const uint64_t fin1 = __builtin_amdgcn_ballot_w64(fin && rid >= (kTileTexels << 6));
+            cstate[0] -= (int)__popcll(__builtin_amdgcn_ballot_w64(fin) & ~fin1);
+            cstate[1] -= (int)__popcll(fin1);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
 
-        // ---- Eq. (1) on the unsigned state, then the sign vote
-        if (lane < nt && T.tex[lane] >= 0) {
-            const int j = T.tex[lane];
-            const unsigned long long key = T.key[lane];
-            const uint32_t fc = T.cnt[lane];
-            const float rmin = key == ~0ull ? __builtin_inff() : __uint_as_float((uint32_t)(key >> 32));
-            const int argray = (int)((key >> 26) & 63u), argtri = (int)(key & ((1u << 26) - 1u));
-            const int x = j & nfm, y = (j >> P.lognf) & nfm, z = j >> (2 * P.lognf);
-            const float c = P.coarse_sdf[(x >> P.logr) + P.nc * ((y >> P.logr) + P.nc * (z >> P.logr))];
-            const float uprev = P.u[j];
-            const uint32_t h = P.hits[j];
-            const uint32_t F = min((h & 0xFFFFu) + (fc & 0xFFFFu), 0xFFFFu);
-            const uint32_t B = min((h >> 16) + (fc >> 16), 0xFFFFu);
-            float uu;
-            if (P.alpha == 1.0f) {
-                uu = uprev;
-            } else {
-                // alpha = 0: no memory, the alpha u term is 0 even before the first hit (u = +inf)
-                uu = P.alpha == 0.0f ? fmaxf(c, 0.0f) : P.alpha * uprev + (1.0f - P.alpha) * fmaxf(c, 0.0f);
+        // ---- Eq. (1) on the unsigned state, then the sign vote, for each tile whose last ray is done
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (cstate[c] < 0 || (cstate[c] & 0xFFFF) > 0) continue;
+            const int nt = cstate[c] >> 16, e = c * kTileTexels + lane;
+            cstate[c] = -1;
+            const TraceScene &Q = BATCHED ? A.scenes[cscene[c]] : A.one;
+            if (lane < nt && T.tex[e] >= 0) {
+                const int j = T.tex[e];
+                const unsigned long long key = T.key[e];
+                const uint32_t fc = T.cnt[e];
+                const float rmin = key == ~0ull ? __builtin_inff() : __uint_as_float((uint32_t)(key >> 32));
+                const int argray = (int)((key >> 26) & 63u), argtri = (int)(key & ((1u << 26) - 1u));
+                const int qm = Q.nf - 1;
+                const int x = j & qm, y = (j >> Q.lognf) & qm, z = j >> (2 * Q.lognf);
+                const float cs = Q.coarse_sdf[(x >> Q.logr) + Q.nc * ((y >> Q.logr) + Q.nc * (z >> Q.logr))];
+                const float uprev = Q.u[j];
+                const uint32_t h = Q.hits[j];
+                const uint32_t F = min((h & 0xFFFFu) + (fc & 0xFFFFu), 0xFFFFu);
+                const uint32_t B = min((h >> 16) + (fc >> 16), 0xFFFFu);
+                float uu;
+                if (Q.alpha == 1.0f) {
+                    uu = uprev;
+                } else {
+                    // alpha = 0: no memory, the alpha u term is 0 even before the first hit (u = +inf)
+                    uu = Q.alpha == 0.0f ? fmaxf(cs, 0.0f) : Q.alpha * uprev + (1.0f - Q.alpha) * fmaxf(cs, 0.0f);
+                }
+                if (rmin < uu) {
+                    uu = rmin;
+                    Q.arg_tri[j] = argtri;
+                    Q.arg_ray[j] = (int32_t)((frame << 8) | (uint32_t)argray);
+                } else if (Q.alpha != 1.0f) {
+                    Q.arg_tri[j] = -1;
+                    Q.arg_ray[j] = -1;
+                }
+                Q.u[j] = uu;
+                Q.hits[j] = F | (B << 16);
+                if (isinf(uu)) Q.fine[j] = cs;
+                else if (Q.sign_policy == RTSDF_SIGN_SHELL) Q.fine[j] = uu - Q.shell;
+                else Q.fine[j] = B > F ? -uu : uu;
             }
-            if (rmin < uu) {
-                uu = rmin;
-                P.arg_tri[j] = argtri;
-                P.arg_ray[j] = (int32_t)((frame << 8) | (uint32_t)argray);
-            } else if (P.alpha != 1.0f) {
-                P.arg_tri[j] = -1;
-                P.arg_ray[j] = -1;
-            }
-            P.u[j] = uu;
-            P.hits[j] = F | (B << 16);
-            if (isinf(uu)) P.fine[j] = c;
-            else if (P.sign_policy == RTSDF_SIGN_SHELL) P.fine[j] = uu - P.shell;
-            else P.fine[j] = B > F ? -uu : uu;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
     }
     if (STATS) {
         unsigned long long *ctr = reinterpret_cast<unsigned long long *>(A.cursor + 2);
@@ -1229,14 +1292,14 @@ __global__ void __launch_bounds__(256) trace_backward_kernel(const float *__rest
 
 // ------------------------------------------------------------- launch ----
 
-static rtsdf_trace_tuning g_tuning = {16, 0, 0, 4, 1, 12, 64, 2};
+static rtsdf_trace_tuning g_tuning = {28, 0, 0, 4, 1, 12, 64, 2};
 constexpr int kMaxBlocksPerCu = 8;  // persistent workgroups per CU (direction buffers and spill area sized for this)
 constexpr int kMinShortStack = 12;  // smallest LDS stack part (spill area sized for this)
 constexpr int kMaxStackDepth = 64;  // deepest hierarchy the tracer takes
 
 static bool tuning_ok(const rtsdf_trace_tuning &t)
 {
-    if (t.refill != 8 && t.refill != 16) return false;
+    if (t.refill != 16 && t.refill != 28) return false;
     if (t.blocks_per_cu < 0 || t.blocks_per_cu > kMaxBlocksPerCu) return false;
     if (t.stats < 0 || t.stats > 1 || t.loop < 0 || t.loop > 4) return false;
     if (t.bin_directions < 0 || t.bin_directions > 1) return false;
@@ -1288,7 +1351,7 @@ static int launch_trace3(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStr
 template <int SL, bool BATCHED>
 static int launch_trace2(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
-    return T.refill == 8 ? launch_trace3<SL, 8, BATCHED>(A, T, s) : launch_trace3<SL, 16, BATCHED>(A, T, s);
+    return T.refill == 16 ? launch_trace3<SL, 16, BATCHED>(A, T, s) : launch_trace3<SL, 28, BATCHED>(A, T, s);
 }
 
 // two-level scenes: the one-fetch loop only
@@ -1302,7 +1365,7 @@ static int launch_trace_inst2(const TraceArgs &A, const rtsdf_trace_tuning &T, h
 template <int SL>
 static int launch_trace_inst1(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
-    return T.refill == 8 ? launch_trace_inst2<SL, 8>(A, T, s) : launch_trace_inst2<SL, 16>(A, T, s);
+    return T.refill == 16 ? launch_trace_inst2<SL, 16>(A, T, s) : launch_trace_inst2<SL, 28>(A, T, s);
 }
 
 static int launch_trace_inst(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
@@ -1325,9 +1388,9 @@ static int launch_trace_wide2(const TraceArgs &A, const rtsdf_trace_tuning &T, h
 static int launch_trace_wide(const TraceArgs &A, const rtsdf_trace_tuning &T, hipStream_t s)
 {
     switch (T.stack_lds) {
-    case 12: return T.refill == 8 ? launch_trace_wide2<12, 8>(A, T, s) : launch_trace_wide2<12, 16>(A, T, s);
-    case 24: return T.refill == 8 ? launch_trace_wide2<24, 8>(A, T, s) : launch_trace_wide2<24, 16>(A, T, s);
-    default: return T.refill == 8 ? launch_trace_wide2<16, 8>(A, T, s) : launch_trace_wide2<16, 16>(A, T, s);
+    case 12: return T.refill == 16 ? launch_trace_wide2<12, 16>(A, T, s) : launch_trace_wide2<12, 28>(A, T, s);
+    case 24: return T.refill == 16 ? launch_trace_wide2<24, 16>(A, T, s) : launch_trace_wide2<24, 28>(A, T, s);
+    default: return T.refill == 16 ? launch_trace_wide2<16, 16>(A, T, s) : launch_trace_wide2<16, 28>(A, T, s);
     }
 }
 
@@ -1365,7 +1428,7 @@ static const rtsdf_trace_tuning &tuning_for(const rtsdf_scene *sc)
 // launch writes besides its outputs lives here, so launches with separate
 // workspaces can run concurrently, on one scene too.
 static size_t trace_lanes_max() { return (size_t)num_cus() * kMaxBlocksPerCu * kTraceWaves * kWave; }
-static size_t dirs_bytes() { return (size_t)num_cus() * kMaxBlocksPerCu * kTraceWaves * kTileRays * sizeof(float4); }
+static size_t dirs_bytes() { return (size_t)num_cus() * kMaxBlocksPerCu * kTraceWaves * 2 * kTileRays * sizeof(float4); }
 static size_t spill_bytes() { return trace_lanes_max() * (kMaxStackDepth - kMinShortStack) * sizeof(int32_t); }
 static size_t trace_ws_bytes() { return 256 + dirs_bytes() + spill_bytes(); }
 static float4 *ws_dirs(void *ws) { return reinterpret_cast<float4 *>(static_cast<char *>(ws) + 256); }

@@ -99,7 +99,7 @@ def test_host_validation(R):
     sp.penumbra, sp.jitter_scale = 1, -1.0  # negative jitter scale with a jitter array
     assert L.rtsdf_shadow_ex(fine, dummy, dummy, 4, C.byref(sp), dummy, dummy, None) == R.EINVAL
     assert L.rtsdf_shadow_ex(fine, dummy, dummy, 4, None, None, dummy, None) == R.EINVAL
-    for bad in (dict(refill=3), dict(loop=5), dict(loop=-1), dict(stack_lds=20), dict(bin_directions=5), dict(blocks_per_cu=-1),
+    for bad in (dict(refill=8), dict(loop=5), dict(loop=-1), dict(stack_lds=20), dict(bin_directions=5), dict(blocks_per_cu=-1),
                 dict(blocks_per_cu=9), dict(tile_texels=48), dict(tile_texels=0), dict(bvh_width=3),
                 dict(bvh_width=8)):
         t = R.TraceTuning(**{**R.rtsdf_trace_config_get().as_dict(), **bad})
@@ -142,8 +142,8 @@ def test_host_validation(R):
     assert L.rtsdf_scene_enable_rebuild(None, None) == R.EINVAL
     assert L.rtsdf_scene_rebuild(None, dummy, None) == R.EINVAL
     default = R.rtsdf_trace_config_get().as_dict()
-    prev = R.rtsdf_trace_config(refill=8, stack_lds=24)
-    assert prev.as_dict() == default and R.rtsdf_trace_config_get().refill == 8
+    prev = R.rtsdf_trace_config(refill=16, stack_lds=24)
+    assert prev.as_dict() == default and R.rtsdf_trace_config_get().refill == 16
     R.rtsdf_trace_config(**default)
     assert R.rtsdf_select_workspace_size(128) >= (128 ** 3 // 1024) * 4
 

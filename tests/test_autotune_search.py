@@ -16,7 +16,7 @@ def AT():
 
 def test_descent_finds_separable_minimum_and_tries_every_value(AT):
     space = AT.SPACE
-    best_vals = {"blocks_per_cu": 4, "tile_texels": 32, "refill": 8, "stack_lds": 16, "bin_directions": 1, "loop": 3,
+    best_vals = {"blocks_per_cu": 4, "tile_texels": 32, "refill": 16, "stack_lds": 16, "bin_directions": 1, "loop": 3,
                  "bvh_width": 4}
 
     def cost(t):

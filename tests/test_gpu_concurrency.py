@@ -96,7 +96,7 @@ def test_scene_tuning_is_per_scene_and_keeps_results(R):
     torch.cuda.synchronize()
     ref = outputs(R, p)
     assert p.scene.tuning().as_dict() == default
-    for t in (dict(tile_texels=16, blocks_per_cu=3), dict(tile_texels=32, refill=8, stack_lds=16),
+    for t in (dict(tile_texels=16, blocks_per_cu=3), dict(tile_texels=32, refill=16, stack_lds=16),
               dict(blocks_per_cu=5, bin_directions=0, loop=2)):
         say("scene tuning", t)
         p.scene.set_tuning(**t)

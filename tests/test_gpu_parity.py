@@ -378,10 +378,10 @@ def test_trace_tunings_agree_bitwise(R, case):
     w = workload(case)
     frames = range(3) if case == "tiny" else range(1)
     default = R.rtsdf_trace_config_get().as_dict()
-    settings = [dict(loop=0), dict(loop=1), dict(loop=2), dict(loop=3, refill=8), dict(loop=1, stack_lds=24),
+    settings = [dict(loop=0), dict(loop=1), dict(loop=2), dict(loop=3, refill=16), dict(loop=1, stack_lds=24),
                 dict(loop=2, stack_lds=16, bin_directions=0), dict(loop=2, blocks_per_cu=2),
                 dict(tile_texels=16, blocks_per_cu=3), dict(tile_texels=32, blocks_per_cu=5, stack_lds=16),
-                dict(blocks_per_cu=4, refill=8, tile_texels=16), dict(loop=4), dict(loop=4, refill=8, stack_lds=16),
+                dict(blocks_per_cu=4, refill=16, tile_texels=16), dict(loop=4), dict(loop=4, refill=16, stack_lds=16),
                 dict(loop=4, tile_texels=16, blocks_per_cu=3, bin_directions=0)]
     try:
         say("tunings", case, "default", default)
