@@ -508,20 +508,27 @@ __device__ __forceinline__ void node4_step_regs(const RaySetup &R, float4 a, flo
     v3 = c3;
 }
 
+// Lanes whose ray is finished (or that have none): a ballot of each compare, combined on the scalar unit (a
+// ballot of the combined condition would first be materialised lane by lane).
+__device__ __forceinline__ uint64_t wave_done(bool busy, int node, int tri_cur, int tri_end)
+{
+    return ~__builtin_amdgcn_ballot_w64(busy) |
+           (__builtin_amdgcn_ballot_w64(node == kDone) & __builtin_amdgcn_ballot_w64(tri_cur >= tri_end));
+}
+
 // Same decisions as node_step, written as selects: the caller performs the
 // (at most one) push and the (at most one) pop after the lane's work of the
 // iteration, so every lane shares one copy of the stack code.
-__device__ __forceinline__ void node_decide(bool h0, float t0, bool h1, float t1, int4 m, int &node, int &tri_cur,
+__device__ __forceinline__ void node_decide(bool h0, bool h1, bool first0, int4 m, int &node, int &tri_cur,
                                             int &tri_end, bool &push, int &push_val, bool &pop)
 {
     const bool any = h0 || h1, both = h0 && h1;
-    const bool first0 = h0 && (!h1 || t0 <= t1);
     const int near = first0 ? m.x : m.y, far = first0 ? m.y : m.x;
     const bool near_leaf = any && near < 0;
-    if (near_leaf) {
-        tri_cur = leaf_first(near);
-        tri_end = tri_cur + leaf_count(near);
-    }
+    // a leaf child's triangles become the lane's range; otherwise the range is left empty (the lane is idle,
+    // so its range is empty already)
+    tri_cur = leaf_first(near);
+    tri_end = tri_cur + (near_leaf ? leaf_count(near) : 0);
     // next: the nearer internal child; after a leaf child, the other hit child; else pop
     push = both && !near_leaf;
     push_val = far;
@@ -536,9 +543,10 @@ __device__ __forceinline__ void node_step_regs(const RaySetup &R, float4 a, floa
     float t0, t1, e0, e1;
     const bool h0 = box_hit2(R, a.x, a.y, a.z, a.w, z.x, z.y, tbest, t0, e0);
     const bool h1 = box_hit2(R, b.x, b.y, b.z, b.w, z.z, z.w, tbest, t1, e1);
-    // equal entries (the origin inside both boxes): the child the ray leaves first first
-    const float k0 = t0 == t1 ? e0 : t0, k1 = t0 == t1 ? e1 : t1;
-    node_decide(h0, k0, h1, k1, m, node, tri_cur, tri_end, push, push_val, pop);
+    // the nearer entry first; equal entries (the origin inside both boxes): the child the ray leaves first
+    // (bitwise, so the compiler keeps it branch-free)
+    const bool second = h1 & ((t1 < t0) | ((t1 == t0) & (e1 < e0)));
+    node_decide(h0, h1, h0 & !second, m, node, tri_cur, tri_end, push, push_val, pop);
 }
 
 __device__ __forceinline__ void node_step_flat(const BvhView &S, const RaySetup &R, int &node, float tbest,
@@ -931,7 +939,7 @@ trace_persistent(TraceArgs A)
                     }
                     if (push) stack_push<SL>(stride, sp, stk, spill, push_val);
                     if (pop) node = stack_pop<SL>(stride, sp, stk, spill);
-                    const uint64_t done = __ballot(!busy || (node == kDone && tri_cur >= tri_end));
+                    const uint64_t done = wave_done(busy, node, tri_cur, tri_end);
                     if (__popcll(done) >= refill_at) break;
                 }
             } else if (LOOP == 4) {
@@ -1022,7 +1030,7 @@ trace_persistent(TraceArgs A)
                     if (pop) node = stack_pop<SL>(stride, sp, stk, spill);
                     // ---- a wavefront's worth of tests
                     if (qt - qh >= kWave) flush(kWave);
-                    const uint64_t done = __builtin_amdgcn_ballot_w64(!busy || (node == kDone && tri_cur >= tri_end));
+                    const uint64_t done = wave_done(busy, node, tri_cur, tri_end);
                     if (__popcll(done) >= refill_at) break;
                 }
                 // the rest of the queue (the finished rays' tests among them)
@@ -1051,7 +1059,7 @@ trace_persistent(TraceArgs A)
                     }
                     if (push) stack_push<SL>(stride, sp, stk, spill, push_val);
                     if (pop) node = stack_pop<SL>(stride, sp, stk, spill);
-                    const uint64_t done = __ballot(!busy || (node == kDone && tri_cur >= tri_end));
+                    const uint64_t done = wave_done(busy, node, tri_cur, tri_end);
                     if (__popcll(done) >= refill_at) break;
                 }
             } else {
@@ -1074,7 +1082,7 @@ trace_persistent(TraceArgs A)
                             node = stack_pop<SL>(stride, sp, stk, spill);
                         }
                     }
-                    const uint64_t done = __ballot(!busy || (node == kDone && tri_cur >= tri_end));
+                    const uint64_t done = wave_done(busy, node, tri_cur, tri_end);
                     if (__popcll(done) >= refill_at) break;
                 }
             }
