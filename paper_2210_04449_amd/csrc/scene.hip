@@ -22,7 +22,7 @@
 //     Computed in double precision from the float vertices on the device (at
 //     creation and at every refit); degenerate triangles get a map no ray hits.
 //
-// Build (host, at creation): binned surface-area heuristic (64 bins per axis),
+// Build (host, at creation): binned surface-area heuristic (256 bins per axis),
 // leaves of at most `leaf_size` references, depth capped (median splits below
 // kMaxBuildDepth) so the traversal stack of the tracer never overflows.
 // Large triangles are split into several *references* before the build (the
@@ -256,7 +256,7 @@ struct HostBuilder {
             });
             return build_split(b, e, mid, depth);
         }
-        constexpr int NB = 64;
+        constexpr int NB = 256;
         double best_cost = INFINITY;
         int best_axis = -1, best_bin = -1;
         for (int a = 0; a < 3; ++a) {
