@@ -248,7 +248,7 @@ def main():
         p.scene.set_tuning(**{**t, "stats": 1})
         p.trace(args.warmup + K)
         torch.cuda.synchronize()
-        c = p.trace_ws[8:72].view(torch.int64).cpu().tolist()
+        c = p.trace_ws[8:88].view(torch.int64).cpu().tolist()
         p.scene.set_tuning(**tuning)
         return c
     ctr = counters(tuning)
@@ -336,7 +336,7 @@ def main():
                         "run_nodes_per_ray": round(ctr[0] / max(ctr[2], 1), 2),
                         "run_tris_per_ray": round(ctr[1] / max(ctr[2], 1), 2),
                         "rays_counted": ctr[2], "wave_iterations": ctr[3] // 64, "refill_rounds": ctr[4] // 64,
-                        "tiles": ctr[6] // 64,
+                        "tiles": ctr[6] // 64, "tiles_started_early": ctr[8] // 64, "drain_rounds": ctr[9] // 64,
                         "empty_node_fraction": round(ctr[7] / max(ctr[0], 1), 4) if tuning["loop"] in (3, 4) else None,
                         "lane_work_fraction": round(ctr[5] / max(ctr[3], 1), 4) if tuning["loop"] >= 1 else None,
                         "bvh_nodes": info.nodes, "bvh_references": info.references, "bvh_max_depth": info.max_depth,

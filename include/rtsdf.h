@@ -441,8 +441,11 @@ int rtsdf_trace_accumulate(const rtsdf_scene *scene, rtsdf_grid coarse, const fl
  *                   of the workspace: node visits, triangle tests, rays,
  *                   traversal iterations x 64, refill rounds x 64, lane
  *                   iterations with work (loop >= 1), tiles x 64, node
- *                   visits entering neither child box (loop 3, 4)
- *                   (slower; for measurement only);
+ *                   visits entering neither child box (loop 3, 4), tiles
+ *                   started while rays of the previous one were still
+ *                   traced x 64, traversal rounds that waited for every
+ *                   lane before a next tile x 64 (slower; for measurement
+ *                   only);
  *   loop            0: two phases per iteration (walk nodes until every lane
  *                   holds a leaf, then test the leaves); 1: one unit of work
  *                   per lane per iteration (a triangle or a node); 2: as 1,

@@ -647,13 +647,15 @@ __global__ void trace_tile_prefix(const TraceScene *scenes, int n, int cap, int3
 // (STATS) also count into 64-bit counters at workspace offsets 8, 16, ...:
 // node visits, triangle tests, rays, traversal-loop iterations x 64, refill
 // rounds x 64, lane-iterations with work (LOOP 1 and 2), tiles x 64, node
-// visits that entered neither child box (LOOP 3).
+// visits that entered neither child box (LOOP 3), tiles started while lanes
+// were still busy x 64, traversal rounds that waited for every lane before a
+// next tile x 64.
 template <int SL, int REFILL, int LOOP, bool STATS, bool BATCHED, bool INST = false, bool WIDE = false>
 __global__ void __launch_bounds__(kTraceWaves * kWave) __attribute__((amdgpu_waves_per_eu(6, 8)))
 trace_persistent(TraceArgs A)
 {
     uint32_t st_nodes = 0, st_tris = 0, st_rays = 0, st_iters = 0, st_refills = 0, st_busy = 0, st_tiles = 0;
-    uint32_t st_empty = 0;
+    uint32_t st_empty = 0, st_early = 0, st_drains = 0;
     __shared__ int stack_mem[kTraceWaves * SL * kWave];
     __shared__ WaveTile tiles[kTraceWaves];
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -713,7 +715,10 @@ trace_persistent(TraceArgs A)
                 const int c = cur ^ 1, g = gnext;
                 gnext = -2;
                 const TraceScene &P = BATCHED ? A.scenes[sn] : A.one;
-                if (STATS) ++st_tiles;
+                if (STATS) {
+                    ++st_tiles;
+                    st_early += any_busy;
+                }
                 const int R = P.rays;
                 // q / R as a multiply-high: exact for q < kTileRays and R <= 64 (the error of the rounded-up
                 // reciprocal, q / 2^32, stays below the distance 1/R of q / R from the next integer)
@@ -832,6 +837,7 @@ trace_persistent(TraceArgs A)
             const bool early = !INST && cstate[cur ^ 1] < 0 &&
                                (gnext == -2 || (gnext >= 0 && (!BATCHED || scene_of(gnext) == cscene[cur])));
             const int refill_at = __builtin_amdgcn_readfirstlane(pool < nrays || early ? REFILL : kWave);
+            if (STATS) st_drains += refill_at == kWave && gnext != -1;  // every lane finishes before the next tile
             if (LOOP == 0) {
                 while (true) {
                     if (busy && leaf == kDone && node < 0 && node != kDone) {
@@ -1171,6 +1177,8 @@ trace_persistent(TraceArgs A)
         atomicAdd(&ctr[5], (unsigned long long)st_busy);
         atomicAdd(&ctr[6], (unsigned long long)st_tiles);
         atomicAdd(&ctr[7], (unsigned long long)st_empty);
+        atomicAdd(&ctr[8], (unsigned long long)st_early);
+        atomicAdd(&ctr[9], (unsigned long long)st_drains);
     }
 }
 

@@ -401,6 +401,34 @@ def test_trace_tunings_agree_bitwise(R, case):
         R.rtsdf_trace_config(**default)
 
 
+def test_two_tile_contexts_in_use(R):
+    """Instrumented room traces: a wavefront starts its next tile while rays of the last one are still in
+    flight (the two tile contexts), and with small tiles some rounds wait for every lane first (the next tile
+    must wait for a context still holding rays of the tile before); the state equals the plain run's."""
+    say("two tile contexts")
+    w = workload("room")
+    default = R.rtsdf_trace_config_get().as_dict()
+    try:
+        ref = run_gpu(R, w, range(1))
+        for t in (dict(), dict(tile_texels=16)):
+            R.rtsdf_trace_config(**{**default, **t, "stats": 1})
+            p = run_gpu(R, w, range(1))
+            ctr = p.trace_ws[8:88].view(torch.int64).cpu().tolist()
+            tiles, early, drains = ctr[6] // 64, ctr[8] // 64, ctr[9] // 64
+            print(t, "tiles", tiles, "started early", early, "drain rounds", drains)
+            assert ctr[2] == int(p.count.item()) * w.rays  # every ray traced once
+            assert 0.5 * tiles < early < tiles
+            if t:
+                assert drains > 0
+            assert torch.equal(p.fine_sdf, ref.fine_sdf) and torch.equal(p.state.u, ref.state.u)
+            assert torch.equal(p.state.hits, ref.state.hits) and torch.equal(p.state.arg_ray, ref.state.arg_ray)
+            p.close()
+            R.rtsdf_trace_config(**default)
+        ref.close()
+    finally:
+        R.rtsdf_trace_config(**default)
+
+
 def test_trace_room_sampled(R):
     say("trace room sampled, 8 frames")
     w = workload("room")
