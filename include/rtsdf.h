@@ -156,19 +156,30 @@ int rtsdf_jfa(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, float beta,
 int rtsdf_jfa_steps(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, const int32_t *steps, int32_t nsteps,
                     float beta, int32_t *dist2, float *coarse_sdf, rtsdf_stream stream);
 
-/* How the step-2 and step-1 passes stage their (8 + 2k)^3 block in LDS, per
- * grid size (the results are the same; only speed differs):
+/* Tuning of the jump flooding per grid size (the results are the same; only
+ * speed differs).
+ * How the step-2 and step-1 passes stage their (8 + 2k)^3 block in LDS:
  *   near_stage 0  automatic (the default): 2;
  *              1  the seed alone (the candidate's distance key is formed
  *                 from it: 4 B per entry, 4 integer instructions per
  *                 candidate);
  *              2  the pair (seed, |seed|^2 term) (8 B per entry, 2).
- * rtsdf_jfa_config sets it for grids of side n (a power of two in [8, 256];
- * EINVAL otherwise or for values outside the set); the setting is process
+ * The order in which the passes with step k >= 8 (2 bricks of 4^3 or more)
+ * hand bricks to wavefronts:
+ *   far_order  0  automatic (the default): 2;
+ *              1  slab order: consecutive bricks, so each XCD takes a slab of
+ *                 z-layers;
+ *              2  coset order: the bricks of one residue class of the brick
+ *                 coordinates modulo k / 4 (a class holds every candidate of
+ *                 its bricks) one class after another, so each brick is read
+ *                 into the L2 of one XCD only.
+ * rtsdf_jfa_config sets both for grids of side n (a power of two in [8, 256];
+ * EINVAL otherwise or for values outside the sets); the setting is process
  * state read at each rtsdf_jfa / rtsdf_jfa_steps call (calls that overlap
  * with a change may see either).  rtsdf_jfa_config_get reads it back. */
 typedef struct rtsdf_jfa_tuning {
     int32_t near_stage;
+    int32_t far_order;
 } rtsdf_jfa_tuning;
 int rtsdf_jfa_config(int32_t n, const rtsdf_jfa_tuning *t);
 int rtsdf_jfa_config_get(int32_t n, rtsdf_jfa_tuning *t);

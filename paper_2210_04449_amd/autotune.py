@@ -17,9 +17,10 @@ batch) with HIP events and keeps the fastest.  The knobs:
   scenes that refit or stay static; batches and device-rebuilt or two-level
   scenes trace two-wide and skip this knob).
 
-For a Pipeline the jump flooding's near-pass staging (``rtsdf_jfa_config``:
-seeds alone or seed pairs in LDS) is timed too and the faster one kept for
-the pipeline's coarse grid size.
+For a Pipeline the jump flooding's two knobs (``rtsdf_jfa_config``: the
+near-pass staging, seeds alone or seed pairs in LDS; the far-pass brick order,
+slab or coset order) are timed too, all four combinations, and the fastest is
+kept for the pipeline's coarse grid size.
 
 The search is coordinate descent from the target's current tuning: each knob
 in turn takes each of its values with the others fixed, a change is kept when
@@ -191,7 +192,7 @@ def tune(target, reps: int = 2, space: dict = SPACE, cache: str | None = DEFAULT
         best = entries[key]["tuning"]
         apply(best)
         if "jfa_near_stage" in entries[key]:
-            R.rtsdf_jfa_config(target.nc, entries[key]["jfa_near_stage"])
+            R.rtsdf_jfa_config(target.nc, entries[key]["jfa_near_stage"], entries[key].get("jfa_far_order", 0))
         return {"tuning": best, "ms": entries[key]["ms"], "trials": [], "cached": True, "key": key,
                 "jfa": entries[key].get("jfa")}
 
@@ -208,24 +209,25 @@ def tune(target, reps: int = 2, space: dict = SPACE, cache: str | None = DEFAULT
     if cache:
         entries[key] = {"tuning": best, "ms": ms}
         if jfa is not None:
-            entries[key].update(jfa_near_stage=jfa["near_stage"], jfa=jfa)
+            entries[key].update(jfa_near_stage=jfa["near_stage"], jfa_far_order=jfa["far_order"], jfa=jfa)
         save_cache(entries, cache)
     return {"tuning": best, "ms": ms, "trials": trials, "cached": False, "key": key, "jfa": jfa}
 
 
 def tune_jfa(p, reps: int = 3) -> dict:
-    """Time the jump flooding of pipeline `p` with each near-pass staging (rtsdf_jfa_config: seeds alone or seed
-    pairs; the results are the same) and keep the faster for grids of p's coarse size (process-wide setting).
-    Each timed run voxelizes first, the same work for both."""
+    """Time the jump flooding of pipeline `p` with each near-pass staging (seeds alone or seed pairs) and each
+    far-pass brick order (slab or coset order) -- rtsdf_jfa_config; the results are the same -- and keep the
+    fastest pair for grids of p's coarse size (process-wide setting).  Each timed run voxelizes first, the same
+    work for every pair."""
     n = p.nc
     times = {}
-    for stage in (1, 2):
-        R.rtsdf_jfa_config(n, stage)
+    for stage, order in itertools.product((1, 2), (1, 2)):
+        R.rtsdf_jfa_config(n, stage, order)
 
         def run():
             p.voxelize()
             p.jfa()
-        times[stage] = _time(run, reps)
-    best = min(times, key=times.get)
-    R.rtsdf_jfa_config(n, best)
-    return {"near_stage": best, "ms": times}
+        times[(stage, order)] = _time(run, reps)
+    stage, order = min(times, key=times.get)
+    R.rtsdf_jfa_config(n, stage, order)
+    return {"near_stage": stage, "far_order": order, "ms": {f"{a},{b}": t for (a, b), t in times.items()}}

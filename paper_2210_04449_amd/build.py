@@ -16,10 +16,18 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # no packed fp32 VALU instructions: the kernels are written for one fp32 operation per lane and instruction
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+]
+
+# The translation units and their extra flags.  The JFA's device code holds no NaNs (its keys are non-negative
+# denormals or a large finite value, its coarse SDF finite), and compiled without NaN semantics a minimum of two
+# keys is one v_min_f64 instead of a v_max_f64 that quiets signalling NaNs plus the v_min_f64.  Host code keeps
+# NaN semantics (its argument checks test for NaN).
+UNITS = [
+    ("rtsdf_lib.hip", []),
+    ("jfa.hip", ["-Xarch_device", "-fno-honor-nans"]),
 ]
 
 
@@ -28,16 +36,38 @@ def sources() -> list[str]:
                   if f.endswith((".hip", ".hpp")))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source (one translation unit) into librtsdf.so."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), os.path.join(SRC_DIR, "rtsdf_lib.hip"), "-o", tmp]
+def _run(cmd: list[str], verbose: bool) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed to build librtsdf.so")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every translation unit (in parallel) and link them into librtsdf.so."""
+    objs, procs = [], []
+    for src, extra in UNITS:
+        obj = os.path.join(SRC_DIR, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-c", os.path.join(SRC_DIR, src),
+               "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        objs.append(obj)
+    failed = False
+    for cmd, pr in procs:
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(" ".join(cmd) + "\n" + out)
+            failed = True
+    if failed:
+        raise RuntimeError("hipcc failed to build librtsdf.so")
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+    for o in objs:
+        os.remove(o)
     os.replace(tmp, LIB)
     return LIB
 

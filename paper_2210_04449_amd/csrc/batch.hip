@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "jfa_device.hpp"
 
 namespace rtsdf {
 
@@ -134,7 +135,7 @@ __global__ void __launch_bounds__(KIND == kJfaNear2 || KIND == kJfaFinal ? 512 :
         const int64_t e = (int64_t)blk * blockDim.x + threadIdx.x;
         if (e < nvox) jfa_to_bricks_body(st.src, st.dst, st.n, st.logn, e);
     } else if (KIND == kJfaFarBricks || KIND == kJfaFarLinear) {
-        jfa_far_body<false, KIND == kJfaFarLinear>(st.src, st.dst, st.n, st.logn, st.kb, blk, nblk, neg2);
+        jfa_far_body<false, KIND == kJfaFarLinear>(st.src, st.dst, st.n, st.logn, st.kb, blk, nblk, neg2, 0);
     } else if (KIND == kJfaNear2) {
         jfa_near_body<2, true, false>(st.src, st.dst, st.n, st.logn, nullptr, nullptr, 0.f, 0.f, blk, nblk, neg2);
     } else {

@@ -1,143 +1,22 @@
-// 3D jump flooding and the coarse SDF (paper Sec. 2.1; the jump flooding of
-// Rong & Tan extended to three dimensions).
+// The JFA's translation unit: its kernels, the pass schedule and the
+// rtsdf_jfa* entry points (the passes themselves are in jfa_device.hpp).
 //
-// Pass k (k = n/2, ..., 1) gives every voxel the best of its own seed and the
-// seeds of the 26 voxels at offsets k (i, j, l), i, j, l in {-1, 0, 1}: the
-// smallest squared distance, ties to the lowest linear seed index.  After the
-// last pass the coarse SDF is c = h sqrt(D^2) - beta.
-//
-// Layout between passes (internal): the grid is cut into 4x4x4 bricks, one
-// wavefront per brick; brick b = bx + B (by + B bz) (B = n / 4) stores its 64
-// voxels contiguously (lane = lx + 4 ly + 16 lz), so every candidate read of a
-// wavefront is one coalesced 256-byte block.  A seed is packed as
-// x | y << 8 | z << 16 (0xFFFFFFFF = none); packed order equals linear-index
-// order, so ties compare the packed word directly.
-//
-// Candidate key: the 64-bit word (hi << 32 | low), read as a float64, where hi
-// orders the candidates by D^2 and low increases with the packed seed.  Its
-// exponent field is zero (hi < 2^20), so it is a non-negative denormal whose
-// order is the integer order, and one v_min_f64 keeps the better of two keys.
-// A missing seed gets bits 0x7F000000 in the high word (a large finite
-// double) and always loses.  Two key forms, both from byte dot products:
-// * 7-bit (far passes, n <= 128): hi = D^2.  The voxel constant C holds
-//   128 - x, 128 - y, 128 - z in its bytes, so u = S + C holds (s - x) + 128
-//   etc. in [1, 255] per byte without carries: u is the key's low word
-//   (S = u - C), u ^ 0x808080 the signed byte differences, and one
-//   v_dot4_i32_i8 squares and sums them.
-// * byte-dot (every pass at n = 256, the near passes at every n): hi =
-//   |S|^2 - 2 S.p + 2^18 = D^2 - |p|^2 + 2^18 for the voxel p, low = S: two
-//   v_dot4_u32_u8 and one 24-bit multiply-add, or, with w(S) = |S|^2 staged
-//   beside each seed, one of each.
-//
-// Steps k >= 4 read whole neighbour bricks straight from global memory (an
-// axis offset that would leave the grid reads the brick with offset 0 on that
-// axis, a candidate the set already holds).  Steps 2 and 1 stage an (8 + 2k)^3 block of voxels (eight bricks
-// plus halo) in LDS; candidates then sit at compile-time LDS offsets and
-// out-of-grid halo entries are empty.  The k = 1 pass writes the final seeds,
-// D^2 and c in the caller's linear layout.
+// Built apart from the rest of the library, with its device code compiled on
+// the assumption that no float is a NaN: the only floating-point values here
+// are the candidate keys (non-negative denormals, or a large finite value for
+// a missing seed) and the finite coarse SDF.  Under that assumption the
+// minimum of two keys is one v_min_f64; otherwise every new key first passes
+// through a v_max_f64 that would quiet a signalling NaN, one more VALU
+// instruction per candidate.  Host code is compiled as usual.
 #include <atomic>
 
-#include "common.hpp"
+// The library's error word is defined in its main translation unit; this unit raises no errors, and renaming its
+// copy keeps the two units' device variables apart.
+#define g_error_word g_error_word_jfa_unit
+#include "jfa_device.hpp"
+#undef g_error_word
 
 namespace rtsdf {
-
-constexpr uint32_t kNoSeed = 0xFFFFFFFFu;
-
-typedef short jfa_short2 __attribute__((ext_vector_type(2)));
-
-// Voxel-side constants.  a: the 7-bit key's C = (128 - x) | (128 - y) << 8 | (128 - z) << 16 (n <= 128);
-// p = x | y << 8 | z << 16 and pp = |p|^2 for the byte-dot key; neg2 = -2, a kernel argument (a constant
-// multiplier would be strength-reduced to a shift and a subtraction instead of one 24-bit multiply-add).
-struct JfaPos {
-    uint32_t a, p;
-    int32_t pp, neg2;
-};
-
-__device__ __forceinline__ JfaPos jfa_pos(int x, int y, int z, int neg2)
-{
-    JfaPos P;
-    P.a = (uint32_t)(128 - x) | ((uint32_t)(128 - y) << 8) | ((uint32_t)(128 - z) << 16);
-    P.p = (uint32_t)x | ((uint32_t)y << 8) | ((uint32_t)z << 16);
-    P.pp = x * x + y * y + z * z;
-    P.neg2 = neg2;
-    return P;
-}
-
-// 7-bit key (n <= 128): high word D^2 from the signed byte differences, low word u = S + C.
-__device__ __forceinline__ double jfa_key7(JfaPos P, uint32_t s)
-{
-    const uint32_t low = s + P.a;
-    const int d = (int)(low ^ 0x00808080u);
-    // the missing-seed bits have zero low 24 bits and D^2 < 2^24, so adding them is or-ing them
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_sdot4(d, d, (int)(s & 0x7F000000u), false);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)low);
-}
-
-// Byte-dot key (n <= 256): high word |S|^2 - 2 S.p + 2^18 = D^2 - |p|^2 + 2^18 (in [2^18 - 3 * 255^2,
-// 2^18 + 3 * 255^2], the same order as D^2 for one voxel) plus the missing-seed bits, low word the seed.  w(S)
-// = |S|^2 + missing bits depends on the seed alone, so staged seeds carry it; the 2^18 enters as -2^17 in
-// the accumulator of S.p (S.p - 2^17 in [-2^17, 2^16): a 24-bit operand of the multiply-add by -2).
-__device__ __forceinline__ uint32_t jfa_w(uint32_t s)
-{
-    return __builtin_amdgcn_udot4(s, s, s & 0x7F000000u, false);
-}
-
-__device__ __forceinline__ double jfa_keyd_w(JfaPos P, uint32_t s, uint32_t w)
-{
-    const int sp = (int)__builtin_amdgcn_udot4(s, P.p, 0xFFFE0000u, false);  // S.p - 2^17 (wraps)
-    const uint32_t hi = (uint32_t)(__mul24(sp, P.neg2) + (int)w);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)s);
-}
-
-__device__ __forceinline__ double jfa_keyd(JfaPos P, uint32_t s) { return jfa_keyd_w(P, s, jfa_w(s)); }
-
-__device__ __forceinline__ uint32_t key_hi(double k) { return (uint32_t)(__builtin_bit_cast(uint64_t, k) >> 32); }
-
-// the packed seed of the best key (kNoSeed if no candidate had one); BYTEDOT: which key formula made it
-template <bool BYTEDOT>
-__device__ __forceinline__ uint32_t key_seed(JfaPos P, double k)
-{
-    if (key_hi(k) >= 0x7F000000u) return kNoSeed;
-    const uint32_t low = (uint32_t)__builtin_bit_cast(uint64_t, k);
-    return BYTEDOT ? low : low - P.a;
-}
-
-// D^2 of a byte-dot key with a seed
-__device__ __forceinline__ uint32_t keyd_d2(JfaPos P, double k) { return key_hi(k) - 0x40000u + (uint32_t)P.pp; }
-
-__device__ __forceinline__ uint32_t pack_linear(int32_t s, int logn)
-{
-    if (s < 0) return kNoSeed;
-    const uint32_t m = (1u << logn) - 1u;
-    const uint32_t u = (uint32_t)s;
-    return (u & m) | (((u >> logn) & m) << 8) | ((u >> (2 * logn)) << 16);
-}
-
-__device__ __forceinline__ int32_t unpack_linear(uint32_t p, int logn)
-{
-    if (p == kNoSeed) return -1;
-    return (int32_t)((p & 0xFFu) | (((p >> 8) & 0xFFu) << logn) | ((p >> 16) << (2 * logn)));
-}
-
-// Spread consecutive workgroups of one XCD over a contiguous range (the
-// dispatcher deals workgroups to the 8 XCDs round-robin; each XCD has its own
-// L2, so neighbouring bricks should land on the same one).
-__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks)
-{
-    if ((nblocks & 7u) != 0) return bid;
-    return (bid & 7u) * (nblocks >> 3) + (bid >> 3);
-}
-
-// linear caller layout -> packed brick layout
-__device__ __forceinline__ void jfa_to_bricks_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
-                                                   int logn, int64_t e)
-{
-    const int B = n >> 2;
-    const int b = (int)(e >> 6), l = (int)(e & 63);
-    const int bx = b % B, by = (b / B) % B, bz = b / (B * B);
-    const int x = bx * 4 + (l & 3), y = by * 4 + ((l >> 2) & 3), z = bz * 4 + (l >> 4);
-    dst[e] = (int32_t)pack_linear(src[x + n * (y + n * z)], logn);
-}
 
 __global__ void __launch_bounds__(256) jfa_to_bricks(const int32_t *__restrict__ src, int32_t *__restrict__ dst,
                                                      int n, int logn)
@@ -145,131 +24,11 @@ __global__ void __launch_bounds__(256) jfa_to_bricks(const int32_t *__restrict__
     jfa_to_bricks_body(src, dst, n, logn, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// The distinct offsets along one axis of a pass with step k = 4 kb >= 4 (brick coordinate c, in units of
-// the stride st).  An offset that would leave the grid is replaced by 0: the brick read is then the candidate
-// whose offset on that axis is 0, which the set already holds, and a duplicate cannot change the minimum.  So
-// an axis where one side leaves the grid (at most one can, unless kb = B/2, where exactly one does) has two
-// distinct offsets, {0, the side that stays}, and an axis where neither does has three.
-template <int N>
-__device__ __forceinline__ void jfa_axis(int c, int kb, int st, int (&d)[N])
-{
-    if (N == 3) {
-        d[0] = -st;
-        d[1] = 0;
-        d[N - 1] = st;
-    } else {
-        d[0] = 0;
-        d[N - 1] = c >= kb ? -st : st;
-    }
-}
-
-// The candidates of brick b: NX * NY * NZ distinct neighbour bricks, every read in the grid.
-template <bool WIDE, bool LINEAR_IN, int NX, int NY, int NZ>
-__device__ __forceinline__ void jfa_far_brick(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
-                                              int logn, int kb, int b, int lane, int neg2)
-{
-    constexpr int NCAND = NX * NY * NZ;
-    const int logB = logn - 2, B = 1 << logB;
-    const int bx = b & (B - 1), by = (b >> logB) & (B - 1), bz = b >> (2 * logB);
-    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
-    const JfaPos P = jfa_pos(bx * 4 + lx, by * 4 + ly, bz * 4 + lz, neg2);
-    double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
-    uint32_t cand[NCAND];
-    if (!LINEAR_IN) {
-        int dx[NX], dy[NY], dz[NZ];
-        jfa_axis(bx, kb, kb, dx);
-        jfa_axis(by, kb, kb << logB, dy);
-        jfa_axis(bz, kb, kb << (2 * logB), dz);
-        // raw buffer loads: the lane's byte offset is one vector register shared by all the reads, the brick's
-        // byte offset a scalar (every read lies in the n^3-word buffer; gfx9 descriptor word 3)
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(src), (short)0, (n * n * n) * 4, 0x00020000);
-#pragma unroll
-        for (int o = 0; o < NCAND; ++o) {
-            const int off = (b + dx[o % NX] + dy[(o / NX) % NY] + dz[o / (NX * NY)]) << 8;
-            cand[o] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, lane * 4, off, 0);
-        }
-    } else {
-        int dx[NX], dy[NY], dz[NZ];
-        jfa_axis(bx, kb, kb, dx);
-        jfa_axis(by, kb, kb, dy);
-        jfa_axis(bz, kb, kb, dz);
-#pragma unroll
-        for (int o = 0; o < NCAND; ++o) {
-            const int x = (bx + dx[o % NX]) * 4 + lx, y = (by + dy[(o / NX) % NY]) * 4 + ly;
-            const int z = (bz + dz[o / (NX * NY)]) * 4 + lz;
-            cand[o] = pack_linear(src[x + (y << logn) + (z << (2 * logn))], logn);
-        }
-    }
-#pragma unroll
-    for (int o = 0; o < NCAND; ++o) best = __builtin_fmin(best, WIDE ? jfa_keyd(P, cand[o]) : jfa_key7(P, cand[o]));
-    dst[(int64_t)b * 64 + lane] = (int32_t)key_seed<WIDE>(P, best);
-}
-
-// One pass with step k >= 4 (a multiple of the brick size) for the four
-// bricks of workgroup `blk` of `nblk`.  LINEAR_IN: the source is the caller's
-// linear index array (first pass only).  Each wavefront (one brick) takes the
-// unrolled body for its own distinct-offset counts per axis: a wave-uniform
-// branch, so every body keeps all its reads in flight together.
-template <bool WIDE, bool LINEAR_IN>
-__device__ __forceinline__ void jfa_far_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
-                                             int logn, int kb, uint32_t blk, uint32_t nblk, int neg2)
-{
-    const int logB = logn - 2, B = 1 << logB;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int b = (int)xcd_remap(blk, nblk) * 4 + wave;
-    const int bx = b & (B - 1), by = (b >> logB) & (B - 1), bz = b >> (2 * logB);
-    const auto two = [&](int c) { return c < kb || c + kb >= B; };  // one side leaves the grid
-    switch ((two(bx) ? 1 : 0) | (two(by) ? 2 : 0) | (two(bz) ? 4 : 0)) {
-    case 0: jfa_far_brick<WIDE, LINEAR_IN, 3, 3, 3>(src, dst, n, logn, kb, b, lane, neg2); break;
-    case 1: jfa_far_brick<WIDE, LINEAR_IN, 2, 3, 3>(src, dst, n, logn, kb, b, lane, neg2); break;
-    case 2: jfa_far_brick<WIDE, LINEAR_IN, 3, 2, 3>(src, dst, n, logn, kb, b, lane, neg2); break;
-    case 3: jfa_far_brick<WIDE, LINEAR_IN, 2, 2, 3>(src, dst, n, logn, kb, b, lane, neg2); break;
-    case 4: jfa_far_brick<WIDE, LINEAR_IN, 3, 3, 2>(src, dst, n, logn, kb, b, lane, neg2); break;
-    case 5: jfa_far_brick<WIDE, LINEAR_IN, 2, 3, 2>(src, dst, n, logn, kb, b, lane, neg2); break;
-    case 6: jfa_far_brick<WIDE, LINEAR_IN, 3, 2, 2>(src, dst, n, logn, kb, b, lane, neg2); break;
-    default: jfa_far_brick<WIDE, LINEAR_IN, 2, 2, 2>(src, dst, n, logn, kb, b, lane, neg2); break;
-    }
-}
-
 template <bool WIDE, bool LINEAR_IN>
 __global__ void __launch_bounds__(256) jfa_far(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
-                                               int logn, int kb, int neg2)
+                                               int logn, int kb, int neg2, int coset)
 {
-    jfa_far_body<WIDE, LINEAR_IN>(src, dst, n, logn, kb, blockIdx.x, gridDim.x, neg2);
-}
-
-// The first pass of plain jump flooding (step n/2) from the caller's linear seeds.  At that step one side of
-// every axis leaves the grid, so a voxel's distinct candidates are its own seed and the seeds at p XOR n/2 on
-// any subset of the axes: the same eight voxels for all eight members of such an orbit, and brick b's
-// candidates sit at the same lane in the bricks b XOR B/2 on those axes.  A workgroup of eight wavefronts
-// takes one orbit of bricks: each wavefront stages its brick once in LDS, and every lane keys the eight staged
-// candidates of its voxel (instead of each wavefront reading all eight bricks from memory).
-template <bool WIDE>
-__device__ __forceinline__ void jfa_first_orbit_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst,
-                                                     int n, int logn, int neg2, uint32_t blk_id, uint32_t nblk)
-{
-    __shared__ uint32_t tile[8][kWave];
-    const int logB = logn - 2, logH = logB - 1, H = 1 << logH;  // orbits: H^3 workgroups, H = B / 2
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int g = (int)xcd_remap(blk_id, nblk);
-    const int gx = g & (H - 1), gy = (g >> logH) & (H - 1), gz = g >> (2 * logH);
-    // this wavefront's brick: the orbit member (wave bit 0: +B/2 in x, bit 1: in y, bit 2: in z)
-    const int bx = gx + ((wave & 1) << logH), by = gy + (((wave >> 1) & 1) << logH), bz = gz + ((wave >> 2) << logH);
-    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
-    const int x = bx * 4 + lx, y = by * 4 + ly, z = bz * 4 + lz;
-    tile[wave][lane] = pack_linear(src[x + (y << logn) + (z << (2 * logn))], logn);
-    __syncthreads();
-    const JfaPos P = jfa_pos(x, y, z, neg2);
-    double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-        const uint32_t c = tile[wave ^ o][lane];
-        best = __builtin_fmin(best, WIDE ? jfa_keyd(P, c) : jfa_key7(P, c));
-    }
-    const int b = bx | (by << logB) | (bz << (2 * logB));
-    dst[((int64_t)b << 6) | lane] = (int32_t)key_seed<WIDE>(P, best);
+    jfa_far_body<WIDE, LINEAR_IN>(src, dst, n, logn, kb, blockIdx.x, gridDim.x, neg2, coset);
 }
 
 template <bool WIDE>
@@ -277,64 +36,6 @@ __global__ void __launch_bounds__(512) jfa_first_orbit(const int32_t *__restrict
                                                        int n, int logn, int neg2)
 {
     jfa_first_orbit_body<WIDE>(src, dst, n, logn, neg2, blockIdx.x, gridDim.x);
-}
-
-// One pass with step K in {1, 2}: eight bricks (an 8^3 block) per workgroup,
-// staged with a K-voxel halo in LDS.  FINAL writes the caller's outputs.
-template <int K, bool PAIRS, bool FINAL>
-__device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
-                                              int logn, int32_t *__restrict__ dist2, float *__restrict__ sdf, float h,
-                                              float beta, uint32_t blk_id, uint32_t nblk, int neg2)
-{
-    constexpr int T = 8 + 2 * K;
-    // PAIRS: each entry staged as the pair (s, w(s)); else the seed alone (w formed per candidate)
-    __shared__ uint32_t tile[(PAIRS ? 2 : 1) * T * T * T];
-    uint2 *tile2 = reinterpret_cast<uint2 *>(tile);
-    // n is a power of two: block and brick coordinates are bit fields (shifts and masks, no divisions)
-    const int logB = logn - 2, logTB = logn - 3, TB = 1 << logTB;  // 8^3 blocks per axis
-    const int blk = (int)xcd_remap(blk_id, nblk);
-    const int tx0 = (blk & (TB - 1)) * 8, ty0 = ((blk >> logTB) & (TB - 1)) * 8, tz0 = (blk >> (2 * logTB)) * 8;
-    for (int i = threadIdx.x; i < T * T * T; i += blockDim.x) {
-        const int x = tx0 - K + i % T, y = ty0 - K + (i / T) % T, z = tz0 - K + i / (T * T);
-        uint32_t v = kNoSeed;
-        if ((unsigned)x < (unsigned)n && (unsigned)y < (unsigned)n && (unsigned)z < (unsigned)n) {
-            const int b = (x >> 2) | ((y >> 2) << logB) | ((z >> 2) << (2 * logB));
-            v = (uint32_t)src[(b << 6) | (x & 3) | ((y & 3) << 2) | ((z & 3) << 4)];
-        }
-        if (PAIRS) tile2[i] = make_uint2(v, jfa_w(v));
-        else tile[i] = v;
-    }
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int lx = (wave & 1) * 4 + (lane & 3), ly = ((wave >> 1) & 1) * 4 + ((lane >> 2) & 3),
-              lz = (wave >> 2) * 4 + (lane >> 4);
-    const int x = tx0 + lx, y = ty0 + ly, z = tz0 + lz;
-    const JfaPos P = jfa_pos(x, y, z, neg2);
-    const int c = (lx + K) + T * ((ly + K) + T * (lz + K));
-    double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
-#pragma unroll
-    for (int o = 0; o < 27; ++o) {
-        const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-        const int e = c + K * (ox + T * (oy + T * oz));
-        best = __builtin_fmin(best, PAIRS ? jfa_keyd_w(P, tile2[e].x, tile2[e].y) : jfa_keyd(P, tile[e]));
-    }
-    if (!FINAL) {
-        const int b = (x >> 2) | ((y >> 2) << logB) | ((z >> 2) << (2 * logB));
-        dst[(b << 6) | (x & 3) | ((y & 3) << 2) | ((z & 3) << 4)] = (int32_t)key_seed<true>(P, best);
-    } else {
-        const uint32_t s = key_seed<true>(P, best);
-        const int idx = x | (y << logn) | (z << (2 * logn));  // n <= 256: below 2^24
-        if (s == kNoSeed) {
-            dst[idx] = -1;
-            dist2[idx] = INT32_MAX;
-            sdf[idx] = __builtin_inff();
-        } else {
-            const int d2 = (int)keyd_d2(P, best);
-            dst[idx] = unpack_linear(s, logn);
-            dist2[idx] = d2;
-            sdf[idx] = rn_sub(rn_mul(h, rn_sqrt((float)d2)), beta);
-        }
-    }
 }
 
 template <int K, bool PAIRS, bool FINAL>
@@ -347,7 +48,7 @@ __global__ void __launch_bounds__(512) jfa_near(const int32_t *__restrict__ src,
 
 template <bool WIDE, bool PAIRS>
 static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float beta, int32_t *dist2, float *sdf,
-                   const int32_t *steps, int m, hipStream_t s)
+                   const int32_t *steps, int m, int coset, hipStream_t s)
 {
     const int n = g.n, logn = ilog2(n);
     const int64_t nvox = (int64_t)n * n * n;
@@ -370,9 +71,9 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
                 if (i == 0 && k == n / 2)
                     jfa_first_orbit<WIDE><<<dim3(orbit_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, -2);
                 else if (i == 0)
-                    jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
+                    jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2, coset);
                 else
-                    jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
+                    jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2, coset);
             } else if (k == 2) {
                 jfa_near<2, PAIRS, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
                                                                                  0.f, 0.f, -2);
@@ -398,7 +99,7 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
             const int k = steps[i];
             int32_t *dst = bufs[next];
             if (k >= 4) {
-                jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
+                jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2, coset);
             } else if (k == 2) {
                 jfa_near<2, PAIRS, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
                                                                                  0.f, 0.f, -2);
@@ -420,13 +121,17 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
 
 }  // namespace rtsdf
 
-// near-pass staging per grid size (index log2 n - 3: n = 8 .. 256)
+// near-pass staging and far-pass brick order per grid size (index log2 n - 3: n = 8 .. 256)
 static std::atomic<int> g_near_stage[6];
+static std::atomic<int> g_far_order[6];
 
 extern "C" int rtsdf_jfa_config(int32_t n, const rtsdf_jfa_tuning *t)
 {
-    if (!t || n < 8 || n > 256 || !rtsdf::is_pow2(n) || t->near_stage < 0 || t->near_stage > 2) return RTSDF_EINVAL;
+    if (!t || n < 8 || n > 256 || !rtsdf::is_pow2(n) || t->near_stage < 0 || t->near_stage > 2 || t->far_order < 0 ||
+        t->far_order > 2)
+        return RTSDF_EINVAL;
     g_near_stage[rtsdf::ilog2(n) - 3].store(t->near_stage);
+    g_far_order[rtsdf::ilog2(n) - 3].store(t->far_order);
     return RTSDF_OK;
 }
 
@@ -434,6 +139,7 @@ extern "C" int rtsdf_jfa_config_get(int32_t n, rtsdf_jfa_tuning *t)
 {
     if (!t || n < 8 || n > 256 || !rtsdf::is_pow2(n)) return RTSDF_EINVAL;
     t->near_stage = g_near_stage[rtsdf::ilog2(n) - 3].load();
+    t->far_order = g_far_order[rtsdf::ilog2(n) - 3].load();
     return RTSDF_OK;
 }
 
@@ -451,11 +157,12 @@ extern "C" int rtsdf_jfa_steps(rtsdf_grid coarse, int32_t *seeds, int32_t *scrat
     hipStream_t s = as_stream(stream);
     const int stage = g_near_stage[ilog2(coarse.n) - 3].load();
     const bool pairs = stage != 1;
+    const int coset = g_far_order[ilog2(coarse.n) - 3].load() != 1 ? 1 : 0;  // 0 (automatic) and 2: coset order
     if (coarse.n <= 128)
-        return pairs ? jfa_run<false, true>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, s)
-                     : jfa_run<false, false>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, s);
-    return pairs ? jfa_run<true, true>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, s)
-                 : jfa_run<true, false>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, s);
+        return pairs ? jfa_run<false, true>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, coset, s)
+                     : jfa_run<false, false>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, coset, s);
+    return pairs ? jfa_run<true, true>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, coset, s)
+                 : jfa_run<true, false>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, coset, s);
 }
 
 extern "C" int rtsdf_jfa(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, float beta, int32_t *dist2,

@@ -1,8 +1,10 @@
-// The whole library is one translation unit, so device globals (the error
-// word, the empty brick) need no relocatable device code.
+// The library's main translation unit: every .hip file of this directory but
+// jfa.hip, so device globals (the error word, the empty brick) need no
+// relocatable device code.  jfa.hip is a unit of its own (its device code is
+// built without NaN semantics); nothing here calls its kernels, and the
+// batched JFA kernel takes the pass bodies from jfa_device.hpp.
 #include "api.hip"
 #include "voxelize.hip"
-#include "jfa.hip"
 #include "select.hip"
 #include "scene.hip"
 #include "instance.hip"

@@ -75,7 +75,7 @@ class TraceTuning(C.Structure):
 
 
 class JfaTuning(C.Structure):
-    _fields_ = [("near_stage", _i32)]
+    _fields_ = [("near_stage", _i32), ("far_order", _i32)]
 
 
 class SceneInfo(C.Structure):
@@ -423,18 +423,28 @@ def rtsdf_trace_config(**kw) -> TraceTuning:
     return old
 
 
-def rtsdf_jfa_config_get(n: int) -> int:
-    """The near-pass staging used for grids of side n (0 automatic, 1 seeds, 2 seed pairs)."""
+def rtsdf_jfa_config_get(n: int, field: str = "near_stage") -> int:
+    """One field of the jump-flooding tuning for grids of side n: "near_stage" (0 automatic, 1 seeds, 2 seed
+    pairs) or "far_order" (0 automatic, 1 slab order, 2 coset order)."""
     t = JfaTuning()
     _check("rtsdf_jfa_config_get", _lib.rtsdf_jfa_config_get(int(n), C.byref(t)))
-    return t.near_stage
+    return int(getattr(t, field))
 
 
-def rtsdf_jfa_config(n: int, near_stage: int) -> int:
-    """Set the near-pass staging for grids of side n; returns the previous setting."""
-    old = rtsdf_jfa_config_get(n)
-    _check("rtsdf_jfa_config", _lib.rtsdf_jfa_config(int(n), C.byref(JfaTuning(int(near_stage)))))
-    return old
+def rtsdf_jfa_config(n: int, near_stage: int | None = None, far_order: int | None = None):
+    """Set the near-pass staging and/or the far-pass brick order for grids of side n (a field left None keeps
+    its setting); returns the previous value of the field set (a (near_stage, far_order) pair when both are)."""
+    t = JfaTuning()
+    _check("rtsdf_jfa_config_get", _lib.rtsdf_jfa_config_get(int(n), C.byref(t)))
+    old = (int(t.near_stage), int(t.far_order))
+    if near_stage is not None:
+        t.near_stage = int(near_stage)
+    if far_order is not None:
+        t.far_order = int(far_order)
+    _check("rtsdf_jfa_config", _lib.rtsdf_jfa_config(int(n), C.byref(t)))
+    if near_stage is not None and far_order is not None:
+        return old
+    return old[1] if far_order is not None else old[0]
 
 
 def rtsdf_trace_accumulate(scene: Scene, coarse: Grid, coarse_sdf, fine: Grid, mask, queue, count,

@@ -107,14 +107,17 @@ def test_host_validation(R):
         assert L.rtsdf_scene_set_tuning(dummy, C.byref(t)) == R.EINVAL  # rejected before the scene is read
         assert L.rtsdf_batch_set_tuning(dummy, C.byref(t)) == R.EINVAL
     assert L.rtsdf_trace_config(None) == R.EINVAL
-    jt = R.JfaTuning(1)
-    for n, stage in ((4, 1), (512, 1), (48, 1), (64, 3), (64, -1)):
-        jt.near_stage = stage
-        assert L.rtsdf_jfa_config(n, C.byref(jt)) == R.EINVAL, (n, stage)
+    jt = R.JfaTuning(1, 0)
+    for n, stage, order in ((4, 1, 0), (512, 1, 0), (48, 1, 0), (64, 3, 0), (64, -1, 0), (64, 1, 3), (64, 1, -1)):
+        jt.near_stage, jt.far_order = stage, order
+        assert L.rtsdf_jfa_config(n, C.byref(jt)) == R.EINVAL, (n, stage, order)
     assert L.rtsdf_jfa_config(64, None) == R.EINVAL and L.rtsdf_jfa_config_get(64, None) == R.EINVAL
-    assert R.rtsdf_jfa_config_get(64) == 0  # automatic by default
+    assert R.rtsdf_jfa_config_get(64) == 0 and R.rtsdf_jfa_config_get(64, "far_order") == 0  # automatic by default
     assert R.rtsdf_jfa_config(64, 1) == 0 and R.rtsdf_jfa_config_get(64) == 1 and R.rtsdf_jfa_config_get(128) == 0
-    R.rtsdf_jfa_config(64, 0)
+    assert R.rtsdf_jfa_config(64, far_order=2) == 0 and R.rtsdf_jfa_config_get(64, "far_order") == 2
+    assert R.rtsdf_jfa_config_get(64) == 1  # setting one field keeps the other
+    assert R.rtsdf_jfa_config(64, 0, 0) == (1, 2)
+    assert R.rtsdf_jfa_config_get(64) == 0 and R.rtsdf_jfa_config_get(64, "far_order") == 0
     assert L.rtsdf_sqrt(None, 4, dummy, None) == R.EINVAL and L.rtsdf_sqrt(dummy, -1, dummy, None) == R.EINVAL
     assert L.rtsdf_sqrt(None, 0, None, None) == R.OK  # nothing to do
     good = R.rtsdf_trace_config_get()

@@ -103,6 +103,8 @@ def test_autotune_applies_valid_tuning_and_keeps_results(R, tmp_path):
         assert got[k] == v, k
     assert R.rtsdf_trace_config_get().as_dict() == default  # applied to the scene, not the process
     assert res["jfa"]["near_stage"] in (1, 2) and R.rtsdf_jfa_config_get(w.nc) == res["jfa"]["near_stage"]
+    assert res["jfa"]["far_order"] in (1, 2) and R.rtsdf_jfa_config_get(w.nc, "far_order") == res["jfa"]["far_order"]
+    assert len(res["jfa"]["ms"]) == 4
     # state was reset: a fresh run under the tuned config equals the default run bitwise
     for f in range(3):
         p.step(f)
@@ -110,7 +112,7 @@ def test_autotune_applies_valid_tuning_and_keeps_results(R, tmp_path):
     assert torch.equal(p.fine_sdf, ref.fine_sdf) and torch.equal(p.state.arg_tri, ref.state.arg_tri)
     again = autotune.tune(p, cache=cache)
     assert again["cached"] and again["tuning"] == res["tuning"]
-    R.rtsdf_jfa_config(w.nc, 0)
+    R.rtsdf_jfa_config(w.nc, 0, 0)
     # the default space by coordinate descent: every knob is tried, results unchanged
     p2 = pipe(w)
     res2 = autotune.tune(p2, reps=1, cache=None)

@@ -129,6 +129,38 @@ def test_jfa_near_stagings_bit_exact(R, case, n, stage):
     assert np.array_equal(c.view(np.int32), want_c.view(np.int32))
 
 
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("case,n,steps", [("tiny", 32, None), ("soup", 64, None), ("room", 128, None),
+                                          ("room", 256, None), ("soup", 64, [8, 32, 16, 8, 4, 2, 1]),
+                                          ("room", 128, [1, 16, 64, 32, 8, 4, 2, 1])])
+def test_jfa_far_orders_bit_exact(R, case, n, steps, order):
+    """Both brick orders of the far passes (slab order, coset order) give the oracle's seeds, D^2 and coarse SDF,
+    also for schedules whose first far pass reads the caller's linear seeds (step below n/2 first) or follows a
+    near pass."""
+    say("jfa far order", order, case, n, steps)
+    mesh = {"tiny": tiny_scene, "room": lambda: room_scene(1), "soup": lambda: random_soup(9, 400)}[case]()
+    steps = steps or R.jfa_schedule(n, "jfa")
+    g = R.Grid.make(n)
+    seeds = torch.empty(n ** 3, dtype=torch.int32, device="cuda")
+    R.rtsdf_voxelize(cu(mesh.vertices), cu(mesh.faces), g, seeds)
+    s0 = seeds.cpu().numpy()
+    scratch, d2 = torch.empty_like(seeds), torch.empty_like(seeds)
+    c = torch.empty(n ** 3, dtype=torch.float32, device="cuda")
+    old = R.rtsdf_jfa_config(n, far_order=order)
+    try:
+        R.rtsdf_jfa_steps(g, seeds, scratch, steps, float(np.float32(0.5) * np.float32(1.0 / n)), d2, c)
+        torch.cuda.synchronize()
+    finally:
+        R.rtsdf_jfa_config(n, far_order=old)
+    s, d2, c = seeds.cpu().numpy(), d2.cpu().numpy(), c.cpu().numpy()
+    want_s = oracle.jfa_steps(n, s0, steps)
+    beta = np.float32(0.5) * np.float32(1.0 / n)
+    want_d2, want_c = oracle.coarse(n, want_s, np.float32(1.0 / n), beta)
+    assert np.array_equal(s, want_s), int((s != want_s).sum())
+    assert np.array_equal(d2, want_d2)
+    assert np.array_equal(c.view(np.int32), want_c.view(np.int32))
+
+
 @pytest.mark.parametrize("variant", ["jfa+1", "jfa+2", "1+jfa"])
 @pytest.mark.parametrize("case,n", [("tiny", 8), ("tiny", 16), ("tiny", 32), ("soup", 64), ("room", 128),
                                     ("room", 256)])
