@@ -286,8 +286,12 @@ __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, i
                                               float beta, uint32_t blk_id, uint32_t nblk, int neg2)
 {
     constexpr int T = 8 + 2 * K;
+    // Entry (u, v, w) of the tile sits at u + PX (v + T w).  The 16 lanes that one LDS read serves together
+    // (a 4 x 4 row block of a brick) reach entries u + PX v, u, v < 4: with 8-byte pairs they fall on distinct
+    // banks for a row pitch PX of 12 entries, not for T = 10 (the step-1 tile), which is padded to 12.
+    constexpr int PX = PAIRS && T == 10 ? 12 : T;
     // PAIRS: each entry staged as the pair (s, w(s)); else the seed alone (w formed per candidate)
-    __shared__ uint32_t tile[(PAIRS ? 2 : 1) * T * T * T];
+    __shared__ uint32_t tile[(PAIRS ? 2 : 1) * PX * T * T];
     uint2 *tile2 = reinterpret_cast<uint2 *>(tile);
     // n is a power of two: block and brick coordinates are bit fields (shifts and masks, no divisions)
     const int logB = logn - 2, logTB = logn - 3, TB = 1 << logTB;  // 8^3 blocks per axis
@@ -304,7 +308,7 @@ __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, i
         const int lx = (wave & 1) * 4 + (lane & 3), ly = ((wave >> 1) & 1) * 4 + ((lane >> 2) & 3),
                   lz = (wave >> 2) * 4 + (lane >> 4);
         const int b = ((tx0 + lx) >> 2) | (((ty0 + ly) >> 2) << logB) | (((tz0 + lz) >> 2) << (2 * logB));
-        stage((lx + K) + T * ((ly + K) + T * (lz + K)), (uint32_t)src[(b << 6) | lane]);
+        stage((lx + K) + PX * ((ly + K) + T * (lz + K)), (uint32_t)src[(b << 6) | lane]);
     }
     // the K-voxel shell around them, voxel by voxel: the z-slabs below and above the bricks (2K whole T x T
     // layers), then the rows in front and behind (2K rows of T per layer), then the ends of the remaining rows
@@ -329,7 +333,7 @@ __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, i
             const int b = (x >> 2) | ((y >> 2) << logB) | ((z >> 2) << (2 * logB));
             val = (uint32_t)src[(b << 6) | (x & 3) | ((y & 3) << 2) | ((z & 3) << 4)];
         }
-        stage(u + T * (v + T * w), val);
+        stage(u + PX * (v + T * w), val);
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -337,12 +341,12 @@ __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, i
               lz = (wave >> 2) * 4 + (lane >> 4);
     const int x = tx0 + lx, y = ty0 + ly, z = tz0 + lz;
     const JfaPos P = jfa_pos(x, y, z, neg2);
-    const int c = (lx + K) + T * ((ly + K) + T * (lz + K));
+    const int c = (lx + K) + PX * ((ly + K) + T * (lz + K));
     double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
         const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-        const int e = c + K * (ox + T * (oy + T * oz));
+        const int e = c + K * (ox + PX * (oy + T * oz));
         best = __builtin_fmin(best, PAIRS ? jfa_keyd_w(P, tile2[e].x, tile2[e].y) : jfa_keyd(P, tile[e]));
     }
     if (!FINAL) {
