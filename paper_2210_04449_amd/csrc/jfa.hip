@@ -38,12 +38,12 @@ __global__ void __launch_bounds__(512) jfa_first_orbit(const int32_t *__restrict
     jfa_first_orbit_body<WIDE>(src, dst, n, logn, neg2, blockIdx.x, gridDim.x);
 }
 
-template <int K, bool PAIRS, bool FINAL>
+template <int K, bool PAIRS, bool FINAL, bool SMALL>
 __global__ void __launch_bounds__(512) jfa_near(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
                                                 int logn, int32_t *__restrict__ dist2, float *__restrict__ sdf,
                                                 float h, float beta, int neg2)
 {
-    jfa_near_body<K, PAIRS, FINAL>(src, dst, n, logn, dist2, sdf, h, beta, blockIdx.x, gridDim.x, neg2);
+    jfa_near_body<K, PAIRS, FINAL, SMALL>(src, dst, n, logn, dist2, sdf, h, beta, blockIdx.x, gridDim.x, neg2);
 }
 
 template <bool WIDE, bool PAIRS>
@@ -52,6 +52,7 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
 {
     const int n = g.n, logn = ilog2(n);
     const int64_t nvox = (int64_t)n * n * n;
+    constexpr bool SMALL = PAIRS && !WIDE;  // n <= 128 with staged pairs: the two-instruction near-pass key
     const unsigned far_blocks = (unsigned)(nvox / 256);
     const unsigned near_blocks = (unsigned)(nvox / 512);
     const unsigned orbit_blocks = (unsigned)(nvox / 512);  // one orbit of eight bricks per workgroup
@@ -75,11 +76,11 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
                 else
                     jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2, coset);
             } else if (k == 2) {
-                jfa_near<2, PAIRS, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
-                                                                                 0.f, 0.f, -2);
+                jfa_near<2, PAIRS, false, SMALL>
+                    <<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr, 0.f, 0.f, -2);
             } else {
-                jfa_near<1, PAIRS, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
-                                                                                 0.f, 0.f, -2);
+                jfa_near<1, PAIRS, false, SMALL>
+                    <<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr, 0.f, 0.f, -2);
             }
             RTSDF_CHECK_LAUNCH();
             cur = dst;
@@ -101,11 +102,11 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
             if (k >= 4) {
                 jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2, coset);
             } else if (k == 2) {
-                jfa_near<2, PAIRS, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
-                                                                                 0.f, 0.f, -2);
+                jfa_near<2, PAIRS, false, SMALL>
+                    <<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr, 0.f, 0.f, -2);
             } else {
-                jfa_near<1, PAIRS, false><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr,
-                                                                                 0.f, 0.f, -2);
+                jfa_near<1, PAIRS, false, SMALL>
+                    <<<dim3(near_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, nullptr, nullptr, 0.f, 0.f, -2);
             }
             RTSDF_CHECK_LAUNCH();
             cur = dst;
@@ -113,8 +114,8 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
         }
     }
     // cur == scratch here by construction
-    jfa_near<1, PAIRS, true><<<dim3(near_blocks), dim3(512), 0, s>>>(cur, seeds, n, logn, dist2, sdf, g.h, beta,
-                                                                      -2);
+    jfa_near<1, PAIRS, true, SMALL>
+        <<<dim3(near_blocks), dim3(512), 0, s>>>(cur, seeds, n, logn, dist2, sdf, g.h, beta, -2);
     RTSDF_CHECK_LAUNCH();
     return RTSDF_OK;
 }

@@ -278,82 +278,129 @@ __device__ __forceinline__ void jfa_first_orbit_body(const int32_t *__restrict__
     dst[((int64_t)b << 6) | lane] = (int32_t)key_seed<WIDE>(P, best);
 }
 
-// One pass with step K in {1, 2}: eight bricks (an 8^3 block) per workgroup,
-// staged with a K-voxel halo in LDS.  FINAL writes the caller's outputs.
-template <int K, bool PAIRS, bool FINAL>
+// The halo shell of a near pass's LDS tile: every entry (u, v, w) of the T^3 tile (T = 8 + 2K) outside the
+// block's eight bricks, in (w, v, u) order, packed as u | v << 4 | w << 8 | (tile index u + PX (v + T w)) << 12.
+// A table built at compile time: a lane reads its entry instead of taking j apart by divisions.
+template <int K, int PX>
+struct ShellTable {
+    static constexpr int T = 8 + 2 * K, N = T * T * T - 512;
+    uint32_t e[N];
+    constexpr ShellTable() : e()
+    {
+        int j = 0;
+        for (int w = 0; w < T; ++w)
+            for (int v = 0; v < T; ++v)
+                for (int u = 0; u < T; ++u)
+                    if (!(u >= K && u < K + 8 && v >= K && v < K + 8 && w >= K && w < K + 8))
+                        e[j++] = (uint32_t)(u | v << 4 | w << 8 | (u + PX * (v + T * w)) << 12);
+    }
+};
+
+namespace {  // one copy per translation unit (the JFA's own unit and the batch kernels' unit)
+template <int K, int PX>
+struct Shell {
+    static __constant__ const ShellTable<K, PX> tab;
+};
+template <int K, int PX>
+__constant__ const ShellTable<K, PX> Shell<K, PX>::tab = ShellTable<K, PX>();
+}  // namespace
+
+// Near-pass key for n <= 128 (every coordinate below 128): the staged pair is (2S, W) with W = |S|^2 - 510 sum(S)
+// + 2^18 (in [2^18 - 3 * 127 * 383, 2^18]), and with q = 255 - p per byte one byte dot product gives
+// hi = (2S).q + W = 510 sum(S) - 2 S.p + |S|^2 - 510 sum(S) + 2^18 = D^2 - |p|^2 + 2^18, the byte-dot key's high
+// word, so a candidate costs the dot product and the min.  The low word 2S orders seeds as S does (no byte of S
+// carries when doubled); the seed is low >> 1.  A missing seed (0xFFFFFFFF) gets the bits 0x7F000000 in W, so
+// its hi stays at or above them (below 2^32: W < 0x7F000000 + 2^20, the dot product below 2^18) and it loses.
+__device__ __forceinline__ uint2 jfa_pair_small(uint32_t s)
+{
+    const uint32_t sum = __builtin_amdgcn_udot4(s, 0x00010101u, 0u, false);
+    const uint32_t sq = __builtin_amdgcn_udot4(s, s, (s & 0x7F000000u) | 0x40000u, false);
+    return make_uint2(s << 1, (uint32_t)__mul24((int)sum, -510) + sq);
+}
+
+__device__ __forceinline__ double jfa_key_small(uint32_t q, uint2 e)
+{
+    return __builtin_bit_cast(double, ((uint64_t)__builtin_amdgcn_udot4(e.x, q, e.y, false) << 32) | (uint64_t)e.x);
+}
+
+// One pass with step K in {1, 2}: eight bricks (an 8^3 block) per workgroup of 512 threads, staged with a
+// K-voxel halo in LDS.  FINAL writes the caller's outputs.  SMALL (n <= 128, with PAIRS): the two-instruction
+// key above.
+template <int K, bool PAIRS, bool FINAL, bool SMALL = false>
 __device__ __forceinline__ void jfa_near_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
                                               int logn, int32_t *__restrict__ dist2, float *__restrict__ sdf, float h,
                                               float beta, uint32_t blk_id, uint32_t nblk, int neg2)
 {
+    static_assert(!SMALL || PAIRS, "the small-grid key stages pairs");
     constexpr int T = 8 + 2 * K;
     // Entry (u, v, w) of the tile sits at u + PX (v + T w).  The 16 lanes that one LDS read serves together
     // (a 4 x 4 row block of a brick) reach entries u + PX v, u, v < 4: with 8-byte pairs they fall on distinct
     // banks for a row pitch PX of 12 entries, not for T = 10 (the step-1 tile), which is padded to 12.
     constexpr int PX = PAIRS && T == 10 ? 12 : T;
-    // PAIRS: each entry staged as the pair (s, w(s)); else the seed alone (w formed per candidate)
+    // PAIRS: each entry staged as a pair ((s, w(s)), or (2s, W) for SMALL); else the seed alone (w formed per
+    // candidate)
     __shared__ uint32_t tile[(PAIRS ? 2 : 1) * PX * T * T];
     uint2 *tile2 = reinterpret_cast<uint2 *>(tile);
     // n is a power of two: block and brick coordinates are bit fields (shifts and masks, no divisions)
     const int logB = logn - 2, logTB = logn - 3, TB = 1 << logTB;  // 8^3 blocks per axis
     const int blk = (int)xcd_remap(blk_id, nblk);
     const int tx0 = (blk & (TB - 1)) * 8, ty0 = ((blk >> logTB) & (TB - 1)) * 8, tz0 = (blk >> (2 * logTB)) * 8;
-    const auto stage = [&](int i, uint32_t v) {
-        if (PAIRS) tile2[i] = make_uint2(v, jfa_w(v));
-        else tile[i] = v;
-    };
-    {
-        // the block's eight bricks: wavefront w stages brick w, each lane its own voxel (one coalesced 256-byte
-        // read per wavefront; the workgroup has 512 threads)
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        const int lx = (wave & 1) * 4 + (lane & 3), ly = ((wave >> 1) & 1) * 4 + ((lane >> 2) & 3),
-                  lz = (wave >> 2) * 4 + (lane >> 4);
-        const int b = ((tx0 + lx) >> 2) | (((ty0 + ly) >> 2) << logB) | (((tz0 + lz) >> 2) << (2 * logB));
-        stage((lx + K) + PX * ((ly + K) + T * (lz + K)), (uint32_t)src[(b << 6) | lane]);
-    }
-    // the K-voxel shell around them, voxel by voxel: the z-slabs below and above the bricks (2K whole T x T
-    // layers), then the rows in front and behind (2K rows of T per layer), then the ends of the remaining rows
-    constexpr int NS = 2 * K * T * T, NR = 2 * K * T * 8, NH = T * T * T - 512;
-    for (int j = threadIdx.x; j < NH; j += blockDim.x) {
-        int u, v, w;
-        if (j < NS) {
-            u = j % T, v = (j / T) % T, w = j / (T * T);
-            w += w >= K ? 8 : 0;
-        } else if (j < NS + NR) {
-            const int q = j - NS;
-            u = q % T, v = (q / T) % (2 * K), w = K + q / (2 * K * T);
-            v += v >= K ? 8 : 0;
-        } else {
-            const int q = j - NS - NR;
-            u = q % (2 * K), v = K + (q / (2 * K)) % 8, w = K + q / (16 * K);
-            u += u >= K ? 8 : 0;
-        }
-        const int x = tx0 - K + u, y = ty0 - K + v, z = tz0 - K + w;
-        uint32_t val = kNoSeed;
-        if ((unsigned)x < (unsigned)n && (unsigned)y < (unsigned)n && (unsigned)z < (unsigned)n) {
-            const int b = (x >> 2) | ((y >> 2) << logB) | ((z >> 2) << (2 * logB));
-            val = (uint32_t)src[(b << 6) | (x & 3) | ((y & 3) << 2) | ((z & 3) << 4)];
-        }
-        stage(u + PX * (v + T * w), val);
-    }
-    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lx = (wave & 1) * 4 + (lane & 3), ly = ((wave >> 1) & 1) * 4 + ((lane >> 2) & 3),
               lz = (wave >> 2) * 4 + (lane >> 4);
+    const int c = (lx + K) + PX * ((ly + K) + T * (lz + K));
+    const auto stage = [&](int i, uint32_t v) {
+        if (SMALL) tile2[i] = jfa_pair_small(v);
+        else if (PAIRS) tile2[i] = make_uint2(v, jfa_w(v));
+        else tile[i] = v;
+    };
+    // All reads first, then all LDS writes, so a wavefront has every staging read in flight at once.  The block's
+    // eight bricks: wavefront w reads brick w, each lane its own voxel (one coalesced 256-byte read per
+    // wavefront).  The K-voxel shell around them (ShellTable), voxel by voxel, out-of-grid entries empty.
+    constexpr int NH = ShellTable<K, PX>::N, R = (NH + 511) / 512;
+    const int b0 = ((tx0 + lx) >> 2) | (((ty0 + ly) >> 2) << logB) | (((tz0 + lz) >> 2) << (2 * logB));
+    const uint32_t inner = (uint32_t)src[(b0 << 6) | lane];
+    uint32_t val[R];
+    int at[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = (int)threadIdx.x + 512 * r;
+        val[r] = kNoSeed;
+        at[r] = -1;
+        if (r < R - 1 || j < NH) {
+            const uint32_t e = Shell<K, PX>::tab.e[j];
+            const int x = tx0 - K + (int)(e & 15u), y = ty0 - K + (int)((e >> 4) & 15u),
+                      z = tz0 - K + (int)((e >> 8) & 15u);
+            at[r] = (int)(e >> 12);
+            if ((unsigned)x < (unsigned)n && (unsigned)y < (unsigned)n && (unsigned)z < (unsigned)n) {
+                const int b = (x >> 2) | ((y >> 2) << logB) | ((z >> 2) << (2 * logB));
+                val[r] = (uint32_t)src[(b << 6) | (x & 3) | ((y & 3) << 2) | ((z & 3) << 4)];
+            }
+        }
+    }
+    stage(c, inner);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (at[r] >= 0) stage(at[r], val[r]);
+    __syncthreads();
     const int x = tx0 + lx, y = ty0 + ly, z = tz0 + lz;
     const JfaPos P = jfa_pos(x, y, z, neg2);
-    const int c = (lx + K) + PX * ((ly + K) + T * (lz + K));
+    const uint32_t q = 0x00FFFFFFu - P.p;  // 255 - p per byte
     double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
         const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
         const int e = c + K * (ox + PX * (oy + T * oz));
-        best = __builtin_fmin(best, PAIRS ? jfa_keyd_w(P, tile2[e].x, tile2[e].y) : jfa_keyd(P, tile[e]));
+        best = __builtin_fmin(best, SMALL   ? jfa_key_small(q, tile2[e])
+                                    : PAIRS ? jfa_keyd_w(P, tile2[e].x, tile2[e].y)
+                                            : jfa_keyd(P, tile[e]));
     }
+    // the seed of the best key (kNoSeed if none): its low word, halved for the small-grid key
+    const uint32_t low = (uint32_t)__builtin_bit_cast(uint64_t, best);
+    const uint32_t s = SMALL ? (key_hi(best) >= 0x7F000000u ? kNoSeed : low >> 1) : key_seed<true>(P, best);
     if (!FINAL) {
-        const int b = (x >> 2) | ((y >> 2) << logB) | ((z >> 2) << (2 * logB));
-        dst[(b << 6) | (x & 3) | ((y & 3) << 2) | ((z & 3) << 4)] = (int32_t)key_seed<true>(P, best);
+        dst[(b0 << 6) | lane] = (int32_t)s;
     } else {
-        const uint32_t s = key_seed<true>(P, best);
         const int idx = x | (y << logn) | (z << (2 * logn));  // n <= 256: below 2^24
         if (s == kNoSeed) {
             dst[idx] = -1;
