@@ -246,6 +246,92 @@ __device__ __forceinline__ void jfa_far_body(const int32_t *__restrict__ src, in
     }
 }
 
+// Two bricks per wavefront: b0 at an even coordinate cx of its residue class along x (coset order, or any
+// brick pair (2i, 2i + 1) at step 4) and b1 = b0 + kb, the next brick of the class.  Their candidate columns
+// along x are cx - 1, cx, cx + 1 and cx, cx + 1, cx + 2 (in class units), so the wavefront reads the (up to)
+// four distinct columns once and keys each against the bricks that take it: 4 x 3 x 3 = 36 reads for two bricks
+// instead of 54.  XL: column cx - 1 lies in the grid (cx > 0); XR: column cx + 2 does; a column outside is not
+// read (for the y and z axes, as for one brick, an offset that leaves the grid is replaced by 0, a duplicate).
+// Each lane keys one voxel of each brick: the same lane position in both.
+template <bool WIDE, bool XL, bool XR, int NY, int NZ>
+__device__ __forceinline__ void jfa_far_pair(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                             int logn, int kb, int b0, int lane, int neg2)
+{
+    constexpr int NX = 2 + (XL ? 1 : 0) + (XR ? 1 : 0), NCAND = NX * NY * NZ;
+    const int logB = logn - 2, B = 1 << logB;
+    const int bx = b0 & (B - 1), by = (b0 >> logB) & (B - 1), bz = b0 >> (2 * logB);
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+    const JfaPos P0 = jfa_pos(bx * 4 + lx, by * 4 + ly, bz * 4 + lz, neg2);
+    const JfaPos P1 = jfa_pos((bx + kb) * 4 + lx, by * 4 + ly, bz * 4 + lz, neg2);
+    int dx[NX], dy[NY], dz[NZ];
+    {
+        int i = 0;
+        if (XL) dx[i++] = -kb;
+        dx[i++] = 0;
+        dx[i++] = kb;
+        if (XR) dx[i++] = 2 * kb;
+    }
+    jfa_axis(by, kb, kb << logB, dy);
+    jfa_axis(bz, kb, kb << (2 * logB), dz);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(src), (short)0, (n * n * n) * 4, 0x00020000);
+    uint32_t cand[NCAND];
+#pragma unroll
+    for (int o = 0; o < NCAND; ++o) {
+        const int off = (b0 + dx[o % NX] + dy[(o / NX) % NY] + dz[o / (NX * NY)]) << 8;
+        cand[o] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, lane * 4, off, 0);
+    }
+    double best0 = __builtin_bit_cast(double, 0x7FE0000000000000ull), best1 = best0;
+    constexpr int X0 = XL ? 1 : 0;  // the slot of column cx
+#pragma unroll
+    for (int o = 0; o < NCAND; ++o) {
+        const int xs = o % NX;
+        if (xs <= X0 + 1) best0 = __builtin_fmin(best0, WIDE ? jfa_keyd(P0, cand[o]) : jfa_key7(P0, cand[o]));
+        if (xs >= X0) best1 = __builtin_fmin(best1, WIDE ? jfa_keyd(P1, cand[o]) : jfa_key7(P1, cand[o]));
+    }
+    dst[(int64_t)b0 * 64 + lane] = (int32_t)key_seed<WIDE>(P0, best0);
+    dst[(int64_t)(b0 + kb) * 64 + lane] = (int32_t)key_seed<WIDE>(P1, best1);
+}
+
+// One pass with step k >= 4 in brick pairs: the four wavefronts of workgroup `blk` of `nblk` take pairs
+// 4 blk' + w (blk' after the XCD remap) of the coset order (far_brick of 2 v and 2 v + 1: one class after another,
+// so an XCD owns whole classes).
+template <bool WIDE>
+__device__ __forceinline__ void jfa_far_pair_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                                  int logn, int kb, uint32_t blk, uint32_t nblk, int neg2)
+{
+    const int logB = logn - 2, B = 1 << logB;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int b0 = far_brick((xcd_remap(blk, nblk) * 4 + wave) * 2, logB, kb, 1);
+    const int bx = b0 & (B - 1), by = (b0 >> logB) & (B - 1), bz = b0 >> (2 * logB);
+    const int lk = __builtin_ctz((unsigned)kb);
+    const int cx = bx >> lk, side = B >> lk;  // class coordinate and class side along x
+    const auto two = [&](int c) { return c < kb || c + kb >= B; };  // one side leaves the grid
+    const int xc = (cx > 0 ? 1 : 0) | (cx + 2 < side ? 2 : 0);
+    switch (xc | (two(by) ? 4 : 0) | (two(bz) ? 8 : 0)) {
+#define RTSDF_PAIR_CASE(C, XL, XR, NY, NZ) \
+    case C: jfa_far_pair<WIDE, XL, XR, NY, NZ>(src, dst, n, logn, kb, b0, lane, neg2); break;
+    RTSDF_PAIR_CASE(0, false, false, 3, 3)
+    RTSDF_PAIR_CASE(1, true, false, 3, 3)
+    RTSDF_PAIR_CASE(2, false, true, 3, 3)
+    RTSDF_PAIR_CASE(3, true, true, 3, 3)
+    RTSDF_PAIR_CASE(4, false, false, 2, 3)
+    RTSDF_PAIR_CASE(5, true, false, 2, 3)
+    RTSDF_PAIR_CASE(6, false, true, 2, 3)
+    RTSDF_PAIR_CASE(7, true, true, 2, 3)
+    RTSDF_PAIR_CASE(8, false, false, 3, 2)
+    RTSDF_PAIR_CASE(9, true, false, 3, 2)
+    RTSDF_PAIR_CASE(10, false, true, 3, 2)
+    RTSDF_PAIR_CASE(11, true, true, 3, 2)
+    RTSDF_PAIR_CASE(12, false, false, 2, 2)
+    RTSDF_PAIR_CASE(13, true, false, 2, 2)
+    RTSDF_PAIR_CASE(14, false, true, 2, 2)
+    default: jfa_far_pair<WIDE, true, true, 2, 2>(src, dst, n, logn, kb, b0, lane, neg2); break;
+#undef RTSDF_PAIR_CASE
+    }
+}
+
 // The first pass of plain jump flooding (step n/2) from the caller's linear seeds.  At that step one side of
 // every axis leaves the grid, so a voxel's distinct candidates are its own seed and the seeds at p XOR n/2 on
 // any subset of the axes: the same eight voxels for all eight members of such an orbit, and brick b's

@@ -129,14 +129,15 @@ def test_jfa_near_stagings_bit_exact(R, case, n, stage):
     assert np.array_equal(c.view(np.int32), want_c.view(np.int32))
 
 
-@pytest.mark.parametrize("order", [1, 2])
-@pytest.mark.parametrize("case,n,steps", [("tiny", 32, None), ("soup", 64, None), ("room", 128, None),
-                                          ("room", 256, None), ("soup", 64, [8, 32, 16, 8, 4, 2, 1]),
+@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("case,n,steps", [("tiny", 8, None), ("tiny", 16, None), ("tiny", 32, None),
+                                          ("soup", 64, None), ("room", 128, None), ("room", 256, None),
+                                          ("soup", 64, [8, 32, 16, 8, 4, 2, 1]),
                                           ("room", 128, [1, 16, 64, 32, 8, 4, 2, 1])])
 def test_jfa_far_orders_bit_exact(R, case, n, steps, order):
-    """Both brick orders of the far passes (slab order, coset order) give the oracle's seeds, D^2 and coarse SDF,
-    also for schedules whose first far pass reads the caller's linear seeds (step below n/2 first) or follows a
-    near pass."""
+    """Every brick order of the far passes (slab order, coset order, coset order in brick pairs) gives the oracle's
+    seeds, D^2 and coarse SDF, also for schedules whose first far pass reads the caller's linear seeds (step below
+    n/2 first) or follows a near pass."""
     say("jfa far order", order, case, n, steps)
     mesh = {"tiny": tiny_scene, "room": lambda: room_scene(1), "soup": lambda: random_soup(9, 400)}[case]()
     steps = steps or R.jfa_schedule(n, "jfa")
