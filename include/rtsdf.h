@@ -166,7 +166,7 @@ int rtsdf_jfa_steps(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, const i
  *              2  the pair (seed, |seed|^2 term) (8 B per entry, 2).
  * The order in which the passes with step k >= 8 (2 bricks of 4^3 or more)
  * hand bricks to wavefronts:
- *   far_order  0  automatic (the default): 3;
+ *   far_order  0  automatic (the default): 4;
  *              1  slab order: consecutive bricks, so each XCD takes a slab of
  *                 z-layers;
  *              2  coset order: the bricks of one residue class of the brick
@@ -175,7 +175,9 @@ int rtsdf_jfa_steps(rtsdf_grid coarse, int32_t *seeds, int32_t *scratch, const i
  *                 into the L2 of one XCD only;
  *              3  coset order in pairs: each wavefront takes two bricks
  *                 next to each other in their class along x and reads their
- *                 shared candidate bricks once (36 reads instead of 54).
+ *                 shared candidate bricks once (36 reads instead of 54);
+ *              4  coset order in 2 x 2 quads (x and y): 48 reads for four
+ *                 bricks instead of 108 (grids of 8^3 voxels take pairs).
  * rtsdf_jfa_config sets both for grids of side n (a power of two in [8, 256];
  * EINVAL otherwise or for values outside the sets); the setting is process
  * state read at each rtsdf_jfa / rtsdf_jfa_steps call (calls that overlap

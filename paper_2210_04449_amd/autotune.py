@@ -19,8 +19,9 @@ batch) with HIP events and keeps the fastest.  The knobs:
 
 For a Pipeline the jump flooding's two knobs (``rtsdf_jfa_config``: the
 near-pass staging, seeds alone or seed pairs in LDS; the far-pass brick order,
-slab order, coset order or coset order in brick pairs) are timed too, all six
-combinations, and the fastest is kept for the pipeline's coarse grid size.
+slab order, coset order, or coset order in brick pairs or 2 x 2 quads) are
+timed too, all eight combinations, and the fastest is kept for the pipeline's
+coarse grid size.
 
 The search is coordinate descent from the target's current tuning: each knob
 in turn takes each of its values with the others fixed, a change is kept when
@@ -216,12 +217,12 @@ def tune(target, reps: int = 2, space: dict = SPACE, cache: str | None = DEFAULT
 
 def tune_jfa(p, reps: int = 3) -> dict:
     """Time the jump flooding of pipeline `p` with each near-pass staging (seeds alone or seed pairs) and each
-    far-pass brick order (slab order, coset order, coset order in brick pairs) -- rtsdf_jfa_config; the results are
-    the same -- and keep the fastest combination for grids of p's coarse size (process-wide setting).  Each timed
-    run voxelizes first, the same work for every combination."""
+    far-pass brick order (slab order, coset order, coset order in brick pairs or quads) -- rtsdf_jfa_config; the
+    results are the same -- and keep the fastest combination for grids of p's coarse size (process-wide setting).
+    Each timed run voxelizes first, the same work for every combination."""
     n = p.nc
     times = {}
-    for stage, order in itertools.product((1, 2), (1, 2, 3)):
+    for stage, order in itertools.product((1, 2), (1, 2, 3, 4)):
         R.rtsdf_jfa_config(n, stage, order)
 
         def run():

@@ -39,6 +39,13 @@ __global__ void __launch_bounds__(256) jfa_far_pairs(const int32_t *__restrict__
 }
 
 template <bool WIDE>
+__global__ void __launch_bounds__(256) jfa_far_quads(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                                     int logn, int kb, int neg2)
+{
+    jfa_far_quad_body<WIDE>(src, dst, n, logn, kb, blockIdx.x, gridDim.x, neg2);
+}
+
+template <bool WIDE>
 __global__ void __launch_bounds__(512) jfa_first_orbit(const int32_t *__restrict__ src, int32_t *__restrict__ dst,
                                                        int n, int logn, int neg2)
 {
@@ -57,15 +64,18 @@ template <bool WIDE, bool PAIRS>
 static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float beta, int32_t *dist2, float *sdf,
                    const int32_t *steps, int m, int order, hipStream_t s)
 {
-    // far-pass brick order: 1 slab order, 2 coset order, 3 coset order in brick pairs
-    const int coset = order >= 2 ? 1 : 0;
     const int n = g.n, logn = ilog2(n);
     const int64_t nvox = (int64_t)n * n * n;
+    // far-pass brick order: 1 slab order, 2 coset order, 3 coset order in brick pairs, 4 in 2 x 2 brick quads
+    // (a grid of 8^3 voxels has only two quads, under one workgroup: it takes pairs)
+    if (order == 4 && nvox < 1024) order = 3;
+    const int coset = order >= 2 ? 1 : 0;
     constexpr bool SMALL = PAIRS && !WIDE;  // n <= 128 with staged pairs: the two-instruction near-pass key
     const unsigned far_blocks = (unsigned)(nvox / 256);
     const unsigned near_blocks = (unsigned)(nvox / 512);
     const unsigned orbit_blocks = (unsigned)(nvox / 512);  // one orbit of eight bricks per workgroup
     const unsigned pair_blocks = (unsigned)(nvox / 512);   // four wavefronts of two bricks each per workgroup
+    const unsigned quad_blocks = (unsigned)(nvox / 1024);  // four wavefronts of four bricks each per workgroup
     // Passes 0 .. m-2 go brick layout to brick layout; the final pass (step 1) must read `scratch` and write the
     // caller's linear layout to `seeds` (and `dist2`, `sdf`).  When the first step is a far one it reads the
     // linear input directly, and the brick passes alternate between `dist2` (written only by the final pass,
@@ -83,6 +93,8 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
                     jfa_first_orbit<WIDE><<<dim3(orbit_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, -2);
                 else if (i == 0)
                     jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2, coset);
+                else if (order == 4)
+                    jfa_far_quads<WIDE><<<dim3(quad_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
                 else if (order == 3)
                     jfa_far_pairs<WIDE><<<dim3(pair_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
                 else
@@ -111,7 +123,9 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
         for (int i = 0; i < npass; ++i) {
             const int k = steps[i];
             int32_t *dst = bufs[next];
-            if (k >= 4 && order == 3) {
+            if (k >= 4 && order == 4) {
+                jfa_far_quads<WIDE><<<dim3(quad_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
+            } else if (k >= 4 && order == 3) {
                 jfa_far_pairs<WIDE><<<dim3(pair_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
             } else if (k >= 4) {
                 jfa_far<WIDE, false><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2, coset);
@@ -143,7 +157,7 @@ static std::atomic<int> g_far_order[6];
 extern "C" int rtsdf_jfa_config(int32_t n, const rtsdf_jfa_tuning *t)
 {
     if (!t || n < 8 || n > 256 || !rtsdf::is_pow2(n) || t->near_stage < 0 || t->near_stage > 2 || t->far_order < 0 ||
-        t->far_order > 3)
+        t->far_order > 4)
         return RTSDF_EINVAL;
     g_near_stage[rtsdf::ilog2(n) - 3].store(t->near_stage);
     g_far_order[rtsdf::ilog2(n) - 3].store(t->far_order);
@@ -173,7 +187,7 @@ extern "C" int rtsdf_jfa_steps(rtsdf_grid coarse, int32_t *seeds, int32_t *scrat
     const int stage = g_near_stage[ilog2(coarse.n) - 3].load();
     const bool pairs = stage != 1;
     int order = g_far_order[ilog2(coarse.n) - 3].load();
-    if (order == 0) order = 3;  // automatic: coset order in brick pairs
+    if (order == 0) order = 4;  // automatic: coset order in 2 x 2 brick quads
     if (coarse.n <= 128)
         return pairs ? jfa_run<false, true>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, order, s)
                      : jfa_run<false, false>(coarse, seeds, scratch, beta, dist2, coarse_sdf, steps, nsteps, order, s);

@@ -332,6 +332,115 @@ __device__ __forceinline__ void jfa_far_pair_body(const int32_t *__restrict__ sr
     }
 }
 
+// Four bricks per wavefront: the 2 x 2 block at even class coordinates (cx, cy) and (cx + 1, cy), (cx, cy + 1),
+// (cx + 1, cy + 1) of one residue class (steps of kb bricks along x and y).  As for a pair, along x and along y
+// the (up to) four distinct columns are read once and keyed against the bricks that take them: 4 x 4 x 3 = 48
+// reads for four bricks instead of 108.  XL / XR / YL / YR: the columns cx - 1 / cx + 2 / cy - 1 / cy + 2 lie in
+// the grid.  Each lane keys one voxel of each brick: the same lane position in all four.
+template <bool WIDE, bool XL, bool XR, bool YL, bool YR, int NZ>
+__device__ __forceinline__ void jfa_far_quad(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                             int logn, int kb, int b0, int lane, int neg2)
+{
+    constexpr int NX = 2 + (XL ? 1 : 0) + (XR ? 1 : 0), NY = 2 + (YL ? 1 : 0) + (YR ? 1 : 0);
+    constexpr int NCAND = NX * NY * NZ;
+    const int logB = logn - 2, B = 1 << logB;
+    const int bx = b0 & (B - 1), by = (b0 >> logB) & (B - 1), bz = b0 >> (2 * logB);
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+    JfaPos P[4];  // brick i + 2 j: (bx + i kb, by + j kb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        P[q] = jfa_pos((bx + (q & 1) * kb) * 4 + lx, (by + (q >> 1) * kb) * 4 + ly, bz * 4 + lz, neg2);
+    const int sy = kb << logB;
+    int dx[NX], dy[NY], dz[NZ];
+    {
+        int i = 0;
+        if (XL) dx[i++] = -kb;
+        dx[i++] = 0;
+        dx[i++] = kb;
+        if (XR) dx[i++] = 2 * kb;
+        i = 0;
+        if (YL) dy[i++] = -sy;
+        dy[i++] = 0;
+        dy[i++] = sy;
+        if (YR) dy[i++] = 2 * sy;
+    }
+    jfa_axis(bz, kb, kb << (2 * logB), dz);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(src), (short)0, (n * n * n) * 4, 0x00020000);
+    uint32_t cand[NCAND];
+#pragma unroll
+    for (int o = 0; o < NCAND; ++o) {
+        const int off = (b0 + dx[o % NX] + dy[(o / NX) % NY] + dz[o / (NX * NY)]) << 8;
+        cand[o] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, lane * 4, off, 0);
+    }
+    double best[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) best[q] = __builtin_bit_cast(double, 0x7FE0000000000000ull);
+    constexpr int X0 = XL ? 1 : 0, Y0 = YL ? 1 : 0;  // the slots of columns cx and cy
+#pragma unroll
+    for (int o = 0; o < NCAND; ++o) {
+        const int xs = o % NX, ys = (o / NX) % NY;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = q & 1, j = q >> 1;
+            if (xs >= X0 - 1 + i && xs <= X0 + 1 + i && ys >= Y0 - 1 + j && ys <= Y0 + 1 + j)
+                best[q] = __builtin_fmin(best[q], WIDE ? jfa_keyd(P[q], cand[o]) : jfa_key7(P[q], cand[o]));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        dst[(int64_t)(b0 + (q & 1) * kb + (q >> 1) * sy) * 64 + lane] = (int32_t)key_seed<WIDE>(P[q], best[q]);
+}
+
+// The (even, even) brick of quad v in coset order: within a class of side 2^m bricks, v's low bits give cx / 2
+// and cy / 2 (m - 1 bits each), then cz (m bits), then the class; the classes and an XCD's range as for one brick.
+__device__ __forceinline__ int quad_brick(uint32_t v, int logB, int kb)
+{
+    const int lk = __builtin_ctz((unsigned)kb), m = logB - lk;
+    const int h = m - 1, hm = (1 << h) - 1;
+    const int qx = (int)v & hm, qy = (int)(v >> h) & hm, cz = (int)(v >> (2 * h)) & ((1 << m) - 1);
+    const int r = (int)(v >> (2 * h + m));
+    const int rx = r & (kb - 1), ry = (r >> lk) & (kb - 1), rz = r >> (2 * lk);
+    return (rx | (qx << (lk + 1))) | ((ry | (qy << (lk + 1))) << logB) | ((rz | (cz << lk)) << (2 * logB));
+}
+
+// One pass with step k >= 4 in 2 x 2 brick quads: the four wavefronts of workgroup `blk` of `nblk` take quads
+// 4 blk' + w (blk' after the XCD remap).
+template <bool WIDE>
+__device__ __forceinline__ void jfa_far_quad_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
+                                                  int logn, int kb, uint32_t blk, uint32_t nblk, int neg2)
+{
+    const int logB = logn - 2, B = 1 << logB;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int b0 = quad_brick(xcd_remap(blk, nblk) * 4 + wave, logB, kb);
+    const int bx = b0 & (B - 1), by = (b0 >> logB) & (B - 1), bz = b0 >> (2 * logB);
+    const int lk = __builtin_ctz((unsigned)kb);
+    const int cx = bx >> lk, cy = by >> lk, side = B >> lk;
+    const bool two_z = bz < kb || bz + kb >= B;  // one side leaves the grid
+    const int c = (cx > 0 ? 1 : 0) | (cx + 2 < side ? 2 : 0) | (cy > 0 ? 4 : 0) | (cy + 2 < side ? 8 : 0) |
+                  (two_z ? 16 : 0);
+    switch (c) {
+#define RTSDF_QUAD_CASE(C)                                                                                       \
+    case C:                                                                                                      \
+        jfa_far_quad<WIDE, (C & 1) != 0, (C & 2) != 0, (C & 4) != 0, (C & 8) != 0, (C & 16) ? 2 : 3>(             \
+            src, dst, n, logn, kb, b0, lane, neg2);                                                              \
+        break;
+    RTSDF_QUAD_CASE(0) RTSDF_QUAD_CASE(1) RTSDF_QUAD_CASE(2) RTSDF_QUAD_CASE(3)
+    RTSDF_QUAD_CASE(4) RTSDF_QUAD_CASE(5) RTSDF_QUAD_CASE(6) RTSDF_QUAD_CASE(7)
+    RTSDF_QUAD_CASE(8) RTSDF_QUAD_CASE(9) RTSDF_QUAD_CASE(10) RTSDF_QUAD_CASE(11)
+    RTSDF_QUAD_CASE(12) RTSDF_QUAD_CASE(13) RTSDF_QUAD_CASE(14) RTSDF_QUAD_CASE(15)
+    RTSDF_QUAD_CASE(16) RTSDF_QUAD_CASE(17) RTSDF_QUAD_CASE(18) RTSDF_QUAD_CASE(19)
+    RTSDF_QUAD_CASE(20) RTSDF_QUAD_CASE(21) RTSDF_QUAD_CASE(22) RTSDF_QUAD_CASE(23)
+    RTSDF_QUAD_CASE(24) RTSDF_QUAD_CASE(25) RTSDF_QUAD_CASE(26) RTSDF_QUAD_CASE(27)
+    RTSDF_QUAD_CASE(28) RTSDF_QUAD_CASE(29) RTSDF_QUAD_CASE(30)
+    default:
+        jfa_far_quad<WIDE, true, true, true, true, 2>(src, dst, n, logn, kb, b0, lane, neg2);
+        break;
+#undef RTSDF_QUAD_CASE
+    }
+}
+
 // The first pass of plain jump flooding (step n/2) from the caller's linear seeds.  At that step one side of
 // every axis leaves the grid, so a voxel's distinct candidates are its own seed and the seeds at p XOR n/2 on
 // any subset of the axes: the same eight voxels for all eight members of such an orbit, and brick b's

@@ -425,7 +425,8 @@ def rtsdf_trace_config(**kw) -> TraceTuning:
 
 def rtsdf_jfa_config_get(n: int, field: str = "near_stage") -> int:
     """One field of the jump-flooding tuning for grids of side n: "near_stage" (0 automatic, 1 seeds, 2 seed
-    pairs) or "far_order" (0 automatic, 1 slab order, 2 coset order, 3 coset order in brick pairs)."""
+    pairs) or "far_order" (0 automatic, 1 slab order, 2 coset order, 3 coset order in brick pairs, 4 in 2 x 2 brick
+    quads)."""
     t = JfaTuning()
     _check("rtsdf_jfa_config_get", _lib.rtsdf_jfa_config_get(int(n), C.byref(t)))
     return int(getattr(t, field))

@@ -108,7 +108,7 @@ def test_host_validation(R):
         assert L.rtsdf_batch_set_tuning(dummy, C.byref(t)) == R.EINVAL
     assert L.rtsdf_trace_config(None) == R.EINVAL
     jt = R.JfaTuning(1, 0)
-    for n, stage, order in ((4, 1, 0), (512, 1, 0), (48, 1, 0), (64, 3, 0), (64, -1, 0), (64, 1, 4), (64, 1, -1)):
+    for n, stage, order in ((4, 1, 0), (512, 1, 0), (48, 1, 0), (64, 3, 0), (64, -1, 0), (64, 1, 5), (64, 1, -1)):
         jt.near_stage, jt.far_order = stage, order
         assert L.rtsdf_jfa_config(n, C.byref(jt)) == R.EINVAL, (n, stage, order)
     assert L.rtsdf_jfa_config(64, None) == R.EINVAL and L.rtsdf_jfa_config_get(64, None) == R.EINVAL

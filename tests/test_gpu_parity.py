@@ -129,7 +129,7 @@ def test_jfa_near_stagings_bit_exact(R, case, n, stage):
     assert np.array_equal(c.view(np.int32), want_c.view(np.int32))
 
 
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 @pytest.mark.parametrize("case,n,steps", [("tiny", 8, None), ("tiny", 16, None), ("tiny", 32, None),
                                           ("soup", 64, None), ("room", 128, None), ("room", 256, None),
                                           ("soup", 64, [8, 32, 16, 8, 4, 2, 1]),
