@@ -6,10 +6,10 @@
 // smallest squared distance, ties to the lowest linear seed index.  After the
 // last pass the coarse SDF is c = h sqrt(D^2) - beta.
 //
-// Layout between passes (internal): the grid is cut into 4x4x4 bricks, one
-// wavefront per brick; brick b = bx + B (by + B bz) (B = n / 4) stores its 64
-// voxels contiguously (lane = lx + 4 ly + 16 lz), so every candidate read of a
-// wavefront is one coalesced 256-byte block.  A seed is packed as
+// Layout between passes (internal): the grid is cut into 4x4x4 bricks; brick
+// b = bx + B (by + B bz) (B = n / 4) stores its 64 voxels contiguously (lane =
+// lx + 4 ly + 16 lz), so every candidate read of a wavefront (one lane per
+// voxel of a brick) is one coalesced 256-byte block.  A seed is packed as
 // x | y << 8 | z << 16 (0xFFFFFFFF = none); packed order equals linear-index
 // order, so ties compare the packed word directly.
 //
@@ -27,14 +27,17 @@
 // * byte-dot (every pass at n = 256, the near passes at every n): hi =
 //   |S|^2 - 2 S.p + 2^18 = D^2 - |p|^2 + 2^18 for the voxel p, low = S: two
 //   v_dot4_u32_u8 and one 24-bit multiply-add, or, with w(S) = |S|^2 staged
-//   beside each seed, one of each.
+//   beside each seed, one of each (near passes at n <= 128 stage a pair that
+//   needs the dot product alone: jfa_pair_small).
 //
 // Steps k >= 4 read whole neighbour bricks straight from global memory (an
-// axis offset that would leave the grid reads the brick with offset 0 on that
-// axis, a candidate the set already holds).  Steps 2 and 1 stage an (8 + 2k)^3 block of voxels (eight bricks
-// plus halo) in LDS; candidates then sit at compile-time LDS offsets and
-// out-of-grid halo entries are empty.  The k = 1 pass writes the final seeds,
-// D^2 and c in the caller's linear layout.
+// axis offset that would leave the grid is not read, or reads the brick with
+// offset 0 on that axis, a candidate the set already holds), one brick per
+// wavefront or, sharing the candidate bricks they have in common, two or four
+// bricks of one residue class per wavefront.  Steps 2 and 1 stage an
+// (8 + 2k)^3 block of voxels (eight bricks plus halo) in LDS; candidates then
+// sit at compile-time LDS offsets and out-of-grid halo entries are empty.  The
+// k = 1 pass writes the final seeds, D^2 and c in the caller's linear layout.
 #pragma once
 
 #include "common.hpp"
