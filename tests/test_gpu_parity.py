@@ -133,18 +133,27 @@ def test_jfa_near_stagings_bit_exact(R, case, n, stage):
 @pytest.mark.parametrize("case,n,steps", [("tiny", 8, None), ("tiny", 16, None), ("tiny", 32, None),
                                           ("soup", 64, None), ("room", 128, None), ("room", 256, None),
                                           ("soup", 64, [8, 32, 16, 8, 4, 2, 1]),
-                                          ("room", 128, [1, 16, 64, 32, 8, 4, 2, 1])])
+                                          ("room", 128, [1, 16, 64, 32, 8, 4, 2, 1]),
+                                          ("sparse", 16, None), ("sparse", 64, None), ("sparse", 128, None),
+                                          ("sparse", 256, None), ("sparse", 128, [32, 64, 16, 4, 8, 2, 1])])
 def test_jfa_far_orders_bit_exact(R, case, n, steps, order):
-    """Every brick order of the far passes (slab order, coset order, coset order in brick pairs) gives the oracle's
-    seeds, D^2 and coarse SDF, also for schedules whose first far pass reads the caller's linear seeds (step below
-    n/2 first) or follows a near pass."""
+    """Every brick order of the far passes (slab order, coset order, coset order in brick pairs or 2 x 2 quads)
+    gives the oracle's seeds, D^2 and coarse SDF, also for schedules whose first far pass reads the caller's
+    linear seeds (step below n/2 first) or follows a near pass, and for a few isolated seeds (every voxel's seed
+    arrives from far away, through every pass)."""
     say("jfa far order", order, case, n, steps)
-    mesh = {"tiny": tiny_scene, "room": lambda: room_scene(1), "soup": lambda: random_soup(9, 400)}[case]()
     steps = steps or R.jfa_schedule(n, "jfa")
     g = R.Grid.make(n)
-    seeds = torch.empty(n ** 3, dtype=torch.int32, device="cuda")
-    R.rtsdf_voxelize(cu(mesh.vertices), cu(mesh.faces), g, seeds)
-    s0 = seeds.cpu().numpy()
+    if case == "sparse":
+        s0 = np.full(n ** 3, -1, np.int32)
+        own = np.random.default_rng(n).choice(n ** 3, size=7, replace=False)
+        s0[own] = own
+        seeds = cu(s0)
+    else:
+        mesh = {"tiny": tiny_scene, "room": lambda: room_scene(1), "soup": lambda: random_soup(9, 400)}[case]()
+        seeds = torch.empty(n ** 3, dtype=torch.int32, device="cuda")
+        R.rtsdf_voxelize(cu(mesh.vertices), cu(mesh.faces), g, seeds)
+        s0 = seeds.cpu().numpy()
     scratch, d2 = torch.empty_like(seeds), torch.empty_like(seeds)
     c = torch.empty(n ** 3, dtype=torch.float32, device="cuda")
     old = R.rtsdf_jfa_config(n, far_order=order)
