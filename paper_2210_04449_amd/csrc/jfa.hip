@@ -52,6 +52,13 @@ __global__ void __launch_bounds__(512) jfa_first_orbit(const int32_t *__restrict
     jfa_first_orbit_body<WIDE>(src, dst, n, logn, neg2, blockIdx.x, gridDim.x);
 }
 
+template <bool WIDE>
+__global__ void __launch_bounds__(512) jfa_first_orbit4(const int32_t *__restrict__ src, int32_t *__restrict__ dst,
+                                                        int n, int logn, int neg2)
+{
+    jfa_first_orbit4_body<WIDE>(src, dst, n, logn, neg2, blockIdx.x, gridDim.x);
+}
+
 template <int K, bool PAIRS, bool FINAL, bool SMALL>
 __global__ void __launch_bounds__(512) jfa_near(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
                                                 int logn, int32_t *__restrict__ dist2, float *__restrict__ sdf,
@@ -89,7 +96,9 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
             const int k = steps[i];
             int32_t *dst = (npass - 1 - i) % 2 == 0 ? scratch : dist2;
             if (k >= 4) {
-                if (i == 0 && k == n / 2)
+                if (i == 0 && k == n / 2 && n >= 32)
+                    jfa_first_orbit4<WIDE><<<dim3(orbit_blocks / 4), dim3(512), 0, s>>>(cur, dst, n, logn, -2);
+                else if (i == 0 && k == n / 2)
                     jfa_first_orbit<WIDE><<<dim3(orbit_blocks), dim3(512), 0, s>>>(cur, dst, n, logn, -2);
                 else if (i == 0)
                     jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2, coset);

@@ -476,6 +476,48 @@ __device__ __forceinline__ void jfa_first_orbit_body(const int32_t *__restrict__
     dst[((int64_t)b << 6) | lane] = (int32_t)key_seed<WIDE>(P, best);
 }
 
+// The same first pass for four orbits next to each other along x (n >= 32, so H = n / 8 >= 4): orbit
+// coordinates (4 gq + t, gy, gz), t = 0..3.  Member m of the four orbits are four bricks next to each other
+// along x, so the workgroup reads each of their rows of 16 voxels as one 64-byte run of the caller's linear
+// seeds (instead of four 16-byte pieces), stages the 32 bricks in LDS, and wavefront m keys the voxel of its
+// lane in the four bricks of member m.
+template <bool WIDE>
+__device__ __forceinline__ void jfa_first_orbit4_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst,
+                                                      int n, int logn, int neg2, uint32_t blk_id, uint32_t nblk)
+{
+    __shared__ uint32_t tile[8][4][kWave];  // [member][orbit t][lane]
+    const int logB = logn - 2, logH = logB - 1, H = 1 << logH, logQ = logH - 2;  // H / 4 groups along x
+    const int g = (int)xcd_remap(blk_id, nblk);
+    const int gx0 = (g & ((1 << logQ) - 1)) * 4, gy = (g >> logQ) & (H - 1), gz = g >> (logQ + logH);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = (int)threadIdx.x + 512 * r;  // 2048 voxels: 16 along x, 16 rows, 8 members
+        const int xx = e & 15, row = (e >> 4) & 15, m = e >> 8;
+        const int x = (gx0 + ((m & 1) << logH)) * 4 + xx;
+        const int y = (gy + (((m >> 1) & 1) << logH)) * 4 + (row & 3);
+        const int z = (gz + ((m >> 2) << logH)) * 4 + (row >> 2);
+        tile[m][xx >> 2][(xx & 3) | ((row & 3) << 2) | ((row >> 2) << 4)] =
+            pack_linear(src[x + (y << logn) + (z << (2 * logn))], logn);
+    }
+    __syncthreads();
+    const int m = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+    const int by = gy + (((m >> 1) & 1) << logH), bz = gz + ((m >> 2) << logH);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int bx = gx0 + t + ((m & 1) << logH);
+        const JfaPos P = jfa_pos(bx * 4 + lx, by * 4 + ly, bz * 4 + lz, neg2);
+        double best = __builtin_bit_cast(double, 0x7FE0000000000000ull);
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const uint32_t c = tile[m ^ o][t][lane];
+            best = __builtin_fmin(best, WIDE ? jfa_keyd(P, c) : jfa_key7(P, c));
+        }
+        const int b = bx | (by << logB) | (bz << (2 * logB));
+        dst[((int64_t)b << 6) | lane] = (int32_t)key_seed<WIDE>(P, best);
+    }
+}
+
 // The halo shell of a near pass's LDS tile: every entry (u, v, w) of the T^3 tile (T = 8 + 2K) outside the
 // block's eight bricks, in (w, v, u) order, packed as u | v << 4 | w << 8 | (tile index u + PX (v + T w)) << 12.
 // A table built at compile time: a lane reads its entry instead of taking j apart by divisions.
