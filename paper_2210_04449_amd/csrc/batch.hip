@@ -134,6 +134,9 @@ __global__ void __launch_bounds__(KIND == kJfaNear2 || KIND == kJfaFinal ? 512 :
         const int64_t nvox = (int64_t)st.n * st.n * st.n;
         const int64_t e = (int64_t)blk * blockDim.x + threadIdx.x;
         if (e < nvox) jfa_to_bricks_body(st.src, st.dst, st.n, st.logn, e);
+    } else if (KIND == kJfaFarBricks && st.n >= 16) {
+        // 2 x 2 brick quads per wavefront (a workgroup per 1024 voxels), as the single-scene passes
+        jfa_far_quad_body<false>(st.src, st.dst, st.n, st.logn, st.kb, blk, nblk, neg2);
     } else if (KIND == kJfaFarBricks || KIND == kJfaFarLinear) {
         jfa_far_body<false, KIND == kJfaFarLinear>(st.src, st.dst, st.n, st.logn, st.kb, blk, nblk, neg2, 0);
     } else if (KIND == kJfaNear2) {
@@ -366,7 +369,7 @@ extern "C" int rtsdf_batch_create(const rtsdf_batch_scene *scenes, int32_t n, ui
                 put(first + j - 1,
                     JfaStep{(linear_first && j == 1) ? kJfaFarLinear : kJfaFarBricks, c.n, L, k / 4, cur, dst, nullptr,
                             nullptr, 0.f, 0.f},
-                    (uint32_t)(nvox / 256));
+                    (uint32_t)(!(linear_first && j == 1) && c.n >= 16 ? nvox / 1024 : nvox / 256));
             else
                 put(first + j - 1, JfaStep{kJfaNear2, c.n, L, 0, cur, dst, nullptr, nullptr, 0.f, 0.f},
                     (uint32_t)(nvox / 512));
