@@ -331,7 +331,9 @@ def main():
         "rays_per_step": rays,
         "rays_per_s": round(rays / trace_s, 1),
         "jfa": {"gbps": round(jfa_gbs, 1), "frac_hbm": round(jfa_gbs / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes": jfa_bytes, "schedule": args.jfa},
+                "algorithmic_bytes": jfa_bytes, "schedule": args.jfa,
+                # 0 = automatic: seed pairs in LDS, far passes in 2 x 2 brick quads of a residue class
+                "near_stage": R.rtsdf_jfa_config_get(w.nc), "far_order": R.rtsdf_jfa_config_get(w.nc, "far_order")},
         "trace_stats": {"nodes_per_ray": round(nodes_per_ray, 2), "tris_per_ray": round(tris_per_ray, 2),
                         "run_nodes_per_ray": round(ctr[0] / max(ctr[2], 1), 2),
                         "run_tris_per_ray": round(ctr[1] / max(ctr[2], 1), 2),
