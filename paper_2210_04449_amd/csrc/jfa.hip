@@ -82,7 +82,8 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
     const unsigned near_blocks = (unsigned)(nvox / 512);
     const unsigned orbit_blocks = (unsigned)(nvox / 512);  // one orbit of eight bricks per workgroup
     const unsigned pair_blocks = (unsigned)(nvox / 512);   // four wavefronts of two bricks each per workgroup
-    const unsigned quad_blocks = (unsigned)(nvox / 1024);  // four wavefronts of four bricks each per workgroup
+    // one wavefront of four bricks per workgroup (measured 1-2 % faster than four wavefronts per workgroup)
+    const unsigned quad_waves = (unsigned)(nvox / 256);
     // Passes 0 .. m-2 go brick layout to brick layout; the final pass (step 1) must read `scratch` and write the
     // caller's linear layout to `seeds` (and `dist2`, `sdf`).  When the first step is a far one it reads the
     // linear input directly, and the brick passes alternate between `dist2` (written only by the final pass,
@@ -103,7 +104,7 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
                 else if (i == 0)
                     jfa_far<WIDE, true><<<dim3(far_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2, coset);
                 else if (order == 4)
-                    jfa_far_quads<WIDE><<<dim3(quad_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
+                    jfa_far_quads<WIDE><<<dim3(quad_waves), dim3(64), 0, s>>>(cur, dst, n, logn, k / 4, -2);
                 else if (order == 3)
                     jfa_far_pairs<WIDE><<<dim3(pair_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
                 else
@@ -133,7 +134,7 @@ static int jfa_run(const rtsdf_grid &g, int32_t *seeds, int32_t *scratch, float 
             const int k = steps[i];
             int32_t *dst = bufs[next];
             if (k >= 4 && order == 4) {
-                jfa_far_quads<WIDE><<<dim3(quad_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
+                jfa_far_quads<WIDE><<<dim3(quad_waves), dim3(64), 0, s>>>(cur, dst, n, logn, k / 4, -2);
             } else if (k >= 4 && order == 3) {
                 jfa_far_pairs<WIDE><<<dim3(pair_blocks), dim3(256), 0, s>>>(cur, dst, n, logn, k / 4, -2);
             } else if (k >= 4) {

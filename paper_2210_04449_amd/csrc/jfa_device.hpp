@@ -407,8 +407,8 @@ __device__ __forceinline__ int quad_brick(uint32_t v, int logB, int kb)
     return (rx | (qx << (lk + 1))) | ((ry | (qy << (lk + 1))) << logB) | ((rz | (cz << lk)) << (2 * logB));
 }
 
-// One pass with step k >= 4 in 2 x 2 brick quads: the four wavefronts of workgroup `blk` of `nblk` take quads
-// 4 blk' + w (blk' after the XCD remap).
+// One pass with step k >= 4 in 2 x 2 brick quads: the W wavefronts of workgroup `blk` of `nblk` take quads
+// W blk' + w (blk' after the XCD remap; W = 1 for the single-scene passes, 4 in the batched kernel).
 template <bool WIDE>
 __device__ __forceinline__ void jfa_far_quad_body(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
                                                   int logn, int kb, uint32_t blk, uint32_t nblk, int neg2)
@@ -416,7 +416,7 @@ __device__ __forceinline__ void jfa_far_quad_body(const int32_t *__restrict__ sr
     const int logB = logn - 2, B = 1 << logB;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int b0 = quad_brick(xcd_remap(blk, nblk) * 4 + wave, logB, kb);
+    const int b0 = quad_brick(xcd_remap(blk, nblk) * (blockDim.x >> 6) + wave, logB, kb);
     const int bx = b0 & (B - 1), by = (b0 >> logB) & (B - 1), bz = b0 >> (2 * logB);
     const int lk = __builtin_ctz((unsigned)kb);
     const int cx = bx >> lk, cy = by >> lk, side = B >> lk;
